@@ -1,0 +1,246 @@
+"""Seeded synthetic workloads for the D2Q9 immersed interface-lattice Boltzmann
+method (II-LBM) of Qin, Kolahdouz & Griffith, arXiv:2003.12186.
+
+This module only describes *inputs*: lattice sizes, relaxation times, spring
+constants, boundary types and the initial Lagrangian marker positions.  It holds
+none of the method's arithmetic (no equilibrium, collision, delta kernel, force
+law or jump), so both the GPU path and the CPU oracle can be fed from it without
+sharing any code of the method itself.  It imports nothing from the rest of the
+package.
+
+Random draws come from SplitMix64 (Steele, Lea & Flood, "Fast splittable
+pseudorandom number generators", OOPSLA 2014): the state advances by the
+golden-ratio increment 0x9E3779B97F4A7C15 and each output is the state passed
+through the two xor-shift-multiply rounds of that paper's mixing function.  A
+draw u in [0, 1) takes the top 53 bits of an output.  Stream (config, instance)
+starts from the state ``config * 2**32 + instance``.
+
+Workloads (lattice units, dx = dt = 1, Sec. 2.2):
+  * ``membrane_c1``  64x64 periodic, SRT tau=0.8, ellipse 12 x 8 centred at
+    (32, 32), 96 markers, spring constant 0.05 (the elastic-interface relaxation
+    of Sec. 4.2 on a small periodic box).
+  * ``cylinder_c2``  1024x512 channel, MRT, no-slip walls, parabolic inflow
+    u_max=0.05, zero-gradient outflow, rigid circle D=32 at (256, 256) with 101
+    direct-forcing markers (the fixed-cylinder problem of Sec. 4.3 in a channel).
+    ``cylinder_c2(small=True)`` is the 128x64, D=4 copy the oracle runs in full.
+  * ``membrane_c3``  LxL periodic (L=4096 by default), SRT with tau drawn in
+    [0.55, 1.5) and kappa log-uniform in [1e-3, 1e-1) from the seed; ellipse
+    0.3L x 0.2L centred, N = L markers.
+  * ``membrane_batch_c4``  512 independent periodic membrane instances with side
+    L in {64, 96, ..., 512}, aspect ratio in [1, 2), kappa log-uniform in
+    [1e-3, 1e-1), tau in [0.55, 1.5) and N = round(2 x ellipse perimeter).
+
+The marker spacing Delta X is measured on the equilibrium circle of equal area,
+as the paper does for its elastic ellipse (Sec. 4.2): 2*pi*sqrt(a*b)/N for a
+membrane, pi*D/N for the rigid circle.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+# ---------------------------------------------------------------------------
+# SplitMix64
+# ---------------------------------------------------------------------------
+_MASK64 = (1 << 64) - 1
+_GAMMA = 0x9E3779B97F4A7C15
+_MIX1 = 0xBF58476D1CE4E5B9
+_MIX2 = 0x94D049BB133111EB
+
+
+class SplitMix64:
+    """SplitMix64 stream; ``uniform()`` returns top-53-bit doubles in [0, 1).
+
+    The generator is counter based: output j of a stream is the mixing function
+    applied to ``start + (j + 1) * gamma``, which ``uniform_array`` evaluates for
+    many j at once with wrapping uint64 arithmetic."""
+
+    def __init__(self, config: int, instance: int = 0):
+        self.start = ((int(config) << 32) + int(instance)) & _MASK64
+        self.count = 0
+
+    @staticmethod
+    def _mix(z: int) -> int:
+        z = ((z ^ (z >> 30)) * _MIX1) & _MASK64
+        z = ((z ^ (z >> 27)) * _MIX2) & _MASK64
+        return z ^ (z >> 31)
+
+    def next_u64(self) -> int:
+        self.count += 1
+        return self._mix((self.start + self.count * _GAMMA) & _MASK64)
+
+    def uniform(self) -> float:
+        return (self.next_u64() >> 11) * (1.0 / 9007199254740992.0)
+
+    def uniform_array(self, n: int) -> np.ndarray:
+        j = np.arange(self.count + 1, self.count + 1 + n, dtype=np.uint64)
+        self.count += n
+        with np.errstate(over="ignore"):
+            z = np.uint64(self.start) + j * np.uint64(_GAMMA)
+            z = (z ^ (z >> np.uint64(30))) * np.uint64(_MIX1)
+            z = (z ^ (z >> np.uint64(27))) * np.uint64(_MIX2)
+            z = z ^ (z >> np.uint64(31))
+        return (z >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+
+    def normal_array(self, n: int) -> np.ndarray:
+        """n standard normals by Box-Muller on consecutive pairs of uniforms."""
+        m = (n + 1) // 2
+        u = self.uniform_array(2 * m).reshape(m, 2)
+        r = np.sqrt(-2.0 * np.log(np.maximum(u[:, 0], 1e-300)))
+        z = np.stack([r * np.cos(2.0 * np.pi * u[:, 1]), r * np.sin(2.0 * np.pi * u[:, 1])], axis=1)
+        return z.reshape(-1)[:n]
+
+
+# ---------------------------------------------------------------------------
+# Problem description (plain data, mirrored field by field into the C structs)
+# ---------------------------------------------------------------------------
+SRT, MRT = 0, 1
+BC_PERIODIC, BC_WALL, BC_INLET, BC_OUTLET = 0, 1, 2, 3
+IF_NONE, IF_MEMBRANE, IF_RIGID = 0, 1, 2
+FORCE_II_LBM, FORCE_IB_LBM = 0, 1
+STORE_FP32, STORE_FP16 = 0, 1
+
+# D2Q9 MRT relaxation rates printed in Sec. 2.2.1 for the non-conserved moments
+# (energy, energy square, two heat fluxes); the two stress rates are 1/tau.
+PAPER_MRT_RATES = {"e": 1.63, "eps": 1.14, "q": 1.92}
+
+
+@dataclasses.dataclass
+class Problem:
+    nx: int
+    ny: int
+    tau: float
+    collision: int = SRT
+    mrt_s: Optional[Sequence[float]] = None  # 9 rates in moment order, None -> paper's
+    bc: Sequence[int] = (BC_PERIODIC,) * 4   # x-low, x-high, y-low, y-high
+    u_max: float = 0.0                       # inlet parabola peak
+    u_wall: Sequence[float] = (0.0,) * 4     # tangential wall speed per side
+    body_force: Sequence[float] = (0.0, 0.0)  # uniform Eulerian force density
+    interface: int = IF_NONE
+    force_mode: int = FORCE_II_LBM
+    n_markers: int = 0
+    kappa: float = 0.0
+    dX: float = 0.0
+    center: Sequence[float] = (0.0, 0.0)      # rigid circle centre
+    radius: float = 0.0                       # rigid circle radius
+    storage: int = STORE_FP32
+    name: str = ""
+
+    def rates(self) -> List[float]:
+        """The nine MRT rates in the moment order (rho, e, eps, jx, qx, jy, qy, pxx, pxy)."""
+        if self.mrt_s is not None:
+            return [float(v) for v in self.mrt_s]
+        r = PAPER_MRT_RATES
+        st = 1.0 / self.tau
+        return [0.0, r["e"], r["eps"], 0.0, r["q"], 0.0, r["q"], st, st]
+
+
+@dataclasses.dataclass
+class Workload:
+    problem: Problem
+    X0: np.ndarray           # (N, 2) float64 initial markers, CCW
+    steps: int
+    meta: dict
+
+
+def ellipse_markers(cx: float, cy: float, a: float, b: float, n: int) -> np.ndarray:
+    """n markers at equal parameter angle on the ellipse, counter-clockwise."""
+    k = np.arange(n, dtype=np.float64)
+    th = 2.0 * np.pi * k / n
+    X = np.empty((n, 2), dtype=np.float64)
+    X[:, 0] = cx + a * np.cos(th)
+    X[:, 1] = cy + b * np.sin(th)
+    return X
+
+
+def circle_markers(cx: float, cy: float, r: float, n: int) -> np.ndarray:
+    return ellipse_markers(cx, cy, r, r, n)
+
+
+def membrane_dX(a: float, b: float, n: int) -> float:
+    """Marker spacing on the equal-area equilibrium circle (Sec. 4.2)."""
+    return 2.0 * math.pi * math.sqrt(a * b) / n
+
+
+def ramanujan_perimeter(a: float, b: float) -> float:
+    h = ((a - b) / (a + b)) ** 2
+    return math.pi * (a + b) * (1.0 + 3.0 * h / (10.0 + math.sqrt(4.0 - 3.0 * h)))
+
+
+# ---------------------------------------------------------------------------
+# The workloads
+# ---------------------------------------------------------------------------
+def membrane_c1(storage: int = STORE_FP32) -> Workload:
+    nx = ny = 64
+    a, b, n = 12.0, 8.0, 96
+    X0 = ellipse_markers(32.0, 32.0, a, b, n)
+    p = Problem(nx=nx, ny=ny, tau=0.8, collision=SRT, interface=IF_MEMBRANE,
+                n_markers=n, kappa=0.05, dX=membrane_dX(a, b, n), storage=storage,
+                name="membrane64")
+    return Workload(p, X0, 2000, {"a": a, "b": b})
+
+
+def cylinder_c2(re: float = 20.0, small: bool = False, storage: int = STORE_FP32) -> Workload:
+    """Channel flow past a fixed circle; tau from Re = U_mean*D/nu with U_mean = 2/3 u_max."""
+    if small:
+        nx, ny, D, n, cx, cy = 128, 64, 4.0, 13, 32.0, 32.0
+    else:
+        nx, ny, D, n, cx, cy = 1024, 512, 32.0, 101, 256.0, 256.0
+    u_max = 0.05
+    u_mean = 2.0 * u_max / 3.0
+    # The small copy keeps the full run's tau (its own Re is then D/32 of it).
+    nu = u_mean * 32.0 / re
+    tau = 0.5 + 3.0 * nu
+    X0 = circle_markers(cx, cy, D / 2.0, n)
+    p = Problem(nx=nx, ny=ny, tau=tau, collision=MRT,
+                bc=(BC_INLET, BC_OUTLET, BC_WALL, BC_WALL), u_max=u_max,
+                interface=IF_RIGID, n_markers=n, kappa=0.0,
+                dX=math.pi * D / n, center=(cx, cy), radius=D / 2.0, storage=storage,
+                name=f"cylinder{nx}x{ny}_D{int(D)}_Re{int(re)}")
+    return Workload(p, X0, 20000, {"D": D, "re": re, "u_mean": u_mean})
+
+
+def membrane_c3(L: int = 4096, seed: int = 0, storage: int = STORE_FP32,
+                n_markers: Optional[int] = None) -> Workload:
+    rng = SplitMix64(3, seed)
+    u0, u1 = rng.uniform(), rng.uniform()
+    tau = 0.55 + 0.95 * u0
+    kappa = 10.0 ** (-3.0 + 2.0 * u1)
+    a, b = 0.3 * L, 0.2 * L
+    n = L if n_markers is None else n_markers
+    X0 = ellipse_markers(L / 2.0, L / 2.0, a, b, n)
+    p = Problem(nx=L, ny=L, tau=tau, collision=SRT, interface=IF_MEMBRANE,
+                n_markers=n, kappa=kappa, dX=membrane_dX(a, b, n), storage=storage,
+                name=f"membrane{L}_seed{seed}")
+    return Workload(p, X0, 5000, {"a": a, "b": b, "seed": seed})
+
+
+def membrane_batch_c4(n_inst: int = 512, first: int = 0) -> List[Workload]:
+    out = []
+    for i in range(first, first + n_inst):
+        rng = SplitMix64(4, i)
+        u0, u1, u2, u3 = rng.uniform(), rng.uniform(), rng.uniform(), rng.uniform()
+        L = 64 + 32 * int(math.floor(15.0 * u0))
+        ar = 1.0 + u1
+        kappa = 10.0 ** (-3.0 + 2.0 * u2)
+        tau = 0.55 + 0.95 * u3
+        r_eq = math.sqrt(0.06) * L
+        a, b = r_eq * math.sqrt(ar), r_eq / math.sqrt(ar)
+        n = int(round(2.0 * ramanujan_perimeter(a, b)))
+        X0 = ellipse_markers(L / 2.0, L / 2.0, a, b, n)
+        p = Problem(nx=L, ny=L, tau=tau, collision=SRT, interface=IF_MEMBRANE,
+                    n_markers=n, kappa=kappa, dX=membrane_dX(a, b, n),
+                    name=f"batch{i}_L{L}")
+        out.append(Workload(p, X0, 4000, {"a": a, "b": b, "ar": ar, "instance": i}))
+    return out
+
+
+def seeded_noise(shape, config: int, instance: int) -> np.ndarray:
+    """Seeded standard-normal array of the given shape (stream (config, instance)).
+    Tests scale it into perturbed distribution fields; it carries no physics."""
+    rng = SplitMix64(config, instance)
+    n = int(np.prod(shape))
+    return rng.normal_array(n).reshape(shape)
