@@ -1,0 +1,141 @@
+"""Throughput of the II-LBM hot path on one MI355X.
+
+One step = one full II-LBM time step of the 4096 x 4096 periodic membrane
+workload (ellipse 0.3L x 0.2L, 4096 markers, seeded tau and kappa): marker
+interpolation/force/binning, the fused collide + pull-stream sweep over every
+node, and the per-tile tangential spread + cut-link jump pass.  Inputs are
+resident in HBM before the timed region.
+
+Prints one JSON line: MLUPS (whole job), the roofline of the dominant kernel
+(the sweep, HBM bound, algorithmic bytes over its HIP-event-timed duration)
+and the FP64 CPU oracle timed on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--storage fp32|fp16] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "sweep_traffic_membrane4096.json")
+SWEEP_SOURCES = [os.path.join(ROOT, "paper_2003_12186_amd", "csrc", n) for n in ("sweep.hip", "common.hpp")]
+
+
+def sweep_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in SWEEP_SOURCES:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(storage: str):
+    """HBM bytes per sweep launch from committed rocprofv3 counter runs, only
+    while the sweep source is unchanged since they were taken."""
+    try:
+        d = json.load(open(PROFILE_TRAFFIC))
+    except (OSError, ValueError):
+        return None
+    ent = d.get(storage)
+    if not ent or ent.get("source_hash") != sweep_source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(w, steps: int):
+    import numpy as np  # noqa: F401
+    import oracle as O
+    p = O.make_problem(w.problem)
+    f = O.rest_state(p)
+    X = w.X0.copy()
+    O.run(p, f, X, 1)                      # first-touch of the arrays, not timed
+    t0 = time.perf_counter()
+    O.run(p, f, X, steps)
+    dt = time.perf_counter() - t0
+    mlups = p.nx * p.ny * steps / dt / 1e6
+    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"{steps} FP64 oracle steps of the same {p.nx}x{p.ny} workload after 1 untimed step "
+                      f"({dt:.1f} s)"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--storage", choices=["fp32", "fp16"], default="fp32")
+    ap.add_argument("--size", type=int, default=4096)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the design notes describe how the lattice would shard).", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2003_12186_amd import binding as B
+    from paper_2003_12186_amd import workloads as W
+
+    storage = W.STORE_FP16 if args.storage == "fp16" else W.STORE_FP32
+    w = W.membrane_c3(L=args.size, storage=storage)
+    p = w.problem
+    sim = B.Sim([p], [w.X0], device="cuda:0")
+    sim.step(args.warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    sim.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    sim.sync()
+    sweep_ms, launches = sim.get_timing()
+    sim.set_timing(False)
+    d = sim.diag()
+
+    lu = p.nx * p.ny * args.steps
+    mlups = lu / dt / 1e6
+    bytes_per_launch = sim.sweep_bytes()
+    avg_sweep_s = sweep_ms / 1e3 / max(launches, 1)
+    achieved = bytes_per_launch / avg_sweep_s / 1e9
+    traffic = measured_traffic(args.storage)
+    out = {
+        "metric": "MLUPS & %HBM peak; learned 2x-coarse vs fine II-LBM time at <=1e-2 L2 err",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt * 1e3 / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if storage == W.STORE_FP32 else "f32 math / f16 storage",
+        "data": "synthetic",
+        "config": {"workload": f"membrane{p.nx}_periodic_srt_{args.storage}",
+                   "nx": p.nx, "ny": p.ny, "markers": p.n_markers, "tau": round(p.tau, 6),
+                   "kappa": p.kappa, "storage": args.storage,
+                   "cut_links": d["n_cut_links"]},
+        "roofline": {"bound": "hbm", "kernel": "k_sweep", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "bytes_per_launch": bytes_per_launch,
+                     "avg_launch_us": round(avg_sweep_s * 1e6, 2), "timed_launches": launches},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+    sim.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,213 @@
+/*
+ * ii_lbm.h -- C ABI of the MI355X (gfx950) implementation of the D2Q9
+ * immersed interface-lattice Boltzmann method (II-LBM) of Qin, Kolahdouz &
+ * Griffith, "An immersed interface-lattice Boltzmann method for
+ * fluid-structure interaction" (arXiv:2003.12186).
+ *
+ * The library advances, on one GPU, a fluid on a D2Q9 lattice (Sec. 2.2.1)
+ * with a closed immersed interface carried by Lagrangian markers:
+ *   - the normal part of the interface force enters through the jump of the
+ *     distribution functions on every lattice link the interface cuts
+ *     ([[f_i]] = w_i G.n / (c_s^2 |dX/ds|), Sec. 3.1 Eq. (32), applied as in
+ *     the jump-corrected update of Sec. 3.2 Eq. (47));
+ *   - the tangential part is spread with Peskin's four-point delta
+ *     (Sec. 3.2 Eq. (46)) into the simple force term of Sec. 2.2.2 Eq. (16);
+ *   - marker velocities are interpolated with the same delta and the markers
+ *     move with them (Sec. 2.2.2 Eq. (20)).
+ * Lattice units throughout: dx = dt = 1 (Sec. 2.2).
+ *
+ * Conventions shared by every call
+ *   - D2Q9 populations are numbered e0=(0,0) e1=(1,0) e2=(0,1) e3=(-1,0)
+ *     e4=(0,-1) e5=(1,1) e6=(-1,1) e7=(-1,-1) e8=(1,-1).
+ *   - Field planes are row-major [ny][nx], x fastest.
+ *   - Markers are interleaved (x, y) pairs in FP64, ordered counter-clockwise;
+ *     the interior of the closed curve is Omega^- (Sec. 2, Fig. 1).
+ *   - All calls return 0 (II_LBM_OK) or a negative error code; none throws.
+ *     Errors raised on the device are sticky: they are reported by the next
+ *     call that synchronises (markers, fields, diag, cutlinks, sync) and the
+ *     handle then refuses further steps (II_LBM_ESTATE) until destroyed.
+ *   - A handle is used by one host thread at a time.  All device work of a
+ *     handle is enqueued on the HIP stream given at init.
+ */
+#ifndef II_LBM_H
+#define II_LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------- */
+#define II_LBM_OK 0
+#define II_LBM_EINVAL (-1)     /* invalid problem or argument */
+#define II_LBM_EWORKSPACE (-2) /* workspace missing, misaligned or too small */
+#define II_LBM_EDEVICE (-3)    /* a HIP call failed */
+#define II_LBM_EUNSTABLE (-4)  /* non-finite state (the run blew up) */
+#define II_LBM_EGEOMETRY (-5)  /* markers left the region the kernels support */
+#define II_LBM_ESTATE (-6)     /* call on a handle that already failed */
+#define II_LBM_ECAPACITY (-7)  /* interface too dense for a tile's chord list */
+
+/* ---- problem description ----------------------------------------------- */
+enum { II_LBM_SRT = 0, II_LBM_MRT = 1 };
+enum { II_LBM_BC_PERIODIC = 0, II_LBM_BC_WALL = 1, II_LBM_BC_INLET = 2, II_LBM_BC_OUTLET = 3 };
+enum { II_LBM_IF_NONE = 0, II_LBM_IF_MEMBRANE = 1, II_LBM_IF_RIGID = 2 };
+enum { II_LBM_FORCE_II = 0 };
+enum { II_LBM_FP32 = 0, II_LBM_FP16 = 1 };
+
+/*
+ * One simulation instance.
+ *  nx, ny       lattice size, 8 <= nx, ny <= 8192.
+ *  tau          relaxation time lambda of Sec. 2.2.1 (nu = (tau - 1/2)/3), > 0.5.
+ *  collision    II_LBM_SRT (Eq. (14)) or II_LBM_MRT (Eq. (15)).
+ *  mrt_s        the nine MRT rates in the moment order (rho, e, eps, jx, qx,
+ *               jy, qy, pxx, pxy); all nine zero selects the rates of
+ *               Sec. 2.2.1 (1.63, 1.14, 1.92 and 1/tau for the stresses).
+ *  bc           x-low, x-high, y-low, y-high side; an axis is periodic on both
+ *               sides or on neither.  Non-periodic sides use non-equilibrium
+ *               extrapolation from the inward neighbour (as cited in Sec. 4):
+ *               WALL (velocity u_wall along the side), INLET (parabola
+ *               4 u_max y (H - y) / H^2 with H = ny - 1; x-low only), OUTLET
+ *               (zero gradient; x-high only).  Corner nodes follow the y side.
+ *  body_force   uniform Eulerian force density added to the force term.
+ *  interface_kind  NONE, MEMBRANE (spring force kappa (X_{k+1} - 2 X_k +
+ *               X_{k-1}) / dX^2, Sec. 2.2.2 Eq. (19)) or RIGID (fixed circle
+ *               with direct forcing G = U^D - U*, eta = 1, U^D = 0, Sec. 2.2.2
+ *               Eq. (18); cut links from the circle's level set, Sec. 3.2).
+ *  n_markers    3 <= N <= 1<<20 markers.
+ *  kappa, dX    spring constant and marker spacing Delta X (> 0, <= 2).
+ *  center, radius  the rigid circle (RIGID only).
+ *  storage      II_LBM_FP32 or II_LBM_FP16: distributions are stored as
+ *               deviations d_i = f_i - w_i rho0 (rho0 = 1); arithmetic is FP32.
+ *  fp16_log2_scale  FP16 storage holds d_i * 2^-fp16_log2_scale; 0 lets the
+ *               library choose it from the initial interface force.
+ * Markers must stay at least 3 lattice units from every side of the lattice.
+ */
+typedef struct ii_lbm_problem {
+    int32_t nx, ny;
+    double tau;
+    int32_t collision;
+    double mrt_s[9];
+    int32_t bc[4];
+    double u_max;
+    double u_wall[4];
+    double body_force[2];
+    int32_t interface_kind;
+    int32_t force_mode;
+    int32_t n_markers;
+    double kappa, dX;
+    double center[2];
+    double radius;
+    int32_t storage;
+    int32_t fp16_log2_scale;
+} ii_lbm_problem;
+
+/* One cut link, as built for the step that last ran: the link from source
+ * node (x, y) to (x, y) + e_dir crosses the interface; sigma = +1 when it
+ * runs from the interior to the exterior and -1 otherwise (Sec. 3.2).  seg is
+ * the chord (markers seg, seg+1) for membranes, the marker interval
+ * [seg, seg+1] for the rigid circle; q is the fraction along the link to the
+ * cut point, theta the fraction along the chord/interval, jp = [[p]] there. */
+typedef struct ii_lbm_link {
+    int32_t x, y, dir, sigma, seg, inst;
+    double q, theta, jp;
+} ii_lbm_link;
+
+typedef struct ii_lbm_diag_t {
+    int64_t step;          /* steps taken since init */
+    double mass;           /* sum of rho over the lattice (FP64) */
+    double momentum[2];    /* sum of u = sum_i e_i f_i */
+    double area;           /* shoelace area of the marker polygon */
+    double force[2];       /* force on the body F = -sum_k G_k dX (Sec. 2.3 Eq. (25)) */
+    int32_t n_cut_links;   /* directed (link, chord) crossings of the last step */
+    int32_t error_bits;    /* device error flags (0 when healthy) */
+} ii_lbm_diag_t;
+
+typedef struct ii_lbm_handle ii_lbm_handle;
+
+/* Device bytes that init needs for n_inst instances (problems p[0..n_inst-1]).
+ * Pure function of its arguments; no device access. */
+int ii_lbm_workspace_size(const ii_lbm_problem* p, int32_t n_inst, size_t* bytes);
+
+/*
+ * Creates a handle.
+ *  p          n_inst problems (copied).
+ *  X0         n_inst host pointers, X0[j] holds 2 * p[j].n_markers doubles
+ *             (interleaved, counter-clockwise); copied.
+ *  d_workspace device memory of at least ws_bytes = ii_lbm_workspace_size
+ *             bytes, 256-byte aligned, owned by the caller and kept alive until
+ *             ii_lbm_destroy; NULL makes the library allocate (and free) it.
+ *  hip_stream hipStream_t on which all work is enqueued (NULL = default).
+ * The fluid starts at rest, f_i = w_i rho0.  Synchronises before returning.
+ */
+int ii_lbm_init(const ii_lbm_problem* p, int32_t n_inst, const double* const* X0,
+                void* d_workspace, size_t ws_bytes, void* hip_stream, ii_lbm_handle** out);
+
+/* Enqueues n_steps time steps of every instance and returns without waiting. */
+int ii_lbm_step(ii_lbm_handle* h, int64_t n_steps);
+
+/* Waits for the handle's stream and reports sticky device errors. */
+int ii_lbm_sync(ii_lbm_handle* h);
+
+/* Synchronises, then copies 2N doubles of the current marker positions X^n,
+ * and of U and G of the last step, into caller-owned host buffers (any may be
+ * NULL). */
+int ii_lbm_markers(ii_lbm_handle* h, int32_t inst, double* X, double* U, double* G);
+
+/* Replaces the marker positions of one instance (2N doubles, host). */
+int ii_lbm_set_markers(ii_lbm_handle* h, int32_t inst, const double* X);
+
+#define II_LBM_F_RHO 1u     /* rho = sum_i f_i */
+#define II_LBM_F_UX 2u      /* u_x = sum_i e_ix f_i */
+#define II_LBM_F_UY 4u      /* u_y */
+#define II_LBM_F_P 8u       /* p = rho / 3 */
+#define II_LBM_F_DISTRIB 16u /* the nine f_i^n planes, population order */
+enum { II_LBM_DT_F32 = 0, II_LBM_DT_F64 = 1 };
+
+/* Synchronises, then writes the requested planes of the current state f^n
+ * (the distributions after streaming, jumps and boundaries, i.e. what the
+ * next collision reads), in bit order RHO, UX, UY, P, DISTRIB, each [ny][nx],
+ * as FP32 or FP64, into `out` (device memory when on_device, else host). */
+int ii_lbm_fields(ii_lbm_handle* h, int32_t inst, uint32_t what, void* out, int32_t dtype,
+                  int32_t on_device);
+
+/* Sets the state of one instance from nine host planes f[9][ny][nx] (FP64,
+ * full distributions): the next step collides exactly this field (periodic
+ * axes; on non-periodic sides the boundary nodes are re-derived by the
+ * extrapolation). */
+int ii_lbm_set_distrib(ii_lbm_handle* h, int32_t inst, const double* f);
+
+/* Raw state for checkpoint/restart: the stored lattice in its storage
+ * precision plus the markers and the step counter.  A handle restored with
+ * ii_lbm_load_state continues bit-identically. */
+int ii_lbm_state_size(ii_lbm_handle* h, int32_t inst, size_t* bytes);
+int ii_lbm_save_state(ii_lbm_handle* h, int32_t inst, void* host_buf, size_t bytes);
+int ii_lbm_load_state(ii_lbm_handle* h, int32_t inst, const void* host_buf, size_t bytes);
+
+/* Synchronises, then copies up to `cap` cut-link records of the last step of
+ * one instance into a host buffer; *count receives the total number (which
+ * may exceed cap).  Records are in no particular order. */
+int ii_lbm_cutlinks(ii_lbm_handle* h, int32_t inst, ii_lbm_link* out, int32_t cap, int32_t* count);
+
+/* Synchronises and fills FP64 diagnostics of one instance. */
+int ii_lbm_diag(ii_lbm_handle* h, int32_t inst, ii_lbm_diag_t* out);
+
+/* Kernel timing of the dense collide-and-stream sweep: while enabled, every
+ * sweep launch of ii_lbm_step is bracketed by HIP events on the handle's
+ * stream; get_timing synchronises and returns the summed milliseconds and
+ * the number of timed launches, then clears them. */
+int ii_lbm_set_timing(ii_lbm_handle* h, int32_t enable);
+int ii_lbm_get_timing(ii_lbm_handle* h, double* sweep_ms, int64_t* launches);
+
+/* Bytes of HBM one sweep of one instance must move: nine loads and nine
+ * stores of the stored deviation per node. */
+int ii_lbm_sweep_bytes(ii_lbm_handle* h, int32_t inst, double* bytes);
+
+int ii_lbm_destroy(ii_lbm_handle* h);
+const char* ii_lbm_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -90,6 +90,7 @@ def lib():
             "or_pressure_jump": (C.c_double, [P, d, d, C.c_double]),
             "or_sizeof_link": (C.c_int, []),
             "or_sizeof_problem": (C.c_int, []),
+            "or_num_threads": (C.c_int, []),
         }
         for name, (res, args) in sig.items():
             fn = getattr(_lib, name)
@@ -262,6 +263,10 @@ def run(p: Problem, f: np.ndarray, X: np.ndarray, n_steps: int, force_hist: bool
     if rc != 0:
         raise RuntimeError("oracle run: a cut link left the lattice")
     return fh
+
+
+def num_threads() -> int:
+    return int(lib().or_num_threads())
 
 
 def polygon_area(X) -> float:

@@ -726,4 +726,12 @@ double or_pressure_jump(const or_problem *p, const double *rho, const double *X,
 }
 
 int or_sizeof_link(void) { return (int)sizeof(or_link); }
+
+/* Threads the OpenMP loops of the oracle use (1 without OpenMP). */
+#ifdef _OPENMP
+#include <omp.h>
+int or_num_threads(void) { return omp_get_max_threads(); }
+#else
+int or_num_threads(void) { return 1; }
+#endif
 int or_sizeof_problem(void) { return (int)sizeof(or_problem); }

@@ -1,0 +1,257 @@
+"""ctypes binding of ``libiilbm.so``: the same calls as ``include/ii_lbm.h``,
+argument marshalling only.  Every step of the method runs in the library's
+HIP kernels; there is no CPU fallback, and importing this module fails loudly
+when the library has not been built.
+
+PyTorch is used only to own device memory (the workspace) and to provide the
+HIP stream the library enqueues on.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libiilbm.so")
+
+OK, EINVAL, EWORKSPACE, EDEVICE, EUNSTABLE, EGEOMETRY, ESTATE, ECAPACITY = 0, -1, -2, -3, -4, -5, -6, -7
+F_RHO, F_UX, F_UY, F_P, F_DISTRIB = 1, 2, 4, 8, 16
+DT_F32, DT_F64 = 0, 1
+
+
+class Problem(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("tau", C.c_double),
+                ("collision", C.c_int32), ("mrt_s", C.c_double * 9), ("bc", C.c_int32 * 4),
+                ("u_max", C.c_double), ("u_wall", C.c_double * 4), ("body_force", C.c_double * 2),
+                ("interface_kind", C.c_int32), ("force_mode", C.c_int32), ("n_markers", C.c_int32),
+                ("kappa", C.c_double), ("dX", C.c_double), ("center", C.c_double * 2),
+                ("radius", C.c_double), ("storage", C.c_int32), ("fp16_log2_scale", C.c_int32)]
+
+
+class Link(C.Structure):
+    _fields_ = [("x", C.c_int32), ("y", C.c_int32), ("dir", C.c_int32), ("sigma", C.c_int32),
+                ("seg", C.c_int32), ("inst", C.c_int32), ("q", C.c_double),
+                ("theta", C.c_double), ("jp", C.c_double)]
+
+
+LINK_DTYPE = np.dtype([("x", "<i4"), ("y", "<i4"), ("dir", "<i4"), ("sigma", "<i4"),
+                       ("seg", "<i4"), ("inst", "<i4"), ("q", "<f8"), ("theta", "<f8"),
+                       ("jp", "<f8")])
+
+
+class Diag(C.Structure):
+    _fields_ = [("step", C.c_int64), ("mass", C.c_double), ("momentum", C.c_double * 2),
+                ("area", C.c_double), ("force", C.c_double * 2), ("n_cut_links", C.c_int32),
+                ("error_bits", C.c_int32)]
+
+
+EXPORTS = [
+    "ii_lbm_workspace_size", "ii_lbm_init", "ii_lbm_step", "ii_lbm_sync", "ii_lbm_markers",
+    "ii_lbm_set_markers", "ii_lbm_fields", "ii_lbm_set_distrib", "ii_lbm_state_size",
+    "ii_lbm_save_state", "ii_lbm_load_state", "ii_lbm_cutlinks", "ii_lbm_diag",
+    "ii_lbm_set_timing", "ii_lbm_get_timing", "ii_lbm_sweep_bytes", "ii_lbm_destroy",
+    "ii_lbm_strerror",
+]
+
+_lib = None
+
+
+def load():
+    """Load the built library (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2003_12186_amd.build` "
+                          "(or __graft_entry__.build())")
+    lib = C.CDLL(LIB_PATH)
+    v, i32, i64, sz, d = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t, C.c_double
+    PP = C.POINTER(Problem)
+    sig = {
+        "ii_lbm_workspace_size": [PP, i32, C.POINTER(sz)],
+        "ii_lbm_init": [PP, i32, C.POINTER(C.POINTER(C.c_double)), v, sz, v, C.POINTER(v)],
+        "ii_lbm_step": [v, i64],
+        "ii_lbm_sync": [v],
+        "ii_lbm_markers": [v, i32, v, v, v],
+        "ii_lbm_set_markers": [v, i32, v],
+        "ii_lbm_fields": [v, i32, C.c_uint32, v, i32, i32],
+        "ii_lbm_set_distrib": [v, i32, v],
+        "ii_lbm_state_size": [v, i32, C.POINTER(sz)],
+        "ii_lbm_save_state": [v, i32, v, sz],
+        "ii_lbm_load_state": [v, i32, v, sz],
+        "ii_lbm_cutlinks": [v, i32, v, i32, C.POINTER(i32)],
+        "ii_lbm_diag": [v, i32, C.POINTER(Diag)],
+        "ii_lbm_set_timing": [v, i32],
+        "ii_lbm_get_timing": [v, C.POINTER(d), C.POINTER(i64)],
+        "ii_lbm_sweep_bytes": [v, i32, C.POINTER(d)],
+        "ii_lbm_destroy": [v],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    lib.ii_lbm_strerror.argtypes = [C.c_int]
+    lib.ii_lbm_strerror.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+class IILBMError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = load().ii_lbm_strerror(code).decode()
+        super().__init__(f"{where}: {msg} ({code})")
+
+
+def check(code: int, where: str) -> None:
+    if code != OK:
+        raise IILBMError(code, where)
+
+
+def make_problem(w) -> Problem:
+    """C problem from a ``workloads.Problem``."""
+    p = Problem()
+    p.nx, p.ny, p.tau = int(w.nx), int(w.ny), float(w.tau)
+    p.collision = int(w.collision)
+    if w.mrt_s is not None:
+        for a in range(9):
+            p.mrt_s[a] = float(w.mrt_s[a])
+    for s in range(4):
+        p.bc[s] = int(w.bc[s])
+        p.u_wall[s] = float(w.u_wall[s])
+    p.u_max = float(w.u_max)
+    p.body_force[0], p.body_force[1] = float(w.body_force[0]), float(w.body_force[1])
+    p.interface_kind = int(w.interface)
+    p.force_mode = int(w.force_mode)
+    p.n_markers = int(w.n_markers)
+    p.kappa, p.dX = float(w.kappa), float(w.dX)
+    p.center[0], p.center[1] = float(w.center[0]), float(w.center[1])
+    p.radius = float(w.radius)
+    p.storage = int(w.storage)
+    p.fp16_log2_scale = int(getattr(w, "fp16_log2_scale", 0))
+    return p
+
+
+def workspace_size(problems: Sequence[Problem]) -> int:
+    arr = (Problem * len(problems))(*problems)
+    n = C.c_size_t()
+    check(load().ii_lbm_workspace_size(arr, len(problems), C.byref(n)), "workspace_size")
+    return n.value
+
+
+class Sim:
+    """A handle of the library with its torch-owned workspace and stream."""
+
+    def __init__(self, problems: Sequence, X0: Sequence[Optional[np.ndarray]], device: str = "cuda:0",
+                 stream=None):
+        import torch
+
+        lib = load()
+        self.problems: List[Problem] = [p if isinstance(p, Problem) else make_problem(p) for p in problems]
+        n = len(self.problems)
+        self.n_inst = n
+        arr = (Problem * n)(*self.problems)
+        self._X0 = []
+        ptrs = (C.POINTER(C.c_double) * n)()
+        for j in range(n):
+            x = np.zeros((1, 2)) if X0[j] is None else np.ascontiguousarray(X0[j], dtype=np.float64)
+            self._X0.append(x)
+            ptrs[j] = x.ctypes.data_as(C.POINTER(C.c_double))
+        nbytes = workspace_size(self.problems)
+        self.device = torch.device(device)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        check(lib.ii_lbm_init(arr, n, ptrs, C.c_void_p(self.workspace.data_ptr()), nbytes,
+                              C.c_void_p(self.stream.cuda_stream), C.byref(h)), "init")
+        self.h = h
+
+    # -- stepping ------------------------------------------------------------
+    def step(self, n: int = 1) -> None:
+        check(load().ii_lbm_step(self.h, int(n)), "step")
+
+    def sync(self) -> None:
+        check(load().ii_lbm_sync(self.h), "sync")
+
+    # -- readout -------------------------------------------------------------
+    def markers(self, inst: int = 0):
+        N = self.problems[inst].n_markers
+        X = np.zeros((N, 2)); U = np.zeros((N, 2)); G = np.zeros((N, 2))
+        check(load().ii_lbm_markers(self.h, inst, X.ctypes.data, U.ctypes.data, G.ctypes.data), "markers")
+        return X, U, G
+
+    def set_markers(self, X: np.ndarray, inst: int = 0) -> None:
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        check(load().ii_lbm_set_markers(self.h, inst, X.ctypes.data), "set_markers")
+
+    def fields(self, what: int = F_RHO | F_UX | F_UY, inst: int = 0, dtype=np.float64) -> np.ndarray:
+        p = self.problems[inst]
+        planes = sum((what >> b) & 1 for b in range(4)) + (9 if what & F_DISTRIB else 0)
+        out = np.zeros((planes, p.ny, p.nx), dtype=dtype)
+        dt = DT_F64 if dtype == np.float64 else DT_F32
+        check(load().ii_lbm_fields(self.h, inst, what, out.ctypes.data, dt, 0), "fields")
+        return out
+
+    def fields_device(self, what: int, out, inst: int = 0) -> None:
+        """Write planes into a caller-owned torch CUDA tensor (float32 or float64)."""
+        import torch
+        dt = DT_F64 if out.dtype == torch.float64 else DT_F32
+        check(load().ii_lbm_fields(self.h, inst, what, C.c_void_p(out.data_ptr()), dt, 1), "fields")
+
+    def set_distrib(self, f: np.ndarray, inst: int = 0) -> None:
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        p = self.problems[inst]
+        assert f.shape == (9, p.ny, p.nx)
+        check(load().ii_lbm_set_distrib(self.h, inst, f.ctypes.data), "set_distrib")
+
+    def save_state(self, inst: int = 0) -> bytes:
+        n = C.c_size_t()
+        check(load().ii_lbm_state_size(self.h, inst, C.byref(n)), "state_size")
+        buf = C.create_string_buffer(n.value)
+        check(load().ii_lbm_save_state(self.h, inst, buf, n.value), "save_state")
+        return buf.raw
+
+    def load_state(self, blob: bytes, inst: int = 0) -> None:
+        check(load().ii_lbm_load_state(self.h, inst, blob, len(blob)), "load_state")
+
+    def cutlinks(self, inst: int = 0) -> np.ndarray:
+        cnt = C.c_int32()
+        check(load().ii_lbm_cutlinks(self.h, inst, None, 0, C.byref(cnt)), "cutlinks")
+        out = np.zeros(max(cnt.value, 1), dtype=LINK_DTYPE)
+        check(load().ii_lbm_cutlinks(self.h, inst, out.ctypes.data, len(out), C.byref(cnt)), "cutlinks")
+        return out[:cnt.value].copy()
+
+    def diag(self, inst: int = 0) -> dict:
+        d = Diag()
+        check(load().ii_lbm_diag(self.h, inst, C.byref(d)), "diag")
+        return {"step": d.step, "mass": d.mass, "momentum": (d.momentum[0], d.momentum[1]),
+                "area": d.area, "force": (d.force[0], d.force[1]), "n_cut_links": d.n_cut_links,
+                "error_bits": d.error_bits}
+
+    # -- timing --------------------------------------------------------------
+    def set_timing(self, enable: bool) -> None:
+        check(load().ii_lbm_set_timing(self.h, 1 if enable else 0), "set_timing")
+
+    def get_timing(self):
+        ms = C.c_double(); n = C.c_int64()
+        check(load().ii_lbm_get_timing(self.h, C.byref(ms), C.byref(n)), "get_timing")
+        return ms.value, n.value
+
+    def sweep_bytes(self, inst: int = 0) -> float:
+        b = C.c_double()
+        check(load().ii_lbm_sweep_bytes(self.h, inst, C.byref(b)), "sweep_bytes")
+        return b.value
+
+    def close(self) -> None:
+        if getattr(self, "h", None) is not None and self.h.value:
+            load().ii_lbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

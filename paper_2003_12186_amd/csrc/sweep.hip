@@ -1,0 +1,233 @@
+// Dense lattice kernels: the fused pull-stream + collide sweep (the hot loop,
+// nine loads and nine stores per node), the field readout, state set-up and
+// the FP64 reductions for diagnostics.
+#include "common.hpp"
+
+namespace iilbm {
+
+// One time step of the bulk: gather f^n at (x, y) (pulled populations that
+// already carry the previous step's jumps and force; extrapolated on bounded
+// sides), collide (SRT or MRT) with the uniform body force, store the
+// post-collision populations at (x, y).  The interface kernel then adds the
+// tangential force and the jumps of this step to the stored values of the
+// few nodes near the interface.
+template <typename T, int COLL, bool BOUNDED>
+__global__ __launch_bounds__(kSweepBX* kSweepBY) void k_sweep(InstDev I,
+                                                             const T* __restrict__ A,
+                                                             T* __restrict__ B, int bx_count)
+{
+    const int bx = blockIdx.x % bx_count, by = blockIdx.x / bx_count;
+    const int x = bx * kSweepBX + threadIdx.x;
+    const int y = by * kSweepBY + threadIdx.y;
+    if (x >= I.nx || y >= I.ny) return;
+    float d[9];
+    if (BOUNDED && is_edge(I, x, y))
+        nee<T>(I, A, x, y, d);
+    else
+        pull<T>(I, A, x, y, d);
+    if (COLL == II_LBM_SRT)
+        collide_srt(d, I.omega, I.body[0], I.body[1]);
+    else
+        collide_mrt(d, I.s, I.body[0], I.body[1]);
+    T* base = B + I.lat_off + (long long)y * I.pitch + x;
+#pragma unroll
+    for (int i = 0; i < 9; i++) Store<T>::st(base + i * I.plane, d[i], I.inv_scale);
+}
+
+template <typename T, int COLL, bool BOUNDED>
+static hipError_t sweep_t(const InstDev& I, const void* A, void* B, hipStream_t s)
+{
+    const int bxn = (I.nx + kSweepBX - 1) / kSweepBX;
+    const int byn = (I.ny + kSweepBY - 1) / kSweepBY;
+    hipLaunchKernelGGL((k_sweep<T, COLL, BOUNDED>), dim3(bxn * byn), dim3(kSweepBX, kSweepBY), 0,
+                       s, I, (const T*)A, (T*)B, bxn);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t sweep_s(const InstDev& I, const void* A, void* B, hipStream_t s)
+{
+    if (I.collision == II_LBM_SRT)
+        return I.bounded ? sweep_t<T, II_LBM_SRT, true>(I, A, B, s)
+                         : sweep_t<T, II_LBM_SRT, false>(I, A, B, s);
+    return I.bounded ? sweep_t<T, II_LBM_MRT, true>(I, A, B, s)
+                     : sweep_t<T, II_LBM_MRT, false>(I, A, B, s);
+}
+
+hipError_t launch_sweep(const InstDev& I, const void* A, void* B, hipStream_t s)
+{
+    return I.storage == II_LBM_FP16 ? sweep_s<_Float16>(I, A, B, s) : sweep_s<float>(I, A, B, s);
+}
+
+// ---------------------------------------------------------------------------
+// Zero fill (rest state d = 0) of one instance's lattice region.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_fill_zero(T* p, long long n)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = (T)0;
+}
+
+hipError_t launch_fill_zero(const InstDev& I, void* A, hipStream_t s)
+{
+    const long long n = 9 * I.plane;
+    if (I.storage == II_LBM_FP16)
+        hipLaunchKernelGGL(k_fill_zero<_Float16>, dim3(2048), dim3(256), 0, s,
+                           (_Float16*)A + I.lat_off, n);
+    else
+        hipLaunchKernelGGL(k_fill_zero<float>, dim3(2048), dim3(256), 0, s, (float*)A + I.lat_off,
+                           n);
+    return hipGetLastError();
+}
+
+__global__ void k_zero_ints(int* p, long long n)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+hipError_t launch_zero_ints(int* p, long long n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_ints, dim3(1024), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Field readout of f^n: planes in bit order RHO, UX, UY, P, DISTRIB(9).
+// ---------------------------------------------------------------------------
+template <typename T, typename O>
+__global__ void k_fields(InstDev I, const T* __restrict__ A, uint32_t what, O* __restrict__ out)
+{
+    const long long n = (long long)I.nx * I.ny;
+    for (long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x; id < n;
+         id += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(id % I.nx), y = (int)(id / I.nx);
+        float d[9];
+        gather<T>(I, A, x, y, d);
+        double r = 0.0, ux = 0.0, uy = 0.0;
+#pragma unroll
+        for (int i = 0; i < 9; i++) {
+            r += (double)d[i];
+            ux += (double)EX[i] * (double)d[i];
+            uy += (double)EY[i] * (double)d[i];
+        }
+        const double rho = 1.0 + r;
+        long long o = 0;
+        if (what & II_LBM_F_RHO) { out[o + id] = (O)rho; o += n; }
+        if (what & II_LBM_F_UX) { out[o + id] = (O)ux; o += n; }
+        if (what & II_LBM_F_UY) { out[o + id] = (O)uy; o += n; }
+        if (what & II_LBM_F_P) { out[o + id] = (O)(rho / 3.0); o += n; }
+        if (what & II_LBM_F_DISTRIB) {
+#pragma unroll
+            for (int i = 0; i < 9; i++) out[o + i * n + id] = (O)(WD[i] + (double)d[i]);
+        }
+    }
+}
+
+template <typename T>
+static hipError_t fields_t(const InstDev& I, const void* A, uint32_t what, void* out, int dtype,
+                           hipStream_t s)
+{
+    if (dtype == II_LBM_DT_F64)
+        hipLaunchKernelGGL((k_fields<T, double>), dim3(1024), dim3(256), 0, s, I, (const T*)A,
+                           what, (double*)out);
+    else
+        hipLaunchKernelGGL((k_fields<T, float>), dim3(1024), dim3(256), 0, s, I, (const T*)A, what,
+                           (float*)out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fields(const InstDev& I, const void* A, uint32_t what, void* out, int dtype,
+                         hipStream_t s)
+{
+    return I.storage == II_LBM_FP16 ? fields_t<_Float16>(I, A, what, out, dtype, s)
+                                    : fields_t<float>(I, A, what, out, dtype, s);
+}
+
+// ---------------------------------------------------------------------------
+// Set the stored lattice so that the next pull yields the given f (FP64,
+// [9][ny][nx]): stored_i(x) = f_i(x + e_i) - w_i.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_set_distrib(InstDev I, const double* __restrict__ f, T* __restrict__ A)
+{
+    const long long n = (long long)I.nx * I.ny;
+    for (long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x; id < n;
+         id += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(id % I.nx), y = (int)(id / I.nx);
+#pragma unroll
+        for (int i = 0; i < 9; i++) {
+            int xd = x + EX[i], yd = y + EY[i];
+            if (I.px) xd = (xd + I.nx) % I.nx;
+            if (I.py) yd = (yd + I.ny) % I.ny;
+            if (xd < 0 || xd >= I.nx || yd < 0 || yd >= I.ny) { xd = x; yd = y; }
+            const double v = f[(long long)i * n + (long long)yd * I.nx + xd] - WD[i];
+            Store<T>::st(A + I.lat_off + i * I.plane + (long long)y * I.pitch + x, (float)v,
+                         I.inv_scale);
+        }
+    }
+}
+
+hipError_t launch_set_distrib(const InstDev& I, const double* f, void* A, hipStream_t s)
+{
+    if (I.storage == II_LBM_FP16)
+        hipLaunchKernelGGL(k_set_distrib<_Float16>, dim3(1024), dim3(256), 0, s, I, f,
+                           (_Float16*)A);
+    else
+        hipLaunchKernelGGL(k_set_distrib<float>, dim3(1024), dim3(256), 0, s, I, f, (float*)A);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// FP64 partial sums of (sum d, sum ux, sum uy, non-finite count) per block;
+// the host adds the partials in block order (deterministic).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_diag(InstDev I, const T* __restrict__ A,
+                                              double* __restrict__ part)
+{
+    __shared__ double sh[4][256];
+    const long long n = (long long)I.nx * I.ny;
+    double r = 0.0, ux = 0.0, uy = 0.0, bad = 0.0;
+    for (long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x; id < n;
+         id += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(id % I.nx), y = (int)(id / I.nx);
+        float d[9];
+        gather<T>(I, A, x, y, d);
+#pragma unroll
+        for (int i = 0; i < 9; i++) {
+            if (!isfinite(d[i])) bad += 1.0;
+            r += (double)d[i];
+            ux += (double)EX[i] * (double)d[i];
+            uy += (double)EY[i] * (double)d[i];
+        }
+    }
+    const int t = threadIdx.x;
+    sh[0][t] = r; sh[1][t] = ux; sh[2][t] = uy; sh[3][t] = bad;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w)
+            for (int c = 0; c < 4; c++) sh[c][t] += sh[c][t + w];
+        __syncthreads();
+    }
+    if (t == 0)
+        for (int c = 0; c < 4; c++) part[4 * blockIdx.x + c] = sh[c][0];
+}
+
+hipError_t launch_diag(const InstDev& I, const void* A, double* partials, int nblocks,
+                       hipStream_t s)
+{
+    if (I.storage == II_LBM_FP16)
+        hipLaunchKernelGGL(k_diag<_Float16>, dim3(nblocks), dim3(256), 0, s, I,
+                           (const _Float16*)A, partials);
+    else
+        hipLaunchKernelGGL(k_diag<float>, dim3(nblocks), dim3(256), 0, s, I, (const float*)A,
+                           partials);
+    return hipGetLastError();
+}
+
+}  // namespace iilbm

@@ -1,0 +1,92 @@
+"""CPU checks of the C ABI: the library loads, exports every call the header
+declares, its structs match the header's layout, and host-side validation
+rejects bad problems before touching a device (no GPU needed)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2003_12186_amd import binding as B
+from paper_2003_12186_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ii_lbm.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(ii_lbm_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_call():
+    lib = B.load()
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(B.EXPORTS) == names
+
+
+def test_struct_layout_matches_header(tmp_path):
+    prog = tmp_path / "sz.c"
+    prog.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "ii_lbm.h"\n'
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(ii_lbm_problem),"
+        " offsetof(ii_lbm_problem, storage), offsetof(ii_lbm_problem, radius),"
+        " sizeof(ii_lbm_link), offsetof(ii_lbm_link, q), sizeof(ii_lbm_diag_t),"
+        " offsetof(ii_lbm_diag_t, n_cut_links));return 0;}\n")
+    exe = tmp_path / "sz"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.dirname(HEADER), str(prog), "-o", str(exe)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    want = [C.sizeof(B.Problem), B.Problem.storage.offset, B.Problem.radius.offset,
+            C.sizeof(B.Link), B.Link.q.offset, C.sizeof(B.Diag), B.Diag.n_cut_links.offset]
+    assert got == want
+    assert B.LINK_DTYPE.itemsize == C.sizeof(B.Link)
+
+
+def _init_rc(prob, X0):
+    lib = B.load()
+    arr = (B.Problem * 1)(prob)
+    x = np.ascontiguousarray(X0, dtype=np.float64)
+    ptrs = (C.POINTER(C.c_double) * 1)(x.ctypes.data_as(C.POINTER(C.c_double)))
+    h = C.c_void_p()
+    return lib.ii_lbm_init(arr, 1, ptrs, None, 0, None, C.byref(h))
+
+
+def test_workspace_size_scales_with_lattice():
+    a = B.workspace_size([B.make_problem(W.membrane_c1().problem)])
+    b = B.workspace_size([B.make_problem(W.membrane_c3(L=256).problem)])
+    c = B.workspace_size([B.make_problem(W.membrane_c3(L=256, storage=W.STORE_FP16).problem)])
+    assert 0 < a < b
+    assert c < b                                  # half-precision lattice
+    two = B.workspace_size([B.make_problem(W.membrane_c1().problem)] * 2)
+    assert two > a
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (lambda p, X: setattr(p, "tau", 0.5), B.EINVAL),
+    (lambda p, X: setattr(p, "nx", 4), B.EINVAL),
+    (lambda p, X: p.bc.__setitem__(0, W.BC_WALL), B.EINVAL),        # one side periodic only
+    (lambda p, X: setattr(p, "collision", 7), B.EINVAL),
+    (lambda p, X: setattr(p, "dX", 3.0), B.EINVAL),
+    (lambda p, X: setattr(p, "n_markers", 2), B.EINVAL),
+    (lambda p, X: setattr(p, "storage", 5), B.EINVAL),
+    (lambda p, X: X.__setitem__(slice(None), X[::-1].copy()), B.EGEOMETRY),  # clockwise
+    (lambda p, X: X.__setitem__((0, 0), 61.5), B.EGEOMETRY),          # near the edge / long chord
+    (lambda p, X: X.__setitem__((5, 1), np.nan), B.EINVAL),
+])
+def test_init_validation_rejects_before_device_access(mutate, code):
+    w = W.membrane_c1()
+    p = B.make_problem(w.problem)
+    X = w.X0.copy()
+    mutate(p, X)
+    assert _init_rc(p, X) == code
+
+
+def test_strerror():
+    lib = B.load()
+    for code in range(-7, 1):
+        assert len(lib.ii_lbm_strerror(code)) > 0

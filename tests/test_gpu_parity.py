@@ -1,0 +1,248 @@
+"""GPU parity of the HIP II-LBM path (called through the C ABI) against the
+FP64 CPU oracle on the same seeded inputs.
+
+Tolerances: FP32 storage, relative L2 velocity <= 1e-6 after 1000 steps;
+scaled FP16 storage <= 1e-3; cut-link classification bit-exact (node,
+direction, sign and chord), with the FP64 cut fractions to 1e-12.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2003_12186_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B(require_gpu):
+    from paper_2003_12186_amd import binding
+    binding.load()
+    return binding
+
+
+def _rel_l2(ug, vg, uo, vo):
+    num = np.sqrt(((ug - uo) ** 2 + (vg - vo) ** 2).sum())
+    den = np.sqrt((uo ** 2 + vo ** 2).sum())
+    return num / den
+
+
+def _oracle_run(prob, X0, steps, f0=None, force_hist=False):
+    p = O.make_problem(prob)
+    f = O.rest_state(p) if f0 is None else np.ascontiguousarray(f0, dtype=np.float64).copy()
+    X = None if X0 is None else X0.copy()
+    fh = O.run(p, f, X, steps, force_hist=force_hist)
+    rho, ux, uy = O.moments(p, f)
+    return {"f": f, "X": X, "rho": rho, "ux": ux, "uy": uy, "fh": fh, "p": p}
+
+
+def _gpu_run(B, prob, X0, steps, f0=None, chunk=None):
+    sim = B.Sim([prob], [X0])
+    if f0 is not None:
+        sim.set_distrib(f0)
+    sim.step(steps)
+    g = sim.fields(B.F_RHO | B.F_UX | B.F_UY)
+    X = sim.markers()[0] if X0 is not None else None
+    return sim, {"rho": g[0], "ux": g[1], "uy": g[2], "X": X}
+
+
+def _noise_state(prob, config, inst, amp):
+    _, _, w = O.d2q9()
+    return np.ascontiguousarray(w[:, None, None] * (1.0 + amp * W.seeded_noise((9, prob.ny, prob.nx), config, inst)))
+
+
+@pytest.mark.parametrize("collision", [W.SRT, W.MRT])
+def test_periodic_bulk_parity(B, collision):
+    _say(f"periodic bulk 72x40 collision={collision}")
+    prob = W.Problem(nx=72, ny=40, tau=0.7, collision=collision)
+    f0 = _noise_state(prob, 50, collision, 1e-3)
+    sim, g = _gpu_run(B, prob, None, 300, f0=f0)
+    o = _oracle_run(prob, None, 300, f0=f0)
+    err = _rel_l2(g["ux"], g["uy"], o["ux"], o["uy"])
+    _say(f"  rel L2 u = {err:.3e}")
+    assert err <= 1e-6
+    assert np.abs(g["rho"] - o["rho"]).max() < 1e-6
+    sim.close()
+
+
+def test_membrane64_parity_1000_steps(B):
+    _say("membrane 64x64 (tau 0.8, 96 markers, kappa 0.05), 1000 steps, FP32")
+    w = W.membrane_c1()
+    sim, g = _gpu_run(B, w.problem, w.X0, 1000)
+    o = _oracle_run(w.problem, w.X0, 1000)
+    err = _rel_l2(g["ux"], g["uy"], o["ux"], o["uy"])
+    dX = np.abs(g["X"] - o["X"]).max()
+    _say(f"  rel L2 u = {err:.3e}  max |dX| = {dX:.3e}")
+    assert err <= 1e-6
+    assert dX <= 1e-6
+    assert np.abs(g["rho"] - o["rho"]).max() < 1e-6
+    d = sim.diag()
+    assert d["error_bits"] == 0
+    assert d["mass"] == pytest.approx(64 * 64, abs=1e-3)
+    sim.close()
+
+
+@pytest.mark.parametrize("steps", [0, 150])
+def test_membrane64_cutlinks_bitexact(B, steps):
+    _say(f"membrane 64x64 cut links after {steps} steps")
+    w = W.membrane_c1()
+    sim = B.Sim([w.problem], [w.X0])
+    sim.step(steps)
+    Xn, _, _ = sim.markers()
+    sim.step(1)                   # builds the links of the interface at X^n
+    got = sim.cutlinks()
+    p = O.make_problem(w.problem)
+    jp = O.marker_forces(p, Xn)["jp"]
+    want = O.cutlinks(p, Xn, jp)
+    key = lambda r: sorted(zip(r["x"].tolist(), r["y"].tolist(), r["dir"].tolist(),
+                               r["sigma"].tolist(), r["seg"].tolist()))
+    assert len(got) == len(want) > 300
+    assert key(got) == key(want)
+    og = np.lexsort((got["seg"], got["dir"], got["y"], got["x"]))
+    ow = np.lexsort((want["seg"], want["dir"], want["y"], want["x"]))
+    assert np.abs(got["q"][og] - want["q"][ow]).max() <= 1e-12
+    assert np.abs(got["theta"][og] - want["theta"][ow]).max() <= 1e-12
+    assert np.abs(got["jp"][og] - want["jp"][ow]).max() <= 1e-12 * np.abs(jp).max()
+    sim.close()
+
+
+@pytest.mark.parametrize("re", [20.0, 100.0])
+def test_cylinder_channel_small_parity(B, re):
+    _say(f"cylinder channel 128x64 D=4 MRT NEE Re={re}, 1000 steps")
+    w = W.cylinder_c2(re=re, small=True)
+    sim = B.Sim([w.problem], [w.X0])
+    fx = []
+    for _ in range(10):
+        sim.step(100)
+        fx.append(sim.diag()["force"])
+    g = sim.fields(B.F_RHO | B.F_UX | B.F_UY)
+    o = _oracle_run(w.problem, w.X0, 1000, force_hist=True)
+    err = _rel_l2(g[1], g[2], o["ux"], o["uy"])
+    fo = o["fh"][99::100]
+    fg = np.array(fx)
+    ferr = np.abs(fg - fo).max() / np.abs(fo).max()
+    _say(f"  rel L2 u = {err:.3e}  force rel err = {ferr:.3e}  F_last = {fg[-1]} vs {fo[-1]}")
+    assert err <= 1e-6
+    assert ferr <= 1e-5
+    sim.close()
+
+
+def test_cylinder_small_cutlinks_bitexact(B):
+    _say("cylinder D=4 level-set cut links")
+    w = W.cylinder_c2(small=True)
+    sim = B.Sim([w.problem], [w.X0])
+    sim.step(10)
+    got = sim.cutlinks()
+    p = O.make_problem(w.problem)
+    want = O.cutlinks(p, w.X0)
+    key = lambda r: sorted(zip(r["x"].tolist(), r["y"].tolist(), r["dir"].tolist(),
+                               r["sigma"].tolist(), r["seg"].tolist()))
+    assert key(got) == key(want) and len(got) > 20
+    sim.close()
+
+
+@pytest.mark.parametrize("storage,tol", [(W.STORE_FP32, 1e-6), (W.STORE_FP16, 1e-3)])
+def test_membrane256_parity(B, storage, tol):
+    _say(f"membrane 256x256 (ellipse 0.3L x 0.2L, seeded tau/kappa) storage={storage}, 1000 steps")
+    w = W.membrane_c3(L=256, storage=storage)
+    sim, g = _gpu_run(B, w.problem, w.X0, 1000)
+    o = _oracle_run(w.problem, w.X0, 1000)
+    err = _rel_l2(g["ux"], g["uy"], o["ux"], o["uy"])
+    dX = np.abs(g["X"] - o["X"]).max()
+    _say(f"  rel L2 u = {err:.3e}  max |dX| = {dX:.3e}")
+    assert err <= tol
+    sim.close()
+
+
+def test_laplace_fixed_point_on_gpu(B):
+    _say("Laplace fixed point 64x64, 50 steps")
+    n, R = 96, 10.0
+    th = 0.37 + 2 * np.pi * np.arange(n) / n
+    X = np.stack([31.61 + R * np.cos(th), 31.61 + R * np.sin(th)], 1)
+    prob = W.Problem(nx=64, ny=64, tau=0.8, interface=W.IF_MEMBRANE, n_markers=n, kappa=0.05,
+                     dX=2 * np.pi * R / n)
+    p = O.make_problem(prob)
+    jp = O.marker_forces(p, X)["jp"].mean()
+    _, _, wt = O.d2q9()
+    f = np.zeros((9, 64, 64))
+    for y in range(64):
+        for x in range(64):
+            f[:, y, x] = wt * (1.0 - 3.0 * jp if O.node_inside(p, X, x, y) else 1.0)
+    sim = B.Sim([prob], [X])
+    sim.set_distrib(f)
+    sim.step(50)
+    g = sim.fields(B.F_UX | B.F_UY | B.F_DISTRIB)
+    Xg = sim.markers()[0]
+    _say(f"  max|u| = {np.abs(g[:2]).max():.3e}  max|df| = {np.abs(g[2:] - f).max():.3e}")
+    assert np.abs(g[:2]).max() < 1e-8
+    assert np.abs(g[2:] - f).max() < 1e-7
+    assert np.abs(Xg - X).max() < 1e-8
+    sim.close()
+
+
+def test_determinism_and_checkpoint_restart(B):
+    _say("determinism + checkpoint/restart, membrane 64x64")
+    w = W.membrane_c1()
+    a = B.Sim([w.problem], [w.X0])
+    a.step(120)
+    blob = a.save_state()
+    a.step(80)
+    fa = a.fields(B.F_DISTRIB, dtype=np.float32)
+    Xa = a.markers()[0]
+    b = B.Sim([w.problem], [w.X0])
+    b.step(200)
+    fb = b.fields(B.F_DISTRIB, dtype=np.float32)
+    c = B.Sim([w.problem], [w.X0])
+    c.step(7)                       # different parity on purpose
+    c.load_state(blob)
+    c.step(80)
+    fc = c.fields(B.F_DISTRIB, dtype=np.float32)
+    assert np.array_equal(fa, fb)
+    assert np.array_equal(fa, fc)
+    assert np.array_equal(Xa, b.markers()[0]) and np.array_equal(Xa, c.markers()[0])
+    assert c.diag()["step"] == 200
+    for s in (a, b, c):
+        s.close()
+
+
+def test_unstable_state_is_reported(B):
+    _say("non-finite state -> EUNSTABLE")
+    w = W.membrane_c1()
+    sim = B.Sim([w.problem], [w.X0])
+    p = O.make_problem(w.problem)
+    f = O.rest_state(p)
+    f[3, 30, 40] = np.nan          # next to the membrane: reaches the markers
+    sim.set_distrib(f)
+    sim.step(3)
+    with pytest.raises(B.IILBMError) as e:
+        sim.sync()
+    assert e.value.code == B.EUNSTABLE
+    with pytest.raises(B.IILBMError) as e:
+        sim.step(1)
+    assert e.value.code == B.ESTATE
+    sim.close()
+
+
+def test_full_size_membrane4096_first_steps(B):
+    # The bench workload at its full size and launch configuration; the oracle
+    # runs the same two steps in FP64.
+    _say("membrane 4096x4096 (bench workload), 2 steps vs oracle")
+    w = W.membrane_c3()
+    sim, g = _gpu_run(B, w.problem, w.X0, 2)
+    o = _oracle_run(w.problem, w.X0, 2)
+    err = _rel_l2(g["ux"], g["uy"], o["ux"], o["uy"])
+    dX = np.abs(g["X"] - o["X"]).max()
+    _say(f"  rel L2 u = {err:.3e}  max |dX| = {dX:.3e}")
+    assert err <= 1e-6
+    assert dX <= 1e-9
+    d = sim.diag()
+    assert d["error_bits"] == 0 and d["n_cut_links"] > 10000
+    sim.close()
