@@ -71,9 +71,14 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--storage", choices=["fp32", "fp16"], default="fp32")
+    ap.add_argument("--math", choices=["fp32", "fp64"], default="fp64",
+                    help="collision arithmetic (storage keeps its own precision)")
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run plain device copies of MIB MiB (20 launches), the reference "
+                         "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -81,12 +86,22 @@ def main() -> int:
         return 2
 
     import torch
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(20):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_each_way": n * 4, "launches": 20}), flush=True)
+        return 0
     from paper_2003_12186_amd import binding as B
     from paper_2003_12186_amd import workloads as W
 
     storage = W.STORE_FP16 if args.storage == "fp16" else W.STORE_FP32
     w = W.membrane_c3(L=args.size, storage=storage)
     p = w.problem
+    p.math = W.MATH_FP64 if args.math == "fp64" else W.MATH_FP32
     sim = B.Sim([p], [w.X0], device="cuda:0")
     sim.step(args.warmup)
     sim.sync()
@@ -119,11 +134,11 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if storage == W.STORE_FP32 else "f32 math / f16 storage",
+        "dtype": ("f32" if storage == W.STORE_FP32 else "f16") + " storage / " + args.math + " collision",
         "data": "synthetic",
         "config": {"workload": f"membrane{p.nx}_periodic_srt_{args.storage}",
                    "nx": p.nx, "ny": p.ny, "markers": p.n_markers, "tau": round(p.tau, 6),
-                   "kappa": p.kappa, "storage": args.storage,
+                   "kappa": p.kappa, "storage": args.storage, "collision_math": args.math,
                    "cut_links": d["n_cut_links"]},
         "roofline": {"bound": "hbm", "kernel": "k_sweep", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

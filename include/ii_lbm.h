@@ -55,6 +55,7 @@ enum { II_LBM_BC_PERIODIC = 0, II_LBM_BC_WALL = 1, II_LBM_BC_INLET = 2, II_LBM_B
 enum { II_LBM_IF_NONE = 0, II_LBM_IF_MEMBRANE = 1, II_LBM_IF_RIGID = 2 };
 enum { II_LBM_FORCE_II = 0 };
 enum { II_LBM_FP32 = 0, II_LBM_FP16 = 1 };
+enum { II_LBM_MATH_FP32 = 0, II_LBM_MATH_FP64 = 1 };
 
 /*
  * One simulation instance.
@@ -79,9 +80,12 @@ enum { II_LBM_FP32 = 0, II_LBM_FP16 = 1 };
  *  kappa, dX    spring constant and marker spacing Delta X (> 0, <= 2).
  *  center, radius  the rigid circle (RIGID only).
  *  storage      II_LBM_FP32 or II_LBM_FP16: distributions are stored as
- *               deviations d_i = f_i - w_i rho0 (rho0 = 1); arithmetic is FP32.
+ *               deviations d_i = f_i - w_i rho0 (rho0 = 1).
  *  fp16_log2_scale  FP16 storage holds d_i * 2^-fp16_log2_scale; 0 lets the
  *               library choose it from the initial interface force.
+ *  math         arithmetic of the collision: II_LBM_MATH_FP32, or
+ *               II_LBM_MATH_FP64 (loads and stores keep the storage type; only
+ *               the per-node moments, equilibrium and relaxation run in FP64).
  * Markers must stay at least 3 lattice units from every side of the lattice.
  */
 typedef struct ii_lbm_problem {
@@ -101,6 +105,7 @@ typedef struct ii_lbm_problem {
     double radius;
     int32_t storage;
     int32_t fp16_log2_scale;
+    int32_t math;
 } ii_lbm_problem;
 
 /* One cut link, as built for the step that last ran: the link from source

@@ -582,6 +582,10 @@ int or_step(const or_problem *p, double *f, double *X, or_step_out *out)
     double M[81], Minv[81];
     or_mrt_matrices(M, Minv);
 
+    /* 0. the bounded-side nodes of f^n obey the extrapolation rule; it only
+     *    reads interior nodes and is idempotent, so this changes nothing
+     *    after the first step and makes any initial state consistent */
+    or_boundaries(p, f);
     /* 1. moments of f^n; uniform body force */
     or_moments(p, f, rho, ux, uy);
     for (long n = 0; n < nn; n++) { gx[n] = p->body[0]; gy[n] = p->body[1]; }

@@ -28,7 +28,8 @@ class Problem(C.Structure):
                 ("u_max", C.c_double), ("u_wall", C.c_double * 4), ("body_force", C.c_double * 2),
                 ("interface_kind", C.c_int32), ("force_mode", C.c_int32), ("n_markers", C.c_int32),
                 ("kappa", C.c_double), ("dX", C.c_double), ("center", C.c_double * 2),
-                ("radius", C.c_double), ("storage", C.c_int32), ("fp16_log2_scale", C.c_int32)]
+                ("radius", C.c_double), ("storage", C.c_int32), ("fp16_log2_scale", C.c_int32),
+                ("math", C.c_int32)]
 
 
 class Link(C.Structure):
@@ -67,6 +68,10 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2003_12186_amd.build` "
                           "(or __graft_entry__.build())")
+    # torch ships its own HIP runtime under the same soname; loading torch
+    # first makes the library bind to that one runtime instead of pulling a
+    # second copy from /opt/rocm into the process.
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     v, i32, i64, sz, d = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t, C.c_double
     PP = C.POINTER(Problem)
@@ -132,6 +137,7 @@ def make_problem(w) -> Problem:
     p.radius = float(w.radius)
     p.storage = int(w.storage)
     p.fp16_log2_scale = int(getattr(w, "fp16_log2_scale", 0))
+    p.math = int(getattr(w, "math", 0))
     return p
 
 

@@ -23,6 +23,7 @@ constexpr int kSweepBX = 64;     // one wavefront spans 64 consecutive x
 constexpr int kSweepBY = 4;      // four rows per 256-thread block
 constexpr int kTile = 16;        // interface tiles are 16 x 16 nodes
 constexpr int kTileCap = 128;    // chords listed per interface tile
+constexpr int kTileNodes = kTile * kTile;
 constexpr int kPitchAlign = 64;  // row pitch in elements
 constexpr double kSnap = 65536.0;  // marker snap grid 2^-16 lu for exact tests
 
@@ -40,6 +41,7 @@ struct InstDev {
     int bounded;          // any non-periodic side
     int bc[4];
     int collision, storage, iface;
+    int math;             // II_LBM_MATH_FP32 or II_LBM_MATH_FP64 collision arithmetic
     int n_markers;
     int mk_off;           // offset of this instance in the marker arrays
     int tiles_x, tiles_y;
@@ -50,6 +52,7 @@ struct InstDev {
     long long lat_off;    // element offset of plane 0 in either lattice buffer
     long long plane;      // elements per population plane (pitch * ny)
     float omega;          // 1 / tau
+    double omega_d;
     float s[9];           // MRT rates
     float u_max;
     float u_wall[4];
@@ -66,9 +69,14 @@ struct DevPtrs {
     double2* G;            // marker force of the last step
     double2* Gt;           // its tangential part
     double* jp;            // [[p]] at the markers
+    double* wx;            // [4 N] delta weights of the 4 stencil columns of each marker
+    double* wy;            // [4 N] ... and of its 4 stencil rows
+    int2* f0;              // first stencil column and row of each marker
     int* tile_count;       // chords appended per tile (reset by the tile kernel)
     int* tile_list;        // chord ids per tile
-    int2* act_list;        // (instance, tile) of the tiles that hold chords
+    int* tile_slot;        // correction slot of a tile this step, -1 when none
+    float* corr;           // per slot: 8 x 256 additions to the outgoing populations
+    int2* act_list[2];     // (instance, tile) of the tiles that hold chords, by parity
     int* act_count;        // [2 * n_inst], double-buffered by step parity
     ii_lbm_link* rec;      // cut-link records
     int* rec_count;        // [2 * n_inst]
@@ -114,11 +122,12 @@ struct Store<_Float16> {
 // Pull gather: the populations that arrive at node (x, y) were stored by the
 // previous step at x - e_i (the stored value already carries that step's
 // force term and jump).  Periodic wrap; callers only pull across a bounded
-// side from a node that extrapolation then overrides.
+// side from a node that extrapolation then overrides.  M is the arithmetic
+// type of the collision (float, or double for FP64 collision arithmetic).
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, typename M>
 __device__ __forceinline__ void pull(const InstDev& I, const T* __restrict__ A, int x, int y,
-                                     float d[9])
+                                     M d[9])
 {
     const int xm = (x == 0) ? I.nx - 1 : x - 1;
     const int xp = (x == I.nx - 1) ? 0 : x + 1;
@@ -129,30 +138,65 @@ __device__ __forceinline__ void pull(const InstDev& I, const T* __restrict__ A, 
                     rp = (long long)yp * I.pitch;
     const long long P = I.plane;
     const float sc = I.scale;
-    d[0] = Store<T>::ld(base + 0 * P + r0 + x, sc);
-    d[1] = Store<T>::ld(base + 1 * P + r0 + xm, sc);
-    d[2] = Store<T>::ld(base + 2 * P + rm + x, sc);
-    d[3] = Store<T>::ld(base + 3 * P + r0 + xp, sc);
-    d[4] = Store<T>::ld(base + 4 * P + rp + x, sc);
-    d[5] = Store<T>::ld(base + 5 * P + rm + xm, sc);
-    d[6] = Store<T>::ld(base + 6 * P + rm + xp, sc);
-    d[7] = Store<T>::ld(base + 7 * P + rp + xp, sc);
-    d[8] = Store<T>::ld(base + 8 * P + rp + xm, sc);
+    d[0] = (M)Store<T>::ld(base + 0 * P + r0 + x, sc);
+    d[1] = (M)Store<T>::ld(base + 1 * P + r0 + xm, sc);
+    d[2] = (M)Store<T>::ld(base + 2 * P + rm + x, sc);
+    d[3] = (M)Store<T>::ld(base + 3 * P + r0 + xp, sc);
+    d[4] = (M)Store<T>::ld(base + 4 * P + rp + x, sc);
+    d[5] = (M)Store<T>::ld(base + 5 * P + rm + xm, sc);
+    d[6] = (M)Store<T>::ld(base + 6 * P + rm + xp, sc);
+    d[7] = (M)Store<T>::ld(base + 7 * P + rp + xp, sc);
+    d[8] = (M)Store<T>::ld(base + 8 * P + rp + xm, sc);
 }
 
-__device__ __forceinline__ void moments(const float d[9], float& r, float& ux, float& uy)
+template <typename M>
+__device__ __forceinline__ void moments(const M d[9], M& r, M& ux, M& uy)
 {
     r = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
     ux = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
     uy = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
 }
 
-// Deviation of the He-Luo incompressible equilibrium (Sec. 2.2.1):
-// f_eq_i - w_i rho0 = w_i [ drho + 3 e.u + 4.5 (e.u)^2 - 1.5 u.u ].
-__device__ __forceinline__ float deq(int i, float r, float ux, float uy, float uu)
+template <typename M>
+struct Lat;
+template <>
+struct Lat<float> {
+    static __device__ __forceinline__ float w(int i) { return WF[i]; }
+};
+template <>
+struct Lat<double> {
+    static __device__ __forceinline__ double w(int i) { return WD[i]; }
+};
+
+// Deviation of the He-Luo incompressible equilibrium (Sec. 2.2.1),
+// f_eq_i - w_i rho0 = w_i [ drho + 3 e.u + 4.5 (e.u)^2 - 1.5 u.u ], written so
+// that its zeroth and first moments are drho and u up to unbiased rounding:
+// the rest population takes drho minus the others, and the axis populations'
+// odd part takes u/2 minus the diagonal ones'.  (With rounded weights the
+// plain form changes the momentum by a fixed relative 1e-8 every step.)
+template <typename M>
+__device__ __forceinline__ void equilibrium(M r, M ux, M uy, M e[9])
 {
-    const float eu = (float)EX[i] * ux + (float)EY[i] * uy;
-    return WF[i] * (r + 3.f * eu + 4.5f * eu * eu - 1.5f * uu);
+    const M uu = ux * ux + uy * uy;
+    M s[9];
+#pragma unroll
+    for (int i = 1; i < 9; i++) {
+        const M eu = (M)EX[i] * ux + (M)EY[i] * uy;
+        s[i] = Lat<M>::w(i) * (r + (M)4.5 * eu * eu - (M)1.5 * uu);
+    }
+    s[0] = r - (((s[1] + s[2]) + (s[3] + s[4])) + ((s[5] + s[6]) + (s[7] + s[8])));
+    const M c12 = (M)(1.0 / 12.0);
+    const M a5 = c12 * (ux + uy), a6 = c12 * (uy - ux);
+    const M a1 = (M)0.5 * ux - (a5 - a6), a2 = (M)0.5 * uy - (a5 + a6);
+    e[0] = s[0];
+    e[1] = s[1] + a1;
+    e[2] = s[2] + a2;
+    e[3] = s[3] - a1;
+    e[4] = s[4] - a2;
+    e[5] = s[5] + a5;
+    e[6] = s[6] + a6;
+    e[7] = s[7] - a5;
+    e[8] = s[8] - a6;
 }
 
 // Is (x, y) a node that non-equilibrium extrapolation sets?
@@ -164,68 +208,77 @@ __device__ __forceinline__ bool is_edge(const InstDev& I, int x, int y)
 // f at a bounded-side node: f_b = f_eq(rho_f, u_b) + (f_f - f_eq(rho_f, u_f)),
 // f_f the pulled populations of the inward neighbour (corners: the diagonal
 // neighbour, velocity rule of the y side).
-template <typename T>
-__device__ void nee(const InstDev& I, const T* __restrict__ A, int x, int y, float d[9])
+template <typename T, typename M>
+__device__ void nee(const InstDev& I, const T* __restrict__ A, int x, int y, M d[9])
 {
     int inx = 0, iny = 0;
     if (!I.px && x == 0) inx = 1;
     if (!I.px && x == I.nx - 1) inx = -1;
     if (!I.py && y == 0) iny = 1;
     if (!I.py && y == I.ny - 1) iny = -1;
-    float df[9];
-    pull<T>(I, A, x + inx, y + iny, df);
-    float r, ux, uy;
-    moments(df, r, ux, uy);
-    float ubx = 0.f, uby = 0.f;
+    M df[9];
+    pull<T, M>(I, A, x + inx, y + iny, df);
+    M r, ux, uy;
+    moments<M>(df, r, ux, uy);
+    M ubx = 0, uby = 0;
     int type;
     if (iny != 0) {
         const int s = iny > 0 ? 2 : 3;
         type = I.bc[s];
-        if (type == II_LBM_BC_WALL) ubx = I.u_wall[s];
+        if (type == II_LBM_BC_WALL) ubx = (M)I.u_wall[s];
     } else {
         const int s = inx > 0 ? 0 : 1;
         type = I.bc[s];
-        if (type == II_LBM_BC_WALL) uby = I.u_wall[s];
+        if (type == II_LBM_BC_WALL) uby = (M)I.u_wall[s];
     }
     if (type == II_LBM_BC_INLET) {
-        const float H = (float)(I.ny - 1);
-        ubx = 4.f * I.u_max * (float)y * (H - (float)y) / (H * H);
-        uby = 0.f;
+        const M H = (M)(I.ny - 1);
+        ubx = (M)4 * (M)I.u_max * (M)y * (H - (M)y) / (H * H);
+        uby = 0;
     } else if (type == II_LBM_BC_OUTLET) {
         ubx = ux;
         uby = uy;
     }
-    const float uub = ubx * ubx + uby * uby, uuf = ux * ux + uy * uy;
+    M eb[9], ef[9];
+    equilibrium<M>(r, ubx, uby, eb);
+    equilibrium<M>(r, ux, uy, ef);
 #pragma unroll
-    for (int i = 0; i < 9; i++) d[i] = deq(i, r, ubx, uby, uub) + (df[i] - deq(i, r, ux, uy, uuf));
+    for (int i = 0; i < 9; i++) d[i] = eb[i] + (df[i] - ef[i]);
 }
 
 // f^n at node (x, y): the pulled populations, or the extrapolated ones on a
 // bounded side.
-template <typename T>
+template <typename T, typename M>
 __device__ __forceinline__ void gather(const InstDev& I, const T* __restrict__ A, int x, int y,
-                                       float d[9])
+                                       M d[9])
 {
     if (I.bounded && is_edge(I, x, y))
-        nee<T>(I, A, x, y, d);
+        nee<T, M>(I, A, x, y, d);
     else
-        pull<T>(I, A, x, y, d);
+        pull<T, M>(I, A, x, y, d);
 }
 
 // ---------------------------------------------------------------------------
 // Collision with the simple force term (Sec. 2.2.1 Eq. (14)/(15), Sec. 2.2.2
 // Eq. (16)); in deviation form the constant w_i rho0 drops out of both.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void collide_srt(float d[9], float omega, float gx, float gy)
+template <typename M>
+__device__ __forceinline__ void force_term(M d[9], M gx, M gy)
 {
-    float r, ux, uy;
-    moments(d, r, ux, uy);
-    const float uu = ux * ux + uy * uy;
 #pragma unroll
-    for (int i = 0; i < 9; i++) {
-        const float e = deq(i, r, ux, uy, uu);
-        d[i] = d[i] + omega * (e - d[i]) + 3.f * WF[i] * ((float)EX[i] * gx + (float)EY[i] * gy);
-    }
+    for (int i = 1; i < 9; i++)
+        d[i] += (M)3 * Lat<M>::w(i) * ((M)EX[i] * gx + (M)EY[i] * gy);
+}
+
+template <typename M>
+__device__ __forceinline__ void collide_srt(M d[9], M omega, M gx, M gy)
+{
+    M r, ux, uy, e[9];
+    moments<M>(d, r, ux, uy);
+    equilibrium<M>(r, ux, uy, e);
+#pragma unroll
+    for (int i = 0; i < 9; i++) d[i] = d[i] + omega * (e[i] - d[i]);
+    force_term<M>(d, gx, gy);
 }
 
 // D2Q9 moment basis of Lallemand & Luo in the order (rho, e, eps, jx, qx, jy,
@@ -241,41 +294,45 @@ constexpr int MB[9][9] = {
     {0, 1, -1, 1, -1, 0, 0, 0, 0},
     {0, 0, 0, 0, 0, 1, -1, 1, -1},
 };
-constexpr float MBN[9] = {1.f / 9.f, 1.f / 36.f, 1.f / 36.f, 1.f / 6.f, 1.f / 12.f,
-                          1.f / 6.f, 1.f / 12.f, 1.f / 4.f, 1.f / 4.f};
+constexpr double MBN[9] = {1.0 / 9.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 6.0, 1.0 / 12.0,
+                           1.0 / 6.0, 1.0 / 12.0, 1.0 / 4.0, 1.0 / 4.0};
 
-// MRT: d* = d - M^-1 S M (d - d_eq); only the six non-conserved moments relax.
-__device__ __forceinline__ void collide_mrt(float d[9], const float s[9], float gx, float gy)
+// MRT: d* = d - M^-1 S M (d - d_eq); only the six non-conserved moments
+// relax, and the integer basis keeps the correction free of any density or
+// momentum.
+template <typename M>
+__device__ __forceinline__ void collide_mrt(M d[9], const float s[9], M gx, M gy)
 {
-    float r, ux, uy;
-    moments(d, r, ux, uy);
-    const float uu = ux * ux + uy * uy;
-    float ne[9];
+    M r, ux, uy, e[9];
+    moments<M>(d, r, ux, uy);
+    equilibrium<M>(r, ux, uy, e);
+    M ne[9];
 #pragma unroll
-    for (int i = 0; i < 9; i++) ne[i] = d[i] - deq(i, r, ux, uy, uu);
-    float m[9];
+    for (int i = 0; i < 9; i++) ne[i] = d[i] - e[i];
+    M m[9];
 #pragma unroll
     for (int a = 0; a < 9; a++) {
-        float acc = 0.f;
+        M acc = 0;
 #pragma unroll
         for (int i = 0; i < 9; i++)
-            if (MB[a][i] != 0) acc += (float)MB[a][i] * ne[i];
-        m[a] = (a == 0 || a == 3 || a == 5) ? 0.f : s[a] * MBN[a] * acc;
+            if (MB[a][i] != 0) acc += (M)MB[a][i] * ne[i];
+        m[a] = (a == 0 || a == 3 || a == 5) ? (M)0 : (M)s[a] * (M)MBN[a] * acc;
     }
 #pragma unroll
     for (int i = 0; i < 9; i++) {
-        float acc = 0.f;
+        M acc = 0;
 #pragma unroll
         for (int a = 0; a < 9; a++)
-            if (MB[a][i] != 0 && a != 0 && a != 3 && a != 5) acc += (float)MB[a][i] * m[a];
-        d[i] = d[i] - acc + 3.f * WF[i] * ((float)EX[i] * gx + (float)EY[i] * gy);
+            if (MB[a][i] != 0 && a != 0 && a != 3 && a != 5) acc += (M)MB[a][i] * m[a];
+        d[i] = d[i] - acc;
     }
+    force_term<M>(d, gx, gy);
 }
 
 // ---------------------------------------------------------------------------
 // Launch helpers implemented in the .hip files (host side).
 // ---------------------------------------------------------------------------
-hipError_t launch_sweep(const InstDev& I, const void* A, void* B, hipStream_t s);
+hipError_t launch_sweep(const InstDev& I, const DevPtrs& P, const void* A, void* B, hipStream_t s);
 hipError_t launch_fill_zero(const InstDev& I, void* A, hipStream_t s);
 hipError_t launch_fields(const InstDev& I, const void* A, uint32_t what, void* out, int dtype,
                          hipStream_t s);
@@ -284,8 +341,7 @@ hipError_t launch_diag(const InstDev& I, const void* A, double* partials, int nb
                        hipStream_t s);
 hipError_t launch_markers(const InstDev& I, const DevPtrs& P, const void* A, int parity,
                           hipStream_t s);
-hipError_t launch_tiles(const InstDev& I, const DevPtrs& P, void* B, int parity, int records,
-                        hipStream_t s);
-hipError_t launch_zero_ints(int* p, long long n, hipStream_t s);
+hipError_t launch_tiles(const InstDev& I, const DevPtrs& P, int parity, int records, hipStream_t s);
+hipError_t launch_fill_ints(int* p, long long n, int value, hipStream_t s);
 
 }  // namespace iilbm

@@ -5,9 +5,10 @@
 //              position X^{n+1}; binning of chord (k, k+1) into 16x16 tiles.
 //   k_tiles    one block per tile that holds chords: spreads the tangential
 //              force onto its nodes, finds every cut link leaving its nodes
-//              with exact integer predicates, adds the force term and the
-//              jumps to the stored post-collision populations in one
-//              read-modify-write, and compacts the cut-link records.
+//              with exact integer predicates, writes the force term plus the
+//              jumps of every outgoing population into the tile's correction
+//              slot (added by the sweep before its store), and compacts the
+//              cut-link records.
 #include "common.hpp"
 
 namespace iilbm {
@@ -30,30 +31,69 @@ __device__ __forceinline__ int wrap_or_clamp(int v, int n, int periodic)
 }
 
 // ---------------------------------------------------------------------------
-// Markers.
+// Markers: 16 lanes per marker, one per node of the 4 x 4 delta stencil.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, typename M>
 __global__ __launch_bounds__(256) void k_markers(InstDev I, DevPtrs P, const T* __restrict__ A,
                                                  int parity)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k == 0) {
-        // counters of the other parity were consumed by the previous step
-        P.act_count[2 * I.inst + (parity ^ 1)] = 0;
-        P.rec_count[2 * I.inst + (parity ^ 1)] = 0;
+    const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
+    // The previous step's tiles give back their correction slots.
+    {
+        const int prev = min(P.act_count[2 * I.inst + (parity ^ 1)], I.act_cap);
+        for (int a = gtid; a < prev; a += gridDim.x * blockDim.x)
+            P.tile_slot[I.tile_off + P.act_list[parity ^ 1][I.act_off + a].y] = -1;
     }
-    if (k >= I.n_markers) return;
     const int N = I.n_markers;
+    const int k = gtid >> 4;          // marker of this 16-lane group
+    const int s = threadIdx.x & 15;   // stencil node of this lane
+    const bool live = k < N;
     const double2* X = P.X[parity] + I.mk_off;
     double2* Xn = P.X[parity ^ 1] + I.mk_off;
-    const double2 Xk = X[k];
+    const double2 Xk = live ? X[k] : make_double2(0.0, 0.0);
+    const bool inside =
+        live && Xk.x >= 0.0 && Xk.x < (double)I.nx && Xk.y >= 0.0 && Xk.y < (double)I.ny;
+
+    // U_k = sum_x u^n(x) delta_h(x - X_k) (Sec. 2.2.2, Eq. (20)); u^n from the
+    // pre-collision f^n, each lane one stencil node, summed in FP64 over the
+    // group in a fixed tree.
+    const int fx0 = inside ? (int)floor(Xk.x) - 1 : 0, fy0 = inside ? (int)floor(Xk.y) - 1 : 0;
+    const int sx = s & 3, sy = s >> 2;
+    const double wx = inside ? peskin((double)(fx0 + sx) - Xk.x) : 0.0;
+    const double wy = inside ? peskin((double)(fy0 + sy) - Xk.y) : 0.0;
+    const double w = wx * wy;
+    double cu = 0.0, cv = 0.0;
+    if (w != 0.0) {
+        M d[9];
+        gather<T, M>(I, A, wrap_or_clamp(fx0 + sx, I.nx, I.px), wrap_or_clamp(fy0 + sy, I.ny, I.py), d);
+        double u = 0.0, v = 0.0;
+#pragma unroll
+        for (int i = 1; i < 9; i++) {
+            u += (double)EX[i] * (double)d[i];
+            v += (double)EY[i] * (double)d[i];
+        }
+        cu = u * w;
+        cv = v * w;
+    }
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) {
+        cu += __shfl_xor(cu, off, 16);
+        cv += __shfl_xor(cv, off, 16);
+    }
+    if (!live) return;
+    // the per-axis delta weights, reused by the spread of this step
+    if (sy == 0) P.wx[4 * (I.mk_off + k) + sx] = wx;
+    if (sx == 0) P.wy[4 * (I.mk_off + k) + sy] = wy;
+    if (s != 0) return;
+    P.f0[I.mk_off + k] = make_int2(fx0, fy0);
+    const double us = cu, vs = cv;
     const int km = (k + N - 1) % N, kp = (k + 1) % N;
     const double2 Xm = X[km], Xp = X[kp];
-    if (!(Xk.x >= 0.0 && Xk.x < (double)I.nx && Xk.y >= 0.0 && Xk.y < (double)I.ny)) {
+    const int m = I.mk_off + k;
+    if (!inside) {
         // non-finite or outside the lattice: keep the marker, flag the handle
         atomicOr(&P.err[I.inst], isfinite(Xk.x) && isfinite(Xk.y) ? (int)kErrGeometry
                                                                   : (int)kErrUnstable);
-        const int m = I.mk_off + k;
         P.U[m] = make_double2(0.0, 0.0);
         P.G[m] = make_double2(0.0, 0.0);
         P.Gt[m] = make_double2(0.0, 0.0);
@@ -61,26 +101,6 @@ __global__ __launch_bounds__(256) void k_markers(InstDev I, DevPtrs P, const T* 
         Xn[k] = Xk;
         return;
     }
-
-    // U_k = sum_x u^n(x) delta_h(x - X_k) (Sec. 2.2.2, Eq. (20)); u^n from the
-    // pre-collision f^n, summed in FP64 from the stored deviations.
-    double us = 0.0, vs = 0.0;
-    const int fx = (int)floor(Xk.x), fy = (int)floor(Xk.y);
-    for (int y = fy - 1; y <= fy + 2; y++)
-        for (int x = fx - 1; x <= fx + 2; x++) {
-            const double w = peskin((double)x - Xk.x) * peskin((double)y - Xk.y);
-            if (w == 0.0) continue;
-            float d[9];
-            gather<T>(I, A, wrap_or_clamp(x, I.nx, I.px), wrap_or_clamp(y, I.ny, I.py), d);
-            double u = 0.0, v = 0.0;
-#pragma unroll
-            for (int i = 1; i < 9; i++) {
-                u += (double)EX[i] * (double)d[i];
-                v += (double)EY[i] * (double)d[i];
-            }
-            us += u * w;
-            vs += v * w;
-        }
 
     double gx, gy, nx_, ny_, jac;
     if (I.iface == II_LBM_IF_MEMBRANE) {
@@ -108,7 +128,6 @@ __global__ __launch_bounds__(256) void k_markers(InstDev I, DevPtrs P, const T* 
     }
     // [[p]] = G.n / |dX/ds| (Sec. 3.1, Eq. (40)); G_par = G - (G.n) n (Eq. (46))
     const double gn = gx * nx_ + gy * ny_;
-    const int m = I.mk_off + k;
     P.U[m] = make_double2(us, vs);
     P.G[m] = make_double2(gx, gy);
     P.jp[m] = gn / jac;
@@ -144,7 +163,7 @@ __global__ __launch_bounds__(256) void k_markers(InstDev I, DevPtrs P, const T* 
             if (pos == 0) {
                 const int a = atomicAdd(&P.act_count[2 * I.inst + parity], 1);
                 if (a < I.act_cap)
-                    P.act_list[I.act_off + a] = make_int2(I.inst, t);
+                    P.act_list[parity][I.act_off + a] = make_int2(I.inst, t);
                 else
                     atomicOr(&P.err[I.inst], (int)kErrCapacity);
             }
@@ -155,8 +174,13 @@ template <typename T>
 static hipError_t markers_t(const InstDev& I, const DevPtrs& P, const void* A, int parity,
                             hipStream_t s)
 {
-    const int nb = (I.n_markers + 255) / 256;
-    hipLaunchKernelGGL(k_markers<T>, dim3(nb), dim3(256), 0, s, I, P, (const T*)A, parity);
+    const int nb = (16 * I.n_markers + 255) / 256;
+    if (I.math == II_LBM_MATH_FP64)
+        hipLaunchKernelGGL((k_markers<T, double>), dim3(nb), dim3(256), 0, s, I, P, (const T*)A,
+                           parity);
+    else
+        hipLaunchKernelGGL((k_markers<T, float>), dim3(nb), dim3(256), 0, s, I, P, (const T*)A,
+                           parity);
     return hipGetLastError();
 }
 
@@ -169,72 +193,125 @@ hipError_t launch_markers(const InstDev& I, const DevPtrs& P, const void* A, int
 
 // ---------------------------------------------------------------------------
 // Exact link/chord crossing on the 2^-16 snapped grid.
+//
+// For the chord A->B and the link P->P+e (P a lattice node, e a D2Q9 vector)
+// every orientation is an int64 (|coordinates| < 2^29, products < 2^61):
+//   oP = orient(A, B, P) = dx (P.y - A.y) - dy (P.x - A.x),  (dx, dy) = B - A
+//   orient(A, B, P + e) = oP + 2^16 (dx e_y - dy e_x)
+//   orient(P, P + e, A) = 2^16 (e_x (A.y - P.y) - e_y (A.x - P.x))
+// Ties are broken as if every lattice node sat at (+eps, +eps^2): the side of
+// a node on the chord's line follows -dy, then dx; the side of a chord end on
+// the link's line follows e_y, then -e_x.  No orientation is then zero and the
+// count of crossings of a link equals inside(P) != inside(P + e).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ long long cross3(long long ax, long long ay, long long bx, long long by,
-                                            long long cx, long long cy)
-{
-    return (bx - ax) * (cy - ay) - (by - ay) * (cx - ax);
-}
+struct Chord {
+    long long ax, ay, bx, by;
+};
 
-// Side (+1 left / -1 right) of the lattice node shifted by (eps, eps^2)
-// relative to the directed chord a->b; a zero orientation is decided by the
-// shift, so the result is never zero.
-__device__ __forceinline__ int node_side(long long ax, long long ay, long long bx, long long by,
-                                         long long px, long long py)
+__device__ __forceinline__ int node_sign(long long o, long long dx, long long dy)
 {
-    const long long o = cross3(ax, ay, bx, by, px, py);
-    if (o > 0) return 1;
-    if (o < 0) return -1;
-    const long long dy = by - ay, dx = bx - ax;
+    if (o != 0) return o > 0 ? 1 : -1;
     if (dy != 0) return dy > 0 ? -1 : 1;
     return dx > 0 ? 1 : -1;
 }
 
-// Side of chord end c relative to the link p->q, both link ends shifted by the
-// same (eps, eps^2).
-__device__ __forceinline__ int end_side(long long px, long long py, long long qx, long long qy,
-                                        long long cx, long long cy)
+__device__ __forceinline__ int end_sign(long long o, int ex, int ey)
 {
-    const long long o = cross3(px, py, qx, qy, cx, cy);
-    if (o > 0) return 1;
-    if (o < 0) return -1;
-    const long long dy = qy - py, dx = qx - px;
-    if (dy != 0) return dy > 0 ? 1 : -1;
-    return dx > 0 ? -1 : 1;
+    if (o != 0) return o > 0 ? 1 : -1;
+    if (ey != 0) return ey;
+    return -ex;
+}
+
+// Crossing of the link leaving lattice node (x, y) along e_i with chord c.
+// On a hit returns true with the sign sigma (+1 from the interior, which lies
+// left of A->B, to the exterior) and, when wanted, q and theta.
+template <bool FRACS>
+__device__ __forceinline__ bool link_crossing(int x, int y, int i, const Chord& c, long long oP,
+                                              int sP, int& sigma, double& q, double& theta)
+{
+    const long long dx = c.bx - c.ax, dy = c.by - c.ay;
+    const int ex = EX[i], ey = EY[i];
+    const long long oQ = oP + ((dx * ey - dy * ex) << 16);
+    if (node_sign(oQ, dx, dy) == sP) return false;
+    const long long px = (long long)x << 16, py = (long long)y << 16;
+    const long long oA = (long long)ex * (c.ay - py) - (long long)ey * (c.ax - px);
+    const long long oB = (long long)ex * (c.by - py) - (long long)ey * (c.bx - px);
+    if (end_sign(oA, ex, ey) == end_sign(oB, ex, ey)) return false;
+    sigma = sP;
+    const double a = (double)(oA << 16), b = (double)(oB << 16);
+    theta = a / (a - b);
+    if (FRACS) q = (double)oP / ((double)oP - (double)oQ);
+    return true;
 }
 
 // ---------------------------------------------------------------------------
 // Tiles.
 // ---------------------------------------------------------------------------
+constexpr int kTileRec = 256;  // records staged per tile before one global write
+
 struct TileShared {
     int raw[kTileCap];
     int key[kTileCap];
-    long long ax[kTileCap], ay[kTileCap], bx[kTileCap], by[kTileCap];
-    int box[kTileCap][4];
+    Chord ch[kTileCap];
+    int box[kTileCap][4];        // candidate source nodes of the chord's links
     double jpa[kTileCap], jpb[kTileCap];
-    double mx[kTileCap], my[kTileCap], gtx[kTileCap], gty[kTileCap];
-    int cnt, base, tot;
-    int woff[4];
+    double wx[kTileCap][4], wy[kTileCap][4];
+    int2 f0[kTileCap];
+    double gtx[kTileCap], gty[kTileCap];
+    double acc[8][kTileNodes];   // jump sums of the eight outgoing populations per node
+    ii_lbm_link rec[kTileRec];
+    int cnt, nrec, base;
 };
 
-template <typename T, int IFACE>
-__global__ __launch_bounds__(256) void k_tiles(InstDev I, DevPtrs P, T* __restrict__ B,
-                                               int parity, int records)
+// Jump of one cut link into the node's accumulator, and its record.
+__device__ __forceinline__ void add_crossing(TileShared& S, const InstDev& I, int lx, int ly,
+                                             int x, int y, int i, int sigma, int seg, double q,
+                                             double theta, double jpc, bool records)
+{
+    // sigma [[f_i]] = sigma w_i [[p]] / c_s^2 (Sec. 3.1, Eq. (32); Sec. 3.2, Eq. (47));
+    // a link cut by two chords gets two terms, whose sum is order-free
+    atomicAdd(&S.acc[i - 1][ly * kTile + lx], (double)sigma * WD[i] * jpc / kCs2);
+    if (!records) return;
+    const int r = atomicAdd(&S.nrec, 1);
+    if (r < kTileRec) {
+        ii_lbm_link& L = S.rec[r];
+        L.x = x; L.y = y; L.dir = i; L.sigma = sigma; L.seg = seg; L.inst = I.inst;
+        L.q = q; L.theta = theta; L.jp = jpc;
+    }
+}
+
+template <int IFACE>
+__global__ __launch_bounds__(256) void k_tiles(InstDev I, DevPtrs P, int parity, int records)
 {
     __shared__ TileShared S;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int N = I.n_markers;
     const double2* X = P.X[parity] + I.mk_off;
     const int nact = min(P.act_count[2 * I.inst + parity], I.act_cap);
+    if (blockIdx.x == 0 && tid == 0) {
+        // the other parity's counters were consumed by the previous step
+        P.act_count[2 * I.inst + (parity ^ 1)] = 0;
+        P.rec_count[2 * I.inst + (parity ^ 1)] = 0;
+    }
     for (int a = blockIdx.x; a < nact; a += gridDim.x) {
-        const int t = P.act_list[I.act_off + a].y;
+        const int t = P.act_list[parity][I.act_off + a].y;
         const int gt = I.tile_off + t;
-        if (tid == 0) S.cnt = min(P.tile_count[gt], kTileCap);
+        const int tx = t % I.tiles_x, ty = t / I.tiles_x;
+        const int x0 = tx * kTile, y0 = ty * kTile;
+        if (tid == 0) {
+            S.cnt = min(P.tile_count[gt], kTileCap);
+            S.nrec = 0;
+        }
+#pragma unroll
+        for (int i = 0; i < 8; i++) S.acc[i][tid] = 0.0;
         __syncthreads();
         const int c = S.cnt;
         if (tid < c) S.raw[tid] = P.tile_list[(long long)gt * kTileCap + tid];
         __syncthreads();
-        if (tid == 0) P.tile_count[gt] = 0;  // ready for the next step
+        if (tid == 0) {
+            P.tile_count[gt] = 0;  // ready for the next step
+            P.tile_slot[gt] = I.act_off + a;
+        }
         // deterministic order: rank sort of the (distinct) chord ids
         if (tid < c) {
             const int key = S.raw[tid];
@@ -248,222 +325,143 @@ __global__ __launch_bounds__(256) void k_tiles(InstDev I, DevPtrs P, T* __restri
             const double2 a0 = X[k], b0 = X[kp];
             const long long ax = (long long)rint(a0.x * kSnap), ay = (long long)rint(a0.y * kSnap);
             const long long bx = (long long)rint(b0.x * kSnap), by = (long long)rint(b0.y * kSnap);
-            S.ax[tid] = ax; S.ay[tid] = ay; S.bx[tid] = bx; S.by[tid] = by;
-            S.box[tid][0] = (int)(min(ax, bx) >> 16);
-            S.box[tid][1] = (int)(-((-max(ax, bx)) >> 16));
-            S.box[tid][2] = (int)(min(ay, by) >> 16);
-            S.box[tid][3] = (int)(-((-max(ay, by)) >> 16));
+            S.ch[tid].ax = ax; S.ch[tid].ay = ay; S.ch[tid].bx = bx; S.ch[tid].by = by;
+            // any link the chord cuts leaves a node within one spacing of the
+            // chord's box; keep the part of that box inside this tile
+            S.box[tid][0] = max((int)(min(ax, bx) >> 16) - 1, x0);
+            S.box[tid][1] = min((int)(-((-max(ax, bx)) >> 16)) + 1, min(x0 + kTile, I.nx) - 1);
+            S.box[tid][2] = max((int)(min(ay, by) >> 16) - 1, y0);
+            S.box[tid][3] = min((int)(-((-max(ay, by)) >> 16)) + 1, min(y0 + kTile, I.ny) - 1);
             S.jpa[tid] = P.jp[I.mk_off + k];
             S.jpb[tid] = P.jp[I.mk_off + kp];
-            S.mx[tid] = a0.x; S.my[tid] = a0.y;
+            const int mk = I.mk_off + k;
+            S.f0[tid] = P.f0[mk];
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                S.wx[tid][q] = P.wx[4 * mk + q];
+                S.wy[tid][q] = P.wy[4 * mk + q];
+            }
             const double2 g = P.Gt[I.mk_off + k];
             S.gtx[tid] = g.x; S.gty[tid] = g.y;
         }
         __syncthreads();
 
-        const int tx = t % I.tiles_x, ty = t / I.tiles_x;
-        const int x = tx * kTile + (tid & (kTile - 1)), y = ty * kTile + tid / kTile;
+        // Cut links.  Membrane: chord by chord, each wave takes whole chords
+        // and its lanes the candidate (node, direction) pairs of the chord.
+        if (IFACE == II_LBM_IF_MEMBRANE) {
+            for (int j = wid; j < c; j += 4) {
+                const int bx0 = S.box[j][0], bx1 = S.box[j][1], by0 = S.box[j][2], by1 = S.box[j][3];
+                if (bx0 > bx1 || by0 > by1) continue;
+                const int w = bx1 - bx0 + 1;
+                const int ncand = 8 * w * (by1 - by0 + 1);
+                const Chord ch = S.ch[j];
+                const long long dx = ch.bx - ch.ax, dy = ch.by - ch.ay;
+                for (int q = lane; q < ncand; q += 64) {
+                    const int i = 1 + (q & 7), nidx = q >> 3;
+                    const int x = bx0 + nidx % w, y = by0 + nidx / w;
+                    const long long px = (long long)x << 16, py = (long long)y << 16;
+                    const long long oP = dx * (py - ch.ay) - dy * (px - ch.ax);
+                    const int sP = node_sign(oP, dx, dy);
+                    int sg;
+                    double qq, th;
+                    if (!link_crossing<true>(x, y, i, ch, oP, sP, sg, qq, th)) continue;
+                    const double jpc = (1.0 - th) * S.jpa[j] + th * S.jpb[j];
+                    add_crossing(S, I, x - x0, y - y0, x, y, i, sg, S.key[j], qq, th, jpc,
+                                 records != 0);
+                }
+            }
+        }
+
+        const int lx = tid & (kTile - 1), ly = tid / kTile;
+        const int x = x0 + lx, y = y0 + ly;
         const bool valid = x < I.nx && y < I.ny;
         double gx = 0.0, gy = 0.0;
-        double acc[9];
-#pragma unroll
-        for (int i = 0; i < 9; i++) acc[i] = 0.0;
-        int ncross = 0;
         if (valid) {
             // tangential force g_par(x) = sum_k G_par,k delta_h(x - X_k) dX (Sec. 3.2, Eq. (46))
+            // (delta weights of marker k at this node, from the marker kernel)
             for (int j = 0; j < c; j++) {
-                const double rx = (double)x - S.mx[j];
-                if (fabs(rx) >= 2.0) continue;
-                const double ry = (double)y - S.my[j];
-                if (fabs(ry) >= 2.0) continue;
-                const double w = peskin(rx) * peskin(ry);
+                const int ix = x - S.f0[j].x, iy = y - S.f0[j].y;
+                if ((unsigned)ix > 3u || (unsigned)iy > 3u) continue;
+                const double w = S.wx[j][ix] * S.wy[j][iy];
+                if (w == 0.0) continue;
                 gx += S.gtx[j] * w * I.dX;
                 gy += S.gty[j] * w * I.dX;
             }
-            // jumps sigma [[f_i]] = sigma w_i [[p]] / c_s^2 on every cut link
-            // leaving (x, y) (Sec. 3.1, Eq. (32); Sec. 3.2, Eq. (47))
-            if (IFACE == II_LBM_IF_MEMBRANE) {
-                const long long px = (long long)x << 16, py = (long long)y << 16;
-                for (int j = 0; j < c; j++) {
-                    if (x + 1 < S.box[j][0] || x - 1 > S.box[j][1] || y + 1 < S.box[j][2] ||
-                        y - 1 > S.box[j][3])
-                        continue;
-                    const long long ax = S.ax[j], ay = S.ay[j], bx = S.bx[j], by = S.by[j];
-                    const int sp = node_side(ax, ay, bx, by, px, py);
-#pragma unroll
-                    for (int i = 1; i < 9; i++) {
-                        const long long qx = (long long)(x + EX[i]) << 16;
-                        const long long qy = (long long)(y + EY[i]) << 16;
-                        if (node_side(ax, ay, bx, by, qx, qy) == sp) continue;
-                        if (end_side(px, py, qx, qy, ax, ay) == end_side(px, py, qx, qy, bx, by))
-                            continue;
-                        const double oA = (double)cross3(px, py, qx, qy, ax, ay);
-                        const double oB = (double)cross3(px, py, qx, qy, bx, by);
-                        const double th = oA / (oA - oB);
-                        const double jpc = (1.0 - th) * S.jpa[j] + th * S.jpb[j];
-                        const double sg = sp > 0 ? 1.0 : -1.0;
-                        acc[i] += sg * WD[i] * jpc / kCs2;
-                        ncross++;
-                    }
-                }
-            } else {
+            if (IFACE == II_LBM_IF_RIGID) {
+                // Rigid circle: level set phi = |x - c|^2 - R^2, interior phi < 0.
                 const double R2 = I.radius * I.radius;
-                const double phP =
-                    ((double)x - I.cx) * ((double)x - I.cx) + ((double)y - I.cy) * ((double)y - I.cy) - R2;
-#pragma unroll
+                const double dx = (double)x - I.cx, dy = (double)y - I.cy;
+                const double phP = dx * dx + dy * dy - R2;
                 for (int i = 1; i < 9; i++) {
                     const double qxd = (double)(x + EX[i]), qyd = (double)(y + EY[i]);
                     const double phQ = (qxd - I.cx) * (qxd - I.cx) + (qyd - I.cy) * (qyd - I.cy) - R2;
                     const bool inP = phP < 0.0, inQ = phQ < 0.0;
                     if (inP == inQ) continue;
-                    const double dx = (double)x - I.cx, dy = (double)y - I.cy;
+                    // cut point: |P + q e - c|^2 = R^2 on the link
                     const double ee = (double)(EX[i] * EX[i] + EY[i] * EY[i]);
                     const double de = dx * EX[i] + dy * EY[i];
                     const double dd = dx * dx + dy * dy - R2;
                     const double disc = sqrt(de * de - ee * dd);
                     const double q = inP ? (-de + disc) / ee : (-de - disc) / ee;
                     const double cxp = (double)x + q * EX[i] - I.cx, cyp = (double)y + q * EY[i] - I.cy;
+                    // [[p]] linear in angle between the two bracketing markers
                     double ang = atan2(cyp, cxp);
                     if (ang < 0.0) ang += 2.0 * M_PI;
                     const double sN = ang * N / (2.0 * M_PI);
-                    int k = (sN >= 0.0 && sN < (double)N) ? (int)floor(sN) : 0;
+                    const int k = (sN >= 0.0 && sN < (double)N) ? (int)floor(sN) : 0;
                     const double th = sN - k;
-                    const double jpc = (1.0 - th) * P.jp[I.mk_off + k] + th * P.jp[I.mk_off + (k + 1) % N];
-                    acc[i] += (inP ? 1.0 : -1.0) * WD[i] * jpc / kCs2;
-                    ncross++;
+                    const double jpc =
+                        (1.0 - th) * P.jp[I.mk_off + k] + th * P.jp[I.mk_off + (k + 1) % N];
+                    add_crossing(S, I, lx, ly, x, y, i, inP ? 1 : -1, k, q, th, jpc, records != 0);
                 }
             }
-        }
-
-        // Record compaction: block-wide exclusive prefix sum of the per-node
-        // crossing counts (wavefront scan + four wave totals), one atomic per
-        // tile for the base of its slice.
-        int v = ncross;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const int o = __shfl_up(v, off, 64);
-            if (lane >= off) v += o;
-        }
-        if (lane == 63) S.woff[wid] = v;
-        __syncthreads();
-        if (tid == 0) {
-            int tot = 0;
-            for (int w = 0; w < 4; w++) {
-                const int cw = S.woff[w];
-                S.woff[w] = tot;
-                tot += cw;
-            }
-            S.tot = tot;
-            S.base = (records && tot > 0) ? atomicAdd(&P.rec_count[2 * I.inst + parity], tot) : 0;
         }
         __syncthreads();
-        if (records && S.tot > 0 && valid && ncross > 0) {
-            int o = S.base + S.woff[wid] + (v - ncross);
-            if (IFACE == II_LBM_IF_MEMBRANE) {
-                const long long px = (long long)x << 16, py = (long long)y << 16;
-                for (int j = 0; j < c; j++) {
-                    if (x + 1 < S.box[j][0] || x - 1 > S.box[j][1] || y + 1 < S.box[j][2] ||
-                        y - 1 > S.box[j][3])
-                        continue;
-                    const long long ax = S.ax[j], ay = S.ay[j], bx = S.bx[j], by = S.by[j];
-                    const int sp = node_side(ax, ay, bx, by, px, py);
-                    for (int i = 1; i < 9; i++) {
-                        const long long qx = (long long)(x + EX[i]) << 16;
-                        const long long qy = (long long)(y + EY[i]) << 16;
-                        if (node_side(ax, ay, bx, by, qx, qy) == sp) continue;
-                        if (end_side(px, py, qx, qy, ax, ay) == end_side(px, py, qx, qy, bx, by))
-                            continue;
-                        const double oP = (double)cross3(ax, ay, bx, by, px, py);
-                        const double oQ = (double)cross3(ax, ay, bx, by, qx, qy);
-                        const double oA = (double)cross3(px, py, qx, qy, ax, ay);
-                        const double oB = (double)cross3(px, py, qx, qy, bx, by);
-                        const double th = oA / (oA - oB);
-                        if (o < I.rec_cap) {
-                            ii_lbm_link r;
-                            r.x = x; r.y = y; r.dir = i; r.sigma = sp > 0 ? 1 : -1;
-                            r.seg = S.key[j]; r.inst = I.inst;
-                            r.q = oP / (oP - oQ); r.theta = th;
-                            r.jp = (1.0 - th) * S.jpa[j] + th * S.jpb[j];
-                            P.rec[I.rec_off + o] = r;
-                        } else {
-                            atomicOr(&P.err[I.inst], (int)kErrRecords);
-                        }
-                        o++;
-                    }
-                }
-            } else {
-                const double R2 = I.radius * I.radius;
-                for (int i = 1; i < 9; i++) {
-                    const double phP = ((double)x - I.cx) * ((double)x - I.cx) +
-                                       ((double)y - I.cy) * ((double)y - I.cy) - R2;
-                    const double qxd = (double)(x + EX[i]), qyd = (double)(y + EY[i]);
-                    const double phQ = (qxd - I.cx) * (qxd - I.cx) + (qyd - I.cy) * (qyd - I.cy) - R2;
-                    const bool inP = phP < 0.0, inQ = phQ < 0.0;
-                    if (inP == inQ) continue;
-                    const double dx = (double)x - I.cx, dy = (double)y - I.cy;
-                    const double ee = (double)(EX[i] * EX[i] + EY[i] * EY[i]);
-                    const double de = dx * EX[i] + dy * EY[i];
-                    const double dd = dx * dx + dy * dy - R2;
-                    const double disc = sqrt(de * de - ee * dd);
-                    const double q = inP ? (-de + disc) / ee : (-de - disc) / ee;
-                    const double cxp = (double)x + q * EX[i] - I.cx, cyp = (double)y + q * EY[i] - I.cy;
-                    double ang = atan2(cyp, cxp);
-                    if (ang < 0.0) ang += 2.0 * M_PI;
-                    const double sN = ang * N / (2.0 * M_PI);
-                    int k = (sN >= 0.0 && sN < (double)N) ? (int)floor(sN) : 0;
-                    const double th = sN - k;
-                    if (o < I.rec_cap) {
-                        ii_lbm_link r;
-                        r.x = x; r.y = y; r.dir = i; r.sigma = inP ? 1 : -1;
-                        r.seg = k; r.inst = I.inst;
-                        r.q = q; r.theta = th;
-                        r.jp = (1.0 - th) * P.jp[I.mk_off + k] + th * P.jp[I.mk_off + (k + 1) % N];
-                        P.rec[I.rec_off + o] = r;
-                    } else {
-                        atomicOr(&P.err[I.inst], (int)kErrRecords);
-                    }
-                    o++;
-                }
-            }
-        }
 
-        // One read-modify-write per corrected population: force term of the
-        // tangential force plus the jumps of the links this node sends.
-        if (valid) {
-            T* base = B + I.lat_off + (long long)y * I.pitch + x;
+        // Corrections of this node's outgoing populations: force term of the
+        // tangential force plus the jumps of the links it sends; the sweep
+        // adds them before its single store.
+        {
+            float* cr = P.corr + (long long)(I.act_off + a) * 8 * kTileNodes + tid;
 #pragma unroll
             for (int i = 1; i < 9; i++) {
                 const double delta =
-                    3.0 * WD[i] * ((double)EX[i] * gx + (double)EY[i] * gy) + acc[i];
-                if (delta != 0.0) {
-                    T* pp = base + i * I.plane;
-                    Store<T>::st(pp, Store<T>::ld(pp, I.scale) + (float)delta, I.inv_scale);
-                }
+                    valid ? 3.0 * WD[i] * ((double)EX[i] * gx + (double)EY[i] * gy) + S.acc[i - 1][tid]
+                          : 0.0;
+                cr[(i - 1) * kTileNodes] = (float)delta;
+            }
+        }
+        // Records of this tile: one global slice for the block, filled from
+        // the LDS staging list.
+        if (records) {
+            const int nr = min(S.nrec, kTileRec);
+            if (tid == 0) {
+                S.base = nr > 0 ? atomicAdd(&P.rec_count[2 * I.inst + parity], nr) : 0;
+                if (S.nrec > kTileRec) atomicOr(&P.err[I.inst], (int)kErrRecords);
+            }
+            __syncthreads();
+            const int base = S.base;
+            for (int r = tid; r < nr; r += blockDim.x) {
+                if (base + r < I.rec_cap)
+                    P.rec[I.rec_off + base + r] = S.rec[r];
+                else
+                    atomicOr(&P.err[I.inst], (int)kErrRecords);
             }
         }
         __syncthreads();
     }
 }
 
-template <typename T>
-static hipError_t tiles_t(const InstDev& I, const DevPtrs& P, void* B, int parity, int records,
-                          hipStream_t s)
+hipError_t launch_tiles(const InstDev& I, const DevPtrs& P, int parity, int records, hipStream_t s)
 {
     const int nb = max(1, min(I.act_cap, 2048));
     if (I.iface == II_LBM_IF_MEMBRANE)
-        hipLaunchKernelGGL((k_tiles<T, II_LBM_IF_MEMBRANE>), dim3(nb), dim3(256), 0, s, I, P,
-                           (T*)B, parity, records);
+        hipLaunchKernelGGL((k_tiles<II_LBM_IF_MEMBRANE>), dim3(nb), dim3(256), 0, s, I, P, parity,
+                           records);
     else
-        hipLaunchKernelGGL((k_tiles<T, II_LBM_IF_RIGID>), dim3(nb), dim3(256), 0, s, I, P, (T*)B,
-                           parity, records);
+        hipLaunchKernelGGL((k_tiles<II_LBM_IF_RIGID>), dim3(nb), dim3(256), 0, s, I, P, parity,
+                           records);
     return hipGetLastError();
-}
-
-hipError_t launch_tiles(const InstDev& I, const DevPtrs& P, void* B, int parity, int records,
-                        hipStream_t s)
-{
-    return I.storage == II_LBM_FP16 ? tiles_t<_Float16>(I, P, B, parity, records, s)
-                                    : tiles_t<float>(I, P, B, parity, records, s);
 }
 
 }  // namespace iilbm

@@ -25,8 +25,9 @@ struct Layout {
     std::vector<InstDev> inst;
     size_t lat_bytes = 0;  // one lattice buffer (all instances)
     size_t off_lat[2] = {0, 0};
-    size_t off_X[2] = {0, 0}, off_U = 0, off_G = 0, off_Gt = 0, off_jp = 0;
-    size_t off_tile_count = 0, off_tile_list = 0, off_act_list = 0, off_act_count = 0;
+    size_t off_X[2] = {0, 0}, off_U = 0, off_G = 0, off_Gt = 0, off_jp = 0, off_wx = 0, off_wy = 0, off_f0 = 0;
+    size_t off_tile_count = 0, off_tile_list = 0, off_tile_slot = 0, off_corr = 0;
+    size_t off_act_list[2] = {0, 0}, off_act_count = 0;
     size_t off_rec = 0, off_rec_count = 0, off_err = 0, off_diag = 0;
     size_t total = 0;
     int n_markers_total = 0, tiles_total = 0, act_total = 0, rec_total = 0;
@@ -46,6 +47,7 @@ int validate(const ii_lbm_problem& p, const double* X0)
     if (p.bc[0] == II_LBM_BC_OUTLET || p.bc[2] == II_LBM_BC_OUTLET || p.bc[3] == II_LBM_BC_OUTLET)
         return II_LBM_EINVAL;
     if (p.storage != II_LBM_FP32 && p.storage != II_LBM_FP16) return II_LBM_EINVAL;
+    if (p.math != II_LBM_MATH_FP32 && p.math != II_LBM_MATH_FP64) return II_LBM_EINVAL;
     if (p.force_mode != II_LBM_FORCE_II) return II_LBM_EINVAL;
     if (p.interface_kind == II_LBM_IF_NONE) return II_LBM_OK;
     if (p.interface_kind != II_LBM_IF_MEMBRANE && p.interface_kind != II_LBM_IF_RIGID)
@@ -111,6 +113,7 @@ int build_layout(const ii_lbm_problem* p, int n_inst, Layout& L)
         }
         I.collision = q.collision;
         I.storage = q.storage;
+        I.math = q.math;
         I.iface = q.interface_kind;
         I.n_markers = q.interface_kind == II_LBM_IF_NONE ? 0 : q.n_markers;
         I.inst = j;
@@ -120,6 +123,7 @@ int build_layout(const ii_lbm_problem* p, int n_inst, Layout& L)
         I.lat_off = (long long)(lat / eb);
         lat += (size_t)9 * I.plane * eb;
         I.omega = (float)(1.0 / q.tau);
+        I.omega_d = 1.0 / q.tau;
         bool all_zero = true;
         for (int a = 0; a < 9; a++) all_zero = all_zero && q.mrt_s[a] == 0.0;
         const double defaults[9] = {0.0, 1.63, 1.14, 0.0, 1.92, 0.0, 1.92, 1.0 / q.tau, 1.0 / q.tau};
@@ -141,7 +145,9 @@ int build_layout(const ii_lbm_problem* p, int n_inst, Layout& L)
         I.tile_off = tiles;
         tiles += I.tiles_x * I.tiles_y;
         I.act_off = act;
-        I.act_cap = std::min(I.tiles_x * I.tiles_y, 9 * std::max(I.n_markers, 1));
+        // tiles within 2.5 lu of a closed curve of N chords; the bound leaves
+        // room for chords of up to 2 lu (longer curves report ECAPACITY)
+        I.act_cap = std::min(I.tiles_x * I.tiles_y, I.n_markers / 2 + 256);
         act += I.act_cap;
         I.rec_off = rec;
         I.rec_cap = 48 * I.n_markers + 1024;
@@ -168,9 +174,15 @@ int build_layout(const ii_lbm_problem* p, int n_inst, Layout& L)
     L.off_G = take(nm * sizeof(double2));
     L.off_Gt = take(nm * sizeof(double2));
     L.off_jp = take(nm * sizeof(double));
+    L.off_wx = take(4 * nm * sizeof(double));
+    L.off_wy = take(4 * nm * sizeof(double));
+    L.off_f0 = take(nm * sizeof(int2));
     L.off_tile_count = take((size_t)tiles * sizeof(int));
     L.off_tile_list = take((size_t)tiles * kTileCap * sizeof(int));
-    L.off_act_list = take((size_t)std::max(act, 1) * sizeof(int2));
+    L.off_tile_slot = take((size_t)tiles * sizeof(int));
+    L.off_corr = take((size_t)std::max(act, 1) * 8 * kTileNodes * sizeof(float));
+    L.off_act_list[0] = take((size_t)std::max(act, 1) * sizeof(int2));
+    L.off_act_list[1] = take((size_t)std::max(act, 1) * sizeof(int2));
     L.off_act_count = take((size_t)2 * n_inst * sizeof(int));
     L.off_rec = take((size_t)std::max(rec, 1) * sizeof(ii_lbm_link));
     L.off_rec_count = take((size_t)2 * n_inst * sizeof(int));
@@ -290,9 +302,15 @@ int ii_lbm_init(const ii_lbm_problem* p, int32_t n_inst, const double* const* X0
     P.G = (double2*)(h->ws + L.off_G);
     P.Gt = (double2*)(h->ws + L.off_Gt);
     P.jp = (double*)(h->ws + L.off_jp);
+    P.wx = (double*)(h->ws + L.off_wx);
+    P.wy = (double*)(h->ws + L.off_wy);
+    P.f0 = (int2*)(h->ws + L.off_f0);
     P.tile_count = (int*)(h->ws + L.off_tile_count);
     P.tile_list = (int*)(h->ws + L.off_tile_list);
-    P.act_list = (int2*)(h->ws + L.off_act_list);
+    P.tile_slot = (int*)(h->ws + L.off_tile_slot);
+    P.corr = (float*)(h->ws + L.off_corr);
+    P.act_list[0] = (int2*)(h->ws + L.off_act_list[0]);
+    P.act_list[1] = (int2*)(h->ws + L.off_act_list[1]);
     P.act_count = (int*)(h->ws + L.off_act_count);
     P.rec = (ii_lbm_link*)(h->ws + L.off_rec);
     P.rec_count = (int*)(h->ws + L.off_rec_count);
@@ -304,10 +322,11 @@ int ii_lbm_init(const ii_lbm_problem* p, int32_t n_inst, const double* const* X0
         e = launch_fill_zero(L.inst[j], P.lat[0], h->stream);
         if (e == hipSuccess) e = launch_fill_zero(L.inst[j], P.lat[1], h->stream);
     }
-    if (e == hipSuccess) e = launch_zero_ints(P.tile_count, L.tiles_total, h->stream);
-    if (e == hipSuccess) e = launch_zero_ints(P.act_count, 2 * n_inst, h->stream);
-    if (e == hipSuccess) e = launch_zero_ints(P.rec_count, 2 * n_inst, h->stream);
-    if (e == hipSuccess) e = launch_zero_ints(P.err, n_inst, h->stream);
+    if (e == hipSuccess) e = launch_fill_ints(P.tile_count, L.tiles_total, 0, h->stream);
+    if (e == hipSuccess) e = launch_fill_ints(P.tile_slot, L.tiles_total, -1, h->stream);
+    if (e == hipSuccess) e = launch_fill_ints(P.act_count, 2 * n_inst, 0, h->stream);
+    if (e == hipSuccess) e = launch_fill_ints(P.rec_count, 2 * n_inst, 0, h->stream);
+    if (e == hipSuccess) e = launch_fill_ints(P.err, n_inst, 0, h->stream);
     for (int j = 0; j < n_inst && e == hipSuccess; j++) {
         const InstDev& I = L.inst[j];
         if (I.n_markers == 0) continue;
@@ -339,18 +358,19 @@ int ii_lbm_step(ii_lbm_handle* h, int64_t n_steps)
         for (int j = 0; j < n_inst; j++) {
             const InstDev& I = h->L.inst[j];
             hipError_t e = hipSuccess;
-            if (I.n_markers > 0) e = launch_markers(I, h->P, A, par, h->stream);
+            if (I.n_markers > 0) {
+                e = launch_markers(I, h->P, A, par, h->stream);
+                if (e == hipSuccess) e = launch_tiles(I, h->P, par, h->records, h->stream);
+            }
             if (e != hipSuccess) return hip_fail(h, e);
             const bool timed = h->timing && h->ev_used + 2 <= (int)h->ev.size();
             if (timed) hipEventRecord(h->ev[h->ev_used], h->stream);
-            e = launch_sweep(I, A, B, h->stream);
+            e = launch_sweep(I, h->P, A, B, h->stream);
             if (e != hipSuccess) return hip_fail(h, e);
             if (timed) {
                 hipEventRecord(h->ev[h->ev_used + 1], h->stream);
                 h->ev_used += 2;
             }
-            if (I.n_markers > 0) e = launch_tiles(I, h->P, B, par, h->records, h->stream);
-            if (e != hipSuccess) return hip_fail(h, e);
         }
         h->parity ^= 1;
         h->steps++;

@@ -7,56 +7,78 @@ namespace iilbm {
 
 // One time step of the bulk: gather f^n at (x, y) (pulled populations that
 // already carry the previous step's jumps and force; extrapolated on bounded
-// sides), collide (SRT or MRT) with the uniform body force, store the
-// post-collision populations at (x, y).  The interface kernel then adds the
-// tangential force and the jumps of this step to the stored values of the
-// few nodes near the interface.
-template <typename T, int COLL, bool BOUNDED>
+// sides), collide (SRT or MRT) with the uniform body force, add this step's
+// interface corrections (tangential force term and jumps of the links this
+// node sends, prepared per 16x16 tile by the interface kernel) and store the
+// result at (x, y): every stored value is rounded exactly once.
+template <typename T, typename M, int COLL, bool BOUNDED>
 __global__ __launch_bounds__(kSweepBX* kSweepBY) void k_sweep(InstDev I,
                                                              const T* __restrict__ A,
-                                                             T* __restrict__ B, int bx_count)
+                                                             T* __restrict__ B, int bx_count,
+                                                             const int* __restrict__ tile_slot,
+                                                             const float* __restrict__ corr)
 {
     const int bx = blockIdx.x % bx_count, by = blockIdx.x / bx_count;
     const int x = bx * kSweepBX + threadIdx.x;
     const int y = by * kSweepBY + threadIdx.y;
     if (x >= I.nx || y >= I.ny) return;
-    float d[9];
+    M d[9];
     if (BOUNDED && is_edge(I, x, y))
-        nee<T>(I, A, x, y, d);
+        nee<T, M>(I, A, x, y, d);
     else
-        pull<T>(I, A, x, y, d);
+        pull<T, M>(I, A, x, y, d);
     if (COLL == II_LBM_SRT)
-        collide_srt(d, I.omega, I.body[0], I.body[1]);
+        collide_srt<M>(d, sizeof(M) == 8 ? (M)I.omega_d : (M)I.omega, (M)I.body[0], (M)I.body[1]);
     else
-        collide_mrt(d, I.s, I.body[0], I.body[1]);
+        collide_mrt<M>(d, I.s, (M)I.body[0], (M)I.body[1]);
+    if (I.n_markers > 0) {
+        const int slot = tile_slot[I.tile_off + (y / kTile) * I.tiles_x + (x / kTile)];
+        if (slot >= 0) {
+            const float* c = corr + (long long)slot * 8 * kTileNodes + (y % kTile) * kTile + (x % kTile);
+#pragma unroll
+            for (int i = 1; i < 9; i++) d[i] += (M)c[(i - 1) * kTileNodes];
+        }
+    }
     T* base = B + I.lat_off + (long long)y * I.pitch + x;
 #pragma unroll
-    for (int i = 0; i < 9; i++) Store<T>::st(base + i * I.plane, d[i], I.inv_scale);
+    for (int i = 0; i < 9; i++) Store<T>::st(base + i * I.plane, (float)d[i], I.inv_scale);
 }
 
-template <typename T, int COLL, bool BOUNDED>
-static hipError_t sweep_t(const InstDev& I, const void* A, void* B, hipStream_t s)
+template <typename T, typename M, int COLL, bool BOUNDED>
+static hipError_t sweep_t(const InstDev& I, const DevPtrs& P, const void* A, void* B,
+                          hipStream_t s)
 {
     const int bxn = (I.nx + kSweepBX - 1) / kSweepBX;
     const int byn = (I.ny + kSweepBY - 1) / kSweepBY;
-    hipLaunchKernelGGL((k_sweep<T, COLL, BOUNDED>), dim3(bxn * byn), dim3(kSweepBX, kSweepBY), 0,
-                       s, I, (const T*)A, (T*)B, bxn);
+    hipLaunchKernelGGL((k_sweep<T, M, COLL, BOUNDED>), dim3(bxn * byn), dim3(kSweepBX, kSweepBY),
+                       0, s, I, (const T*)A, (T*)B, bxn, P.tile_slot, P.corr);
     return hipGetLastError();
 }
 
-template <typename T>
-static hipError_t sweep_s(const InstDev& I, const void* A, void* B, hipStream_t s)
+template <typename T, typename M>
+static hipError_t sweep_m(const InstDev& I, const DevPtrs& P, const void* A, void* B,
+                          hipStream_t s)
 {
     if (I.collision == II_LBM_SRT)
-        return I.bounded ? sweep_t<T, II_LBM_SRT, true>(I, A, B, s)
-                         : sweep_t<T, II_LBM_SRT, false>(I, A, B, s);
-    return I.bounded ? sweep_t<T, II_LBM_MRT, true>(I, A, B, s)
-                     : sweep_t<T, II_LBM_MRT, false>(I, A, B, s);
+        return I.bounded ? sweep_t<T, M, II_LBM_SRT, true>(I, P, A, B, s)
+                         : sweep_t<T, M, II_LBM_SRT, false>(I, P, A, B, s);
+    return I.bounded ? sweep_t<T, M, II_LBM_MRT, true>(I, P, A, B, s)
+                     : sweep_t<T, M, II_LBM_MRT, false>(I, P, A, B, s);
 }
 
-hipError_t launch_sweep(const InstDev& I, const void* A, void* B, hipStream_t s)
+template <typename T>
+static hipError_t sweep_s(const InstDev& I, const DevPtrs& P, const void* A, void* B,
+                          hipStream_t s)
 {
-    return I.storage == II_LBM_FP16 ? sweep_s<_Float16>(I, A, B, s) : sweep_s<float>(I, A, B, s);
+    return I.math == II_LBM_MATH_FP64 ? sweep_m<T, double>(I, P, A, B, s)
+                                      : sweep_m<T, float>(I, P, A, B, s);
+}
+
+hipError_t launch_sweep(const InstDev& I, const DevPtrs& P, const void* A, void* B,
+                        hipStream_t s)
+{
+    return I.storage == II_LBM_FP16 ? sweep_s<_Float16>(I, P, A, B, s)
+                                    : sweep_s<float>(I, P, A, B, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -82,32 +104,32 @@ hipError_t launch_fill_zero(const InstDev& I, void* A, hipStream_t s)
     return hipGetLastError();
 }
 
-__global__ void k_zero_ints(int* p, long long n)
+__global__ void k_fill_ints(int* p, long long n, int value)
 {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x)
-        p[i] = 0;
+        p[i] = value;
 }
 
-hipError_t launch_zero_ints(int* p, long long n, hipStream_t s)
+hipError_t launch_fill_ints(int* p, long long n, int value, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_zero_ints, dim3(1024), dim3(256), 0, s, p, n);
+    hipLaunchKernelGGL(k_fill_ints, dim3(1024), dim3(256), 0, s, p, n, value);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // Field readout of f^n: planes in bit order RHO, UX, UY, P, DISTRIB(9).
 // ---------------------------------------------------------------------------
-template <typename T, typename O>
+template <typename T, typename M, typename O>
 __global__ void k_fields(InstDev I, const T* __restrict__ A, uint32_t what, O* __restrict__ out)
 {
     const long long n = (long long)I.nx * I.ny;
     for (long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x; id < n;
          id += (long long)gridDim.x * blockDim.x) {
         const int x = (int)(id % I.nx), y = (int)(id / I.nx);
-        float d[9];
-        gather<T>(I, A, x, y, d);
+        M d[9];
+        gather<T, M>(I, A, x, y, d);
         double r = 0.0, ux = 0.0, uy = 0.0;
 #pragma unroll
         for (int i = 0; i < 9; i++) {
@@ -128,24 +150,27 @@ __global__ void k_fields(InstDev I, const T* __restrict__ A, uint32_t what, O* _
     }
 }
 
-template <typename T>
+template <typename T, typename M>
 static hipError_t fields_t(const InstDev& I, const void* A, uint32_t what, void* out, int dtype,
                            hipStream_t s)
 {
     if (dtype == II_LBM_DT_F64)
-        hipLaunchKernelGGL((k_fields<T, double>), dim3(1024), dim3(256), 0, s, I, (const T*)A,
+        hipLaunchKernelGGL((k_fields<T, M, double>), dim3(1024), dim3(256), 0, s, I, (const T*)A,
                            what, (double*)out);
     else
-        hipLaunchKernelGGL((k_fields<T, float>), dim3(1024), dim3(256), 0, s, I, (const T*)A, what,
-                           (float*)out);
+        hipLaunchKernelGGL((k_fields<T, M, float>), dim3(1024), dim3(256), 0, s, I, (const T*)A,
+                           what, (float*)out);
     return hipGetLastError();
 }
 
 hipError_t launch_fields(const InstDev& I, const void* A, uint32_t what, void* out, int dtype,
                          hipStream_t s)
 {
-    return I.storage == II_LBM_FP16 ? fields_t<_Float16>(I, A, what, out, dtype, s)
-                                    : fields_t<float>(I, A, what, out, dtype, s);
+    if (I.math == II_LBM_MATH_FP64)
+        return I.storage == II_LBM_FP16 ? fields_t<_Float16, double>(I, A, what, out, dtype, s)
+                                        : fields_t<float, double>(I, A, what, out, dtype, s);
+    return I.storage == II_LBM_FP16 ? fields_t<_Float16, float>(I, A, what, out, dtype, s)
+                                    : fields_t<float, float>(I, A, what, out, dtype, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -186,7 +211,7 @@ hipError_t launch_set_distrib(const InstDev& I, const double* f, void* A, hipStr
 // FP64 partial sums of (sum d, sum ux, sum uy, non-finite count) per block;
 // the host adds the partials in block order (deterministic).
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, typename M>
 __global__ __launch_bounds__(256) void k_diag(InstDev I, const T* __restrict__ A,
                                               double* __restrict__ part)
 {
@@ -196,8 +221,8 @@ __global__ __launch_bounds__(256) void k_diag(InstDev I, const T* __restrict__ A
     for (long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x; id < n;
          id += (long long)gridDim.x * blockDim.x) {
         const int x = (int)(id % I.nx), y = (int)(id / I.nx);
-        float d[9];
-        gather<T>(I, A, x, y, d);
+        M d[9];
+        gather<T, M>(I, A, x, y, d);
 #pragma unroll
         for (int i = 0; i < 9; i++) {
             if (!isfinite(d[i])) bad += 1.0;
@@ -221,12 +246,21 @@ __global__ __launch_bounds__(256) void k_diag(InstDev I, const T* __restrict__ A
 hipError_t launch_diag(const InstDev& I, const void* A, double* partials, int nblocks,
                        hipStream_t s)
 {
-    if (I.storage == II_LBM_FP16)
-        hipLaunchKernelGGL(k_diag<_Float16>, dim3(nblocks), dim3(256), 0, s, I,
-                           (const _Float16*)A, partials);
-    else
-        hipLaunchKernelGGL(k_diag<float>, dim3(nblocks), dim3(256), 0, s, I, (const float*)A,
-                           partials);
+    if (I.storage == II_LBM_FP16) {
+        if (I.math == II_LBM_MATH_FP64)
+            hipLaunchKernelGGL((k_diag<_Float16, double>), dim3(nblocks), dim3(256), 0, s, I,
+                               (const _Float16*)A, partials);
+        else
+            hipLaunchKernelGGL((k_diag<_Float16, float>), dim3(nblocks), dim3(256), 0, s, I,
+                               (const _Float16*)A, partials);
+    } else {
+        if (I.math == II_LBM_MATH_FP64)
+            hipLaunchKernelGGL((k_diag<float, double>), dim3(nblocks), dim3(256), 0, s, I,
+                               (const float*)A, partials);
+        else
+            hipLaunchKernelGGL((k_diag<float, float>), dim3(nblocks), dim3(256), 0, s, I,
+                               (const float*)A, partials);
+    }
     return hipGetLastError();
 }
 

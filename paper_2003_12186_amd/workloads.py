@@ -102,6 +102,7 @@ BC_PERIODIC, BC_WALL, BC_INLET, BC_OUTLET = 0, 1, 2, 3
 IF_NONE, IF_MEMBRANE, IF_RIGID = 0, 1, 2
 FORCE_II_LBM, FORCE_IB_LBM = 0, 1
 STORE_FP32, STORE_FP16 = 0, 1
+MATH_FP32, MATH_FP64 = 0, 1
 
 # D2Q9 MRT relaxation rates printed in Sec. 2.2.1 for the non-conserved moments
 # (energy, energy square, two heat fluxes); the two stress rates are 1/tau.
@@ -127,6 +128,7 @@ class Problem:
     center: Sequence[float] = (0.0, 0.0)      # rigid circle centre
     radius: float = 0.0                       # rigid circle radius
     storage: int = STORE_FP32
+    math: int = MATH_FP32                     # collision arithmetic
     name: str = ""
 
     def rates(self) -> List[float]:
