@@ -19,8 +19,10 @@ namespace iilbm {
 // ---------------------------------------------------------------------------
 // Geometry of the launch grids.
 // ---------------------------------------------------------------------------
-constexpr int kSweepBX = 64;     // one wavefront spans 64 consecutive x
-constexpr int kSweepBY = 4;      // four rows per 256-thread block
+// The sweep runs one block per row segment of 512, 256 or 64 nodes (the
+// widest that divides the row): whole rows of distributions stream through
+// each block and the y +- 1 rows its neighbours need are read by blocks
+// dispatched close in time on the same XCD.
 constexpr int kTile = 16;        // interface tiles are 16 x 16 nodes
 constexpr int kTileCap = 128;    // chords listed per interface tile
 constexpr int kTileNodes = kTile * kTile;
@@ -100,10 +102,16 @@ constexpr double WD[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
 template <typename T>
 struct Store;
 
+// st_stream: the sweep's stores, which the next step reads back only after the
+// whole lattice has streamed through (non-temporal hint).
 template <>
 struct Store<float> {
     static __device__ __forceinline__ float ld(const float* p, float) { return *p; }
     static __device__ __forceinline__ void st(float* p, float v, float) { *p = v; }
+    static __device__ __forceinline__ void st_stream(float* p, float v, float)
+    {
+        __builtin_nontemporal_store(v, p);
+    }
 };
 
 template <>
@@ -115,6 +123,10 @@ struct Store<_Float16> {
     static __device__ __forceinline__ void st(_Float16* p, float v, float inv_scale)
     {
         *p = (_Float16)(v * inv_scale);
+    }
+    static __device__ __forceinline__ void st_stream(_Float16* p, float v, float inv_scale)
+    {
+        __builtin_nontemporal_store((_Float16)(v * inv_scale), p);
     }
 };
 

@@ -84,66 +84,69 @@ __global__ __launch_bounds__(256) void k_markers(InstDev I, DevPtrs P, const T* 
     // the per-axis delta weights, reused by the spread of this step
     if (sy == 0) P.wx[4 * (I.mk_off + k) + sx] = wx;
     if (sx == 0) P.wy[4 * (I.mk_off + k) + sy] = wy;
-    if (s != 0) return;
-    P.f0[I.mk_off + k] = make_int2(fx0, fy0);
-    const double us = cu, vs = cv;
     const int km = (k + N - 1) % N, kp = (k + 1) % N;
-    const double2 Xm = X[km], Xp = X[kp];
-    const int m = I.mk_off + k;
-    if (!inside) {
-        // non-finite or outside the lattice: keep the marker, flag the handle
-        atomicOr(&P.err[I.inst], isfinite(Xk.x) && isfinite(Xk.y) ? (int)kErrGeometry
-                                                                  : (int)kErrUnstable);
-        P.U[m] = make_double2(0.0, 0.0);
-        P.G[m] = make_double2(0.0, 0.0);
-        P.Gt[m] = make_double2(0.0, 0.0);
-        P.jp[m] = 0.0;
-        Xn[k] = Xk;
-        return;
+    const double2 Xp = X[kp];
+
+    if (s == 0) {
+        P.f0[I.mk_off + k] = make_int2(fx0, fy0);
+        const double us = cu, vs = cv;
+        const double2 Xm = X[km];
+        const int m = I.mk_off + k;
+        if (!inside) {
+            // non-finite or outside the lattice: keep the marker, flag the handle
+            atomicOr(&P.err[I.inst], isfinite(Xk.x) && isfinite(Xk.y) ? (int)kErrGeometry
+                                                                      : (int)kErrUnstable);
+            P.U[m] = make_double2(0.0, 0.0);
+            P.G[m] = make_double2(0.0, 0.0);
+            P.Gt[m] = make_double2(0.0, 0.0);
+            P.jp[m] = 0.0;
+            Xn[k] = Xk;
+        } else {
+            double gx, gy, nx_, ny_, jac;
+            if (I.iface == II_LBM_IF_MEMBRANE) {
+                // spring force kappa (X_{k+1} - 2 X_k + X_{k-1}) / dX^2 (Sec. 2.2.2, Eq. (19))
+                const double d2 = I.dX * I.dX;
+                gx = I.kappa * (Xp.x - 2.0 * Xk.x + Xm.x) / d2;
+                gy = I.kappa * (Xp.y - 2.0 * Xk.y + Xm.y) / d2;
+                // outward normal of the counter-clockwise curve, from the central chord
+                const double tx = Xp.x - Xm.x, ty = Xp.y - Xm.y;
+                const double tl = sqrt(tx * tx + ty * ty);
+                nx_ = ty / tl;
+                ny_ = -tx / tl;
+                // |dX/ds|: mean length of the two chords at the marker over Delta X
+                const double lp = hypot(Xp.x - Xk.x, Xp.y - Xk.y);
+                const double lm = hypot(Xk.x - Xm.x, Xk.y - Xm.y);
+                jac = (lp + lm) / (2.0 * I.dX);
+            } else {
+                // direct forcing to U^D = 0 with eta = 1 (Sec. 2.2.2, Eq. (18));
+                // |dX/ds| = 1 and the radial normal of the rigid circle (Sec. 3.1)
+                gx = 0.0 - us;
+                gy = 0.0 - vs;
+                nx_ = (Xk.x - I.cx) / I.radius;
+                ny_ = (Xk.y - I.cy) / I.radius;
+                jac = 1.0;
+            }
+            // [[p]] = G.n / |dX/ds| (Sec. 3.1, Eq. (40)); G_par = G - (G.n) n (Eq. (46))
+            const double gn = gx * nx_ + gy * ny_;
+            P.U[m] = make_double2(us, vs);
+            P.G[m] = make_double2(gx, gy);
+            P.jp[m] = gn / jac;
+            P.Gt[m] = make_double2(gx - gn * nx_, gy - gn * ny_);
+            // X^{n+1} = X^n + U^n (Sec. 2.2.2, Eq. (20)); a fixed body stays put.
+            double2 Xnew = Xk;
+            if (I.iface == II_LBM_IF_MEMBRANE) Xnew = make_double2(Xk.x + us, Xk.y + vs);
+            Xn[k] = Xnew;
+            if (!isfinite(us) || !isfinite(vs)) atomicOr(&P.err[I.inst], (int)kErrUnstable);
+            if (!(Xnew.x >= 3.0 && Xnew.x <= (double)(I.nx - 4) && Xnew.y >= 3.0 &&
+                  Xnew.y <= (double)(I.ny - 4)))
+                atomicOr(&P.err[I.inst], (int)kErrGeometry);
+        }
     }
+    if (!inside) return;
 
-    double gx, gy, nx_, ny_, jac;
-    if (I.iface == II_LBM_IF_MEMBRANE) {
-        // spring force kappa (X_{k+1} - 2 X_k + X_{k-1}) / dX^2 (Sec. 2.2.2, Eq. (19))
-        const double d2 = I.dX * I.dX;
-        gx = I.kappa * (Xp.x - 2.0 * Xk.x + Xm.x) / d2;
-        gy = I.kappa * (Xp.y - 2.0 * Xk.y + Xm.y) / d2;
-        // outward normal of the counter-clockwise curve, from the central chord
-        const double tx = Xp.x - Xm.x, ty = Xp.y - Xm.y;
-        const double tl = sqrt(tx * tx + ty * ty);
-        nx_ = ty / tl;
-        ny_ = -tx / tl;
-        // |dX/ds|: mean length of the two chords at the marker over Delta X
-        const double lp = hypot(Xp.x - Xk.x, Xp.y - Xk.y);
-        const double lm = hypot(Xk.x - Xm.x, Xk.y - Xm.y);
-        jac = (lp + lm) / (2.0 * I.dX);
-    } else {
-        // direct forcing to U^D = 0 with eta = 1 (Sec. 2.2.2, Eq. (18));
-        // |dX/ds| = 1 and the radial normal of the rigid circle (Sec. 3.1)
-        gx = 0.0 - us;
-        gy = 0.0 - vs;
-        nx_ = (Xk.x - I.cx) / I.radius;
-        ny_ = (Xk.y - I.cy) / I.radius;
-        jac = 1.0;
-    }
-    // [[p]] = G.n / |dX/ds| (Sec. 3.1, Eq. (40)); G_par = G - (G.n) n (Eq. (46))
-    const double gn = gx * nx_ + gy * ny_;
-    P.U[m] = make_double2(us, vs);
-    P.G[m] = make_double2(gx, gy);
-    P.jp[m] = gn / jac;
-    P.Gt[m] = make_double2(gx - gn * nx_, gy - gn * ny_);
-
-    // X^{n+1} = X^n + U^n (Sec. 2.2.2, Eq. (20)); a fixed body stays put.
-    double2 Xnew = Xk;
-    if (I.iface == II_LBM_IF_MEMBRANE) Xnew = make_double2(Xk.x + us, Xk.y + vs);
-    Xn[k] = Xnew;
-    if (!isfinite(us) || !isfinite(vs)) atomicOr(&P.err[I.inst], (int)kErrUnstable);
-    if (!(Xnew.x >= 3.0 && Xnew.x <= (double)(I.nx - 4) && Xnew.y >= 3.0 &&
-          Xnew.y <= (double)(I.ny - 4)))
-        atomicOr(&P.err[I.inst], (int)kErrGeometry);
-
-    // Bin chord (k, k+1) into every tile within 2.5 lu of it: those tiles hold
-    // the nodes whose links it can cut and the support of marker k's delta.
+    // Bin chord (k, k+1) into every tile within 2.5 lu of it (those tiles hold
+    // the nodes whose links it can cut and the support of marker k's delta),
+    // one tile per lane of the group.
     const double xmin = fmin(Xk.x, Xp.x) - 2.5, xmax = fmax(Xk.x, Xp.x) + 2.5;
     const double ymin = fmin(Xk.y, Xp.y) - 2.5, ymax = fmax(Xk.y, Xp.y) + 2.5;
     if (!(xmin == xmin) || !(ymin == ymin) || !(xmax == xmax) || !(ymax == ymax)) return;
@@ -151,23 +154,23 @@ __global__ __launch_bounds__(256) void k_markers(InstDev I, DevPtrs P, const T* 
     const int tx1 = min(I.tiles_x - 1, (int)floor(fmin(xmax, (double)I.nx) / kTile));
     const int ty0 = max(0, (int)floor(fmax(ymin, 0.0) / kTile));
     const int ty1 = min(I.tiles_y - 1, (int)floor(fmin(ymax, (double)I.ny) / kTile));
-    for (int ty = ty0; ty <= ty1; ty++)
-        for (int tx = tx0; tx <= tx1; tx++) {
-            const int t = ty * I.tiles_x + tx;
-            const int gt = I.tile_off + t;
-            const int pos = atomicAdd(&P.tile_count[gt], 1);
-            if (pos < kTileCap)
-                P.tile_list[(long long)gt * kTileCap + pos] = k;
+    const int tw = tx1 - tx0 + 1, ntile = tw * (ty1 - ty0 + 1);
+    for (int q = s; q < ntile; q += 16) {
+        const int t = (ty0 + q / tw) * I.tiles_x + tx0 + q % tw;
+        const int gt = I.tile_off + t;
+        const int pos = atomicAdd(&P.tile_count[gt], 1);
+        if (pos < kTileCap)
+            P.tile_list[(long long)gt * kTileCap + pos] = k;
+        else
+            atomicOr(&P.err[I.inst], (int)kErrCapacity);
+        if (pos == 0) {
+            const int a = atomicAdd(&P.act_count[2 * I.inst + parity], 1);
+            if (a < I.act_cap)
+                P.act_list[parity][I.act_off + a] = make_int2(I.inst, t);
             else
                 atomicOr(&P.err[I.inst], (int)kErrCapacity);
-            if (pos == 0) {
-                const int a = atomicAdd(&P.act_count[2 * I.inst + parity], 1);
-                if (a < I.act_cap)
-                    P.act_list[parity][I.act_off + a] = make_int2(I.inst, t);
-                else
-                    atomicOr(&P.err[I.inst], (int)kErrCapacity);
-            }
         }
+    }
 }
 
 template <typename T>

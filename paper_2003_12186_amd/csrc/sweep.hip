@@ -11,17 +11,15 @@ namespace iilbm {
 // interface corrections (tangential force term and jumps of the links this
 // node sends, prepared per 16x16 tile by the interface kernel) and store the
 // result at (x, y): every stored value is rounded exactly once.
-template <typename T, typename M, int COLL, bool BOUNDED>
-__global__ __launch_bounds__(kSweepBX* kSweepBY) void k_sweep(InstDev I,
-                                                             const T* __restrict__ A,
-                                                             T* __restrict__ B, int bx_count,
-                                                             const int* __restrict__ tile_slot,
-                                                             const float* __restrict__ corr)
+template <typename T, typename M, int COLL, bool BOUNDED, int BX>
+__global__ __launch_bounds__(BX) void k_sweep(InstDev I, const T* __restrict__ A,
+                                              T* __restrict__ B, int bx_count,
+                                              const int* __restrict__ tile_slot,
+                                              const float* __restrict__ corr)
 {
-    const int bx = blockIdx.x % bx_count, by = blockIdx.x / bx_count;
-    const int x = bx * kSweepBX + threadIdx.x;
-    const int y = by * kSweepBY + threadIdx.y;
-    if (x >= I.nx || y >= I.ny) return;
+    const int bx = blockIdx.x % bx_count, y = blockIdx.x / bx_count;
+    const int x = bx * BX + threadIdx.x;
+    if (x >= I.nx) return;
     M d[9];
     if (BOUNDED && is_edge(I, x, y))
         nee<T, M>(I, A, x, y, d);
@@ -41,18 +39,26 @@ __global__ __launch_bounds__(kSweepBX* kSweepBY) void k_sweep(InstDev I,
     }
     T* base = B + I.lat_off + (long long)y * I.pitch + x;
 #pragma unroll
-    for (int i = 0; i < 9; i++) Store<T>::st(base + i * I.plane, (float)d[i], I.inv_scale);
+    for (int i = 0; i < 9; i++) Store<T>::st_stream(base + i * I.plane, (float)d[i], I.inv_scale);
+}
+
+template <typename T, typename M, int COLL, bool BOUNDED, int BX>
+static hipError_t sweep_b(const InstDev& I, const DevPtrs& P, const void* A, void* B,
+                          hipStream_t s)
+{
+    const int bxn = (I.nx + BX - 1) / BX;
+    hipLaunchKernelGGL((k_sweep<T, M, COLL, BOUNDED, BX>), dim3(bxn * I.ny), dim3(BX), 0, s, I,
+                       (const T*)A, (T*)B, bxn, P.tile_slot, P.corr);
+    return hipGetLastError();
 }
 
 template <typename T, typename M, int COLL, bool BOUNDED>
 static hipError_t sweep_t(const InstDev& I, const DevPtrs& P, const void* A, void* B,
                           hipStream_t s)
 {
-    const int bxn = (I.nx + kSweepBX - 1) / kSweepBX;
-    const int byn = (I.ny + kSweepBY - 1) / kSweepBY;
-    hipLaunchKernelGGL((k_sweep<T, M, COLL, BOUNDED>), dim3(bxn * byn), dim3(kSweepBX, kSweepBY),
-                       0, s, I, (const T*)A, (T*)B, bxn, P.tile_slot, P.corr);
-    return hipGetLastError();
+    if (I.nx % 512 == 0) return sweep_b<T, M, COLL, BOUNDED, 512>(I, P, A, B, s);
+    if (I.nx % 256 == 0) return sweep_b<T, M, COLL, BOUNDED, 256>(I, P, A, B, s);
+    return sweep_b<T, M, COLL, BOUNDED, 64>(I, P, A, B, s);
 }
 
 template <typename T, typename M>
