@@ -108,7 +108,7 @@ typedef struct ii_lbm_problem {
     int32_t math;
 } ii_lbm_problem;
 
-/* One cut link, as built for the step that last ran: the link from source
+/* One cut link (see ii_lbm_cutlinks for which step): the link from source
  * node (x, y) to (x, y) + e_dir crosses the interface; sigma = +1 when it
  * runs from the interior to the exterior and -1 otherwise (Sec. 3.2).  seg is
  * the chord (markers seg, seg+1) for membranes, the marker interval
@@ -125,7 +125,7 @@ typedef struct ii_lbm_diag_t {
     double momentum[2];    /* sum of u = sum_i e_i f_i */
     double area;           /* shoelace area of the marker polygon */
     double force[2];       /* force on the body F = -sum_k G_k dX (Sec. 2.3 Eq. (25)) */
-    int32_t n_cut_links;   /* directed (link, chord) crossings of the last step */
+    int32_t n_cut_links;   /* directed (link, chord) crossings, as ii_lbm_cutlinks counts them */
     int32_t error_bits;    /* device error flags (0 when healthy) */
 } ii_lbm_diag_t;
 
@@ -143,24 +143,34 @@ int ii_lbm_workspace_size(const ii_lbm_problem* p, int32_t n_inst, size_t* bytes
  *  d_workspace device memory of at least ws_bytes = ii_lbm_workspace_size
  *             bytes, 256-byte aligned, owned by the caller and kept alive until
  *             ii_lbm_destroy; NULL makes the library allocate (and free) it.
- *  hip_stream hipStream_t on which all work is enqueued (NULL = default).
+ *  hip_stream hipStream_t on which all work is enqueued (NULL = default);
+ *             membrane handles also create one internal non-blocking stream
+ *             (default priority) that the handle's stream joins every step.
  * The fluid starts at rest, f_i = w_i rho0.  Synchronises before returning.
  */
 int ii_lbm_init(const ii_lbm_problem* p, int32_t n_inst, const double* const* X0,
                 void* d_workspace, size_t ws_bytes, void* hip_stream, ii_lbm_handle** out);
 
-/* Enqueues n_steps time steps of every instance and returns without waiting. */
+/* Enqueues n_steps time steps of every instance and returns without waiting.
+ * For membranes the marker force depends on the positions only, so the
+ * geometry and tile pass of step n+1 (at X^{n+1}) runs on an internal stream
+ * while the sweep of step n runs on the handle's stream; the handle's stream
+ * waits for it before the step ends.  Rigid bodies, whose direct-forcing
+ * force needs U^n, run their phases in order on the handle's stream. */
 int ii_lbm_step(ii_lbm_handle* h, int64_t n_steps);
 
 /* Waits for the handle's stream and reports sticky device errors. */
 int ii_lbm_sync(ii_lbm_handle* h);
 
-/* Synchronises, then copies 2N doubles of the current marker positions X^n,
- * and of U and G of the last step, into caller-owned host buffers (any may be
- * NULL). */
+/* Synchronises, then copies 2N doubles each of the current marker positions
+ * X^n, of the velocity U^{n-1} that moved them there, and of the force G
+ * (membranes: G^n at the current positions; rigid bodies: the direct forcing
+ * of the last step) into caller-owned host buffers (any may be NULL). */
 int ii_lbm_markers(ii_lbm_handle* h, int32_t inst, double* X, double* U, double* G);
 
-/* Replaces the marker positions of one instance (2N doubles, host). */
+/* Replaces the marker positions of one instance (2N doubles, host) and, for
+ * membranes, rebuilds the force, cut links and tile corrections of the
+ * current step from them. */
 int ii_lbm_set_markers(ii_lbm_handle* h, int32_t inst, const double* X);
 
 #define II_LBM_F_RHO 1u     /* rho = sum_i f_i */
@@ -190,9 +200,11 @@ int ii_lbm_state_size(ii_lbm_handle* h, int32_t inst, size_t* bytes);
 int ii_lbm_save_state(ii_lbm_handle* h, int32_t inst, void* host_buf, size_t bytes);
 int ii_lbm_load_state(ii_lbm_handle* h, int32_t inst, const void* host_buf, size_t bytes);
 
-/* Synchronises, then copies up to `cap` cut-link records of the last step of
- * one instance into a host buffer; *count receives the total number (which
- * may exceed cap).  Records are in no particular order. */
+/* Synchronises, then copies up to `cap` cut-link records of one instance into
+ * a host buffer; *count receives the total number (which may exceed cap).
+ * Membranes: the links cut by the polygon through the current markers X^n,
+ * which the next step applies.  Rigid bodies: the links of the last step (none
+ * before the first step).  Records are in no particular order. */
 int ii_lbm_cutlinks(ii_lbm_handle* h, int32_t inst, ii_lbm_link* out, int32_t cap, int32_t* count);
 
 /* Synchronises and fills FP64 diagnostics of one instance. */
@@ -205,9 +217,23 @@ int ii_lbm_diag(ii_lbm_handle* h, int32_t inst, ii_lbm_diag_t* out);
 int ii_lbm_set_timing(ii_lbm_handle* h, int32_t enable);
 int ii_lbm_get_timing(ii_lbm_handle* h, double* sweep_ms, int64_t* launches);
 
-/* Bytes of HBM one sweep of one instance must move: nine loads and nine
- * stores of the stored deviation per node. */
+/* Bytes of HBM one sweep of one instance (inst = -1: of all instances) must
+ * move: nine loads and nine stores of the stored deviation per node. */
 int ii_lbm_sweep_bytes(ii_lbm_handle* h, int32_t inst, double* bytes);
+
+/* Replays the step as a HIP graph (two steps per graph launch, captured on
+ * first use and after re-tuning) when enable != 0.  Timing mode uses direct
+ * launches.  Results are identical either way. */
+int ii_lbm_set_graph(ii_lbm_handle* h, int32_t enable);
+
+/* Handles with several instances advance them all through one launch per
+ * phase and step, driven by work tables.  This autotuner times the batched
+ * sweep on the current state (writing only the buffer the next step
+ * overwrites) for slices of 128, 256 and 512 nodes and two instance orders
+ * (as given, largest first), `trials` launches each, and keeps the fastest.
+ * Outputs (may be NULL): the slice size, the order and its time in us.  A
+ * single-instance handle reports 0 and keeps its row-segment sweep. */
+int ii_lbm_autotune(ii_lbm_handle* h, int32_t trials, int32_t* unit, int32_t* order, double* best_us);
 
 int ii_lbm_destroy(ii_lbm_handle* h);
 const char* ii_lbm_strerror(int code);

@@ -53,8 +53,8 @@ EXPORTS = [
     "ii_lbm_workspace_size", "ii_lbm_init", "ii_lbm_step", "ii_lbm_sync", "ii_lbm_markers",
     "ii_lbm_set_markers", "ii_lbm_fields", "ii_lbm_set_distrib", "ii_lbm_state_size",
     "ii_lbm_save_state", "ii_lbm_load_state", "ii_lbm_cutlinks", "ii_lbm_diag",
-    "ii_lbm_set_timing", "ii_lbm_get_timing", "ii_lbm_sweep_bytes", "ii_lbm_destroy",
-    "ii_lbm_strerror",
+    "ii_lbm_set_timing", "ii_lbm_get_timing", "ii_lbm_sweep_bytes", "ii_lbm_set_graph",
+    "ii_lbm_autotune", "ii_lbm_destroy", "ii_lbm_strerror",
 ]
 
 _lib = None
@@ -92,6 +92,8 @@ def load():
         "ii_lbm_set_timing": [v, i32],
         "ii_lbm_get_timing": [v, C.POINTER(d), C.POINTER(i64)],
         "ii_lbm_sweep_bytes": [v, i32, C.POINTER(d)],
+        "ii_lbm_set_graph": [v, i32],
+        "ii_lbm_autotune": [v, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(d)],
         "ii_lbm_destroy": [v],
     }
     for name, args in sig.items():
@@ -245,6 +247,14 @@ class Sim:
         ms = C.c_double(); n = C.c_int64()
         check(load().ii_lbm_get_timing(self.h, C.byref(ms), C.byref(n)), "get_timing")
         return ms.value, n.value
+
+    def set_graph(self, enable: bool) -> None:
+        check(load().ii_lbm_set_graph(self.h, 1 if enable else 0), "set_graph")
+
+    def autotune(self, trials: int = 5):
+        u = C.c_int32(); o = C.c_int32(); us = C.c_double()
+        check(load().ii_lbm_autotune(self.h, int(trials), C.byref(u), C.byref(o), C.byref(us)), "autotune")
+        return {"unit": u.value, "order": o.value, "sweep_us": us.value}
 
     def sweep_bytes(self, inst: int = 0) -> float:
         b = C.c_double()

@@ -50,6 +50,8 @@ struct InstDev {
     int tile_off;         // offset in tile_count (tiles), tile_list (tiles * kTileCap)
     int act_off, act_cap;
     int rec_off, rec_cap;
+    int mk_blocks;        // 256-thread blocks of the marker kernel (16 markers each)
+    int tile_blocks;      // blocks of the tile kernel (they stride over the active tiles)
     int inst;
     long long lat_off;    // element offset of plane 0 in either lattice buffer
     long long plane;      // elements per population plane (pitch * ny)
@@ -76,8 +78,8 @@ struct DevPtrs {
     int2* f0;              // first stencil column and row of each marker
     int* tile_count;       // chords appended per tile (reset by the tile kernel)
     int* tile_list;        // chord ids per tile
-    int* tile_slot;        // correction slot of a tile this step, -1 when none
-    float* corr;           // per slot: 8 x 256 additions to the outgoing populations
+    int* tile_slot[2];     // correction slot of a tile at step m (plane m & 1), -1 when none
+    float* corr[2];        // per slot: 8 x 256 additions to the outgoing populations
     int2* act_list[2];     // (instance, tile) of the tiles that hold chords, by parity
     int* act_count;        // [2 * n_inst], double-buffered by step parity
     ii_lbm_link* rec;      // cut-link records
@@ -341,19 +343,44 @@ __device__ __forceinline__ void collide_mrt(M d[9], const float s[9], M gx, M gy
     force_term<M>(d, gx, gy);
 }
 
+// Work tables of the batched launches: one entry (instance, unit) per block.
+struct Batch {
+    const InstDev* insts;  // device copy of the descriptors
+    const int2* mk_table;  // (instance, block within the instance)
+    const int2* tile_table;
+    const int2* sweep_table;  // (instance, first node of a slice of `sweep_unit` nodes)
+    int mk_units, tile_units, sweep_units;
+    int sweep_unit;        // 128, 256 or 512 nodes per sweep block
+    int storage, math, iface;
+};
+
 // ---------------------------------------------------------------------------
 // Launch helpers implemented in the .hip files (host side).
 // ---------------------------------------------------------------------------
-hipError_t launch_sweep(const InstDev& I, const DevPtrs& P, const void* A, void* B, hipStream_t s);
+// par: parity of the step whose correction planes the sweep adds.
+hipError_t launch_sweep(const InstDev& I, const DevPtrs& P, const void* A, void* B, int par,
+                        hipStream_t s);
 hipError_t launch_fill_zero(const InstDev& I, void* A, hipStream_t s);
 hipError_t launch_fields(const InstDev& I, const void* A, uint32_t what, void* out, int dtype,
                          hipStream_t s);
 hipError_t launch_set_distrib(const InstDev& I, const double* f, void* A, hipStream_t s);
 hipError_t launch_diag(const InstDev& I, const void* A, double* partials, int nblocks,
                        hipStream_t s);
-hipError_t launch_markers(const InstDev& I, const DevPtrs& P, const void* A, int parity,
+// Marker pass modes (bit 1: interpolation and marker update, bit 2: force,
+// geometry, delta weights and tile binning).
+enum MarkerMode { kModeInterp = 1, kModeGeom = 2, kModeFull = 3 };
+hipError_t launch_markers(const InstDev& I, const DevPtrs& P, const void* A, int par, int mode,
                           hipStream_t s);
+hipError_t launch_slot_reset(const InstDev& I, const DevPtrs& P, int par, hipStream_t s);
+hipError_t launch_slot_reset_batch(const Batch& b, int n_inst, const DevPtrs& P, int par,
+                                   hipStream_t s);
 hipError_t launch_tiles(const InstDev& I, const DevPtrs& P, int parity, int records, hipStream_t s);
 hipError_t launch_fill_ints(int* p, long long n, int value, hipStream_t s);
+hipError_t launch_markers_batch(const Batch& b, const DevPtrs& P, const void* A, int par, int mode,
+                                hipStream_t s);
+hipError_t launch_tiles_batch(const Batch& b, const DevPtrs& P, int parity, int records,
+                              hipStream_t s);
+hipError_t launch_sweep_batch(const Batch& b, const DevPtrs& P, const void* A, void* B, int par,
+                              hipStream_t s);
 
 }  // namespace iilbm

@@ -32,117 +32,134 @@ __device__ __forceinline__ int wrap_or_clamp(int v, int n, int periodic)
 
 // ---------------------------------------------------------------------------
 // Markers: 16 lanes per marker, one per node of the 4 x 4 delta stencil.
+//
+// Step m uses three marker phases:
+//   INTERP  U^m = sum_x u^m delta_h (Sec. 2.2.2, Eq. (20)) from f^m and, for a
+//           membrane, X^{m+1} = X^m + U^m;
+//   GEOM    from X^m: force, outward normal, |dX/ds|, [[p]] (Sec. 3.1,
+//           Eq. (40)), tangential part (Sec. 3.2, Eq. (46)), the delta weights
+//           used by the spread, and the binning of chord (k, k+1) into tiles;
+//   FULL    both in one pass, for direct forcing, whose force needs U^m.
+// A membrane's force depends on X only, so GEOM/tiles of step m+1 can run
+// while the sweep of step m streams the lattice.
 // ---------------------------------------------------------------------------
-template <typename T, typename M>
-__global__ __launch_bounds__(256) void k_markers(InstDev I, DevPtrs P, const T* __restrict__ A,
-                                                 int parity)
+// Marker slots of the step: X^m lives in X[m & 1].
+template <typename T, typename M, int MODE>
+__device__ __forceinline__ void markers_body(const InstDev& I, const DevPtrs& P,
+                                             const T* __restrict__ A, int par, int blk)
 {
-    const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
-    // The previous step's tiles give back their correction slots.
-    {
-        const int prev = min(P.act_count[2 * I.inst + (parity ^ 1)], I.act_cap);
-        for (int a = gtid; a < prev; a += gridDim.x * blockDim.x)
-            P.tile_slot[I.tile_off + P.act_list[parity ^ 1][I.act_off + a].y] = -1;
-    }
+    const int gtid = blk * blockDim.x + threadIdx.x;
     const int N = I.n_markers;
     const int k = gtid >> 4;          // marker of this 16-lane group
     const int s = threadIdx.x & 15;   // stencil node of this lane
     const bool live = k < N;
-    const double2* X = P.X[parity] + I.mk_off;
-    double2* Xn = P.X[parity ^ 1] + I.mk_off;
+    const double2* X = P.X[par] + I.mk_off;
+    double2* Xn = P.X[par ^ 1] + I.mk_off;
     const double2 Xk = live ? X[k] : make_double2(0.0, 0.0);
     const bool inside =
         live && Xk.x >= 0.0 && Xk.x < (double)I.nx && Xk.y >= 0.0 && Xk.y < (double)I.ny;
 
-    // U_k = sum_x u^n(x) delta_h(x - X_k) (Sec. 2.2.2, Eq. (20)); u^n from the
-    // pre-collision f^n, each lane one stencil node, summed in FP64 over the
-    // group in a fixed tree.
     const int fx0 = inside ? (int)floor(Xk.x) - 1 : 0, fy0 = inside ? (int)floor(Xk.y) - 1 : 0;
     const int sx = s & 3, sy = s >> 2;
     const double wx = inside ? peskin((double)(fx0 + sx) - Xk.x) : 0.0;
     const double wy = inside ? peskin((double)(fy0 + sy) - Xk.y) : 0.0;
-    const double w = wx * wy;
-    double cu = 0.0, cv = 0.0;
-    if (w != 0.0) {
-        M d[9];
-        gather<T, M>(I, A, wrap_or_clamp(fx0 + sx, I.nx, I.px), wrap_or_clamp(fy0 + sy, I.ny, I.py), d);
-        double u = 0.0, v = 0.0;
+
+    double us = 0.0, vs = 0.0;
+    if (MODE & kModeInterp) {
+        // u^m of the pre-collision f^m at this lane's stencil node, weighted,
+        // summed in FP64 over the group in a fixed tree
+        const double w = wx * wy;
+        double cu = 0.0, cv = 0.0;
+        if (w != 0.0) {
+            M d[9];
+            gather<T, M>(I, A, wrap_or_clamp(fx0 + sx, I.nx, I.px),
+                         wrap_or_clamp(fy0 + sy, I.ny, I.py), d);
+            double u = 0.0, v = 0.0;
 #pragma unroll
-        for (int i = 1; i < 9; i++) {
-            u += (double)EX[i] * (double)d[i];
-            v += (double)EY[i] * (double)d[i];
+            for (int i = 1; i < 9; i++) {
+                u += (double)EX[i] * (double)d[i];
+                v += (double)EY[i] * (double)d[i];
+            }
+            cu = u * w;
+            cv = v * w;
         }
-        cu = u * w;
-        cv = v * w;
-    }
 #pragma unroll
-    for (int off = 8; off > 0; off >>= 1) {
-        cu += __shfl_xor(cu, off, 16);
-        cv += __shfl_xor(cv, off, 16);
+        for (int off = 8; off > 0; off >>= 1) {
+            cu += __shfl_xor(cu, off, 16);
+            cv += __shfl_xor(cv, off, 16);
+        }
+        us = cu;
+        vs = cv;
     }
     if (!live) return;
-    // the per-axis delta weights, reused by the spread of this step
-    if (sy == 0) P.wx[4 * (I.mk_off + k) + sx] = wx;
-    if (sx == 0) P.wy[4 * (I.mk_off + k) + sy] = wy;
-    const int km = (k + N - 1) % N, kp = (k + 1) % N;
-    const double2 Xp = X[kp];
-
-    if (s == 0) {
-        P.f0[I.mk_off + k] = make_int2(fx0, fy0);
-        const double us = cu, vs = cv;
-        const double2 Xm = X[km];
-        const int m = I.mk_off + k;
-        if (!inside) {
-            // non-finite or outside the lattice: keep the marker, flag the handle
-            atomicOr(&P.err[I.inst], isfinite(Xk.x) && isfinite(Xk.y) ? (int)kErrGeometry
-                                                                      : (int)kErrUnstable);
+    const int m = I.mk_off + k;
+    if (s == 0 && !inside) {
+        // non-finite or outside the lattice: keep the marker, flag the handle
+        atomicOr(&P.err[I.inst], isfinite(Xk.x) && isfinite(Xk.y) ? (int)kErrGeometry
+                                                                  : (int)kErrUnstable);
+        if (MODE & kModeInterp) {
             P.U[m] = make_double2(0.0, 0.0);
+            Xn[k] = Xk;
+        }
+        if (MODE & kModeGeom) {
             P.G[m] = make_double2(0.0, 0.0);
             P.Gt[m] = make_double2(0.0, 0.0);
             P.jp[m] = 0.0;
-            Xn[k] = Xk;
-        } else {
-            double gx, gy, nx_, ny_, jac;
-            if (I.iface == II_LBM_IF_MEMBRANE) {
-                // spring force kappa (X_{k+1} - 2 X_k + X_{k-1}) / dX^2 (Sec. 2.2.2, Eq. (19))
-                const double d2 = I.dX * I.dX;
-                gx = I.kappa * (Xp.x - 2.0 * Xk.x + Xm.x) / d2;
-                gy = I.kappa * (Xp.y - 2.0 * Xk.y + Xm.y) / d2;
-                // outward normal of the counter-clockwise curve, from the central chord
-                const double tx = Xp.x - Xm.x, ty = Xp.y - Xm.y;
-                const double tl = sqrt(tx * tx + ty * ty);
-                nx_ = ty / tl;
-                ny_ = -tx / tl;
-                // |dX/ds|: mean length of the two chords at the marker over Delta X
-                const double lp = hypot(Xp.x - Xk.x, Xp.y - Xk.y);
-                const double lm = hypot(Xk.x - Xm.x, Xk.y - Xm.y);
-                jac = (lp + lm) / (2.0 * I.dX);
-            } else {
-                // direct forcing to U^D = 0 with eta = 1 (Sec. 2.2.2, Eq. (18));
-                // |dX/ds| = 1 and the radial normal of the rigid circle (Sec. 3.1)
-                gx = 0.0 - us;
-                gy = 0.0 - vs;
-                nx_ = (Xk.x - I.cx) / I.radius;
-                ny_ = (Xk.y - I.cy) / I.radius;
-                jac = 1.0;
-            }
-            // [[p]] = G.n / |dX/ds| (Sec. 3.1, Eq. (40)); G_par = G - (G.n) n (Eq. (46))
-            const double gn = gx * nx_ + gy * ny_;
-            P.U[m] = make_double2(us, vs);
-            P.G[m] = make_double2(gx, gy);
-            P.jp[m] = gn / jac;
-            P.Gt[m] = make_double2(gx - gn * nx_, gy - gn * ny_);
-            // X^{n+1} = X^n + U^n (Sec. 2.2.2, Eq. (20)); a fixed body stays put.
-            double2 Xnew = Xk;
-            if (I.iface == II_LBM_IF_MEMBRANE) Xnew = make_double2(Xk.x + us, Xk.y + vs);
-            Xn[k] = Xnew;
-            if (!isfinite(us) || !isfinite(vs)) atomicOr(&P.err[I.inst], (int)kErrUnstable);
-            if (!(Xnew.x >= 3.0 && Xnew.x <= (double)(I.nx - 4) && Xnew.y >= 3.0 &&
-                  Xnew.y <= (double)(I.ny - 4)))
-                atomicOr(&P.err[I.inst], (int)kErrGeometry);
         }
     }
     if (!inside) return;
+
+    if ((MODE & kModeInterp) && s == 0) {
+        P.U[m] = make_double2(us, vs);
+        // X^{m+1} = X^m + U^m (Sec. 2.2.2, Eq. (20)); a fixed body stays put.
+        double2 Xnew = Xk;
+        if (I.iface == II_LBM_IF_MEMBRANE) Xnew = make_double2(Xk.x + us, Xk.y + vs);
+        Xn[k] = Xnew;
+        if (!isfinite(us) || !isfinite(vs)) atomicOr(&P.err[I.inst], (int)kErrUnstable);
+        if (!(Xnew.x >= 3.0 && Xnew.x <= (double)(I.nx - 4) && Xnew.y >= 3.0 &&
+              Xnew.y <= (double)(I.ny - 4)))
+            atomicOr(&P.err[I.inst], (int)kErrGeometry);
+    }
+    if (!(MODE & kModeGeom)) return;
+
+    // the per-axis delta weights, reused by the spread of this step
+    if (sy == 0) P.wx[4 * m + sx] = wx;
+    if (sx == 0) P.wy[4 * m + sy] = wy;
+    const int km = (k + N - 1) % N, kp = (k + 1) % N;
+    const double2 Xp = X[kp];
+    if (s == 0) {
+        P.f0[m] = make_int2(fx0, fy0);
+        const double2 Xm = X[km];
+        double gx, gy, nx_, ny_, jac;
+        if (I.iface == II_LBM_IF_MEMBRANE) {
+            // spring force kappa (X_{k+1} - 2 X_k + X_{k-1}) / dX^2 (Sec. 2.2.2, Eq. (19))
+            const double d2 = I.dX * I.dX;
+            gx = I.kappa * (Xp.x - 2.0 * Xk.x + Xm.x) / d2;
+            gy = I.kappa * (Xp.y - 2.0 * Xk.y + Xm.y) / d2;
+            // outward normal of the counter-clockwise curve, from the central chord
+            const double tx = Xp.x - Xm.x, ty = Xp.y - Xm.y;
+            const double tl = sqrt(tx * tx + ty * ty);
+            nx_ = ty / tl;
+            ny_ = -tx / tl;
+            // |dX/ds|: mean length of the two chords at the marker over Delta X
+            const double lp = hypot(Xp.x - Xk.x, Xp.y - Xk.y);
+            const double lm = hypot(Xk.x - Xm.x, Xk.y - Xm.y);
+            jac = (lp + lm) / (2.0 * I.dX);
+        } else {
+            // direct forcing to U^D = 0 with eta = 1 (Sec. 2.2.2, Eq. (18));
+            // |dX/ds| = 1 and the radial normal of the rigid circle (Sec. 3.1)
+            gx = 0.0 - us;
+            gy = 0.0 - vs;
+            nx_ = (Xk.x - I.cx) / I.radius;
+            ny_ = (Xk.y - I.cy) / I.radius;
+            jac = 1.0;
+        }
+        // [[p]] = G.n / |dX/ds| (Sec. 3.1, Eq. (40)); G_par = G - (G.n) n (Eq. (46))
+        const double gn = gx * nx_ + gy * ny_;
+        P.G[m] = make_double2(gx, gy);
+        P.jp[m] = gn / jac;
+        P.Gt[m] = make_double2(gx - gn * nx_, gy - gn * ny_);
+    }
 
     // Bin chord (k, k+1) into every tile within 2.5 lu of it (those tiles hold
     // the nodes whose links it can cut and the support of marker k's delta),
@@ -164,34 +181,135 @@ __global__ __launch_bounds__(256) void k_markers(InstDev I, DevPtrs P, const T* 
         else
             atomicOr(&P.err[I.inst], (int)kErrCapacity);
         if (pos == 0) {
-            const int a = atomicAdd(&P.act_count[2 * I.inst + parity], 1);
+            const int a = atomicAdd(&P.act_count[2 * I.inst + par], 1);
             if (a < I.act_cap)
-                P.act_list[parity][I.act_off + a] = make_int2(I.inst, t);
+                P.act_list[par][I.act_off + a] = make_int2(I.inst, t);
             else
                 atomicOr(&P.err[I.inst], (int)kErrCapacity);
         }
     }
 }
 
-template <typename T>
-static hipError_t markers_t(const InstDev& I, const DevPtrs& P, const void* A, int parity,
+template <typename T, typename M, int MODE>
+__global__ __launch_bounds__(256) void k_markers(InstDev I, DevPtrs P, const T* __restrict__ A,
+                                                 int par)
+{
+    markers_body<T, M, MODE>(I, P, A, par, blockIdx.x);
+}
+
+// Batched: every block looks its (instance, block) up in a work table.
+template <typename T, typename M, int MODE>
+__global__ __launch_bounds__(256) void k_markers_batch(const InstDev* __restrict__ insts,
+                                                       const int2* __restrict__ units, DevPtrs P,
+                                                       const T* __restrict__ A, int par)
+{
+    const int2 u = units[blockIdx.x];
+    const InstDev I = insts[u.x];
+    markers_body<T, M, MODE>(I, P, A, par, u.y);
+}
+
+// Before the tiles of step m are binned: the tiles of step m-2 (same slot
+// plane) give their correction slots back, and the active-tile and record
+// counts of that plane restart.  One block per instance.
+__device__ __forceinline__ void slot_reset_body(const InstDev& I, const DevPtrs& P, int par)
+{
+    const int prev = min(P.act_count[2 * I.inst + par], I.act_cap);
+    int* slot = P.tile_slot[par];
+    for (int a = threadIdx.x; a < prev; a += blockDim.x)
+        slot[I.tile_off + P.act_list[par][I.act_off + a].y] = -1;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        P.act_count[2 * I.inst + par] = 0;
+        P.rec_count[2 * I.inst + par] = 0;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_slot_reset(InstDev I, DevPtrs P, int par)
+{
+    slot_reset_body(I, P, par);
+}
+
+__global__ __launch_bounds__(1024) void k_slot_reset_batch(const InstDev* __restrict__ insts,
+                                                           DevPtrs P, int par)
+{
+    const InstDev I = insts[blockIdx.x];
+    if (I.n_markers > 0) slot_reset_body(I, P, par);
+}
+
+template <typename T, int MODE>
+static hipError_t markers_t(const InstDev& I, const DevPtrs& P, const void* A, int par,
                             hipStream_t s)
 {
-    const int nb = (16 * I.n_markers + 255) / 256;
+    const int nb = I.mk_blocks;
     if (I.math == II_LBM_MATH_FP64)
-        hipLaunchKernelGGL((k_markers<T, double>), dim3(nb), dim3(256), 0, s, I, P, (const T*)A,
-                           parity);
+        hipLaunchKernelGGL((k_markers<T, double, MODE>), dim3(nb), dim3(256), 0, s, I, P,
+                           (const T*)A, par);
     else
-        hipLaunchKernelGGL((k_markers<T, float>), dim3(nb), dim3(256), 0, s, I, P, (const T*)A,
-                           parity);
+        hipLaunchKernelGGL((k_markers<T, float, MODE>), dim3(nb), dim3(256), 0, s, I, P,
+                           (const T*)A, par);
     return hipGetLastError();
 }
 
-hipError_t launch_markers(const InstDev& I, const DevPtrs& P, const void* A, int parity,
+template <int MODE>
+static hipError_t markers_m(const InstDev& I, const DevPtrs& P, const void* A, int par,
+                            hipStream_t s)
+{
+    return I.storage == II_LBM_FP16 ? markers_t<_Float16, MODE>(I, P, A, par, s)
+                                    : markers_t<float, MODE>(I, P, A, par, s);
+}
+
+hipError_t launch_markers(const InstDev& I, const DevPtrs& P, const void* A, int par, int mode,
                           hipStream_t s)
 {
-    return I.storage == II_LBM_FP16 ? markers_t<_Float16>(I, P, A, parity, s)
-                                    : markers_t<float>(I, P, A, parity, s);
+    if (I.n_markers == 0) return hipSuccess;
+    if (mode == kModeInterp) return markers_m<kModeInterp>(I, P, A, par, s);
+    if (mode == kModeGeom) return markers_m<kModeGeom>(I, P, A, par, s);
+    return markers_m<kModeFull>(I, P, A, par, s);
+}
+
+template <typename T, int MODE>
+static hipError_t markers_batch_t(const Batch& b, const DevPtrs& P, const void* A, int par,
+                                  hipStream_t s)
+{
+    if (b.math == II_LBM_MATH_FP64)
+        hipLaunchKernelGGL((k_markers_batch<T, double, MODE>), dim3(b.mk_units), dim3(256), 0, s,
+                           b.insts, b.mk_table, P, (const T*)A, par);
+    else
+        hipLaunchKernelGGL((k_markers_batch<T, float, MODE>), dim3(b.mk_units), dim3(256), 0, s,
+                           b.insts, b.mk_table, P, (const T*)A, par);
+    return hipGetLastError();
+}
+
+template <int MODE>
+static hipError_t markers_batch_m(const Batch& b, const DevPtrs& P, const void* A, int par,
+                                  hipStream_t s)
+{
+    return b.storage == II_LBM_FP16 ? markers_batch_t<_Float16, MODE>(b, P, A, par, s)
+                                    : markers_batch_t<float, MODE>(b, P, A, par, s);
+}
+
+hipError_t launch_markers_batch(const Batch& b, const DevPtrs& P, const void* A, int par, int mode,
+                                hipStream_t s)
+{
+    if (b.mk_units == 0) return hipSuccess;
+    if (mode == kModeInterp) return markers_batch_m<kModeInterp>(b, P, A, par, s);
+    if (mode == kModeGeom) return markers_batch_m<kModeGeom>(b, P, A, par, s);
+    return markers_batch_m<kModeFull>(b, P, A, par, s);
+}
+
+hipError_t launch_slot_reset(const InstDev& I, const DevPtrs& P, int par, hipStream_t s)
+{
+    if (I.n_markers == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_slot_reset, dim3(1), dim3(1024), 0, s, I, P, par);
+    return hipGetLastError();
+}
+
+hipError_t launch_slot_reset_batch(const Batch& b, int n_inst, const DevPtrs& P, int par,
+                                   hipStream_t s)
+{
+    if (b.mk_units == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_slot_reset_batch, dim3(n_inst), dim3(1024), 0, s, b.insts, P, par);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -284,19 +402,15 @@ __device__ __forceinline__ void add_crossing(TileShared& S, const InstDev& I, in
 }
 
 template <int IFACE>
-__global__ __launch_bounds__(256) void k_tiles(InstDev I, DevPtrs P, int parity, int records)
+__device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, int parity,
+                                           int records, int blk, int nblk)
 {
     __shared__ TileShared S;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int N = I.n_markers;
     const double2* X = P.X[parity] + I.mk_off;
     const int nact = min(P.act_count[2 * I.inst + parity], I.act_cap);
-    if (blockIdx.x == 0 && tid == 0) {
-        // the other parity's counters were consumed by the previous step
-        P.act_count[2 * I.inst + (parity ^ 1)] = 0;
-        P.rec_count[2 * I.inst + (parity ^ 1)] = 0;
-    }
-    for (int a = blockIdx.x; a < nact; a += gridDim.x) {
+    for (int a = blk; a < nact; a += nblk) {
         const int t = P.act_list[parity][I.act_off + a].y;
         const int gt = I.tile_off + t;
         const int tx = t % I.tiles_x, ty = t / I.tiles_x;
@@ -313,7 +427,7 @@ __global__ __launch_bounds__(256) void k_tiles(InstDev I, DevPtrs P, int parity,
         __syncthreads();
         if (tid == 0) {
             P.tile_count[gt] = 0;  // ready for the next step
-            P.tile_slot[gt] = I.act_off + a;
+            P.tile_slot[parity][gt] = I.act_off + a;
         }
         // deterministic order: rank sort of the (distinct) chord ids
         if (tid < c) {
@@ -425,7 +539,7 @@ __global__ __launch_bounds__(256) void k_tiles(InstDev I, DevPtrs P, int parity,
         // tangential force plus the jumps of the links it sends; the sweep
         // adds them before its single store.
         {
-            float* cr = P.corr + (long long)(I.act_off + a) * 8 * kTileNodes + tid;
+            float* cr = P.corr[parity] + (long long)(I.act_off + a) * 8 * kTileNodes + tid;
 #pragma unroll
             for (int i = 1; i < 9; i++) {
                 const double delta =
@@ -455,15 +569,44 @@ __global__ __launch_bounds__(256) void k_tiles(InstDev I, DevPtrs P, int parity,
     }
 }
 
+template <int IFACE>
+__global__ __launch_bounds__(256) void k_tiles(InstDev I, DevPtrs P, int parity, int records)
+{
+    tiles_body<IFACE>(I, P, parity, records, blockIdx.x, gridDim.x);
+}
+
+template <int IFACE>
+__global__ __launch_bounds__(256) void k_tiles_batch(const InstDev* __restrict__ insts,
+                                                     const int2* __restrict__ units, DevPtrs P,
+                                                     int parity, int records)
+{
+    const int2 u = units[blockIdx.x];
+    const InstDev I = insts[u.x];
+    tiles_body<IFACE>(I, P, parity, records, u.y, I.tile_blocks);
+}
+
 hipError_t launch_tiles(const InstDev& I, const DevPtrs& P, int parity, int records, hipStream_t s)
 {
-    const int nb = max(1, min(I.act_cap, 2048));
+    const int nb = I.tile_blocks;
     if (I.iface == II_LBM_IF_MEMBRANE)
         hipLaunchKernelGGL((k_tiles<II_LBM_IF_MEMBRANE>), dim3(nb), dim3(256), 0, s, I, P, parity,
                            records);
     else
         hipLaunchKernelGGL((k_tiles<II_LBM_IF_RIGID>), dim3(nb), dim3(256), 0, s, I, P, parity,
                            records);
+    return hipGetLastError();
+}
+
+hipError_t launch_tiles_batch(const Batch& b, const DevPtrs& P, int parity, int records,
+                              hipStream_t s)
+{
+    if (b.tile_units == 0) return hipSuccess;
+    if (b.iface == II_LBM_IF_MEMBRANE)
+        hipLaunchKernelGGL((k_tiles_batch<II_LBM_IF_MEMBRANE>), dim3(b.tile_units), dim3(256), 0,
+                           s, b.insts, b.tile_table, P, parity, records);
+    else
+        hipLaunchKernelGGL((k_tiles_batch<II_LBM_IF_RIGID>), dim3(b.tile_units), dim3(256), 0, s,
+                           b.insts, b.tile_table, P, parity, records);
     return hipGetLastError();
 }
 

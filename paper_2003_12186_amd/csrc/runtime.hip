@@ -26,9 +26,11 @@ struct Layout {
     size_t lat_bytes = 0;  // one lattice buffer (all instances)
     size_t off_lat[2] = {0, 0};
     size_t off_X[2] = {0, 0}, off_U = 0, off_G = 0, off_Gt = 0, off_jp = 0, off_wx = 0, off_wy = 0, off_f0 = 0;
-    size_t off_tile_count = 0, off_tile_list = 0, off_tile_slot = 0, off_corr = 0;
+    size_t off_tile_count = 0, off_tile_list = 0, off_tile_slot[2] = {0, 0}, off_corr[2] = {0, 0};
     size_t off_act_list[2] = {0, 0}, off_act_count = 0;
     size_t off_rec = 0, off_rec_count = 0, off_err = 0, off_diag = 0;
+    size_t off_insts = 0, off_mk_table = 0, off_tile_table = 0, off_sweep_table = 0;
+    int mk_units = 0, tile_units = 0, sweep_units_max = 0;
     size_t total = 0;
     int n_markers_total = 0, tiles_total = 0, act_total = 0, rec_total = 0;
 };
@@ -150,8 +152,12 @@ int build_layout(const ii_lbm_problem* p, int n_inst, Layout& L)
         I.act_cap = std::min(I.tiles_x * I.tiles_y, I.n_markers / 2 + 256);
         act += I.act_cap;
         I.rec_off = rec;
-        I.rec_cap = 48 * I.n_markers + 1024;
+        I.rec_cap = 16 * I.n_markers + 1024;
         rec += I.rec_cap;
+        I.mk_blocks = (16 * I.n_markers + 255) / 256;
+        I.tile_blocks = std::max(1, std::min(I.act_cap, 2048));
+        L.mk_units += I.n_markers > 0 ? I.mk_blocks : 0;
+        L.sweep_units_max += (int)(((long long)q.nx * q.ny + 127) / 128);
         L.inst[j] = I;
     }
     L.lat_bytes = align_up(lat);
@@ -179,8 +185,10 @@ int build_layout(const ii_lbm_problem* p, int n_inst, Layout& L)
     L.off_f0 = take(nm * sizeof(int2));
     L.off_tile_count = take((size_t)tiles * sizeof(int));
     L.off_tile_list = take((size_t)tiles * kTileCap * sizeof(int));
-    L.off_tile_slot = take((size_t)tiles * sizeof(int));
-    L.off_corr = take((size_t)std::max(act, 1) * 8 * kTileNodes * sizeof(float));
+    for (int q = 0; q < 2; q++) {
+        L.off_tile_slot[q] = take((size_t)tiles * sizeof(int));
+        L.off_corr[q] = take((size_t)std::max(act, 1) * 8 * kTileNodes * sizeof(float));
+    }
     L.off_act_list[0] = take((size_t)std::max(act, 1) * sizeof(int2));
     L.off_act_list[1] = take((size_t)std::max(act, 1) * sizeof(int2));
     L.off_act_count = take((size_t)2 * n_inst * sizeof(int));
@@ -188,6 +196,14 @@ int build_layout(const ii_lbm_problem* p, int n_inst, Layout& L)
     L.off_rec_count = take((size_t)2 * n_inst * sizeof(int));
     L.off_err = take((size_t)n_inst * sizeof(int));
     L.off_diag = take((size_t)4 * kDiagBlocks * sizeof(double));
+    // batched launches: descriptors and work tables (tile table sized for the
+    // largest per-instance block count)
+    int tile_units = 0;
+    for (const InstDev& I : L.inst) tile_units += I.n_markers > 0 ? I.act_cap : 0;
+    L.off_insts = take((size_t)n_inst * sizeof(InstDev));
+    L.off_mk_table = take((size_t)std::max(L.mk_units, 1) * sizeof(int2));
+    L.off_tile_table = take((size_t)std::max(tile_units, 1) * sizeof(int2));
+    L.off_sweep_table = take((size_t)std::max(L.sweep_units_max, 1) * sizeof(int2));
     L.total = o;
     return II_LBM_OK;
 }
@@ -210,6 +226,21 @@ struct ii_lbm_handle {
     int ev_used = 0;
     double timed_ms = 0.0;
     int64_t timed_launches = 0;
+    // batched mode (several instances): one launch per phase for all of them
+    bool batched = false;
+    Batch batch;
+    int sweep_order = 0;           // 0: instance order, 1: largest instances first
+    double tuned_us = 0.0;
+    // hipGraph replay of two steps (one graph per starting parity)
+    bool use_graph = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    // Membranes: the interface work of step m+1 runs on `aux` while the
+    // sweep of step m runs on the main stream (fork/join through events).
+    bool lookahead = false;
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    bool rec_valid = false;  // rigid bodies: a step has built cut-link records
 };
 
 static int hip_fail(ii_lbm_handle* h, hipError_t e)
@@ -242,6 +273,194 @@ static int sync_and_check(ii_lbm_handle* h)
     if (e != hipSuccess) return hip_fail(h, e);
     if (h->failed) return h->failed;
     return check_device_errors(h);
+}
+
+// Tiles within 2.5 lu of the initial chords: the tile kernel's blocks per
+// instance (they stride over whatever the active count turns out to be).
+static int estimate_active_tiles(const ii_lbm_problem& p, const double* X0)
+{
+    const int N = p.n_markers, tx = (p.nx + kTile - 1) / kTile, ty = (p.ny + kTile - 1) / kTile;
+    std::vector<unsigned char> hit((size_t)tx * ty, 0);
+    int n = 0;
+    for (int k = 0; k < N; k++) {
+        const int kp = (k + 1) % N;
+        const double x0 = std::min(X0[2 * k], X0[2 * kp]) - 2.5, x1 = std::max(X0[2 * k], X0[2 * kp]) + 2.5;
+        const double y0 = std::min(X0[2 * k + 1], X0[2 * kp + 1]) - 2.5,
+                     y1 = std::max(X0[2 * k + 1], X0[2 * kp + 1]) + 2.5;
+        for (int b = std::max(0, (int)floor(y0 / kTile)); b <= std::min(ty - 1, (int)floor(y1 / kTile)); b++)
+            for (int a = std::max(0, (int)floor(x0 / kTile)); a <= std::min(tx - 1, (int)floor(x1 / kTile)); a++)
+                if (!hit[(size_t)b * tx + a]) { hit[(size_t)b * tx + a] = 1; n++; }
+    }
+    return n;
+}
+
+// Sweep work table: slices of `unit` nodes, instances in the given order.
+static std::vector<int2> sweep_table(const Layout& L, int unit, int order)
+{
+    std::vector<int> idx(L.inst.size());
+    for (size_t j = 0; j < idx.size(); j++) idx[j] = (int)j;
+    if (order == 1)
+        std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+            return (long long)L.inst[a].nx * L.inst[a].ny > (long long)L.inst[b].nx * L.inst[b].ny;
+        });
+    std::vector<int2> t;
+    for (int j : idx) {
+        const long long n = (long long)L.inst[j].nx * L.inst[j].ny;
+        for (long long r = 0; r < n; r += unit) t.push_back(make_int2(j, (int)r));
+    }
+    return t;
+}
+
+static hipError_t upload_sweep_table(ii_lbm_handle* h, int unit, int order)
+{
+    const std::vector<int2> t = sweep_table(h->L, unit, order);
+    hipError_t e = hipMemcpy((void*)h->batch.sweep_table, t.data(), t.size() * sizeof(int2),
+                             hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        h->batch.sweep_units = (int)t.size();
+        h->batch.sweep_unit = unit;
+        h->sweep_order = order;
+    }
+    return e;
+}
+
+// Interface phases of one step on stream s: slot/count reset of plane `par`,
+// the marker pass (`mode`), then the tile pass.
+static hipError_t enqueue_interface(ii_lbm_handle* h, int par, int mode, hipStream_t s)
+{
+    void* A = h->P.lat[par];
+    hipError_t e = hipSuccess;
+    if (h->batched) {
+        e = launch_slot_reset_batch(h->batch, (int)h->L.inst.size(), h->P, par, s);
+        if (e == hipSuccess) e = launch_markers_batch(h->batch, h->P, A, par, mode, s);
+        if (e == hipSuccess) e = launch_tiles_batch(h->batch, h->P, par, h->records, s);
+        return e;
+    }
+    for (size_t j = 0; j < h->L.inst.size() && e == hipSuccess; j++) {
+        const InstDev& I = h->L.inst[j];
+        if (I.n_markers == 0) continue;
+        e = launch_slot_reset(I, h->P, par, s);
+        if (e == hipSuccess) e = launch_markers(I, h->P, A, par, mode, s);
+        if (e == hipSuccess) e = launch_tiles(I, h->P, par, h->records, s);
+    }
+    return e;
+}
+
+static hipError_t enqueue_sweep(ii_lbm_handle* h, int par, hipStream_t s, bool timed)
+{
+    void* A = h->P.lat[par];
+    void* B = h->P.lat[par ^ 1];
+    hipError_t e = hipSuccess;
+    if (h->batched) {
+        if (timed) (void)hipEventRecord(h->ev[h->ev_used], s);
+        e = launch_sweep_batch(h->batch, h->P, A, B, par, s);
+        if (timed) {
+            (void)hipEventRecord(h->ev[h->ev_used + 1], s);
+            h->ev_used += 2;
+        }
+        return e;
+    }
+    for (size_t j = 0; j < h->L.inst.size() && e == hipSuccess; j++) {
+        const bool t = timed && h->ev_used + 2 <= (int)h->ev.size();
+        if (t) (void)hipEventRecord(h->ev[h->ev_used], s);
+        e = launch_sweep(h->L.inst[j], h->P, A, B, par, s);
+        if (t) {
+            (void)hipEventRecord(h->ev[h->ev_used + 1], s);
+            h->ev_used += 2;
+        }
+    }
+    return e;
+}
+
+// Interpolation of step m on plane `par` from f^m, then the geometry and tile
+// pass of step m+1 at X^{m+1} on the other plane.
+static hipError_t enqueue_lookahead(ii_lbm_handle* h, int par, hipStream_t s)
+{
+    void* A = h->P.lat[par];
+    hipError_t e = h->batched ? launch_markers_batch(h->batch, h->P, A, par, kModeInterp, s)
+                              : hipSuccess;
+    for (size_t j = 0; !h->batched && j < h->L.inst.size() && e == hipSuccess; j++)
+        e = launch_markers(h->L.inst[j], h->P, A, par, kModeInterp, s);
+    if (e == hipSuccess) e = enqueue_interface(h, par ^ 1, kModeGeom, s);
+    return e;
+}
+
+// Enqueue one time step of every instance on stream s (no host work besides
+// launches and event operations, so it can be captured into a graph).
+//   membranes:    fork -> aux: interp(m), reset/geom/tiles(m+1);  s: sweep(m) -> join
+//   rigid bodies: reset/full markers/tiles(m) -> sweep(m), in order on s
+static hipError_t enqueue_step(ii_lbm_handle* h, int par, hipStream_t s, bool timed)
+{
+    hipError_t e = hipSuccess;
+    if (h->lookahead) {
+        e = hipEventRecord(h->ev_fork, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(h->aux, h->ev_fork, 0);
+        if (e == hipSuccess) e = enqueue_lookahead(h, par, h->aux);
+        if (e == hipSuccess) e = enqueue_sweep(h, par, s, timed);
+        if (e == hipSuccess) e = hipEventRecord(h->ev_join, h->aux);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, h->ev_join, 0);
+        return e;
+    }
+    e = enqueue_interface(h, par, kModeFull, s);
+    if (e == hipSuccess) e = enqueue_sweep(h, par, s, timed);
+    return e;
+}
+
+// Membranes: build the interface data of the current step from the current
+// markers (after init, set_markers or load_state).
+static hipError_t prime(ii_lbm_handle* h)
+{
+    if (!h->lookahead) return hipSuccess;
+    const hipError_t e = enqueue_interface(h, h->parity, kModeGeom, h->stream);
+    return e == hipSuccess ? hipStreamSynchronize(h->stream) : e;
+}
+
+static void drop_graphs(ii_lbm_handle* h)
+{
+    for (auto& g : h->gexec)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+}
+
+// Two steps starting at parity `par`, captured on the handle's own stream.
+static hipError_t build_graph(ii_lbm_handle* h, int par)
+{
+    if (!h->cap_stream) {
+        hipError_t e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t e1 = enqueue_step(h, par, h->cap_stream, false);
+    if (e1 == hipSuccess) e1 = enqueue_step(h, par ^ 1, h->cap_stream, false);
+    e = hipStreamEndCapture(h->cap_stream, &g);
+    if (e1 != hipSuccess) e = e1;
+    if (e == hipSuccess) e = hipGraphInstantiate(&h->gexec[par], g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    return e;
+}
+
+// Plane of the newest cut-link records: membranes hold those of the current
+// markers, rigid bodies those built by the last step (-1: none yet).
+static int record_parity(const ii_lbm_handle* h)
+{
+    if (h->lookahead) return h->parity;
+    return h->rec_valid ? (h->parity ^ 1) : -1;
+}
+
+static void release(ii_lbm_handle* h)
+{
+    drop_graphs(h);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    if (h->aux) (void)hipStreamDestroy(h->aux);
+    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+    for (auto& ev : h->ev) (void)hipEventDestroy(ev);
+    if (h->owns_ws) (void)hipFree(h->ws);
+    delete h;
 }
 
 extern "C" {
@@ -307,8 +526,10 @@ int ii_lbm_init(const ii_lbm_problem* p, int32_t n_inst, const double* const* X0
     P.f0 = (int2*)(h->ws + L.off_f0);
     P.tile_count = (int*)(h->ws + L.off_tile_count);
     P.tile_list = (int*)(h->ws + L.off_tile_list);
-    P.tile_slot = (int*)(h->ws + L.off_tile_slot);
-    P.corr = (float*)(h->ws + L.off_corr);
+    for (int q = 0; q < 2; q++) {
+        P.tile_slot[q] = (int*)(h->ws + L.off_tile_slot[q]);
+        P.corr[q] = (float*)(h->ws + L.off_corr[q]);
+    }
     P.act_list[0] = (int2*)(h->ws + L.off_act_list[0]);
     P.act_list[1] = (int2*)(h->ws + L.off_act_list[1]);
     P.act_count = (int*)(h->ws + L.off_act_count);
@@ -323,7 +544,8 @@ int ii_lbm_init(const ii_lbm_problem* p, int32_t n_inst, const double* const* X0
         if (e == hipSuccess) e = launch_fill_zero(L.inst[j], P.lat[1], h->stream);
     }
     if (e == hipSuccess) e = launch_fill_ints(P.tile_count, L.tiles_total, 0, h->stream);
-    if (e == hipSuccess) e = launch_fill_ints(P.tile_slot, L.tiles_total, -1, h->stream);
+    for (int q = 0; q < 2 && e == hipSuccess; q++)
+        e = launch_fill_ints(P.tile_slot[q], L.tiles_total, -1, h->stream);
     if (e == hipSuccess) e = launch_fill_ints(P.act_count, 2 * n_inst, 0, h->stream);
     if (e == hipSuccess) e = launch_fill_ints(P.rec_count, 2 * n_inst, 0, h->stream);
     if (e == hipSuccess) e = launch_fill_ints(P.err, n_inst, 0, h->stream);
@@ -336,10 +558,72 @@ int ii_lbm_init(const ii_lbm_problem* p, int32_t n_inst, const double* const* X0
             e = hipMemcpyAsync(P.X[1] + I.mk_off, X0[j], (size_t)I.n_markers * sizeof(double2),
                                hipMemcpyHostToDevice, h->stream);
     }
+    // Several instances advance together through the batched launches; they
+    // share storage precision, collision arithmetic and interface kind.
+    if (e == hipSuccess && n_inst > 1) {
+        int iface = II_LBM_IF_NONE;
+        for (int j = 0; j < n_inst; j++) {
+            if (p[j].storage != p[0].storage || p[j].math != p[0].math) {
+                e = hipErrorInvalidValue;
+                break;
+            }
+            if (p[j].interface_kind != II_LBM_IF_NONE) {
+                if (iface != II_LBM_IF_NONE && iface != p[j].interface_kind) {
+                    e = hipErrorInvalidValue;
+                    break;
+                }
+                iface = p[j].interface_kind;
+            }
+        }
+        if (e != hipSuccess) {
+            if (h->owns_ws) (void)hipFree(h->ws);
+            delete h;
+            return II_LBM_EINVAL;
+        }
+        h->batched = true;
+        Batch& b = h->batch;
+        b.insts = (const InstDev*)(h->ws + L.off_insts);
+        b.mk_table = (const int2*)(h->ws + L.off_mk_table);
+        b.tile_table = (const int2*)(h->ws + L.off_tile_table);
+        b.sweep_table = (const int2*)(h->ws + L.off_sweep_table);
+        b.storage = p[0].storage;
+        b.math = p[0].math;
+        b.iface = iface;
+        std::vector<int2> mk, tl;
+        for (int j = 0; j < n_inst; j++) {
+            InstDev& I = h->L.inst[j];
+            if (I.n_markers == 0) continue;
+            const int est = estimate_active_tiles(p[j], X0[j]);
+            I.tile_blocks = std::max(1, std::min(I.act_cap, est + est / 4 + 1));
+            for (int q = 0; q < I.mk_blocks; q++) mk.push_back(make_int2(j, q));
+            for (int q = 0; q < I.tile_blocks; q++) tl.push_back(make_int2(j, q));
+        }
+        b.mk_units = (int)mk.size();
+        b.tile_units = (int)tl.size();
+        e = hipMemcpy((void*)b.insts, h->L.inst.data(), n_inst * sizeof(InstDev), hipMemcpyHostToDevice);
+        if (e == hipSuccess && !mk.empty())
+            e = hipMemcpy((void*)b.mk_table, mk.data(), mk.size() * sizeof(int2), hipMemcpyHostToDevice);
+        if (e == hipSuccess && !tl.empty())
+            e = hipMemcpy((void*)b.tile_table, tl.data(), tl.size() * sizeof(int2), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = upload_sweep_table(h, 256, 1);
+    }
+    // membranes (no direct forcing) take the overlapped schedule
+    bool any = false, all_membrane = true;
+    for (int j = 0; j < n_inst; j++)
+        if (p[j].interface_kind != II_LBM_IF_NONE) {
+            any = true;
+            all_membrane = all_membrane && p[j].interface_kind == II_LBM_IF_MEMBRANE;
+        }
+    h->lookahead = any && all_membrane;
+    if (e == hipSuccess && h->lookahead) {
+        e = hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) e = prime(h);
     if (e != hipSuccess) {
-        if (h->owns_ws) hipFree(h->ws);
-        delete h;
+        release(h);
         return II_LBM_EDEVICE;
     }
     *out = h;
@@ -350,31 +634,88 @@ int ii_lbm_step(ii_lbm_handle* h, int64_t n_steps)
 {
     if (!h || n_steps < 0) return II_LBM_EINVAL;
     if (h->failed) return II_LBM_ESTATE;
-    const int n_inst = (int)h->prob.size();
-    for (int64_t s = 0; s < n_steps; s++) {
-        const int par = h->parity;
-        void* A = h->P.lat[par];
-        void* B = h->P.lat[par ^ 1];
-        for (int j = 0; j < n_inst; j++) {
-            const InstDev& I = h->L.inst[j];
-            hipError_t e = hipSuccess;
-            if (I.n_markers > 0) {
-                e = launch_markers(I, h->P, A, par, h->stream);
-                if (e == hipSuccess) e = launch_tiles(I, h->P, par, h->records, h->stream);
+    int64_t left = n_steps;
+    if (h->use_graph && !h->timing) {
+        while (left >= 2) {
+            const int par = h->parity;
+            if (!h->gexec[par]) {
+                const hipError_t e = build_graph(h, par);
+                if (e != hipSuccess) return hip_fail(h, e);
             }
+            const hipError_t e = hipGraphLaunch(h->gexec[par], h->stream);
             if (e != hipSuccess) return hip_fail(h, e);
-            const bool timed = h->timing && h->ev_used + 2 <= (int)h->ev.size();
-            if (timed) hipEventRecord(h->ev[h->ev_used], h->stream);
-            e = launch_sweep(I, h->P, A, B, h->stream);
-            if (e != hipSuccess) return hip_fail(h, e);
-            if (timed) {
-                hipEventRecord(h->ev[h->ev_used + 1], h->stream);
-                h->ev_used += 2;
-            }
+            h->steps += 2;   // two parity flips leave the parity unchanged
+            left -= 2;
         }
+    }
+    for (; left > 0; left--) {
+        const bool timed = h->timing && h->ev_used + 2 <= (int)h->ev.size();
+        const hipError_t e = enqueue_step(h, h->parity, h->stream, timed);
+        if (e != hipSuccess) return hip_fail(h, e);
         h->parity ^= 1;
         h->steps++;
     }
+    if (n_steps > 0) h->rec_valid = true;
+    return II_LBM_OK;
+}
+
+int ii_lbm_set_graph(ii_lbm_handle* h, int32_t enable)
+{
+    if (!h) return II_LBM_EINVAL;
+    h->use_graph = enable != 0;
+    if (!h->use_graph) drop_graphs(h);
+    return II_LBM_OK;
+}
+
+int ii_lbm_autotune(ii_lbm_handle* h, int32_t trials, int32_t* unit, int32_t* order, double* best_us)
+{
+    if (!h || trials < 1) return II_LBM_EINVAL;
+    if (h->failed) return II_LBM_ESTATE;
+    if (!h->batched) {
+        if (unit) *unit = 0;
+        if (order) *order = 0;
+        if (best_us) *best_us = 0.0;
+        return II_LBM_OK;
+    }
+    // The sweep is a pure function of the current lattice: time each
+    // candidate on it writing the other buffer, which the next step rewrites.
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return hip_fail(h, hipErrorUnknown);
+    const int units[3] = {128, 256, 512};
+    double best = 1e300;
+    int bu = 256, bo = 1;
+    hipError_t e = hipSuccess;
+    for (int o = 0; o < 2 && e == hipSuccess; o++)
+        for (int ui = 0; ui < 3 && e == hipSuccess; ui++) {
+            e = upload_sweep_table(h, units[ui], o);
+            void* A = h->P.lat[h->parity];
+            void* B = h->P.lat[h->parity ^ 1];
+            const int par = h->parity;
+            if (e == hipSuccess) e = launch_sweep_batch(h->batch, h->P, A, B, par, h->stream);
+            if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+            for (int t = 0; t < trials && e == hipSuccess; t++)
+                e = launch_sweep_batch(h->batch, h->P, A, B, par, h->stream);
+            if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            const double us = 1e3 * ms / trials;
+            if (e == hipSuccess && us < best) {
+                best = us;
+                bu = units[ui];
+                bo = o;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e == hipSuccess) e = upload_sweep_table(h, bu, bo);
+    if (e != hipSuccess) return hip_fail(h, e);
+    drop_graphs(h);
+    h->tuned_us = best;
+    if (unit) *unit = bu;
+    if (order) *order = bo;
+    if (best_us) *best_us = best;
     return II_LBM_OK;
 }
 
@@ -402,11 +743,12 @@ int ii_lbm_set_markers(ii_lbm_handle* h, int32_t inst, const double* X)
     const InstDev& I = h->L.inst[inst];
     const int rc = validate(h->prob[inst], X);
     if (rc) return rc;
-    const hipError_t e = hipMemcpyAsync(h->P.X[h->parity] + I.mk_off, X,
-                                        (size_t)I.n_markers * sizeof(double2),
-                                        hipMemcpyHostToDevice, h->stream);
-    if (e != hipSuccess) return hip_fail(h, e);
-    return hip_fail(h, hipStreamSynchronize(h->stream));
+    hipError_t e = hipMemcpyAsync(h->P.X[h->parity] + I.mk_off, X,
+                                  (size_t)I.n_markers * sizeof(double2), hipMemcpyHostToDevice,
+                                  h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) e = prime(h);
+    return hip_fail(h, e);
 }
 
 int ii_lbm_fields(ii_lbm_handle* h, int32_t inst, uint32_t what, void* out, int32_t dtype,
@@ -430,7 +772,7 @@ int ii_lbm_fields(ii_lbm_handle* h, int32_t inst, uint32_t what, void* out, int3
     if (e == hipSuccess && !on_device)
         e = hipMemcpyAsync(out, dst, bytes, hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    if (!on_device) hipFree(dst);
+    if (!on_device) (void)hipFree(dst);
     return hip_fail(h, e);
 }
 
@@ -445,7 +787,7 @@ int ii_lbm_set_distrib(ii_lbm_handle* h, int32_t inst, const double* f)
     hipError_t e = hipMemcpyAsync(d, f, bytes, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = launch_set_distrib(I, d, h->P.lat[h->parity], h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    hipFree(d);
+    (void)hipFree(d);
     return hip_fail(h, e);
 }
 
@@ -502,6 +844,8 @@ int ii_lbm_load_state(ii_lbm_handle* h, int32_t inst, const void* host_buf, size
     if (e == hipSuccess)
         e = hipMemcpy((char*)h->P.lat[h->parity] + I.lat_off * eb, b, (size_t)9 * I.plane * eb,
                       hipMemcpyHostToDevice);
+    h->rec_valid = false;
+    if (e == hipSuccess) e = prime(h);
     return hip_fail(h, e);
 }
 
@@ -511,12 +855,11 @@ int ii_lbm_cutlinks(ii_lbm_handle* h, int32_t inst, ii_lbm_link* out, int32_t ca
     const int rc = sync_and_check(h);
     if (rc) return rc;
     const InstDev& I = h->L.inst[inst];
-    // records of the last step live under the parity that step used
-    const int par = h->parity ^ 1;
     int n = 0;
-    hipError_t e = hipMemcpy(&n, h->P.rec_count + 2 * inst + par, sizeof(int), hipMemcpyDeviceToHost);
+    hipError_t e = hipSuccess;
+    const int par = record_parity(h);
+    if (par >= 0) e = hipMemcpy(&n, h->P.rec_count + 2 * inst + par, sizeof(int), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(h, e);
-    if (h->steps == 0) n = 0;
     *count = n;
     const int m = std::min(std::min(n, I.rec_cap), (int)cap);
     if (m > 0 && out)
@@ -531,7 +874,7 @@ int ii_lbm_diag(ii_lbm_handle* h, int32_t inst, ii_lbm_diag_t* out)
     int rc = sync_and_check(h);
     const InstDev& I = h->L.inst[inst];
     int errbits = 0;
-    hipMemcpy(&errbits, h->P.err + inst, sizeof(int), hipMemcpyDeviceToHost);
+    (void)hipMemcpy(&errbits, h->P.err + inst, sizeof(int), hipMemcpyDeviceToHost);
     out->error_bits = errbits;
     out->step = h->steps;
     if (rc && rc != II_LBM_EUNSTABLE) return rc;
@@ -567,11 +910,13 @@ int ii_lbm_diag(ii_lbm_handle* h, int32_t inst, ii_lbm_diag_t* out)
             fy -= G[k].y * I.dX;
         }
         out->area = 0.5 * a;
-        out->force[0] = h->steps > 0 ? fx : 0.0;
-        out->force[1] = h->steps > 0 ? fy : 0.0;
+        const bool have_g = h->lookahead || h->rec_valid;
+        out->force[0] = have_g ? fx : 0.0;
+        out->force[1] = have_g ? fy : 0.0;
         int n = 0;
-        if (h->steps > 0)
-            hipMemcpy(&n, h->P.rec_count + 2 * inst + (h->parity ^ 1), sizeof(int), hipMemcpyDeviceToHost);
+        const int par = record_parity(h);
+        if (par >= 0)
+            (void)hipMemcpy(&n, h->P.rec_count + 2 * inst + par, sizeof(int), hipMemcpyDeviceToHost);
         out->n_cut_links = n;
     }
     return h->failed;
@@ -608,19 +953,23 @@ int ii_lbm_get_timing(ii_lbm_handle* h, double* sweep_ms, int64_t* launches)
 
 int ii_lbm_sweep_bytes(ii_lbm_handle* h, int32_t inst, double* bytes)
 {
-    if (!h || !bytes || inst < 0 || inst >= (int)h->prob.size()) return II_LBM_EINVAL;
-    const InstDev& I = h->L.inst[inst];
-    *bytes = 18.0 * storage_bytes(I.storage) * (double)I.nx * (double)I.ny;
+    if (!h || !bytes || inst < -1 || inst >= (int)h->prob.size()) return II_LBM_EINVAL;
+    double b = 0.0;
+    for (int j = 0; j < (int)h->prob.size(); j++) {
+        if (inst >= 0 && j != inst) continue;
+        const InstDev& I = h->L.inst[j];
+        b += 18.0 * storage_bytes(I.storage) * (double)I.nx * (double)I.ny;
+    }
+    *bytes = b;
     return II_LBM_OK;
 }
 
 int ii_lbm_destroy(ii_lbm_handle* h)
 {
     if (!h) return II_LBM_EINVAL;
-    hipStreamSynchronize(h->stream);
-    for (auto& ev : h->ev) hipEventDestroy(ev);
-    if (h->owns_ws) hipFree(h->ws);
-    delete h;
+    (void)hipStreamSynchronize(h->stream);
+    if (h->aux) (void)hipStreamSynchronize(h->aux);
+    release(h);
     return II_LBM_OK;
 }
 

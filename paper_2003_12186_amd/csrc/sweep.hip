@@ -11,15 +11,12 @@ namespace iilbm {
 // interface corrections (tangential force term and jumps of the links this
 // node sends, prepared per 16x16 tile by the interface kernel) and store the
 // result at (x, y): every stored value is rounded exactly once.
-template <typename T, typename M, int COLL, bool BOUNDED, int BX>
-__global__ __launch_bounds__(BX) void k_sweep(InstDev I, const T* __restrict__ A,
-                                              T* __restrict__ B, int bx_count,
-                                              const int* __restrict__ tile_slot,
-                                              const float* __restrict__ corr)
+template <typename T, typename M, int COLL, bool BOUNDED>
+__device__ __forceinline__ void sweep_node(const InstDev& I, const T* __restrict__ A,
+                                           T* __restrict__ B, int x, int y,
+                                           const int* __restrict__ tile_slot,
+                                           const float* __restrict__ corr)
 {
-    const int bx = blockIdx.x % bx_count, y = blockIdx.x / bx_count;
-    const int x = bx * BX + threadIdx.x;
-    if (x >= I.nx) return;
     M d[9];
     if (BOUNDED && is_edge(I, x, y))
         nee<T, M>(I, A, x, y, d);
@@ -43,48 +40,119 @@ __global__ __launch_bounds__(BX) void k_sweep(InstDev I, const T* __restrict__ A
 }
 
 template <typename T, typename M, int COLL, bool BOUNDED, int BX>
+__global__ __launch_bounds__(BX) void k_sweep(InstDev I, const T* __restrict__ A,
+                                              T* __restrict__ B, int bx_count,
+                                              const int* __restrict__ tile_slot,
+                                              const float* __restrict__ corr)
+{
+    const int bx = blockIdx.x % bx_count, y = blockIdx.x / bx_count;
+    const int x = bx * BX + threadIdx.x;
+    if (x >= I.nx) return;
+    sweep_node<T, M, COLL, BOUNDED>(I, A, B, x, y, tile_slot, corr);
+}
+
+// Batched: block b sweeps `UNIT` consecutive nodes (row-major) of one
+// instance, from the work table; collision and boundary kind per instance.
+template <typename T, typename M, int UNIT>
+__global__ __launch_bounds__(UNIT) void k_sweep_batch(const InstDev* __restrict__ insts,
+                                                      const int2* __restrict__ units,
+                                                      const T* __restrict__ A, T* __restrict__ B,
+                                                      const int* __restrict__ tile_slot,
+                                                      const float* __restrict__ corr)
+{
+    const int2 u = units[blockIdx.x];
+    const InstDev I = insts[u.x];
+    const int r = u.y + threadIdx.x;
+    if (r >= I.nx * I.ny) return;
+    const int y = r / I.nx, x = r - y * I.nx;
+    if (I.collision == II_LBM_SRT) {
+        if (I.bounded)
+            sweep_node<T, M, II_LBM_SRT, true>(I, A, B, x, y, tile_slot, corr);
+        else
+            sweep_node<T, M, II_LBM_SRT, false>(I, A, B, x, y, tile_slot, corr);
+    } else {
+        if (I.bounded)
+            sweep_node<T, M, II_LBM_MRT, true>(I, A, B, x, y, tile_slot, corr);
+        else
+            sweep_node<T, M, II_LBM_MRT, false>(I, A, B, x, y, tile_slot, corr);
+    }
+}
+
+template <typename T, typename M>
+static hipError_t sweep_batch_m(const Batch& b, const DevPtrs& P, const void* A, void* B, int par,
+                                hipStream_t s)
+{
+    const dim3 g(b.sweep_units);
+    switch (b.sweep_unit) {
+    case 128:
+        hipLaunchKernelGGL((k_sweep_batch<T, M, 128>), g, dim3(128), 0, s, b.insts, b.sweep_table,
+                           (const T*)A, (T*)B, P.tile_slot[par], P.corr[par]);
+        break;
+    case 512:
+        hipLaunchKernelGGL((k_sweep_batch<T, M, 512>), g, dim3(512), 0, s, b.insts, b.sweep_table,
+                           (const T*)A, (T*)B, P.tile_slot[par], P.corr[par]);
+        break;
+    default:
+        hipLaunchKernelGGL((k_sweep_batch<T, M, 256>), g, dim3(256), 0, s, b.insts, b.sweep_table,
+                           (const T*)A, (T*)B, P.tile_slot[par], P.corr[par]);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_batch(const Batch& b, const DevPtrs& P, const void* A, void* B, int par,
+                              hipStream_t s)
+{
+    if (b.sweep_units == 0) return hipSuccess;
+    if (b.storage == II_LBM_FP16)
+        return b.math == II_LBM_MATH_FP64 ? sweep_batch_m<_Float16, double>(b, P, A, B, par, s)
+                                          : sweep_batch_m<_Float16, float>(b, P, A, B, par, s);
+    return b.math == II_LBM_MATH_FP64 ? sweep_batch_m<float, double>(b, P, A, B, par, s)
+                                      : sweep_batch_m<float, float>(b, P, A, B, par, s);
+}
+
+template <typename T, typename M, int COLL, bool BOUNDED, int BX>
 static hipError_t sweep_b(const InstDev& I, const DevPtrs& P, const void* A, void* B,
-                          hipStream_t s)
+                          int par, hipStream_t s)
 {
     const int bxn = (I.nx + BX - 1) / BX;
     hipLaunchKernelGGL((k_sweep<T, M, COLL, BOUNDED, BX>), dim3(bxn * I.ny), dim3(BX), 0, s, I,
-                       (const T*)A, (T*)B, bxn, P.tile_slot, P.corr);
+                       (const T*)A, (T*)B, bxn, P.tile_slot[par], P.corr[par]);
     return hipGetLastError();
 }
 
 template <typename T, typename M, int COLL, bool BOUNDED>
-static hipError_t sweep_t(const InstDev& I, const DevPtrs& P, const void* A, void* B,
+static hipError_t sweep_t(const InstDev& I, const DevPtrs& P, const void* A, void* B, int par,
                           hipStream_t s)
 {
-    if (I.nx % 512 == 0) return sweep_b<T, M, COLL, BOUNDED, 512>(I, P, A, B, s);
-    if (I.nx % 256 == 0) return sweep_b<T, M, COLL, BOUNDED, 256>(I, P, A, B, s);
-    return sweep_b<T, M, COLL, BOUNDED, 64>(I, P, A, B, s);
+    if (I.nx % 512 == 0) return sweep_b<T, M, COLL, BOUNDED, 512>(I, P, A, B, par, s);
+    if (I.nx % 256 == 0) return sweep_b<T, M, COLL, BOUNDED, 256>(I, P, A, B, par, s);
+    return sweep_b<T, M, COLL, BOUNDED, 64>(I, P, A, B, par, s);
 }
 
 template <typename T, typename M>
-static hipError_t sweep_m(const InstDev& I, const DevPtrs& P, const void* A, void* B,
+static hipError_t sweep_m(const InstDev& I, const DevPtrs& P, const void* A, void* B, int par,
                           hipStream_t s)
 {
     if (I.collision == II_LBM_SRT)
-        return I.bounded ? sweep_t<T, M, II_LBM_SRT, true>(I, P, A, B, s)
-                         : sweep_t<T, M, II_LBM_SRT, false>(I, P, A, B, s);
-    return I.bounded ? sweep_t<T, M, II_LBM_MRT, true>(I, P, A, B, s)
-                     : sweep_t<T, M, II_LBM_MRT, false>(I, P, A, B, s);
+        return I.bounded ? sweep_t<T, M, II_LBM_SRT, true>(I, P, A, B, par, s)
+                         : sweep_t<T, M, II_LBM_SRT, false>(I, P, A, B, par, s);
+    return I.bounded ? sweep_t<T, M, II_LBM_MRT, true>(I, P, A, B, par, s)
+                     : sweep_t<T, M, II_LBM_MRT, false>(I, P, A, B, par, s);
 }
 
 template <typename T>
-static hipError_t sweep_s(const InstDev& I, const DevPtrs& P, const void* A, void* B,
+static hipError_t sweep_s(const InstDev& I, const DevPtrs& P, const void* A, void* B, int par,
                           hipStream_t s)
 {
-    return I.math == II_LBM_MATH_FP64 ? sweep_m<T, double>(I, P, A, B, s)
-                                      : sweep_m<T, float>(I, P, A, B, s);
+    return I.math == II_LBM_MATH_FP64 ? sweep_m<T, double>(I, P, A, B, par, s)
+                                      : sweep_m<T, float>(I, P, A, B, par, s);
 }
 
-hipError_t launch_sweep(const InstDev& I, const DevPtrs& P, const void* A, void* B,
+hipError_t launch_sweep(const InstDev& I, const DevPtrs& P, const void* A, void* B, int par,
                         hipStream_t s)
 {
-    return I.storage == II_LBM_FP16 ? sweep_s<_Float16>(I, P, A, B, s)
-                                    : sweep_s<float>(I, P, A, B, s);
+    return I.storage == II_LBM_FP16 ? sweep_s<_Float16>(I, P, A, B, par, s)
+                                    : sweep_s<float>(I, P, A, B, par, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -105,8 +105,7 @@ def test_membrane64_cutlinks_bitexact(B, steps):
     sim = B.Sim([w.problem], [w.X0])
     sim.step(steps)
     Xn, _, _ = sim.markers()
-    sim.step(1)                   # builds the links of the interface at X^n
-    got = sim.cutlinks()
+    got = sim.cutlinks()          # the links of the interface at the current markers
     p = O.make_problem(w.problem)
     jp = O.marker_forces(p, Xn)["jp"]
     want = O.cutlinks(p, Xn, jp)
@@ -141,6 +140,24 @@ def test_cylinder_channel_small_parity(B, re):
     _say(f"  rel L2 u = {err:.3e}  force rel err = {ferr:.3e}  F_last = {fg[-1]} vs {fo[-1]}")
     assert err <= 1e-6
     assert ferr <= 1e-5
+    sim.close()
+
+
+def test_set_markers_then_run_matches_oracle(B):
+    # Replacing the markers rebuilds the interface data of the current step.
+    _say("membrane 64x64: set_markers (shifted, rescaled curve) then 200 steps")
+    w = W.membrane_c1()
+    w.problem.math = W.MATH_FP64
+    X1 = np.ascontiguousarray(32.0 + 1.05 * (w.X0 - 32.0) + np.array([0.37, -0.21]))
+    sim = B.Sim([w.problem], [w.X0])
+    sim.set_markers(X1)
+    sim.step(200)
+    g = sim.fields(B.F_UX | B.F_UY)
+    o = _oracle_run(w.problem, X1, 200)
+    err = _rel_l2(g[0], g[1], o["ux"], o["uy"])
+    dX = np.abs(sim.markers()[0] - o["X"]).max()
+    _say(f"  rel L2 u = {err:.3e}  max |dX| = {dX:.3e}")
+    assert err <= 1e-6 and dX <= 1e-6     # as for the 1000-step membrane run
     sim.close()
 
 
