@@ -78,7 +78,7 @@ def bench_batch(args, B, W) -> int:
     sim = B.Sim([w.problem for w in ws], [w.X0 for w in ws], device="cuda:0")
     sim.step(2)
     tune = sim.autotune(5)
-    sim.set_graph(True)
+    sim.set_graph(args.graph == "on")
     sim.step(args.warmup)
     sim.sync()
     torch.cuda.synchronize()
@@ -106,7 +106,7 @@ def bench_batch(args, B, W) -> int:
         "dtype": f"{args.storage} storage / {args.math} collision", "data": "synthetic",
         "config": {"workload": f"membrane_batch{len(ws)}", "instances": len(ws), "nodes": nodes,
                    "markers": sum(w.problem.n_markers for w in ws), "autotune": tune,
-                   "graph": True},
+                   "graph": args.graph == "on"},
         "roofline": {"bound": "hbm", "kernel": "k_sweep_batch", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None, "bytes_per_launch": bytes_per_launch,
@@ -130,6 +130,8 @@ def main() -> int:
                     help="membrane: one L x L membrane (the bench line); batch512: 512 uneven "
                          "membrane instances advanced together (reported in the design notes)")
     ap.add_argument("--instances", type=int, default=512)
+    ap.add_argument("--graph", choices=["on", "off"], default="on",
+                    help="batch512: replay steps as HIP graphs or launch directly")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",

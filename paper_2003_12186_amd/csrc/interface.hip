@@ -365,40 +365,64 @@ __device__ __forceinline__ bool link_crossing(int x, int y, int i, const Chord& 
     return true;
 }
 
+// Cut point of the link from node (x, y) along e_i on the rigid circle
+// |x - c| = R (the root of |P + q e_i - c|^2 = R^2 inside the link), and the
+// marker interval that brackets it by angle: [[p]] there is linear in the
+// angle between markers k and k+1.
+__device__ __forceinline__ void rigid_cut(const InstDev& I, int x, int y, int i, bool inP,
+                                          double& q, double& th, int& k)
+{
+    const int N = I.n_markers;
+    const double R2 = I.radius * I.radius;
+    const double dx = (double)x - I.cx, dy = (double)y - I.cy;
+    const double ee = (double)(EX[i] * EX[i] + EY[i] * EY[i]);
+    const double de = dx * EX[i] + dy * EY[i];
+    const double dd = dx * dx + dy * dy - R2;
+    const double disc = sqrt(de * de - ee * dd);
+    q = inP ? (-de + disc) / ee : (-de - disc) / ee;
+    const double cxp = (double)x + q * EX[i] - I.cx, cyp = (double)y + q * EY[i] - I.cy;
+    double ang = atan2(cyp, cxp);
+    if (ang < 0.0) ang += 2.0 * M_PI;
+    const double sN = ang * N / (2.0 * M_PI);
+    k = (sN >= 0.0 && sN < (double)N) ? (int)floor(sN) : 0;
+    th = sN - k;
+}
+
 // ---------------------------------------------------------------------------
 // Tiles.
 // ---------------------------------------------------------------------------
-constexpr int kTileRec = 256;  // records staged per tile before one global write
+constexpr int kTileRec = 1024;  // cut links recorded per tile (packed in LDS, then written)
 
+// LDS of one tile block, about 27 KB so that five blocks share a CU.
 struct TileShared {
-    int raw[kTileCap];
-    int key[kTileCap];
+    union {
+        int raw[kTileCap];       // chord ids as binned
+        int start[kTileCap];     // first flattened candidate of each sorted chord
+    };
+    int key[kTileCap];           // chord ids in increasing order
     Chord ch[kTileCap];
-    int box[kTileCap][4];        // candidate source nodes of the chord's links
+    short box[kTileCap][4];      // candidate source nodes of the chord's links
     double jpa[kTileCap], jpb[kTileCap];
-    double wx[kTileCap][4], wy[kTileCap][4];
+    float wx[kTileCap][4], wy[kTileCap][4];
     int2 f0[kTileCap];
     double gtx[kTileCap], gty[kTileCap];
-    double acc[8][kTileNodes];   // jump sums of the eight outgoing populations per node
-    ii_lbm_link rec[kTileRec];
-    int cnt, nrec, base;
+    float acc[8][kTileNodes];    // jump sums of the eight outgoing populations per node
+    unsigned rec[kTileRec];      // packed (node, direction, chord) of each cut link
+    int cnt, total, nrec, base;
 };
 
-// Jump of one cut link into the node's accumulator, and its record.
-__device__ __forceinline__ void add_crossing(TileShared& S, const InstDev& I, int lx, int ly,
-                                             int x, int y, int i, int sigma, int seg, double q,
-                                             double theta, double jpc, bool records)
+// [[f_i]] of one cut link into the node's accumulator: sigma w_i [[p]] / c_s^2
+// (Sec. 3.1, Eq. (32); Sec. 3.2, Eq. (47)).  A link cut by two chords gets two
+// terms, whose sum does not depend on their order.
+__device__ __forceinline__ void add_jump(TileShared& S, int node, int i, int sigma, double jpc)
 {
-    // sigma [[f_i]] = sigma w_i [[p]] / c_s^2 (Sec. 3.1, Eq. (32); Sec. 3.2, Eq. (47));
-    // a link cut by two chords gets two terms, whose sum is order-free
-    atomicAdd(&S.acc[i - 1][ly * kTile + lx], (double)sigma * WD[i] * jpc / kCs2);
-    if (!records) return;
+    atomicAdd(&S.acc[i - 1][node], (float)((double)sigma * WD[i] * jpc / kCs2));
+}
+
+__device__ __forceinline__ void stage_record(TileShared& S, int node, int i, int j)
+{
     const int r = atomicAdd(&S.nrec, 1);
-    if (r < kTileRec) {
-        ii_lbm_link& L = S.rec[r];
-        L.x = x; L.y = y; L.dir = i; L.sigma = sigma; L.seg = seg; L.inst = I.inst;
-        L.q = q; L.theta = theta; L.jp = jpc;
-    }
+    if (r < kTileRec) S.rec[r] = (unsigned)node | ((unsigned)(i - 1) << 8) | ((unsigned)j << 11);
 }
 
 template <int IFACE>
@@ -415,76 +439,102 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
         const int gt = I.tile_off + t;
         const int tx = t % I.tiles_x, ty = t / I.tiles_x;
         const int x0 = tx * kTile, y0 = ty * kTile;
+        // the list is read whole (its slots beyond the count are stale but
+        // allocated) while thread 0 reads the count
+        if (tid < kTileCap) S.raw[tid] = P.tile_list[(long long)gt * kTileCap + tid];
         if (tid == 0) {
             S.cnt = min(P.tile_count[gt], kTileCap);
             S.nrec = 0;
         }
 #pragma unroll
-        for (int i = 0; i < 8; i++) S.acc[i][tid] = 0.0;
+        for (int i = 0; i < 8; i++) S.acc[i][tid] = 0.f;
         __syncthreads();
         const int c = S.cnt;
-        if (tid < c) S.raw[tid] = P.tile_list[(long long)gt * kTileCap + tid];
-        __syncthreads();
         if (tid == 0) {
             P.tile_count[gt] = 0;  // ready for the next step
             P.tile_slot[parity][gt] = I.act_off + a;
         }
-        // deterministic order: rank sort of the (distinct) chord ids
+        // deterministic order: chord k goes to its rank among the (distinct) ids
+        int k = 0, r = 0;
         if (tid < c) {
-            const int key = S.raw[tid];
-            int r = 0;
-            for (int m = 0; m < c; m++) r += (S.raw[m] < key) ? 1 : 0;
-            S.key[r] = key;
+            k = S.raw[tid];
+            for (int m = 0; m < c; m++) r += (S.raw[m] < k) ? 1 : 0;
         }
-        __syncthreads();
+        __syncthreads();   // raw is reused as start below
         if (tid < c) {
-            const int k = S.key[tid], kp = (k + 1) % N;
+            S.key[r] = k;
+            const int kp = (k + 1) % N;
             const double2 a0 = X[k], b0 = X[kp];
             const long long ax = (long long)rint(a0.x * kSnap), ay = (long long)rint(a0.y * kSnap);
             const long long bx = (long long)rint(b0.x * kSnap), by = (long long)rint(b0.y * kSnap);
-            S.ch[tid].ax = ax; S.ch[tid].ay = ay; S.ch[tid].bx = bx; S.ch[tid].by = by;
+            S.ch[r].ax = ax; S.ch[r].ay = ay; S.ch[r].bx = bx; S.ch[r].by = by;
             // any link the chord cuts leaves a node within one spacing of the
             // chord's box; keep the part of that box inside this tile
-            S.box[tid][0] = max((int)(min(ax, bx) >> 16) - 1, x0);
-            S.box[tid][1] = min((int)(-((-max(ax, bx)) >> 16)) + 1, min(x0 + kTile, I.nx) - 1);
-            S.box[tid][2] = max((int)(min(ay, by) >> 16) - 1, y0);
-            S.box[tid][3] = min((int)(-((-max(ay, by)) >> 16)) + 1, min(y0 + kTile, I.ny) - 1);
-            S.jpa[tid] = P.jp[I.mk_off + k];
-            S.jpb[tid] = P.jp[I.mk_off + kp];
+            const int bx0 = max((int)(min(ax, bx) >> 16) - 1, x0);
+            const int bx1 = min((int)(-((-max(ax, bx)) >> 16)) + 1, min(x0 + kTile, I.nx) - 1);
+            const int by0 = max((int)(min(ay, by) >> 16) - 1, y0);
+            const int by1 = min((int)(-((-max(ay, by)) >> 16)) + 1, min(y0 + kTile, I.ny) - 1);
+            S.box[r][0] = (short)bx0; S.box[r][1] = (short)bx1;
+            S.box[r][2] = (short)by0; S.box[r][3] = (short)by1;
+            S.start[r] = (IFACE == II_LBM_IF_MEMBRANE && bx0 <= bx1 && by0 <= by1)
+                             ? (bx1 - bx0 + 1) * (by1 - by0 + 1) : 0;
+            S.jpa[r] = P.jp[I.mk_off + k];
+            S.jpb[r] = P.jp[I.mk_off + kp];
             const int mk = I.mk_off + k;
-            S.f0[tid] = P.f0[mk];
+            S.f0[r] = P.f0[mk];
 #pragma unroll
             for (int q = 0; q < 4; q++) {
-                S.wx[tid][q] = P.wx[4 * mk + q];
-                S.wy[tid][q] = P.wy[4 * mk + q];
+                S.wx[r][q] = (float)P.wx[4 * mk + q];
+                S.wy[r][q] = (float)P.wy[4 * mk + q];
             }
-            const double2 g = P.Gt[I.mk_off + k];
-            S.gtx[tid] = g.x; S.gty[tid] = g.y;
+            const double2 g = P.Gt[mk];
+            S.gtx[r] = g.x; S.gty[r] = g.y;
         }
         __syncthreads();
 
-        // Cut links.  Membrane: chord by chord, each wave takes whole chords
-        // and its lanes the candidate (node, direction) pairs of the chord.
+        // Cut links of a membrane.  The (chord, source node) candidates of all
+        // chords are numbered consecutively and every thread of the block takes
+        // every 256th; a thread finds the side of its node once and then tests
+        // the eight links the node sends.
         if (IFACE == II_LBM_IF_MEMBRANE) {
-            for (int j = wid; j < c; j += 4) {
-                const int bx0 = S.box[j][0], bx1 = S.box[j][1], by0 = S.box[j][2], by1 = S.box[j][3];
-                if (bx0 > bx1 || by0 > by1) continue;
-                const int w = bx1 - bx0 + 1;
-                const int ncand = 8 * w * (by1 - by0 + 1);
+            if (wid == 0) {
+                // exclusive scan of the candidate counts, two chords per lane
+                const int v0 = 2 * lane < c ? S.start[2 * lane] : 0;
+                const int v1 = 2 * lane + 1 < c ? S.start[2 * lane + 1] : 0;
+                int sc = v0 + v1;
+#pragma unroll
+                for (int off = 1; off < 64; off <<= 1) {
+                    const int u = __shfl_up(sc, off);
+                    if (lane >= off) sc += u;
+                }
+                if (2 * lane < c) S.start[2 * lane] = sc - v0 - v1;
+                if (2 * lane + 1 < c) S.start[2 * lane + 1] = sc - v1;
+                if (lane == 63) S.total = sc;
+            }
+            __syncthreads();
+            const int total = S.total;
+            for (int g = tid; g < total; g += blockDim.x) {
+                int lo = 0, hi = c - 1;   // last chord whose range starts at or before g
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (S.start[mid] <= g) lo = mid; else hi = mid - 1;
+                }
+                const int j = lo, q = g - S.start[j];
+                const int bx0 = S.box[j][0], by0 = S.box[j][2];
+                const int w = S.box[j][1] - bx0 + 1;
+                const int x = bx0 + q % w, y = by0 + q / w;
                 const Chord ch = S.ch[j];
                 const long long dx = ch.bx - ch.ax, dy = ch.by - ch.ay;
-                for (int q = lane; q < ncand; q += 64) {
-                    const int i = 1 + (q & 7), nidx = q >> 3;
-                    const int x = bx0 + nidx % w, y = by0 + nidx / w;
-                    const long long px = (long long)x << 16, py = (long long)y << 16;
-                    const long long oP = dx * (py - ch.ay) - dy * (px - ch.ax);
-                    const int sP = node_sign(oP, dx, dy);
+                const long long oP = dx * (((long long)y << 16) - ch.ay) - dy * (((long long)x << 16) - ch.ax);
+                const int sP = node_sign(oP, dx, dy);
+                const int node = (y - y0) * kTile + (x - x0);
+#pragma unroll
+                for (int i = 1; i < 9; i++) {
                     int sg;
                     double qq, th;
-                    if (!link_crossing<true>(x, y, i, ch, oP, sP, sg, qq, th)) continue;
-                    const double jpc = (1.0 - th) * S.jpa[j] + th * S.jpb[j];
-                    add_crossing(S, I, x - x0, y - y0, x, y, i, sg, S.key[j], qq, th, jpc,
-                                 records != 0);
+                    if (!link_crossing<false>(x, y, i, ch, oP, sP, sg, qq, th)) continue;
+                    add_jump(S, node, i, sg, (1.0 - th) * S.jpa[j] + th * S.jpb[j]);
+                    if (records) stage_record(S, node, i, j);
                 }
             }
         }
@@ -495,14 +545,16 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
         double gx = 0.0, gy = 0.0;
         if (valid) {
             // tangential force g_par(x) = sum_k G_par,k delta_h(x - X_k) dX (Sec. 3.2, Eq. (46))
-            // (delta weights of marker k at this node, from the marker kernel)
+            // with the delta weights of marker k from the marker pass; markers
+            // whose stencil misses this node add an exact zero
+#pragma unroll 4
             for (int j = 0; j < c; j++) {
-                const int ix = x - S.f0[j].x, iy = y - S.f0[j].y;
-                if ((unsigned)ix > 3u || (unsigned)iy > 3u) continue;
-                const double w = S.wx[j][ix] * S.wy[j][iy];
-                if (w == 0.0) continue;
-                gx += S.gtx[j] * w * I.dX;
-                gy += S.gty[j] * w * I.dX;
+                const int2 f = S.f0[j];
+                const int ix = x - f.x, iy = y - f.y;
+                const bool in = (unsigned)ix <= 3u && (unsigned)iy <= 3u;
+                const double wgt = in ? (double)S.wx[j][ix & 3] * (double)S.wy[j][iy & 3] : 0.0;
+                gx += S.gtx[j] * wgt * I.dX;
+                gy += S.gty[j] * wgt * I.dX;
             }
             if (IFACE == II_LBM_IF_RIGID) {
                 // Rigid circle: level set phi = |x - c|^2 - R^2, interior phi < 0.
@@ -514,22 +566,13 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
                     const double phQ = (qxd - I.cx) * (qxd - I.cx) + (qyd - I.cy) * (qyd - I.cy) - R2;
                     const bool inP = phP < 0.0, inQ = phQ < 0.0;
                     if (inP == inQ) continue;
-                    // cut point: |P + q e - c|^2 = R^2 on the link
-                    const double ee = (double)(EX[i] * EX[i] + EY[i] * EY[i]);
-                    const double de = dx * EX[i] + dy * EY[i];
-                    const double dd = dx * dx + dy * dy - R2;
-                    const double disc = sqrt(de * de - ee * dd);
-                    const double q = inP ? (-de + disc) / ee : (-de - disc) / ee;
-                    const double cxp = (double)x + q * EX[i] - I.cx, cyp = (double)y + q * EY[i] - I.cy;
-                    // [[p]] linear in angle between the two bracketing markers
-                    double ang = atan2(cyp, cxp);
-                    if (ang < 0.0) ang += 2.0 * M_PI;
-                    const double sN = ang * N / (2.0 * M_PI);
-                    const int k = (sN >= 0.0 && sN < (double)N) ? (int)floor(sN) : 0;
-                    const double th = sN - k;
+                    double q, th;
+                    int k;
+                    rigid_cut(I, x, y, i, inP, q, th, k);
                     const double jpc =
                         (1.0 - th) * P.jp[I.mk_off + k] + th * P.jp[I.mk_off + (k + 1) % N];
-                    add_crossing(S, I, lx, ly, x, y, i, inP ? 1 : -1, k, q, th, jpc, records != 0);
+                    add_jump(S, tid, i, inP ? 1 : -1, jpc);
+                    if (records) stage_record(S, tid, i, 0);
                 }
             }
         }
@@ -543,13 +586,14 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
 #pragma unroll
             for (int i = 1; i < 9; i++) {
                 const double delta =
-                    valid ? 3.0 * WD[i] * ((double)EX[i] * gx + (double)EY[i] * gy) + S.acc[i - 1][tid]
+                    valid ? 3.0 * WD[i] * ((double)EX[i] * gx + (double)EY[i] * gy) +
+                                (double)S.acc[i - 1][tid]
                           : 0.0;
                 cr[(i - 1) * kTileNodes] = (float)delta;
             }
         }
-        // Records of this tile: one global slice for the block, filled from
-        // the LDS staging list.
+        // Records of this tile: one global slice for the block; each is
+        // expanded from its packed form by recomputing the crossing.
         if (records) {
             const int nr = min(S.nrec, kTileRec);
             if (tid == 0) {
@@ -558,11 +602,35 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
             }
             __syncthreads();
             const int base = S.base;
-            for (int r = tid; r < nr; r += blockDim.x) {
-                if (base + r < I.rec_cap)
-                    P.rec[I.rec_off + base + r] = S.rec[r];
-                else
+            for (int rr = tid; rr < nr; rr += blockDim.x) {
+                if (base + rr >= I.rec_cap) {
                     atomicOr(&P.err[I.inst], (int)kErrRecords);
+                    continue;
+                }
+                const unsigned pk = S.rec[rr];
+                const int node = pk & 255, i = 1 + ((pk >> 8) & 7), j = pk >> 11;
+                const int x = x0 + (node & (kTile - 1)), y = y0 + node / kTile;
+                ii_lbm_link L;
+                L.x = x; L.y = y; L.dir = i; L.inst = I.inst;
+                if (IFACE == II_LBM_IF_MEMBRANE) {
+                    const Chord ch = S.ch[j];
+                    const long long dx = ch.bx - ch.ax, dy = ch.by - ch.ay;
+                    const long long oP = dx * (((long long)y << 16) - ch.ay) - dy * (((long long)x << 16) - ch.ax);
+                    int sg = 0;
+                    double qq = 0.0, th = 0.0;
+                    (void)link_crossing<true>(x, y, i, ch, oP, node_sign(oP, dx, dy), sg, qq, th);
+                    L.sigma = sg; L.seg = S.key[j]; L.q = qq; L.theta = th;
+                    L.jp = (1.0 - th) * S.jpa[j] + th * S.jpb[j];
+                } else {
+                    const double dx = (double)x - I.cx, dy = (double)y - I.cy;
+                    const bool inP = dx * dx + dy * dy - I.radius * I.radius < 0.0;
+                    double q, th;
+                    int k;
+                    rigid_cut(I, x, y, i, inP, q, th, k);
+                    L.sigma = inP ? 1 : -1; L.seg = k; L.q = q; L.theta = th;
+                    L.jp = (1.0 - th) * P.jp[I.mk_off + k] + th * P.jp[I.mk_off + (k + 1) % N];
+                }
+                P.rec[I.rec_off + base + rr] = L;
             }
         }
         __syncthreads();
