@@ -65,6 +65,13 @@ def cpu_baseline(w, steps: int):
                       f"({dt:.1f} s)"}
 
 
+def set_overlap(sim, B, args) -> None:
+    modes = {"serial": B.OVERLAP_SERIAL, "full": B.OVERLAP_FULL,
+             "interp_first": B.OVERLAP_INTERP_FIRST}
+    if args.overlap != "default":
+        sim.set_overlap(modes[args.overlap])
+
+
 def bench_batch(args, B, W) -> int:
     """Uneven ensemble: all instances advance through one launch per phase,
     replayed as HIP graphs; the sweep slice size and instance order come from
@@ -76,6 +83,7 @@ def bench_batch(args, B, W) -> int:
         w.problem.math = W.MATH_FP64 if args.math == "fp64" else W.MATH_FP32
         w.problem.storage = W.STORE_FP16 if args.storage == "fp16" else W.STORE_FP32
     sim = B.Sim([w.problem for w in ws], [w.X0 for w in ws], device="cuda:0")
+    set_overlap(sim, B, args)
     sim.step(2)
     tune = sim.autotune(5)
     sim.set_graph(args.graph == "on")
@@ -132,6 +140,8 @@ def main() -> int:
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--graph", choices=["on", "off"], default="on",
                     help="batch512: replay steps as HIP graphs or launch directly")
+    ap.add_argument("--overlap", choices=["default", "serial", "full", "interp_first"],
+                    default="default", help="membrane step schedule")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -163,6 +173,7 @@ def main() -> int:
     p = w.problem
     p.math = W.MATH_FP64 if args.math == "fp64" else W.MATH_FP32
     sim = B.Sim([p], [w.X0], device="cuda:0")
+    set_overlap(sim, B, args)
     sim.step(args.warmup)
     sim.sync()
     torch.cuda.synchronize()

@@ -226,6 +226,17 @@ int ii_lbm_sweep_bytes(ii_lbm_handle* h, int32_t inst, double* bytes);
  * launches.  Results are identical either way. */
 int ii_lbm_set_graph(ii_lbm_handle* h, int32_t enable);
 
+/* Schedule of a membrane step (rigid bodies always run in order).  The sweep
+ * of step n and the marker/tile pass of step n+1 touch disjoint buffers:
+ *   SERIAL        all phases in order on the handle's stream;
+ *   FULL          interpolation and the next step's interface pass on an
+ *                 internal stream, concurrent with the sweep (the default);
+ *   INTERP_FIRST  interpolation first, then the interface pass concurrent
+ *                 with the sweep.
+ * Results are bit-identical in every mode. */
+enum { II_LBM_OVERLAP_SERIAL = 0, II_LBM_OVERLAP_FULL = 1, II_LBM_OVERLAP_INTERP_FIRST = 2 };
+int ii_lbm_set_overlap(ii_lbm_handle* h, int32_t mode);
+
 /* Handles with several instances advance them all through one launch per
  * phase and step, driven by work tables.  This autotuner times the batched
  * sweep on the current state (writing only the buffer the next step

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libiilbm.so")
 
 OK, EINVAL, EWORKSPACE, EDEVICE, EUNSTABLE, EGEOMETRY, ESTATE, ECAPACITY = 0, -1, -2, -3, -4, -5, -6, -7
 F_RHO, F_UX, F_UY, F_P, F_DISTRIB = 1, 2, 4, 8, 16
+OVERLAP_SERIAL, OVERLAP_FULL, OVERLAP_INTERP_FIRST = 0, 1, 2
 DT_F32, DT_F64 = 0, 1
 
 
@@ -54,7 +55,7 @@ EXPORTS = [
     "ii_lbm_set_markers", "ii_lbm_fields", "ii_lbm_set_distrib", "ii_lbm_state_size",
     "ii_lbm_save_state", "ii_lbm_load_state", "ii_lbm_cutlinks", "ii_lbm_diag",
     "ii_lbm_set_timing", "ii_lbm_get_timing", "ii_lbm_sweep_bytes", "ii_lbm_set_graph",
-    "ii_lbm_autotune", "ii_lbm_destroy", "ii_lbm_strerror",
+    "ii_lbm_set_overlap", "ii_lbm_autotune", "ii_lbm_destroy", "ii_lbm_strerror",
 ]
 
 _lib = None
@@ -93,6 +94,7 @@ def load():
         "ii_lbm_get_timing": [v, C.POINTER(d), C.POINTER(i64)],
         "ii_lbm_sweep_bytes": [v, i32, C.POINTER(d)],
         "ii_lbm_set_graph": [v, i32],
+        "ii_lbm_set_overlap": [v, i32],
         "ii_lbm_autotune": [v, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(d)],
         "ii_lbm_destroy": [v],
     }
@@ -250,6 +252,10 @@ class Sim:
 
     def set_graph(self, enable: bool) -> None:
         check(load().ii_lbm_set_graph(self.h, 1 if enable else 0), "set_graph")
+
+    def set_overlap(self, mode: int) -> None:
+        """Membrane step schedule (OVERLAP_SERIAL / _FULL / _INTERP_FIRST)."""
+        check(load().ii_lbm_set_overlap(self.h, int(mode)), "set_overlap")
 
     def autotune(self, trials: int = 5):
         u = C.c_int32(); o = C.c_int32(); us = C.c_double()

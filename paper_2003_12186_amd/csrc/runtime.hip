@@ -238,6 +238,7 @@ struct ii_lbm_handle {
     // Membranes: the interface work of step m+1 runs on `aux` while the
     // sweep of step m runs on the main stream (fork/join through events).
     bool lookahead = false;
+    int overlap = 1;           // II_LBM_OVERLAP_* (membranes only)
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool rec_valid = false;  // rigid bodies: a step has built cut-link records
@@ -372,30 +373,42 @@ static hipError_t enqueue_sweep(ii_lbm_handle* h, int par, hipStream_t s, bool t
     return e;
 }
 
-// Interpolation of step m on plane `par` from f^m, then the geometry and tile
-// pass of step m+1 at X^{m+1} on the other plane.
-static hipError_t enqueue_lookahead(ii_lbm_handle* h, int par, hipStream_t s)
+// Interpolation of step m on plane `par` from f^m (U^m, X^{m+1}).
+static hipError_t enqueue_interp(ii_lbm_handle* h, int par, hipStream_t s)
 {
     void* A = h->P.lat[par];
-    hipError_t e = h->batched ? launch_markers_batch(h->batch, h->P, A, par, kModeInterp, s)
-                              : hipSuccess;
-    for (size_t j = 0; !h->batched && j < h->L.inst.size() && e == hipSuccess; j++)
+    if (h->batched) return launch_markers_batch(h->batch, h->P, A, par, kModeInterp, s);
+    hipError_t e = hipSuccess;
+    for (size_t j = 0; j < h->L.inst.size() && e == hipSuccess; j++)
         e = launch_markers(h->L.inst[j], h->P, A, par, kModeInterp, s);
-    if (e == hipSuccess) e = enqueue_interface(h, par ^ 1, kModeGeom, s);
     return e;
 }
 
 // Enqueue one time step of every instance on stream s (no host work besides
 // launches and event operations, so it can be captured into a graph).
-//   membranes:    fork -> aux: interp(m), reset/geom/tiles(m+1);  s: sweep(m) -> join
+//   membranes, by overlap mode (the sweep of step m and the interface pass of
+//   step m+1 touch disjoint buffers):
+//     SERIAL:  sweep(m), interp(m), reset/geom/tiles(m+1), all on s
+//     FULL:    fork -> aux: interp(m), reset/geom/tiles(m+1); s: sweep(m) -> join
+//     INTERP_FIRST: interp(m) on s, fork -> aux: reset/geom/tiles(m+1);
+//              s: sweep(m) -> join
 //   rigid bodies: reset/full markers/tiles(m) -> sweep(m), in order on s
 static hipError_t enqueue_step(ii_lbm_handle* h, int par, hipStream_t s, bool timed)
 {
     hipError_t e = hipSuccess;
+    if (h->lookahead && h->overlap == II_LBM_OVERLAP_SERIAL) {
+        e = enqueue_sweep(h, par, s, timed);
+        if (e == hipSuccess) e = enqueue_interp(h, par, s);
+        if (e == hipSuccess) e = enqueue_interface(h, par ^ 1, kModeGeom, s);
+        return e;
+    }
     if (h->lookahead) {
-        e = hipEventRecord(h->ev_fork, s);
+        const bool first = h->overlap == II_LBM_OVERLAP_INTERP_FIRST;
+        if (first) e = enqueue_interp(h, par, s);
+        if (e == hipSuccess) e = hipEventRecord(h->ev_fork, s);
         if (e == hipSuccess) e = hipStreamWaitEvent(h->aux, h->ev_fork, 0);
-        if (e == hipSuccess) e = enqueue_lookahead(h, par, h->aux);
+        if (e == hipSuccess && !first) e = enqueue_interp(h, par, h->aux);
+        if (e == hipSuccess) e = enqueue_interface(h, par ^ 1, kModeGeom, h->aux);
         if (e == hipSuccess) e = enqueue_sweep(h, par, s, timed);
         if (e == hipSuccess) e = hipEventRecord(h->ev_join, h->aux);
         if (e == hipSuccess) e = hipStreamWaitEvent(s, h->ev_join, 0);
@@ -615,6 +628,7 @@ int ii_lbm_init(const ii_lbm_problem* p, int32_t n_inst, const double* const* X0
             all_membrane = all_membrane && p[j].interface_kind == II_LBM_IF_MEMBRANE;
         }
     h->lookahead = any && all_membrane;
+    h->overlap = II_LBM_OVERLAP_FULL;
     if (e == hipSuccess && h->lookahead) {
         e = hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming);
@@ -656,6 +670,14 @@ int ii_lbm_step(ii_lbm_handle* h, int64_t n_steps)
         h->steps++;
     }
     if (n_steps > 0) h->rec_valid = true;
+    return II_LBM_OK;
+}
+
+int ii_lbm_set_overlap(ii_lbm_handle* h, int32_t mode)
+{
+    if (!h || mode < II_LBM_OVERLAP_SERIAL || mode > II_LBM_OVERLAP_INTERP_FIRST) return II_LBM_EINVAL;
+    if (h->overlap != mode) drop_graphs(h);
+    h->overlap = mode;
     return II_LBM_OK;
 }
 

@@ -92,6 +92,24 @@ def test_graph_replay_equals_direct_launches(B, case):
     b.close()
 
 
+@pytest.mark.parametrize("batched", [False, True])
+def test_overlap_modes_are_bit_identical(B, batched):
+    _say(f"overlap modes serial / full / interp-first, batched={batched}")
+    ws = _small_batch(3) if batched else [W.membrane_c1()]
+    probs, X0 = [w.problem for w in ws], [w.X0 for w in ws]
+    out = []
+    for mode in (B.OVERLAP_SERIAL, B.OVERLAP_FULL, B.OVERLAP_INTERP_FIRST):
+        s = B.Sim(probs, X0)
+        s.set_overlap(mode)
+        s.step(57)
+        out.append([(s.fields(B.F_DISTRIB, inst=j, dtype=np.float32), s.markers(j)[0])
+                    for j in range(len(ws))])
+        s.close()
+    for other in out[1:]:
+        for (fa, xa), (fb, xb) in zip(out[0], other):
+            assert np.array_equal(fa, fb) and np.array_equal(xa, xb)
+
+
 def test_batch_rejects_mixed_storage(B):
     ws = _small_batch(2)
     ws[1].problem.storage = W.STORE_FP16
