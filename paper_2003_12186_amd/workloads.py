@@ -38,7 +38,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
-from typing import List, Optional, Sequence
+from typing import Tuple, List, Optional, Sequence
 
 import numpy as np
 
@@ -238,6 +238,25 @@ def membrane_batch_c4(n_inst: int = 512, first: int = 0) -> List[Workload]:
                     name=f"batch{i}_L{L}")
         out.append(Workload(p, X0, 4000, {"a": a, "b": b, "ar": ar, "instance": i}))
     return out
+
+
+def learned_pair_c5(seed: int, L: int = 256, n_markers: int = 512) -> Tuple[Workload, Workload]:
+    """Coarse/fine membrane pair for the learned correction: the config-3
+    generator (same seed, so the same tau and kappa draw) at L x L and at
+    2L x 2L, with the fine run in diffusive scaling: the same tau (so the same
+    lattice viscosity), markers at twice the coordinates (same count), half
+    the lattice stiffness, four fine steps per coarse step and half the
+    lattice velocity.  Coarse node (i, j) sits on fine node (2i, 2j)."""
+    c = membrane_c3(L=L, seed=seed, n_markers=n_markers)
+    f = membrane_c3(L=2 * L, seed=seed, n_markers=n_markers)
+    f.problem.kappa = c.problem.kappa / 2.0
+    c.steps, f.steps = 2000, 8000
+    c.meta["role"], f.meta["role"] = "coarse", "fine"
+    return c, f
+
+
+LEARNED_TRAIN_SEEDS = range(0, 2000)
+LEARNED_HELDOUT_SEEDS = range(10000, 10200)
 
 
 def seeded_noise(shape, config: int, instance: int) -> np.ndarray:

@@ -1,0 +1,210 @@
+"""Pins of the FP64 oracle of the learned coarse correction (CPU only).
+
+The network, its gradients and the optimiser are pinned to their
+definitions by independent means: brute-force convolution loops, shift
+kernels, central finite differences of the loss, and Adam's closed-form
+first step.  Features and targets are pinned by closed forms (moments of
+the equilibrium, distances to a square and to a regular polygon) and by
+the C oracle's own point-in-polygon predicate.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import oracle.learned as L
+from paper_2003_12186_amd import workloads as W
+
+
+def _conv_loops(a, Wt, b):
+    n, h, w, ci = a.shape
+    co = Wt.shape[3]
+    z = np.zeros((n, h - 2, w - 2, co))
+    for q in range(n):
+        for y in range(h - 2):
+            for x in range(w - 2):
+                for o in range(co):
+                    s = b[o]
+                    for dy in range(3):
+                        for dx in range(3):
+                            for c in range(ci):
+                                s += a[q, y + dy, x + dx, c] * Wt[dy, dx, c, o]
+                    z[q, y, x, o] = s
+    return z
+
+
+def test_conv_matches_brute_force_loops():
+    rng = np.random.default_rng(1)
+    a = rng.normal(size=(2, 5, 6, 3))
+    Wt = rng.normal(size=(3, 3, 3, 2))
+    b = rng.normal(size=2)
+    assert np.allclose(L.conv3x3_valid(a, Wt, b), _conv_loops(a, Wt, b), rtol=0, atol=1e-12)
+
+
+def test_conv_with_a_single_tap_is_a_shift():
+    rng = np.random.default_rng(2)
+    a = rng.normal(size=(1, 7, 8, 2))
+    Wt = np.zeros((3, 3, 2, 2))
+    Wt[1, 2, 0, 1] = 1.0
+    Wt[0, 0, 1, 0] = 1.0
+    z = L.conv3x3_valid(a, Wt, np.zeros(2))
+    assert np.array_equal(z[0, :, :, 1], a[0, 1:6, 2:8, 0])
+    assert np.array_equal(z[0, :, :, 0], a[0, 0:5, 0:6, 1])
+
+
+def _flat_loss(W, b, x, t, m):
+    return L.loss(L.forward(W, b, x)[4], t, m)
+
+
+@pytest.mark.parametrize("channels,size", [((4, 3, 3, 3, 9), 10), ((4, 5, 4, 3, 9), 11)])
+def test_backward_matches_central_differences_everywhere(channels, size):
+    rng = np.random.default_rng(3)
+    W, b = L.init_params(seed=4, channels=channels)
+    for bb in b:
+        bb[:] = rng.normal(scale=0.1, size=bb.shape)
+    x = rng.normal(size=(2, size, size, 4))
+    out = L.forward(W, b, x)[4]
+    t = rng.normal(size=out.shape)
+    m = rng.random(out.shape[:3]) < 0.7
+    gW, gb = L.backward(W, b, L.forward(W, b, x), t, m)
+    h = 1e-6
+    for P, G in list(zip(W, gW)) + list(zip(b, gb)):
+        for idx in np.ndindex(P.shape):
+            keep = P[idx]
+            P[idx] = keep + h
+            lp = _flat_loss(W, b, x, t, m)
+            P[idx] = keep - h
+            lm = _flat_loss(W, b, x, t, m)
+            P[idx] = keep
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - G[idx]) <= 1e-6 * max(1.0, abs(fd)) + 1e-9, (idx, fd, G[idx])
+
+
+def test_backward_full_size_network_sampled_entries():
+    rng = np.random.default_rng(5)
+    W, b = L.init_params(seed=6)
+    x = rng.normal(size=(1, 12, 12, 4))
+    out = L.forward(W, b, x)[4]
+    t = rng.normal(size=out.shape)
+    m = np.ones(out.shape[:3], dtype=bool)
+    gW, gb = L.backward(W, b, L.forward(W, b, x), t, m)
+    h = 1e-6
+    for l in range(4):
+        for _ in range(6):
+            idx = tuple(int(rng.integers(s)) for s in W[l].shape)
+            keep = W[l][idx]
+            W[l][idx] = keep + h
+            lp = _flat_loss(W, b, x, t, m)
+            W[l][idx] = keep - h
+            lm = _flat_loss(W, b, x, t, m)
+            W[l][idx] = keep
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - gW[l][idx]) <= 1e-6 * max(1.0, abs(fd)) + 1e-9
+
+
+def test_adam_first_steps_closed_form():
+    # with a constant gradient g the bias-corrected moments are g and g^2,
+    # so every step moves each parameter by lr * g / (|g| + eps)
+    p = np.array([1.0, -2.0, 0.5])
+    g = np.array([0.3, -1e-3, 0.0])
+    opt = L.Adam([p], lr=1e-2)
+    want = p.copy()
+    for _ in range(3):
+        opt.step([p], [g])
+        want -= 1e-2 * g / (np.abs(g) + 1e-8)
+        assert np.allclose(p, want, rtol=0, atol=1e-15)
+
+
+def test_feq_matches_c_oracle_and_its_moments():
+    rng = np.random.default_rng(7)
+    ex, ey, _ = O.d2q9()
+    for _ in range(5):
+        r, u, v = 1 + 0.01 * rng.normal(), 0.01 * rng.normal(), 0.01 * rng.normal()
+        f = L.feq(np.array(r), np.array(u), np.array(v))
+        assert np.allclose(f, O.equilibrium(r, u, v), rtol=0, atol=1e-15)
+        assert math.isclose(f.sum(), r, abs_tol=1e-15)
+        assert math.isclose((ex * f).sum(), u, abs_tol=1e-16)
+        assert math.isclose((ey * f).sum(), v, abs_tol=1e-16)
+
+
+def test_targets_carry_the_moment_difference_and_vanish_when_moments_agree():
+    rng = np.random.default_rng(8)
+    ny = nx = 8
+    ex, ey, _ = O.d2q9()
+    rc = 1 + 1e-3 * rng.normal(size=(ny, nx))
+    uc = 1e-3 * rng.normal(size=(ny, nx))
+    vc = 1e-3 * rng.normal(size=(ny, nx))
+    fc = L.feq(rc, uc, vc) + 1e-5 * rng.normal(size=(9, ny, nx)) * np.array([0, 0, 0, 0, 0, 1, -1, 1, -1])[:, None, None]
+    rcc, ucc, vcc = fc.sum(0), np.tensordot(ex.astype(float), fc, 1), np.tensordot(ey.astype(float), fc, 1)
+    # a fine field whose restricted moments match the coarse ones exactly
+    ff = np.zeros((9, 2 * ny, 2 * nx))
+    ff[:, ::2, ::2] = L.feq(1 + (rcc - 1) / 4, ucc / 2, vcc / 2)
+    ff[:, 1::2, :] = 1.0 / 9.0
+    ff[:, :, 1::2] = 1.0 / 9.0
+    assert np.abs(L.targets(fc, ff)).max() < 1e-15
+    # arbitrary fine moments: sum_i df_i and sum_i e_i df_i are the differences
+    ff[:, ::2, ::2] = L.feq(1 + 1e-3 * rng.normal(size=(ny, nx)), 1e-3 * rng.normal(size=(ny, nx)),
+                            1e-3 * rng.normal(size=(ny, nx)))
+    d = L.targets(fc, ff)
+    sub = ff[:, ::2, ::2]
+    assert np.allclose(d.sum(-1), 1 + 4 * (sub.sum(0) - 1) - rcc, rtol=0, atol=1e-15)
+    assert np.allclose((d * ex).sum(-1), 2 * np.tensordot(ex.astype(float), sub, 1) - ucc, rtol=0, atol=1e-16)
+    assert np.allclose((d * ey).sum(-1), 2 * np.tensordot(ey.astype(float), sub, 1) - vcc, rtol=0, atol=1e-16)
+
+
+def test_signed_distance_square_and_regular_polygon():
+    # CCW square [10, 20]^2 with 4 markers per side
+    s = np.linspace(0, 1, 5)[:-1]
+    X = np.concatenate([np.stack([10 + 10 * s, 10 + 0 * s], 1), np.stack([20 + 0 * s, 10 + 10 * s], 1),
+                        np.stack([20 - 10 * s, 20 + 0 * s], 1), np.stack([10 + 0 * s, 20 - 10 * s], 1)])
+    px = np.array([15.0, 12.0, 25.0, 23.0, 15.0])
+    py = np.array([15.0, 17.5, 15.0, 24.0, 5.0])
+    want = np.array([-5.0, -2.0, 5.0, 5.0, 5.0])
+    assert np.allclose(L.signed_distance(X, px, py), want, rtol=0, atol=1e-12)
+    # regular N-gon: the centre lies the apothem R cos(pi / N) inside
+    N, R = 48, 9.0
+    th = 2 * np.pi * np.arange(N) / N
+    P = np.stack([30 + R * np.cos(th), 31 + R * np.sin(th)], 1)
+    assert math.isclose(float(L.signed_distance(P, 30.0, 31.0)), -R * math.cos(math.pi / N), abs_tol=1e-12)
+
+
+def test_inside_polygon_agrees_with_c_oracle_on_the_lattice():
+    w = W.membrane_c1()
+    p = O.make_problem(w.problem)
+    yy, xx = np.mgrid[0:64, 0:64]
+    ins = L.inside_polygon(w.X0, xx.astype(float), yy.astype(float))
+    sd = L.signed_distance(w.X0, xx.astype(float), yy.astype(float))
+    for y in range(0, 64, 3):
+        for x in range(64):
+            if abs(sd[y, x]) > 1e-9:
+                assert ins[y, x] == O.node_inside(p, w.X0, x, y), (x, y)
+
+
+def test_extract_patch_wraps_periodically():
+    ny, nx = 32, 48
+    idx = (np.arange(ny)[:, None] * 1000 + np.arange(nx)[None, :])[..., None]
+    pt = L.extract_patch(idx, 0, 1)
+    assert pt.shape == (24, 24, 1)
+    assert pt[0, 0, 0] == (16 - 4) * 1000 + (nx - 4)
+    assert pt[23, 23, 0] == (16 + 19) % ny * 1000 + 19
+
+
+def test_apply_correction_skips_cut_links_and_non_band_nodes():
+    w = W.membrane_c1()
+    f = np.ones((9, 64, 64))
+    yy, xx = np.mgrid[0:64, 0:64]
+    sd = L.signed_distance(w.X0, xx.astype(float), yy.astype(float))
+    df = np.full((64, 64, 9), 0.5)
+    g = f.copy()
+    L.apply_correction(g, df, sd)
+    ex, ey, _ = O.d2q9()
+    band = np.abs(sd) <= 4.0
+    assert np.array_equal(g[:, ~band], f[:, ~band])
+    for i in range(9):
+        for y, x in [(32, 20), (32, 44), (24, 32), (40, 32), (32, 32)]:
+            src_in = sd[(y - ey[i]) % 64, (x - ex[i]) % 64] < 0
+            changed = g[i, y, x] != f[i, y, x]
+            assert changed == (band[y, x] and (i == 0 or src_in == (sd[y, x] < 0)))
+    # across the membrane some populations must be left alone
+    assert (g[:, band] == 1.0).any() and (g[:, band] == 1.5).any()
