@@ -27,6 +27,7 @@ UNITS = {
     "sweep.hip": [],
     "interface.hip": ["-ffp-contract=off"],
     "runtime.hip": [],
+    "learned.hip": [],
 }
 
 

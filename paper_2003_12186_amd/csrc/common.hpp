@@ -354,6 +354,19 @@ struct Batch {
     int storage, math, iface;
 };
 
+// What other translation units may see of a handle: descriptors (host and
+// device copies), the device buffers, the current parity and the stream.
+struct HandleView {
+    int n_inst;
+    const InstDev* inst;     // host copies
+    const InstDev* d_inst;   // device copies
+    DevPtrs P;
+    int parity;              // lattice and marker buffers of the current state
+    hipStream_t stream;
+    int failed;
+};
+int handle_view(ii_lbm_handle* h, HandleView* v);
+
 // ---------------------------------------------------------------------------
 // Launch helpers implemented in the .hip files (host side).
 // ---------------------------------------------------------------------------

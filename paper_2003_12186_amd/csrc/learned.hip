@@ -1,0 +1,776 @@
+// Learned near-interface correction of a 2x-coarsened membrane run: patch
+// features from the lattice and the marker polygon, a four-layer 3 x 3
+// convolutional network on BF16 MFMA (v_mfma_f32_16x16x32_bf16, FP32
+// accumulation), its backward pass, Adam, training targets from a fine run,
+// and the fused per-tile correction (the C ABI of include/ii_learned.h).
+//
+// Convolutions are implicit GEMMs: a wave owns 16 output pixels (MFMA rows)
+// by 16 output channels (columns) and walks K = 9 taps x 32 input channels
+// in steps of 32, one tap per step, so that each lane's eight K values are
+// eight consecutive channels of one pixel: one 16-byte LDS read.  The B
+// fragments of a layer (at most 9 x 2) stay in registers for all of the
+// wave's output tiles.
+#include <math.h>
+
+#include "common.hpp"
+#include "../../include/ii_learned.h"
+
+namespace iilbm {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16;
+
+constexpr int kPatch = 24, kOut = 16, kHalo = 4;
+constexpr int kNP = II_CNN_NPARAM;
+// map sizes of the input and of layers 1-4, channel counts
+constexpr int HS[5] = {24, 22, 20, 18, 16};
+constexpr int CI[4] = {4, 32, 32, 32};
+constexpr int CO[4] = {32, 32, 32, 9};
+// FP32 parameter offsets: W[dy][dx][ci][co] then b[co], layer by layer
+constexpr int OFF_W[4] = {0, 1184, 10432, 19680};
+constexpr int OFF_B[4] = {1152, 10400, 19648, 22272};
+// Packed BF16 fragments (u16 elements): 512 per (k step, n tile).
+// Forward: K = 9 * CI padded to 32-multiples, N = CO padded to 16-multiples.
+constexpr int FKS[4] = {2, 9, 9, 9};
+constexpr int FNT[4] = {2, 2, 2, 1};
+constexpr int FOFF[4] = {0, 2048, 11264, 20480};
+// Backward-data of layers 2-4: K = 9 taps x 32 output channels, N = 32.
+constexpr int BOFF = 25088;
+constexpr int BSIZE = 9 * 2 * 512;
+constexpr int kPacked = BOFF + 3 * BSIZE;
+// saved activations per patch: a1 | a2 | a3 (BF16, [pixel][32])
+constexpr int SAVE_OFF[4] = {0, 0, 15488, 28288};
+constexpr int kSave = 38656;
+constexpr int kMaxCand = 1024;   // candidate chords per patch
+constexpr float kBand = 4.0f, kClip = 8.0f;
+
+__device__ __forceinline__ u16 to_bf16(float f)
+{
+    // round to nearest even (finite inputs)
+    unsigned u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (u16)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(u16 h) { return __uint_as_float((unsigned)h << 16); }
+
+// ---------------------------------------------------------------------------
+// Packing
+// ---------------------------------------------------------------------------
+__global__ void k_pack(const float* __restrict__ prm, u16* __restrict__ out)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= kPacked) return;
+    float v = 0.f;
+    if (e < BOFF) {
+        int l = 3;
+        while (FOFF[l] > e) l--;
+        const int r = e - FOFF[l], j = r & 7, lane = (r >> 3) & 63, idx = r >> 9;
+        const int ks = idx / FNT[l], nt = idx % FNT[l];
+        const int k = 32 * ks + 8 * (lane >> 4) + j, n = 16 * nt + (lane & 15);
+        if (k < 9 * CI[l] && n < CO[l]) {
+            const int t = k / CI[l], ci = k % CI[l];
+            v = prm[OFF_W[l] + (t * CI[l] + ci) * CO[l] + n];
+        }
+    } else {
+        const int r0 = e - BOFF, l = 1 + r0 / BSIZE, r = r0 % BSIZE;
+        const int j = r & 7, lane = (r >> 3) & 63, idx = r >> 9;
+        const int ks = idx >> 1, nt = idx & 1;
+        const int k = 32 * ks + 8 * (lane >> 4) + j, ci = 16 * nt + (lane & 15);
+        const int t = k >> 5, co = k & 31;
+        if (co < CO[l]) v = prm[OFF_W[l] + (t * 32 + ci) * CO[l] + co];
+    }
+    out[e] = to_bf16(v);
+}
+
+// ---------------------------------------------------------------------------
+// One convolution as an implicit GEMM on MFMA.
+//   FULL = false: out[q] = sum_t src[q + d_t] W_t   (valid, map HSRC -> HSRC-2)
+//   FULL = true:  out[q] = sum_t src[q - d_t] W'_t  (full, map HSRC -> HSRC+2,
+//                 reads outside the source are zero)
+// `src` is LDS [HSRC^2][CIN] BF16; epi(row, n, value) gets every output.
+// ---------------------------------------------------------------------------
+template <int HSRC, int HDST, int CIN, int KS, int NT, bool FULL, class Epi>
+__device__ __forceinline__ void conv_mfma(const u16* src, const u16* __restrict__ frag, Epi epi)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+    const int g = lane >> 4;
+    bf16x8 b[KS][NT];
+#pragma unroll
+    for (int ks = 0; ks < KS; ks++)
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++)
+            b[ks][nt] = *(const bf16x8*)(frag + ((ks * NT + nt) * 64 + lane) * 8);
+    constexpr int M = HDST * HDST, MT = (M + 15) / 16;
+    for (int mt = wave; mt < MT; mt += nwave) {
+        const int p = min(mt * 16 + (lane & 15), M - 1);
+        const int py = p / HDST, px = p % HDST;
+        f32x4 acc[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ks++) {
+            bf16x8 a;
+            if (CIN == 32) {
+                const int dy = ks / 3, dx = ks % 3;
+                int sy, sx;
+                bool ok = true;
+                if (FULL) {
+                    sy = py - dy;
+                    sx = px - dx;
+                    ok = sy >= 0 && sy < HSRC && sx >= 0 && sx < HSRC;
+                } else {
+                    sy = py + dy;
+                    sx = px + dx;
+                }
+                if (ok) {
+                    a = *(const bf16x8*)(src + (sy * HSRC + sx) * 32 + 8 * g);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 8; j++) a[j] = (__bf16)0.0f;
+                }
+            } else {
+                // four channels per tap: lane group g takes taps 8 ks + 2 g and + 1
+#pragma unroll
+                for (int h = 0; h < 2; h++) {
+                    const int t = 8 * ks + 2 * g + h;
+                    uint2 v = make_uint2(0u, 0u);
+                    if (t < 9) v = *(const uint2*)(src + ((py + t / 3) * HSRC + px + t % 3) * 4);
+                    a[4 * h + 0] = __builtin_bit_cast(__bf16, (u16)(v.x & 0xffffu));
+                    a[4 * h + 1] = __builtin_bit_cast(__bf16, (u16)(v.x >> 16));
+                    a[4 * h + 2] = __builtin_bit_cast(__bf16, (u16)(v.y & 0xffffu));
+                    a[4 * h + 3] = __builtin_bit_cast(__bf16, (u16)(v.y >> 16));
+                }
+            }
+#pragma unroll
+            for (int nt = 0; nt < NT; nt++)
+                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[ks][nt], acc[nt], 0, 0, 0);
+        }
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int row = mt * 16 + 4 * g + j;
+                if (row < M) epi(row, 16 * nt + (lane & 15), acc[nt][j]);
+            }
+    }
+}
+
+// Forward layer l (0..3) of the network from LDS src to LDS dst (layers
+// 0-2, ReLU, BF16) and, when `save` is set, to the saved activations.
+template <int L>
+__device__ __forceinline__ void hidden_layer(const u16* src, u16* dst, const u16* __restrict__ packed,
+                                             const float* __restrict__ prm, u16* save)
+{
+    const float* bias = prm + OFF_B[L];
+    conv_mfma<HS[L], HS[L + 1], CI[L], FKS[L], FNT[L], false>(
+        src, packed + FOFF[L], [&](int row, int n, float v) {
+            const u16 h = to_bf16(fmaxf(v + bias[n], 0.f));
+            dst[row * 32 + n] = h;
+            if (save) save[row * 32 + n] = h;
+        });
+}
+
+// ---------------------------------------------------------------------------
+// Training forward: one block per patch.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_forward(const float* __restrict__ prm,
+                                                 const u16* __restrict__ packed,
+                                                 const u16* __restrict__ in, float* __restrict__ out,
+                                                 u16* __restrict__ save)
+{
+    __shared__ __align__(16) u16 bx[20 * 20 * 32];
+    __shared__ __align__(16) u16 by[22 * 22 * 32];
+    const long long n = blockIdx.x;
+    const u16* src = in + n * (kPatch * kPatch * 4);
+    for (int e = threadIdx.x; e < kPatch * kPatch * 4 / 2; e += blockDim.x)
+        ((unsigned*)bx)[e] = ((const unsigned*)src)[e];
+    __syncthreads();
+    u16* sv = save ? save + n * kSave : nullptr;
+    hidden_layer<0>(bx, by, packed, prm, sv ? sv + SAVE_OFF[1] : nullptr);
+    __syncthreads();
+    hidden_layer<1>(by, bx, packed, prm, sv ? sv + SAVE_OFF[2] : nullptr);
+    __syncthreads();
+    hidden_layer<2>(bx, by, packed, prm, sv ? sv + SAVE_OFF[3] : nullptr);
+    __syncthreads();
+    const float* b4 = prm + OFF_B[3];
+    float* o = out + n * (kOut * kOut * 9);
+    conv_mfma<18, 16, 32, 9, 1, false>(by, packed + FOFF[3], [&](int row, int c, float v) {
+        if (c < 9) o[row * 9 + c] = v + b4[c];
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Backward: one block per patch; per-patch gradients go to a partial buffer
+// that k_reduce sums over patches in a fixed order.
+// ---------------------------------------------------------------------------
+// Weight gradient of layer L: dW[(t, ci), co] = sum_p a[p + d_t, ci] dz[p, co]
+// (MFMA rows (t, ci), columns co, K over the output pixels).
+template <int L>
+__device__ __forceinline__ void weight_grad(const u16* a, const u16* dz, float* part)
+{
+    constexpr int HA = HS[L], HD = HS[L + 1], CIN = CI[L], COUT = CO[L];
+    constexpr int P = HD * HD, KS = (P + 31) / 32;
+    constexpr int MT = (9 * CIN + 15) / 16, NT = (COUT + 15) / 16;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+    const int g = lane >> 4;
+    for (int f = wave; f < MT * NT; f += nwave) {
+        const int mt = f / NT, nt = f % NT;
+        const int r = mt * 16 + (lane & 15);         // A row of this lane
+        const int t = r / CIN, ci = r % CIN;
+        const bool rok = r < 9 * CIN;
+        const int dy = rok ? t / 3 : 0, dx = rok ? t % 3 : 0;
+        const int co = nt * 16 + (lane & 15);        // B column of this lane
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        for (int ks = 0; ks < KS; ks++) {
+            bf16x8 av, bv;
+#pragma unroll
+            for (int j = 0; j < 8; j++) {
+                const int p = 32 * ks + 8 * g + j;
+                u16 ha = 0, hb = 0;
+                if (p < P) {
+                    const int py = p / HD, px = p % HD;
+                    if (rok) ha = a[((py + dy) * HA + px + dx) * CIN + ci];
+                    hb = dz[p * 32 + co];
+                }
+                av[j] = __builtin_bit_cast(__bf16, ha);
+                bv[j] = __builtin_bit_cast(__bf16, hb);
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int rr = mt * 16 + 4 * g + j;
+            if (rr < 9 * CIN && co < COUT) {
+                const int tt = rr / CIN, cc = rr % CIN;
+                part[OFF_W[L] + (tt * CIN + cc) * COUT + co] = acc[j];
+            }
+        }
+    }
+    // bias: sum of dz over the pixels, one thread per channel in pixel order
+    if ((int)threadIdx.x < COUT) {
+        float s = 0.f;
+        for (int p = 0; p < P; p++) s += from_bf16(dz[p * 32 + threadIdx.x]);
+        part[OFF_B[L] + threadIdx.x] = s;
+    }
+}
+
+// dz of the input of layer L (1..3): (sum_t dz_next[q - d_t] W_t^T) * (a[q] > 0)
+template <int L>
+__device__ __forceinline__ void data_grad(const u16* dz_next, const u16* a, u16* dz,
+                                          const u16* __restrict__ packed)
+{
+    conv_mfma<HS[L + 1], HS[L], 32, 9, 2, true>(
+        dz_next, packed + BOFF + (L - 1) * BSIZE, [&](int row, int n, float v) {
+            dz[row * 32 + n] = a[row * 32 + n] != 0 && !(a[row * 32 + n] & 0x8000u) ? to_bf16(v) : 0;
+        });
+}
+
+template <int L>
+__device__ __forceinline__ void load_act(u16* dst, const u16* __restrict__ src)
+{
+    constexpr int n = HS[L] * HS[L] * CI[L] / 2;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) ((unsigned*)dst)[e] = ((const unsigned*)src)[e];
+}
+
+__global__ void k_count(const uint8_t* __restrict__ mask, long long n, int* __restrict__ count)
+{
+    __shared__ int s[256];
+    int c = 0;
+    for (long long e = threadIdx.x; e < n; e += blockDim.x) c += mask[e] ? 1 : 0;
+    s[threadIdx.x] = c;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *count = s[0];
+}
+
+__global__ __launch_bounds__(256) void k_backward(
+    const u16* __restrict__ packed, const u16* __restrict__ in, const u16* __restrict__ save,
+    const float* __restrict__ out, const float* __restrict__ target,
+    const uint8_t* __restrict__ mask, const int* __restrict__ count, float* __restrict__ part)
+{
+    __shared__ __align__(16) u16 ba[22 * 22 * 32];
+    __shared__ __align__(16) u16 bz0[22 * 22 * 32];
+    __shared__ __align__(16) u16 bz1[22 * 22 * 32];
+    __shared__ float red[256];
+    const long long n = blockIdx.x;
+    float* pp = part + n * (kNP + 1);
+    const float* o = out + n * (kOut * kOut * 9);
+    const float* tg = target + n * (kOut * kOut * 9);
+    const uint8_t* mk = mask + n * (kOut * kOut);
+    const float scale = 2.f / (9.f * (float)max(*count, 1));
+    // dz of the output: 2 m (out - target) / (9 sum m); channels 9..31 zero
+    float ls = 0.f;
+    for (int e = threadIdx.x; e < kOut * kOut * 32; e += blockDim.x) {
+        const int p = e >> 5, c = e & 31;
+        float v = 0.f;
+        if (c < 9 && mk[p]) {
+            const float d = o[p * 9 + c] - tg[p * 9 + c];
+            v = scale * d;
+            ls += d * d;
+        }
+        bz0[e] = to_bf16(v);
+    }
+    red[threadIdx.x] = ls;
+    load_act<3>(ba, save + n * kSave + SAVE_OFF[3]);
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) pp[kNP] = red[0];
+    weight_grad<3>(ba, bz0, pp);
+    data_grad<3>(bz0, ba, bz1, packed);
+    __syncthreads();
+    load_act<2>(ba, save + n * kSave + SAVE_OFF[2]);
+    __syncthreads();
+    weight_grad<2>(ba, bz1, pp);
+    data_grad<2>(bz1, ba, bz0, packed);
+    __syncthreads();
+    load_act<1>(ba, save + n * kSave + SAVE_OFF[1]);
+    __syncthreads();
+    weight_grad<1>(ba, bz0, pp);
+    data_grad<1>(bz0, ba, bz1, packed);
+    __syncthreads();
+    load_act<0>(ba, in + n * (kPatch * kPatch * 4));
+    __syncthreads();
+    weight_grad<0>(ba, bz1, pp);
+}
+
+// grad[j] = sum over patches in order; loss = sum of squares / (9 count)
+__global__ void k_reduce(const float* __restrict__ part, int n, const int* __restrict__ count,
+                         float* __restrict__ grad, float* __restrict__ loss)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j > kNP) return;
+    float s = 0.f;
+    for (int q = 0; q < n; q++) s += part[(long long)q * (kNP + 1) + j];
+    if (j < kNP)
+        grad[j] = s;
+    else
+        loss[0] = s / (9.f * (float)max(*count, 1));
+}
+
+__global__ void k_adam(float* __restrict__ prm, const float* __restrict__ grad,
+                       float* __restrict__ m, float* __restrict__ v, float lr, float c1, float c2)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= kNP) return;
+    const float g = grad[j];
+    const float mj = 0.9f * m[j] + 0.1f * g;
+    const float vj = 0.999f * v[j] + 0.001f * g * g;
+    m[j] = mj;
+    v[j] = vj;
+    prm[j] -= lr * (mj / c1) / (sqrtf(vj / c2) + 1e-8f);
+}
+
+// ---------------------------------------------------------------------------
+// Band tiles, features and the fused correction
+// ---------------------------------------------------------------------------
+// One block per instance, one thread per tile: a tile is in the band when a
+// chord's box, grown by 4.5, meets the tile's node box.
+__global__ void k_band_tiles(const InstDev* __restrict__ insts, const double2* __restrict__ Xall,
+                             int cap, int* __restrict__ tiles, int* __restrict__ count)
+{
+    const InstDev I = insts[blockIdx.x];
+    __shared__ int flag[1024];
+    __shared__ int base[1024];
+    const int nt = I.tiles_x * I.tiles_y;
+    const double2* X = Xall + I.mk_off;
+    const int N = I.n_markers;
+    for (int t = threadIdx.x; t < nt; t += blockDim.x) {
+        const double x0 = (t % I.tiles_x) * kTile, y0 = (t / I.tiles_x) * kTile;
+        int hit = 0;
+        for (int k = 0; k < N && !hit; k++) {
+            const double2 a = X[k], b = X[(k + 1) % N];
+            const double lx = fmin(a.x, b.x) - 4.5, hx = fmax(a.x, b.x) + 4.5;
+            const double ly = fmin(a.y, b.y) - 4.5, hy = fmax(a.y, b.y) + 4.5;
+            hit = lx <= x0 + 15 && hx >= x0 && ly <= y0 + 15 && hy >= y0;
+        }
+        flag[t] = hit;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int c = 0;
+        for (int t = 0; t < nt; t++) {
+            base[t] = c;
+            c += flag[t];
+        }
+        count[blockIdx.x] = min(c, cap);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < nt; t += blockDim.x)
+        if (flag[t] && base[t] < cap)
+            ((int2*)tiles)[(long long)blockIdx.x * cap + base[t]] =
+                make_int2(t % I.tiles_x, t / I.tiles_x);
+}
+
+struct PatchShared {
+    float4 cand[kMaxCand];    // candidate chords, relative to the patch origin
+    int ncand, parity;
+};
+
+// Features of the 24 x 24 patch around tile (tx, ty) into LDS: BF16 input
+// (scaled) and flags (bit 0 inside, bit 1 band).  The sign comes from the
+// parity of the crossings of the segment from a fixed interior point of the
+// tile to the node (the point's own side from a ray towards +x over all
+// chords); the distance from the chords that come within 8 of the patch.
+template <typename T>
+__device__ void build_patch(const InstDev& I, const T* __restrict__ A, const double2* __restrict__ X,
+                            int tx, int ty, const ii_cnn_scales& sc, PatchShared& S, u16* in,
+                            uint8_t* flags)
+{
+    const int N = I.n_markers;
+    const int ox = tx * kTile - kHalo, oy = ty * kTile - kHalo;  // patch origin node
+    const double cxd = ox + kHalo + 7.37, cyd = oy + kHalo + 7.71;
+    if (threadIdx.x == 0) {
+        S.ncand = 0;
+        S.parity = 0;
+    }
+    __syncthreads();
+    int par = 0;
+    for (int k = threadIdx.x; k < N; k += blockDim.x) {
+        const double2 a = X[k], b = X[(k + 1) % N];
+        if ((a.y > cyd) != (b.y > cyd)) {
+            const double xc = a.x + (cyd - a.y) * (b.x - a.x) / (b.y - a.y);
+            if (cxd < xc) par ^= 1;
+        }
+        const double m = kClip + 1.0;
+        if (fmax(a.x, b.x) >= ox - m && fmin(a.x, b.x) <= ox + kPatch - 1 + m &&
+            fmax(a.y, b.y) >= oy - m && fmin(a.y, b.y) <= oy + kPatch - 1 + m) {
+            const int c = atomicAdd(&S.ncand, 1);
+            if (c < kMaxCand)
+                S.cand[c] = make_float4((float)(a.x - ox), (float)(a.y - oy), (float)(b.x - ox),
+                                        (float)(b.y - oy));
+        }
+    }
+    if (par) atomicXor(&S.parity, 1);
+    __syncthreads();
+    const int nc = min(S.ncand, kMaxCand);
+    const int inside_c = S.parity;
+    const float cx = (float)(cxd - ox), cy = (float)(cyd - oy);
+    for (int q = threadIdx.x; q < kPatch * kPatch; q += blockDim.x) {
+        const int py = q / kPatch, px = q % kPatch;
+        const float fx = (float)px, fy = (float)py;
+        float d2 = kClip * kClip;
+        int cross = 0;
+        for (int c = 0; c < nc; c++) {
+            const float4 s = S.cand[c];
+            const float dx = s.z - s.x, dy = s.w - s.y;
+            const float ll = dx * dx + dy * dy;
+            float t = ((fx - s.x) * dx + (fy - s.y) * dy) / ll;
+            t = fminf(fmaxf(t, 0.f), 1.f);
+            const float qx = s.x + t * dx - fx, qy = s.y + t * dy - fy;
+            d2 = fminf(d2, qx * qx + qy * qy);
+            // segment (c -> node) against chord (a -> b)
+            const float o1 = (fx - cx) * (s.y - cy) - (fy - cy) * (s.x - cx);
+            const float o2 = (fx - cx) * (s.w - cy) - (fy - cy) * (s.z - cx);
+            const float o3 = dx * (cy - s.y) - dy * (cx - s.x);
+            const float o4 = dx * (fy - s.y) - dy * (fx - s.x);
+            cross ^= ((o1 > 0.f) != (o2 > 0.f)) && ((o3 > 0.f) != (o4 > 0.f));
+        }
+        const int ins = inside_c ^ cross;
+        const float dist = sqrtf(d2);
+        const float sd = ins ? -dist : dist;
+        // moments of the pulled distributions at the node (periodic wrap)
+        int gx = (ox + px) % I.nx, gy = (oy + py) % I.ny;
+        if (gx < 0) gx += I.nx;
+        if (gy < 0) gy += I.ny;
+        float d[9];
+        pull<T, float>(I, A, gx, gy, d);
+        float r, ux, uy;
+        moments<float>(d, r, ux, uy);
+        in[q * 4 + 0] = to_bf16(r * sc.in_scale[0]);
+        in[q * 4 + 1] = to_bf16(ux * sc.in_scale[1]);
+        in[q * 4 + 2] = to_bf16(uy * sc.in_scale[2]);
+        in[q * 4 + 3] = to_bf16(sd * sc.in_scale[3]);
+        flags[q] = (uint8_t)(ins | (dist <= kBand ? 2 : 0));
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_patches(const InstDev* __restrict__ insts, const void* A0,
+                                                 const double2* __restrict__ Xall, ii_cnn_scales sc,
+                                                 int cap, const int* __restrict__ tiles,
+                                                 const int* __restrict__ count, u16* __restrict__ in,
+                                                 uint8_t* __restrict__ flags)
+{
+    const int inst = blockIdx.x / cap, r = blockIdx.x % cap;
+    if (r >= count[inst]) return;
+    const InstDev I = insts[inst];
+    __shared__ PatchShared S;
+    const int2 t = ((const int2*)tiles)[blockIdx.x];
+    const long long slot = blockIdx.x;
+    build_patch<T>(I, (const T*)A0, Xall + I.mk_off, t.x, t.y, sc, S,
+                   in + slot * (kPatch * kPatch * 4), flags + slot * (kPatch * kPatch));
+}
+
+// Targets: f^eq(rho_hat, u_hat) - f^eq(rho_c, u_c) in network units; the
+// band mask of the output pixels from the patch flags.
+template <typename TC, typename TF>
+__global__ void k_targets(const InstDev* __restrict__ ic, const void* Ac,
+                          const InstDev* __restrict__ iff, const void* Af, float inv_out, int cap,
+                          const int* __restrict__ tiles, const int* __restrict__ count,
+                          const uint8_t* __restrict__ flags, float* __restrict__ target,
+                          uint8_t* __restrict__ mask)
+{
+    const int inst = blockIdx.x / cap, r = blockIdx.x % cap;
+    if (r >= count[inst]) return;
+    const InstDev C = ic[inst], F = iff[inst];
+    const int2 t = ((const int2*)tiles)[blockIdx.x];
+    const long long slot = blockIdx.x;
+    const int q = threadIdx.x;   // 256 output nodes
+    const int oy = q / kOut, ox = q % kOut;
+    const int x = t.x * kTile + ox, y = t.y * kTile + oy;
+    double dc[9], df[9];
+    pull<TC, double>(C, (const TC*)Ac, x, y, dc);
+    pull<TF, double>(F, (const TF*)Af, 2 * x, 2 * y, df);
+    double rc, uc, vc, rf, uf, vf;
+    moments<double>(dc, rc, uc, vc);
+    moments<double>(df, rf, uf, vf);
+    rf *= 4.0;
+    uf *= 2.0;
+    vf *= 2.0;
+    // He-Luo equilibrium deviations w_i [drho + 3 e.u + 4.5 (e.u)^2 - 1.5 u.u]
+    float* tg = target + slot * (kOut * kOut * 9) + q * 9;
+#pragma unroll
+    for (int i = 0; i < 9; i++) {
+        const double ef = EX[i] * uf + EY[i] * vf, ec = EX[i] * uc + EY[i] * vc;
+        const double a = WD[i] * (rf + 3.0 * ef + 4.5 * ef * ef - 1.5 * (uf * uf + vf * vf));
+        const double b = WD[i] * (rc + 3.0 * ec + 4.5 * ec * ec - 1.5 * (uc * uc + vc * vc));
+        tg[i] = (float)((a - b) * (double)inv_out);
+    }
+    const uint8_t fl = flags[slot * (kPatch * kPatch) + (oy + kHalo) * kPatch + ox + kHalo];
+    mask[slot * (kOut * kOut) + q] = (fl & 2) ? 1 : 0;
+}
+
+// The network and the masked add of one coarse step, one block per band
+// tile, on the patches that k_patches built from the state before any tile
+// was corrected (a tile's halo overlaps its neighbours' nodes).
+template <typename T>
+__global__ __launch_bounds__(256) void k_correct(const InstDev* __restrict__ insts, void* A0,
+                                                 const float* __restrict__ prm,
+                                                 const u16* __restrict__ packed, ii_cnn_scales sc,
+                                                 int cap, const int* __restrict__ tiles,
+                                                 const int* __restrict__ count,
+                                                 const u16* __restrict__ in,
+                                                 const uint8_t* __restrict__ flags)
+{
+    const int inst = blockIdx.x / cap, r = blockIdx.x % cap;
+    if (r >= count[inst]) return;
+    const InstDev I = insts[inst];
+    __shared__ __align__(16) u16 bx[20 * 20 * 32];
+    __shared__ __align__(16) u16 by[22 * 22 * 32];
+    __shared__ uint8_t fl[kPatch * kPatch];
+    const int2 t = ((const int2*)tiles)[blockIdx.x];
+    T* A = (T*)A0;
+    const long long slot = blockIdx.x;
+    {
+        const unsigned* src = (const unsigned*)(in + slot * (kPatch * kPatch * 4));
+        for (int e = threadIdx.x; e < kPatch * kPatch * 2; e += blockDim.x) ((unsigned*)bx)[e] = src[e];
+        for (int e = threadIdx.x; e < kPatch * kPatch; e += blockDim.x)
+            fl[e] = flags[slot * (kPatch * kPatch) + e];
+    }
+    __syncthreads();
+    hidden_layer<0>(bx, by, packed, prm, nullptr);
+    __syncthreads();
+    hidden_layer<1>(by, bx, packed, prm, nullptr);
+    __syncthreads();
+    hidden_layer<2>(bx, by, packed, prm, nullptr);
+    __syncthreads();
+    const float* b4 = prm + OFF_B[3];
+    const float os = sc.out_scale;
+    T* base = A + I.lat_off;
+    conv_mfma<18, 16, 32, 9, 1, false>(by, packed + FOFF[3], [&](int row, int c, float v) {
+        if (c >= 9) return;
+        const int oy = row / kOut, ox = row % kOut;
+        const int q = (oy + kHalo) * kPatch + ox + kHalo;
+        const uint8_t f = fl[q];
+        if (!(f & 2)) return;
+        if (c != 0) {
+            const uint8_t fs = fl[q - EY[c] * kPatch - EX[c]];
+            if ((fs & 1) != (f & 1)) return;   // a link across the polygon
+        }
+        // pre-collision f_c(x) is the value stored at x - e_c
+        int x = t.x * kTile + ox - EX[c], y = t.y * kTile + oy - EY[c];
+        x = x < 0 ? x + I.nx : (x >= I.nx ? x - I.nx : x);
+        y = y < 0 ? y + I.ny : (y >= I.ny ? y - I.ny : y);
+        T* p = base + c * I.plane + (long long)y * I.pitch + x;
+        Store<T>::st(p, Store<T>::ld(p, I.scale) + os * (v + b4[c]), I.inv_scale);
+    });
+}
+
+// Learned correction needs periodic membranes on 16-multiples (the patches
+// wrap) and the same storage across instances.
+int check_learned(const HandleView& v)
+{
+    if (v.failed) return II_LBM_ESTATE;
+    for (int j = 0; j < v.n_inst; j++) {
+        const InstDev& I = v.inst[j];
+        if (I.iface != II_LBM_IF_MEMBRANE || I.bounded || I.nx % kTile || I.ny % kTile ||
+            I.tiles_x * I.tiles_y > 1024 || I.storage != v.inst[0].storage)
+            return II_LBM_EINVAL;
+    }
+    return II_LBM_OK;
+}
+
+int err(hipError_t e) { return e == hipSuccess ? II_LBM_OK : II_LBM_EDEVICE; }
+
+}  // namespace
+}  // namespace iilbm
+
+using namespace iilbm;
+
+extern "C" {
+
+size_t ii_cnn_packed_bytes(void) { return (size_t)kPacked * sizeof(u16); }
+size_t ii_cnn_save_bytes(void) { return (size_t)kSave * sizeof(u16); }
+size_t ii_cnn_work_bytes(int32_t n)
+{
+    return n < 1 ? 0 : (size_t)n * (kNP + 1) * sizeof(float) + 256;
+}
+
+int ii_cnn_pack(const float* params, void* packed, void* stream)
+{
+    if (!params || !packed) return II_LBM_EINVAL;
+    hipLaunchKernelGGL(k_pack, dim3((kPacked + 255) / 256), dim3(256), 0, (hipStream_t)stream,
+                       params, (u16*)packed);
+    return err(hipGetLastError());
+}
+
+int ii_cnn_forward(const float* params, const void* packed, const uint16_t* in, int32_t n,
+                   float* out, uint16_t* save, void* stream)
+{
+    if (!params || !packed || !in || !out || n < 0) return II_LBM_EINVAL;
+    if (n == 0) return II_LBM_OK;
+    hipLaunchKernelGGL(k_forward, dim3(n), dim3(256), 0, (hipStream_t)stream, params,
+                       (const u16*)packed, (const u16*)in, out, (u16*)save);
+    return err(hipGetLastError());
+}
+
+int ii_cnn_backward(const float* params, const void* packed, const uint16_t* in,
+                    const uint16_t* save, const float* out, const float* target,
+                    const uint8_t* mask, int32_t n, float* grad, float* loss, void* work,
+                    void* stream)
+{
+    if (!params || !packed || !in || !save || !out || !target || !mask || !grad || !loss ||
+        !work || n < 1)
+        return II_LBM_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int* count = (int*)work;
+    float* part = (float*)((char*)work + 256);
+    hipLaunchKernelGGL(k_count, dim3(1), dim3(256), 0, s, mask, (long long)n * kOut * kOut, count);
+    hipLaunchKernelGGL(k_backward, dim3(n), dim3(256), 0, s, (const u16*)packed, (const u16*)in,
+                       (const u16*)save, out, target, mask, count, part);
+    hipLaunchKernelGGL(k_reduce, dim3((kNP + 1 + 255) / 256), dim3(256), 0, s, part, (int)n, count,
+                       grad, loss);
+    return err(hipGetLastError());
+}
+
+int ii_cnn_adam(float* params, const float* grad, float* m, float* v, int32_t t, float lr,
+                void* packed, void* stream)
+{
+    if (!params || !grad || !m || !v || t < 1 || !packed) return II_LBM_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const float c1 = (float)(1.0 - pow(0.9, t)), c2 = (float)(1.0 - pow(0.999, t));
+    hipLaunchKernelGGL(k_adam, dim3((kNP + 255) / 256), dim3(256), 0, s, params, grad, m, v, lr, c1,
+                       c2);
+    hipLaunchKernelGGL(k_pack, dim3((kPacked + 255) / 256), dim3(256), 0, s, params, (u16*)packed);
+    return err(hipGetLastError());
+}
+
+int ii_lbm_learned_tiles(ii_lbm_handle* h, int32_t cap, int32_t* tiles, int32_t* count)
+{
+    HandleView v;
+    int rc = handle_view(h, &v);
+    if (rc) return rc;
+    if ((rc = check_learned(v))) return rc;
+    if (!tiles || !count || cap < 1) return II_LBM_EINVAL;
+    for (int j = 0; j < v.n_inst; j++)
+        if (cap < v.inst[j].tiles_x * v.inst[j].tiles_y) return II_LBM_EINVAL;
+    hipLaunchKernelGGL(k_band_tiles, dim3(v.n_inst), dim3(256), 0, v.stream, v.d_inst,
+                       v.P.X[v.parity], (int)cap, (int*)tiles, (int*)count);
+    return err(hipGetLastError());
+}
+
+int ii_lbm_learned_patches(ii_lbm_handle* h, const ii_cnn_scales* sc, int32_t cap,
+                           const int32_t* tiles, const int32_t* count, uint16_t* in,
+                           uint8_t* flags)
+{
+    HandleView v;
+    int rc = handle_view(h, &v);
+    if (rc) return rc;
+    if ((rc = check_learned(v))) return rc;
+    if (!sc || !tiles || !count || !in || !flags || cap < 1) return II_LBM_EINVAL;
+    const dim3 grid((unsigned)(v.n_inst * cap));
+    if (v.inst[0].storage == II_LBM_FP16)
+        hipLaunchKernelGGL(k_patches<_Float16>, grid, dim3(256), 0, v.stream, v.d_inst,
+                           v.P.lat[v.parity], v.P.X[v.parity], *sc, (int)cap, (const int*)tiles,
+                           (const int*)count, (u16*)in, flags);
+    else
+        hipLaunchKernelGGL(k_patches<float>, grid, dim3(256), 0, v.stream, v.d_inst,
+                           v.P.lat[v.parity], v.P.X[v.parity], *sc, (int)cap, (const int*)tiles,
+                           (const int*)count, (u16*)in, flags);
+    return err(hipGetLastError());
+}
+
+int ii_lbm_learned_targets(ii_lbm_handle* hc, ii_lbm_handle* hf, const ii_cnn_scales* sc,
+                           int32_t cap, const int32_t* tiles, const int32_t* count,
+                           const uint8_t* flags, float* target, uint8_t* mask)
+{
+    HandleView c, f;
+    int rc = handle_view(hc, &c);
+    if (rc) return rc;
+    if ((rc = handle_view(hf, &f))) return rc;
+    if ((rc = check_learned(c))) return rc;
+    if ((rc = check_learned(f))) return rc;
+    if (!sc || !tiles || !count || !flags || !target || !mask || cap < 1 || !(sc->out_scale > 0.f))
+        return II_LBM_EINVAL;
+    if (c.n_inst != f.n_inst) return II_LBM_EINVAL;
+    for (int j = 0; j < c.n_inst; j++)
+        if (f.inst[j].nx != 2 * c.inst[j].nx || f.inst[j].ny != 2 * c.inst[j].ny) return II_LBM_EINVAL;
+    // the fine handle's queue must be done before the coarse stream reads it
+    hipError_t e = hipStreamSynchronize(f.stream);
+    if (e != hipSuccess) return II_LBM_EDEVICE;
+    const dim3 grid((unsigned)(c.n_inst * cap));
+    const float inv = 1.f / sc->out_scale;
+    const bool c16 = c.inst[0].storage == II_LBM_FP16, f16 = f.inst[0].storage == II_LBM_FP16;
+#define II_TARGETS(TC, TF)                                                                       \
+    hipLaunchKernelGGL((k_targets<TC, TF>), grid, dim3(256), 0, c.stream, c.d_inst,              \
+                       c.P.lat[c.parity], f.d_inst, f.P.lat[f.parity], inv, (int)cap,            \
+                       (const int*)tiles, (const int*)count, flags, target, mask)
+    if (c16 && f16) II_TARGETS(_Float16, _Float16);
+    else if (c16) II_TARGETS(_Float16, float);
+    else if (f16) II_TARGETS(float, _Float16);
+    else II_TARGETS(float, float);
+#undef II_TARGETS
+    return err(hipGetLastError());
+}
+
+int ii_lbm_learned_correct(ii_lbm_handle* h, const float* params, const void* packed,
+                           const ii_cnn_scales* sc, int32_t cap, int32_t* tiles, int32_t* count,
+                           uint16_t* in, uint8_t* flags)
+{
+    if (!params || !packed || !sc || !in || !flags) return II_LBM_EINVAL;
+    int rc = ii_lbm_learned_tiles(h, cap, tiles, count);
+    if (rc) return rc;
+    if ((rc = ii_lbm_learned_patches(h, sc, cap, tiles, count, in, flags))) return rc;
+    HandleView v;
+    handle_view(h, &v);
+    const dim3 grid((unsigned)(v.n_inst * cap));
+    if (v.inst[0].storage == II_LBM_FP16)
+        hipLaunchKernelGGL(k_correct<_Float16>, grid, dim3(256), 0, v.stream, v.d_inst,
+                           v.P.lat[v.parity], params, (const u16*)packed, *sc, (int)cap,
+                           (const int*)tiles, (const int*)count, (const u16*)in, flags);
+    else
+        hipLaunchKernelGGL(k_correct<float>, grid, dim3(256), 0, v.stream, v.d_inst,
+                           v.P.lat[v.parity], params, (const u16*)packed, *sc, (int)cap,
+                           (const int*)tiles, (const int*)count, (const u16*)in, flags);
+    return err(hipGetLastError());
+}
+
+}  // extern "C"

@@ -476,6 +476,21 @@ static void release(ii_lbm_handle* h)
     delete h;
 }
 
+namespace iilbm {
+int handle_view(ii_lbm_handle* h, HandleView* v)
+{
+    if (!h || !v) return II_LBM_EINVAL;
+    v->n_inst = (int)h->prob.size();
+    v->inst = h->L.inst.data();
+    v->d_inst = (const InstDev*)(h->ws + h->L.off_insts);
+    v->P = h->P;
+    v->parity = h->parity;
+    v->stream = h->stream;
+    v->failed = h->failed;
+    return II_LBM_OK;
+}
+}  // namespace iilbm
+
 extern "C" {
 
 int ii_lbm_workspace_size(const ii_lbm_problem* p, int32_t n_inst, size_t* bytes)
@@ -620,6 +635,10 @@ int ii_lbm_init(const ii_lbm_problem* p, int32_t n_inst, const double* const* X0
             e = hipMemcpy((void*)b.tile_table, tl.data(), tl.size() * sizeof(int2), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = upload_sweep_table(h, 256, 1);
     }
+    // every handle keeps a device copy of its descriptors
+    if (e == hipSuccess)
+        e = hipMemcpy(h->ws + L.off_insts, h->L.inst.data(), n_inst * sizeof(InstDev),
+                      hipMemcpyHostToDevice);
     // membranes (no direct forcing) take the overlapped schedule
     bool any = false, all_membrane = true;
     for (int j = 0; j < n_inst; j++)

@@ -90,3 +90,41 @@ def test_strerror():
     lib = B.load()
     for code in range(-7, 1):
         assert len(lib.ii_lbm_strerror(code)) > 0
+
+
+LEARNED_HEADER = os.path.join(ROOT, "include", "ii_learned.h")
+
+
+def test_learned_header_calls_are_exported_and_sized():
+    from paper_2003_12186_amd import learned as LN
+    src = open(LEARNED_HEADER).read()
+    names = sorted(set(re.findall(r"\b(ii_(?:cnn|lbm_learned)_[a-z_]+)\s*\(", src)))
+    lib = LN.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(LN.EXPORTS) == names
+    # host-only size queries
+    assert lib.ii_cnn_packed_bytes() == 2 * (25088 + 3 * 9 * 2 * 512)
+    assert lib.ii_cnn_save_bytes() == 2 * (22 * 22 + 20 * 20 + 18 * 18) * 32
+    assert lib.ii_cnn_work_bytes(3) == 3 * (LN.NPARAM + 1) * 4 + 256
+    assert C.sizeof(LN.Scales) == 20
+
+
+def test_learned_parameter_layout_round_trips_with_the_oracle():
+    import oracle.learned as OL
+    from paper_2003_12186_amd import learned as LN
+    Wt, b = OL.init_params(seed=3)
+    assert sum(w.size for w in Wt) + sum(x.size for x in b) == LN.NPARAM
+    p = LN.flatten_params(Wt, b)
+    W2, b2 = LN.split_params(p)
+    for l in range(4):
+        assert np.array_equal(W2[l], Wt[l].astype(np.float32).astype(np.float64))
+        assert W2[l].shape == Wt[l].shape and b2[l].shape == b[l].shape
+
+
+def test_learned_calls_reject_null_arguments_without_a_device():
+    from paper_2003_12186_amd import learned as LN
+    lib = LN.lib()
+    assert lib.ii_cnn_pack(None, None, None) == B.EINVAL
+    assert lib.ii_cnn_forward(None, None, None, 1, None, None, None) == B.EINVAL
+    assert lib.ii_lbm_learned_tiles(None, 16, None, None) == B.EINVAL

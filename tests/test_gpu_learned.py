@@ -1,0 +1,299 @@
+"""GPU parity of the learned-correction kernels (through the C ABI) against
+the FP64 oracle in ``oracle/learned.py``.
+
+The network runs on BF16 MFMA with FP32 accumulation and BF16 activations,
+so its outputs and gradients are compared with the oracle evaluated on the
+same BF16-rounded weights and inputs, to BF16 accuracy (relative L2 1e-2 for
+outputs, 3e-2 for gradients).  Features and targets use FP32/FP64
+arithmetic and are compared to their rounding; flags are exact away from
+ties (|sd| within 1e-4 of 0 or of the band edge 4).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import oracle.learned as OL
+from paper_2003_12186_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mods(require_gpu):
+    from paper_2003_12186_amd import binding, learned
+    binding.load()
+    learned.lib()
+    return binding, learned
+
+
+def _bf16(a):
+    import torch
+    return torch.tensor(np.asarray(a, dtype=np.float32)).to(torch.bfloat16).float().numpy().astype(np.float64)
+
+
+def _rel(a, b):
+    return np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300)
+
+
+def _params(seed, bias=0.05):
+    Wt, b = OL.init_params(seed=seed)
+    rng = np.random.default_rng(seed + 100)
+    b = [rng.normal(scale=bias, size=x.shape) for x in b]
+    return Wt, b
+
+
+def _net(LN, Wt, b):
+    p = LN.flatten_params(Wt, b)
+    net = LN.Net(p)
+    Wq = [_bf16(w) for w in Wt]                         # what the kernels multiply with
+    bq = [np.asarray(x, dtype=np.float32).astype(np.float64) for x in b]
+    return net, Wq, bq
+
+
+def _inputs(n, seed):
+    import torch
+    rng = np.random.default_rng(seed)
+    x = rng.normal(size=(n, 24, 24, 4)).astype(np.float32)
+    t = torch.tensor(x).to(torch.bfloat16).cuda()
+    return t, t.float().cpu().numpy().astype(np.float64)
+
+
+def test_forward_matches_oracle(mods):
+    _, LN = mods
+    _say("CNN forward, 6 random patches, BF16 MFMA vs FP64 oracle")
+    Wt, b = _params(1)
+    net, Wq, bq = _net(LN, Wt, b)
+    xg, xo = _inputs(6, 2)
+    out, _ = net.forward(xg)
+    got = out.cpu().numpy().astype(np.float64)
+    want = OL.forward(Wq, bq, xo)[4]
+    r = _rel(got, want)
+    _say(f"  rel L2 {r:.3e}  max|d| {np.abs(got - want).max():.3e} of max {np.abs(want).max():.3e}")
+    assert got.shape == want.shape
+    assert r <= 1e-2
+    assert np.abs(got - want).max() <= 3e-2 * np.abs(want).max()
+
+
+def test_backward_matches_oracle(mods):
+    import torch
+    _, LN = mods
+    _say("CNN backward (masked MSE), 5 patches, per-layer gradients vs FP64 oracle")
+    Wt, b = _params(3)
+    net, Wq, bq = _net(LN, Wt, b)
+    xg, xo = _inputs(5, 4)
+    rng = np.random.default_rng(5)
+    tgt = rng.normal(size=(5, 16, 16, 9)).astype(np.float32)
+    mask = (rng.random((5, 16, 16)) < 0.6).astype(np.uint8)
+    out, sv = net.forward(xg, save=True)
+    grad, loss = net.backward(xg, sv, out, torch.tensor(tgt).cuda(), torch.tensor(mask).cuda())
+    g = grad.cpu().numpy().astype(np.float64)
+    acts = OL.forward(Wq, bq, xo)
+    gW, gb = OL.backward(Wq, bq, acts, tgt.astype(np.float64), mask.astype(bool))
+    lo = OL.loss(acts[4], tgt.astype(np.float64), mask.astype(bool))
+    gw2, gb2 = LN.split_params(g)
+    for l in range(4):
+        rw, rb = _rel(gw2[l], gW[l]), _rel(gb2[l], gb[l])
+        _say(f"  layer {l + 1}: rel L2 dW {rw:.3e}  db {rb:.3e}")
+        assert rw <= 3e-2 and rb <= 3e-2
+    _say(f"  loss {loss.item():.6e} vs {lo:.6e}")
+    assert abs(loss.item() - lo) <= 1e-2 * lo
+
+
+def test_backward_is_deterministic(mods):
+    import torch
+    _, LN = mods
+    Wt, b = _params(6)
+    net, _, _ = _net(LN, Wt, b)
+    xg, _ = _inputs(7, 7)
+    tgt = torch.randn((7, 16, 16, 9), device="cuda")
+    mask = torch.ones((7, 16, 16), dtype=torch.uint8, device="cuda")
+    out, sv = net.forward(xg, save=True)
+    g1, _ = net.backward(xg, sv, out, tgt, mask)
+    g2, _ = net.backward(xg, sv, out, tgt, mask)
+    assert torch.equal(g1, g2)
+
+
+def test_adam_matches_oracle_and_repacks(mods):
+    import torch
+    _, LN = mods
+    _say("Adam: three FP32 steps vs FP64 oracle, then forward with the new weights")
+    Wt, b = _params(8)
+    p0 = LN.flatten_params(Wt, b)
+    net = LN.Net(p0)
+    rng = np.random.default_rng(9)
+    ref = p0.astype(np.float64).copy()
+    opt = OL.Adam([ref], lr=1e-3)
+    for _ in range(3):
+        g = rng.normal(size=LN.NPARAM).astype(np.float32)
+        net.adam(torch.tensor(g).cuda(), lr=1e-3)
+        opt.step([ref], [g.astype(np.float64)])
+    got = net.numpy().astype(np.float64)
+    assert np.abs(got - ref).max() <= 1e-6 * max(1.0, np.abs(ref).max())
+    # the packed copy follows the master weights
+    xg, xo = _inputs(2, 10)
+    out, _ = net.forward(xg)
+    Wn, bn = LN.split_params(net.numpy())
+    want = OL.forward([_bf16(w) for w in Wn], bn, xo)[4]
+    assert _rel(out.cpu().numpy().astype(np.float64), want) <= 1e-2
+
+
+def _pair(steps_c=40, L=64, n=128, seed=10003):
+    c, f = W.learned_pair_c5(seed, L=L, n_markers=n)
+    c.problem.math = W.MATH_FP64
+    f.problem.math = W.MATH_FP64
+    return c, f, steps_c
+
+
+SC = dict(in_scale=(1e3, 1e3, 1e3, 0.125), out_scale=1e-4)
+
+
+def test_band_tiles_and_patches_match_oracle(mods):
+    B, LN = mods
+    c, _, steps = _pair()
+    _say(f"band tiles + patches: coarse {c.problem.nx}^2, N={c.problem.n_markers}, {steps} steps")
+    sim = B.Sim([c.problem], [c.X0])
+    sim.step(steps)
+    band = LN.Band(sim)
+    sc = LN.make_scales(**SC)
+    band.find()
+    band.patches(sc)
+    f = sim.fields(B.F_DISTRIB)
+    X = sim.markers()[0]
+    feat, sd = OL.node_features(f, X)
+    want_tiles = OL.band_tiles(sd)
+    slots = band.slots()
+    got_tiles = [band.tile_of(s) for s in slots]
+    _say(f"  {len(got_tiles)} GPU tiles, {len(want_tiles)} oracle band tiles")
+    assert set(want_tiles) <= set(got_tiles)
+    assert got_tiles == sorted(got_tiles, key=lambda t: (t[1], t[0]))
+    inp = band.inp.float().cpu().numpy().astype(np.float64)
+    fl = band.flags.cpu().numpy()
+    scale = np.array(SC["in_scale"])
+    for s, (tx, ty) in zip(slots, got_tiles):
+        fo = OL.extract_patch(feat, tx, ty)
+        so = OL.extract_patch(sd, tx, ty)
+        g = inp[s] / scale
+        for ch in range(3):
+            assert np.all(np.abs(g[..., ch] - fo[..., ch]) <= 5e-3 * np.abs(fo[..., ch]) + 1e-9), (tx, ty, ch)
+        assert np.all(np.abs(g[..., 3] - fo[..., 3]) <= 5e-3 * np.abs(fo[..., 3]) + 1e-4)
+        away0 = np.abs(so) > 1e-4
+        assert np.array_equal((fl[s] & 1)[away0] == 1, (so < 0)[away0]), (tx, ty)
+        away4 = np.abs(np.abs(so) - 4.0) > 1e-4
+        assert np.array_equal((fl[s] & 2)[away4] == 2, (np.abs(so) <= 4.0)[away4]), (tx, ty)
+    sim.close()
+
+
+def test_targets_match_oracle(mods):
+    B, LN = mods
+    c, f, steps = _pair()
+    _say(f"targets: coarse {c.problem.nx}^2 x {steps} steps vs fine {f.problem.nx}^2 x {4 * steps}")
+    sc_ = B.Sim([c.problem], [c.X0])
+    sf = B.Sim([f.problem], [f.X0])
+    sc_.step(steps)
+    sf.step(4 * steps)
+    band = LN.Band(sc_)
+    sc = LN.make_scales(**SC)
+    band.find()
+    band.patches(sc)
+    tg, mk = band.targets(sf, sc)
+    fc, ff = sc_.fields(B.F_DISTRIB), sf.fields(B.F_DISTRIB)
+    want = OL.targets(fc, ff)
+    _, sd = OL.node_features(fc, sc_.markers()[0])
+    tg = tg.cpu().numpy().astype(np.float64) * SC["out_scale"]
+    mk = mk.cpu().numpy()
+    scale = np.abs(want).max()
+    n = 0
+    for s in band.slots():
+        tx, ty = band.tile_of(s)
+        wo = want[ty * 16:(ty + 1) * 16, tx * 16:(tx + 1) * 16]
+        so = sd[ty * 16:(ty + 1) * 16, tx * 16:(tx + 1) * 16]
+        m = mk[s].astype(bool)
+        away4 = np.abs(np.abs(so) - 4.0) > 1e-4
+        assert np.array_equal(m[away4], (np.abs(so) <= 4.0)[away4])
+        assert np.abs(tg[s][m] - wo[m]).max(initial=0.0) <= 1e-5 * scale
+        n += int(m.sum())
+    _say(f"  {n} band nodes, max |target| {scale:.3e}")
+    assert n > 100
+    sc_.close()
+    sf.close()
+
+
+def test_correction_matches_oracle(mods):
+    B, LN = mods
+    c, _, steps = _pair()
+    _say("fused correction (patches -> network -> masked add) vs oracle network on the same patches")
+    sim = B.Sim([c.problem], [c.X0])
+    sim.step(steps)
+    Wt, b = _params(11, bias=0.2)
+    net, Wq, bq = _net(LN, Wt, b)
+    band = LN.Band(sim)
+    sc = LN.make_scales(**SC)
+    f0 = sim.fields(B.F_DISTRIB)
+    band.correct(net, sc)
+    f1 = sim.fields(B.F_DISTRIB)
+    got = f1 - f0
+    inp = band.inp.float().cpu().numpy().astype(np.float64)
+    fl = band.flags.cpu().numpy()
+    slots = band.slots()
+    out = OL.forward(Wq, bq, inp[slots])[4] * SC["out_scale"]
+    ex, ey, _ = O.d2q9()
+    want = np.zeros_like(got)
+    for q, s in enumerate(slots):
+        tx, ty = band.tile_of(s)
+        for oy in range(16):
+            for ox in range(16):
+                fq = fl[s, oy + 4, ox + 4]
+                if not fq & 2:
+                    continue
+                for i in range(9):
+                    if i and (fl[s, oy + 4 - ey[i], ox + 4 - ex[i]] & 1) != (fq & 1):
+                        continue
+                    want[i, ty * 16 + oy, tx * 16 + ox] = out[q, oy, ox, i]
+    _say(f"  max |df| {np.abs(want).max():.3e}, rel L2 {_rel(got, want):.3e}")
+    assert np.array_equal(got == 0.0, want == 0.0)
+    assert _rel(got, want) <= 1e-2
+    assert np.abs(got - want).max() <= 3e-2 * np.abs(want).max()
+    sim.close()
+
+
+def test_training_reduces_the_loss(mods):
+    import torch
+    B, LN = mods
+    _say("training: 2 coarse/fine pairs 64^2/128^2, patches every 20 coarse steps, 150 Adam steps")
+    sc = LN.make_scales(**SC)
+    pairs = [W.learned_pair_c5(s, L=64, n_markers=128) for s in (0, 1)]
+    sc_ = B.Sim([p[0].problem for p in pairs], [p[0].X0 for p in pairs])
+    sf = B.Sim([p[1].problem for p in pairs], [p[1].X0 for p in pairs])
+    band = LN.Band(sc_)
+    X, T, M = [], [], []
+    for _ in range(5):
+        sc_.step(20)
+        sf.step(80)
+        band.find()
+        band.patches(sc)
+        tg, mk = band.targets(sf, sc)
+        sl = torch.tensor(band.slots(), device="cuda")
+        X.append(band.inp[sl].clone())
+        T.append(tg[sl].clone())
+        M.append(mk[sl].clone())
+    X, T, M = torch.cat(X), torch.cat(T), torch.cat(M)
+    Wt, b = OL.init_params(seed=12)
+    net = LN.Net(LN.flatten_params(Wt, b))
+    losses = []
+    for it in range(150):
+        out, sv = net.forward(X, save=True)
+        g, loss = net.backward(X, sv, out, T, M)
+        net.adam(g, lr=1e-3)
+        losses.append(loss.item())
+    _say(f"  {X.shape[0]} patches; loss {losses[0]:.4e} -> {losses[-1]:.4e}")
+    assert np.isfinite(losses).all()
+    assert losses[-1] < 0.5 * losses[0]
+    sc_.close()
+    sf.close()
