@@ -9,8 +9,10 @@
  *  - input channels per node: (rho - 1, u_x, u_y) of the pulled distributions
  *    (u = sum_i e_i f_i as in the method, Sec. 2.2.1) and the signed distance
  *    to the marker polygon (positive outside, clipped to [-8, 8]), each times
- *    a per-channel input scale;
- *  - output: nine population corrections df_i (times an output scale) added
+ *    a per-channel input scale; the three flow channels are then divided by
+ *    the patch amplitude s = max(rms over the patch of their vector, 1e-6);
+ *  - output: nine population corrections df_i (times the output scale and
+ *    s) added
  *    to the pre-collision f_i at nodes with |sd| <= 4, except on links whose
  *    two end nodes lie on different sides of the polygon;
  *  - training target: f^eq(rho_hat, u_hat) - f^eq(rho_c, u_c) (He-Luo
@@ -26,8 +28,8 @@
  * and return without waiting; errors are II_LBM_* codes from ii_lbm.h.
  * Patch tensors: input [n][24][24][4] BF16 (as uint16), flags [n][24][24]
  * uint8 (bit 0: inside the polygon, bit 1: |sd| <= 4), output / target
- * [n][16][16][9] FP32 (network units, i.e. before the output scale), mask
- * [n][16][16] uint8.
+ * [n][16][16][9] FP32 (network units, i.e. before the output scale and the
+ * patch amplitude), mask [n][16][16] uint8, patch amplitudes pscale[n] FP32.
  */
 #ifndef II_LEARNED_H
 #define II_LEARNED_H
@@ -93,14 +95,23 @@ int ii_lbm_learned_tiles(ii_lbm_handle* h, int32_t cap, int32_t* tiles, int32_t*
  * state. */
 int ii_lbm_learned_patches(ii_lbm_handle* h, const ii_cnn_scales* sc, int32_t cap,
                            const int32_t* tiles, const int32_t* count, uint16_t* in,
-                           uint8_t* flags);
+                           uint8_t* flags, float* pscale);
 
 /* Training targets of the listed tiles, coarse handle hc against fine
  * handle hf (same instance count, fine sides twice the coarse ones), in
  * network units, and the band mask taken from flags. */
 int ii_lbm_learned_targets(ii_lbm_handle* hc, ii_lbm_handle* hf, const ii_cnn_scales* sc,
                            int32_t cap, const int32_t* tiles, const int32_t* count,
-                           const uint8_t* flags, float* target, uint8_t* mask);
+                           const uint8_t* flags, const float* pscale, float* target,
+                           uint8_t* mask);
+
+/* The masked add of given corrections out[n][16][16][9] (network units) to
+ * the listed tiles of the handle's current state, with the band and side
+ * flags of ii_lbm_learned_patches (used, for instance, to apply the exact
+ * targets of a fine run as the ideal correction). */
+int ii_lbm_learned_apply(ii_lbm_handle* h, const ii_cnn_scales* sc, int32_t cap,
+                         const int32_t* tiles, const int32_t* count, const uint8_t* flags,
+                         const float* pscale, const float* out);
 
 /* The correction of one coarse step, in place on the handle's current
  * state: band tiles, patches of the uncorrected state, then the network and
@@ -108,7 +119,7 @@ int ii_lbm_learned_targets(ii_lbm_handle* hc, ii_lbm_handle* hf, const ii_cnn_sc
  * the shapes above (n_inst * cap slots). */
 int ii_lbm_learned_correct(ii_lbm_handle* h, const float* params, const void* packed,
                            const ii_cnn_scales* sc, int32_t cap, int32_t* tiles, int32_t* count,
-                           uint16_t* in, uint8_t* flags);
+                           uint16_t* in, uint8_t* flags, float* pscale);
 
 #ifdef __cplusplus
 }

@@ -183,6 +183,14 @@ def node_features(f: np.ndarray, X: np.ndarray):
     return feat, sd
 
 
+def patch_amplitude(feat_patch: np.ndarray, in_scale) -> float:
+    """s = max(rms over the patch nodes of |(rho - 1, u_x, u_y) * in_scale|, 1e-6):
+    the network sees the flow channels divided by s and its output is
+    multiplied back by s."""
+    v = feat_patch[..., :3] * np.asarray(in_scale[:3], dtype=np.float64)
+    return max(float(np.sqrt((v * v).sum(axis=-1).mean())), 1e-6)
+
+
 def band_tiles(sd: np.ndarray):
     """Tiles (tx, ty) of 16 x 16 nodes holding a band node (|sd| <= 4), in
     row-major tile order."""

@@ -371,8 +371,9 @@ __global__ void k_adam(float* __restrict__ prm, const float* __restrict__ grad,
 // ---------------------------------------------------------------------------
 // Band tiles, features and the fused correction
 // ---------------------------------------------------------------------------
-// One block per instance, one thread per tile: a tile is in the band when a
-// chord's box, grown by 4.5, meets the tile's node box.
+// One block per instance: every chord marks the tiles that its box, grown
+// by 4.5, meets (a tile is in the band when some chord does), then the marked
+// tiles are listed in row-major order.
 __global__ void k_band_tiles(const InstDev* __restrict__ insts, const double2* __restrict__ Xall,
                              int cap, int* __restrict__ tiles, int* __restrict__ count)
 {
@@ -382,16 +383,17 @@ __global__ void k_band_tiles(const InstDev* __restrict__ insts, const double2* _
     const int nt = I.tiles_x * I.tiles_y;
     const double2* X = Xall + I.mk_off;
     const int N = I.n_markers;
-    for (int t = threadIdx.x; t < nt; t += blockDim.x) {
-        const double x0 = (t % I.tiles_x) * kTile, y0 = (t / I.tiles_x) * kTile;
-        int hit = 0;
-        for (int k = 0; k < N && !hit; k++) {
-            const double2 a = X[k], b = X[(k + 1) % N];
-            const double lx = fmin(a.x, b.x) - 4.5, hx = fmax(a.x, b.x) + 4.5;
-            const double ly = fmin(a.y, b.y) - 4.5, hy = fmax(a.y, b.y) + 4.5;
-            hit = lx <= x0 + 15 && hx >= x0 && ly <= y0 + 15 && hy >= y0;
-        }
-        flag[t] = hit;
+    for (int t = threadIdx.x; t < nt; t += blockDim.x) flag[t] = 0;
+    __syncthreads();
+    for (int k = threadIdx.x; k < N; k += blockDim.x) {
+        const double2 a = X[k], b = X[(k + 1) % N];
+        // tile (tx, ty) covers nodes [16 tx, 16 tx + 15] x [16 ty, 16 ty + 15]
+        const int tx0 = max(0, (int)ceil((fmin(a.x, b.x) - 4.5 - 15.0) / kTile));
+        const int tx1 = min(I.tiles_x - 1, (int)floor((fmax(a.x, b.x) + 4.5) / kTile));
+        const int ty0 = max(0, (int)ceil((fmin(a.y, b.y) - 4.5 - 15.0) / kTile));
+        const int ty1 = min(I.tiles_y - 1, (int)floor((fmax(a.y, b.y) + 4.5) / kTile));
+        for (int ty = ty0; ty <= ty1; ty++)
+            for (int tx = tx0; tx <= tx1; tx++) flag[ty * I.tiles_x + tx] = 1;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -411,18 +413,23 @@ __global__ void k_band_tiles(const InstDev* __restrict__ insts, const double2* _
 
 struct PatchShared {
     float4 cand[kMaxCand];    // candidate chords, relative to the patch origin
+    float raw[kPatch * kPatch][3];  // scaled rho - 1, u_x, u_y
+    float red[256];
     int ncand, parity;
 };
 
-// Features of the 24 x 24 patch around tile (tx, ty) into LDS: BF16 input
-// (scaled) and flags (bit 0 inside, bit 1 band).  The sign comes from the
+// Features of the 24 x 24 patch around tile (tx, ty): BF16 input and flags
+// (bit 0 inside, bit 1 band).  The flow channels (times their input scales)
+// are divided by the patch amplitude s = max(rms over the patch of their
+// vector, 1e-6), returned in *pscale: the network sees amplitude-free flow
+// and its output is multiplied back by s.  The sign comes from the
 // parity of the crossings of the segment from a fixed interior point of the
 // tile to the node (the point's own side from a ray towards +x over all
 // chords); the distance from the chords that come within 8 of the patch.
 template <typename T>
 __device__ void build_patch(const InstDev& I, const T* __restrict__ A, const double2* __restrict__ X,
                             int tx, int ty, const ii_cnn_scales& sc, PatchShared& S, u16* in,
-                            uint8_t* flags)
+                            uint8_t* flags, float* pscale)
 {
     const int N = I.n_markers;
     const int ox = tx * kTile - kHalo, oy = ty * kTile - kHalo;  // patch origin node
@@ -484,12 +491,30 @@ __device__ void build_patch(const InstDev& I, const T* __restrict__ A, const dou
         pull<T, float>(I, A, gx, gy, d);
         float r, ux, uy;
         moments<float>(d, r, ux, uy);
-        in[q * 4 + 0] = to_bf16(r * sc.in_scale[0]);
-        in[q * 4 + 1] = to_bf16(ux * sc.in_scale[1]);
-        in[q * 4 + 2] = to_bf16(uy * sc.in_scale[2]);
+        S.raw[q][0] = r * sc.in_scale[0];
+        S.raw[q][1] = ux * sc.in_scale[1];
+        S.raw[q][2] = uy * sc.in_scale[2];
         in[q * 4 + 3] = to_bf16(sd * sc.in_scale[3]);
         flags[q] = (uint8_t)(ins | (dist <= kBand ? 2 : 0));
     }
+    __syncthreads();
+    float ss = 0.f;
+    for (int q = threadIdx.x; q < kPatch * kPatch; q += blockDim.x)
+        ss += S.raw[q][0] * S.raw[q][0] + S.raw[q][1] * S.raw[q][1] + S.raw[q][2] * S.raw[q][2];
+    S.red[threadIdx.x] = ss;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) S.red[threadIdx.x] += S.red[threadIdx.x + w];
+        __syncthreads();
+    }
+    const float amp = fmaxf(sqrtf(S.red[0] / (float)(kPatch * kPatch)), 1e-6f);
+    const float inv = 1.f / amp;
+    for (int q = threadIdx.x; q < kPatch * kPatch; q += blockDim.x) {
+        in[q * 4 + 0] = to_bf16(S.raw[q][0] * inv);
+        in[q * 4 + 1] = to_bf16(S.raw[q][1] * inv);
+        in[q * 4 + 2] = to_bf16(S.raw[q][2] * inv);
+    }
+    if (threadIdx.x == 0) *pscale = amp;
 }
 
 template <typename T>
@@ -497,7 +522,7 @@ __global__ __launch_bounds__(256) void k_patches(const InstDev* __restrict__ ins
                                                  const double2* __restrict__ Xall, ii_cnn_scales sc,
                                                  int cap, const int* __restrict__ tiles,
                                                  const int* __restrict__ count, u16* __restrict__ in,
-                                                 uint8_t* __restrict__ flags)
+                                                 uint8_t* __restrict__ flags, float* __restrict__ pscale)
 {
     const int inst = blockIdx.x / cap, r = blockIdx.x % cap;
     if (r >= count[inst]) return;
@@ -506,17 +531,19 @@ __global__ __launch_bounds__(256) void k_patches(const InstDev* __restrict__ ins
     const int2 t = ((const int2*)tiles)[blockIdx.x];
     const long long slot = blockIdx.x;
     build_patch<T>(I, (const T*)A0, Xall + I.mk_off, t.x, t.y, sc, S,
-                   in + slot * (kPatch * kPatch * 4), flags + slot * (kPatch * kPatch));
+                   in + slot * (kPatch * kPatch * 4), flags + slot * (kPatch * kPatch),
+                   pscale + slot);
 }
 
-// Targets: f^eq(rho_hat, u_hat) - f^eq(rho_c, u_c) in network units; the
+// Targets: f^eq(rho_hat, u_hat) - f^eq(rho_c, u_c) in network units (over
+// the output scale and the patch amplitude); the
 // band mask of the output pixels from the patch flags.
 template <typename TC, typename TF>
 __global__ void k_targets(const InstDev* __restrict__ ic, const void* Ac,
                           const InstDev* __restrict__ iff, const void* Af, float inv_out, int cap,
                           const int* __restrict__ tiles, const int* __restrict__ count,
-                          const uint8_t* __restrict__ flags, float* __restrict__ target,
-                          uint8_t* __restrict__ mask)
+                          const uint8_t* __restrict__ flags, const float* __restrict__ pscale,
+                          float* __restrict__ target, uint8_t* __restrict__ mask)
 {
     const int inst = blockIdx.x / cap, r = blockIdx.x % cap;
     if (r >= count[inst]) return;
@@ -537,12 +564,13 @@ __global__ void k_targets(const InstDev* __restrict__ ic, const void* Ac,
     vf *= 2.0;
     // He-Luo equilibrium deviations w_i [drho + 3 e.u + 4.5 (e.u)^2 - 1.5 u.u]
     float* tg = target + slot * (kOut * kOut * 9) + q * 9;
+    const double inv = (double)inv_out / (double)pscale[slot];
 #pragma unroll
     for (int i = 0; i < 9; i++) {
         const double ef = EX[i] * uf + EY[i] * vf, ec = EX[i] * uc + EY[i] * vc;
         const double a = WD[i] * (rf + 3.0 * ef + 4.5 * ef * ef - 1.5 * (uf * uf + vf * vf));
         const double b = WD[i] * (rc + 3.0 * ec + 4.5 * ec * ec - 1.5 * (uc * uc + vc * vc));
-        tg[i] = (float)((a - b) * (double)inv_out);
+        tg[i] = (float)((a - b) * inv);
     }
     const uint8_t fl = flags[slot * (kPatch * kPatch) + (oy + kHalo) * kPatch + ox + kHalo];
     mask[slot * (kOut * kOut) + q] = (fl & 2) ? 1 : 0;
@@ -558,7 +586,8 @@ __global__ __launch_bounds__(256) void k_correct(const InstDev* __restrict__ ins
                                                  int cap, const int* __restrict__ tiles,
                                                  const int* __restrict__ count,
                                                  const u16* __restrict__ in,
-                                                 const uint8_t* __restrict__ flags)
+                                                 const uint8_t* __restrict__ flags,
+                                                 const float* __restrict__ pscale)
 {
     const int inst = blockIdx.x / cap, r = blockIdx.x % cap;
     if (r >= count[inst]) return;
@@ -583,7 +612,7 @@ __global__ __launch_bounds__(256) void k_correct(const InstDev* __restrict__ ins
     hidden_layer<2>(bx, by, packed, prm, nullptr);
     __syncthreads();
     const float* b4 = prm + OFF_B[3];
-    const float os = sc.out_scale;
+    const float os = sc.out_scale * pscale[slot];
     T* base = A + I.lat_off;
     conv_mfma<18, 16, 32, 9, 1, false>(by, packed + FOFF[3], [&](int row, int c, float v) {
         if (c >= 9) return;
@@ -602,6 +631,35 @@ __global__ __launch_bounds__(256) void k_correct(const InstDev* __restrict__ ins
         T* p = base + c * I.plane + (long long)y * I.pitch + x;
         Store<T>::st(p, Store<T>::ld(p, I.scale) + os * (v + b4[c]), I.inv_scale);
     });
+}
+
+// The masked add of given corrections (network units), one block per slot.
+template <typename T>
+__global__ void k_apply(const InstDev* __restrict__ insts, void* A0, float out_scale, int cap,
+                        const int* __restrict__ tiles, const int* __restrict__ count,
+                        const uint8_t* __restrict__ flags, const float* __restrict__ pscale,
+                        const float* __restrict__ out)
+{
+    const int inst = blockIdx.x / cap, r = blockIdx.x % cap;
+    if (r >= count[inst]) return;
+    const InstDev I = insts[inst];
+    const int2 t = ((const int2*)tiles)[blockIdx.x];
+    const long long slot = blockIdx.x;
+    const int oy = threadIdx.x / kOut, ox = threadIdx.x % kOut;
+    const uint8_t* fl = flags + slot * (kPatch * kPatch);
+    const int q = (oy + kHalo) * kPatch + ox + kHalo;
+    const uint8_t f = fl[q];
+    if (!(f & 2)) return;
+    T* base = (T*)A0 + I.lat_off;
+    for (int c = 0; c < 9; c++) {
+        if (c != 0 && (fl[q - EY[c] * kPatch - EX[c]] & 1) != (f & 1)) continue;
+        int x = t.x * kTile + ox - EX[c], y = t.y * kTile + oy - EY[c];
+        x = x < 0 ? x + I.nx : (x >= I.nx ? x - I.nx : x);
+        y = y < 0 ? y + I.ny : (y >= I.ny ? y - I.ny : y);
+        T* p = base + c * I.plane + (long long)y * I.pitch + x;
+        const float d = out_scale * pscale[slot] * out[slot * (kOut * kOut * 9) + threadIdx.x * 9 + c];
+        Store<T>::st(p, Store<T>::ld(p, I.scale) + d, I.inv_scale);
+    }
 }
 
 // Learned correction needs periodic membranes on 16-multiples (the patches
@@ -699,28 +757,28 @@ int ii_lbm_learned_tiles(ii_lbm_handle* h, int32_t cap, int32_t* tiles, int32_t*
 
 int ii_lbm_learned_patches(ii_lbm_handle* h, const ii_cnn_scales* sc, int32_t cap,
                            const int32_t* tiles, const int32_t* count, uint16_t* in,
-                           uint8_t* flags)
+                           uint8_t* flags, float* pscale)
 {
     HandleView v;
     int rc = handle_view(h, &v);
     if (rc) return rc;
     if ((rc = check_learned(v))) return rc;
-    if (!sc || !tiles || !count || !in || !flags || cap < 1) return II_LBM_EINVAL;
+    if (!sc || !tiles || !count || !in || !flags || !pscale || cap < 1) return II_LBM_EINVAL;
     const dim3 grid((unsigned)(v.n_inst * cap));
     if (v.inst[0].storage == II_LBM_FP16)
         hipLaunchKernelGGL(k_patches<_Float16>, grid, dim3(256), 0, v.stream, v.d_inst,
                            v.P.lat[v.parity], v.P.X[v.parity], *sc, (int)cap, (const int*)tiles,
-                           (const int*)count, (u16*)in, flags);
+                           (const int*)count, (u16*)in, flags, pscale);
     else
         hipLaunchKernelGGL(k_patches<float>, grid, dim3(256), 0, v.stream, v.d_inst,
                            v.P.lat[v.parity], v.P.X[v.parity], *sc, (int)cap, (const int*)tiles,
-                           (const int*)count, (u16*)in, flags);
+                           (const int*)count, (u16*)in, flags, pscale);
     return err(hipGetLastError());
 }
 
 int ii_lbm_learned_targets(ii_lbm_handle* hc, ii_lbm_handle* hf, const ii_cnn_scales* sc,
                            int32_t cap, const int32_t* tiles, const int32_t* count,
-                           const uint8_t* flags, float* target, uint8_t* mask)
+                           const uint8_t* flags, const float* pscale, float* target, uint8_t* mask)
 {
     HandleView c, f;
     int rc = handle_view(hc, &c);
@@ -728,7 +786,8 @@ int ii_lbm_learned_targets(ii_lbm_handle* hc, ii_lbm_handle* hf, const ii_cnn_sc
     if ((rc = handle_view(hf, &f))) return rc;
     if ((rc = check_learned(c))) return rc;
     if ((rc = check_learned(f))) return rc;
-    if (!sc || !tiles || !count || !flags || !target || !mask || cap < 1 || !(sc->out_scale > 0.f))
+    if (!sc || !tiles || !count || !flags || !pscale || !target || !mask || cap < 1 ||
+        !(sc->out_scale > 0.f))
         return II_LBM_EINVAL;
     if (c.n_inst != f.n_inst) return II_LBM_EINVAL;
     for (int j = 0; j < c.n_inst; j++)
@@ -742,7 +801,7 @@ int ii_lbm_learned_targets(ii_lbm_handle* hc, ii_lbm_handle* hf, const ii_cnn_sc
 #define II_TARGETS(TC, TF)                                                                       \
     hipLaunchKernelGGL((k_targets<TC, TF>), grid, dim3(256), 0, c.stream, c.d_inst,              \
                        c.P.lat[c.parity], f.d_inst, f.P.lat[f.parity], inv, (int)cap,            \
-                       (const int*)tiles, (const int*)count, flags, target, mask)
+                       (const int*)tiles, (const int*)count, flags, pscale, target, mask)
     if (c16 && f16) II_TARGETS(_Float16, _Float16);
     else if (c16) II_TARGETS(_Float16, float);
     else if (f16) II_TARGETS(float, _Float16);
@@ -751,25 +810,46 @@ int ii_lbm_learned_targets(ii_lbm_handle* hc, ii_lbm_handle* hf, const ii_cnn_sc
     return err(hipGetLastError());
 }
 
+int ii_lbm_learned_apply(ii_lbm_handle* h, const ii_cnn_scales* sc, int32_t cap,
+                         const int32_t* tiles, const int32_t* count, const uint8_t* flags,
+                         const float* pscale, const float* out)
+{
+    HandleView v;
+    int rc = handle_view(h, &v);
+    if (rc) return rc;
+    if ((rc = check_learned(v))) return rc;
+    if (!sc || !tiles || !count || !flags || !pscale || !out || cap < 1) return II_LBM_EINVAL;
+    const dim3 grid((unsigned)(v.n_inst * cap));
+    if (v.inst[0].storage == II_LBM_FP16)
+        hipLaunchKernelGGL(k_apply<_Float16>, grid, dim3(256), 0, v.stream, v.d_inst,
+                           v.P.lat[v.parity], sc->out_scale, (int)cap, (const int*)tiles,
+                           (const int*)count, flags, pscale, out);
+    else
+        hipLaunchKernelGGL(k_apply<float>, grid, dim3(256), 0, v.stream, v.d_inst,
+                           v.P.lat[v.parity], sc->out_scale, (int)cap, (const int*)tiles,
+                           (const int*)count, flags, pscale, out);
+    return err(hipGetLastError());
+}
+
 int ii_lbm_learned_correct(ii_lbm_handle* h, const float* params, const void* packed,
                            const ii_cnn_scales* sc, int32_t cap, int32_t* tiles, int32_t* count,
-                           uint16_t* in, uint8_t* flags)
+                           uint16_t* in, uint8_t* flags, float* pscale)
 {
-    if (!params || !packed || !sc || !in || !flags) return II_LBM_EINVAL;
+    if (!params || !packed || !sc || !in || !flags || !pscale) return II_LBM_EINVAL;
     int rc = ii_lbm_learned_tiles(h, cap, tiles, count);
     if (rc) return rc;
-    if ((rc = ii_lbm_learned_patches(h, sc, cap, tiles, count, in, flags))) return rc;
+    if ((rc = ii_lbm_learned_patches(h, sc, cap, tiles, count, in, flags, pscale))) return rc;
     HandleView v;
     handle_view(h, &v);
     const dim3 grid((unsigned)(v.n_inst * cap));
     if (v.inst[0].storage == II_LBM_FP16)
         hipLaunchKernelGGL(k_correct<_Float16>, grid, dim3(256), 0, v.stream, v.d_inst,
                            v.P.lat[v.parity], params, (const u16*)packed, *sc, (int)cap,
-                           (const int*)tiles, (const int*)count, (const u16*)in, flags);
+                           (const int*)tiles, (const int*)count, (const u16*)in, flags, pscale);
     else
         hipLaunchKernelGGL(k_correct<float>, grid, dim3(256), 0, v.stream, v.d_inst,
                            v.P.lat[v.parity], params, (const u16*)packed, *sc, (int)cap,
-                           (const int*)tiles, (const int*)count, (const u16*)in, flags);
+                           (const int*)tiles, (const int*)count, (const u16*)in, flags, pscale);
     return err(hipGetLastError());
 }
 

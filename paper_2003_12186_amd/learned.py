@@ -22,7 +22,8 @@ _SHAPES = [(3, 3, 4, 32), (32,), (3, 3, 32, 32), (32,), (3, 3, 32, 32), (32,), (
 
 EXPORTS = ["ii_cnn_packed_bytes", "ii_cnn_pack", "ii_cnn_save_bytes", "ii_cnn_forward",
            "ii_cnn_work_bytes", "ii_cnn_backward", "ii_cnn_adam", "ii_lbm_learned_tiles",
-           "ii_lbm_learned_patches", "ii_lbm_learned_targets", "ii_lbm_learned_correct"]
+           "ii_lbm_learned_patches", "ii_lbm_learned_targets", "ii_lbm_learned_apply",
+           "ii_lbm_learned_correct"]
 
 
 class Scales(C.Structure):
@@ -54,9 +55,10 @@ def lib():
             "ii_cnn_backward": ([v, v, v, v, v, v, v, i32, v, v, v, v], C.c_int),
             "ii_cnn_adam": ([v, v, v, v, i32, C.c_float, v, v], C.c_int),
             "ii_lbm_learned_tiles": ([v, i32, v, v], C.c_int),
-            "ii_lbm_learned_patches": ([v, S, i32, v, v, v, v], C.c_int),
-            "ii_lbm_learned_targets": ([v, v, S, i32, v, v, v, v, v], C.c_int),
-            "ii_lbm_learned_correct": ([v, v, v, S, i32, v, v, v, v], C.c_int),
+            "ii_lbm_learned_patches": ([v, S, i32, v, v, v, v, v], C.c_int),
+            "ii_lbm_learned_targets": ([v, v, S, i32, v, v, v, v, v, v], C.c_int),
+            "ii_lbm_learned_apply": ([v, S, i32, v, v, v, v, v], C.c_int),
+            "ii_lbm_learned_correct": ([v, v, v, S, i32, v, v, v, v, v], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -160,6 +162,7 @@ class Band:
         self.count = torch.zeros(sim.n_inst, dtype=torch.int32, device=dev)
         self.inp = torch.zeros((n, PATCH, PATCH, 4), dtype=torch.bfloat16, device=dev)
         self.flags = torch.zeros((n, PATCH, PATCH), dtype=torch.uint8, device=dev)
+        self.pscale = torch.ones(n, dtype=torch.float32, device=dev)
 
     def find(self) -> None:
         B.check(lib().ii_lbm_learned_tiles(self.sim.h, self.cap, _p(self.tiles), _p(self.count)),
@@ -167,8 +170,8 @@ class Band:
 
     def patches(self, sc: Scales) -> None:
         B.check(lib().ii_lbm_learned_patches(self.sim.h, C.byref(sc), self.cap, _p(self.tiles),
-                                             _p(self.count), _p(self.inp), _p(self.flags)),
-                "ii_lbm_learned_patches")
+                                             _p(self.count), _p(self.inp), _p(self.flags),
+                                             _p(self.pscale)), "ii_lbm_learned_patches")
 
     def targets(self, fine: "B.Sim", sc: Scales):
         """(target float32 [n, 16, 16, 9], mask uint8 [n, 16, 16]) of the slots."""
@@ -177,14 +180,20 @@ class Band:
         tg = torch.zeros((n, TILE, TILE, 9), dtype=torch.float32, device=self.sim.device)
         mk = torch.zeros((n, TILE, TILE), dtype=torch.uint8, device=self.sim.device)
         B.check(lib().ii_lbm_learned_targets(self.sim.h, fine.h, C.byref(sc), self.cap, _p(self.tiles),
-                                             _p(self.count), _p(self.flags), _p(tg), _p(mk)),
-                "ii_lbm_learned_targets")
+                                             _p(self.count), _p(self.flags), _p(self.pscale), _p(tg),
+                                             _p(mk)), "ii_lbm_learned_targets")
         return tg, mk
+
+    def apply(self, out, sc: Scales) -> None:
+        """Masked add of given corrections (network units) to the listed tiles."""
+        B.check(lib().ii_lbm_learned_apply(self.sim.h, C.byref(sc), self.cap, _p(self.tiles),
+                                           _p(self.count), _p(self.flags), _p(self.pscale), _p(out)),
+                "ii_lbm_learned_apply")
 
     def correct(self, net: Net, sc: Scales) -> None:
         B.check(lib().ii_lbm_learned_correct(self.sim.h, _p(net.params), _p(net.packed), C.byref(sc),
                                              self.cap, _p(self.tiles), _p(self.count), _p(self.inp),
-                                             _p(self.flags)), "ii_lbm_learned_correct")
+                                             _p(self.flags), _p(self.pscale)), "ii_lbm_learned_correct")
 
     def slots(self):
         """Indices of the filled slots (host)."""

@@ -1,0 +1,282 @@
+"""Training data, training and evaluation of the learned coarse correction.
+
+Coarse/fine pairs are membrane runs of the config-3 generator at 256^2 and
+512^2 in diffusive scaling (``workloads.learned_pair_c5``); both advance on
+the GPU through the library, many instances per handle.  Training patches
+are the band tiles of the uncorrected coarse run at seeded snapshot steps,
+with the equilibrium-change targets of the fine run at the same physical
+time.  Evaluation runs held-out seeds three ways (fine, coarse, coarse with
+the correction after every coarse step) and compares the coarse velocity
+with the fine one restricted to the coarse nodes (times 2).
+
+    python -m paper_2003_12186_amd.train_learned --train 2000 --heldout 200 \
+        --out paper_2003_12186_amd/data/cnn_c5.npz
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import binding as B
+from . import learned as LN
+from . import workloads as W
+
+COARSE_STEPS = 2000
+FINE_PER_COARSE = 4
+
+
+def log(msg: str) -> None:
+    print(f"[learned] {msg}", flush=True)
+
+
+def _sims(seeds, L=256, n_markers=512):
+    pairs = [W.learned_pair_c5(s, L=L, n_markers=n_markers) for s in seeds]
+    sc = B.Sim([c.problem for c, _ in pairs], [c.X0 for c, _ in pairs])
+    sf = B.Sim([f.problem for _, f in pairs], [f.X0 for _, f in pairs])
+    return sc, sf
+
+
+def snapshot_steps(seed: int, k: int):
+    """k distinct coarse steps in [50, 2000], drawn from stream (5, seed)."""
+    rng = W.SplitMix64(5, seed)
+    out = set()
+    while len(out) < k:
+        out.add(50 + int(rng.uniform() * (COARSE_STEPS - 50)))
+    return sorted(out)
+
+
+def generate(seeds, sc: LN.Scales, per_seed: int = 4, batch: int = 128, L: int = 256,
+             n_markers: int = 512):
+    """Patches, targets and masks (device tensors) of the band tiles of the
+    uncorrected coarse runs at `per_seed` snapshot steps per seed.  All
+    instances of a batch share the union of their snapshot steps; a seed
+    keeps only its own."""
+    import torch
+    X, T, M = [], [], []
+    seeds = list(seeds)
+    for b0 in range(0, len(seeds), batch):
+        sb = seeds[b0:b0 + batch]
+        t0 = time.perf_counter()
+        sc_, sf = _sims(sb, L, n_markers)
+        sc_.set_graph(True)
+        sf.set_graph(True)
+        band = LN.Band(sc_)
+        want = {s: set(snapshot_steps(s, per_seed)) for s in sb}
+        stops = sorted(set().union(*want.values()))
+        now = 0
+        for st in stops:
+            sc_.step(st - now)
+            sf.step(FINE_PER_COARSE * (st - now))
+            now = st
+            band.find()
+            band.patches(sc)
+            tg, mk = band.targets(sf, sc)
+            cnt = band.count.cpu().numpy()
+            keep = [j * band.cap + r for j, s in enumerate(sb) if st in want[s] for r in range(int(cnt[j]))]
+            if keep:
+                idx = torch.tensor(keep, device=band.inp.device)
+                X.append(band.inp[idx].clone())
+                T.append(tg[idx].clone())
+                M.append(mk[idx].clone())
+        sc_.sync()
+        sf.sync()
+        sc_.close()
+        sf.close()
+        log(f"seeds {sb[0]}..{sb[-1]}: {sum(x.shape[0] for x in X)} patches so far "
+            f"({time.perf_counter() - t0:.1f} s)")
+    return torch.cat(X), torch.cat(T), torch.cat(M)
+
+
+IN_SCALE = (1.0, 3.0 ** 0.5, 3.0 ** 0.5, 0.125)
+
+
+def fit_scales(seeds, per_seed=2, L=256, n_markers=512) -> LN.Scales:
+    """Fixed input scales (rho - 1 against sqrt(3) u, the acoustic balance
+    c_s drho = u, and sd / 8) and the output scale: the standard deviation
+    of the band targets over the patch amplitude, from a few seeds."""
+    unit = LN.make_scales(IN_SCALE, 1.0)
+    _, T, M = generate(seeds, unit, per_seed=per_seed, batch=len(seeds), L=L, n_markers=n_markers)
+    s_out = max(float(T[M.bool()].std()), 1e-12)
+    return LN.make_scales(IN_SCALE, s_out)
+
+
+def fit(X, T, M, steps: int, batch: int = 512, lr: float = 1e-3, seed: int = 0, log_every: int = 500,
+        init=None):
+    """Adam on random mini-batches of patches; returns the network and the
+    loss history (one value per step)."""
+    import torch
+    from .learned import Net
+    n = X.shape[0]
+    p0 = init if init is not None else he_init(seed)
+    net = Net(p0)
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    hist = []
+    t0 = time.perf_counter()
+    for it in range(steps):
+        idx = torch.randint(0, n, (min(batch, n),), generator=g).to(X.device)
+        xb, tb, mb = X[idx], T[idx], M[idx]
+        out, sv = net.forward(xb, save=True)
+        grad, loss = net.backward(xb, sv, out, tb, mb)
+        net.adam(grad, lr=lr)
+        hist.append(loss)
+        if (it + 1) % log_every == 0:
+            ls = torch.stack(hist[-log_every:]).mean().item()
+            log(f"step {it + 1}/{steps}: loss {ls:.4e} ({time.perf_counter() - t0:.1f} s)")
+    return net, torch.cat(hist).cpu().numpy()
+
+
+def he_init(seed: int) -> np.ndarray:
+    """He-normal weights (std sqrt(2 / fan_in)), zero biases, from stream
+    (5, 1000000 + seed)."""
+    rng = W.SplitMix64(5, 1000000 + seed)
+    parts = []
+    for ci, co in zip(LN.CHANNELS[:-1], LN.CHANNELS[1:]):
+        parts.append(rng.normal_array(9 * ci * co) * np.sqrt(2.0 / (9 * ci)))
+        parts.append(np.zeros(co))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def _err(sc_, sf, j):
+    gc = sc_.fields(B.F_UX | B.F_UY, inst=j)
+    gf = sf.fields(B.F_UX | B.F_UY, inst=j)
+    r = 2.0 * gf[:, ::2, ::2]
+    return float(np.sqrt(((gc - r) ** 2).sum() / (r ** 2).sum()))
+
+
+def heldout_loss(net, sc: LN.Scales, seeds, per_seed: int = 4):
+    """One-step metric on held-out seeds: masked MSE of the network against
+    the targets, and of the zero correction (the method without it)."""
+    X, T, M = generate(seeds, sc, per_seed=per_seed, batch=len(seeds))
+    out, _ = net.forward(X)
+    m = M.unsqueeze(-1).float()
+    den = 9.0 * float(M.sum().item())
+    return (float((m * (out - T) ** 2).sum().item()) / den, float((m * T ** 2).sum().item()) / den)
+
+
+def evaluate(net, sc: LN.Scales, seeds, L: int = 256, n_markers: int = 512, checkpoints=(500, 1000, 2000),
+             alpha: float = 1.0):
+    """Per-seed relative L2 velocity error of the coarse run against the fine
+    one, without and with the correction (times `alpha`), and the wall time
+    of each run (all seeds batched in one handle, HIP graphs for the plain
+    runs)."""
+    sc = LN.make_scales(list(sc.in_scale), sc.out_scale * alpha)
+    import torch
+    seeds = list(seeds)
+    res = {"seeds": seeds, "checkpoints": list(checkpoints)}
+    # fine reference
+    pairs = [W.learned_pair_c5(s, L=L, n_markers=n_markers) for s in seeds]
+    sf = B.Sim([f.problem for _, f in pairs], [f.X0 for _, f in pairs])
+    sp = B.Sim([c.problem for c, _ in pairs], [c.X0 for c, _ in pairs])
+    sl = B.Sim([c.problem for c, _ in pairs], [c.X0 for c, _ in pairs])
+    band = LN.Band(sl)
+    for s in (sf, sp):
+        s.set_graph(True)
+    t_f = t_p = t_l = 0.0
+    now = 0
+    e_plain, e_learn = [], []
+    for cp in checkpoints:
+        n = cp - now
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sf.step(FINE_PER_COARSE * n)
+        sf.sync()
+        t_f += time.perf_counter() - t0
+        t0 = time.perf_counter()
+        sp.step(n)
+        sp.sync()
+        t_p += time.perf_counter() - t0
+        t0 = time.perf_counter()
+        if sl is not None:
+            try:
+                for _ in range(n):
+                    sl.step(1)
+                    band.correct(net, sc)
+                sl.sync()
+            except B.IILBMError as e:
+                log(f"corrected run failed before coarse step {cp}: {e}")
+                sl.close()
+                sl = None
+        t_l += time.perf_counter() - t0
+        now = cp
+        e_plain.append([_err(sp, sf, j) for j in range(len(seeds))])
+        e_learn.append([_err(sl, sf, j) if sl is not None else float("nan") for j in range(len(seeds))])
+        log(f"coarse step {cp}: median rel L2 plain {np.median(e_plain[-1]):.3e} "
+            f"learned {np.median(e_learn[-1]):.3e}")
+    res.update(err_plain=e_plain, err_learned=e_learn, t_fine=t_f, t_coarse=t_p,
+               t_coarse_learned=t_l, learned_stable=sl is not None)
+    for s in (sf, sp, sl):
+        if s is not None:
+            s.close()
+    return res
+
+
+def main(argv=None) -> int:
+    import torch
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train", type=int, default=2000, help="training seeds 0..n-1")
+    ap.add_argument("--heldout", type=int, default=200, help="held-out seeds 10000..")
+    ap.add_argument("--per-seed", type=int, default=4)
+    ap.add_argument("--steps", type=int, default=6000)
+    ap.add_argument("--batch", type=int, default=512)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--gen-batch", type=int, default=128)
+    ap.add_argument("--out", default=os.path.join(os.path.dirname(__file__), "data", "cnn_c5.npz"))
+    ap.add_argument("--report", default=None, help="JSON summary path")
+    ap.add_argument("--alpha", type=float, nargs="*", default=[1.0],
+                    help="evaluate the correction scaled by each factor")
+    a = ap.parse_args(argv)
+    B.load()
+    LN.lib()
+    t0 = time.perf_counter()
+    sc = fit_scales(range(a.train)[:8])
+    log(f"scales in {list(sc.in_scale)} out {sc.out_scale:.3e}")
+    X, T, M = generate(range(a.train), sc, per_seed=a.per_seed, batch=a.gen_batch)
+    t_gen = time.perf_counter() - t0
+    log(f"{X.shape[0]} training patches, {int(M.sum().item())} band nodes ({t_gen:.1f} s)")
+    t1 = time.perf_counter()
+    net, hist = fit(X, T, M, a.steps, batch=a.batch, lr=a.lr)
+    t_train = time.perf_counter() - t1
+    del X, T, M
+    torch.cuda.empty_cache()
+    os.makedirs(os.path.dirname(a.out), exist_ok=True)
+    np.savez(a.out, params=net.numpy(), in_scale=np.array(list(sc.in_scale), np.float32),
+             out_scale=np.float32(sc.out_scale), loss=hist.astype(np.float32),
+             meta=json.dumps({"train_seeds": a.train, "per_seed": a.per_seed, "steps": a.steps,
+                              "batch": a.batch, "lr": a.lr}))
+    log(f"saved {a.out}")
+    held = list(W.LEARNED_HELDOUT_SEEDS)[:a.heldout]
+    l_net, l_zero = heldout_loss(net, sc, held[:32])
+    log(f"held-out one-step loss: network {l_net:.4e}, no correction {l_zero:.4e}")
+    runs = {}
+    for al in a.alpha:
+        ev = evaluate(net, sc, held, alpha=al)
+        fin_p = np.array(ev["err_plain"][-1])
+        fin_l = np.array(ev["err_learned"][-1])
+        runs[str(al)] = {
+            "median_err_plain": [float(np.median(e)) for e in ev["err_plain"]],
+            "median_err_learned": [float(np.nanmedian(e)) if np.isfinite(e).any() else None
+                                   for e in ev["err_learned"]],
+            "checkpoints": ev["checkpoints"], "stable": ev["learned_stable"],
+            "frac_within_1e-2_learned": float((fin_l <= 1e-2).mean()),
+            "frac_improved": float((fin_l < fin_p).mean()),
+            "t_fine": ev["t_fine"], "t_coarse": ev["t_coarse"], "t_coarse_learned": ev["t_coarse_learned"],
+            "speedup_learned_vs_fine": ev["t_fine"] / ev["t_coarse_learned"],
+        }
+    summary = {"heldout": a.heldout, "heldout_loss_network": l_net, "heldout_loss_zero": l_zero,
+               "runs": runs, "t_generate": t_gen, "t_train": t_train,
+               "final_loss": float(hist[-200:].mean())}
+    ev = runs
+    log(json.dumps(summary))
+    if a.report:
+        with open(a.report, "w") as fh:
+            json.dump({"summary": summary, "eval": ev}, fh)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -175,11 +175,15 @@ def test_band_tiles_and_patches_match_oracle(mods):
     assert got_tiles == sorted(got_tiles, key=lambda t: (t[1], t[0]))
     inp = band.inp.float().cpu().numpy().astype(np.float64)
     fl = band.flags.cpu().numpy()
+    ps = band.pscale.cpu().numpy().astype(np.float64)
     scale = np.array(SC["in_scale"])
     for s, (tx, ty) in zip(slots, got_tiles):
         fo = OL.extract_patch(feat, tx, ty)
         so = OL.extract_patch(sd, tx, ty)
+        amp = OL.patch_amplitude(fo, scale)
+        assert abs(ps[s] - amp) <= 1e-4 * amp, (tx, ty, ps[s], amp)
         g = inp[s] / scale
+        g[..., :3] *= ps[s]
         for ch in range(3):
             assert np.all(np.abs(g[..., ch] - fo[..., ch]) <= 5e-3 * np.abs(fo[..., ch]) + 1e-9), (tx, ty, ch)
         assert np.all(np.abs(g[..., 3] - fo[..., 3]) <= 5e-3 * np.abs(fo[..., 3]) + 1e-4)
@@ -207,6 +211,7 @@ def test_targets_match_oracle(mods):
     want = OL.targets(fc, ff)
     _, sd = OL.node_features(fc, sc_.markers()[0])
     tg = tg.cpu().numpy().astype(np.float64) * SC["out_scale"]
+    tg *= band.pscale.cpu().numpy().astype(np.float64)[:, None, None, None]
     mk = mk.cpu().numpy()
     scale = np.abs(want).max()
     n = 0
@@ -243,6 +248,7 @@ def test_correction_matches_oracle(mods):
     fl = band.flags.cpu().numpy()
     slots = band.slots()
     out = OL.forward(Wq, bq, inp[slots])[4] * SC["out_scale"]
+    out *= band.pscale.cpu().numpy().astype(np.float64)[slots][:, None, None, None]
     ex, ey, _ = O.d2q9()
     want = np.zeros_like(got)
     for q, s in enumerate(slots):
@@ -297,3 +303,20 @@ def test_training_reduces_the_loss(mods):
     assert losses[-1] < 0.5 * losses[0]
     sc_.close()
     sf.close()
+
+
+def test_trained_network_gains_over_no_correction(mods):
+    # Ablation on held-out seeds with the committed weights: the one-step
+    # band error of the network against the fine run's targets, next to the
+    # error of applying no correction (the plain coarse method).
+    import os
+    _, LN = mods
+    from paper_2003_12186_amd import train_learned as TL
+    d = np.load(os.path.join(os.path.dirname(LN.__file__), "data", "cnn_c5.npz"))
+    net = LN.Net(d["params"])
+    sc = LN.make_scales(d["in_scale"], float(d["out_scale"]))
+    held = list(W.LEARNED_HELDOUT_SEEDS)[:8]
+    l_net, l_zero = TL.heldout_loss(net, sc, held, per_seed=2)
+    _say(f"held-out seeds {held[0]}..{held[-1]}: one-step band loss network {l_net:.4e} "
+         f"vs no correction {l_zero:.4e}")
+    assert l_net < 0.7 * l_zero

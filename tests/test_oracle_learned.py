@@ -208,3 +208,15 @@ def test_apply_correction_skips_cut_links_and_non_band_nodes():
             assert changed == (band[y, x] and (i == 0 or src_in == (sd[y, x] < 0)))
     # across the membrane some populations must be left alone
     assert (g[:, band] == 1.0).any() and (g[:, band] == 1.5).any()
+
+
+def test_patch_amplitude_closed_forms():
+    p = np.zeros((24, 24, 4))
+    assert L.patch_amplitude(p, (1e3, 1e3, 1e3, 0.1)) == 1e-6
+    p[..., 0] = 2e-4
+    p[..., 1] = -3e-4
+    p[..., 3] = 7.0                       # the distance channel does not count
+    want = np.sqrt((0.2 ** 2 + 0.3 ** 2))
+    assert math.isclose(L.patch_amplitude(p, (1e3, 1e3, 1e3, 0.1)), want, rel_tol=1e-14)
+    p[:12, :, :3] = 0.0                   # half the nodes at rest
+    assert math.isclose(L.patch_amplitude(p, (1e3, 1e3, 1e3, 0.1)), want / np.sqrt(2), rel_tol=1e-14)
