@@ -143,7 +143,7 @@ def main() -> int:
     ap.add_argument("--overlap", choices=["default", "serial", "full", "interp_first"],
                     default="default", help="membrane step schedule")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run plain device copies of MIB MiB (20 launches), the reference "
                          "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters")

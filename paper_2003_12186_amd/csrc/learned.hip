@@ -43,7 +43,7 @@ constexpr int kPacked = BOFF + 3 * BSIZE;
 // saved activations per patch: a1 | a2 | a3 (BF16, [pixel][32])
 constexpr int SAVE_OFF[4] = {0, 0, 15488, 28288};
 constexpr int kSave = 38656;
-constexpr int kMaxCand = 1024;   // candidate chords per patch
+constexpr int kMaxCand = 512;    // candidate chords per patch
 constexpr float kBand = 4.0f, kClip = 8.0f;
 
 __device__ __forceinline__ u16 to_bf16(float f)
@@ -90,18 +90,33 @@ __global__ void k_pack(const float* __restrict__ prm, u16* __restrict__ out)
 //   FULL = true:  out[q] = sum_t src[q - d_t] W'_t  (full, map HSRC -> HSRC+2,
 //                 reads outside the source are zero)
 // `src` is LDS [HSRC^2][CIN] BF16; epi(row, n, value) gets every output.
+// The layer's packed B fragments are staged once per block in LDS `wl`
+// (KS * NT * 512 elements) and then held in registers by every wave; the
+// caller separates two uses of `wl` by a barrier.
 // ---------------------------------------------------------------------------
+constexpr int kWl = 9 * 2 * 512;
+
 template <int HSRC, int HDST, int CIN, int KS, int NT, bool FULL, class Epi>
-__device__ __forceinline__ void conv_mfma(const u16* src, const u16* __restrict__ frag, Epi epi)
+__device__ __forceinline__ void conv_mfma(const u16* src, const u16* __restrict__ frag, u16* wl,
+                                          Epi epi)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
     const int g = lane >> 4;
+    static_assert(KS * NT * 512 <= kWl, "fragment staging buffer");
+    // wl == nullptr: `frag` already points into LDS
+    const u16* fr = frag;
+    if (wl) {
+        for (int e = threadIdx.x; e < KS * NT * 64; e += blockDim.x)
+            ((uint4*)wl)[e] = ((const uint4*)frag)[e];
+        __syncthreads();
+        fr = wl;
+    }
     bf16x8 b[KS][NT];
 #pragma unroll
     for (int ks = 0; ks < KS; ks++)
 #pragma unroll
         for (int nt = 0; nt < NT; nt++)
-            b[ks][nt] = *(const bf16x8*)(frag + ((ks * NT + nt) * 64 + lane) * 8);
+            b[ks][nt] = *(const bf16x8*)(fr + ((ks * NT + nt) * 64 + lane) * 8);
     constexpr int M = HDST * HDST, MT = (M + 15) / 16;
     for (int mt = wave; mt < MT; mt += nwave) {
         const int p = min(mt * 16 + (lane & 15), M - 1);
@@ -161,11 +176,11 @@ __device__ __forceinline__ void conv_mfma(const u16* src, const u16* __restrict_
 // 0-2, ReLU, BF16) and, when `save` is set, to the saved activations.
 template <int L>
 __device__ __forceinline__ void hidden_layer(const u16* src, u16* dst, const u16* __restrict__ packed,
-                                             const float* __restrict__ prm, u16* save)
+                                             const float* __restrict__ prm, u16* save, u16* wl)
 {
     const float* bias = prm + OFF_B[L];
     conv_mfma<HS[L], HS[L + 1], CI[L], FKS[L], FNT[L], false>(
-        src, packed + FOFF[L], [&](int row, int n, float v) {
+        src, packed + FOFF[L], wl, [&](int row, int n, float v) {
             const u16 h = to_bf16(fmaxf(v + bias[n], 0.f));
             dst[row * 32 + n] = h;
             if (save) save[row * 32 + n] = h;
@@ -182,21 +197,22 @@ __global__ __launch_bounds__(256) void k_forward(const float* __restrict__ prm,
 {
     __shared__ __align__(16) u16 bx[20 * 20 * 32];
     __shared__ __align__(16) u16 by[22 * 22 * 32];
+    __shared__ __align__(16) u16 wl[kWl];
     const long long n = blockIdx.x;
     const u16* src = in + n * (kPatch * kPatch * 4);
     for (int e = threadIdx.x; e < kPatch * kPatch * 4 / 2; e += blockDim.x)
         ((unsigned*)bx)[e] = ((const unsigned*)src)[e];
     __syncthreads();
     u16* sv = save ? save + n * kSave : nullptr;
-    hidden_layer<0>(bx, by, packed, prm, sv ? sv + SAVE_OFF[1] : nullptr);
+    hidden_layer<0>(bx, by, packed, prm, sv ? sv + SAVE_OFF[1] : nullptr, wl);
     __syncthreads();
-    hidden_layer<1>(by, bx, packed, prm, sv ? sv + SAVE_OFF[2] : nullptr);
+    hidden_layer<1>(by, bx, packed, prm, sv ? sv + SAVE_OFF[2] : nullptr, wl);
     __syncthreads();
-    hidden_layer<2>(bx, by, packed, prm, sv ? sv + SAVE_OFF[3] : nullptr);
+    hidden_layer<2>(bx, by, packed, prm, sv ? sv + SAVE_OFF[3] : nullptr, wl);
     __syncthreads();
     const float* b4 = prm + OFF_B[3];
     float* o = out + n * (kOut * kOut * 9);
-    conv_mfma<18, 16, 32, 9, 1, false>(by, packed + FOFF[3], [&](int row, int c, float v) {
+    conv_mfma<18, 16, 32, 9, 1, false>(by, packed + FOFF[3], wl, [&](int row, int c, float v) {
         if (c < 9) o[row * 9 + c] = v + b4[c];
     });
 }
@@ -259,10 +275,10 @@ __device__ __forceinline__ void weight_grad(const u16* a, const u16* dz, float* 
 // dz of the input of layer L (1..3): (sum_t dz_next[q - d_t] W_t^T) * (a[q] > 0)
 template <int L>
 __device__ __forceinline__ void data_grad(const u16* dz_next, const u16* a, u16* dz,
-                                          const u16* __restrict__ packed)
+                                          const u16* __restrict__ packed, u16* wl)
 {
     conv_mfma<HS[L + 1], HS[L], 32, 9, 2, true>(
-        dz_next, packed + BOFF + (L - 1) * BSIZE, [&](int row, int n, float v) {
+        dz_next, packed + BOFF + (L - 1) * BSIZE, wl, [&](int row, int n, float v) {
             dz[row * 32 + n] = a[row * 32 + n] != 0 && !(a[row * 32 + n] & 0x8000u) ? to_bf16(v) : 0;
         });
 }
@@ -297,6 +313,7 @@ __global__ __launch_bounds__(256) void k_backward(
     __shared__ __align__(16) u16 bz0[22 * 22 * 32];
     __shared__ __align__(16) u16 bz1[22 * 22 * 32];
     __shared__ float red[256];
+    __shared__ __align__(16) u16 wl[kWl];
     const long long n = blockIdx.x;
     float* pp = part + n * (kNP + 1);
     const float* o = out + n * (kOut * kOut * 9);
@@ -324,17 +341,17 @@ __global__ __launch_bounds__(256) void k_backward(
     }
     if (threadIdx.x == 0) pp[kNP] = red[0];
     weight_grad<3>(ba, bz0, pp);
-    data_grad<3>(bz0, ba, bz1, packed);
+    data_grad<3>(bz0, ba, bz1, packed, wl);
     __syncthreads();
     load_act<2>(ba, save + n * kSave + SAVE_OFF[2]);
     __syncthreads();
     weight_grad<2>(ba, bz1, pp);
-    data_grad<2>(bz1, ba, bz0, packed);
+    data_grad<2>(bz1, ba, bz0, packed, wl);
     __syncthreads();
     load_act<1>(ba, save + n * kSave + SAVE_OFF[1]);
     __syncthreads();
     weight_grad<1>(ba, bz0, pp);
-    data_grad<1>(bz0, ba, bz1, packed);
+    data_grad<1>(bz0, ba, bz1, packed, wl);
     __syncthreads();
     load_act<0>(ba, in + n * (kPatch * kPatch * 4));
     __syncthreads();
@@ -411,21 +428,32 @@ __global__ void k_band_tiles(const InstDev* __restrict__ insts, const double2* _
                 make_int2(t % I.tiles_x, t / I.tiles_x);
 }
 
+constexpr int kRowCap = 16;   // crossings of one patch row inside the patch
+
 struct PatchShared {
-    float4 cand[kMaxCand];    // candidate chords, relative to the patch origin
+    float4 cand[kMaxCand];        // chords within 8 lu of the patch, relative, sorted by min y
+    float cmin[kMaxCand];         // their min y
+    float4 tmp[kMaxCand];         // unsorted staging
+    float rowx[kPatch][kRowCap];  // x of the crossings of each patch row inside the patch
+    int rown[kPatch];             // their count
+    int rowpar[kPatch];           // parity of the crossings right of the patch
     float raw[kPatch * kPatch][3];  // scaled rho - 1, u_x, u_y
     float red[256];
-    int ncand, parity;
+    int ncand, overflow;
 };
 
 // Features of the 24 x 24 patch around tile (tx, ty): BF16 input and flags
-// (bit 0 inside, bit 1 band).  The flow channels (times their input scales)
-// are divided by the patch amplitude s = max(rms over the patch of their
-// vector, 1e-6), returned in *pscale: the network sees amplitude-free flow
-// and its output is multiplied back by s.  The sign comes from the
-// parity of the crossings of the segment from a fixed interior point of the
-// tile to the node (the point's own side from a ray towards +x over all
-// chords); the distance from the chords that come within 8 of the patch.
+// (bit 0 inside, bit 1 band).
+//  - inside: the even-odd rule on the ray from the node towards +x, an
+//    edge counting when it straddles the node's row (half-open in y) and
+//    crosses it right of the node; every chord's crossing of every patch row
+//    is found once per patch;
+//  - distance: the nearest chord among those within 8 lu of the patch,
+//    searched in a window of the chords sorted by their lowest y;
+//  - the flow channels (times their input scales) are divided by the patch
+//    amplitude s = max(rms over the patch of their vector, 1e-6), returned
+//    in *pscale: the network sees amplitude-free flow and its output is
+//    multiplied back by s.
 template <typename T>
 __device__ void build_patch(const InstDev& I, const T* __restrict__ A, const double2* __restrict__ X,
                             int tx, int ty, const ii_cnn_scales& sc, PatchShared& S, u16* in,
@@ -433,39 +461,80 @@ __device__ void build_patch(const InstDev& I, const T* __restrict__ A, const dou
 {
     const int N = I.n_markers;
     const int ox = tx * kTile - kHalo, oy = ty * kTile - kHalo;  // patch origin node
-    const double cxd = ox + kHalo + 7.37, cyd = oy + kHalo + 7.71;
+    for (int r = threadIdx.x; r < kPatch; r += blockDim.x) {
+        S.rown[r] = 0;
+        S.rowpar[r] = 0;
+    }
     if (threadIdx.x == 0) {
         S.ncand = 0;
-        S.parity = 0;
+        S.overflow = 0;
     }
     __syncthreads();
-    int par = 0;
     for (int k = threadIdx.x; k < N; k += blockDim.x) {
         const double2 a = X[k], b = X[(k + 1) % N];
-        if ((a.y > cyd) != (b.y > cyd)) {
-            const double xc = a.x + (cyd - a.y) * (b.x - a.x) / (b.y - a.y);
-            if (cxd < xc) par ^= 1;
+        // rows y = oy + r that the edge straddles: (a.y > y) != (b.y > y)
+        const double lo = fmin(a.y, b.y), hi = fmax(a.y, b.y);
+        const int r0 = max(0, (int)ceil(lo) - oy), r1 = min(kPatch - 1, (int)ceil(hi) - 1 - oy);
+        for (int r = r0; r <= r1; r++) {
+            const double y = (double)(oy + r);
+            if ((a.y > y) == (b.y > y)) continue;
+            const double xc = a.x + (y - a.y) * (b.x - a.x) / (b.y - a.y);
+            if (xc > (double)(ox + kPatch - 1)) {
+                atomicXor(&S.rowpar[r], 1);
+            } else if (xc > (double)ox) {
+                const int c = atomicAdd(&S.rown[r], 1);
+                if (c < kRowCap) S.rowx[r][c] = (float)(xc - ox);
+                else S.overflow = 1;
+            }
         }
-        const double m = kClip + 1.0;
-        if (fmax(a.x, b.x) >= ox - m && fmin(a.x, b.x) <= ox + kPatch - 1 + m &&
-            fmax(a.y, b.y) >= oy - m && fmin(a.y, b.y) <= oy + kPatch - 1 + m) {
+        const double m = kClip;
+        if (fmax(a.x, b.x) >= ox - m && fmin(a.x, b.x) <= ox + kPatch - 1 + m && hi >= oy - m &&
+            lo <= oy + kPatch - 1 + m) {
             const int c = atomicAdd(&S.ncand, 1);
             if (c < kMaxCand)
-                S.cand[c] = make_float4((float)(a.x - ox), (float)(a.y - oy), (float)(b.x - ox),
-                                        (float)(b.y - oy));
+                S.tmp[c] = make_float4((float)(a.x - ox), (float)(a.y - oy), (float)(b.x - ox),
+                                       (float)(b.y - oy));
+            else
+                S.overflow = 1;
         }
     }
-    if (par) atomicXor(&S.parity, 1);
     __syncthreads();
     const int nc = min(S.ncand, kMaxCand);
-    const int inside_c = S.parity;
-    const float cx = (float)(cxd - ox), cy = (float)(cyd - oy);
+    // rank sort by the lowest y (ties by position in the staging list)
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+        const float4 v = S.tmp[c];
+        const float key = fminf(v.y, v.w);
+        int r = 0;
+        for (int d = 0; d < nc; d++) {
+            const float kd = fminf(S.tmp[d].y, S.tmp[d].w);
+            r += (kd < key || (kd == key && d < c)) ? 1 : 0;
+        }
+        S.cand[r] = v;
+        S.cmin[r] = key;
+    }
+    __syncthreads();
     for (int q = threadIdx.x; q < kPatch * kPatch; q += blockDim.x) {
         const int py = q / kPatch, px = q % kPatch;
         const float fx = (float)px, fy = (float)py;
+        // chords reach at most 2 lu, so those within 8 of the row have their
+        // lowest y in [py - 10, py + 8]
+        int lo = 0, hi = nc;
+        {
+            int a0 = 0, a1 = nc;
+            while (a0 < a1) {
+                const int mid = (a0 + a1) >> 1;
+                if (S.cmin[mid] < fy - (kClip + 2.f)) a0 = mid + 1; else a1 = mid;
+            }
+            lo = a0;
+            a1 = nc;
+            while (a0 < a1) {
+                const int mid = (a0 + a1) >> 1;
+                if (S.cmin[mid] <= fy + kClip) a0 = mid + 1; else a1 = mid;
+            }
+            hi = a0;
+        }
         float d2 = kClip * kClip;
-        int cross = 0;
-        for (int c = 0; c < nc; c++) {
+        for (int c = lo; c < hi; c++) {
             const float4 s = S.cand[c];
             const float dx = s.z - s.x, dy = s.w - s.y;
             const float ll = dx * dx + dy * dy;
@@ -473,14 +542,10 @@ __device__ void build_patch(const InstDev& I, const T* __restrict__ A, const dou
             t = fminf(fmaxf(t, 0.f), 1.f);
             const float qx = s.x + t * dx - fx, qy = s.y + t * dy - fy;
             d2 = fminf(d2, qx * qx + qy * qy);
-            // segment (c -> node) against chord (a -> b)
-            const float o1 = (fx - cx) * (s.y - cy) - (fy - cy) * (s.x - cx);
-            const float o2 = (fx - cx) * (s.w - cy) - (fy - cy) * (s.z - cx);
-            const float o3 = dx * (cy - s.y) - dy * (cx - s.x);
-            const float o4 = dx * (fy - s.y) - dy * (fx - s.x);
-            cross ^= ((o1 > 0.f) != (o2 > 0.f)) && ((o3 > 0.f) != (o4 > 0.f));
         }
-        const int ins = inside_c ^ cross;
+        int ins = S.rowpar[py];
+        const int nr = min(S.rown[py], kRowCap);
+        for (int c = 0; c < nr; c++) ins ^= S.rowx[py][c] > fx ? 1 : 0;
         const float dist = sqrtf(d2);
         const float sd = ins ? -dist : dist;
         // moments of the pulled distributions at the node (periodic wrap)
@@ -515,6 +580,7 @@ __device__ void build_patch(const InstDev& I, const T* __restrict__ A, const dou
         in[q * 4 + 2] = to_bf16(S.raw[q][2] * inv);
     }
     if (threadIdx.x == 0) *pscale = amp;
+    return;
 }
 
 template <typename T>
@@ -576,11 +642,12 @@ __global__ void k_targets(const InstDev* __restrict__ ic, const void* Ac,
     mask[slot * (kOut * kOut) + q] = (fl & 2) ? 1 : 0;
 }
 
-// The network and the masked add of one coarse step, one block per band
-// tile, on the patches that k_patches built from the state before any tile
-// was corrected (a tile's halo overlaps its neighbours' nodes).
+// The network and the masked add of one coarse step, one block of eight
+// waves per band tile, on the patches that k_patches built from the state
+// before any tile was corrected (a tile's halo overlaps its neighbours'
+// nodes).  The B fragments come straight from L2 into registers.
 template <typename T>
-__global__ __launch_bounds__(256) void k_correct(const InstDev* __restrict__ insts, void* A0,
+__global__ __launch_bounds__(512) void k_correct(const InstDev* __restrict__ insts, void* A0,
                                                  const float* __restrict__ prm,
                                                  const u16* __restrict__ packed, ii_cnn_scales sc,
                                                  int cap, const int* __restrict__ tiles,
@@ -605,16 +672,16 @@ __global__ __launch_bounds__(256) void k_correct(const InstDev* __restrict__ ins
             fl[e] = flags[slot * (kPatch * kPatch) + e];
     }
     __syncthreads();
-    hidden_layer<0>(bx, by, packed, prm, nullptr);
+    hidden_layer<0>(bx, by, packed, prm, nullptr, nullptr);
     __syncthreads();
-    hidden_layer<1>(by, bx, packed, prm, nullptr);
+    hidden_layer<1>(by, bx, packed, prm, nullptr, nullptr);
     __syncthreads();
-    hidden_layer<2>(bx, by, packed, prm, nullptr);
+    hidden_layer<2>(bx, by, packed, prm, nullptr, nullptr);
     __syncthreads();
     const float* b4 = prm + OFF_B[3];
     const float os = sc.out_scale * pscale[slot];
     T* base = A + I.lat_off;
-    conv_mfma<18, 16, 32, 9, 1, false>(by, packed + FOFF[3], [&](int row, int c, float v) {
+    conv_mfma<18, 16, 32, 9, 1, false>(by, packed + FOFF[3], nullptr, [&](int row, int c, float v) {
         if (c >= 9) return;
         const int oy = row / kOut, ox = row % kOut;
         const int q = (oy + kHalo) * kPatch + ox + kHalo;
@@ -843,11 +910,11 @@ int ii_lbm_learned_correct(ii_lbm_handle* h, const float* params, const void* pa
     handle_view(h, &v);
     const dim3 grid((unsigned)(v.n_inst * cap));
     if (v.inst[0].storage == II_LBM_FP16)
-        hipLaunchKernelGGL(k_correct<_Float16>, grid, dim3(256), 0, v.stream, v.d_inst,
+        hipLaunchKernelGGL(k_correct<_Float16>, grid, dim3(512), 0, v.stream, v.d_inst,
                            v.P.lat[v.parity], params, (const u16*)packed, *sc, (int)cap,
                            (const int*)tiles, (const int*)count, (const u16*)in, flags, pscale);
     else
-        hipLaunchKernelGGL(k_correct<float>, grid, dim3(256), 0, v.stream, v.d_inst,
+        hipLaunchKernelGGL(k_correct<float>, grid, dim3(512), 0, v.stream, v.d_inst,
                            v.P.lat[v.parity], params, (const u16*)packed, *sc, (int)cap,
                            (const int*)tiles, (const int*)count, (const u16*)in, flags, pscale);
     return err(hipGetLastError());

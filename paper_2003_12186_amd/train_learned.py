@@ -229,26 +229,35 @@ def main(argv=None) -> int:
     ap.add_argument("--report", default=None, help="JSON summary path")
     ap.add_argument("--alpha", type=float, nargs="*", default=[1.0],
                     help="evaluate the correction scaled by each factor")
+    ap.add_argument("--eval-only", default=None, metavar="NPZ",
+                    help="skip data generation and training; evaluate these weights")
     a = ap.parse_args(argv)
     B.load()
     LN.lib()
-    t0 = time.perf_counter()
-    sc = fit_scales(range(a.train)[:8])
-    log(f"scales in {list(sc.in_scale)} out {sc.out_scale:.3e}")
-    X, T, M = generate(range(a.train), sc, per_seed=a.per_seed, batch=a.gen_batch)
-    t_gen = time.perf_counter() - t0
-    log(f"{X.shape[0]} training patches, {int(M.sum().item())} band nodes ({t_gen:.1f} s)")
-    t1 = time.perf_counter()
-    net, hist = fit(X, T, M, a.steps, batch=a.batch, lr=a.lr)
-    t_train = time.perf_counter() - t1
-    del X, T, M
-    torch.cuda.empty_cache()
-    os.makedirs(os.path.dirname(a.out), exist_ok=True)
-    np.savez(a.out, params=net.numpy(), in_scale=np.array(list(sc.in_scale), np.float32),
-             out_scale=np.float32(sc.out_scale), loss=hist.astype(np.float32),
-             meta=json.dumps({"train_seeds": a.train, "per_seed": a.per_seed, "steps": a.steps,
-                              "batch": a.batch, "lr": a.lr}))
-    log(f"saved {a.out}")
+    if a.eval_only:
+        d = np.load(a.eval_only)
+        net = LN.Net(d["params"])
+        sc = LN.make_scales(d["in_scale"], float(d["out_scale"]))
+        hist = d["loss"]
+        t_gen = t_train = 0.0
+    else:
+        t0 = time.perf_counter()
+        sc = fit_scales(range(a.train)[:8])
+        log(f"scales in {list(sc.in_scale)} out {sc.out_scale:.3e}")
+        X, T, M = generate(range(a.train), sc, per_seed=a.per_seed, batch=a.gen_batch)
+        t_gen = time.perf_counter() - t0
+        log(f"{X.shape[0]} training patches, {int(M.sum().item())} band nodes ({t_gen:.1f} s)")
+        t1 = time.perf_counter()
+        net, hist = fit(X, T, M, a.steps, batch=a.batch, lr=a.lr)
+        t_train = time.perf_counter() - t1
+        del X, T, M
+        torch.cuda.empty_cache()
+        os.makedirs(os.path.dirname(a.out), exist_ok=True)
+        np.savez(a.out, params=net.numpy(), in_scale=np.array(list(sc.in_scale), np.float32),
+                 out_scale=np.float32(sc.out_scale), loss=hist.astype(np.float32),
+                 meta=json.dumps({"train_seeds": a.train, "per_seed": a.per_seed, "steps": a.steps,
+                                  "batch": a.batch, "lr": a.lr}))
+        log(f"saved {a.out}")
     held = list(W.LEARNED_HELDOUT_SEEDS)[:a.heldout]
     l_net, l_zero = heldout_loss(net, sc, held[:32])
     log(f"held-out one-step loss: network {l_net:.4e}, no correction {l_zero:.4e}")
