@@ -131,8 +131,10 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--storage", choices=["fp32", "fp16"], default="fp32")
-    ap.add_argument("--math", choices=["fp32", "fp64"], default="fp64",
-                    help="collision arithmetic (storage keeps its own precision)")
+    ap.add_argument("--math", choices=["fp32", "fp64"], default=None,
+                    help="collision arithmetic (storage keeps its own precision); default FP64 "
+                         "for FP32 storage (its 1e-6 parity bar) and FP32 for FP16 storage "
+                         "(1e-3 bar)")
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--workload", choices=["membrane", "batch512"], default="membrane",
                     help="membrane: one L x L membrane (the bench line); batch512: 512 uneven "
@@ -148,6 +150,8 @@ def main() -> int:
                     help="only run plain device copies of MIB MiB (20 launches), the reference "
                          "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
+    if args.math is None:
+        args.math = "fp32" if args.storage == "fp16" else "fp64"
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the design notes describe how the lattice would shard).", file=sys.stderr)

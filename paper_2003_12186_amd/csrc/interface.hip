@@ -224,12 +224,12 @@ __device__ __forceinline__ void slot_reset_body(const InstDev& I, const DevPtrs&
     }
 }
 
-__global__ __launch_bounds__(1024) void k_slot_reset(InstDev I, DevPtrs P, int par)
+__global__ __launch_bounds__(256) void k_slot_reset(InstDev I, DevPtrs P, int par)
 {
     slot_reset_body(I, P, par);
 }
 
-__global__ __launch_bounds__(1024) void k_slot_reset_batch(const InstDev* __restrict__ insts,
+__global__ __launch_bounds__(64) void k_slot_reset_batch(const InstDev* __restrict__ insts,
                                                            DevPtrs P, int par)
 {
     const InstDev I = insts[blockIdx.x];
@@ -300,7 +300,7 @@ hipError_t launch_markers_batch(const Batch& b, const DevPtrs& P, const void* A,
 hipError_t launch_slot_reset(const InstDev& I, const DevPtrs& P, int par, hipStream_t s)
 {
     if (I.n_markers == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_slot_reset, dim3(1), dim3(1024), 0, s, I, P, par);
+    hipLaunchKernelGGL(k_slot_reset, dim3(1), dim3(256), 0, s, I, P, par);
     return hipGetLastError();
 }
 
@@ -308,7 +308,7 @@ hipError_t launch_slot_reset_batch(const Batch& b, int n_inst, const DevPtrs& P,
                                    hipStream_t s)
 {
     if (b.mk_units == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_slot_reset_batch, dim3(n_inst), dim3(1024), 0, s, b.insts, P, par);
+    hipLaunchKernelGGL(k_slot_reset_batch, dim3(n_inst), dim3(64), 0, s, b.insts, P, par);
     return hipGetLastError();
 }
 

@@ -116,3 +116,26 @@ def test_batch_rejects_mixed_storage(B):
     with pytest.raises(B.IILBMError) as e:
         B.Sim([w.problem for w in ws], [w.X0 for w in ws])
     assert e.value.code == B.EINVAL
+
+
+def test_batch_mixing_membranes_and_plain_fluid(B):
+    # Instances without an interface ride along in a membrane batch.
+    ws = _small_batch(2)
+    plain = W.Problem(nx=48, ny=80, tau=0.7, math=W.MATH_FP64)
+    probs = [ws[0].problem, plain, ws[1].problem]
+    X0 = [ws[0].X0, None, ws[1].X0]
+    _say("batch: membrane, plain 48x80 fluid, membrane; 120 steps")
+    sim = B.Sim(probs, X0)
+    f_plain = np.ascontiguousarray(
+        O.d2q9()[2][:, None, None] * (1.0 + 1e-3 * W.seeded_noise((9, 80, 48), 60, 0)))
+    sim.set_distrib(f_plain, inst=1)
+    sim.step(120)
+    for j, (p, x) in enumerate(zip(probs, X0)):
+        one = B.Sim([p], [x])
+        if j == 1:
+            one.set_distrib(f_plain)
+        one.step(120)
+        assert np.array_equal(sim.fields(B.F_DISTRIB, inst=j, dtype=np.float32),
+                              one.fields(B.F_DISTRIB, dtype=np.float32)), j
+        one.close()
+    sim.close()

@@ -279,3 +279,68 @@ def test_full_size_membrane4096_first_steps(B):
     d = sim.diag()
     assert d["error_bits"] == 0 and d["n_cut_links"] > 10000
     sim.close()
+
+
+def test_max_size_lattice_sampled_parity(B):
+    # The largest lattice the library accepts (8192 x 8192, 604 M stored
+    # values per buffer), one step from a structured state; every sampled node
+    # (edges included, where the pull wraps) against the oracle's collision of
+    # the nine upstream nodes.
+    _say("8192x8192 periodic bulk, 1 step, 96 sampled nodes vs oracle")
+    n = 8192
+    prob = W.Problem(nx=n, ny=n, tau=0.62, collision=W.SRT, body_force=(1e-6, -2e-6), math=W.MATH_FP64)
+    ex, ey, w = O.d2q9()
+    xs = np.arange(n, dtype=np.float64)
+    f0 = np.empty((9, n, n))
+    for i in range(9):
+        f0[i] = w[i] * (1.0 + 1e-3 * np.sin(2 * np.pi * (i + 1) * xs / n)[None, :]
+                        * np.cos(2 * np.pi * (9 - i) * xs / n + 0.3 * i)[:, None])
+    sim = B.Sim([prob], [None])
+    sim.set_distrib(f0)
+    sim.step(1)
+    g = sim.fields(B.F_DISTRIB, dtype=np.float32)
+    p = O.make_problem(prob)
+    rng = np.random.default_rng(12)
+    pts = [(0, 0), (n - 1, n - 1), (0, n - 1), (n - 1, 0), (n // 2, 0), (0, n // 2)]
+    pts += [(int(a), int(b)) for a, b in rng.integers(0, n, size=(90, 2))]
+    worst = 0.0
+    for x, y in pts:
+        for i in range(9):
+            sx, sy = (x - ex[i]) % n, (y - ey[i]) % n
+            want = O.collide_node(p, f0[:, sy, sx], 1e-6, -2e-6)[i]
+            worst = max(worst, abs(float(g[i, y, x]) - want))
+    _say(f"  max |df| over samples {worst:.3e}")
+    assert worst <= 2e-7            # FP32 storage of values near w_i (1e-1)
+    sim.close()
+
+
+def test_minimal_triangle_membrane(B):
+    # The smallest closed membrane (three markers, chords under 2 lu) in a
+    # 32 x 32 box: its cut links bit-exact, then 200 steps against the oracle.
+    # The flow here is nearly static (|u| ~ 2e-5) under a strong pressure jump,
+    # so FP32 storage rounding of the pressure-carrying deviations, not the
+    # method, sets the velocity error: the bar is 1e-5 relative L2 and the
+    # ratio is printed.
+    _say("triangle membrane (N = 3) 32x32: links, then 200 steps")
+    c = np.array([15.3, 16.1])
+    th = 0.2 + 2 * np.pi * np.arange(3) / 3
+    X = np.stack([c[0] + 1.05 * np.cos(th), c[1] + 1.05 * np.sin(th)], 1)
+    prob = W.Problem(nx=32, ny=32, tau=0.9, interface=W.IF_MEMBRANE, n_markers=3, kappa=0.02,
+                     dX=1.05 * np.sqrt(3.0), math=W.MATH_FP64)
+    p = O.make_problem(prob)
+    key = lambda r: sorted(zip(r["x"].tolist(), r["y"].tolist(), r["dir"].tolist(),
+                               r["sigma"].tolist(), r["seg"].tolist()))
+    sim = B.Sim([prob], [X])
+    got = sim.cutlinks()
+    assert len(got) > 10 and key(got) == key(O.cutlinks(p, X))
+    sim.step(200)
+    Xg = sim.markers()[0]
+    assert key(sim.cutlinks()) == key(O.cutlinks(p, Xg))
+    g = sim.fields(B.F_RHO | B.F_UX | B.F_UY)
+    o = _oracle_run(prob, X, 200)
+    err = _rel_l2(g[1], g[2], o["ux"], o["uy"])
+    dX = np.abs(Xg - o["X"]).max()
+    ratio = np.abs(o["rho"] - 1).max() / np.abs(np.stack([o["ux"], o["uy"]])).max()
+    _say(f"  rel L2 u = {err:.3e}  max |dX| = {dX:.3e}  max|rho-1| / max|u| = {ratio:.1f}")
+    assert err <= 1e-5 and dX <= 1e-6
+    sim.close()
