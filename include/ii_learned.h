@@ -15,9 +15,10 @@
  *    s) added
  *    to the pre-collision f_i at nodes with |sd| <= 4, except on links whose
  *    two end nodes lie on different sides of the polygon;
- *  - training target: f^eq(rho_hat, u_hat) - f^eq(rho_c, u_c) (He-Luo
- *    equilibrium, Sec. 2.2.1) with the fine run's moments at fine node
- *    (2x, 2y), rho_hat - 1 = 4 (rho_f - 1), u_hat = 2 u_f (diffusive scaling).
+ *  - training target: f^eq(rho_c, u_hat) - f^eq(rho_c, u_c) (He-Luo
+ *    equilibrium, Sec. 2.2.1): the change of the equilibrium that gives the
+ *    coarse node the fine run's velocity u_hat = 2 u_f at fine node (2x, 2y)
+ *    (diffusive scaling) at unchanged density.
  *
  * Parameters are one FP32 array of II_CNN_NPARAM values in the order
  * W1 b1 W2 b2 W3 b3 W4 b4, each W[dy][dx][ci][co] row-major.  Kernels read

@@ -17,11 +17,10 @@ Conventions
   method itself uses) and the signed distance to the marker polygon,
   positive outside, clipped to [-8, 8].
 * Band: nodes with |sd| <= 4.  Target: the change of the equilibrium part
-  that brings the coarse moments to the fine ones,
-  df_i = f_i^eq(rho_hat, u_hat) - f_i^eq(rho_c, u_c),
-  with rho_hat - 1 = 4 (rho_f - 1) and u_hat = 2 u_f at fine node (2x, 2y)
-  (diffusive scaling: lattice velocities halve and lattice pressures
-  quarter on the twice finer grid).
+  that brings the coarse velocity to the fine one at unchanged density,
+  df_i = f_i^eq(rho_c, u_hat) - f_i^eq(rho_c, u_c),
+  with u_hat = 2 u_f at fine node (2x, 2y) (diffusive scaling: lattice
+  velocities halve on the twice finer grid).
 """
 from __future__ import annotations
 
@@ -225,17 +224,16 @@ def feq(rho, ux, uy) -> np.ndarray:
 
 
 def targets(f_coarse: np.ndarray, f_fine: np.ndarray) -> np.ndarray:
-    """df[ny][nx][9] = f^eq(rho_hat, u_hat) - f^eq(rho_c, u_c) at every coarse
-    node, the fine moments taken at (2x, 2y) and rescaled."""
+    """df[ny][nx][9] = f^eq(rho_c, u_hat) - f^eq(rho_c, u_c) at every coarse
+    node, with u_hat twice the fine velocity at (2x, 2y)."""
     ex, ey, _ = O.d2q9()
     rc = f_coarse.sum(axis=0)
     uc = np.tensordot(ex.astype(np.float64), f_coarse, axes=1)
     vc = np.tensordot(ey.astype(np.float64), f_coarse, axes=1)
     ff = f_fine[:, ::2, ::2]
-    rf = 1.0 + 4.0 * (ff.sum(axis=0) - 1.0)
     uf = 2.0 * np.tensordot(ex.astype(np.float64), ff, axes=1)
     vf = 2.0 * np.tensordot(ey.astype(np.float64), ff, axes=1)
-    d = feq(rf, uf, vf) - feq(rc, uc, vc)
+    d = feq(rc, uf, vf) - feq(rc, uc, vc)
     return np.moveaxis(d, 0, -1)
 
 

@@ -601,8 +601,9 @@ __global__ __launch_bounds__(256) void k_patches(const InstDev* __restrict__ ins
                    pscale + slot);
 }
 
-// Targets: f^eq(rho_hat, u_hat) - f^eq(rho_c, u_c) in network units (over
-// the output scale and the patch amplitude); the
+// Targets: f^eq(rho_c, u_hat) - f^eq(rho_c, u_c) in network units (over the
+// output scale and the patch amplitude), u_hat = 2 u_f at fine node (2x, 2y);
+// the
 // band mask of the output pixels from the patch flags.
 template <typename TC, typename TF>
 __global__ void k_targets(const InstDev* __restrict__ ic, const void* Ac,
@@ -625,7 +626,8 @@ __global__ void k_targets(const InstDev* __restrict__ ic, const void* Ac,
     double rc, uc, vc, rf, uf, vf;
     moments<double>(dc, rc, uc, vc);
     moments<double>(df, rf, uf, vf);
-    rf *= 4.0;
+    // velocity target only: the density stays the coarse one
+    rf = rc;
     uf *= 2.0;
     vf *= 2.0;
     // He-Luo equilibrium deviations w_i [drho + 3 e.u + 4.5 (e.u)^2 - 1.5 u.u]

@@ -41,17 +41,23 @@ def _sims(seeds, L=256, n_markers=512):
     return sc, sf
 
 
-def snapshot_steps(seed: int, k: int):
-    """k distinct coarse steps in [50, 2000], drawn from stream (5, seed)."""
+def snapshot_steps(seed: int, k: int, spacing: str = "uniform"):
+    """k distinct coarse steps drawn from stream (5, seed): uniform in
+    [50, 2000), or log-uniform in [1, 2000) so that the early transient is
+    sampled as densely per decade as the late decay."""
     rng = W.SplitMix64(5, seed)
     out = set()
     while len(out) < k:
-        out.add(50 + int(rng.uniform() * (COARSE_STEPS - 50)))
+        u = rng.uniform()
+        if spacing == "log":
+            out.add(max(1, min(COARSE_STEPS - 1, int(np.exp(u * np.log(COARSE_STEPS))))))
+        else:
+            out.add(50 + int(u * (COARSE_STEPS - 50)))
     return sorted(out)
 
 
 def generate(seeds, sc: LN.Scales, per_seed: int = 4, batch: int = 128, L: int = 256,
-             n_markers: int = 512):
+             n_markers: int = 512, spacing: str = "uniform"):
     """Patches, targets and masks (device tensors) of the band tiles of the
     uncorrected coarse runs at `per_seed` snapshot steps per seed.  All
     instances of a batch share the union of their snapshot steps; a seed
@@ -66,7 +72,7 @@ def generate(seeds, sc: LN.Scales, per_seed: int = 4, batch: int = 128, L: int =
         sc_.set_graph(True)
         sf.set_graph(True)
         band = LN.Band(sc_)
-        want = {s: set(snapshot_steps(s, per_seed)) for s in sb}
+        want = {s: set(snapshot_steps(s, per_seed, spacing)) for s in sb}
         stops = sorted(set().union(*want.values()))
         now = 0
         for st in stops:
@@ -229,6 +235,8 @@ def main(argv=None) -> int:
     ap.add_argument("--report", default=None, help="JSON summary path")
     ap.add_argument("--alpha", type=float, nargs="*", default=[1.0],
                     help="evaluate the correction scaled by each factor")
+    ap.add_argument("--spacing", choices=["uniform", "log"], default="uniform",
+                    help="snapshot steps: uniform in [50, 2000) or log-uniform in [1, 2000)")
     ap.add_argument("--eval-only", default=None, metavar="NPZ",
                     help="skip data generation and training; evaluate these weights")
     a = ap.parse_args(argv)
@@ -244,7 +252,8 @@ def main(argv=None) -> int:
         t0 = time.perf_counter()
         sc = fit_scales(range(a.train)[:8])
         log(f"scales in {list(sc.in_scale)} out {sc.out_scale:.3e}")
-        X, T, M = generate(range(a.train), sc, per_seed=a.per_seed, batch=a.gen_batch)
+        X, T, M = generate(range(a.train), sc, per_seed=a.per_seed, batch=a.gen_batch,
+                           spacing=a.spacing)
         t_gen = time.perf_counter() - t0
         log(f"{X.shape[0]} training patches, {int(M.sum().item())} band nodes ({t_gen:.1f} s)")
         t1 = time.perf_counter()
@@ -256,7 +265,7 @@ def main(argv=None) -> int:
         np.savez(a.out, params=net.numpy(), in_scale=np.array(list(sc.in_scale), np.float32),
                  out_scale=np.float32(sc.out_scale), loss=hist.astype(np.float32),
                  meta=json.dumps({"train_seeds": a.train, "per_seed": a.per_seed, "steps": a.steps,
-                                  "batch": a.batch, "lr": a.lr}))
+                                  "batch": a.batch, "lr": a.lr, "spacing": a.spacing}))
         log(f"saved {a.out}")
     held = list(W.LEARNED_HELDOUT_SEEDS)[:a.heldout]
     l_net, l_zero = heldout_loss(net, sc, held[:32])
