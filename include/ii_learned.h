@@ -88,7 +88,10 @@ int ii_cnn_adam(float* params, const float* grad, float* m, float* v, int32_t t,
  * a node at |sd| <= 4 is among them).  tiles[inst * cap + r] = (tx, ty) for
  * r < count[inst], in row-major tile order (tiles holds 2 * n_inst * cap
  * int32); cap >= tiles per instance.
- * Instances must be periodic membranes whose side is a multiple of 16. */
+ * Instances must be periodic membranes whose sides are multiples of 16, with at
+ * most 1024 tiles (EINVAL otherwise).  A patch near more chords than its
+ * lists hold (512 within 8 lu, 16 crossings of one row) marks the instance,
+ * which the next synchronising call reports as II_LBM_ECAPACITY. */
 int ii_lbm_learned_tiles(ii_lbm_handle* h, int32_t cap, int32_t* tiles, int32_t* count);
 
 /* Input patches and flags of the listed band tiles (slots inst * cap + r,

@@ -457,7 +457,7 @@ struct PatchShared {
 template <typename T>
 __device__ void build_patch(const InstDev& I, const T* __restrict__ A, const double2* __restrict__ X,
                             int tx, int ty, const ii_cnn_scales& sc, PatchShared& S, u16* in,
-                            uint8_t* flags, float* pscale)
+                            uint8_t* flags, float* pscale, int* err)
 {
     const int N = I.n_markers;
     const int ox = tx * kTile - kHalo, oy = ty * kTile - kHalo;  // patch origin node
@@ -579,8 +579,12 @@ __device__ void build_patch(const InstDev& I, const T* __restrict__ A, const dou
         in[q * 4 + 1] = to_bf16(S.raw[q][1] * inv);
         in[q * 4 + 2] = to_bf16(S.raw[q][2] * inv);
     }
-    if (threadIdx.x == 0) *pscale = amp;
-    return;
+    if (threadIdx.x == 0) {
+        *pscale = amp;
+        // more chords near the patch than the lists hold: the features are
+        // incomplete, which the handle reports as ECAPACITY
+        if (S.overflow) atomicOr(err, (int)kErrCapacity);
+    }
 }
 
 template <typename T>
@@ -588,7 +592,8 @@ __global__ __launch_bounds__(256) void k_patches(const InstDev* __restrict__ ins
                                                  const double2* __restrict__ Xall, ii_cnn_scales sc,
                                                  int cap, const int* __restrict__ tiles,
                                                  const int* __restrict__ count, u16* __restrict__ in,
-                                                 uint8_t* __restrict__ flags, float* __restrict__ pscale)
+                                                 uint8_t* __restrict__ flags, float* __restrict__ pscale,
+                                                 int* __restrict__ err)
 {
     const int inst = blockIdx.x / cap, r = blockIdx.x % cap;
     if (r >= count[inst]) return;
@@ -598,7 +603,7 @@ __global__ __launch_bounds__(256) void k_patches(const InstDev* __restrict__ ins
     const long long slot = blockIdx.x;
     build_patch<T>(I, (const T*)A0, Xall + I.mk_off, t.x, t.y, sc, S,
                    in + slot * (kPatch * kPatch * 4), flags + slot * (kPatch * kPatch),
-                   pscale + slot);
+                   pscale + slot, err + inst);
 }
 
 // Targets: f^eq(rho_c, u_hat) - f^eq(rho_c, u_c) in network units (over the
@@ -837,11 +842,11 @@ int ii_lbm_learned_patches(ii_lbm_handle* h, const ii_cnn_scales* sc, int32_t ca
     if (v.inst[0].storage == II_LBM_FP16)
         hipLaunchKernelGGL(k_patches<_Float16>, grid, dim3(256), 0, v.stream, v.d_inst,
                            v.P.lat[v.parity], v.P.X[v.parity], *sc, (int)cap, (const int*)tiles,
-                           (const int*)count, (u16*)in, flags, pscale);
+                           (const int*)count, (u16*)in, flags, pscale, v.P.err);
     else
         hipLaunchKernelGGL(k_patches<float>, grid, dim3(256), 0, v.stream, v.d_inst,
                            v.P.lat[v.parity], v.P.X[v.parity], *sc, (int)cap, (const int*)tiles,
-                           (const int*)count, (u16*)in, flags, pscale);
+                           (const int*)count, (u16*)in, flags, pscale, v.P.err);
     return err(hipGetLastError());
 }
 

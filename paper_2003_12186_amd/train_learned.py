@@ -57,11 +57,13 @@ def snapshot_steps(seed: int, k: int, spacing: str = "uniform"):
 
 
 def generate(seeds, sc: LN.Scales, per_seed: int = 4, batch: int = 128, L: int = 256,
-             n_markers: int = 512, spacing: str = "uniform"):
+             n_markers: int = 512, spacing: str = "uniform", net=None, alpha: float = 0.0):
     """Patches, targets and masks (device tensors) of the band tiles of the
-    uncorrected coarse runs at `per_seed` snapshot steps per seed.  All
-    instances of a batch share the union of their snapshot steps; a seed
-    keeps only its own."""
+    coarse runs at `per_seed` snapshot steps per seed.  All instances of a
+    batch share the union of their snapshot steps; a seed keeps only its own.
+    With `net`, the coarse runs are corrected by it (scaled by `alpha`) after
+    every step, so the patches come from the states the corrected run visits;
+    a batch whose corrected run fails stops contributing."""
     import torch
     X, T, M = [], [], []
     seeds = list(seeds)
@@ -75,8 +77,24 @@ def generate(seeds, sc: LN.Scales, per_seed: int = 4, batch: int = 128, L: int =
         want = {s: set(snapshot_steps(s, per_seed, spacing)) for s in sb}
         stops = sorted(set().union(*want.values()))
         now = 0
+        corr = None
+        if net is not None:
+            corr = LN.Band(sc_)
+            sca = LN.make_scales(list(sc.in_scale), sc.out_scale * alpha)
+        failed = False
         for st in stops:
-            sc_.step(st - now)
+            if corr is None:
+                sc_.step(st - now)
+            else:
+                try:
+                    for _ in range(st - now):
+                        sc_.step(1)
+                        corr.correct(net, sca)
+                    sc_.sync()
+                except B.IILBMError as e:
+                    log(f"corrected collection failed at step {st}: {e}")
+                    failed = True
+                    break
             sf.step(FINE_PER_COARSE * (st - now))
             now = st
             band.find()
@@ -89,7 +107,8 @@ def generate(seeds, sc: LN.Scales, per_seed: int = 4, batch: int = 128, L: int =
                 X.append(band.inp[idx].clone())
                 T.append(tg[idx].clone())
                 M.append(mk[idx].clone())
-        sc_.sync()
+        if not failed:
+            sc_.sync()
         sf.sync()
         sc_.close()
         sf.close()
@@ -237,6 +256,9 @@ def main(argv=None) -> int:
                     help="evaluate the correction scaled by each factor")
     ap.add_argument("--spacing", choices=["uniform", "log"], default="uniform",
                     help="snapshot steps: uniform in [50, 2000) or log-uniform in [1, 2000)")
+    ap.add_argument("--dagger", default=None, metavar="NPZ",
+                    help="start from these weights and add patches from runs corrected by them")
+    ap.add_argument("--dagger-alpha", type=float, default=0.1)
     ap.add_argument("--eval-only", default=None, metavar="NPZ",
                     help="skip data generation and training; evaluate these weights")
     a = ap.parse_args(argv)
@@ -250,14 +272,25 @@ def main(argv=None) -> int:
         t_gen = t_train = 0.0
     else:
         t0 = time.perf_counter()
-        sc = fit_scales(range(a.train)[:8])
+        init = None
+        if a.dagger:
+            d0 = np.load(a.dagger)
+            sc = LN.make_scales(d0["in_scale"], float(d0["out_scale"]))
+            init = d0["params"]
+        else:
+            sc = fit_scales(range(a.train)[:8])
         log(f"scales in {list(sc.in_scale)} out {sc.out_scale:.3e}")
         X, T, M = generate(range(a.train), sc, per_seed=a.per_seed, batch=a.gen_batch,
                            spacing=a.spacing)
+        if a.dagger:
+            X2, T2, M2 = generate(range(a.train), sc, per_seed=a.per_seed, batch=a.gen_batch,
+                                  spacing=a.spacing, net=LN.Net(init), alpha=a.dagger_alpha)
+            X, T, M = torch.cat([X, X2]), torch.cat([T, T2]), torch.cat([M, M2])
+            del X2, T2, M2
         t_gen = time.perf_counter() - t0
         log(f"{X.shape[0]} training patches, {int(M.sum().item())} band nodes ({t_gen:.1f} s)")
         t1 = time.perf_counter()
-        net, hist = fit(X, T, M, a.steps, batch=a.batch, lr=a.lr)
+        net, hist = fit(X, T, M, a.steps, batch=a.batch, lr=a.lr, init=init)
         t_train = time.perf_counter() - t1
         del X, T, M
         torch.cuda.empty_cache()
