@@ -18,6 +18,7 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr int kDiagBlocks = 1024;
 constexpr int kEventPool = 16384;
+constexpr int kXcds = 8;   // MI355X: eight accelerator complex dies, one L2 each
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -158,6 +159,7 @@ int build_layout(const ii_lbm_problem* p, int n_inst, Layout& L)
         I.tile_blocks = std::max(1, std::min(I.act_cap, 2048));
         L.mk_units += I.n_markers > 0 ? I.mk_blocks : 0;
         L.sweep_units_max += (int)(((long long)q.nx * q.ny + 127) / 128);
+        if (j == n_inst - 1) L.sweep_units_max += kXcds;   // padding of the XCD interleave
         L.inst[j] = I;
     }
     L.lat_bytes = align_up(lat);
@@ -309,7 +311,14 @@ static std::vector<int2> sweep_table(const Layout& L, int unit, int order)
         const long long n = (long long)L.inst[j].nx * L.inst[j].ny;
         for (long long r = 0; r < n; r += unit) t.push_back(make_int2(j, (int)r));
     }
-    return t;
+    // Workgroups go to the XCDs round-robin by index, each XCD with its own
+    // L2.  Cut the slice sequence into one contiguous run per XCD and
+    // interleave the runs, so that an XCD sweeps neighbouring rows and reads
+    // their y +- 1 neighbours from its own L2; (-1, 0) pads the last round.
+    const size_t per = (t.size() + kXcds - 1) / kXcds;
+    std::vector<int2> out(per * kXcds, make_int2(-1, 0));
+    for (size_t q = 0; q < t.size(); q++) out[(q % per) * kXcds + q / per] = t[q];
+    return out;
 }
 
 static hipError_t upload_sweep_table(ii_lbm_handle* h, int unit, int order)

@@ -61,6 +61,7 @@ __global__ __launch_bounds__(UNIT) void k_sweep_batch(const InstDev* __restrict_
                                                       const float* __restrict__ corr)
 {
     const int2 u = units[blockIdx.x];
+    if (u.x < 0) return;   // padding of the table
     const InstDev I = insts[u.x];
     const int r = u.y + threadIdx.x;
     if (r >= I.nx * I.ny) return;
