@@ -139,3 +139,33 @@ def test_batch_mixing_membranes_and_plain_fluid(B):
                               one.fields(B.F_DISTRIB, dtype=np.float32)), j
         one.close()
     sim.close()
+
+
+def test_full_batch512_sampled_instances_match_oracle(B):
+    # The 512-instance workload in the launch configuration the bench times
+    # (autotuned table, HIP graphs): 20 steps, then the smallest, the largest
+    # and two other instances against the oracle.
+    ws = W.membrane_batch_c4(512)
+    for w in ws:
+        w.problem.math = W.MATH_FP64
+    _say("batch of 512 uneven membranes, 20 steps (graphs, autotuned), 4 sampled vs oracle")
+    sim = B.Sim([w.problem for w in ws], [w.X0 for w in ws])
+    sim.autotune(2)
+    sim.set_graph(True)
+    sim.step(20)
+    sizes = [w.problem.nx for w in ws]
+    picks = [int(np.argmin(sizes)), int(np.argmax(sizes)), 137, 400]
+    for j in picks:
+        w = ws[j]
+        p = O.make_problem(w.problem)
+        f = O.rest_state(p)
+        X = w.X0.copy()
+        O.run(p, f, X, 20)
+        _, ux, uy = O.moments(p, f)
+        g = sim.fields(B.F_UX | B.F_UY, inst=j)
+        err = np.sqrt(((g[0] - ux) ** 2 + (g[1] - uy) ** 2).sum() / (ux ** 2 + uy ** 2).sum())
+        dX = np.abs(sim.markers(j)[0] - X).max()
+        _say(f"  instance {j} (L={w.problem.nx}, N={w.problem.n_markers}): rel L2 u {err:.2e}, |dX| {dX:.1e}")
+        assert err <= 1e-6 and dX <= 1e-9
+    assert all(sim.diag(j)["error_bits"] == 0 for j in picks)
+    sim.close()

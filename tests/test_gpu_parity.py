@@ -344,3 +344,28 @@ def test_minimal_triangle_membrane(B):
     _say(f"  rel L2 u = {err:.3e}  max |dX| = {dX:.3e}  max|rho-1| / max|u| = {ratio:.1f}")
     assert err <= 1e-5 and dX <= 1e-6
     sim.close()
+
+
+@pytest.mark.parametrize("re", [20.0, 100.0])
+def test_cylinder_full_size_first_steps(B, re):
+    # The 1024 x 512 channel of the cylinder workload at its full size: 600
+    # steps, long enough for the inflow's pressure front to pass the cylinder
+    # at x = 256, against the oracle, with the drag/lift history.
+    _say(f"cylinder channel 1024x512 D=32 MRT Re={re}, 600 steps vs oracle")
+    w = W.cylinder_c2(re=re)
+    w.problem.math = W.MATH_FP64
+    sim = B.Sim([w.problem], [w.X0])
+    fx = []
+    for _ in range(6):
+        sim.step(100)
+        fx.append(sim.diag()["force"])
+    g = sim.fields(B.F_RHO | B.F_UX | B.F_UY)
+    o = _oracle_run(w.problem, w.X0, 600, force_hist=True)
+    err = _rel_l2(g[1], g[2], o["ux"], o["uy"])
+    fo = o["fh"][99::100]
+    assert np.abs(fo).max() > 0.0
+    ferr = np.abs(np.array(fx) - fo).max() / np.abs(fo).max()
+    _say(f"  rel L2 u = {err:.3e}  force rel err = {ferr:.3e}  F(600) = {fx[-1]}")
+    assert err <= 1e-6 and ferr <= 1e-5
+    assert sim.diag()["n_cut_links"] > 400
+    sim.close()
