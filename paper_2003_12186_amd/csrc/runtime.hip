@@ -244,6 +244,7 @@ struct ii_lbm_handle {
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool rec_valid = false;  // rigid bodies: a step has built cut-link records
+    int n_cu = 256;
 };
 
 static int hip_fail(ii_lbm_handle* h, hipError_t e)
@@ -473,6 +474,18 @@ static int record_parity(const ii_lbm_handle* h)
     return h->rec_valid ? (h->parity ^ 1) : -1;
 }
 
+// Blocks of the tile kernel of a single instance.  Beside the sweep it runs
+// with one block per CU (each block walks several tiles), which leaves the
+// sweep more room; on the critical path it runs with up to 2048 blocks.
+static void size_tile_blocks(ii_lbm_handle* h)
+{
+    if (h->batched) return;
+    const bool beside = h->lookahead && h->overlap != II_LBM_OVERLAP_SERIAL;
+    for (InstDev& I : h->L.inst)
+        if (I.n_markers > 0)
+            I.tile_blocks = std::max(1, std::min(I.act_cap, beside ? h->n_cu : 2048));
+}
+
 static void release(ii_lbm_handle* h)
 {
     drop_graphs(h);
@@ -657,6 +670,14 @@ int ii_lbm_init(const ii_lbm_problem* p, int32_t n_inst, const double* const* X0
         }
     h->lookahead = any && all_membrane;
     h->overlap = II_LBM_OVERLAP_FULL;
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            cus > 0)
+            h->n_cu = cus;
+    }
+    size_tile_blocks(h);
     if (e == hipSuccess && h->lookahead) {
         e = hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming);
@@ -706,6 +727,7 @@ int ii_lbm_set_overlap(ii_lbm_handle* h, int32_t mode)
     if (!h || mode < II_LBM_OVERLAP_SERIAL || mode > II_LBM_OVERLAP_INTERP_FIRST) return II_LBM_EINVAL;
     if (h->overlap != mode) drop_graphs(h);
     h->overlap = mode;
+    size_tile_blocks(h);
     return II_LBM_OK;
 }
 

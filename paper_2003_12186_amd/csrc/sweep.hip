@@ -45,6 +45,9 @@ __global__ __launch_bounds__(BX) void k_sweep(InstDev I, const T* __restrict__ A
                                               const int* __restrict__ tile_slot,
                                               const float* __restrict__ corr)
 {
+    // the interface pass of the next step may share the CUs: the sweep's
+    // waves issue first
+    __builtin_amdgcn_s_setprio(3);
     const int bx = blockIdx.x % bx_count, y = blockIdx.x / bx_count;
     const int x = bx * BX + threadIdx.x;
     if (x >= I.nx) return;
@@ -60,6 +63,7 @@ __global__ __launch_bounds__(UNIT) void k_sweep_batch(const InstDev* __restrict_
                                                       const int* __restrict__ tile_slot,
                                                       const float* __restrict__ corr)
 {
+    __builtin_amdgcn_s_setprio(3);
     const int2 u = units[blockIdx.x];
     if (u.x < 0) return;   // padding of the table
     const InstDev I = insts[u.x];
