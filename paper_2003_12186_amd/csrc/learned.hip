@@ -678,7 +678,13 @@ __global__ __launch_bounds__(512) void k_correct(const InstDev* __restrict__ ins
         for (int e = threadIdx.x; e < kPatch * kPatch; e += blockDim.x)
             fl[e] = flags[slot * (kPatch * kPatch) + e];
     }
-    __syncthreads();
+    // a tile whose output nodes all lie outside the band gets no correction
+    int any = 0;
+    if (threadIdx.x < kOut * kOut) {
+        const int oy = threadIdx.x / kOut, ox = threadIdx.x % kOut;
+        any = flags[slot * (kPatch * kPatch) + (oy + kHalo) * kPatch + ox + kHalo] & 2;
+    }
+    if (!__syncthreads_or(any)) return;
     hidden_layer<0>(bx, by, packed, prm, nullptr, nullptr);
     __syncthreads();
     hidden_layer<1>(by, bx, packed, prm, nullptr, nullptr);
