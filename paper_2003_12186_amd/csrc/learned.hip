@@ -587,6 +587,11 @@ __device__ void build_patch(const InstDev& I, const T* __restrict__ A, const dou
     }
 }
 
+// Grid (n_inst, G): block y of instance x takes the instance's band tiles
+// y, y + G, ... below its count, so that the launch does not depend on the
+// counts, which only the device knows, and empty slots cost no block.
+constexpr int kSlotStride = 64;
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_patches(const InstDev* __restrict__ insts, const void* A0,
                                                  const double2* __restrict__ Xall, ii_cnn_scales sc,
@@ -595,15 +600,18 @@ __global__ __launch_bounds__(256) void k_patches(const InstDev* __restrict__ ins
                                                  uint8_t* __restrict__ flags, float* __restrict__ pscale,
                                                  int* __restrict__ err)
 {
-    const int inst = blockIdx.x / cap, r = blockIdx.x % cap;
-    if (r >= count[inst]) return;
+    const int inst = blockIdx.x, n = count[inst];
+    if ((int)blockIdx.y >= n) return;
     const InstDev I = insts[inst];
     __shared__ PatchShared S;
-    const int2 t = ((const int2*)tiles)[blockIdx.x];
-    const long long slot = blockIdx.x;
-    build_patch<T>(I, (const T*)A0, Xall + I.mk_off, t.x, t.y, sc, S,
-                   in + slot * (kPatch * kPatch * 4), flags + slot * (kPatch * kPatch),
-                   pscale + slot, err + inst);
+    for (int r = blockIdx.y; r < n; r += gridDim.y) {
+        if (r != (int)blockIdx.y) __syncthreads();   // the previous patch is done with S
+        const long long slot = (long long)inst * cap + r;
+        const int2 t = ((const int2*)tiles)[slot];
+        build_patch<T>(I, (const T*)A0, Xall + I.mk_off, t.x, t.y, sc, S,
+                       in + slot * (kPatch * kPatch * 4), flags + slot * (kPatch * kPatch),
+                       pscale + slot, err + inst);
+    }
 }
 
 // Targets: f^eq(rho_c, u_hat) - f^eq(rho_c, u_c) in network units (over the
@@ -663,54 +671,57 @@ __global__ __launch_bounds__(512) void k_correct(const InstDev* __restrict__ ins
                                                  const uint8_t* __restrict__ flags,
                                                  const float* __restrict__ pscale)
 {
-    const int inst = blockIdx.x / cap, r = blockIdx.x % cap;
-    if (r >= count[inst]) return;
+    const int inst = blockIdx.x, n = count[inst];
+    if ((int)blockIdx.y >= n) return;
     const InstDev I = insts[inst];
     __shared__ __align__(16) u16 bx[20 * 20 * 32];
     __shared__ __align__(16) u16 by[22 * 22 * 32];
     __shared__ uint8_t fl[kPatch * kPatch];
-    const int2 t = ((const int2*)tiles)[blockIdx.x];
     T* A = (T*)A0;
-    const long long slot = blockIdx.x;
-    {
-        const unsigned* src = (const unsigned*)(in + slot * (kPatch * kPatch * 4));
-        for (int e = threadIdx.x; e < kPatch * kPatch * 2; e += blockDim.x) ((unsigned*)bx)[e] = src[e];
-        for (int e = threadIdx.x; e < kPatch * kPatch; e += blockDim.x)
-            fl[e] = flags[slot * (kPatch * kPatch) + e];
-    }
-    // a tile whose output nodes all lie outside the band gets no correction
-    int any = 0;
-    if (threadIdx.x < kOut * kOut) {
-        const int oy = threadIdx.x / kOut, ox = threadIdx.x % kOut;
-        any = flags[slot * (kPatch * kPatch) + (oy + kHalo) * kPatch + ox + kHalo] & 2;
-    }
-    if (!__syncthreads_or(any)) return;
-    hidden_layer<0>(bx, by, packed, prm, nullptr, nullptr);
-    __syncthreads();
-    hidden_layer<1>(by, bx, packed, prm, nullptr, nullptr);
-    __syncthreads();
-    hidden_layer<2>(bx, by, packed, prm, nullptr, nullptr);
-    __syncthreads();
-    const float* b4 = prm + OFF_B[3];
-    const float os = sc.out_scale * pscale[slot];
-    T* base = A + I.lat_off;
-    conv_mfma<18, 16, 32, 9, 1, false>(by, packed + FOFF[3], nullptr, [&](int row, int c, float v) {
-        if (c >= 9) return;
-        const int oy = row / kOut, ox = row % kOut;
-        const int q = (oy + kHalo) * kPatch + ox + kHalo;
-        const uint8_t f = fl[q];
-        if (!(f & 2)) return;
-        if (c != 0) {
-            const uint8_t fs = fl[q - EY[c] * kPatch - EX[c]];
-            if ((fs & 1) != (f & 1)) return;   // a link across the polygon
+    for (int r = blockIdx.y; r < n; r += gridDim.y) {
+        if (r != (int)blockIdx.y) __syncthreads();   // the previous tile is done with the buffers
+        const long long slot = (long long)inst * cap + r;
+        const int2 t = ((const int2*)tiles)[slot];
+        {
+            const unsigned* src = (const unsigned*)(in + slot * (kPatch * kPatch * 4));
+            for (int e = threadIdx.x; e < kPatch * kPatch * 2; e += blockDim.x) ((unsigned*)bx)[e] = src[e];
+            for (int e = threadIdx.x; e < kPatch * kPatch; e += blockDim.x)
+                fl[e] = flags[slot * (kPatch * kPatch) + e];
         }
-        // pre-collision f_c(x) is the value stored at x - e_c
-        int x = t.x * kTile + ox - EX[c], y = t.y * kTile + oy - EY[c];
-        x = x < 0 ? x + I.nx : (x >= I.nx ? x - I.nx : x);
-        y = y < 0 ? y + I.ny : (y >= I.ny ? y - I.ny : y);
-        T* p = base + c * I.plane + (long long)y * I.pitch + x;
-        Store<T>::st(p, Store<T>::ld(p, I.scale) + os * (v + b4[c]), I.inv_scale);
-    });
+        // a tile whose output nodes all lie outside the band gets no correction
+        int any = 0;
+        if (threadIdx.x < kOut * kOut) {
+            const int oy = threadIdx.x / kOut, ox = threadIdx.x % kOut;
+            any = flags[slot * (kPatch * kPatch) + (oy + kHalo) * kPatch + ox + kHalo] & 2;
+        }
+        if (!__syncthreads_or(any)) continue;
+        hidden_layer<0>(bx, by, packed, prm, nullptr, nullptr);
+        __syncthreads();
+        hidden_layer<1>(by, bx, packed, prm, nullptr, nullptr);
+        __syncthreads();
+        hidden_layer<2>(bx, by, packed, prm, nullptr, nullptr);
+        __syncthreads();
+        const float* b4 = prm + OFF_B[3];
+        const float os = sc.out_scale * pscale[slot];
+        T* base = A + I.lat_off;
+        conv_mfma<18, 16, 32, 9, 1, false>(by, packed + FOFF[3], nullptr, [&](int row, int c, float v) {
+            if (c >= 9) return;
+            const int oy = row / kOut, ox = row % kOut;
+            const int q = (oy + kHalo) * kPatch + ox + kHalo;
+            const uint8_t f = fl[q];
+            if (!(f & 2)) return;
+            if (c != 0) {
+                const uint8_t fs = fl[q - EY[c] * kPatch - EX[c]];
+                if ((fs & 1) != (f & 1)) return;   // a link across the polygon
+            }
+            // pre-collision f_c(x) is the value stored at x - e_c
+            int x = t.x * kTile + ox - EX[c], y = t.y * kTile + oy - EY[c];
+            x = x < 0 ? x + I.nx : (x >= I.nx ? x - I.nx : x);
+            y = y < 0 ? y + I.ny : (y >= I.ny ? y - I.ny : y);
+            T* p = base + c * I.plane + (long long)y * I.pitch + x;
+            Store<T>::st(p, Store<T>::ld(p, I.scale) + os * (v + b4[c]), I.inv_scale);
+        });
+    }
 }
 
 // The masked add of given corrections (network units), one block per slot.
@@ -844,7 +855,7 @@ int ii_lbm_learned_patches(ii_lbm_handle* h, const ii_cnn_scales* sc, int32_t ca
     if (rc) return rc;
     if ((rc = check_learned(v))) return rc;
     if (!sc || !tiles || !count || !in || !flags || !pscale || cap < 1) return II_LBM_EINVAL;
-    const dim3 grid((unsigned)(v.n_inst * cap));
+    const dim3 grid((unsigned)v.n_inst, (unsigned)std::min((int)cap, kSlotStride));
     if (v.inst[0].storage == II_LBM_FP16)
         hipLaunchKernelGGL(k_patches<_Float16>, grid, dim3(256), 0, v.stream, v.d_inst,
                            v.P.lat[v.parity], v.P.X[v.parity], *sc, (int)cap, (const int*)tiles,
@@ -921,7 +932,7 @@ int ii_lbm_learned_correct(ii_lbm_handle* h, const float* params, const void* pa
     if ((rc = ii_lbm_learned_patches(h, sc, cap, tiles, count, in, flags, pscale))) return rc;
     HandleView v;
     handle_view(h, &v);
-    const dim3 grid((unsigned)(v.n_inst * cap));
+    const dim3 grid((unsigned)v.n_inst, (unsigned)std::min((int)cap, kSlotStride));
     if (v.inst[0].storage == II_LBM_FP16)
         hipLaunchKernelGGL(k_correct<_Float16>, grid, dim3(512), 0, v.stream, v.d_inst,
                            v.P.lat[v.parity], params, (const u16*)packed, *sc, (int)cap,

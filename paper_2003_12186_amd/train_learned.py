@@ -57,13 +57,21 @@ def snapshot_steps(seed: int, k: int, spacing: str = "uniform"):
 
 
 def generate(seeds, sc: LN.Scales, per_seed: int = 4, batch: int = 128, L: int = 256,
-             n_markers: int = 512, spacing: str = "uniform", net=None, alpha: float = 0.0):
+             n_markers: int = 512, spacing: str = "uniform", net=None, alpha: float = 0.0,
+             teacher: bool = False):
     """Patches, targets and masks (device tensors) of the band tiles of the
     coarse runs at `per_seed` snapshot steps per seed.  All instances of a
     batch share the union of their snapshot steps; a seed keeps only its own.
     With `net`, the coarse runs are corrected by it (scaled by `alpha`) after
     every step, so the patches come from the states the corrected run visits;
-    a batch whose corrected run fails stops contributing."""
+    a batch whose corrected run fails stops contributing.
+
+    With `teacher`, the coarse runs are corrected after every step by the
+    exact targets of that step (the fine run advances in lockstep).  A target
+    is then the one-step drift of the coarse scheme from a state that agrees
+    with the fine run, which is what the correction meets when it is applied
+    every step; targets of the uncorrected run instead hold the drift
+    accumulated since the start."""
     import torch
     X, T, M = [], [], []
     seeds = list(seeds)
@@ -82,6 +90,26 @@ def generate(seeds, sc: LN.Scales, per_seed: int = 4, batch: int = 128, L: int =
             corr = LN.Band(sc_)
             sca = LN.make_scales(list(sc.in_scale), sc.out_scale * alpha)
         failed = False
+        if teacher:
+            last = stops[-1]
+            for n in range(1, last + 1):
+                sc_.step(1)
+                sf.step(FINE_PER_COARSE)
+                band.find()
+                band.patches(sc)
+                tg, mk = band.targets(sf, sc)
+                keep = []
+                if n in stops:
+                    cnt = band.count.cpu().numpy()
+                    keep = [j * band.cap + r for j, s in enumerate(sb) if n in want[s]
+                            for r in range(int(cnt[j]))]
+                if keep:
+                    idx = torch.tensor(keep, device=band.inp.device)
+                    X.append(band.inp[idx].clone())
+                    T.append(tg[idx].clone())
+                    M.append(mk[idx].clone())
+                band.apply(tg, sc)
+            stops = []
         for st in stops:
             if corr is None:
                 sc_.step(st - now)
@@ -120,12 +148,13 @@ def generate(seeds, sc: LN.Scales, per_seed: int = 4, batch: int = 128, L: int =
 IN_SCALE = (1.0, 3.0 ** 0.5, 3.0 ** 0.5, 0.125)
 
 
-def fit_scales(seeds, per_seed=2, L=256, n_markers=512) -> LN.Scales:
+def fit_scales(seeds, per_seed=2, L=256, n_markers=512, teacher: bool = False) -> LN.Scales:
     """Fixed input scales (rho - 1 against sqrt(3) u, the acoustic balance
     c_s drho = u, and sd / 8) and the output scale: the standard deviation
     of the band targets over the patch amplitude, from a few seeds."""
     unit = LN.make_scales(IN_SCALE, 1.0)
-    _, T, M = generate(seeds, unit, per_seed=per_seed, batch=len(seeds), L=L, n_markers=n_markers)
+    _, T, M = generate(seeds, unit, per_seed=per_seed, batch=len(seeds), L=L, n_markers=n_markers,
+                       teacher=teacher)
     s_out = max(float(T[M.bool()].std()), 1e-12)
     return LN.make_scales(IN_SCALE, s_out)
 
@@ -173,10 +202,10 @@ def _err(sc_, sf, j):
     return float(np.sqrt(((gc - r) ** 2).sum() / (r ** 2).sum()))
 
 
-def heldout_loss(net, sc: LN.Scales, seeds, per_seed: int = 4):
+def heldout_loss(net, sc: LN.Scales, seeds, per_seed: int = 4, teacher: bool = False):
     """One-step metric on held-out seeds: masked MSE of the network against
     the targets, and of the zero correction (the method without it)."""
-    X, T, M = generate(seeds, sc, per_seed=per_seed, batch=len(seeds))
+    X, T, M = generate(seeds, sc, per_seed=per_seed, batch=len(seeds), teacher=teacher)
     out, _ = net.forward(X)
     m = M.unsqueeze(-1).float()
     den = 9.0 * float(M.sum().item())
@@ -256,6 +285,9 @@ def main(argv=None) -> int:
                     help="evaluate the correction scaled by each factor")
     ap.add_argument("--spacing", choices=["uniform", "log"], default="uniform",
                     help="snapshot steps: uniform in [50, 2000) or log-uniform in [1, 2000)")
+    ap.add_argument("--teacher", action="store_true",
+                    help="targets from coarse runs kept on the fine run by the exact correction "
+                         "every step (one-step drift) instead of from uncorrected runs")
     ap.add_argument("--dagger", default=None, metavar="NPZ",
                     help="start from these weights and add patches from runs corrected by them")
     ap.add_argument("--dagger-alpha", type=float, default=0.1)
@@ -278,10 +310,10 @@ def main(argv=None) -> int:
             sc = LN.make_scales(d0["in_scale"], float(d0["out_scale"]))
             init = d0["params"]
         else:
-            sc = fit_scales(range(a.train)[:8])
+            sc = fit_scales(range(a.train)[:8], teacher=a.teacher)
         log(f"scales in {list(sc.in_scale)} out {sc.out_scale:.3e}")
         X, T, M = generate(range(a.train), sc, per_seed=a.per_seed, batch=a.gen_batch,
-                           spacing=a.spacing)
+                           spacing=a.spacing, teacher=a.teacher)
         if a.dagger:
             X2, T2, M2 = generate(range(a.train), sc, per_seed=a.per_seed, batch=a.gen_batch,
                                   spacing=a.spacing, net=LN.Net(init), alpha=a.dagger_alpha)
@@ -298,10 +330,14 @@ def main(argv=None) -> int:
         np.savez(a.out, params=net.numpy(), in_scale=np.array(list(sc.in_scale), np.float32),
                  out_scale=np.float32(sc.out_scale), loss=hist.astype(np.float32),
                  meta=json.dumps({"train_seeds": a.train, "per_seed": a.per_seed, "steps": a.steps,
-                                  "batch": a.batch, "lr": a.lr, "spacing": a.spacing}))
+                                  "batch": a.batch, "lr": a.lr, "spacing": a.spacing,
+                                  "teacher": a.teacher}))
         log(f"saved {a.out}")
     held = list(W.LEARNED_HELDOUT_SEEDS)[:a.heldout]
-    l_net, l_zero = heldout_loss(net, sc, held[:32])
+    teacher = a.teacher
+    if a.eval_only:
+        teacher = bool(json.loads(str(d["meta"])).get("teacher", False)) if "meta" in d else False
+    l_net, l_zero = heldout_loss(net, sc, held[:32], teacher=teacher)
     log(f"held-out one-step loss: network {l_net:.4e}, no correction {l_zero:.4e}")
     runs = {}
     for al in a.alpha:
