@@ -25,6 +25,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0   # dense MFMA
+# multiply-adds of one band tile through the network: valid 3 x 3 convolutions
+# 24 -> 22 -> 20 -> 18 -> 16, channels 4 -> 32 -> 32 -> 32 -> 9
+CNN_FLOP_PER_TILE = 2 * (22 * 22 * 9 * 4 * 32 + 20 * 20 * 9 * 32 * 32 + 18 * 18 * 9 * 32 * 32
+                         + 16 * 16 * 9 * 32 * 9)
+LEARNED_WEIGHTS = os.path.join(ROOT, "paper_2003_12186_amd", "data", "cnn_c5.npz")
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "sweep_traffic_membrane4096.json")
 SWEEP_SOURCES = [os.path.join(ROOT, "paper_2003_12186_amd", "csrc", n) for n in ("sweep.hip", "common.hpp")]
 
@@ -65,6 +71,148 @@ def cpu_baseline(w, steps: int):
                       f"({dt:.1f} s)"}
 
 
+def cpu_baseline_learned(w, net_file: str, steps: int):
+    """The FP64 oracle's corrected coarse step on one instance: a method step,
+    features of the whole field, the network on every band tile, the masked
+    add."""
+    import numpy as np
+    import oracle as O
+    import oracle.learned as OL
+    from paper_2003_12186_amd.learned import split_params
+    d = np.load(net_file)
+    Wt, b = split_params(d["params"])
+    in_scale = np.asarray(d["in_scale"], dtype=np.float64)
+    out_scale = 0.0                        # the GPU leg's alpha = 0
+    p = O.make_problem(w.problem)
+    f = O.rest_state(p)
+    X = w.X0.copy()
+    O.run(p, f, X, 1)                      # first-touch of the arrays, not timed
+    n_tiles = 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        O.run(p, f, X, 1)
+        feat, sd = OL.node_features(f, X)
+        tiles = OL.band_tiles(sd)
+        xs, amps = [], []
+        for tx, ty in tiles:
+            raw = OL.extract_patch(feat, tx, ty)
+            a = OL.patch_amplitude(raw, in_scale)
+            pt = raw * in_scale
+            pt[..., :3] /= a
+            xs.append(pt)
+            amps.append(a)
+        out = OL.forward(Wt, b, np.stack(xs))[4]
+        df = np.zeros((p.ny, p.nx, 9))
+        for k, (tx, ty) in enumerate(tiles):
+            df[ty * 16:(ty + 1) * 16, tx * 16:(tx + 1) * 16] = out[k] * (out_scale * amps[k])
+        OL.apply_correction(f, df, sd)
+        n_tiles += len(tiles)
+    dt = time.perf_counter() - t0
+    return {"value": round(p.nx * p.ny * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": O.num_threads(),
+            "kind": "oracle",
+            "sample": f"{steps} FP64 oracle corrected coarse steps of one {p.nx}x{p.ny} instance "
+                      f"({n_tiles} band tiles through the network) after 1 untimed step ({dt:.1f} s)"}
+
+
+def bench_learned(args, B, W) -> int:
+    """Learned correction of 2x-coarsened membranes: held-out coarse/fine
+    pairs (256^2 / 512^2, 512 markers, diffusive scaling) batched in one
+    handle per resolution.  Timed: K coarse steps each followed by the
+    correction (band tiles, patches, network + masked add), next to 4K fine
+    steps (HIP graphs) covering the same physical time.  The correction is
+    scaled by alpha = 0: every kernel runs in full and adds zero, so the
+    trajectory and the timing do not depend on the network's stability.  The
+    network kernel's roofline comes from a second pass with HIP events around
+    each of its launches."""
+    import numpy as np
+    import torch
+    from paper_2003_12186_amd import learned as LN
+    n = args.instances or 200
+    seeds = list(W.LEARNED_HELDOUT_SEEDS)[:n]
+    pairs = [W.learned_pair_c5(s) for s in seeds]
+    d = np.load(LEARNED_WEIGHTS)
+    net = LN.Net(d["params"])
+    sc = LN.make_scales(d["in_scale"], 0.0)
+    sl = B.Sim([c.problem for c, _ in pairs], [c.X0 for c, _ in pairs], device="cuda:0")
+    sp = B.Sim([c.problem for c, _ in pairs], [c.X0 for c, _ in pairs], device="cuda:0")
+    sf = B.Sim([f.problem for _, f in pairs], [f.X0 for _, f in pairs], device="cuda:0")
+    sp.set_graph(True)
+    sf.set_graph(True)
+    band = LN.Band(sl)
+    for _ in range(args.warmup):
+        sl.step(1)
+        band.correct(net, sc)
+    sp.step(args.warmup)
+    sf.step(4 * args.warmup)
+    for s in (sl, sp, sf):
+        s.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sl.step(1)
+        band.correct(net, sc)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    sl.sync()
+    t0 = time.perf_counter()
+    sp.step(args.steps)
+    torch.cuda.synchronize()
+    dt_plain = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    sf.step(4 * args.steps)
+    torch.cuda.synchronize()
+    dt_fine = time.perf_counter() - t0
+    # event-timed network launches on the same trajectory
+    n_t = min(args.steps, 200)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_t)]
+    run_tiles = torch.zeros((), dtype=torch.int64, device="cuda:0")
+    pix = torch.arange(band.cap, device="cuda:0")
+    for k in range(n_t):
+        sl.step(1)
+        band.find()
+        band.patches(sc)
+        ev[k][0].record(sl.stream)
+        band.infer(net, sc)
+        ev[k][1].record(sl.stream)
+        # tiles that run the network: listed, with a band node among their outputs
+        listed = (pix[None, :] < band.count[:, None]).reshape(-1)
+        has = (band.flags[:, 4:20, 4:20] & 2).reshape(band.flags.shape[0], -1).amax(dim=1) > 0
+        run_tiles += (listed & has).sum()
+    torch.cuda.synchronize()
+    sl.sync()
+    t_infer = sum(a.elapsed_time(b) for a, b in ev) / 1e3
+    tiles = int(run_tiles.item())
+    avg = t_infer / n_t
+    achieved = tiles / n_t * CNN_FLOP_PER_TILE / avg / 1e12
+    nodes = sum(c.problem.nx * c.problem.ny for c, _ in pairs)
+    nodes_f = sum(f.problem.nx * f.problem.ny for _, f in pairs)
+    out = {
+        "metric": "MLUPS & %HBM peak; learned 2x-coarse vs fine II-LBM time at <=1e-2 L2 err",
+        "value": round(nodes * args.steps / dt / 1e6, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3 / args.steps, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 storage / fp32 collision; bf16 MFMA network, f32 accumulation",
+        "data": "synthetic",
+        "config": {"workload": f"learned_c5_{n}", "instances": n, "coarse": 256, "fine": 512,
+                   "markers": 512, "fine_steps_per_coarse": 4, "alpha": 0.0,
+                   "t_corrected_coarse_s": round(dt, 4), "t_plain_coarse_s": round(dt_plain, 4),
+                   "t_fine_s": round(dt_fine, 4), "speedup_vs_fine": round(dt_fine / dt, 3),
+                   "fine_mlups": round(nodes_f * 4 * args.steps / dt_fine / 1e6, 1),
+                   "plain_coarse_mlups": round(nodes * args.steps / dt_plain / 1e6, 1)},
+        "roofline": {"bound": "mfma", "kernel": "k_correct", "achieved": round(achieved, 2),
+                     "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / BF16_PEAK_TFLOPS, 4), "traffic": None,
+                     "flop_per_tile": CNN_FLOP_PER_TILE, "tiles_per_launch": round(tiles / n_t, 1),
+                     "avg_launch_us": round(avg * 1e6, 2), "timed_launches": n_t},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_learned(pairs[0][0], LEARNED_WEIGHTS, args.cpu_steps)
+    for s in (sl, sp, sf):
+        s.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def set_overlap(sim, B, args) -> None:
     modes = {"serial": B.OVERLAP_SERIAL, "full": B.OVERLAP_FULL,
              "interp_first": B.OVERLAP_INTERP_FIRST}
@@ -78,7 +226,7 @@ def bench_batch(args, B, W) -> int:
     the autotuner.  The sweep's average duration is taken in a second, event-
     timed pass of direct launches over the same state."""
     import torch
-    ws = W.membrane_batch_c4(n_inst=args.instances)
+    ws = W.membrane_batch_c4(n_inst=args.instances or 512)
     for w in ws:
         w.problem.math = W.MATH_FP64 if args.math == "fp64" else W.MATH_FP32
         w.problem.storage = W.STORE_FP16 if args.storage == "fp16" else W.STORE_FP32
@@ -136,10 +284,13 @@ def main() -> int:
                          "for FP32 storage (its 1e-6 parity bar) and FP32 for FP16 storage "
                          "(1e-3 bar)")
     ap.add_argument("--size", type=int, default=4096)
-    ap.add_argument("--workload", choices=["membrane", "batch512"], default="membrane",
+    ap.add_argument("--workload", choices=["membrane", "batch512", "learned"], default="membrane",
                     help="membrane: one L x L membrane (the bench line); batch512: 512 uneven "
-                         "membrane instances advanced together (reported in the design notes)")
-    ap.add_argument("--instances", type=int, default=512)
+                         "membrane instances advanced together; learned: 200 coarse membranes "
+                         "with the learned correction every step against their fine runs (both "
+                         "reported in the design notes)")
+    ap.add_argument("--instances", type=int, default=None,
+                    help="instances of the batch512 (default 512) or learned (200) workload")
     ap.add_argument("--graph", choices=["on", "off"], default="on",
                     help="replay steps as HIP graphs (two steps per replay) or launch directly")
     ap.add_argument("--overlap", choices=["default", "serial", "full", "interp_first"],
@@ -172,6 +323,8 @@ def main() -> int:
 
     if args.workload == "batch512":
         return bench_batch(args, B, W)
+    if args.workload == "learned":
+        return bench_learned(args, B, W)
     storage = W.STORE_FP16 if args.storage == "fp16" else W.STORE_FP32
     w = W.membrane_c3(L=args.size, storage=storage)
     p = w.problem

@@ -117,9 +117,18 @@ int ii_lbm_learned_apply(ii_lbm_handle* h, const ii_cnn_scales* sc, int32_t cap,
                          const int32_t* tiles, const int32_t* count, const uint8_t* flags,
                          const float* pscale, const float* out);
 
+/* The network and the masked add of ii_lbm_learned_apply, fused per tile,
+ * on patches from ii_lbm_learned_patches of the same state (every patch
+ * must be built before any tile is corrected: a tile's halo overlaps its
+ * neighbours' nodes).  Tiles with no band node are skipped. */
+int ii_lbm_learned_infer(ii_lbm_handle* h, const float* params, const void* packed,
+                         const ii_cnn_scales* sc, int32_t cap, const int32_t* tiles,
+                         const int32_t* count, const uint16_t* in, const uint8_t* flags,
+                         const float* pscale);
+
 /* The correction of one coarse step, in place on the handle's current
- * state: band tiles, patches of the uncorrected state, then the network and
- * the masked add fused per tile.  tiles / count / in / flags are scratch of
+ * state: ii_lbm_learned_tiles, ii_lbm_learned_patches of the uncorrected
+ * state, then ii_lbm_learned_infer.  tiles / count / in / flags are scratch of
  * the shapes above (n_inst * cap slots). */
 int ii_lbm_learned_correct(ii_lbm_handle* h, const float* params, const void* packed,
                            const ii_cnn_scales* sc, int32_t cap, int32_t* tiles, int32_t* count,

@@ -922,16 +922,17 @@ int ii_lbm_learned_apply(ii_lbm_handle* h, const ii_cnn_scales* sc, int32_t cap,
     return err(hipGetLastError());
 }
 
-int ii_lbm_learned_correct(ii_lbm_handle* h, const float* params, const void* packed,
-                           const ii_cnn_scales* sc, int32_t cap, int32_t* tiles, int32_t* count,
-                           uint16_t* in, uint8_t* flags, float* pscale)
+int ii_lbm_learned_infer(ii_lbm_handle* h, const float* params, const void* packed,
+                         const ii_cnn_scales* sc, int32_t cap, const int32_t* tiles,
+                         const int32_t* count, const uint16_t* in, const uint8_t* flags,
+                         const float* pscale)
 {
-    if (!params || !packed || !sc || !in || !flags || !pscale) return II_LBM_EINVAL;
-    int rc = ii_lbm_learned_tiles(h, cap, tiles, count);
-    if (rc) return rc;
-    if ((rc = ii_lbm_learned_patches(h, sc, cap, tiles, count, in, flags, pscale))) return rc;
     HandleView v;
-    handle_view(h, &v);
+    int rc = handle_view(h, &v);
+    if (rc) return rc;
+    if ((rc = check_learned(v))) return rc;
+    if (!params || !packed || !sc || !tiles || !count || !in || !flags || !pscale || cap < 1)
+        return II_LBM_EINVAL;
     const dim3 grid((unsigned)v.n_inst, (unsigned)std::min((int)cap, kSlotStride));
     if (v.inst[0].storage == II_LBM_FP16)
         hipLaunchKernelGGL(k_correct<_Float16>, grid, dim3(512), 0, v.stream, v.d_inst,
@@ -942,6 +943,17 @@ int ii_lbm_learned_correct(ii_lbm_handle* h, const float* params, const void* pa
                            v.P.lat[v.parity], params, (const u16*)packed, *sc, (int)cap,
                            (const int*)tiles, (const int*)count, (const u16*)in, flags, pscale);
     return err(hipGetLastError());
+}
+
+int ii_lbm_learned_correct(ii_lbm_handle* h, const float* params, const void* packed,
+                           const ii_cnn_scales* sc, int32_t cap, int32_t* tiles, int32_t* count,
+                           uint16_t* in, uint8_t* flags, float* pscale)
+{
+    if (!params || !packed || !sc || !in || !flags || !pscale) return II_LBM_EINVAL;
+    int rc = ii_lbm_learned_tiles(h, cap, tiles, count);
+    if (rc) return rc;
+    if ((rc = ii_lbm_learned_patches(h, sc, cap, tiles, count, in, flags, pscale))) return rc;
+    return ii_lbm_learned_infer(h, params, packed, sc, cap, tiles, count, in, flags, pscale);
 }
 
 }  // extern "C"

@@ -23,7 +23,7 @@ _SHAPES = [(3, 3, 4, 32), (32,), (3, 3, 32, 32), (32,), (3, 3, 32, 32), (32,), (
 EXPORTS = ["ii_cnn_packed_bytes", "ii_cnn_pack", "ii_cnn_save_bytes", "ii_cnn_forward",
            "ii_cnn_work_bytes", "ii_cnn_backward", "ii_cnn_adam", "ii_lbm_learned_tiles",
            "ii_lbm_learned_patches", "ii_lbm_learned_targets", "ii_lbm_learned_apply",
-           "ii_lbm_learned_correct"]
+           "ii_lbm_learned_correct", "ii_lbm_learned_infer"]
 
 
 class Scales(C.Structure):
@@ -59,6 +59,7 @@ def lib():
             "ii_lbm_learned_targets": ([v, v, S, i32, v, v, v, v, v, v], C.c_int),
             "ii_lbm_learned_apply": ([v, S, i32, v, v, v, v, v], C.c_int),
             "ii_lbm_learned_correct": ([v, v, v, S, i32, v, v, v, v, v], C.c_int),
+            "ii_lbm_learned_infer": ([v, v, v, S, i32, v, v, v, v, v], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -194,6 +195,12 @@ class Band:
         B.check(lib().ii_lbm_learned_correct(self.sim.h, _p(net.params), _p(net.packed), C.byref(sc),
                                              self.cap, _p(self.tiles), _p(self.count), _p(self.inp),
                                              _p(self.flags), _p(self.pscale)), "ii_lbm_learned_correct")
+
+    def infer(self, net: Net, sc: Scales) -> None:
+        """The network and the masked add on the patches of the last `patches`."""
+        B.check(lib().ii_lbm_learned_infer(self.sim.h, _p(net.params), _p(net.packed), C.byref(sc),
+                                           self.cap, _p(self.tiles), _p(self.count), _p(self.inp),
+                                           _p(self.flags), _p(self.pscale)), "ii_lbm_learned_infer")
 
     def slots(self):
         """Indices of the filled slots (host)."""

@@ -128,3 +128,4 @@ def test_learned_calls_reject_null_arguments_without_a_device():
     assert lib.ii_cnn_pack(None, None, None) == B.EINVAL
     assert lib.ii_cnn_forward(None, None, None, 1, None, None, None) == B.EINVAL
     assert lib.ii_lbm_learned_tiles(None, 16, None, None) == B.EINVAL
+    assert lib.ii_lbm_learned_infer(None, None, None, None, 16, None, None, None, None, None) == B.EINVAL

@@ -269,6 +269,56 @@ def test_correction_matches_oracle(mods):
     sim.close()
 
 
+def test_infer_over_many_tiles_matches_forward_and_apply(mods):
+    B, LN = mods
+    # a 512^2 instance lists more band tiles than one block per instance
+    # strides over, next to a 256^2 one
+    pairs = [W.learned_pair_c5(10003, L=256, n_markers=512), W.learned_pair_c5(10004, L=512, n_markers=1024)]
+    for c, _ in pairs:
+        c.problem.math = W.MATH_FP64
+    _say("correct == tiles + patches + infer (bit-exact) == training forward + apply, 256^2 and 512^2")
+    sims = [B.Sim([c.problem for c, _ in pairs], [c.X0 for c, _ in pairs]) for _ in range(3)]
+    for s in sims:
+        s.step(30)
+    Wt, b = _params(12, bias=0.2)
+    net, _, _ = _net(LN, Wt, b)
+    sc = LN.make_scales(**SC)
+    bands = [LN.Band(s) for s in sims]
+    bands[0].correct(net, sc)
+    bands[1].find()
+    bands[1].patches(sc)
+    bands[1].infer(net, sc)
+    bands[2].find()
+    bands[2].patches(sc)
+    out, _ = net.forward(bands[2].inp)
+    bands[2].apply(out, sc)
+    cnt = bands[0].count.cpu().numpy()
+    _say(f"  band tiles per instance {cnt.tolist()}")
+    assert cnt[1] > 64 and np.array_equal(cnt, bands[1].count.cpu().numpy())
+    f0 = [sims[0].fields(B.F_DISTRIB, inst=j) for j in range(2)]
+    for j in range(2):
+        assert np.array_equal(sims[1].fields(B.F_DISTRIB, inst=j), f0[j])
+    ref = [B.Sim([pairs[j][0].problem], [pairs[j][0].X0]) for j in range(2)]
+    for j, r in enumerate(ref):
+        r.step(30)
+        base = r.fields(B.F_DISTRIB)
+        d0 = f0[j] - base
+        d2 = sims[2].fields(B.F_DISTRIB, inst=j) - base
+        _say(f"  inst {j}: max |df| {np.abs(d0).max():.3e}, max diff {np.abs(d0 - d2).max():.3e}")
+        assert np.abs(d0).max() > 0
+        assert np.abs(d0 - d2).max() <= 1e-6 * np.abs(d0).max()
+        # every listed tile with a band node received a correction (its rest population)
+        sl = slice(j * bands[0].cap, j * bands[0].cap + cnt[j])
+        tl = bands[0].tiles.view(-1, 2).cpu().numpy()[sl]
+        has = (bands[0].flags.cpu().numpy()[sl, 4:20, 4:20] & 2).reshape(cnt[j], -1).any(axis=1)
+        hit = np.abs(d0[0]).reshape(r.problems[0].ny // 16, 16, r.problems[0].nx // 16, 16).max(axis=(1, 3))
+        assert has.sum() > 0.8 * cnt[j]
+        assert (hit[tl[has, 1], tl[has, 0]] > 0).all()
+        r.close()
+    for s in sims:
+        s.close()
+
+
 def test_training_reduces_the_loss(mods):
     import torch
     B, LN = mods
