@@ -90,7 +90,7 @@ int ii_cnn_adam(float* params, const float* grad, float* m, float* v, int32_t t,
  * int32); cap >= tiles per instance.
  * Instances must be periodic membranes whose sides are multiples of 16, with at
  * most 1024 tiles (EINVAL otherwise).  A patch near more chords than its
- * lists hold (512 within 8 lu, 16 crossings of one row) marks the instance,
+ * lists hold (256 within 8 lu, 16 crossings of one row) marks the instance,
  * which the next synchronising call reports as II_LBM_ECAPACITY. */
 int ii_lbm_learned_tiles(ii_lbm_handle* h, int32_t cap, int32_t* tiles, int32_t* count);
 
@@ -120,7 +120,8 @@ int ii_lbm_learned_apply(ii_lbm_handle* h, const ii_cnn_scales* sc, int32_t cap,
 /* The network and the masked add of ii_lbm_learned_apply, fused per tile,
  * on patches from ii_lbm_learned_patches of the same state (every patch
  * must be built before any tile is corrected: a tile's halo overlaps its
- * neighbours' nodes).  Tiles with no band node are skipped. */
+ * neighbours' nodes).  Tiles with no band node are skipped.  At most 4096
+ * instances per handle (EINVAL otherwise). */
 int ii_lbm_learned_infer(ii_lbm_handle* h, const float* params, const void* packed,
                          const ii_cnn_scales* sc, int32_t cap, const int32_t* tiles,
                          const int32_t* count, const uint16_t* in, const uint8_t* flags,

@@ -364,6 +364,7 @@ struct HandleView {
     int parity;              // lattice and marker buffers of the current state
     hipStream_t stream;
     int failed;
+    int n_cu;                // compute units of the handle's device
 };
 int handle_view(ii_lbm_handle* h, HandleView* v);
 

@@ -4,12 +4,13 @@
 // accumulation), its backward pass, Adam, training targets from a fine run,
 // and the fused per-tile correction (the C ABI of include/ii_learned.h).
 //
-// Convolutions are implicit GEMMs: a wave owns 16 output pixels (MFMA rows)
-// by 16 output channels (columns) and walks K = 9 taps x 32 input channels
-// in steps of 32, one tap per step, so that each lane's eight K values are
-// eight consecutive channels of one pixel: one 16-byte LDS read.  The B
-// fragments of a layer (at most 9 x 2) stay in registers for all of the
-// wave's output tiles.
+// Convolutions are implicit GEMMs: a wave owns 16 output channels (MFMA
+// rows, the weights) by 16 output pixels (columns) and walks K = 9 taps x 32
+// input channels in steps of 32, one tap per step, so that each lane's eight
+// K values are eight consecutive channels of one pixel: one 16-byte LDS
+// read.  Each lane ends with four consecutive output channels of one pixel,
+// written back as one 8-byte store.  The weight fragments of a layer (at
+// most 9 x 2) stay in registers for all of the wave's pixel tiles.
 #include <math.h>
 
 #include "common.hpp"
@@ -43,7 +44,7 @@ constexpr int kPacked = BOFF + 3 * BSIZE;
 // saved activations per patch: a1 | a2 | a3 (BF16, [pixel][32])
 constexpr int SAVE_OFF[4] = {0, 0, 15488, 28288};
 constexpr int kSave = 38656;
-constexpr int kMaxCand = 512;    // candidate chords per patch
+constexpr int kMaxCand = 256;    // candidate chords per patch
 constexpr float kBand = 4.0f, kClip = 8.0f;
 
 __device__ __forceinline__ u16 to_bf16(float f)
@@ -54,6 +55,14 @@ __device__ __forceinline__ u16 to_bf16(float f)
     return (u16)(u >> 16);
 }
 __device__ __forceinline__ float from_bf16(u16 h) { return __uint_as_float((unsigned)h << 16); }
+// two floats to packed BF16 (lo in the low half), round to nearest even
+// (v_cvt_pk_bf16_f32)
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ unsigned pack_bf16(float lo, float hi)
+{
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2{lo, hi}, bf16x2));
+}
 
 // ---------------------------------------------------------------------------
 // Packing
@@ -89,8 +98,11 @@ __global__ void k_pack(const float* __restrict__ prm, u16* __restrict__ out)
 //   FULL = false: out[q] = sum_t src[q + d_t] W_t   (valid, map HSRC -> HSRC-2)
 //   FULL = true:  out[q] = sum_t src[q - d_t] W'_t  (full, map HSRC -> HSRC+2,
 //                 reads outside the source are zero)
-// `src` is LDS [HSRC^2][CIN] BF16; epi(row, n, value) gets every output.
-// The layer's packed B fragments are staged once per block in LDS `wl`
+// `src` is LDS [HSRC^2][CIN] BF16.  The weights are the MFMA's first operand
+// (rows = output channels) and the pixels its second (columns), so that
+// each lane ends with four consecutive channels of one pixel:
+// epi(pixel, n0, v) gets channels n0 .. n0 + 3 of every output pixel.
+// The layer's packed weight fragments are staged once per block in LDS `wl`
 // (KS * NT * 512 elements) and then held in registers by every wave; the
 // caller separates two uses of `wl` by a barrier.
 // ---------------------------------------------------------------------------
@@ -100,9 +112,22 @@ template <int HSRC, int HDST, int CIN, int KS, int NT, bool FULL, class Epi>
 __device__ __forceinline__ void conv_mfma(const u16* src, const u16* __restrict__ frag, u16* wl,
                                           Epi epi)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, nwave = blockDim.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int g = lane >> 4;
     static_assert(KS * NT * 512 <= kWl, "fragment staging buffer");
+    // per-lane LDS offsets (elements) of the two taps of the 4-channel input
+    // layer: lane group g takes taps 8 ks + 2 g and + 1 (-1: past the 9 taps)
+    int toff[CIN == 4 ? KS : 1][2];
+    if (CIN == 4) {
+#pragma unroll
+        for (int ks = 0; ks < (CIN == 4 ? KS : 1); ks++)
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                const int t = 8 * ks + 2 * g + h;
+                toff[ks][h] = t < 9 ? ((t / 3) * HSRC + t % 3) * 4 : -1;
+            }
+    }
     // wl == nullptr: `frag` already points into LDS
     const u16* fr = frag;
     if (wl) {
@@ -119,8 +144,11 @@ __device__ __forceinline__ void conv_mfma(const u16* src, const u16* __restrict_
             b[ks][nt] = *(const bf16x8*)(fr + ((ks * NT + nt) * 64 + lane) * 8);
     constexpr int M = HDST * HDST, MT = (M + 15) / 16;
     for (int mt = wave; mt < MT; mt += nwave) {
-        const int p = min(mt * 16 + (lane & 15), M - 1);
+        const int pix = mt * 16 + (lane & 15);
+        const int p = min(pix, M - 1);
         const int py = p / HDST, px = p % HDST;
+        // the pixel's own source position; taps add compile-time offsets
+        const u16* sp = src + (py * HSRC + px) * CIN + (CIN == 32 ? 8 * g : 0);
         f32x4 acc[NT];
 #pragma unroll
         for (int nt = 0; nt < NT; nt++) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -129,29 +157,27 @@ __device__ __forceinline__ void conv_mfma(const u16* src, const u16* __restrict_
             bf16x8 a;
             if (CIN == 32) {
                 const int dy = ks / 3, dx = ks % 3;
-                int sy, sx;
+                int sy = 0, sx = 0;
                 bool ok = true;
                 if (FULL) {
                     sy = py - dy;
                     sx = px - dx;
                     ok = sy >= 0 && sy < HSRC && sx >= 0 && sx < HSRC;
-                } else {
-                    sy = py + dy;
-                    sx = px + dx;
                 }
-                if (ok) {
+                if (!FULL) {
+                    a = *(const bf16x8*)(sp + (dy * HSRC + dx) * 32);
+                } else if (ok) {
                     a = *(const bf16x8*)(src + (sy * HSRC + sx) * 32 + 8 * g);
                 } else {
 #pragma unroll
                     for (int j = 0; j < 8; j++) a[j] = (__bf16)0.0f;
                 }
             } else {
-                // four channels per tap: lane group g takes taps 8 ks + 2 g and + 1
+                // four channels per tap
 #pragma unroll
                 for (int h = 0; h < 2; h++) {
-                    const int t = 8 * ks + 2 * g + h;
                     uint2 v = make_uint2(0u, 0u);
-                    if (t < 9) v = *(const uint2*)(src + ((py + t / 3) * HSRC + px + t % 3) * 4);
+                    if (toff[CIN == 4 ? ks : 0][h] >= 0) v = *(const uint2*)(sp + toff[CIN == 4 ? ks : 0][h]);
                     a[4 * h + 0] = __builtin_bit_cast(__bf16, (u16)(v.x & 0xffffu));
                     a[4 * h + 1] = __builtin_bit_cast(__bf16, (u16)(v.x >> 16));
                     a[4 * h + 2] = __builtin_bit_cast(__bf16, (u16)(v.y & 0xffffu));
@@ -160,15 +186,12 @@ __device__ __forceinline__ void conv_mfma(const u16* src, const u16* __restrict_
             }
 #pragma unroll
             for (int nt = 0; nt < NT; nt++)
-                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[ks][nt], acc[nt], 0, 0, 0);
+                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[ks][nt], a, acc[nt], 0, 0, 0);
         }
+        if (pix < M) {
 #pragma unroll
-        for (int nt = 0; nt < NT; nt++)
-#pragma unroll
-            for (int j = 0; j < 4; j++) {
-                const int row = mt * 16 + 4 * g + j;
-                if (row < M) epi(row, 16 * nt + (lane & 15), acc[nt][j]);
-            }
+            for (int nt = 0; nt < NT; nt++) epi(pix, 16 * nt + 4 * g, acc[nt]);
+        }
     }
 }
 
@@ -180,10 +203,12 @@ __device__ __forceinline__ void hidden_layer(const u16* src, u16* dst, const u16
 {
     const float* bias = prm + OFF_B[L];
     conv_mfma<HS[L], HS[L + 1], CI[L], FKS[L], FNT[L], false>(
-        src, packed + FOFF[L], wl, [&](int row, int n, float v) {
-            const u16 h = to_bf16(fmaxf(v + bias[n], 0.f));
-            dst[row * 32 + n] = h;
-            if (save) save[row * 32 + n] = h;
+        src, packed + FOFF[L], wl, [&](int pix, int n0, f32x4 v) {
+            const float4 bb = *(const float4*)(bias + n0);
+            const uint2 h = make_uint2(pack_bf16(fmaxf(v[0] + bb.x, 0.f), fmaxf(v[1] + bb.y, 0.f)),
+                                       pack_bf16(fmaxf(v[2] + bb.z, 0.f), fmaxf(v[3] + bb.w, 0.f)));
+            *(uint2*)(dst + pix * 32 + n0) = h;
+            if (save) *(uint2*)(save + pix * 32 + n0) = h;
         });
 }
 
@@ -212,8 +237,10 @@ __global__ __launch_bounds__(256) void k_forward(const float* __restrict__ prm,
     __syncthreads();
     const float* b4 = prm + OFF_B[3];
     float* o = out + n * (kOut * kOut * 9);
-    conv_mfma<18, 16, 32, 9, 1, false>(by, packed + FOFF[3], wl, [&](int row, int c, float v) {
-        if (c < 9) o[row * 9 + c] = v + b4[c];
+    conv_mfma<18, 16, 32, 9, 1, false>(by, packed + FOFF[3], wl, [&](int pix, int n0, f32x4 v) {
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+            if (n0 + j < 9) o[pix * 9 + n0 + j] = v[j] + b4[n0 + j];
     });
 }
 
@@ -278,8 +305,14 @@ __device__ __forceinline__ void data_grad(const u16* dz_next, const u16* a, u16*
                                           const u16* __restrict__ packed, u16* wl)
 {
     conv_mfma<HS[L + 1], HS[L], 32, 9, 2, true>(
-        dz_next, packed + BOFF + (L - 1) * BSIZE, wl, [&](int row, int n, float v) {
-            dz[row * 32 + n] = a[row * 32 + n] != 0 && !(a[row * 32 + n] & 0x8000u) ? to_bf16(v) : 0;
+        dz_next, packed + BOFF + (L - 1) * BSIZE, wl, [&](int pix, int n0, f32x4 v) {
+            // ReLU'(z) from the saved activation: zero where a <= 0
+            const uint2 av = *(const uint2*)(a + pix * 32 + n0);
+            const unsigned ah[4] = {av.x & 0xffffu, av.x >> 16, av.y & 0xffffu, av.y >> 16};
+            float w[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) w[j] = ah[j] != 0 && !(ah[j] & 0x8000u) ? v[j] : 0.f;
+            *(uint2*)(dz + pix * 32 + n0) = make_uint2(pack_bf16(w[0], w[1]), pack_bf16(w[2], w[3]));
         });
 }
 
@@ -431,16 +464,24 @@ __global__ void k_band_tiles(const InstDev* __restrict__ insts, const double2* _
 constexpr int kRowCap = 16;   // crossings of one patch row inside the patch
 
 struct PatchShared {
-    float4 cand[kMaxCand];        // chords within 8 lu of the patch, relative, sorted by min y
+    float4 cand[kMaxCand];        // chords (a, b - a) within 8 lu of the patch, relative,
+                                  // sorted by min y
+    float cinv[kMaxCand];         // 1 / |b - a|^2 (0 for a degenerate chord)
     float cmin[kMaxCand];         // their min y
-    float4 tmp[kMaxCand];         // unsorted staging
+    union {
+        struct {
+            float4 tmp[kMaxCand];   // unsorted staging
+            float tkey[kMaxCand];   // and its min y
+        };
+        float raw[kPatch * kPatch][3];   // scaled rho - 1, u_x, u_y (after the sort)
+    };
     float rowx[kPatch][kRowCap];  // x of the crossings of each patch row inside the patch
     int rown[kPatch];             // their count
     int rowpar[kPatch];           // parity of the crossings right of the patch
-    float raw[kPatch * kPatch][3];  // scaled rho - 1, u_x, u_y
-    float red[256];
+    float red[16];
     int ncand, overflow;
 };
+constexpr int kPatchThreads = 256;
 
 // Features of the 24 x 24 patch around tile (tx, ty): BF16 input and flags
 // (bit 0 inside, bit 1 band).
@@ -491,11 +532,14 @@ __device__ void build_patch(const InstDev& I, const T* __restrict__ A, const dou
         if (fmax(a.x, b.x) >= ox - m && fmin(a.x, b.x) <= ox + kPatch - 1 + m && hi >= oy - m &&
             lo <= oy + kPatch - 1 + m) {
             const int c = atomicAdd(&S.ncand, 1);
-            if (c < kMaxCand)
-                S.tmp[c] = make_float4((float)(a.x - ox), (float)(a.y - oy), (float)(b.x - ox),
-                                       (float)(b.y - oy));
-            else
+            if (c < kMaxCand) {
+                const float ax = (float)(a.x - ox), ay = (float)(a.y - oy);
+                const float bx = (float)(b.x - ox), by = (float)(b.y - oy);
+                S.tmp[c] = make_float4(ax, ay, bx - ax, by - ay);
+                S.tkey[c] = fminf(ay, by);
+            } else {
                 S.overflow = 1;
+            }
         }
     }
     __syncthreads();
@@ -503,19 +547,28 @@ __device__ void build_patch(const InstDev& I, const T* __restrict__ A, const dou
     // rank sort by the lowest y (ties by position in the staging list)
     for (int c = threadIdx.x; c < nc; c += blockDim.x) {
         const float4 v = S.tmp[c];
-        const float key = fminf(v.y, v.w);
+        const float key = S.tkey[c];
         int r = 0;
         for (int d = 0; d < nc; d++) {
-            const float kd = fminf(S.tmp[d].y, S.tmp[d].w);
+            const float kd = S.tkey[d];
             r += (kd < key || (kd == key && d < c)) ? 1 : 0;
         }
+        const float ll = v.z * v.z + v.w * v.w;
         S.cand[r] = v;
+        S.cinv[r] = ll > 0.f ? 1.f / ll : 0.f;
         S.cmin[r] = key;
     }
     __syncthreads();
     for (int q = threadIdx.x; q < kPatch * kPatch; q += blockDim.x) {
         const int py = q / kPatch, px = q % kPatch;
         const float fx = (float)px, fy = (float)py;
+        // the node's pulled distributions (periodic wrap) are loaded first so
+        // that they arrive during the distance search
+        int gx = (ox + px) % I.nx, gy = (oy + py) % I.ny;
+        if (gx < 0) gx += I.nx;
+        if (gy < 0) gy += I.ny;
+        float d[9];
+        pull<T, float>(I, A, gx, gy, d);
         // chords reach at most 2 lu, so those within 8 of the row have their
         // lowest y in [py - 10, py + 8]
         int lo = 0, hi = nc;
@@ -536,11 +589,9 @@ __device__ void build_patch(const InstDev& I, const T* __restrict__ A, const dou
         float d2 = kClip * kClip;
         for (int c = lo; c < hi; c++) {
             const float4 s = S.cand[c];
-            const float dx = s.z - s.x, dy = s.w - s.y;
-            const float ll = dx * dx + dy * dy;
-            float t = ((fx - s.x) * dx + (fy - s.y) * dy) / ll;
+            float t = ((fx - s.x) * s.z + (fy - s.y) * s.w) * S.cinv[c];
             t = fminf(fmaxf(t, 0.f), 1.f);
-            const float qx = s.x + t * dx - fx, qy = s.y + t * dy - fy;
+            const float qx = s.x + t * s.z - fx, qy = s.y + t * s.w - fy;
             d2 = fminf(d2, qx * qx + qy * qy);
         }
         int ins = S.rowpar[py];
@@ -548,12 +599,6 @@ __device__ void build_patch(const InstDev& I, const T* __restrict__ A, const dou
         for (int c = 0; c < nr; c++) ins ^= S.rowx[py][c] > fx ? 1 : 0;
         const float dist = sqrtf(d2);
         const float sd = ins ? -dist : dist;
-        // moments of the pulled distributions at the node (periodic wrap)
-        int gx = (ox + px) % I.nx, gy = (oy + py) % I.ny;
-        if (gx < 0) gx += I.nx;
-        if (gy < 0) gy += I.ny;
-        float d[9];
-        pull<T, float>(I, A, gx, gy, d);
         float r, ux, uy;
         moments<float>(d, r, ux, uy);
         S.raw[q][0] = r * sc.in_scale[0];
@@ -566,13 +611,13 @@ __device__ void build_patch(const InstDev& I, const T* __restrict__ A, const dou
     float ss = 0.f;
     for (int q = threadIdx.x; q < kPatch * kPatch; q += blockDim.x)
         ss += S.raw[q][0] * S.raw[q][0] + S.raw[q][1] * S.raw[q][1] + S.raw[q][2] * S.raw[q][2];
-    S.red[threadIdx.x] = ss;
+    // per-wave sums, then the waves' sums in order
+    for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o);
+    if ((threadIdx.x & 63) == 0) S.red[threadIdx.x >> 6] = ss;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) S.red[threadIdx.x] += S.red[threadIdx.x + w];
-        __syncthreads();
-    }
-    const float amp = fmaxf(sqrtf(S.red[0] / (float)(kPatch * kPatch)), 1e-6f);
+    float tot = 0.f;
+    for (int w = 0; w < (int)(blockDim.x >> 6); w++) tot += S.red[w];
+    const float amp = fmaxf(sqrtf(tot / (float)(kPatch * kPatch)), 1e-6f);
     const float inv = 1.f / amp;
     for (int q = threadIdx.x; q < kPatch * kPatch; q += blockDim.x) {
         in[q * 4 + 0] = to_bf16(S.raw[q][0] * inv);
@@ -593,7 +638,7 @@ __device__ void build_patch(const InstDev& I, const T* __restrict__ A, const dou
 constexpr int kSlotStride = 64;
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_patches(const InstDev* __restrict__ insts, const void* A0,
+__global__ __launch_bounds__(kPatchThreads) void k_patches(const InstDev* __restrict__ insts, const void* A0,
                                                  const double2* __restrict__ Xall, ii_cnn_scales sc,
                                                  int cap, const int* __restrict__ tiles,
                                                  const int* __restrict__ count, u16* __restrict__ in,
@@ -657,13 +702,21 @@ __global__ void k_targets(const InstDev* __restrict__ ic, const void* Ac,
     mask[slot * (kOut * kOut) + q] = (fl & 2) ? 1 : 0;
 }
 
-// The network and the masked add of one coarse step, one block of eight
-// waves per band tile, on the patches that k_patches built from the state
-// before any tile was corrected (a tile's halo overlaps its neighbours'
-// nodes).  The B fragments come straight from L2 into registers.
+// The network and the masked add of one coarse step on the patches that
+// k_patches built from the state before any tile was corrected (a tile's
+// halo overlaps its neighbours' nodes).  Persistent: one block of twelve
+// waves per compute unit (LDS holds one block's buffers and fragments)
+// stages every forward weight fragment in LDS once and
+// then walks the band tiles of all instances, listed instance by instance,
+// in a grid stride, so that the work is balanced and no layer waits on L2
+// for its fragments.
+constexpr int kMaxInstLds = 4096;   // instances whose tile offsets fit in LDS
+constexpr int kFwdFrag = FOFF[3] + 9 * 512;
+constexpr int kCorrThreads = 768;   // twelve waves: three per SIMD
+
 template <typename T>
-__global__ __launch_bounds__(512) void k_correct(const InstDev* __restrict__ insts, void* A0,
-                                                 const float* __restrict__ prm,
+__global__ __launch_bounds__(kCorrThreads) void k_correct(const InstDev* __restrict__ insts, int n_inst,
+                                                 void* A0, const float* __restrict__ prm,
                                                  const u16* __restrict__ packed, ii_cnn_scales sc,
                                                  int cap, const int* __restrict__ tiles,
                                                  const int* __restrict__ count,
@@ -671,56 +724,123 @@ __global__ __launch_bounds__(512) void k_correct(const InstDev* __restrict__ ins
                                                  const uint8_t* __restrict__ flags,
                                                  const float* __restrict__ pscale)
 {
-    const int inst = blockIdx.x, n = count[inst];
-    if ((int)blockIdx.y >= n) return;
-    const InstDev I = insts[inst];
     __shared__ __align__(16) u16 bx[20 * 20 * 32];
     __shared__ __align__(16) u16 by[22 * 22 * 32];
-    __shared__ uint8_t fl[kPatch * kPatch];
-    T* A = (T*)A0;
-    for (int r = blockIdx.y; r < n; r += gridDim.y) {
-        if (r != (int)blockIdx.y) __syncthreads();   // the previous tile is done with the buffers
-        const long long slot = (long long)inst * cap + r;
-        const int2 t = ((const int2*)tiles)[slot];
-        {
-            const unsigned* src = (const unsigned*)(in + slot * (kPatch * kPatch * 4));
-            for (int e = threadIdx.x; e < kPatch * kPatch * 2; e += blockDim.x) ((unsigned*)bx)[e] = src[e];
-            for (int e = threadIdx.x; e < kPatch * kPatch; e += blockDim.x)
-                fl[e] = flags[slot * (kPatch * kPatch) + e];
+    __shared__ __align__(16) u16 wf[kFwdFrag];
+    __shared__ int first[kMaxInstLds + 1];   // first[j]: band tiles of instances < j
+    __shared__ __align__(16) u16 pin[2][kPatch * kPatch * 4];   // input patches, double buffered
+    __shared__ __align__(4) uint8_t pfl[2][kPatch * kPatch];     // and their flags
+    for (int e = threadIdx.x; e < kFwdFrag / 8; e += blockDim.x)
+        ((uint4*)wf)[e] = ((const uint4*)packed)[e];
+    // exclusive scan of the counts, one block width at a time
+    __shared__ int part[kCorrThreads];
+    int carry = 0;
+    for (int j0 = 0; j0 < n_inst; j0 += kCorrThreads) {
+        const int j = j0 + threadIdx.x;
+        const int c = j < n_inst ? min(count[j], cap) : 0;
+        part[threadIdx.x] = c;
+        __syncthreads();
+        for (int o = 1; o < kCorrThreads; o <<= 1) {
+            const int v = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+            __syncthreads();
+            part[threadIdx.x] += v;
+            __syncthreads();
         }
+        if (j < n_inst) first[j + 1] = carry + part[threadIdx.x];
+        carry += part[kCorrThreads - 1];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) first[0] = 0;
+    __syncthreads();
+    const int total = first[n_inst];
+    // slot of the k-th band tile: its instance is the last j with first[j] <= k
+    auto slot_of = [&](int k, int& inst) -> long long {
+        int lo = 0, hi = n_inst;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (first[mid] <= k) lo = mid; else hi = mid;
+        }
+        inst = __builtin_amdgcn_readfirstlane(lo);
+        return (long long)inst * cap + (k - first[inst]);
+    };
+    // a patch and its flags are 1152 + 144 dwords: two and at most one per thread
+    constexpr int kInW = kPatch * kPatch * 2, kFlW = kPatch * kPatch / 4;
+    static_assert(kInW <= 2 * kCorrThreads && kFlW <= kCorrThreads, "patch staging");
+    unsigned r0 = 0, r1 = 0, rf = 0;
+    auto fetch = [&](long long slot) {
+        const unsigned* si = (const unsigned*)(in + slot * (kPatch * kPatch * 4));
+        const unsigned* sf = (const unsigned*)(flags + slot * (kPatch * kPatch));
+        r0 = si[threadIdx.x];
+        if (threadIdx.x + kCorrThreads < kInW) r1 = si[threadIdx.x + kCorrThreads];
+        if (threadIdx.x < kFlW) rf = sf[threadIdx.x];
+    };
+    auto stage = [&](int b) {
+        ((unsigned*)pin[b])[threadIdx.x] = r0;
+        if (threadIdx.x + kCorrThreads < kInW) ((unsigned*)pin[b])[threadIdx.x + kCorrThreads] = r1;
+        if (threadIdx.x < kFlW) ((unsigned*)pfl[b])[threadIdx.x] = rf;
+    };
+    T* A = (T*)A0;
+    int cur = 0;
+    if ((int)blockIdx.x < total) {
+        int inst;
+        fetch(slot_of(blockIdx.x, inst));
+        stage(0);
+    }
+    for (int k = blockIdx.x; k < total; k += gridDim.x) {
+        __syncthreads();   // pin[cur] staged; the previous tile is done with every buffer
+        int inst;
+        const long long slot = slot_of(k, inst);
+        const InstDev I = insts[inst];
+        const int2 t = ((const int2*)tiles)[slot];
+        const float os = sc.out_scale * pscale[slot];
+        // the next tile's patch travels while this one is computed
+        const int kn = k + gridDim.x;
+        if (kn < total) {
+            int in_n;
+            fetch(slot_of(kn, in_n));
+        }
+        const uint8_t* fl = pfl[cur];
         // a tile whose output nodes all lie outside the band gets no correction
         int any = 0;
         if (threadIdx.x < kOut * kOut) {
             const int oy = threadIdx.x / kOut, ox = threadIdx.x % kOut;
-            any = flags[slot * (kPatch * kPatch) + (oy + kHalo) * kPatch + ox + kHalo] & 2;
+            any = fl[(oy + kHalo) * kPatch + ox + kHalo] & 2;
         }
-        if (!__syncthreads_or(any)) continue;
-        hidden_layer<0>(bx, by, packed, prm, nullptr, nullptr);
-        __syncthreads();
-        hidden_layer<1>(by, bx, packed, prm, nullptr, nullptr);
-        __syncthreads();
-        hidden_layer<2>(bx, by, packed, prm, nullptr, nullptr);
-        __syncthreads();
-        const float* b4 = prm + OFF_B[3];
-        const float os = sc.out_scale * pscale[slot];
-        T* base = A + I.lat_off;
-        conv_mfma<18, 16, 32, 9, 1, false>(by, packed + FOFF[3], nullptr, [&](int row, int c, float v) {
-            if (c >= 9) return;
-            const int oy = row / kOut, ox = row % kOut;
-            const int q = (oy + kHalo) * kPatch + ox + kHalo;
-            const uint8_t f = fl[q];
-            if (!(f & 2)) return;
-            if (c != 0) {
-                const uint8_t fs = fl[q - EY[c] * kPatch - EX[c]];
-                if ((fs & 1) != (f & 1)) return;   // a link across the polygon
-            }
-            // pre-collision f_c(x) is the value stored at x - e_c
-            int x = t.x * kTile + ox - EX[c], y = t.y * kTile + oy - EY[c];
-            x = x < 0 ? x + I.nx : (x >= I.nx ? x - I.nx : x);
-            y = y < 0 ? y + I.ny : (y >= I.ny ? y - I.ny : y);
-            T* p = base + c * I.plane + (long long)y * I.pitch + x;
-            Store<T>::st(p, Store<T>::ld(p, I.scale) + os * (v + b4[c]), I.inv_scale);
-        });
+        if (__syncthreads_or(any)) {
+            hidden_layer<0>(pin[cur], by, wf, prm, nullptr, nullptr);
+            __syncthreads();
+            hidden_layer<1>(by, bx, wf, prm, nullptr, nullptr);
+            __syncthreads();
+            hidden_layer<2>(bx, by, wf, prm, nullptr, nullptr);
+            __syncthreads();
+            const float* b4 = prm + OFF_B[3];
+            T* base = A + I.lat_off;
+            conv_mfma<18, 16, 32, 9, 1, false>(by, wf + FOFF[3], nullptr, [&](int pix, int n0, f32x4 v) {
+                if (n0 >= 9) return;
+                const int oy = pix / kOut, ox = pix % kOut;
+                const int q = (oy + kHalo) * kPatch + ox + kHalo;
+                const uint8_t f = fl[q];
+                if (!(f & 2)) return;
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    const int c = n0 + j;
+                    if (c >= 9) break;
+                    if (c != 0) {
+                        const uint8_t fs = fl[q - EY[c] * kPatch - EX[c]];
+                        if ((fs & 1) != (f & 1)) continue;   // a link across the polygon
+                    }
+                    // pre-collision f_c(x) is the value stored at x - e_c (no
+                    // other tile touches it)
+                    int x = t.x * kTile + ox - EX[c], y = t.y * kTile + oy - EY[c];
+                    x = x < 0 ? x + I.nx : (x >= I.nx ? x - I.nx : x);
+                    y = y < 0 ? y + I.ny : (y >= I.ny ? y - I.ny : y);
+                    T* p = base + c * I.plane + (long long)y * I.pitch + x;
+                    Store<T>::st(p, Store<T>::ld(p, I.scale) + os * (v[j] + b4[c]), I.inv_scale);
+                }
+            });
+        }
+        if (kn < total) stage(cur ^ 1);
+        cur ^= 1;
     }
 }
 
@@ -857,11 +977,11 @@ int ii_lbm_learned_patches(ii_lbm_handle* h, const ii_cnn_scales* sc, int32_t ca
     if (!sc || !tiles || !count || !in || !flags || !pscale || cap < 1) return II_LBM_EINVAL;
     const dim3 grid((unsigned)v.n_inst, (unsigned)std::min((int)cap, kSlotStride));
     if (v.inst[0].storage == II_LBM_FP16)
-        hipLaunchKernelGGL(k_patches<_Float16>, grid, dim3(256), 0, v.stream, v.d_inst,
+        hipLaunchKernelGGL(k_patches<_Float16>, grid, dim3(kPatchThreads), 0, v.stream, v.d_inst,
                            v.P.lat[v.parity], v.P.X[v.parity], *sc, (int)cap, (const int*)tiles,
                            (const int*)count, (u16*)in, flags, pscale, v.P.err);
     else
-        hipLaunchKernelGGL(k_patches<float>, grid, dim3(256), 0, v.stream, v.d_inst,
+        hipLaunchKernelGGL(k_patches<float>, grid, dim3(kPatchThreads), 0, v.stream, v.d_inst,
                            v.P.lat[v.parity], v.P.X[v.parity], *sc, (int)cap, (const int*)tiles,
                            (const int*)count, (u16*)in, flags, pscale, v.P.err);
     return err(hipGetLastError());
@@ -933,13 +1053,14 @@ int ii_lbm_learned_infer(ii_lbm_handle* h, const float* params, const void* pack
     if ((rc = check_learned(v))) return rc;
     if (!params || !packed || !sc || !tiles || !count || !in || !flags || !pscale || cap < 1)
         return II_LBM_EINVAL;
-    const dim3 grid((unsigned)v.n_inst, (unsigned)std::min((int)cap, kSlotStride));
+    if (v.n_inst > kMaxInstLds) return II_LBM_EINVAL;
+    const dim3 grid((unsigned)std::max(1, v.n_cu));
     if (v.inst[0].storage == II_LBM_FP16)
-        hipLaunchKernelGGL(k_correct<_Float16>, grid, dim3(512), 0, v.stream, v.d_inst,
+        hipLaunchKernelGGL(k_correct<_Float16>, grid, dim3(kCorrThreads), 0, v.stream, v.d_inst, v.n_inst,
                            v.P.lat[v.parity], params, (const u16*)packed, *sc, (int)cap,
                            (const int*)tiles, (const int*)count, (const u16*)in, flags, pscale);
     else
-        hipLaunchKernelGGL(k_correct<float>, grid, dim3(512), 0, v.stream, v.d_inst,
+        hipLaunchKernelGGL(k_correct<float>, grid, dim3(kCorrThreads), 0, v.stream, v.d_inst, v.n_inst,
                            v.P.lat[v.parity], params, (const u16*)packed, *sc, (int)cap,
                            (const int*)tiles, (const int*)count, (const u16*)in, flags, pscale);
     return err(hipGetLastError());

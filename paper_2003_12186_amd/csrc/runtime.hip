@@ -509,6 +509,7 @@ int handle_view(ii_lbm_handle* h, HandleView* v)
     v->parity = h->parity;
     v->stream = h->stream;
     v->failed = h->failed;
+    v->n_cu = h->n_cu;
     return II_LBM_OK;
 }
 }  // namespace iilbm
