@@ -71,6 +71,28 @@ def cpu_baseline(w, steps: int):
                       f"({dt:.1f} s)"}
 
 
+def cnn_flops(flags, listed):
+    """Algorithmic FLOPs of the network kernel over the listed band tiles:
+    per layer, the pixel tiles (16 outputs) that hold a row feeding an output
+    row with a band node, each output pixel 2 x 9 x c_in x c_out FLOP."""
+    import torch
+    band = (flags[:, 4:20, 4:20] & 2) != 0
+    rows = [band.any(dim=2) & listed[:, None]]          # output rows with a band node
+    for _ in range(3):                                   # rows of the layers below
+        m = rows[0]
+        z1 = torch.zeros_like(m[:, :1])
+        rows.insert(0, torch.cat([m, z1, z1], 1) | torch.cat([z1, m, z1], 1) | torch.cat([z1, z1, m], 1))
+    total = torch.zeros((), dtype=torch.float64, device=flags.device)
+    for m, h, ci, co in zip(rows, (22, 20, 18, 16), (4, 32, 32, 32), (32, 32, 32, 9)):
+        n_pix = h * h
+        mt = torch.arange((n_pix + 15) // 16, device=flags.device)
+        r0, r1 = mt * 16 // h, torch.clamp(mt * 16 + 15, max=n_pix - 1) // h
+        need = m[:, r0] | m[:, r1]
+        pix = torch.clamp(n_pix - mt * 16, max=16).to(torch.float64)
+        total += (need.to(torch.float64) * pix).sum() * (2 * 9 * ci * co)
+    return total, (rows[-1].any(dim=1)).sum()
+
+
 def cpu_baseline_learned(w, net_file: str, steps: int):
     """The FP64 oracle's corrected coarse step on one instance: a method step,
     features of the whole field, the network on every band tile, the masked
@@ -117,12 +139,14 @@ def cpu_baseline_learned(w, net_file: str, steps: int):
 def bench_learned(args, B, W) -> int:
     """Learned correction of 2x-coarsened membranes: held-out coarse/fine
     pairs (256^2 / 512^2, 512 markers, diffusive scaling) batched in one
-    handle per resolution.  Timed: K coarse steps each followed by the
-    correction (band tiles, patches, network + masked add), next to 4K fine
-    steps (HIP graphs) covering the same physical time.  The correction is
+    handle per resolution.  Timed: K coarse steps with the correction
+    registered on the handle (band tiles, patches, network + masked add
+    inside every step, direct launches), next to 4K fine steps (HIP graphs)
+    covering the same physical time; beside them, the same K steps with the
+    correction called after each step from the host.  The correction is
     scaled by alpha = 0: every kernel runs in full and adds zero, so the
     trajectory and the timing do not depend on the network's stability.  The
-    network kernel's roofline comes from a second pass with HIP events around
+    network kernel's roofline comes from a last pass with HIP events around
     each of its launches."""
     import numpy as np
     import torch
@@ -134,26 +158,37 @@ def bench_learned(args, B, W) -> int:
     net = LN.Net(d["params"])
     sc = LN.make_scales(d["in_scale"], 0.0)
     sl = B.Sim([c.problem for c, _ in pairs], [c.X0 for c, _ in pairs], device="cuda:0")
+    sm = B.Sim([c.problem for c, _ in pairs], [c.X0 for c, _ in pairs], device="cuda:0")
     sp = B.Sim([c.problem for c, _ in pairs], [c.X0 for c, _ in pairs], device="cuda:0")
     sf = B.Sim([f.problem for _, f in pairs], [f.X0 for _, f in pairs], device="cuda:0")
-    sp.set_graph(True)
-    sf.set_graph(True)
+    # the handle's three streams overlap when launched directly; graph
+    # replays of the corrected step run its branches one after another
+    for s in (sp, sf):
+        s.set_graph(True)
     band = LN.Band(sl)
+    band.attach(net, sc)
+    bm = LN.Band(sm)
+    sl.step(args.warmup)
     for _ in range(args.warmup):
-        sl.step(1)
-        band.correct(net, sc)
+        sm.step(1)
+        bm.correct(net, sc)
     sp.step(args.warmup)
     sf.step(4 * args.warmup)
-    for s in (sl, sp, sf):
+    for s in (sl, sm, sp, sf):
         s.sync()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        sl.step(1)
-        band.correct(net, sc)
+    sl.step(args.steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     sl.sync()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sm.step(1)
+        bm.correct(net, sc)
+    torch.cuda.synchronize()
+    dt_manual = time.perf_counter() - t0
+    sm.sync()
     t0 = time.perf_counter()
     sp.step(args.steps)
     torch.cuda.synchronize()
@@ -163,9 +198,11 @@ def bench_learned(args, B, W) -> int:
     torch.cuda.synchronize()
     dt_fine = time.perf_counter() - t0
     # event-timed network launches on the same trajectory
+    band.detach()
     n_t = min(args.steps, 200)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_t)]
     run_tiles = torch.zeros((), dtype=torch.int64, device="cuda:0")
+    run_flop = torch.zeros((), dtype=torch.float64, device="cuda:0")
     pix = torch.arange(band.cap, device="cuda:0")
     for k in range(n_t):
         sl.step(1)
@@ -174,16 +211,19 @@ def bench_learned(args, B, W) -> int:
         ev[k][0].record(sl.stream)
         band.infer(net, sc)
         ev[k][1].record(sl.stream)
-        # tiles that run the network: listed, with a band node among their outputs
+        # tiles that run the network (listed, with a band node among their
+        # outputs) and the layers' pixel tiles that feed such outputs
         listed = (pix[None, :] < band.count[:, None]).reshape(-1)
-        has = (band.flags[:, 4:20, 4:20] & 2).reshape(band.flags.shape[0], -1).amax(dim=1) > 0
-        run_tiles += (listed & has).sum()
+        fl, nt = cnn_flops(band.flags, listed)
+        run_flop += fl
+        run_tiles += nt
     torch.cuda.synchronize()
     sl.sync()
     t_infer = sum(a.elapsed_time(b) for a, b in ev) / 1e3
     tiles = int(run_tiles.item())
+    flop = float(run_flop.item())
     avg = t_infer / n_t
-    achieved = tiles / n_t * CNN_FLOP_PER_TILE / avg / 1e12
+    achieved = flop / n_t / avg / 1e12
     nodes = sum(c.problem.nx * c.problem.ny for c, _ in pairs)
     nodes_f = sum(f.problem.nx * f.problem.ny for _, f in pairs)
     out = {
@@ -195,19 +235,22 @@ def bench_learned(args, B, W) -> int:
         "data": "synthetic",
         "config": {"workload": f"learned_c5_{n}", "instances": n, "coarse": 256, "fine": 512,
                    "markers": 512, "fine_steps_per_coarse": 4, "alpha": 0.0,
-                   "t_corrected_coarse_s": round(dt, 4), "t_plain_coarse_s": round(dt_plain, 4),
+                   "t_corrected_coarse_s": round(dt, 4),
+                   "t_corrected_coarse_host_calls_s": round(dt_manual, 4),
+                   "t_plain_coarse_s": round(dt_plain, 4),
                    "t_fine_s": round(dt_fine, 4), "speedup_vs_fine": round(dt_fine / dt, 3),
                    "fine_mlups": round(nodes_f * 4 * args.steps / dt_fine / 1e6, 1),
                    "plain_coarse_mlups": round(nodes * args.steps / dt_plain / 1e6, 1)},
         "roofline": {"bound": "mfma", "kernel": "k_correct", "achieved": round(achieved, 2),
                      "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / BF16_PEAK_TFLOPS, 4), "traffic": None,
-                     "flop_per_tile": CNN_FLOP_PER_TILE, "tiles_per_launch": round(tiles / n_t, 1),
+                     "flop_per_launch": round(flop / n_t), "dense_flop_per_tile": CNN_FLOP_PER_TILE,
+                     "tiles_per_launch": round(tiles / n_t, 1),
                      "avg_launch_us": round(avg * 1e6, 2), "timed_launches": n_t},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline_learned(pairs[0][0], LEARNED_WEIGHTS, args.cpu_steps)
-    for s in (sl, sp, sf):
+    for s in (sl, sm, sp, sf):
         s.close()
     print(json.dumps(out), flush=True)
     return 0

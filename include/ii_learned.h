@@ -135,6 +135,23 @@ int ii_lbm_learned_correct(ii_lbm_handle* h, const float* params, const void* pa
                            const ii_cnn_scales* sc, int32_t cap, int32_t* tiles, int32_t* count,
                            uint16_t* in, uint8_t* flags, float* pscale);
 
+/* Registers the correction of ii_lbm_learned_correct to be applied by the
+ * handle at the end of every step (ii_lbm_step), so that the state after n
+ * steps is that of n rounds of ii_lbm_step(h, 1) followed by
+ * ii_lbm_learned_correct with the same arguments.  Inside a step:
+ *  - band tiles and patch geometry need only the moved markers and run on
+ *    an internal stream beside the sweep and the interface pass;
+ *  - patch flow and the network + masked add follow the sweep on the
+ *    handle's stream, beside the interface pass of the next step (which
+ *    does not read the lattice).
+ * Steps replayed as HIP graphs include the correction.  params, packed and
+ * the scratch buffers (as for ii_lbm_learned_correct) must stay valid while
+ * registered; *sc is copied.  params == NULL unregisters.  EINVAL as for
+ * ii_lbm_learned_infer. */
+int ii_lbm_set_learned(ii_lbm_handle* h, const float* params, const void* packed,
+                       const ii_cnn_scales* sc, int32_t cap, int32_t* tiles, int32_t* count,
+                       uint16_t* in, uint8_t* flags, float* pscale);
+
 #ifdef __cplusplus
 }
 #endif

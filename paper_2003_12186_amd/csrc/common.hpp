@@ -12,7 +12,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "../../include/ii_lbm.h"
+#include "../../include/ii_learned.h"
 
 namespace iilbm {
 
@@ -367,6 +367,29 @@ struct HandleView {
     int n_cu;                // compute units of the handle's device
 };
 int handle_view(ii_lbm_handle* h, HandleView* v);
+
+// The learned coarse correction: network, scales and the caller's scratch
+// (tiles, counts, patches, flags, amplitudes of n_inst * cap slots).
+struct LearnedCfg {
+    bool on = false;
+    const float* params = nullptr;
+    const void* packed = nullptr;
+    ii_cnn_scales sc{};
+    int cap = 0;
+    int* tiles = nullptr;
+    int* count = nullptr;
+    uint16_t* in = nullptr;
+    uint8_t* flags = nullptr;
+    float* pscale = nullptr;
+};
+// Its phases (learned.hip), enqueued on v.stream for the state of plane
+// v.parity: band tiles and patch geometry need only the markers, patch flow
+// only the lattice, and the network + masked add both of those.
+int learned_validate(const HandleView& v, int cap);
+hipError_t learned_band(const HandleView& v, const LearnedCfg& c);
+hipError_t learned_geom(const HandleView& v, const LearnedCfg& c);
+hipError_t learned_flow(const HandleView& v, const LearnedCfg& c);
+hipError_t learned_infer(const HandleView& v, const LearnedCfg& c);
 
 // ---------------------------------------------------------------------------
 // Launch helpers implemented in the .hip files (host side).

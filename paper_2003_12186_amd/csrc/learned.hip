@@ -108,9 +108,11 @@ __global__ void k_pack(const float* __restrict__ prm, u16* __restrict__ out)
 // ---------------------------------------------------------------------------
 constexpr int kWl = 9 * 2 * 512;
 
+// `rows`: bit r set when output row r is needed; a pixel tile none of whose
+// rows is needed is skipped (its outputs are left as they are).
 template <int HSRC, int HDST, int CIN, int KS, int NT, bool FULL, class Epi>
 __device__ __forceinline__ void conv_mfma(const u16* src, const u16* __restrict__ frag, u16* wl,
-                                          Epi epi)
+                                          Epi epi, unsigned rows = ~0u)
 {
     const int lane = threadIdx.x & 63, nwave = blockDim.x >> 6;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -143,7 +145,12 @@ __device__ __forceinline__ void conv_mfma(const u16* src, const u16* __restrict_
         for (int nt = 0; nt < NT; nt++)
             b[ks][nt] = *(const bf16x8*)(fr + ((ks * NT + nt) * 64 + lane) * 8);
     constexpr int M = HDST * HDST, MT = (M + 15) / 16;
+    static_assert(HDST <= 32, "row mask");
+    rows = __builtin_amdgcn_readfirstlane(rows);   // the same in every lane
     for (int mt = wave; mt < MT; mt += nwave) {
+        // rows of the tile's first and last pixel (at most two: HDST >= 16)
+        const int r0 = (mt * 16) / HDST, r1 = min(mt * 16 + 15, M - 1) / HDST;
+        if (!((rows >> r0) & ((2u << (r1 - r0)) - 1u))) continue;
         const int pix = mt * 16 + (lane & 15);
         const int p = min(pix, M - 1);
         const int py = p / HDST, px = p % HDST;
@@ -199,7 +206,8 @@ __device__ __forceinline__ void conv_mfma(const u16* src, const u16* __restrict_
 // 0-2, ReLU, BF16) and, when `save` is set, to the saved activations.
 template <int L>
 __device__ __forceinline__ void hidden_layer(const u16* src, u16* dst, const u16* __restrict__ packed,
-                                             const float* __restrict__ prm, u16* save, u16* wl)
+                                             const float* __restrict__ prm, u16* save, u16* wl,
+                                             unsigned rows = ~0u)
 {
     const float* bias = prm + OFF_B[L];
     conv_mfma<HS[L], HS[L + 1], CI[L], FKS[L], FNT[L], false>(
@@ -209,7 +217,7 @@ __device__ __forceinline__ void hidden_layer(const u16* src, u16* dst, const u16
                                        pack_bf16(fmaxf(v[2] + bb.z, 0.f), fmaxf(v[3] + bb.w, 0.f)));
             *(uint2*)(dst + pix * 32 + n0) = h;
             if (save) *(uint2*)(save + pix * 32 + n0) = h;
-        });
+        }, rows);
 }
 
 // ---------------------------------------------------------------------------
@@ -463,42 +471,38 @@ __global__ void k_band_tiles(const InstDev* __restrict__ insts, const double2* _
 
 constexpr int kRowCap = 16;   // crossings of one patch row inside the patch
 
-struct PatchShared {
+struct GeomShared {
     float4 cand[kMaxCand];        // chords (a, b - a) within 8 lu of the patch, relative,
                                   // sorted by min y
     float cinv[kMaxCand];         // 1 / |b - a|^2 (0 for a degenerate chord)
     float cmin[kMaxCand];         // their min y
-    union {
-        struct {
-            float4 tmp[kMaxCand];   // unsorted staging
-            float tkey[kMaxCand];   // and its min y
-        };
-        float raw[kPatch * kPatch][3];   // scaled rho - 1, u_x, u_y (after the sort)
-    };
+    float4 tmp[kMaxCand];         // unsorted staging
+    float tkey[kMaxCand];         // and its min y
     float rowx[kPatch][kRowCap];  // x of the crossings of each patch row inside the patch
     int rown[kPatch];             // their count
     int rowpar[kPatch];           // parity of the crossings right of the patch
-    float red[16];
     int ncand, overflow;
+};
+struct FlowShared {
+    float raw[kPatch * kPatch][3];   // scaled rho - 1, u_x, u_y
+    float red[16];
 };
 constexpr int kPatchThreads = 256;
 
-// Features of the 24 x 24 patch around tile (tx, ty): BF16 input and flags
+// Features of the 24 x 24 patch around tile (tx, ty), in two parts: the
+// geometry (from the markers alone) and the flow (from the lattice alone),
+// so that the first can run before the lattice it pairs with exists.
+// Geometry: the signed-distance channel of the BF16 input and the flags
 // (bit 0 inside, bit 1 band).
 //  - inside: the even-odd rule on the ray from the node towards +x, an
 //    edge counting when it straddles the node's row (half-open in y) and
 //    crosses it right of the node; every chord's crossing of every patch row
 //    is found once per patch;
 //  - distance: the nearest chord among those within 8 lu of the patch,
-//    searched in a window of the chords sorted by their lowest y;
-//  - the flow channels (times their input scales) are divided by the patch
-//    amplitude s = max(rms over the patch of their vector, 1e-6), returned
-//    in *pscale: the network sees amplitude-free flow and its output is
-//    multiplied back by s.
-template <typename T>
-__device__ void build_patch(const InstDev& I, const T* __restrict__ A, const double2* __restrict__ X,
-                            int tx, int ty, const ii_cnn_scales& sc, PatchShared& S, u16* in,
-                            uint8_t* flags, float* pscale, int* err)
+//    searched in a window of the chords sorted by their lowest y.
+__device__ void patch_geom(const InstDev& I, const double2* __restrict__ X, int tx, int ty,
+                           const ii_cnn_scales& sc, GeomShared& S, u16* in, uint8_t* flags,
+                           int* err)
 {
     const int N = I.n_markers;
     const int ox = tx * kTile - kHalo, oy = ty * kTile - kHalo;  // patch origin node
@@ -562,13 +566,6 @@ __device__ void build_patch(const InstDev& I, const T* __restrict__ A, const dou
     for (int q = threadIdx.x; q < kPatch * kPatch; q += blockDim.x) {
         const int py = q / kPatch, px = q % kPatch;
         const float fx = (float)px, fy = (float)py;
-        // the node's pulled distributions (periodic wrap) are loaded first so
-        // that they arrive during the distance search
-        int gx = (ox + px) % I.nx, gy = (oy + py) % I.ny;
-        if (gx < 0) gx += I.nx;
-        if (gy < 0) gy += I.ny;
-        float d[9];
-        pull<T, float>(I, A, gx, gy, d);
         // chords reach at most 2 lu, so those within 8 of the row have their
         // lowest y in [py - 10, py + 8]
         int lo = 0, hi = nc;
@@ -599,13 +596,35 @@ __device__ void build_patch(const InstDev& I, const T* __restrict__ A, const dou
         for (int c = 0; c < nr; c++) ins ^= S.rowx[py][c] > fx ? 1 : 0;
         const float dist = sqrtf(d2);
         const float sd = ins ? -dist : dist;
+        in[q * 4 + 3] = to_bf16(sd * sc.in_scale[3]);
+        flags[q] = (uint8_t)(ins | (dist <= kBand ? 2 : 0));
+    }
+    // more chords near the patch than the lists hold: the features are
+    // incomplete, which the handle reports as ECAPACITY
+    if (threadIdx.x == 0 && S.overflow) atomicOr(err, (int)kErrCapacity);
+}
+
+// Flow: the three flow channels (rho - 1, u_x, u_y of the pulled
+// distributions, u = sum_i e_i f_i, times their input scales), divided by the
+// patch amplitude s = max(rms over the patch of their vector, 1e-6), which
+// goes to *pscale: the network sees amplitude-free flow and its output is
+// multiplied back by s.
+template <typename T>
+__device__ void patch_flow(const InstDev& I, const T* __restrict__ A, int tx, int ty,
+                           const ii_cnn_scales& sc, FlowShared& S, u16* in, float* pscale)
+{
+    const int ox = tx * kTile - kHalo, oy = ty * kTile - kHalo;
+    for (int q = threadIdx.x; q < kPatch * kPatch; q += blockDim.x) {
+        int gx = (ox + q % kPatch) % I.nx, gy = (oy + q / kPatch) % I.ny;
+        if (gx < 0) gx += I.nx;
+        if (gy < 0) gy += I.ny;
+        float d[9];
+        pull<T, float>(I, A, gx, gy, d);
         float r, ux, uy;
         moments<float>(d, r, ux, uy);
         S.raw[q][0] = r * sc.in_scale[0];
         S.raw[q][1] = ux * sc.in_scale[1];
         S.raw[q][2] = uy * sc.in_scale[2];
-        in[q * 4 + 3] = to_bf16(sd * sc.in_scale[3]);
-        flags[q] = (uint8_t)(ins | (dist <= kBand ? 2 : 0));
     }
     __syncthreads();
     float ss = 0.f;
@@ -624,12 +643,7 @@ __device__ void build_patch(const InstDev& I, const T* __restrict__ A, const dou
         in[q * 4 + 1] = to_bf16(S.raw[q][1] * inv);
         in[q * 4 + 2] = to_bf16(S.raw[q][2] * inv);
     }
-    if (threadIdx.x == 0) {
-        *pscale = amp;
-        // more chords near the patch than the lists hold: the features are
-        // incomplete, which the handle reports as ECAPACITY
-        if (S.overflow) atomicOr(err, (int)kErrCapacity);
-    }
+    if (threadIdx.x == 0) *pscale = amp;
 }
 
 // Grid (n_inst, G): block y of instance x takes the instance's band tiles
@@ -637,25 +651,40 @@ __device__ void build_patch(const InstDev& I, const T* __restrict__ A, const dou
 // counts, which only the device knows, and empty slots cost no block.
 constexpr int kSlotStride = 64;
 
-template <typename T>
-__global__ __launch_bounds__(kPatchThreads) void k_patches(const InstDev* __restrict__ insts, const void* A0,
-                                                 const double2* __restrict__ Xall, ii_cnn_scales sc,
-                                                 int cap, const int* __restrict__ tiles,
-                                                 const int* __restrict__ count, u16* __restrict__ in,
-                                                 uint8_t* __restrict__ flags, float* __restrict__ pscale,
-                                                 int* __restrict__ err)
+__global__ __launch_bounds__(kPatchThreads) void k_patch_geom(
+    const InstDev* __restrict__ insts, const double2* __restrict__ Xall, ii_cnn_scales sc, int cap,
+    const int* __restrict__ tiles, const int* __restrict__ count, u16* __restrict__ in,
+    uint8_t* __restrict__ flags, int* __restrict__ err)
 {
     const int inst = blockIdx.x, n = count[inst];
     if ((int)blockIdx.y >= n) return;
     const InstDev I = insts[inst];
-    __shared__ PatchShared S;
+    __shared__ GeomShared S;
     for (int r = blockIdx.y; r < n; r += gridDim.y) {
         if (r != (int)blockIdx.y) __syncthreads();   // the previous patch is done with S
         const long long slot = (long long)inst * cap + r;
         const int2 t = ((const int2*)tiles)[slot];
-        build_patch<T>(I, (const T*)A0, Xall + I.mk_off, t.x, t.y, sc, S,
-                       in + slot * (kPatch * kPatch * 4), flags + slot * (kPatch * kPatch),
-                       pscale + slot, err + inst);
+        patch_geom(I, Xall + I.mk_off, t.x, t.y, sc, S, in + slot * (kPatch * kPatch * 4),
+                   flags + slot * (kPatch * kPatch), err + inst);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kPatchThreads) void k_patch_flow(
+    const InstDev* __restrict__ insts, const void* A0, ii_cnn_scales sc, int cap,
+    const int* __restrict__ tiles, const int* __restrict__ count, u16* __restrict__ in,
+    float* __restrict__ pscale)
+{
+    const int inst = blockIdx.x, n = count[inst];
+    if ((int)blockIdx.y >= n) return;
+    const InstDev I = insts[inst];
+    __shared__ FlowShared S;
+    for (int r = blockIdx.y; r < n; r += gridDim.y) {
+        if (r != (int)blockIdx.y) __syncthreads();   // the previous patch is done with S
+        const long long slot = (long long)inst * cap + r;
+        const int2 t = ((const int2*)tiles)[slot];
+        patch_flow<T>(I, (const T*)A0, t.x, t.y, sc, S, in + slot * (kPatch * kPatch * 4),
+                      pscale + slot);
     }
 }
 
@@ -730,6 +759,7 @@ __global__ __launch_bounds__(kCorrThreads) void k_correct(const InstDev* __restr
     __shared__ int first[kMaxInstLds + 1];   // first[j]: band tiles of instances < j
     __shared__ __align__(16) u16 pin[2][kPatch * kPatch * 4];   // input patches, double buffered
     __shared__ __align__(4) uint8_t pfl[2][kPatch * kPatch];     // and their flags
+    __shared__ unsigned band_rows[4];
     for (int e = threadIdx.x; e < kFwdFrag / 8; e += blockDim.x)
         ((uint4*)wf)[e] = ((const uint4*)packed)[e];
     // exclusive scan of the counts, one block width at a time
@@ -800,18 +830,32 @@ __global__ __launch_bounds__(kCorrThreads) void k_correct(const InstDev* __restr
             fetch(slot_of(kn, in_n));
         }
         const uint8_t* fl = pfl[cur];
-        // a tile whose output nodes all lie outside the band gets no correction
-        int any = 0;
+        // Output rows with a band node (the others get no correction), and
+        // the rows of each hidden layer that feed them: a valid 3 x 3
+        // convolution's output row r reads input rows r .. r + 2.  The first
+        // four waves see four output rows each.
         if (threadIdx.x < kOut * kOut) {
             const int oy = threadIdx.x / kOut, ox = threadIdx.x % kOut;
-            any = fl[(oy + kHalo) * kPatch + ox + kHalo] & 2;
+            const unsigned long long b =
+                __ballot((fl[(oy + kHalo) * kPatch + ox + kHalo] & 2) != 0);
+            if ((threadIdx.x & 63) == 0) {
+                unsigned m = 0;
+                for (int r = 0; r < 4; r++)
+                    if ((b >> (16 * r)) & 0xffffull) m |= 1u << r;
+                band_rows[threadIdx.x >> 6] = m << (4 * (threadIdx.x >> 6));
+            }
         }
-        if (__syncthreads_or(any)) {
-            hidden_layer<0>(pin[cur], by, wf, prm, nullptr, nullptr);
+        __syncthreads();
+        const unsigned m4 = band_rows[0] | band_rows[1] | band_rows[2] | band_rows[3];
+        const unsigned m3 = (m4 | m4 << 1 | m4 << 2) & 0x3ffffu;
+        const unsigned m2 = (m3 | m3 << 1 | m3 << 2) & 0xfffffu;
+        const unsigned m1 = (m2 | m2 << 1 | m2 << 2) & 0x3fffffu;
+        if (m4) {
+            hidden_layer<0>(pin[cur], by, wf, prm, nullptr, nullptr, m1);
             __syncthreads();
-            hidden_layer<1>(by, bx, wf, prm, nullptr, nullptr);
+            hidden_layer<1>(by, bx, wf, prm, nullptr, nullptr, m2);
             __syncthreads();
-            hidden_layer<2>(bx, by, wf, prm, nullptr, nullptr);
+            hidden_layer<2>(bx, by, wf, prm, nullptr, nullptr, m3);
             __syncthreads();
             const float* b4 = prm + OFF_B[3];
             T* base = A + I.lat_off;
@@ -837,7 +881,7 @@ __global__ __launch_bounds__(kCorrThreads) void k_correct(const InstDev* __restr
                     T* p = base + c * I.plane + (long long)y * I.pitch + x;
                     Store<T>::st(p, Store<T>::ld(p, I.scale) + os * (v[j] + b4[c]), I.inv_scale);
                 }
-            });
+            }, m4);
         }
         if (kn < total) stage(cur ^ 1);
         cur ^= 1;
@@ -889,7 +933,67 @@ int check_learned(const HandleView& v)
 
 int err(hipError_t e) { return e == hipSuccess ? II_LBM_OK : II_LBM_EDEVICE; }
 
+dim3 slot_grid(const HandleView& v, const LearnedCfg& c)
+{
+    return dim3((unsigned)v.n_inst, (unsigned)std::min(c.cap, kSlotStride));
+}
+
 }  // namespace
+
+int learned_validate(const HandleView& v, int cap)
+{
+    const int rc = check_learned(v);
+    if (rc) return rc;
+    if (v.n_inst > kMaxInstLds || cap < 1) return II_LBM_EINVAL;
+    for (int j = 0; j < v.n_inst; j++)
+        if (cap < v.inst[j].tiles_x * v.inst[j].tiles_y) return II_LBM_EINVAL;
+    return II_LBM_OK;
+}
+
+hipError_t learned_band(const HandleView& v, const LearnedCfg& c)
+{
+    hipLaunchKernelGGL(k_band_tiles, dim3(v.n_inst), dim3(256), 0, v.stream, v.d_inst,
+                       v.P.X[v.parity], c.cap, c.tiles, c.count);
+    return hipGetLastError();
+}
+
+hipError_t learned_geom(const HandleView& v, const LearnedCfg& c)
+{
+    hipLaunchKernelGGL(k_patch_geom, slot_grid(v, c), dim3(kPatchThreads), 0, v.stream, v.d_inst,
+                       v.P.X[v.parity], c.sc, c.cap, (const int*)c.tiles, (const int*)c.count,
+                       (u16*)c.in, c.flags, v.P.err);
+    return hipGetLastError();
+}
+
+hipError_t learned_flow(const HandleView& v, const LearnedCfg& c)
+{
+    if (v.inst[0].storage == II_LBM_FP16)
+        hipLaunchKernelGGL(k_patch_flow<_Float16>, slot_grid(v, c), dim3(kPatchThreads), 0,
+                           v.stream, v.d_inst, v.P.lat[v.parity], c.sc, c.cap,
+                           (const int*)c.tiles, (const int*)c.count, (u16*)c.in, c.pscale);
+    else
+        hipLaunchKernelGGL(k_patch_flow<float>, slot_grid(v, c), dim3(kPatchThreads), 0,
+                           v.stream, v.d_inst, v.P.lat[v.parity], c.sc, c.cap,
+                           (const int*)c.tiles, (const int*)c.count, (u16*)c.in, c.pscale);
+    return hipGetLastError();
+}
+
+hipError_t learned_infer(const HandleView& v, const LearnedCfg& c)
+{
+    const dim3 grid((unsigned)std::max(1, v.n_cu));
+    if (v.inst[0].storage == II_LBM_FP16)
+        hipLaunchKernelGGL(k_correct<_Float16>, grid, dim3(kCorrThreads), 0, v.stream, v.d_inst,
+                           v.n_inst, v.P.lat[v.parity], c.params, (const u16*)c.packed, c.sc,
+                           c.cap, (const int*)c.tiles, (const int*)c.count, (const u16*)c.in,
+                           c.flags, c.pscale);
+    else
+        hipLaunchKernelGGL(k_correct<float>, grid, dim3(kCorrThreads), 0, v.stream, v.d_inst,
+                           v.n_inst, v.P.lat[v.parity], c.params, (const u16*)c.packed, c.sc,
+                           c.cap, (const int*)c.tiles, (const int*)c.count, (const u16*)c.in,
+                           c.flags, c.pscale);
+    return hipGetLastError();
+}
+
 }  // namespace iilbm
 
 using namespace iilbm;
@@ -957,13 +1061,13 @@ int ii_lbm_learned_tiles(ii_lbm_handle* h, int32_t cap, int32_t* tiles, int32_t*
     HandleView v;
     int rc = handle_view(h, &v);
     if (rc) return rc;
-    if ((rc = check_learned(v))) return rc;
-    if (!tiles || !count || cap < 1) return II_LBM_EINVAL;
-    for (int j = 0; j < v.n_inst; j++)
-        if (cap < v.inst[j].tiles_x * v.inst[j].tiles_y) return II_LBM_EINVAL;
-    hipLaunchKernelGGL(k_band_tiles, dim3(v.n_inst), dim3(256), 0, v.stream, v.d_inst,
-                       v.P.X[v.parity], (int)cap, (int*)tiles, (int*)count);
-    return err(hipGetLastError());
+    if ((rc = learned_validate(v, cap))) return rc;
+    if (!tiles || !count) return II_LBM_EINVAL;
+    LearnedCfg c;
+    c.cap = cap;
+    c.tiles = tiles;
+    c.count = count;
+    return err(learned_band(v, c));
 }
 
 int ii_lbm_learned_patches(ii_lbm_handle* h, const ii_cnn_scales* sc, int32_t cap,
@@ -973,18 +1077,19 @@ int ii_lbm_learned_patches(ii_lbm_handle* h, const ii_cnn_scales* sc, int32_t ca
     HandleView v;
     int rc = handle_view(h, &v);
     if (rc) return rc;
-    if ((rc = check_learned(v))) return rc;
-    if (!sc || !tiles || !count || !in || !flags || !pscale || cap < 1) return II_LBM_EINVAL;
-    const dim3 grid((unsigned)v.n_inst, (unsigned)std::min((int)cap, kSlotStride));
-    if (v.inst[0].storage == II_LBM_FP16)
-        hipLaunchKernelGGL(k_patches<_Float16>, grid, dim3(kPatchThreads), 0, v.stream, v.d_inst,
-                           v.P.lat[v.parity], v.P.X[v.parity], *sc, (int)cap, (const int*)tiles,
-                           (const int*)count, (u16*)in, flags, pscale, v.P.err);
-    else
-        hipLaunchKernelGGL(k_patches<float>, grid, dim3(kPatchThreads), 0, v.stream, v.d_inst,
-                           v.P.lat[v.parity], v.P.X[v.parity], *sc, (int)cap, (const int*)tiles,
-                           (const int*)count, (u16*)in, flags, pscale, v.P.err);
-    return err(hipGetLastError());
+    if ((rc = learned_validate(v, cap))) return rc;
+    if (!sc || !tiles || !count || !in || !flags || !pscale) return II_LBM_EINVAL;
+    LearnedCfg c;
+    c.sc = *sc;
+    c.cap = cap;
+    c.tiles = (int*)tiles;
+    c.count = (int*)count;
+    c.in = in;
+    c.flags = flags;
+    c.pscale = pscale;
+    hipError_t e = learned_geom(v, c);
+    if (e == hipSuccess) e = learned_flow(v, c);
+    return err(e);
 }
 
 int ii_lbm_learned_targets(ii_lbm_handle* hc, ii_lbm_handle* hf, const ii_cnn_scales* sc,
@@ -1050,20 +1155,20 @@ int ii_lbm_learned_infer(ii_lbm_handle* h, const float* params, const void* pack
     HandleView v;
     int rc = handle_view(h, &v);
     if (rc) return rc;
-    if ((rc = check_learned(v))) return rc;
-    if (!params || !packed || !sc || !tiles || !count || !in || !flags || !pscale || cap < 1)
+    if ((rc = learned_validate(v, cap))) return rc;
+    if (!params || !packed || !sc || !tiles || !count || !in || !flags || !pscale)
         return II_LBM_EINVAL;
-    if (v.n_inst > kMaxInstLds) return II_LBM_EINVAL;
-    const dim3 grid((unsigned)std::max(1, v.n_cu));
-    if (v.inst[0].storage == II_LBM_FP16)
-        hipLaunchKernelGGL(k_correct<_Float16>, grid, dim3(kCorrThreads), 0, v.stream, v.d_inst, v.n_inst,
-                           v.P.lat[v.parity], params, (const u16*)packed, *sc, (int)cap,
-                           (const int*)tiles, (const int*)count, (const u16*)in, flags, pscale);
-    else
-        hipLaunchKernelGGL(k_correct<float>, grid, dim3(kCorrThreads), 0, v.stream, v.d_inst, v.n_inst,
-                           v.P.lat[v.parity], params, (const u16*)packed, *sc, (int)cap,
-                           (const int*)tiles, (const int*)count, (const u16*)in, flags, pscale);
-    return err(hipGetLastError());
+    LearnedCfg c;
+    c.params = params;
+    c.packed = packed;
+    c.sc = *sc;
+    c.cap = cap;
+    c.tiles = (int*)tiles;
+    c.count = (int*)count;
+    c.in = (uint16_t*)in;
+    c.flags = (uint8_t*)flags;
+    c.pscale = (float*)pscale;
+    return err(learned_infer(v, c));
 }
 
 int ii_lbm_learned_correct(ii_lbm_handle* h, const float* params, const void* packed,

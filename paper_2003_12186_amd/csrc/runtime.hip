@@ -245,6 +245,12 @@ struct ii_lbm_handle {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool rec_valid = false;  // rigid bodies: a step has built cut-link records
     int n_cu = 256;
+    // learned correction after every step (ii_lbm_set_learned): its marker-
+    // only phases run on `lrn` as soon as the step's interpolation has moved
+    // the markers (ev_x); ev_b / ev_g mark its band tiles / patch geometry
+    LearnedCfg learned;
+    hipStream_t lrn = nullptr;
+    hipEvent_t ev_x = nullptr, ev_b = nullptr, ev_g = nullptr;
 };
 
 static int hip_fail(ii_lbm_handle* h, hipError_t e)
@@ -403,13 +409,31 @@ static hipError_t enqueue_interp(ii_lbm_handle* h, int par, hipStream_t s)
 //     INTERP_FIRST: interp(m) on s, fork -> aux: reset/geom/tiles(m+1);
 //              s: sweep(m) -> join
 //   rigid bodies: reset/full markers/tiles(m) -> sweep(m), in order on s
+// The learned correction's phases for the state of plane `par` on stream s.
+static hipError_t enqueue_learned(ii_lbm_handle* h, int par, hipStream_t s,
+                                  hipError_t (*phase)(const HandleView&, const LearnedCfg&))
+{
+    HandleView v;
+    handle_view(h, &v);
+    v.parity = par;
+    v.stream = s;
+    return phase(v, h->learned);
+}
+
 static hipError_t enqueue_step(ii_lbm_handle* h, int par, hipStream_t s, bool timed)
 {
     hipError_t e = hipSuccess;
+    const bool lrn = h->learned.on;
     if (h->lookahead && h->overlap == II_LBM_OVERLAP_SERIAL) {
         e = enqueue_sweep(h, par, s, timed);
         if (e == hipSuccess) e = enqueue_interp(h, par, s);
         if (e == hipSuccess) e = enqueue_interface(h, par ^ 1, kModeGeom, s);
+        if (lrn) {
+            if (e == hipSuccess) e = enqueue_learned(h, par ^ 1, s, learned_band);
+            if (e == hipSuccess) e = enqueue_learned(h, par ^ 1, s, learned_geom);
+            if (e == hipSuccess) e = enqueue_learned(h, par ^ 1, s, learned_flow);
+            if (e == hipSuccess) e = enqueue_learned(h, par ^ 1, s, learned_infer);
+        }
         return e;
     }
     if (h->lookahead) {
@@ -418,8 +442,27 @@ static hipError_t enqueue_step(ii_lbm_handle* h, int par, hipStream_t s, bool ti
         if (e == hipSuccess) e = hipEventRecord(h->ev_fork, s);
         if (e == hipSuccess) e = hipStreamWaitEvent(h->aux, h->ev_fork, 0);
         if (e == hipSuccess && !first) e = enqueue_interp(h, par, h->aux);
+        if (lrn) {
+            // band tiles and patch geometry of the next state need only the
+            // moved markers X^{m+1}; they run beside the sweep and the
+            // interface pass
+            if (e == hipSuccess) e = hipEventRecord(h->ev_x, first ? s : h->aux);
+            if (e == hipSuccess) e = hipStreamWaitEvent(h->lrn, h->ev_x, 0);
+            if (e == hipSuccess) e = enqueue_learned(h, par ^ 1, h->lrn, learned_band);
+            if (e == hipSuccess) e = hipEventRecord(h->ev_b, h->lrn);
+            if (e == hipSuccess) e = enqueue_learned(h, par ^ 1, h->lrn, learned_geom);
+            if (e == hipSuccess) e = hipEventRecord(h->ev_g, h->lrn);
+        }
         if (e == hipSuccess) e = enqueue_interface(h, par ^ 1, kModeGeom, h->aux);
         if (e == hipSuccess) e = enqueue_sweep(h, par, s, timed);
+        if (lrn) {
+            // patch flow and the network need the swept lattice; the interface
+            // pass of the next step does not read it, so they overlap it too
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, h->ev_b, 0);
+            if (e == hipSuccess) e = enqueue_learned(h, par ^ 1, s, learned_flow);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, h->ev_g, 0);
+            if (e == hipSuccess) e = enqueue_learned(h, par ^ 1, s, learned_infer);
+        }
         if (e == hipSuccess) e = hipEventRecord(h->ev_join, h->aux);
         if (e == hipSuccess) e = hipStreamWaitEvent(s, h->ev_join, 0);
         return e;
@@ -491,6 +534,9 @@ static void release(ii_lbm_handle* h)
     drop_graphs(h);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     if (h->aux) (void)hipStreamDestroy(h->aux);
+    if (h->lrn) (void)hipStreamDestroy(h->lrn);
+    for (hipEvent_t ev : {h->ev_x, h->ev_b, h->ev_g})
+        if (ev) (void)hipEventDestroy(ev);
     if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
     if (h->ev_join) (void)hipEventDestroy(h->ev_join);
     for (auto& ev : h->ev) (void)hipEventDestroy(ev);
@@ -729,6 +775,43 @@ int ii_lbm_set_overlap(ii_lbm_handle* h, int32_t mode)
     if (h->overlap != mode) drop_graphs(h);
     h->overlap = mode;
     size_tile_blocks(h);
+    return II_LBM_OK;
+}
+
+int ii_lbm_set_learned(ii_lbm_handle* h, const float* params, const void* packed,
+                       const ii_cnn_scales* sc, int32_t cap, int32_t* tiles, int32_t* count,
+                       uint16_t* in, uint8_t* flags, float* pscale)
+{
+    if (!h) return II_LBM_EINVAL;
+    if (!params) {
+        if (h->learned.on) drop_graphs(h);
+        h->learned = LearnedCfg();
+        return II_LBM_OK;
+    }
+    HandleView v;
+    handle_view(h, &v);
+    int rc = learned_validate(v, cap);
+    if (rc) return rc;
+    if (!packed || !sc || !tiles || !count || !in || !flags || !pscale) return II_LBM_EINVAL;
+    if (!h->lrn) {
+        hipError_t e = hipStreamCreateWithFlags(&h->lrn, hipStreamNonBlocking);
+        for (hipEvent_t* ev : {&h->ev_x, &h->ev_b, &h->ev_g})
+            if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(h, e);
+    }
+    LearnedCfg c;
+    c.on = true;
+    c.params = params;
+    c.packed = packed;
+    c.sc = *sc;
+    c.cap = cap;
+    c.tiles = tiles;
+    c.count = count;
+    c.in = in;
+    c.flags = flags;
+    c.pscale = pscale;
+    drop_graphs(h);
+    h->learned = c;
     return II_LBM_OK;
 }
 
@@ -1042,6 +1125,7 @@ int ii_lbm_destroy(ii_lbm_handle* h)
     if (!h) return II_LBM_EINVAL;
     (void)hipStreamSynchronize(h->stream);
     if (h->aux) (void)hipStreamSynchronize(h->aux);
+    if (h->lrn) (void)hipStreamSynchronize(h->lrn);
     release(h);
     return II_LBM_OK;
 }

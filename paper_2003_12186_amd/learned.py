@@ -23,7 +23,7 @@ _SHAPES = [(3, 3, 4, 32), (32,), (3, 3, 32, 32), (32,), (3, 3, 32, 32), (32,), (
 EXPORTS = ["ii_cnn_packed_bytes", "ii_cnn_pack", "ii_cnn_save_bytes", "ii_cnn_forward",
            "ii_cnn_work_bytes", "ii_cnn_backward", "ii_cnn_adam", "ii_lbm_learned_tiles",
            "ii_lbm_learned_patches", "ii_lbm_learned_targets", "ii_lbm_learned_apply",
-           "ii_lbm_learned_correct", "ii_lbm_learned_infer"]
+           "ii_lbm_learned_correct", "ii_lbm_learned_infer", "ii_lbm_set_learned"]
 
 
 class Scales(C.Structure):
@@ -60,6 +60,7 @@ def lib():
             "ii_lbm_learned_apply": ([v, S, i32, v, v, v, v, v], C.c_int),
             "ii_lbm_learned_correct": ([v, v, v, S, i32, v, v, v, v, v], C.c_int),
             "ii_lbm_learned_infer": ([v, v, v, S, i32, v, v, v, v, v], C.c_int),
+            "ii_lbm_set_learned": ([v, v, v, S, i32, v, v, v, v, v], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -201,6 +202,19 @@ class Band:
         B.check(lib().ii_lbm_learned_infer(self.sim.h, _p(net.params), _p(net.packed), C.byref(sc),
                                            self.cap, _p(self.tiles), _p(self.count), _p(self.inp),
                                            _p(self.flags), _p(self.pscale)), "ii_lbm_learned_infer")
+
+    def attach(self, net: Net, sc: Scales) -> None:
+        """Have the handle apply the correction after every step (its own
+        stream schedule and graphs); the band scratch is this object's."""
+        self._attached = (net, sc)   # the handle keeps pointers into both
+        B.check(lib().ii_lbm_set_learned(self.sim.h, _p(net.params), _p(net.packed), C.byref(sc),
+                                         self.cap, _p(self.tiles), _p(self.count), _p(self.inp),
+                                         _p(self.flags), _p(self.pscale)), "ii_lbm_set_learned")
+
+    def detach(self) -> None:
+        B.check(lib().ii_lbm_set_learned(self.sim.h, None, None, None, 0, None, None, None, None,
+                                         None), "ii_lbm_set_learned")
+        self._attached = None
 
     def slots(self):
         """Indices of the filled slots (host)."""

@@ -98,7 +98,7 @@ LEARNED_HEADER = os.path.join(ROOT, "include", "ii_learned.h")
 def test_learned_header_calls_are_exported_and_sized():
     from paper_2003_12186_amd import learned as LN
     src = open(LEARNED_HEADER).read()
-    names = sorted(set(re.findall(r"\b(ii_(?:cnn|lbm_learned)_[a-z_]+)\s*\(", src)))
+    names = sorted(set(re.findall(r"\b(ii_(?:cnn|lbm_learned)_[a-z_]+|ii_lbm_set_learned)\s*\(", src)))
     lib = LN.lib()
     for n in names:
         assert hasattr(lib, n), n
@@ -129,3 +129,4 @@ def test_learned_calls_reject_null_arguments_without_a_device():
     assert lib.ii_cnn_forward(None, None, None, 1, None, None, None) == B.EINVAL
     assert lib.ii_lbm_learned_tiles(None, 16, None, None) == B.EINVAL
     assert lib.ii_lbm_learned_infer(None, None, None, None, 16, None, None, None, None, None) == B.EINVAL
+    assert lib.ii_lbm_set_learned(None, None, None, None, 16, None, None, None, None, None) == B.EINVAL

@@ -319,6 +319,47 @@ def test_infer_over_many_tiles_matches_forward_and_apply(mods):
         s.close()
 
 
+@pytest.mark.parametrize("mode", ["full", "interp_first", "serial"])
+def test_registered_correction_matches_manual_steps(mods, mode):
+    B, LN = mods
+    # the handle applying the correction inside its steps (other streams,
+    # graph replays) gives the same state as step + correct called in turn
+    pairs = [W.learned_pair_c5(s, L=64, n_markers=128) for s in (10003, 10006)]
+    for c, _ in pairs:
+        c.problem.math = W.MATH_FP64
+    modes = {"full": B.OVERLAP_FULL, "interp_first": B.OVERLAP_INTERP_FIRST, "serial": B.OVERLAP_SERIAL}
+    _say(f"registered correction vs step + correct, overlap {mode}, 2 instances, 8 steps")
+    Wt, b = _params(13, bias=0.2)
+    net, _, _ = _net(LN, Wt, b)
+    sc = LN.make_scales(**SC)
+    sims = [B.Sim([c.problem for c, _ in pairs], [c.X0 for c, _ in pairs]) for _ in range(3)]
+    for sm in sims:
+        sm.set_overlap(modes[mode])
+    manual, reg, plain = sims
+    bm = LN.Band(manual)
+    for _ in range(8):
+        manual.step(1)
+        bm.correct(net, sc)
+    br = LN.Band(reg)
+    br.attach(net, sc)
+    reg.step(2)
+    reg.set_graph(True)
+    reg.step(6)
+    plain.step(8)
+    for j in range(2):
+        fm = manual.fields(B.F_DISTRIB, inst=j)
+        assert np.array_equal(reg.fields(B.F_DISTRIB, inst=j), fm)
+        assert np.array_equal(reg.markers(j)[0], manual.markers(j)[0])
+        assert np.abs(fm - plain.fields(B.F_DISTRIB, inst=j)).max() > 0
+    # unregistered, the handle steps without the correction again
+    br.detach()
+    reg.step(2)
+    manual.step(2)
+    assert np.array_equal(reg.fields(B.F_DISTRIB, inst=1), manual.fields(B.F_DISTRIB, inst=1))
+    for sm in sims:
+        sm.close()
+
+
 def test_training_reduces_the_loss(mods):
     import torch
     B, LN = mods
