@@ -203,8 +203,10 @@ int ii_lbm_load_state(ii_lbm_handle* h, int32_t inst, const void* host_buf, size
 /* Synchronises, then copies up to `cap` cut-link records of one instance into
  * a host buffer; *count receives the total number (which may exceed cap).
  * Membranes: the links cut by the polygon through the current markers X^n,
- * which the next step applies.  Rigid bodies: the links of the last step (none
- * before the first step).  Records are in no particular order. */
+ * which the next step applies; steps do not write them, the first call after
+ * a step builds them (one interface pass on the handle's stream).  Rigid
+ * bodies: the links of the last step (none before the first step).  Records
+ * are in no particular order. */
 int ii_lbm_cutlinks(ii_lbm_handle* h, int32_t inst, ii_lbm_link* out, int32_t cap, int32_t* count);
 
 /* Synchronises and fills FP64 diagnostics of one instance. */

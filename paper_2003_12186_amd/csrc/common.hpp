@@ -411,11 +411,11 @@ hipError_t launch_markers(const InstDev& I, const DevPtrs& P, const void* A, int
 hipError_t launch_slot_reset(const InstDev& I, const DevPtrs& P, int par, hipStream_t s);
 hipError_t launch_slot_reset_batch(const Batch& b, int n_inst, const DevPtrs& P, int par,
                                    hipStream_t s);
-hipError_t launch_tiles(const InstDev& I, const DevPtrs& P, int parity, int records, hipStream_t s);
+hipError_t launch_tiles(const InstDev& I, const DevPtrs& P, int parity, bool records, hipStream_t s);
 hipError_t launch_fill_ints(int* p, long long n, int value, hipStream_t s);
 hipError_t launch_markers_batch(const Batch& b, const DevPtrs& P, const void* A, int par, int mode,
                                 hipStream_t s);
-hipError_t launch_tiles_batch(const Batch& b, const DevPtrs& P, int parity, int records,
+hipError_t launch_tiles_batch(const Batch& b, const DevPtrs& P, int parity, bool records,
                               hipStream_t s);
 hipError_t launch_sweep_batch(const Batch& b, const DevPtrs& P, const void* A, void* B, int par,
                               hipStream_t s);

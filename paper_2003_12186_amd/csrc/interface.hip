@@ -393,7 +393,9 @@ __device__ __forceinline__ void rigid_cut(const InstDev& I, int x, int y, int i,
 // ---------------------------------------------------------------------------
 constexpr int kTileRec = 1024;  // cut links recorded per tile (packed in LDS, then written)
 
-// LDS of one tile block, about 27 KB so that five blocks share a CU.
+// LDS of one tile block: about 24 KB (six blocks share a CU), and 4 KB more
+// with the cut-link record stage.
+template <bool REC>
 struct TileShared {
     union {
         int raw[kTileCap];       // chord ids as binned
@@ -407,29 +409,33 @@ struct TileShared {
     int2 f0[kTileCap];
     double gtx[kTileCap], gty[kTileCap];
     float acc[8][kTileNodes];    // jump sums of the eight outgoing populations per node
-    unsigned rec[kTileRec];      // packed (node, direction, chord) of each cut link
+    unsigned rec[REC ? kTileRec : 1];   // packed (node, direction, chord) of each cut link
     int cnt, total, nrec, base;
 };
 
 // [[f_i]] of one cut link into the node's accumulator: sigma w_i [[p]] / c_s^2
 // (Sec. 3.1, Eq. (32); Sec. 3.2, Eq. (47)).  A link cut by two chords gets two
 // terms, whose sum does not depend on their order.
-__device__ __forceinline__ void add_jump(TileShared& S, int node, int i, int sigma, double jpc)
+template <class TS>
+__device__ __forceinline__ void add_jump(TS& S, int node, int i, int sigma, double jpc)
 {
     atomicAdd(&S.acc[i - 1][node], (float)((double)sigma * WD[i] * jpc / kCs2));
 }
 
-__device__ __forceinline__ void stage_record(TileShared& S, int node, int i, int j)
+template <class TS>
+__device__ __forceinline__ void stage_record(TS& S, int node, int i, int j)
 {
     const int r = atomicAdd(&S.nrec, 1);
     if (r < kTileRec) S.rec[r] = (unsigned)node | ((unsigned)(i - 1) << 8) | ((unsigned)j << 11);
 }
 
-template <int IFACE>
-__device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, int parity,
-                                           int records, int blk, int nblk)
+// REC: also write the cut-link records of the tile (packed in LDS, then
+// expanded by recomputing each crossing).
+template <int IFACE, bool REC>
+__device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, int parity, int blk,
+                                           int nblk)
 {
-    __shared__ TileShared S;
+    __shared__ TileShared<REC> S;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int N = I.n_markers;
     const double2* X = P.X[parity] + I.mk_off;
@@ -454,17 +460,32 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
             P.tile_count[gt] = 0;  // ready for the next step
             P.tile_slot[parity][gt] = I.act_off + a;
         }
-        // deterministic order: chord k goes to its rank among the (distinct) ids
+        // deterministic order: chord k goes to its rank among the (distinct)
+        // ids; its marker data are requested first and arrive during the rank
+        // count
         int k = 0, r = 0;
+        double2 a0 = make_double2(0.0, 0.0), b0 = a0, g = a0;
+        double jpa = 0.0, jpb = 0.0, wxd[4] = {0.0, 0.0, 0.0, 0.0}, wyd[4] = {0.0, 0.0, 0.0, 0.0};
+        int2 f0 = make_int2(0, 0);
         if (tid < c) {
             k = S.raw[tid];
+            const int kp = (k + 1) % N, mk = I.mk_off + k;
+            a0 = X[k];
+            b0 = X[kp];
+            jpa = P.jp[mk];
+            jpb = P.jp[I.mk_off + kp];
+            f0 = P.f0[mk];
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                wxd[q] = P.wx[4 * mk + q];
+                wyd[q] = P.wy[4 * mk + q];
+            }
+            g = P.Gt[mk];
             for (int m = 0; m < c; m++) r += (S.raw[m] < k) ? 1 : 0;
         }
         __syncthreads();   // raw is reused as start below
         if (tid < c) {
             S.key[r] = k;
-            const int kp = (k + 1) % N;
-            const double2 a0 = X[k], b0 = X[kp];
             const long long ax = (long long)rint(a0.x * kSnap), ay = (long long)rint(a0.y * kSnap);
             const long long bx = (long long)rint(b0.x * kSnap), by = (long long)rint(b0.y * kSnap);
             S.ch[r].ax = ax; S.ch[r].ay = ay; S.ch[r].bx = bx; S.ch[r].by = by;
@@ -478,16 +499,14 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
             S.box[r][2] = (short)by0; S.box[r][3] = (short)by1;
             S.start[r] = (IFACE == II_LBM_IF_MEMBRANE && bx0 <= bx1 && by0 <= by1)
                              ? (bx1 - bx0 + 1) * (by1 - by0 + 1) : 0;
-            S.jpa[r] = P.jp[I.mk_off + k];
-            S.jpb[r] = P.jp[I.mk_off + kp];
-            const int mk = I.mk_off + k;
-            S.f0[r] = P.f0[mk];
+            S.jpa[r] = jpa;
+            S.jpb[r] = jpb;
+            S.f0[r] = f0;
 #pragma unroll
             for (int q = 0; q < 4; q++) {
-                S.wx[r][q] = (float)P.wx[4 * mk + q];
-                S.wy[r][q] = (float)P.wy[4 * mk + q];
+                S.wx[r][q] = (float)wxd[q];
+                S.wy[r][q] = (float)wyd[q];
             }
-            const double2 g = P.Gt[mk];
             S.gtx[r] = g.x; S.gty[r] = g.y;
         }
         __syncthreads();
@@ -534,7 +553,7 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
                     double qq, th;
                     if (!link_crossing<false>(x, y, i, ch, oP, sP, sg, qq, th)) continue;
                     add_jump(S, node, i, sg, (1.0 - th) * S.jpa[j] + th * S.jpb[j]);
-                    if (records) stage_record(S, node, i, j);
+                    if constexpr (REC) stage_record(S, node, i, j);
                 }
             }
         }
@@ -572,7 +591,7 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
                     const double jpc =
                         (1.0 - th) * P.jp[I.mk_off + k] + th * P.jp[I.mk_off + (k + 1) % N];
                     add_jump(S, tid, i, inP ? 1 : -1, jpc);
-                    if (records) stage_record(S, tid, i, 0);
+                    if constexpr (REC) stage_record(S, tid, i, 0);
                 }
             }
         }
@@ -594,7 +613,7 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
         }
         // Records of this tile: one global slice for the block; each is
         // expanded from its packed form by recomputing the crossing.
-        if (records) {
+        if constexpr (REC) {
             const int nr = min(S.nrec, kTileRec);
             if (tid == 0) {
                 S.base = nr > 0 ? atomicAdd(&P.rec_count[2 * I.inst + parity], nr) : 0;
@@ -637,45 +656,61 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
     }
 }
 
-template <int IFACE>
-__global__ __launch_bounds__(256) void k_tiles(InstDev I, DevPtrs P, int parity, int records)
+template <int IFACE, bool REC>
+__global__ __launch_bounds__(256) void k_tiles(InstDev I, DevPtrs P, int parity)
 {
-    tiles_body<IFACE>(I, P, parity, records, blockIdx.x, gridDim.x);
+    tiles_body<IFACE, REC>(I, P, parity, blockIdx.x, gridDim.x);
 }
 
-template <int IFACE>
+template <int IFACE, bool REC>
 __global__ __launch_bounds__(256) void k_tiles_batch(const InstDev* __restrict__ insts,
                                                      const int2* __restrict__ units, DevPtrs P,
-                                                     int parity, int records)
+                                                     int parity)
 {
     const int2 u = units[blockIdx.x];
     const InstDev I = insts[u.x];
-    tiles_body<IFACE>(I, P, parity, records, u.y, I.tile_blocks);
+    tiles_body<IFACE, REC>(I, P, parity, u.y, I.tile_blocks);
 }
 
-hipError_t launch_tiles(const InstDev& I, const DevPtrs& P, int parity, int records, hipStream_t s)
+template <int IFACE>
+static hipError_t tiles_i(const InstDev& I, const DevPtrs& P, int parity, bool records,
+                          hipStream_t s)
 {
     const int nb = I.tile_blocks;
-    if (I.iface == II_LBM_IF_MEMBRANE)
-        hipLaunchKernelGGL((k_tiles<II_LBM_IF_MEMBRANE>), dim3(nb), dim3(256), 0, s, I, P, parity,
-                           records);
+    if (records)
+        hipLaunchKernelGGL((k_tiles<IFACE, true>), dim3(nb), dim3(256), 0, s, I, P, parity);
     else
-        hipLaunchKernelGGL((k_tiles<II_LBM_IF_RIGID>), dim3(nb), dim3(256), 0, s, I, P, parity,
-                           records);
+        hipLaunchKernelGGL((k_tiles<IFACE, false>), dim3(nb), dim3(256), 0, s, I, P, parity);
     return hipGetLastError();
 }
 
-hipError_t launch_tiles_batch(const Batch& b, const DevPtrs& P, int parity, int records,
+hipError_t launch_tiles(const InstDev& I, const DevPtrs& P, int parity, bool records, hipStream_t s)
+{
+    return I.iface == II_LBM_IF_MEMBRANE ? tiles_i<II_LBM_IF_MEMBRANE>(I, P, parity, records, s)
+                                         : tiles_i<II_LBM_IF_RIGID>(I, P, parity, records, s);
+}
+
+template <int IFACE>
+static hipError_t tiles_batch_i(const Batch& b, const DevPtrs& P, int parity, bool records,
+                                hipStream_t s)
+{
+    const dim3 g(b.tile_units);
+    if (records)
+        hipLaunchKernelGGL((k_tiles_batch<IFACE, true>), g, dim3(256), 0, s, b.insts,
+                           b.tile_table, P, parity);
+    else
+        hipLaunchKernelGGL((k_tiles_batch<IFACE, false>), g, dim3(256), 0, s, b.insts,
+                           b.tile_table, P, parity);
+    return hipGetLastError();
+}
+
+hipError_t launch_tiles_batch(const Batch& b, const DevPtrs& P, int parity, bool records,
                               hipStream_t s)
 {
     if (b.tile_units == 0) return hipSuccess;
-    if (b.iface == II_LBM_IF_MEMBRANE)
-        hipLaunchKernelGGL((k_tiles_batch<II_LBM_IF_MEMBRANE>), dim3(b.tile_units), dim3(256), 0,
-                           s, b.insts, b.tile_table, P, parity, records);
-    else
-        hipLaunchKernelGGL((k_tiles_batch<II_LBM_IF_RIGID>), dim3(b.tile_units), dim3(256), 0, s,
-                           b.insts, b.tile_table, P, parity, records);
-    return hipGetLastError();
+    return b.iface == II_LBM_IF_MEMBRANE
+               ? tiles_batch_i<II_LBM_IF_MEMBRANE>(b, P, parity, records, s)
+               : tiles_batch_i<II_LBM_IF_RIGID>(b, P, parity, records, s);
 }
 
 }  // namespace iilbm

@@ -222,7 +222,9 @@ struct ii_lbm_handle {
     int parity = 0;        // which lattice / marker buffer is current
     int64_t steps = 0;
     int failed = 0;        // sticky error code
-    int records = 1;
+    // Membranes' steps build no cut-link records; rec_fresh: those of the
+    // current markers have been built since (ensure_records)
+    bool rec_fresh = false;
     bool timing = false;
     std::vector<hipEvent_t> ev;  // start/stop pairs
     int ev_used = 0;
@@ -342,15 +344,17 @@ static hipError_t upload_sweep_table(ii_lbm_handle* h, int unit, int order)
 }
 
 // Interface phases of one step on stream s: slot/count reset of plane `par`,
-// the marker pass (`mode`), then the tile pass.
-static hipError_t enqueue_interface(ii_lbm_handle* h, int par, int mode, hipStream_t s)
+// the marker pass (`mode`), then the tile pass (with the cut-link records
+// when `records`).
+static hipError_t enqueue_interface(ii_lbm_handle* h, int par, int mode, hipStream_t s,
+                                    bool records)
 {
     void* A = h->P.lat[par];
     hipError_t e = hipSuccess;
     if (h->batched) {
         e = launch_slot_reset_batch(h->batch, (int)h->L.inst.size(), h->P, par, s);
         if (e == hipSuccess) e = launch_markers_batch(h->batch, h->P, A, par, mode, s);
-        if (e == hipSuccess) e = launch_tiles_batch(h->batch, h->P, par, h->records, s);
+        if (e == hipSuccess) e = launch_tiles_batch(h->batch, h->P, par, records, s);
         return e;
     }
     for (size_t j = 0; j < h->L.inst.size() && e == hipSuccess; j++) {
@@ -358,7 +362,7 @@ static hipError_t enqueue_interface(ii_lbm_handle* h, int par, int mode, hipStre
         if (I.n_markers == 0) continue;
         e = launch_slot_reset(I, h->P, par, s);
         if (e == hipSuccess) e = launch_markers(I, h->P, A, par, mode, s);
-        if (e == hipSuccess) e = launch_tiles(I, h->P, par, h->records, s);
+        if (e == hipSuccess) e = launch_tiles(I, h->P, par, records, s);
     }
     return e;
 }
@@ -427,7 +431,7 @@ static hipError_t enqueue_step(ii_lbm_handle* h, int par, hipStream_t s, bool ti
     if (h->lookahead && h->overlap == II_LBM_OVERLAP_SERIAL) {
         e = enqueue_sweep(h, par, s, timed);
         if (e == hipSuccess) e = enqueue_interp(h, par, s);
-        if (e == hipSuccess) e = enqueue_interface(h, par ^ 1, kModeGeom, s);
+        if (e == hipSuccess) e = enqueue_interface(h, par ^ 1, kModeGeom, s, false);
         if (lrn) {
             if (e == hipSuccess) e = enqueue_learned(h, par ^ 1, s, learned_band);
             if (e == hipSuccess) e = enqueue_learned(h, par ^ 1, s, learned_geom);
@@ -453,7 +457,7 @@ static hipError_t enqueue_step(ii_lbm_handle* h, int par, hipStream_t s, bool ti
             if (e == hipSuccess) e = enqueue_learned(h, par ^ 1, h->lrn, learned_geom);
             if (e == hipSuccess) e = hipEventRecord(h->ev_g, h->lrn);
         }
-        if (e == hipSuccess) e = enqueue_interface(h, par ^ 1, kModeGeom, h->aux);
+        if (e == hipSuccess) e = enqueue_interface(h, par ^ 1, kModeGeom, h->aux, false);
         if (e == hipSuccess) e = enqueue_sweep(h, par, s, timed);
         if (lrn) {
             // patch flow and the network need the swept lattice; the interface
@@ -467,7 +471,7 @@ static hipError_t enqueue_step(ii_lbm_handle* h, int par, hipStream_t s, bool ti
         if (e == hipSuccess) e = hipStreamWaitEvent(s, h->ev_join, 0);
         return e;
     }
-    e = enqueue_interface(h, par, kModeFull, s);
+    e = enqueue_interface(h, par, kModeFull, s, true);
     if (e == hipSuccess) e = enqueue_sweep(h, par, s, timed);
     return e;
 }
@@ -477,8 +481,23 @@ static hipError_t enqueue_step(ii_lbm_handle* h, int par, hipStream_t s, bool ti
 static hipError_t prime(ii_lbm_handle* h)
 {
     if (!h->lookahead) return hipSuccess;
-    const hipError_t e = enqueue_interface(h, h->parity, kModeGeom, h->stream);
+    h->rec_fresh = false;
+    const hipError_t e = enqueue_interface(h, h->parity, kModeGeom, h->stream, false);
     return e == hipSuccess ? hipStreamSynchronize(h->stream) : e;
+}
+
+// Membranes: the cut-link records of the current markers, for the calls that
+// report them.  The interface pass of the current plane runs again with the
+// records on; it is a deterministic function of the markers and rewrites the
+// same forces, tile lists and corrections that the next sweep reads.
+static int ensure_records(ii_lbm_handle* h)
+{
+    if (!h->lookahead || h->rec_fresh) return II_LBM_OK;
+    hipError_t e = enqueue_interface(h, h->parity, kModeGeom, h->stream, true);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e);
+    h->rec_fresh = true;
+    return check_device_errors(h);
 }
 
 static void drop_graphs(ii_lbm_handle* h)
@@ -765,7 +784,10 @@ int ii_lbm_step(ii_lbm_handle* h, int64_t n_steps)
         h->parity ^= 1;
         h->steps++;
     }
-    if (n_steps > 0) h->rec_valid = true;
+    if (n_steps > 0) {
+        h->rec_valid = true;
+        h->rec_fresh = false;
+    }
     return II_LBM_OK;
 }
 
@@ -1008,8 +1030,9 @@ int ii_lbm_load_state(ii_lbm_handle* h, int32_t inst, const void* host_buf, size
 int ii_lbm_cutlinks(ii_lbm_handle* h, int32_t inst, ii_lbm_link* out, int32_t cap, int32_t* count)
 {
     if (!h || !count || cap < 0 || inst < 0 || inst >= (int)h->prob.size()) return II_LBM_EINVAL;
-    const int rc = sync_and_check(h);
+    int rc = sync_and_check(h);
     if (rc) return rc;
+    if ((rc = ensure_records(h))) return rc;
     const InstDev& I = h->L.inst[inst];
     int n = 0;
     hipError_t e = hipSuccess;
@@ -1069,9 +1092,12 @@ int ii_lbm_diag(ii_lbm_handle* h, int32_t inst, ii_lbm_diag_t* out)
         const bool have_g = h->lookahead || h->rec_valid;
         out->force[0] = have_g ? fx : 0.0;
         out->force[1] = have_g ? fy : 0.0;
+        // a failed membrane handle reports no links unless its records are current
         int n = 0;
+        const bool current =
+            !h->lookahead || h->rec_fresh || (!h->failed && ensure_records(h) == II_LBM_OK);
         const int par = record_parity(h);
-        if (par >= 0)
+        if (current && par >= 0)
             (void)hipMemcpy(&n, h->P.rec_count + 2 * inst + par, sizeof(int), hipMemcpyDeviceToHost);
         out->n_cut_links = n;
     }

@@ -360,6 +360,46 @@ def test_registered_correction_matches_manual_steps(mods, mode):
         sm.close()
 
 
+def test_fp16_storage_correction_paths_agree(mods):
+    B, LN = mods
+    # FP16 deviation storage: the registered correction, the host-called one
+    # and the training forward + masked add give the same lattice
+    pairs = [W.learned_pair_c5(s, L=64, n_markers=128) for s in (10003, 10006)]
+    for c, _ in pairs:
+        c.problem.storage = W.STORE_FP16
+        c.problem.math = W.MATH_FP32
+    _say("FP16 storage: registered == step + correct (bit-exact) ~ step + forward + apply")
+    Wt, b = _params(14, bias=0.2)
+    net, _, _ = _net(LN, Wt, b)
+    sc = LN.make_scales(**SC)
+    sims = [B.Sim([c.problem for c, _ in pairs], [c.X0 for c, _ in pairs]) for _ in range(4)]
+    reg, manual, fwd, plain = sims
+    br = LN.Band(reg)
+    br.attach(net, sc)
+    reg.step(6)
+    bm, bf = LN.Band(manual), LN.Band(fwd)
+    for _ in range(6):
+        manual.step(1)
+        bm.correct(net, sc)
+        fwd.step(1)
+        bf.find()
+        bf.patches(sc)
+        out, _ = net.forward(bf.inp)
+        bf.apply(out, sc)
+    plain.step(6)
+    for j in range(2):
+        fr = reg.fields(B.F_DISTRIB, inst=j)
+        assert np.array_equal(fr, manual.fields(B.F_DISTRIB, inst=j))
+        d_reg = fr - plain.fields(B.F_DISTRIB, inst=j)
+        d_fwd = fwd.fields(B.F_DISTRIB, inst=j) - plain.fields(B.F_DISTRIB, inst=j)
+        _say(f"  inst {j}: max |df| {np.abs(d_reg).max():.3e}, rel L2 reg vs fwd {_rel(d_reg, d_fwd):.3e}")
+        assert np.abs(d_reg).max() > 0
+        # both round every corrected value to FP16 once, in the same way
+        assert _rel(d_reg, d_fwd) <= 1e-3
+    for sm in sims:
+        sm.close()
+
+
 def test_training_reduces_the_loss(mods):
     import torch
     B, LN = mods
