@@ -269,6 +269,11 @@ def bench_batch(args, B, W) -> int:
     the autotuner.  The sweep's average duration is taken in a second, event-
     timed pass of direct launches over the same state."""
     import torch
+    # the stiffest instances of this ensemble (kappa near 0.1 at 0.5 lu
+    # marker spacing) leave the explicit spring scheme's stable range after
+    # about 1000 steps (markers cluster, chords pass 2 lu, as in the oracle);
+    # the line is timed over at most 1000 steps
+    args.steps = min(args.steps, 1000)
     ws = W.membrane_batch_c4(n_inst=args.instances or 512)
     for w in ws:
         w.problem.math = W.MATH_FP64 if args.math == "fp64" else W.MATH_FP32
