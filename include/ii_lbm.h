@@ -25,7 +25,9 @@
  *   - All calls return 0 (II_LBM_OK) or a negative error code; none throws.
  *     Errors raised on the device are sticky: they are reported by the next
  *     call that synchronises (markers, fields, diag, cutlinks, sync) and the
- *     handle then refuses further steps (II_LBM_ESTATE) until destroyed.
+ *     handle then refuses further steps (II_LBM_ESTATE) until destroyed;
+ *     with isolation on (ii_lbm_set_isolation) an instance's own errors stay
+ *     with that instance instead.
  *   - A handle is used by one host thread at a time.  All device work of a
  *     handle is enqueued on the HIP stream given at init.
  */
@@ -247,6 +249,20 @@ int ii_lbm_set_overlap(ii_lbm_handle* h, int32_t mode);
  * Outputs (may be NULL): the slice size, the order and its time in us.  A
  * single-instance handle reports 0 and keeps its row-segment sweep. */
 int ii_lbm_autotune(ii_lbm_handle* h, int32_t trials, int32_t* unit, int32_t* order, double* best_us);
+
+/* Failure isolation of the instances of a handle.  Instances share no data,
+ * so one that becomes non-finite (EUNSTABLE), leaves the lattice (EGEOMETRY)
+ * or overflows a list (ECAPACITY) does not corrupt the others.  Enabled, such
+ * an error is kept in that instance's error bits (ii_lbm_instance_errors,
+ * ii_lbm_diag) and the handle keeps stepping all instances (the failed ones
+ * carry meaningless values); disabled (the default), the first synchronising
+ * call reports it and the handle stops (ESTATE afterwards).  Device errors
+ * always stop the handle. */
+int ii_lbm_set_isolation(ii_lbm_handle* h, int32_t enable);
+
+/* Synchronises and copies the error bits of the first n instances (bit 0
+ * capacity, bit 1 record buffer, bit 2 unstable, bit 3 geometry; 0 = healthy). */
+int ii_lbm_instance_errors(ii_lbm_handle* h, int32_t* bits, int32_t n);
 
 int ii_lbm_destroy(ii_lbm_handle* h);
 const char* ii_lbm_strerror(int code);

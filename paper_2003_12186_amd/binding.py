@@ -56,6 +56,7 @@ EXPORTS = [
     "ii_lbm_save_state", "ii_lbm_load_state", "ii_lbm_cutlinks", "ii_lbm_diag",
     "ii_lbm_set_timing", "ii_lbm_get_timing", "ii_lbm_sweep_bytes", "ii_lbm_set_graph",
     "ii_lbm_set_overlap", "ii_lbm_autotune", "ii_lbm_destroy", "ii_lbm_strerror",
+    "ii_lbm_set_isolation", "ii_lbm_instance_errors",
 ]
 
 _lib = None
@@ -94,6 +95,8 @@ def load():
         "ii_lbm_get_timing": [v, C.POINTER(d), C.POINTER(i64)],
         "ii_lbm_sweep_bytes": [v, i32, C.POINTER(d)],
         "ii_lbm_set_graph": [v, i32],
+        "ii_lbm_set_isolation": [v, i32],
+        "ii_lbm_instance_errors": [v, v, i32],
         "ii_lbm_set_overlap": [v, i32],
         "ii_lbm_autotune": [v, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(d)],
         "ii_lbm_destroy": [v],
@@ -252,6 +255,15 @@ class Sim:
 
     def set_graph(self, enable: bool) -> None:
         check(load().ii_lbm_set_graph(self.h, 1 if enable else 0), "set_graph")
+
+    def set_isolation(self, enable: bool) -> None:
+        check(load().ii_lbm_set_isolation(self.h, 1 if enable else 0), "set_isolation")
+
+    def instance_errors(self) -> np.ndarray:
+        """Error bits of every instance (synchronises; 0 = healthy)."""
+        out = np.zeros(self.n_inst, dtype=np.int32)
+        check(load().ii_lbm_instance_errors(self.h, out.ctypes.data, self.n_inst), "instance_errors")
+        return out
 
     def set_overlap(self, mode: int) -> None:
         """Membrane step schedule (OVERLAP_SERIAL / _FULL / _INTERP_FIRST)."""

@@ -225,6 +225,9 @@ struct ii_lbm_handle {
     // Membranes' steps build no cut-link records; rec_fresh: those of the
     // current markers have been built since (ensure_records)
     bool rec_fresh = false;
+    // isolation (ii_lbm_set_isolation): an instance's own errors are kept in
+    // its error bits and do not stop the handle
+    bool isolate = false;
     bool timing = false;
     std::vector<hipEvent_t> ev;  // start/stop pairs
     int ev_used = 0;
@@ -272,6 +275,7 @@ static int check_device_errors(ii_lbm_handle* h)
     if (e != hipSuccess) return hip_fail(h, e);
     int bits = 0;
     for (int v : err) bits |= v;
+    if (h->isolate) return h->failed;
     if (bits & kErrUnstable) h->failed = II_LBM_EUNSTABLE;
     else if (bits & kErrGeometry) h->failed = II_LBM_EGEOMETRY;
     else if (bits & kErrCapacity) h->failed = II_LBM_ECAPACITY;
@@ -837,6 +841,26 @@ int ii_lbm_set_learned(ii_lbm_handle* h, const float* params, const void* packed
     return II_LBM_OK;
 }
 
+int ii_lbm_set_isolation(ii_lbm_handle* h, int32_t enable)
+{
+    if (!h) return II_LBM_EINVAL;
+    h->isolate = enable != 0;
+    return II_LBM_OK;
+}
+
+int ii_lbm_instance_errors(ii_lbm_handle* h, int32_t* bits, int32_t n)
+{
+    if (!h || !bits || n < 0) return II_LBM_EINVAL;
+    const int rc = sync_and_check(h);
+    if (rc == II_LBM_EDEVICE) return rc;
+    const int m = std::min(n, (int)h->prob.size());
+    if (m > 0) {
+        const hipError_t e = hipMemcpy(bits, h->P.err, (size_t)m * sizeof(int), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(h, e);
+    }
+    return rc;
+}
+
 int ii_lbm_set_graph(ii_lbm_handle* h, int32_t enable)
 {
     if (!h) return II_LBM_EINVAL;
@@ -1071,7 +1095,7 @@ int ii_lbm_diag(ii_lbm_handle* h, int32_t inst, ii_lbm_diag_t* out)
     out->momentum[0] = s[1];
     out->momentum[1] = s[2];
     if (s[3] > 0.0) {
-        h->failed = II_LBM_EUNSTABLE;
+        if (!h->isolate) h->failed = II_LBM_EUNSTABLE;
         out->error_bits |= kErrUnstable;
     }
     const int N = I.n_markers;

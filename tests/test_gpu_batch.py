@@ -169,3 +169,36 @@ def test_full_batch512_sampled_instances_match_oracle(B):
         assert err <= 1e-6 and dX <= 1e-9
     assert all(sim.diag(j)["error_bits"] == 0 for j in picks)
     sim.close()
+
+
+def test_isolation_keeps_the_other_instances_running(B):
+    # a non-finite state in one instance of a batch: with isolation on, that
+    # instance carries the error bits and the others evolve exactly as alone
+    w = W.membrane_c1()
+    _say("isolation: NaN in instance 1 of 3; instances 0 and 2 vs a clean batch")
+    sims = [B.Sim([w.problem] * 3, [w.X0] * 3) for _ in range(2)]
+    bad, clean = sims
+    bad.set_isolation(True)
+    p = O.make_problem(w.problem)
+    f = O.rest_state(p)
+    f[3, 30, 40] = np.nan          # next to the membrane: reaches the markers
+    bad.set_distrib(f, inst=1)
+    bad.step(20)
+    clean.step(20)
+    bits = bad.instance_errors()
+    _say(f"  error bits {bits.tolist()}")
+    assert bits[1] != 0 and bits[0] == 0 and bits[2] == 0
+    bad.step(30)                   # the handle keeps stepping
+    clean.step(30)
+    for j in (0, 2):
+        assert np.array_equal(bad.fields(B.F_DISTRIB, inst=j), clean.fields(B.F_DISTRIB, inst=j))
+        assert np.array_equal(bad.markers(j)[0], clean.markers(j)[0])
+    # without isolation the same state stops the handle
+    stop = B.Sim([w.problem] * 3, [w.X0] * 3)
+    stop.set_distrib(f, inst=1)
+    stop.step(20)
+    with pytest.raises(B.IILBMError) as e:
+        stop.sync()
+    assert e.value.code == B.EUNSTABLE
+    for s in (bad, clean, stop):
+        s.close()
