@@ -256,6 +256,61 @@ def bench_learned(args, B, W) -> int:
     return 0
 
 
+def bench_cylinder(args, B, W) -> int:
+    """Rigid cylinder (D = 32) in the 1024 x 512 channel: MRT, extrapolation
+    walls, parabolic inflow, direct forcing; the configured 20000 steps as HIP
+    graphs, then the drag and lift coefficients C = 2 F / (U_mean^2 D).  The
+    lattice pair (37.7 MB) fits in the Infinity Cache, so the sweep's
+    bandwidth is not an HBM figure."""
+    import torch
+    storage = W.STORE_FP16 if args.storage == "fp16" else W.STORE_FP32
+    w = W.cylinder_c2(re=args.re, storage=storage)
+    p = w.problem
+    p.math = W.MATH_FP64 if args.math == "fp64" else W.MATH_FP32
+    sim = B.Sim([p], [w.X0], device="cuda:0")
+    sim.set_graph(args.graph == "on")
+    sim.step(args.warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    d = sim.diag()
+    sim.set_graph(False)
+    sim.set_timing(True)
+    sim.step(min(args.steps, 200))
+    sim.sync()
+    sweep_ms, launches = sim.get_timing()
+    sim.set_timing(False)
+    avg = sweep_ms / 1e3 / max(launches, 1)
+    bytes_per_launch = sim.sweep_bytes()
+    achieved = bytes_per_launch / avg / 1e9
+    scale = 2.0 / (w.meta["u_mean"] ** 2 * w.meta["D"])
+    out = {
+        "metric": "MLUPS & %HBM peak; learned 2x-coarse vs fine II-LBM time at <=1e-2 L2 err",
+        "value": round(p.nx * p.ny * args.steps / dt / 1e6, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3 / args.steps, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": ("f32" if storage == W.STORE_FP32 else "f16") + " storage / " + args.math + " collision",
+        "data": "synthetic",
+        "config": {"workload": f"cylinder{p.nx}x{p.ny}_D32_Re{int(args.re)}", "nx": p.nx, "ny": p.ny,
+                   "markers": p.n_markers, "tau": round(p.tau, 6), "collision": "mrt",
+                   "graph": args.graph == "on", "C_D": d["force"][0] * scale,
+                   "C_L": d["force"][1] * scale, "cut_links": d["n_cut_links"]},
+        "roofline": {"bound": "hbm", "kernel": "k_sweep", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "cache_resident": True, "bytes_per_launch": bytes_per_launch,
+                     "avg_launch_us": round(avg * 1e6, 2), "timed_launches": launches},
+    }
+    if not args.no_cpu:
+        # the lattice is 32 x smaller than the membrane bench's: 16 x the steps
+        out["cpu_baseline"] = cpu_baseline(w, 16 * args.cpu_steps)
+    sim.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def set_overlap(sim, B, args) -> None:
     modes = {"serial": B.OVERLAP_SERIAL, "full": B.OVERLAP_FULL,
              "interp_first": B.OVERLAP_INTERP_FIRST}
@@ -337,11 +392,13 @@ def main() -> int:
                          "for FP32 storage (its 1e-6 parity bar) and FP32 for FP16 storage "
                          "(1e-3 bar)")
     ap.add_argument("--size", type=int, default=4096)
-    ap.add_argument("--workload", choices=["membrane", "batch512", "learned"], default="membrane",
+    ap.add_argument("--workload", choices=["membrane", "batch512", "learned", "cylinder"],
+                    default="membrane",
                     help="membrane: one L x L membrane (the bench line); batch512: 512 uneven "
                          "membrane instances advanced together; learned: 200 coarse membranes "
                          "with the learned correction every step against their fine runs (both "
                          "reported in the design notes)")
+    ap.add_argument("--re", type=float, default=100.0, help="Reynolds number of the cylinder workload")
     ap.add_argument("--instances", type=int, default=None,
                     help="instances of the batch512 (default 512) or learned (200) workload")
     ap.add_argument("--graph", choices=["on", "off"], default="on",
@@ -355,7 +412,7 @@ def main() -> int:
                          "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.steps is None:
-        args.steps = 4000 if args.workload == "batch512" else 2000
+        args.steps = {"batch512": 4000, "cylinder": 20000}.get(args.workload, 2000)
     if args.math is None:
         args.math = "fp32" if args.storage == "fp16" else "fp64"
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -380,6 +437,8 @@ def main() -> int:
         return bench_batch(args, B, W)
     if args.workload == "learned":
         return bench_learned(args, B, W)
+    if args.workload == "cylinder":
+        return bench_cylinder(args, B, W)
     storage = W.STORE_FP16 if args.storage == "fp16" else W.STORE_FP32
     w = W.membrane_c3(L=args.size, storage=storage)
     p = w.problem
