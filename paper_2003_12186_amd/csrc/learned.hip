@@ -732,7 +732,7 @@ __global__ void k_targets(const InstDev* __restrict__ ic, const void* Ac,
 }
 
 // The network and the masked add of one coarse step on the patches that
-// k_patches built from the state before any tile was corrected (a tile's
+// k_patch_geom and k_patch_flow built from the state before any tile was corrected (a tile's
 // halo overlaps its neighbours' nodes).  Persistent: one block of twelve
 // waves per compute unit (LDS holds one block's buffers and fragments)
 // stages every forward weight fragment in LDS once and
