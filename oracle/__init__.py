@@ -21,7 +21,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 SRT, MRT = 0, 1
 PERIODIC, WALL, INLET, OUTLET = 0, 1, 2, 3
 IF_NONE, IF_MEMBRANE, IF_RIGID = 0, 1, 2
-II_LBM, IB_LBM = 0, 1
+II_LBM, IB_LBM, IB_LBM_GUO, II_LBM_GUO = 0, 1, 2, 3
 
 
 def build(force: bool = False) -> str:
@@ -76,6 +76,7 @@ def lib():
             "or_moments": (None, [P, d, d, d, d]),
             "or_mrt_matrices": (None, [d, d]),
             "or_collide_node": (None, [P, d, C.c_double, C.c_double, d]),
+            "or_guo_term": (None, [C.c_double, C.c_double, C.c_double, C.c_double, d]),
             "or_peskin_phi": (C.c_double, [C.c_double]),
             "or_interp": (None, [P, d, d, d, d]),
             "or_spread": (None, [P, d, d, d, d]),
@@ -165,6 +166,13 @@ def collide_node(p: Problem, f9, gx=0.0, gy=0.0):
     f9 = np.ascontiguousarray(f9, dtype=np.float64)
     out = np.zeros(9)
     lib().or_collide_node(C.byref(p), _ptr(f9), gx, gy, _ptr(out))
+    return out
+
+
+def guo_term(ux, uy, gx, gy):
+    """G~_i of Guo's force term (without its relaxation factor)."""
+    out = np.zeros(9)
+    lib().or_guo_term(float(ux), float(uy), float(gx), float(gy), _ptr(out))
     return out
 
 

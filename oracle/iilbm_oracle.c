@@ -34,7 +34,13 @@
  *      to a 2^-16 grid, tested with exact integer orientations and the node
  *      perturbation tie rule; [[p]] is linear along each chord;
  *  R11 marker velocity from u = sum e_i f_i of the pre-collision field;
- *  R12 non-equilibrium extrapolation on non-periodic sides, corners as walls.
+ *  R12 non-equilibrium extrapolation on non-periodic sides, corners as walls;
+ *  R24 under Guo's force term (the comparison method of Sec. 2.2.2) the
+ *      collision uses the compressible equilibrium and the velocity
+ *      u = (sum e_i f_i + g/2) / rho the paper gives with it, g the whole
+ *      Eulerian force (g_par plus the body force for II-LBM, Sec. 3.2); the
+ *      markers move with that u (R11 holds for the simple force term); the
+ *      direct-forcing u* carries the body force only.
  */
 #define _GNU_SOURCE
 #include <math.h>
@@ -48,7 +54,11 @@
 enum { OR_SRT = 0, OR_MRT = 1 };
 enum { OR_PERIODIC = 0, OR_WALL = 1, OR_INLET = 2, OR_OUTLET = 3 };
 enum { OR_IF_NONE = 0, OR_IF_MEMBRANE = 1, OR_IF_RIGID = 2 };
-enum { OR_II_LBM = 0, OR_IB_LBM = 1 };
+/* Force modes: II-LBM (jumps, tangential force in the simple term, the
+ * paper's method); IB-LBM (the full force spread, no jumps) with the simple
+ * term or Guo's term; II-LBM with Guo's term of the tangential force
+ * (Sec. 3.2, the remark on Guo's terms). */
+enum { OR_II_LBM = 0, OR_IB_LBM = 1, OR_IB_LBM_GUO = 2, OR_II_LBM_GUO = 3 };
 
 typedef struct {
     int32_t nx, ny;
@@ -65,6 +75,9 @@ typedef struct {
     double kappa, dX;
     double cx, cy, radius; /* rigid circle */
 } or_problem;
+
+static int has_jumps(const or_problem *p) { return p->force_mode == OR_II_LBM || p->force_mode == OR_II_LBM_GUO; }
+static int uses_guo(const or_problem *p) { return p->force_mode == OR_IB_LBM_GUO || p->force_mode == OR_II_LBM_GUO; }
 
 /* One cut link: source node (x, y), direction i, its sign and where it is cut. */
 typedef struct {
@@ -192,11 +205,63 @@ static void collide_with(const or_problem *p, const double *M, const double *Min
     for (int i = 0; i < 9; i++) out[i] += WT[i] * (EX[i] * gx + EY[i] * gy) / CS2;
 }
 
+/* Guo's force distribution without its relaxation factor (Sec. 2.2.2, the
+ * bracket of Eq. (SRT_Guo_) and the G~_i of Eq. (MRT_Guo_)):
+ *   G~_i = w_i [ (e_i - u)/c_s^2 + (e_i.u) e_i / c_s^4 ] . g */
+void or_guo_term(double ux, double uy, double gx, double gy, double *G)
+{
+    for (int i = 0; i < 9; i++) {
+        double eu = EX[i] * ux + EY[i] * uy, eg = EX[i] * gx + EY[i] * gy;
+        G[i] = WT[i] * (((EX[i] - ux) * gx + (EY[i] - uy) * gy) / CS2 + eu * eg / (CS2 * CS2));
+    }
+}
+
+/* Collision with Guo's force term (reading R24): the velocity
+ * p/c_s^2 u = sum_i e_i f_i + g/2 and the equilibrium
+ * w_i p/c_s^2 [1 + e.u/c_s^2 + (e.u)^2/(2 c_s^4) - u.u/(2 c_s^2)];
+ * SRT: f* = f - (f - f_eq)/tau + (1 - 1/(2 tau)) G~;
+ * MRT: f* = f - M^-1 S (M f - M f_eq) + M^-1 (I - S/2) M G~. */
+static void collide_guo(const or_problem *p, const double *M, const double *Minv,
+                        const double *f, double gx, double gy, double *out)
+{
+    double rho, jx, jy, feq[9], G[9];
+    or_moments_node(f, &rho, &jx, &jy);
+    double ux = (jx + 0.5 * gx) / rho, uy = (jy + 0.5 * gy) / rho;
+    double uu = ux * ux + uy * uy;
+    for (int i = 0; i < 9; i++) {
+        double eu = EX[i] * ux + EY[i] * uy;
+        feq[i] = WT[i] * rho * (1.0 + eu / CS2 + eu * eu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
+    }
+    or_guo_term(ux, uy, gx, gy, G);
+    if (p->collision == OR_SRT) {
+        for (int i = 0; i < 9; i++)
+            out[i] = f[i] - (f[i] - feq[i]) / p->tau + (1.0 - 0.5 / p->tau) * G[i];
+        return;
+    }
+    double m[9], meq[9], mg[9], mstar[9];
+    for (int a = 0; a < 9; a++) {
+        m[a] = 0.0; meq[a] = 0.0; mg[a] = 0.0;
+        for (int i = 0; i < 9; i++) {
+            m[a] += M[a * 9 + i] * f[i];
+            meq[a] += M[a * 9 + i] * feq[i];
+            mg[a] += M[a * 9 + i] * G[i];
+        }
+        mstar[a] = m[a] - p->s[a] * (m[a] - meq[a]) + (1.0 - 0.5 * p->s[a]) * mg[a];
+    }
+    for (int i = 0; i < 9; i++) {
+        out[i] = 0.0;
+        for (int a = 0; a < 9; a++) out[i] += Minv[i * 9 + a] * mstar[a];
+    }
+}
+
 void or_collide_node(const or_problem *p, const double *f, double gx, double gy, double *out)
 {
     double M[81], Minv[81];
     or_mrt_matrices(M, Minv);
-    collide_with(p, M, Minv, f, gx, gy, out);
+    if (uses_guo(p))
+        collide_guo(p, M, Minv, f, gx, gy, out);
+    else
+        collide_with(p, M, Minv, f, gx, gy, out);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -565,8 +630,9 @@ typedef struct {
  * with [[f_i]] = w_i [[p]] / c_s^2 (Sec. 3.1, Eq. (32)) on every cut link,
  * f* = collide(f) + w_i e_i.g_par / c_s^2, g_par the spread tangential force;
  * then X^{n+1} = X^n + U^n (Sec. 2.2.2, Eq. (20)).
- * Under force_mode IB-LBM the full G is spread and no jump is applied
- * (Sec. 2.2.2, Eq. (16)-(17)), the comparison method of the paper. */
+ * Under the IB-LBM force modes the full G is spread and no jump is applied
+ * (Sec. 2.2.2, Eq. (16)-(17)), the comparison method of the paper; the Guo
+ * modes collide with Guo's term of the spread force (reading R24). */
 int or_step(const or_problem *p, double *f, double *X, or_step_out *out)
 {
     int nx = p->nx, ny = p->ny, N = p->n_markers;
@@ -589,15 +655,35 @@ int or_step(const or_problem *p, double *f, double *X, or_step_out *out)
     /* 1. moments of f^n; uniform body force */
     or_moments(p, f, rho, ux, uy);
     for (long n = 0; n < nn; n++) { gx[n] = p->body[0]; gy[n] = p->body[1]; }
+    /* under Guo's term the velocity carries half the force (reading R24);
+     * before the spread that is the body force alone */
+    double *jx = NULL, *jy = NULL;
+    if (uses_guo(p)) {
+        jx = calloc(nn, sizeof(double)); jy = calloc(nn, sizeof(double));
+        memcpy(jx, ux, nn * sizeof(double)); memcpy(jy, uy, nn * sizeof(double));
+        for (long n = 0; n < nn; n++) {
+            ux[n] = (jx[n] + 0.5 * gx[n]) / rho[n];
+            uy[n] = (jy[n] + 0.5 * gy[n]) / rho[n];
+        }
+    }
 
     if (p->interface != OR_IF_NONE && N > 0) {
         /* 2. marker velocity from u^n; force, normal, [[p]], tangential part */
         or_interp(p, ux, uy, X, U);
         or_marker_forces(p, X, U, G, nrm, J, jp, Gt);
         /* 3. spread the tangential force (the full force under IB-LBM) */
-        or_spread(p, X, p->force_mode == OR_II_LBM ? Gt : G, gx, gy);
+        or_spread(p, X, has_jumps(p) ? Gt : G, gx, gy);
+        /* 3b. Guo's term: a membrane moves with u = (j + g/2) / rho of the
+         *     whole force (a membrane's force depends on X alone) */
+        if (uses_guo(p) && p->interface == OR_IF_MEMBRANE) {
+            for (long n = 0; n < nn; n++) {
+                ux[n] = (jx[n] + 0.5 * gx[n]) / rho[n];
+                uy[n] = (jy[n] + 0.5 * gy[n]) / rho[n];
+            }
+            or_interp(p, ux, uy, X, U);
+        }
         /* 4. cut links and the per-link jump sigma w_i [[p]] / c_s^2 */
-        if (p->force_mode == OR_II_LBM) {
+        if (has_jumps(p)) {
             int cap = 64 * N + 4096;
             links = calloc(cap, sizeof(or_link));
             nl = or_cutlinks(p, X, jp, links, cap);
@@ -618,7 +704,10 @@ int or_step(const or_problem *p, double *f, double *X, or_step_out *out)
             double fn[9], fo[9];
             long n = (long)y * nx + x;
             for (int i = 0; i < 9; i++) fn[i] = f[idx(p, i, x, y)];
-            collide_with(p, M, Minv, fn, gx[n], gy[n], fo);
+            if (uses_guo(p))
+                collide_guo(p, M, Minv, fn, gx[n], gy[n], fo);
+            else
+                collide_with(p, M, Minv, fn, gx[n], gy[n], fo);
             for (int i = 0; i < 9; i++) fpost[idx(p, i, x, y)] = fo[i];
         }
 
@@ -655,7 +744,7 @@ int or_step(const or_problem *p, double *f, double *X, or_step_out *out)
         out->n_links = nl;
     }
     free(rho); free(ux); free(uy); free(gx); free(gy); free(fpost); free(jump);
-    free(U); free(G); free(nrm); free(J); free(jp); free(Gt); free(links);
+    free(U); free(G); free(nrm); free(J); free(jp); free(Gt); free(links); free(jx); free(jy);
     return bad ? -1 : 0;
 }
 

@@ -100,7 +100,7 @@ class SplitMix64:
 SRT, MRT = 0, 1
 BC_PERIODIC, BC_WALL, BC_INLET, BC_OUTLET = 0, 1, 2, 3
 IF_NONE, IF_MEMBRANE, IF_RIGID = 0, 1, 2
-FORCE_II_LBM, FORCE_IB_LBM = 0, 1
+FORCE_II_LBM, FORCE_IB_LBM, FORCE_IB_LBM_GUO, FORCE_II_LBM_GUO = 0, 1, 2, 3
 STORE_FP32, STORE_FP16 = 0, 1
 MATH_FP32, MATH_FP64 = 0, 1
 
