@@ -55,7 +55,19 @@ extern "C" {
 enum { II_LBM_SRT = 0, II_LBM_MRT = 1 };
 enum { II_LBM_BC_PERIODIC = 0, II_LBM_BC_WALL = 1, II_LBM_BC_INLET = 2, II_LBM_BC_OUTLET = 3 };
 enum { II_LBM_IF_NONE = 0, II_LBM_IF_MEMBRANE = 1, II_LBM_IF_RIGID = 2 };
-enum { II_LBM_FORCE_II = 0 };
+/* Force modes (how the interface force enters the fluid):
+ *  II      the paper's method: jumps on cut links for the normal part, the
+ *          tangential part g_par in the simple force term (Sec. 3.2);
+ *  IB      the comparison IB-LBM: the whole force G spread into the simple
+ *          force term, no jumps (Sec. 2.2.2, Eqs. (16)-(17));
+ *  IB_GUO  IB-LBM with Guo's force term (Sec. 2.2.2, the SRT and MRT forms):
+ *          compressible equilibrium w_i rho [1 + e.u/c_s^2 + (e.u)^2/(2 c_s^4)
+ *          - u.u/(2 c_s^2)] with rho u = sum e_i f_i + g/2, and the markers
+ *          move with that u;
+ *  II_GUO  II-LBM with Guo's term of g_par (Sec. 3.2).
+ * The body force joins g in every mode; direct forcing's u* carries the body
+ * force only.  Field readouts report u = sum e_i f_i in every mode. */
+enum { II_LBM_FORCE_II = 0, II_LBM_FORCE_IB = 1, II_LBM_FORCE_IB_GUO = 2, II_LBM_FORCE_II_GUO = 3 };
 enum { II_LBM_FP32 = 0, II_LBM_FP16 = 1 };
 enum { II_LBM_MATH_FP32 = 0, II_LBM_MATH_FP64 = 1 };
 
@@ -74,6 +86,7 @@ enum { II_LBM_MATH_FP32 = 0, II_LBM_MATH_FP64 = 1 };
  *               4 u_max y (H - y) / H^2 with H = ny - 1; x-low only), OUTLET
  *               (zero gradient; x-high only).  Corner nodes follow the y side.
  *  body_force   uniform Eulerian force density added to the force term.
+ *  force_mode   II_LBM_FORCE_II, _IB, _IB_GUO or _II_GUO (above).
  *  interface_kind  NONE, MEMBRANE (spring force kappa (X_{k+1} - 2 X_k +
  *               X_{k-1}) / dX^2, Sec. 2.2.2 Eq. (19)) or RIGID (fixed circle
  *               with direct forcing G = U^D - U*, eta = 1, U^D = 0, Sec. 2.2.2
@@ -88,7 +101,8 @@ enum { II_LBM_MATH_FP32 = 0, II_LBM_MATH_FP64 = 1 };
  *  math         arithmetic of the collision: II_LBM_MATH_FP32, or
  *               II_LBM_MATH_FP64 (loads and stores keep the storage type; only
  *               the per-node moments, equilibrium and relaxation run in FP64).
- * Markers must stay at least 3 lattice units from every side of the lattice.
+ * Markers must stay at least 3 lattice units from every side of the lattice,
+ * and the initial chords X_{k+1} - X_k be at most 4 lattice units long.
  */
 typedef struct ii_lbm_problem {
     int32_t nx, ny;
@@ -148,6 +162,8 @@ int ii_lbm_workspace_size(const ii_lbm_problem* p, int32_t n_inst, size_t* bytes
  *  hip_stream hipStream_t on which all work is enqueued (NULL = default);
  *             membrane handles also create one internal non-blocking stream
  *             (default priority) that the handle's stream joins every step.
+ * Several instances advance together and must share storage, math and force
+ * mode, and their interfaces one kind (EINVAL otherwise).
  * The fluid starts at rest, f_i = w_i rho0.  Synchronises before returning.
  */
 int ii_lbm_init(const ii_lbm_problem* p, int32_t n_inst, const double* const* X0,

@@ -24,13 +24,17 @@ namespace iilbm {
 // each block and the y +- 1 rows its neighbours need are read by blocks
 // dispatched close in time on the same XCD.
 constexpr int kTile = 16;        // interface tiles are 16 x 16 nodes
-constexpr int kTileCap = 128;    // chords listed per interface tile
+constexpr int kTileCap = 128;    // chords listed per interface tile (II-LBM)
+constexpr int kTileCapIB = 512;  // markers listed per tile under IB-LBM (dense markers, no jumps)
 constexpr int kTileNodes = kTile * kTile;
+// Planes of a tile's correction slot: the additions to the eight moving
+// populations, then (under Guo's force term) the spread force g_x, g_y.
+constexpr int kCorrPlanes = 10;
 constexpr int kPitchAlign = 64;  // row pitch in elements
 constexpr double kSnap = 65536.0;  // marker snap grid 2^-16 lu for exact tests
 
 enum ErrBits : int {
-    kErrCapacity = 1,   // a tile had more chords than kTileCap
+    kErrCapacity = 1,   // a tile had more chords than its list holds
     kErrRecords = 2,    // cut-link record buffer full (records only)
     kErrUnstable = 4,   // non-finite marker velocity
     kErrGeometry = 8,   // a marker left the supported region
@@ -43,11 +47,15 @@ struct InstDev {
     int bounded;          // any non-periodic side
     int bc[4];
     int collision, storage, iface;
+    int jumps;            // force mode with jumps on cut links (II-LBM)
+    int guo;              // force mode with Guo's force term
     int math;             // II_LBM_MATH_FP32 or II_LBM_MATH_FP64 collision arithmetic
     int n_markers;
     int mk_off;           // offset of this instance in the marker arrays
     int tiles_x, tiles_y;
-    int tile_off;         // offset in tile_count (tiles), tile_list (tiles * kTileCap)
+    int tile_off;         // offset in tile_count and tile_slot (tiles)
+    int tile_cap;         // chord list capacity of a tile (kTileCap or kTileCapIB)
+    long long list_off;   // offset in tile_list (ints)
     int act_off, act_cap;
     int rec_off, rec_cap;
     int mk_blocks;        // 256-thread blocks of the marker kernel (16 markers each)
@@ -79,7 +87,7 @@ struct DevPtrs {
     int* tile_count;       // chords appended per tile (reset by the tile kernel)
     int* tile_list;        // chord ids per tile
     int* tile_slot[2];     // correction slot of a tile at step m (plane m & 1), -1 when none
-    float* corr[2];        // per slot: 8 x 256 additions to the outgoing populations
+    float* corr[2];        // per slot: kCorrPlanes x 256 (population additions, then g)
     int2* act_list[2];     // (instance, tile) of the tiles that hold chords, by parity
     int* act_count;        // [2 * n_inst], double-buffered by step parity
     ii_lbm_link* rec;      // cut-link records
@@ -213,6 +221,51 @@ __device__ __forceinline__ void equilibrium(M r, M ux, M uy, M e[9])
     e[8] = s[8] - a6;
 }
 
+// Deviation of the compressible equilibrium of Guo's force term (Sec. 2.2.2),
+// f_eq_i - w_i = w_i [ drho + 3 e.J + (4.5 (e.J)^2 - 1.5 J.J) / rho ] with
+// J = rho u, in the same moment-preserving arrangement as above (zeroth and
+// first moments drho and J).
+template <typename M>
+__device__ __forceinline__ void equilibrium_guo(M r, M jx, M jy, M inv_rho, M e[9])
+{
+    const M jj = jx * jx + jy * jy;
+    M s[9];
+#pragma unroll
+    for (int i = 1; i < 9; i++) {
+        const M ej = (M)EX[i] * jx + (M)EY[i] * jy;
+        s[i] = Lat<M>::w(i) * (r + ((M)4.5 * ej * ej - (M)1.5 * jj) * inv_rho);
+    }
+    s[0] = r - (((s[1] + s[2]) + (s[3] + s[4])) + ((s[5] + s[6]) + (s[7] + s[8])));
+    const M c12 = (M)(1.0 / 12.0);
+    const M a5 = c12 * (jx + jy), a6 = c12 * (jy - jx);
+    const M a1 = (M)0.5 * jx - (a5 - a6), a2 = (M)0.5 * jy - (a5 + a6);
+    e[0] = s[0];
+    e[1] = s[1] + a1;
+    e[2] = s[2] + a2;
+    e[3] = s[3] - a1;
+    e[4] = s[4] - a2;
+    e[5] = s[5] + a5;
+    e[6] = s[6] + a6;
+    e[7] = s[7] - a5;
+    e[8] = s[8] - a6;
+}
+
+// Guo's force distribution G~_i = w_i [ 3 (e_i - u).g + 9 (e_i.u)(e_i.g) ]
+// (Sec. 2.2.2) with u = J / rho; its rest entry closes the zero sum.
+template <typename M>
+__device__ __forceinline__ void guo_force(M ux, M uy, M gx, M gy, M G[9])
+{
+    const M ug = ux * gx + uy * gy;
+    M t = 0;
+#pragma unroll
+    for (int i = 1; i < 9; i++) {
+        const M eu = (M)EX[i] * ux + (M)EY[i] * uy, eg = (M)EX[i] * gx + (M)EY[i] * gy;
+        G[i] = Lat<M>::w(i) * ((M)3 * (eg - ug) + (M)9 * eu * eg);
+        t += G[i];
+    }
+    G[0] = -t;
+}
+
 // Is (x, y) a node that non-equilibrium extrapolation sets?
 __device__ __forceinline__ bool is_edge(const InstDev& I, int x, int y)
 {
@@ -343,6 +396,64 @@ __device__ __forceinline__ void collide_mrt(M d[9], const float s[9], M gx, M gy
     force_term<M>(d, gx, gy);
 }
 
+// Collisions with Guo's force term (Sec. 2.2.2): rho u = J = j + g/2, the
+// compressible equilibrium of J and
+//   SRT: d* = d + omega (d_eq - d) + (1 - omega/2) G~,
+//   MRT: d* = d - M^-1 [ S M (d - d_eq) - (I - S/2) M G~ ].
+// The momentum moments gain exactly g whatever their rate (the relaxation of
+// j - J = -g/2 and (1 - s/2) g add up to g), so they take g directly.
+template <typename M>
+__device__ __forceinline__ void guo_prepare(const M d[9], M gx, M gy, M e[9], M G[9])
+{
+    M r, jx, jy;
+    moments<M>(d, r, jx, jy);
+    const M inv_rho = (M)1 / ((M)1 + r);
+    const M Jx = jx + (M)0.5 * gx, Jy = jy + (M)0.5 * gy;
+    equilibrium_guo<M>(r, Jx, Jy, inv_rho, e);
+    guo_force<M>(Jx * inv_rho, Jy * inv_rho, gx, gy, G);
+}
+
+template <typename M>
+__device__ __forceinline__ void collide_guo_srt(M d[9], M omega, M gx, M gy)
+{
+    M e[9], G[9];
+    guo_prepare<M>(d, gx, gy, e, G);
+    const M h = (M)1 - (M)0.5 * omega;
+#pragma unroll
+    for (int i = 0; i < 9; i++) d[i] = d[i] + omega * (e[i] - d[i]) + h * G[i];
+}
+
+template <typename M>
+__device__ __forceinline__ void collide_guo_mrt(M d[9], const float s[9], M gx, M gy)
+{
+    M e[9], G[9];
+    guo_prepare<M>(d, gx, gy, e, G);
+    M m[9];
+#pragma unroll
+    for (int a = 0; a < 9; a++) {
+        M ne = 0, mg = 0;
+#pragma unroll
+        for (int i = 0; i < 9; i++)
+            if (MB[a][i] != 0) {
+                ne += (M)MB[a][i] * (d[i] - e[i]);
+                mg += (M)MB[a][i] * G[i];
+            }
+        const M sa = (M)s[a];
+        m[a] = (M)MBN[a] * (sa * ne - ((M)1 - (M)0.5 * sa) * mg);
+    }
+    m[0] = 0;
+    m[3] = -(M)MBN[3] * gx;
+    m[5] = -(M)MBN[5] * gy;
+#pragma unroll
+    for (int i = 0; i < 9; i++) {
+        M acc = 0;
+#pragma unroll
+        for (int a = 0; a < 9; a++)
+            if (MB[a][i] != 0) acc += (M)MB[a][i] * m[a];
+        d[i] = d[i] - acc;
+    }
+}
+
 // Work tables of the batched launches: one entry (instance, unit) per block.
 struct Batch {
     const InstDev* insts;  // device copy of the descriptors
@@ -352,6 +463,8 @@ struct Batch {
     int mk_units, tile_units, sweep_units;
     int sweep_unit;        // 128, 256 or 512 nodes per sweep block
     int storage, math, iface;
+    int guo;               // Guo's force term (uniform over the batch)
+    int jumps;             // II-LBM force mode (uniform over the batch)
 };
 
 // What other translation units may see of a handle: descriptors (host and

@@ -4,7 +4,8 @@
 //              outward normal, |dX/ds|, [[p]] and the tangential part; the new
 //              position X^{n+1}; binning of chord (k, k+1) into 16x16 tiles.
 //   k_tiles    one block per tile that holds chords: spreads the tangential
-//              force onto its nodes, finds every cut link leaving its nodes
+//              force (the whole force under IB-LBM) onto its nodes, finds
+//              (under II-LBM) every cut link leaving its nodes
 //              with exact integer predicates, writes the force term plus the
 //              jumps of every outgoing population into the tile's correction
 //              slot (added by the sweep before its store), and compacts the
@@ -67,18 +68,40 @@ __device__ __forceinline__ void markers_body(const InstDev& I, const DevPtrs& P,
     double us = 0.0, vs = 0.0;
     if (MODE & kModeInterp) {
         // u^m of the pre-collision f^m at this lane's stencil node, weighted,
-        // summed in FP64 over the group in a fixed tree
+        // summed in FP64 over the group in a fixed tree.  Under Guo's term
+        // u = (sum e f + g/2) / rho (Sec. 2.2.2): g is the body force plus,
+        // for a membrane, the force this step's tile pass spread (the node's
+        // slot of plane `par`); direct forcing's u* has the body force only.
         const double w = wx * wy;
         double cu = 0.0, cv = 0.0;
         if (w != 0.0) {
             M d[9];
-            gather<T, M>(I, A, wrap_or_clamp(fx0 + sx, I.nx, I.px),
-                         wrap_or_clamp(fy0 + sy, I.ny, I.py), d);
+            const int xs = wrap_or_clamp(fx0 + sx, I.nx, I.px);
+            const int ys = wrap_or_clamp(fy0 + sy, I.ny, I.py);
+            gather<T, M>(I, A, xs, ys, d);
             double u = 0.0, v = 0.0;
 #pragma unroll
             for (int i = 1; i < 9; i++) {
                 u += (double)EX[i] * (double)d[i];
                 v += (double)EY[i] * (double)d[i];
+            }
+            if (I.guo) {
+                double r = 0.0;
+#pragma unroll
+                for (int i = 0; i < 9; i++) r += (double)d[i];
+                double gx = (double)I.body[0], gy = (double)I.body[1];
+                if (!(MODE & kModeGeom)) {
+                    const int slot =
+                        P.tile_slot[par][I.tile_off + (ys / kTile) * I.tiles_x + (xs / kTile)];
+                    if (slot >= 0) {
+                        const float* c = P.corr[par] + (long long)slot * kCorrPlanes * kTileNodes +
+                                         (ys % kTile) * kTile + (xs % kTile);
+                        gx += (double)c[8 * kTileNodes];
+                        gy += (double)c[9 * kTileNodes];
+                    }
+                }
+                u = (u + 0.5 * gx) / (1.0 + r);
+                v = (v + 0.5 * gy) / (1.0 + r);
             }
             cu = u * w;
             cv = v * w;
@@ -176,8 +199,8 @@ __device__ __forceinline__ void markers_body(const InstDev& I, const DevPtrs& P,
         const int t = (ty0 + q / tw) * I.tiles_x + tx0 + q % tw;
         const int gt = I.tile_off + t;
         const int pos = atomicAdd(&P.tile_count[gt], 1);
-        if (pos < kTileCap)
-            P.tile_list[(long long)gt * kTileCap + pos] = k;
+        if (pos < I.tile_cap)
+            P.tile_list[I.list_off + (long long)t * I.tile_cap + pos] = k;
         else
             atomicOr(&P.err[I.inst], (int)kErrCapacity);
         if (pos == 0) {
@@ -447,7 +470,7 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
         const int x0 = tx * kTile, y0 = ty * kTile;
         // the list is read whole (its slots beyond the count are stale but
         // allocated) while thread 0 reads the count
-        if (tid < kTileCap) S.raw[tid] = P.tile_list[(long long)gt * kTileCap + tid];
+        if (tid < kTileCap) S.raw[tid] = P.tile_list[I.list_off + (long long)t * kTileCap + tid];
         if (tid == 0) {
             S.cnt = min(P.tile_count[gt], kTileCap);
             S.nrec = 0;
@@ -480,7 +503,7 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
                 wxd[q] = P.wx[4 * mk + q];
                 wyd[q] = P.wy[4 * mk + q];
             }
-            g = P.Gt[mk];
+            g = I.jumps ? P.Gt[mk] : P.G[mk];
             for (int m = 0; m < c; m++) r += (S.raw[m] < k) ? 1 : 0;
         }
         __syncthreads();   // raw is reused as start below
@@ -497,7 +520,7 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
             const int by1 = min((int)(-((-max(ay, by)) >> 16)) + 1, min(y0 + kTile, I.ny) - 1);
             S.box[r][0] = (short)bx0; S.box[r][1] = (short)bx1;
             S.box[r][2] = (short)by0; S.box[r][3] = (short)by1;
-            S.start[r] = (IFACE == II_LBM_IF_MEMBRANE && bx0 <= bx1 && by0 <= by1)
+            S.start[r] = (IFACE == II_LBM_IF_MEMBRANE && I.jumps && bx0 <= bx1 && by0 <= by1)
                              ? (bx1 - bx0 + 1) * (by1 - by0 + 1) : 0;
             S.jpa[r] = jpa;
             S.jpb[r] = jpb;
@@ -575,7 +598,7 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
                 gx += S.gtx[j] * wgt * I.dX;
                 gy += S.gty[j] * wgt * I.dX;
             }
-            if (IFACE == II_LBM_IF_RIGID) {
+            if (IFACE == II_LBM_IF_RIGID && I.jumps) {
                 // Rigid circle: level set phi = |x - c|^2 - R^2, interior phi < 0.
                 const double R2 = I.radius * I.radius;
                 const double dx = (double)x - I.cx, dy = (double)y - I.cy;
@@ -597,18 +620,24 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
         }
         __syncthreads();
 
-        // Corrections of this node's outgoing populations: force term of the
-        // tangential force plus the jumps of the links it sends; the sweep
-        // adds them before its single store.
+        // Corrections of this node's outgoing populations: the simple force
+        // term of the spread force plus the jumps of the links it sends; the
+        // sweep adds them before its single store.  Under Guo's term the
+        // populations take the jumps alone and the force itself follows.
         {
-            float* cr = P.corr[parity] + (long long)(I.act_off + a) * 8 * kTileNodes + tid;
+            float* cr = P.corr[parity] + (long long)(I.act_off + a) * kCorrPlanes * kTileNodes + tid;
+            const double fs = I.guo ? 0.0 : 3.0;
 #pragma unroll
             for (int i = 1; i < 9; i++) {
                 const double delta =
-                    valid ? 3.0 * WD[i] * ((double)EX[i] * gx + (double)EY[i] * gy) +
+                    valid ? fs * WD[i] * ((double)EX[i] * gx + (double)EY[i] * gy) +
                                 (double)S.acc[i - 1][tid]
                           : 0.0;
                 cr[(i - 1) * kTileNodes] = (float)delta;
+            }
+            if (I.guo) {
+                cr[8 * kTileNodes] = valid ? (float)gx : 0.f;
+                cr[9 * kTileNodes] = valid ? (float)gy : 0.f;
             }
         }
         // Records of this tile: one global slice for the block; each is
@@ -656,6 +685,99 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
     }
 }
 
+// ---------------------------------------------------------------------------
+// IB-LBM tile pass: no cut links, so a tile only gathers the force of the
+// markers binned to it, G spread with the delta weights of the marker pass
+// (Sec. 2.2.2), summed in increasing marker order.  The comparison method
+// places markers 1/3 lu apart, so a tile lists up to kTileCapIB of them.
+// ---------------------------------------------------------------------------
+struct TileSharedIB {
+    int raw[kTileCapIB];         // marker ids as binned
+    int2 f0[kTileCapIB];         // in increasing id order: first stencil node,
+    float wx[kTileCapIB][4], wy[kTileCapIB][4];   // delta weights,
+    double gx[kTileCapIB], gy[kTileCapIB];        // and force
+    int cnt;
+};
+
+__device__ __forceinline__ void tiles_ib_body(const InstDev& I, const DevPtrs& P, int parity,
+                                              int blk, int nblk)
+{
+    __shared__ TileSharedIB S;
+    const int tid = threadIdx.x;
+    const int nact = min(P.act_count[2 * I.inst + parity], I.act_cap);
+    for (int a = blk; a < nact; a += nblk) {
+        const int t = P.act_list[parity][I.act_off + a].y;
+        const int gt = I.tile_off + t;
+        const int tx = t % I.tiles_x, ty = t / I.tiles_x;
+        const int* list = P.tile_list + I.list_off + (long long)t * I.tile_cap;
+        if (tid == 0) S.cnt = min(P.tile_count[gt], min(I.tile_cap, kTileCapIB));
+        __syncthreads();
+        const int c = S.cnt;
+        for (int q = tid; q < c; q += blockDim.x) S.raw[q] = list[q];
+        __syncthreads();
+        if (tid == 0) {
+            P.tile_count[gt] = 0;  // ready for the next step
+            P.tile_slot[parity][gt] = I.act_off + a;
+        }
+        for (int q = tid; q < c; q += blockDim.x) {
+            const int k = S.raw[q];
+            int r = 0;
+            for (int m = 0; m < c; m++) r += (S.raw[m] < k) ? 1 : 0;
+            const int mk = I.mk_off + k;
+            S.f0[r] = P.f0[mk];
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                S.wx[r][j] = (float)P.wx[4 * mk + j];
+                S.wy[r][j] = (float)P.wy[4 * mk + j];
+            }
+            const double2 G = P.G[mk];
+            S.gx[r] = G.x;
+            S.gy[r] = G.y;
+        }
+        __syncthreads();
+        const int x = tx * kTile + (tid & (kTile - 1)), y = ty * kTile + tid / kTile;
+        const bool valid = x < I.nx && y < I.ny;
+        double gx = 0.0, gy = 0.0;
+        if (valid) {
+            // g(x) = sum_k G_k delta_h(x - X_k) dX (Sec. 2.2.2)
+            for (int j = 0; j < c; j++) {
+                const int2 f = S.f0[j];
+                const int ix = x - f.x, iy = y - f.y;
+                const bool in = (unsigned)ix <= 3u && (unsigned)iy <= 3u;
+                const double wgt = in ? (double)S.wx[j][ix & 3] * (double)S.wy[j][iy & 3] : 0.0;
+                gx += S.gx[j] * wgt * I.dX;
+                gy += S.gy[j] * wgt * I.dX;
+            }
+        }
+        // the simple force term of g, or (Guo's term) g itself for the sweep
+        float* cr = P.corr[parity] + (long long)(I.act_off + a) * kCorrPlanes * kTileNodes + tid;
+        const double fs = I.guo ? 0.0 : 3.0;
+#pragma unroll
+        for (int i = 1; i < 9; i++)
+            cr[(i - 1) * kTileNodes] =
+                valid ? (float)(fs * WD[i] * ((double)EX[i] * gx + (double)EY[i] * gy)) : 0.f;
+        if (I.guo) {
+            cr[8 * kTileNodes] = valid ? (float)gx : 0.f;
+            cr[9 * kTileNodes] = valid ? (float)gy : 0.f;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_tiles_ib(InstDev I, DevPtrs P, int parity)
+{
+    tiles_ib_body(I, P, parity, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(256) void k_tiles_ib_batch(const InstDev* __restrict__ insts,
+                                                        const int2* __restrict__ units, DevPtrs P,
+                                                        int parity)
+{
+    const int2 u = units[blockIdx.x];
+    const InstDev I = insts[u.x];
+    tiles_ib_body(I, P, parity, u.y, I.tile_blocks);
+}
+
 template <int IFACE, bool REC>
 __global__ __launch_bounds__(256) void k_tiles(InstDev I, DevPtrs P, int parity)
 {
@@ -686,6 +808,10 @@ static hipError_t tiles_i(const InstDev& I, const DevPtrs& P, int parity, bool r
 
 hipError_t launch_tiles(const InstDev& I, const DevPtrs& P, int parity, bool records, hipStream_t s)
 {
+    if (!I.jumps) {
+        hipLaunchKernelGGL(k_tiles_ib, dim3(I.tile_blocks), dim3(256), 0, s, I, P, parity);
+        return hipGetLastError();
+    }
     return I.iface == II_LBM_IF_MEMBRANE ? tiles_i<II_LBM_IF_MEMBRANE>(I, P, parity, records, s)
                                          : tiles_i<II_LBM_IF_RIGID>(I, P, parity, records, s);
 }
@@ -708,6 +834,11 @@ hipError_t launch_tiles_batch(const Batch& b, const DevPtrs& P, int parity, bool
                               hipStream_t s)
 {
     if (b.tile_units == 0) return hipSuccess;
+    if (!b.jumps) {
+        hipLaunchKernelGGL(k_tiles_ib_batch, dim3(b.tile_units), dim3(256), 0, s, b.insts,
+                           b.tile_table, P, parity);
+        return hipGetLastError();
+    }
     return b.iface == II_LBM_IF_MEMBRANE
                ? tiles_batch_i<II_LBM_IF_MEMBRANE>(b, P, parity, records, s)
                : tiles_batch_i<II_LBM_IF_RIGID>(b, P, parity, records, s);

@@ -51,7 +51,7 @@ int validate(const ii_lbm_problem& p, const double* X0)
         return II_LBM_EINVAL;
     if (p.storage != II_LBM_FP32 && p.storage != II_LBM_FP16) return II_LBM_EINVAL;
     if (p.math != II_LBM_MATH_FP32 && p.math != II_LBM_MATH_FP64) return II_LBM_EINVAL;
-    if (p.force_mode != II_LBM_FORCE_II) return II_LBM_EINVAL;
+    if (p.force_mode < II_LBM_FORCE_II || p.force_mode > II_LBM_FORCE_II_GUO) return II_LBM_EINVAL;
     if (p.interface_kind == II_LBM_IF_NONE) return II_LBM_OK;
     if (p.interface_kind != II_LBM_IF_MEMBRANE && p.interface_kind != II_LBM_IF_RIGID)
         return II_LBM_EINVAL;
@@ -68,7 +68,7 @@ int validate(const ii_lbm_problem& p, const double* X0)
         const int kp = (k + 1) % N;
         area += X0[2 * k] * X0[2 * kp + 1] - X0[2 * kp] * X0[2 * k + 1];
         const double l = hypot(X0[2 * kp] - x, X0[2 * kp + 1] - y);
-        if (l > 2.0 || l == 0.0) return II_LBM_EGEOMETRY;
+        if (l > 4.0 || l == 0.0) return II_LBM_EGEOMETRY;
     }
     if (!(area > 0.0)) return II_LBM_EGEOMETRY;  // must be counter-clockwise
     return II_LBM_OK;
@@ -100,6 +100,7 @@ int build_layout(const ii_lbm_problem* p, int n_inst, Layout& L)
     L.inst.resize(n_inst);
     size_t lat = 0;
     int mk = 0, tiles = 0, act = 0, rec = 0;
+    long long list = 0;
     for (int j = 0; j < n_inst; j++) {
         const ii_lbm_problem& q = p[j];
         InstDev I;
@@ -118,6 +119,8 @@ int build_layout(const ii_lbm_problem* p, int n_inst, Layout& L)
         I.storage = q.storage;
         I.math = q.math;
         I.iface = q.interface_kind;
+        I.jumps = q.force_mode == II_LBM_FORCE_II || q.force_mode == II_LBM_FORCE_II_GUO;
+        I.guo = q.force_mode == II_LBM_FORCE_IB_GUO || q.force_mode == II_LBM_FORCE_II_GUO;
         I.n_markers = q.interface_kind == II_LBM_IF_NONE ? 0 : q.n_markers;
         I.inst = j;
         I.plane = (long long)I.pitch * q.ny;
@@ -147,13 +150,17 @@ int build_layout(const ii_lbm_problem* p, int n_inst, Layout& L)
         I.tiles_y = (q.ny + kTile - 1) / kTile;
         I.tile_off = tiles;
         tiles += I.tiles_x * I.tiles_y;
+        I.tile_cap = I.jumps ? kTileCap : kTileCapIB;
+        I.list_off = list;
+        list += (long long)I.tiles_x * I.tiles_y * I.tile_cap;
         I.act_off = act;
         // tiles within 2.5 lu of a closed curve of N chords; the bound leaves
-        // room for chords of up to 2 lu (longer curves report ECAPACITY)
-        I.act_cap = std::min(I.tiles_x * I.tiles_y, I.n_markers / 2 + 256);
+        // room for chords of up to 4 lu (longer curves report ECAPACITY), and
+        // the record buffer for the links such chords cut
+        I.act_cap = std::min(I.tiles_x * I.tiles_y, I.n_markers + 256);
         act += I.act_cap;
         I.rec_off = rec;
-        I.rec_cap = 16 * I.n_markers + 1024;
+        I.rec_cap = 32 * I.n_markers + 1024;
         rec += I.rec_cap;
         I.mk_blocks = (16 * I.n_markers + 255) / 256;
         I.tile_blocks = std::max(1, std::min(I.act_cap, 2048));
@@ -186,10 +193,10 @@ int build_layout(const ii_lbm_problem* p, int n_inst, Layout& L)
     L.off_wy = take(4 * nm * sizeof(double));
     L.off_f0 = take(nm * sizeof(int2));
     L.off_tile_count = take((size_t)tiles * sizeof(int));
-    L.off_tile_list = take((size_t)tiles * kTileCap * sizeof(int));
+    L.off_tile_list = take((size_t)std::max(list, 1LL) * sizeof(int));
     for (int q = 0; q < 2; q++) {
         L.off_tile_slot[q] = take((size_t)tiles * sizeof(int));
-        L.off_corr[q] = take((size_t)std::max(act, 1) * 8 * kTileNodes * sizeof(float));
+        L.off_corr[q] = take((size_t)std::max(act, 1) * kCorrPlanes * kTileNodes * sizeof(float));
     }
     L.off_act_list[0] = take((size_t)std::max(act, 1) * sizeof(int2));
     L.off_act_list[1] = take((size_t)std::max(act, 1) * sizeof(int2));
@@ -679,11 +686,13 @@ int ii_lbm_init(const ii_lbm_problem* p, int32_t n_inst, const double* const* X0
                                hipMemcpyHostToDevice, h->stream);
     }
     // Several instances advance together through the batched launches; they
-    // share storage precision, collision arithmetic and interface kind.
+    // share storage precision, collision arithmetic, force mode and interface
+    // kind.
     if (e == hipSuccess && n_inst > 1) {
         int iface = II_LBM_IF_NONE;
         for (int j = 0; j < n_inst; j++) {
-            if (p[j].storage != p[0].storage || p[j].math != p[0].math) {
+            if (p[j].storage != p[0].storage || p[j].math != p[0].math ||
+                p[j].force_mode != p[0].force_mode) {
                 e = hipErrorInvalidValue;
                 break;
             }
@@ -709,6 +718,8 @@ int ii_lbm_init(const ii_lbm_problem* p, int32_t n_inst, const double* const* X0
         b.storage = p[0].storage;
         b.math = p[0].math;
         b.iface = iface;
+        b.guo = h->L.inst[0].guo;
+        b.jumps = h->L.inst[0].jumps;
         std::vector<int2> mk, tl;
         for (int j = 0; j < n_inst; j++) {
             InstDev& I = h->L.inst[j];

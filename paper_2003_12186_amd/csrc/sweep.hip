@@ -11,7 +11,10 @@ namespace iilbm {
 // interface corrections (tangential force term and jumps of the links this
 // node sends, prepared per 16x16 tile by the interface kernel) and store the
 // result at (x, y): every stored value is rounded exactly once.
-template <typename T, typename M, int COLL, bool BOUNDED>
+// GUO: Guo's force term of the whole Eulerian force (the body force plus the
+// spread force the tile's slot holds in its last two planes); the slot's
+// population planes then hold the jumps alone.
+template <typename T, typename M, int COLL, bool BOUNDED, bool GUO>
 __device__ __forceinline__ void sweep_node(const InstDev& I, const T* __restrict__ A,
                                            T* __restrict__ B, int x, int y,
                                            const int* __restrict__ tile_slot,
@@ -22,6 +25,30 @@ __device__ __forceinline__ void sweep_node(const InstDev& I, const T* __restrict
         nee<T, M>(I, A, x, y, d);
     else
         pull<T, M>(I, A, x, y, d);
+    if constexpr (GUO) {
+        const float* c = nullptr;
+        M gx = (M)I.body[0], gy = (M)I.body[1];
+        if (I.n_markers > 0) {
+            const int slot = tile_slot[I.tile_off + (y / kTile) * I.tiles_x + (x / kTile)];
+            if (slot >= 0) {
+                c = corr + (long long)slot * kCorrPlanes * kTileNodes + (y % kTile) * kTile + (x % kTile);
+                gx += (M)c[8 * kTileNodes];
+                gy += (M)c[9 * kTileNodes];
+            }
+        }
+        if (COLL == II_LBM_SRT)
+            collide_guo_srt<M>(d, sizeof(M) == 8 ? (M)I.omega_d : (M)I.omega, gx, gy);
+        else
+            collide_guo_mrt<M>(d, I.s, gx, gy);
+        if (c) {
+#pragma unroll
+            for (int i = 1; i < 9; i++) d[i] += (M)c[(i - 1) * kTileNodes];
+        }
+        T* base = B + I.lat_off + (long long)y * I.pitch + x;
+#pragma unroll
+        for (int i = 0; i < 9; i++) Store<T>::st_stream(base + i * I.plane, (float)d[i], I.inv_scale);
+        return;
+    }
     if (COLL == II_LBM_SRT)
         collide_srt<M>(d, sizeof(M) == 8 ? (M)I.omega_d : (M)I.omega, (M)I.body[0], (M)I.body[1]);
     else
@@ -29,7 +56,7 @@ __device__ __forceinline__ void sweep_node(const InstDev& I, const T* __restrict
     if (I.n_markers > 0) {
         const int slot = tile_slot[I.tile_off + (y / kTile) * I.tiles_x + (x / kTile)];
         if (slot >= 0) {
-            const float* c = corr + (long long)slot * 8 * kTileNodes + (y % kTile) * kTile + (x % kTile);
+            const float* c = corr + (long long)slot * kCorrPlanes * kTileNodes + (y % kTile) * kTile + (x % kTile);
 #pragma unroll
             for (int i = 1; i < 9; i++) d[i] += (M)c[(i - 1) * kTileNodes];
         }
@@ -39,7 +66,7 @@ __device__ __forceinline__ void sweep_node(const InstDev& I, const T* __restrict
     for (int i = 0; i < 9; i++) Store<T>::st_stream(base + i * I.plane, (float)d[i], I.inv_scale);
 }
 
-template <typename T, typename M, int COLL, bool BOUNDED, int BX>
+template <typename T, typename M, int COLL, bool BOUNDED, int BX, bool GUO>
 __global__ __launch_bounds__(BX) void k_sweep(InstDev I, const T* __restrict__ A,
                                               T* __restrict__ B, int bx_count,
                                               const int* __restrict__ tile_slot,
@@ -51,12 +78,12 @@ __global__ __launch_bounds__(BX) void k_sweep(InstDev I, const T* __restrict__ A
     const int bx = blockIdx.x % bx_count, y = blockIdx.x / bx_count;
     const int x = bx * BX + threadIdx.x;
     if (x >= I.nx) return;
-    sweep_node<T, M, COLL, BOUNDED>(I, A, B, x, y, tile_slot, corr);
+    sweep_node<T, M, COLL, BOUNDED, GUO>(I, A, B, x, y, tile_slot, corr);
 }
 
 // Batched: block b sweeps `UNIT` consecutive nodes (row-major) of one
 // instance, from the work table; collision and boundary kind per instance.
-template <typename T, typename M, int UNIT>
+template <typename T, typename M, int UNIT, bool GUO>
 __global__ __launch_bounds__(UNIT) void k_sweep_batch(const InstDev* __restrict__ insts,
                                                       const int2* __restrict__ units,
                                                       const T* __restrict__ A, T* __restrict__ B,
@@ -72,36 +99,44 @@ __global__ __launch_bounds__(UNIT) void k_sweep_batch(const InstDev* __restrict_
     const int y = r / I.nx, x = r - y * I.nx;
     if (I.collision == II_LBM_SRT) {
         if (I.bounded)
-            sweep_node<T, M, II_LBM_SRT, true>(I, A, B, x, y, tile_slot, corr);
+            sweep_node<T, M, II_LBM_SRT, true, GUO>(I, A, B, x, y, tile_slot, corr);
         else
-            sweep_node<T, M, II_LBM_SRT, false>(I, A, B, x, y, tile_slot, corr);
+            sweep_node<T, M, II_LBM_SRT, false, GUO>(I, A, B, x, y, tile_slot, corr);
     } else {
         if (I.bounded)
-            sweep_node<T, M, II_LBM_MRT, true>(I, A, B, x, y, tile_slot, corr);
+            sweep_node<T, M, II_LBM_MRT, true, GUO>(I, A, B, x, y, tile_slot, corr);
         else
-            sweep_node<T, M, II_LBM_MRT, false>(I, A, B, x, y, tile_slot, corr);
+            sweep_node<T, M, II_LBM_MRT, false, GUO>(I, A, B, x, y, tile_slot, corr);
     }
+}
+
+template <typename T, typename M, bool GUO>
+static hipError_t sweep_batch_g(const Batch& b, const DevPtrs& P, const void* A, void* B, int par,
+                                hipStream_t s)
+{
+    const dim3 g(b.sweep_units);
+    switch (b.sweep_unit) {
+    case 128:
+        hipLaunchKernelGGL((k_sweep_batch<T, M, 128, GUO>), g, dim3(128), 0, s, b.insts,
+                           b.sweep_table, (const T*)A, (T*)B, P.tile_slot[par], P.corr[par]);
+        break;
+    case 512:
+        hipLaunchKernelGGL((k_sweep_batch<T, M, 512, GUO>), g, dim3(512), 0, s, b.insts,
+                           b.sweep_table, (const T*)A, (T*)B, P.tile_slot[par], P.corr[par]);
+        break;
+    default:
+        hipLaunchKernelGGL((k_sweep_batch<T, M, 256, GUO>), g, dim3(256), 0, s, b.insts,
+                           b.sweep_table, (const T*)A, (T*)B, P.tile_slot[par], P.corr[par]);
+    }
+    return hipGetLastError();
 }
 
 template <typename T, typename M>
 static hipError_t sweep_batch_m(const Batch& b, const DevPtrs& P, const void* A, void* B, int par,
                                 hipStream_t s)
 {
-    const dim3 g(b.sweep_units);
-    switch (b.sweep_unit) {
-    case 128:
-        hipLaunchKernelGGL((k_sweep_batch<T, M, 128>), g, dim3(128), 0, s, b.insts, b.sweep_table,
-                           (const T*)A, (T*)B, P.tile_slot[par], P.corr[par]);
-        break;
-    case 512:
-        hipLaunchKernelGGL((k_sweep_batch<T, M, 512>), g, dim3(512), 0, s, b.insts, b.sweep_table,
-                           (const T*)A, (T*)B, P.tile_slot[par], P.corr[par]);
-        break;
-    default:
-        hipLaunchKernelGGL((k_sweep_batch<T, M, 256>), g, dim3(256), 0, s, b.insts, b.sweep_table,
-                           (const T*)A, (T*)B, P.tile_slot[par], P.corr[par]);
-    }
-    return hipGetLastError();
+    return b.guo ? sweep_batch_g<T, M, true>(b, P, A, B, par, s)
+                 : sweep_batch_g<T, M, false>(b, P, A, B, par, s);
 }
 
 hipError_t launch_sweep_batch(const Batch& b, const DevPtrs& P, const void* A, void* B, int par,
@@ -120,8 +155,12 @@ static hipError_t sweep_b(const InstDev& I, const DevPtrs& P, const void* A, voi
                           int par, hipStream_t s)
 {
     const int bxn = (I.nx + BX - 1) / BX;
-    hipLaunchKernelGGL((k_sweep<T, M, COLL, BOUNDED, BX>), dim3(bxn * I.ny), dim3(BX), 0, s, I,
-                       (const T*)A, (T*)B, bxn, P.tile_slot[par], P.corr[par]);
+    if (I.guo)
+        hipLaunchKernelGGL((k_sweep<T, M, COLL, BOUNDED, BX, true>), dim3(bxn * I.ny), dim3(BX), 0,
+                           s, I, (const T*)A, (T*)B, bxn, P.tile_slot[par], P.corr[par]);
+    else
+        hipLaunchKernelGGL((k_sweep<T, M, COLL, BOUNDED, BX, false>), dim3(bxn * I.ny), dim3(BX),
+                           0, s, I, (const T*)A, (T*)B, bxn, P.tile_slot[par], P.corr[par]);
     return hipGetLastError();
 }
 

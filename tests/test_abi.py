@@ -74,8 +74,11 @@ def test_workspace_size_scales_with_lattice():
     (lambda p, X: setattr(p, "dX", 3.0), B.EINVAL),
     (lambda p, X: setattr(p, "n_markers", 2), B.EINVAL),
     (lambda p, X: setattr(p, "storage", 5), B.EINVAL),
+    (lambda p, X: setattr(p, "force_mode", 4), B.EINVAL),
+    (lambda p, X: setattr(p, "force_mode", -1), B.EINVAL),
     (lambda p, X: X.__setitem__(slice(None), X[::-1].copy()), B.EGEOMETRY),  # clockwise
     (lambda p, X: X.__setitem__((0, 0), 61.5), B.EGEOMETRY),          # near the edge / long chord
+    (lambda p, X: X.__setitem__((0, 0), X[0, 0] + 4.5), B.EGEOMETRY),  # chords over 4 lu
     (lambda p, X: X.__setitem__((5, 1), np.nan), B.EINVAL),
 ])
 def test_init_validation_rejects_before_device_access(mutate, code):
