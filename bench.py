@@ -11,6 +11,9 @@ Prints one JSON line: MLUPS (whole job), the roofline of the dominant kernel
 and the FP64 CPU oracle timed on a bounded sample of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--storage fp32|fp16] [--no-cpu]
+
+Other workloads (--workload): batch512, learned, cylinder, and area (the
+elastic-membrane area comparison of Sec. 4.2 under the four force modes).
 """
 from __future__ import annotations
 
@@ -311,6 +314,123 @@ def bench_cylinder(args, B, W) -> int:
     return 0
 
 
+# Sec. 4.2, Table 2: area loss per unit time L/U and total area loss at
+# t = 30 L/U of the thin elastic membrane, by lattice size L.
+PAPER_TABLE2 = {
+    "IB-LBM": {80: (2.42e-3, 7.93e-2), 160: (1.42e-3, 4.29e-2), 240: (8.82e-4, 2.87e-2)},
+    "IB-LBM (G)": {80: (3.70e-3, 1.38e-1), 160: (2.42e-3, 7.93e-2), 240: (1.78e-3, 5.51e-2)},
+    "II-LBM": {80: (7.87e-6, 2.64e-4), 160: (1.83e-6, 5.29e-5), 240: (6.28e-7, 2.35e-5)},
+}
+
+
+def bench_area(args, B, W) -> int:
+    """The area comparison of Sec. 4.2 (Table 2): the elastic membrane under
+    IB-LBM with the simple and with Guo's force term and under II-LBM (also
+    with Guo's term), L = 80, 160, 240, to t = 30 L/U, the enclosed area read
+    after every L/U (HIP graphs between the reads).  Reports the loss rate
+    (least-squares slope of the area loss over t = 1..30 L/U, and the total
+    over 30) and the throughput of every run.  Then the sweep with Guo's term
+    against the plain one on the 4096^2 membrane, HIP-event timed."""
+    import numpy as np
+    import torch
+    names = {W.FORCE_IB_LBM: "IB-LBM", W.FORCE_IB_LBM_GUO: "IB-LBM (G)",
+             W.FORCE_II_LBM: "II-LBM", W.FORCE_II_LBM_GUO: "II-LBM (G)"}
+    math_ = W.MATH_FP64 if args.math == "fp64" else W.MATH_FP32
+    rows, lu_all, t_all = [], 0, 0.0
+    for L in [int(v) for v in args.area_sizes.split(",") if v.strip()]:
+        for mode, name in names.items():
+            w = W.elastic_membrane_e2(L, mode)
+            p = w.problem
+            p.math = math_
+            sim = B.Sim([p], [w.X0], device="cuda:0")
+            sim.set_graph(args.graph == "on")
+            A0 = sim.diag()["area"]
+            span = w.meta["span"]
+            loss, failed = [], None
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(30):
+                sim.step(span)
+                try:
+                    d = sim.diag()
+                except B.IILBMError as err:
+                    # a run that leaves the supported region (the simple-term
+                    # IB-LBM membrane drifts outward and buckles) ends here
+                    failed = {"at_L_over_U": k + 1, "error": str(err)}
+                    break
+                loss.append((A0 - d["area"]) / A0)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            n_ok = len(loss)
+            steps = (n_ok + (1 if failed else 0)) * span
+            lu = p.nx * p.ny * steps
+            lu_all += lu
+            t_all += dt
+            t = np.arange(1, n_ok + 1, dtype=float)
+            slope = float(np.polyfit(t, np.array(loss), 1)[0]) if n_ok >= 2 else None
+            row = {"L": L, "method": name, "markers": p.n_markers, "steps": steps,
+                   "loss_rate": slope, "loss_total": loss[-1] if loss else None,
+                   "loss_mean_rate": loss[-1] / n_ok if loss else None,
+                   "loss_history": [round(v, 8) for v in loss[::5]],
+                   "semi_axis_x": None, "mlups": round(lu / dt / 1e6, 1),
+                   "us_per_step": round(dt * 1e6 / steps, 2), "failed": failed}
+            if not failed:
+                X = sim.markers()[0]
+                row["semi_axis_x"] = float(X[:, 0].max() - L / 2.0)
+            if name in PAPER_TABLE2:
+                row["paper"] = list(PAPER_TABLE2[name][L]) if L in PAPER_TABLE2[name] else None
+            rows.append(row)
+            print(f"[area] L={L} {name}: rate {slope} total {row['loss_total']} failed {failed} "
+                  f"({row['mlups']} MLUPS, {dt:.1f} s)", file=sys.stderr, flush=True)
+            sim.close()
+
+    # the sweep with Guo's term on the HBM-bound 4096^2 membrane, beside the plain one
+    sweeps = {}
+    for mode in (W.FORCE_II_LBM, W.FORCE_II_LBM_GUO, W.FORCE_IB_LBM_GUO):
+        wm = W.membrane_c3(L=4096)
+        wm.problem.math = math_
+        wm.problem.force_mode = mode
+        if mode == W.FORCE_IB_LBM_GUO:
+            wm = W.membrane_c3(L=4096, n_markers=4096 * 6)   # 1/3 lu spacing
+            wm.problem.math = math_
+            wm.problem.force_mode = mode
+        sim = B.Sim([wm.problem], [wm.X0], device="cuda:0")
+        sim.step(20)
+        sim.sync()
+        sim.set_timing(True)
+        sim.step(200)
+        sim.sync()
+        ms, launches = sim.get_timing()
+        sim.set_timing(False)
+        avg = ms / 1e3 / max(launches, 1)
+        sweeps[names[mode]] = {"avg_launch_us": round(avg * 1e6, 2),
+                               "achieved_gbs": round(sim.sweep_bytes() / avg / 1e9, 1),
+                               "frac": round(sim.sweep_bytes() / avg / 1e9 / HBM_PEAK_GBS, 4),
+                               "bytes_per_launch": sim.sweep_bytes()}
+        sim.close()
+    g = sweeps["II-LBM (G)"]
+    n_steps = sum(r["steps"] for r in rows)
+    out = {
+        "metric": "MLUPS & %HBM peak; learned 2x-coarse vs fine II-LBM time at <=1e-2 L2 err",
+        "value": round(lu_all / t_all / 1e6, 1) if rows else None, "unit": "MLUPS", "n_gpus": 1,
+        "steps": n_steps, "warmup": 0,
+        "ms_per_step": round(t_all * 1e3 / n_steps, 5) if rows else None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 storage / " + args.math + " collision", "data": "synthetic",
+        "config": {"workload": "elastic_membrane_area_table2", "sizes": args.area_sizes,
+                   "t_end_L_over_U": 30, "rows": rows, "sweeps_4096": sweeps},
+        "roofline": {"bound": "hbm", "kernel": "k_sweep<GUO> (II-LBM with Guo's term, 4096^2)",
+                     "achieved": g["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": g["frac"], "traffic": None, "bytes_per_launch": g["bytes_per_launch"],
+                     "avg_launch_us": g["avg_launch_us"]},
+    }
+    if not args.no_cpu:
+        w = W.elastic_membrane_e2(80, W.FORCE_IB_LBM_GUO)
+        out["cpu_baseline"] = cpu_baseline(w, 250 * args.cpu_steps)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def set_overlap(sim, B, args) -> None:
     modes = {"serial": B.OVERLAP_SERIAL, "full": B.OVERLAP_FULL,
              "interp_first": B.OVERLAP_INTERP_FIRST}
@@ -392,13 +512,15 @@ def main() -> int:
                          "for FP32 storage (its 1e-6 parity bar) and FP32 for FP16 storage "
                          "(1e-3 bar)")
     ap.add_argument("--size", type=int, default=4096)
-    ap.add_argument("--workload", choices=["membrane", "batch512", "learned", "cylinder"],
+    ap.add_argument("--workload", choices=["membrane", "batch512", "learned", "cylinder", "area"],
                     default="membrane",
                     help="membrane: one L x L membrane (the bench line); batch512: 512 uneven "
                          "membrane instances advanced together; learned: 200 coarse membranes "
                          "with the learned correction every step against their fine runs (both "
                          "reported in the design notes)")
     ap.add_argument("--re", type=float, default=100.0, help="Reynolds number of the cylinder workload")
+    ap.add_argument("--area-sizes", default="80,160,240",
+                    help="lattice sizes L of the area workload (the elastic membrane of Sec. 4.2)")
     ap.add_argument("--instances", type=int, default=None,
                     help="instances of the batch512 (default 512) or learned (200) workload")
     ap.add_argument("--graph", choices=["on", "off"], default="on",
@@ -439,6 +561,8 @@ def main() -> int:
         return bench_learned(args, B, W)
     if args.workload == "cylinder":
         return bench_cylinder(args, B, W)
+    if args.workload == "area":
+        return bench_area(args, B, W)
     storage = W.STORE_FP16 if args.storage == "fp16" else W.STORE_FP32
     w = W.membrane_c3(L=args.size, storage=storage)
     p = w.problem

@@ -205,6 +205,26 @@ def cylinder_c2(re: float = 20.0, small: bool = False, storage: int = STORE_FP32
     return Workload(p, X0, 20000, {"D": D, "re": re, "u_mean": u_mean})
 
 
+def elastic_membrane_e2(L: int, force_mode: int = FORCE_II_LBM, storage: int = STORE_FP32) -> Workload:
+    """Thin elastic membrane of Sec. 4.2: ellipse a = 0.35 L, b = 0.25^2/0.35 L
+    centred in a walled L x L box, MRT, kappa_bar = kappa/(U^2 L) = 0.1,
+    nu = 0.02, Re = 100, U = nu Re / L; markers at most 2 lu apart (II-LBM) or
+    1/3 lu apart (IB-LBM) on the equilibrium circle of radius L/4.  Runs to
+    30 L/U."""
+    nu, re, kbar = 0.02, 100.0, 0.1
+    U = nu * re / L
+    R = 0.25 * L
+    spacing = 2.0 if force_mode in (FORCE_II_LBM, FORCE_II_LBM_GUO) else 1.0 / 3.0
+    n = int(math.ceil(2.0 * math.pi * R / spacing - 1e-9))   # spacing at most the paper's
+    X0 = ellipse_markers(L / 2.0, L / 2.0, 0.35 * L, 0.25 ** 2 / 0.35 * L, n)
+    p = Problem(nx=L, ny=L, tau=0.5 + 3.0 * nu, collision=MRT, bc=(BC_WALL,) * 4,
+                interface=IF_MEMBRANE, force_mode=force_mode, n_markers=n,
+                kappa=kbar * U * U * L, dX=2.0 * math.pi * R / n, storage=storage,
+                name=f"elastic{L}_mode{force_mode}")
+    span = int(round(L / U))
+    return Workload(p, X0, 30 * span, {"U": U, "span": span, "R": R})
+
+
 def membrane_c3(L: int = 4096, seed: int = 0, storage: int = STORE_FP32,
                 n_markers: Optional[int] = None) -> Workload:
     rng = SplitMix64(3, seed)

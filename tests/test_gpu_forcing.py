@@ -7,7 +7,6 @@ membrane of Sec. 4.2 and a batch.
 Tolerances as for II-LBM: FP32 storage with FP64 collision arithmetic,
 relative L2 velocity <= 1e-6 after 1000 steps, markers within 1e-6 lu.
 """
-import math
 import sys
 
 import numpy as np
@@ -121,29 +120,15 @@ def test_cylinder_small_force_modes(B, mode):
     sim.close()
 
 
-def _e2(L, mode):
-    """Thin elastic membrane of Sec. 4.2 (ellipse a = 0.35 L, b = 0.25^2/0.35 L,
-    walled box, kappa_bar = 0.1, nu = 0.02, Re = 100, marker spacing 2 lu
-    (II-LBM) or 1/3 lu (IB-LBM) on the equilibrium circle)."""
-    nu, U = 0.02, 0.02 * 100.0 / L
-    R = 0.25 * L
-    dX = 2.0 if mode in (W.FORCE_II_LBM, W.FORCE_II_LBM_GUO) else 1.0 / 3.0
-    n = int(round(2 * math.pi * R / dX))
-    X0 = W.ellipse_markers(L / 2, L / 2, 0.35 * L, 0.25 ** 2 / 0.35 * L, n)
-    prob = W.Problem(nx=L, ny=L, tau=0.5 + 3 * nu, collision=W.MRT, bc=(W.BC_WALL,) * 4,
-                     interface=W.IF_MEMBRANE, force_mode=mode, n_markers=n,
-                     kappa=0.1 * U * U * L, dX=2 * math.pi * R / n, math=W.MATH_FP64)
-    return prob, X0, U
-
-
 @pytest.mark.parametrize("mode", [W.FORCE_II_LBM, W.FORCE_IB_LBM, W.FORCE_IB_LBM_GUO,
                                   W.FORCE_II_LBM_GUO])
 def test_elastic_membrane_area_history(B, mode):
     # The area comparison of Sec. 4.2 at L = 48 over 3 L/U (3456 steps): the
     # enclosed area after every L/U and the final markers against the oracle.
     L = 48
-    prob, X0, U = _e2(L, mode)
-    span = int(round(L / U))
+    w = W.elastic_membrane_e2(L, mode)
+    prob, X0, span = w.problem, w.X0, w.meta["span"]
+    prob.math = W.MATH_FP64
     _say(f"elastic membrane L={L} force_mode={mode} markers={prob.n_markers}, 3 x {span} steps")
     sim = B.Sim([prob], [X0])
     p = O.make_problem(prob)

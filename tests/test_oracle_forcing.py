@@ -223,24 +223,15 @@ def test_laplace_fixed_point_ii_lbm_with_guo_term(collision):
 
 
 def _e2_area_history(L, mode, spans):
-    """Thin elastic membrane of Sec. 4.2: ellipse a = 0.35 L, b = 0.25^2/0.35 L
-    in a walled L x L box, kappa_bar = 0.1, nu = 0.02, Re = 100, U = nu Re / L;
-    marker spacing 2 lu (II-LBM) or 1/3 lu (IB-LBM) on the equilibrium circle
-    of radius L/4.  Returns the enclosed area after each span (in L/U)."""
-    nu, re, kbar = 0.02, 100.0, 0.1
-    U = nu * re / L
-    R = 0.25 * L
-    dX = 2.0 if mode in (W.FORCE_II_LBM, W.FORCE_II_LBM_GUO) else 1.0 / 3.0
-    n = int(round(2 * math.pi * R / dX))
-    X = W.ellipse_markers(L / 2, L / 2, 0.35 * L, 0.25 ** 2 / 0.35 * L, n)
-    p = O.make_problem(W.Problem(nx=L, ny=L, tau=0.5 + 3 * nu, collision=W.MRT,
-                                 bc=(W.BC_WALL,) * 4, interface=W.IF_MEMBRANE,
-                                 force_mode=mode, n_markers=n, kappa=kbar * U * U * L,
-                                 dX=2 * math.pi * R / n))
+    """The thin elastic membrane of Sec. 4.2 in the oracle; the enclosed area
+    at the start and after each span (in L/U)."""
+    w = W.elastic_membrane_e2(L, mode)
+    p = O.make_problem(w.problem)
     f = O.rest_state(p)
+    X = w.X0.copy()
     areas = [O.polygon_area(X)]
     for span in spans:
-        O.run(p, f, X, int(round(span * L / U)))
+        O.run(p, f, X, int(round(span * w.meta["span"])))
         areas.append(O.polygon_area(X))
     return np.array(areas)
 
