@@ -421,7 +421,8 @@ def bench_area(args, B, W) -> int:
                    "t_end_L_over_U": 30, "rows": rows, "sweeps_4096": sweeps},
         "roofline": {"bound": "hbm", "kernel": "k_sweep<GUO> (II-LBM with Guo's term, 4096^2)",
                      "achieved": g["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": g["frac"], "traffic": None, "bytes_per_launch": g["bytes_per_launch"],
+                     "frac": g["frac"], "traffic": measured_traffic("fp32_guo"),
+                     "bytes_per_launch": g["bytes_per_launch"],
                      "avg_launch_us": g["avg_launch_us"]},
     }
     if not args.no_cpu:
