@@ -20,7 +20,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 SRT, MRT = 0, 1
 PERIODIC, WALL, INLET, OUTLET = 0, 1, 2, 3
-IF_NONE, IF_MEMBRANE, IF_RIGID = 0, 1, 2
+IF_NONE, IF_MEMBRANE, IF_RIGID, IF_NORMAL = 0, 1, 2, 3
 II_LBM, IB_LBM, IB_LBM_GUO, II_LBM_GUO = 0, 1, 2, 3
 
 
@@ -40,7 +40,7 @@ class Problem(C.Structure):
                 ("u_max", C.c_double), ("u_wall", C.c_double * 4), ("body", C.c_double * 2),
                 ("interface", C.c_int32), ("force_mode", C.c_int32), ("n_markers", C.c_int32),
                 ("kappa", C.c_double), ("dX", C.c_double), ("cx", C.c_double),
-                ("cy", C.c_double), ("radius", C.c_double)]
+                ("cy", C.c_double), ("radius", C.c_double), ("f_normal", C.c_double)]
 
 
 class Link(C.Structure):
@@ -126,6 +126,7 @@ def make_problem(w) -> Problem:
     p.kappa, p.dX = float(w.kappa), float(w.dX)
     p.cx, p.cy = float(w.center[0]), float(w.center[1])
     p.radius = float(w.radius)
+    p.f_normal = float(getattr(w, "f_normal", 0.0))
     return p
 
 

@@ -53,7 +53,9 @@
 /* ------------------------------------------------------------------------ */
 enum { OR_SRT = 0, OR_MRT = 1 };
 enum { OR_PERIODIC = 0, OR_WALL = 1, OR_INLET = 2, OR_OUTLET = 3 };
-enum { OR_IF_NONE = 0, OR_IF_MEMBRANE = 1, OR_IF_RIGID = 2 };
+/* Interfaces: a spring membrane, a fixed circle with direct forcing, and a
+ * fixed circle with a prescribed uniform normal force (Sec. 4.1). */
+enum { OR_IF_NONE = 0, OR_IF_MEMBRANE = 1, OR_IF_RIGID = 2, OR_IF_NORMAL = 3 };
 /* Force modes: II-LBM (jumps, tangential force in the simple term, the
  * paper's method); IB-LBM (the full force spread, no jumps) with the simple
  * term or Guo's term; II-LBM with Guo's term of the tangential force
@@ -74,6 +76,7 @@ typedef struct {
     int32_t n_markers;
     double kappa, dX;
     double cx, cy, radius; /* rigid circle */
+    double f_normal;       /* prescribed force per unit length along the outward normal */
 } or_problem;
 
 static int has_jumps(const or_problem *p) { return p->force_mode == OR_II_LBM || p->force_mode == OR_II_LBM_GUO; }
@@ -357,6 +360,13 @@ void or_marker_forces(const or_problem *p, const double *X, const double *U,
             double lp = hypot(X[2 * kp] - X[2 * k], X[2 * kp + 1] - X[2 * k + 1]);
             double lm = hypot(X[2 * k] - X[2 * km], X[2 * k + 1] - X[2 * km + 1]);
             jac = (lp + lm) / (2.0 * p->dX);
+        } else if (p->interface == OR_IF_NORMAL) {
+            /* a uniform normal force G = F n on a fixed circle (Sec. 4.1) */
+            nx_ = (X[2 * k] - p->cx) / p->radius;
+            ny_ = (X[2 * k + 1] - p->cy) / p->radius;
+            gx = p->f_normal * nx_;
+            gy = p->f_normal * ny_;
+            jac = 1.0;
         } else {
             gx = 0.0 - U[2 * k];
             gy = 0.0 - U[2 * k + 1];
@@ -512,7 +522,7 @@ static int cutlinks_rigid(const or_problem *p, const double *jp, or_link *rec, i
 int or_cutlinks(const or_problem *p, const double *X, const double *jp, or_link *rec, int cap)
 {
     if (p->interface == OR_IF_MEMBRANE) return cutlinks_membrane(p, X, jp, rec, cap);
-    if (p->interface == OR_IF_RIGID) return cutlinks_rigid(p, jp, rec, cap);
+    if (p->interface == OR_IF_RIGID || p->interface == OR_IF_NORMAL) return cutlinks_rigid(p, jp, rec, cap);
     return 0;
 }
 

@@ -99,7 +99,7 @@ class SplitMix64:
 # ---------------------------------------------------------------------------
 SRT, MRT = 0, 1
 BC_PERIODIC, BC_WALL, BC_INLET, BC_OUTLET = 0, 1, 2, 3
-IF_NONE, IF_MEMBRANE, IF_RIGID = 0, 1, 2
+IF_NONE, IF_MEMBRANE, IF_RIGID, IF_NORMAL = 0, 1, 2, 3
 FORCE_II_LBM, FORCE_IB_LBM, FORCE_IB_LBM_GUO, FORCE_II_LBM_GUO = 0, 1, 2, 3
 STORE_FP32, STORE_FP16 = 0, 1
 MATH_FP32, MATH_FP64 = 0, 1
@@ -127,6 +127,7 @@ class Problem:
     dX: float = 0.0
     center: Sequence[float] = (0.0, 0.0)      # rigid circle centre
     radius: float = 0.0                       # rigid circle radius
+    f_normal: float = 0.0                     # prescribed normal force per unit length (IF_NORMAL)
     storage: int = STORE_FP32
     math: int = MATH_FP32                     # collision arithmetic
     name: str = ""
@@ -203,6 +204,23 @@ def cylinder_c2(re: float = 20.0, small: bool = False, storage: int = STORE_FP32
                 dX=math.pi * D / n, center=(cx, cy), radius=D / 2.0, storage=storage,
                 name=f"cylinder{nx}x{ny}_D{int(D)}_Re{int(re)}")
     return Workload(p, X0, 20000, {"D": D, "re": re, "u_mean": u_mean})
+
+
+def normal_force_circle_e1(D: int, force_mode: int = FORCE_II_LBM, storage: int = STORE_FP32) -> Workload:
+    """Uniform normal force along a fixed circle (Sec. 4.1): the fluid domain
+    [-D, D]^2 ((2D+1)^2 nodes) with outflow extrapolation on every side, the
+    circle of diameter D at its centre, MRT, nu = 0.05, Re = 100, U = nu Re / D,
+    a force F n per unit length with F = rho U^2, run to t = D/U.  The exact
+    velocity is zero.  Markers at most 1 lu apart."""
+    nu, re = 0.05, 100.0
+    U = nu * re / D
+    n = int(math.ceil(math.pi * D - 1e-9))
+    X0 = circle_markers(float(D), float(D), D / 2.0, n)
+    p = Problem(nx=2 * D + 1, ny=2 * D + 1, tau=0.5 + 3.0 * nu, collision=MRT,
+                bc=(BC_OUTLET,) * 4, interface=IF_NORMAL, force_mode=force_mode, n_markers=n,
+                dX=math.pi * D / n, center=(float(D), float(D)), radius=D / 2.0,
+                f_normal=U * U, storage=storage, name=f"normal{D}_mode{force_mode}")
+    return Workload(p, X0, int(round(D / U)), {"U": U, "D": D})
 
 
 def elastic_membrane_e2(L: int, force_mode: int = FORCE_II_LBM, storage: int = STORE_FP32) -> Workload:
