@@ -12,8 +12,9 @@ and the FP64 CPU oracle timed on a bounded sample of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--storage fp32|fp16] [--no-cpu]
 
-Other workloads (--workload): batch512, learned, cylinder, and area (the
-elastic-membrane area comparison of Sec. 4.2 under the four force modes).
+Other workloads (--workload): batch512, learned, cylinder, area (the
+elastic-membrane area comparison of Sec. 4.2 under the four force modes) and
+table1 (the normal-force circle of Sec. 4.1, II-LBM against IB-LBM).
 """
 from __future__ import annotations
 
@@ -432,6 +433,97 @@ def bench_area(args, B, W) -> int:
     return 0
 
 
+# Sec. 4.1, Table 1: L2 and Linf velocity errors (over U) of the direct-forcing
+# IB-LBM and the II-LBM at t = D/U, by circle diameter D.
+PAPER_TABLE1 = {20: {"IB-LBM": (1.45e-3, 6.39e-3), "II-LBM": (1.86e-6, 3.31e-6)},
+                40: {"IB-LBM": (5.30e-4, 3.23e-3), "II-LBM": (4.62e-7, 8.46e-7)},
+                80: {"IB-LBM": (1.90e-4, 1.70e-3), "II-LBM": (1.14e-7, 2.12e-7)},
+                160: {"IB-LBM": (6.77e-5, 8.34e-4), "II-LBM": (2.84e-8, 5.32e-8)}}
+
+
+def bench_table1(args, B, W) -> int:
+    """The uniform normal force along a circle (Sec. 4.1, Table 1): D = 20,
+    40, 80, 160 under II-LBM and IB-LBM to t = D/U (HIP graphs), from a fluid
+    at rest and from the exact solution (the pressure jump of the force at
+    rest), with the velocity errors over U in the paper's L2 and Linf norms
+    and their orders.  Then the sweep of the D = 160 case, HIP-event timed."""
+    import numpy as np
+    import torch
+    math_ = W.MATH_FP64 if args.math == "fp64" else W.MATH_FP32
+    names = {W.FORCE_IB_LBM: "IB-LBM", W.FORCE_II_LBM: "II-LBM"}
+    sizes = [int(v) for v in args.table1_sizes.split(",") if v.strip()]
+    rows, lu_all, t_all = [], 0, 0.0
+    for start in ("rest", "exact"):
+        for D in sizes:
+            for mode, name in names.items():
+                w = W.normal_force_circle_e1(D, mode)
+                p = w.problem
+                p.math = math_
+                sim = B.Sim([p], [w.X0], device="cuda:0")
+                sim.set_graph(args.graph == "on")
+                if start == "exact":
+                    sim.set_distrib(W.normal_force_jump_state(w))
+                sim.sync()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                sim.step(w.steps)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                ux, uy = sim.fields(B.F_UX | B.F_UY)
+                U = w.meta["U"]
+                l2 = float(np.sqrt((ux ** 2 + uy ** 2).mean()) / U)
+                linf = float(max(np.abs(ux).max(), np.abs(uy).max()) / U)
+                lu = p.nx * p.ny * w.steps
+                lu_all += lu
+                t_all += dt
+                rows.append({"start": start, "D": D, "method": name, "steps": w.steps,
+                             "markers": p.n_markers, "L2": l2, "Linf": linf,
+                             "paper": list(PAPER_TABLE1[D][name]) if D in PAPER_TABLE1 else None,
+                             "mlups": round(lu / dt / 1e6, 1)})
+                print(f"[table1] {start} D={D} {name}: L2 {l2:.3e} Linf {linf:.3e} "
+                      f"({rows[-1]['mlups']} MLUPS)", file=sys.stderr, flush=True)
+                sim.close()
+    for r in rows:
+        prev = [q for q in rows if q["start"] == r["start"] and q["method"] == r["method"]
+                and q["D"] * 2 == r["D"]]
+        if prev and prev[0]["L2"] > 0 and r["L2"] > 0:
+            r["order_L2"] = round(float(np.log2(prev[0]["L2"] / r["L2"])), 2)
+            r["order_Linf"] = round(float(np.log2(prev[0]["Linf"] / r["Linf"])), 2)
+    w = W.normal_force_circle_e1(max(sizes) if sizes else 160)
+    w.problem.math = math_
+    sim = B.Sim([w.problem], [w.X0], device="cuda:0")
+    sim.step(20)
+    sim.sync()
+    sim.set_timing(True)
+    sim.step(200)
+    sim.sync()
+    ms, launches = sim.get_timing()
+    sim.set_timing(False)
+    avg = ms / 1e3 / max(launches, 1)
+    bpl = sim.sweep_bytes()
+    sim.close()
+    n_steps = sum(r["steps"] for r in rows)
+    out = {
+        "metric": "MLUPS & %HBM peak; learned 2x-coarse vs fine II-LBM time at <=1e-2 L2 err",
+        "value": round(lu_all / t_all / 1e6, 1) if rows else None, "unit": "MLUPS", "n_gpus": 1,
+        "steps": n_steps, "warmup": 0,
+        "ms_per_step": round(t_all * 1e3 / n_steps, 5) if rows else None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 storage / " + args.math + " collision", "data": "synthetic",
+        "config": {"workload": "normal_force_circle_table1", "sizes": args.table1_sizes,
+                   "rows": rows},
+        "roofline": {"bound": "hbm", "kernel": f"k_sweep ({w.problem.nx}^2, D = {w.meta['D']})",
+                     "achieved": round(bpl / avg / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(bpl / avg / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                     "cache_resident": True, "bytes_per_launch": bpl,
+                     "avg_launch_us": round(avg * 1e6, 2), "timed_launches": launches},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(W.normal_force_circle_e1(40), 25 * args.cpu_steps)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def set_overlap(sim, B, args) -> None:
     modes = {"serial": B.OVERLAP_SERIAL, "full": B.OVERLAP_FULL,
              "interp_first": B.OVERLAP_INTERP_FIRST}
@@ -513,13 +605,16 @@ def main() -> int:
                          "for FP32 storage (its 1e-6 parity bar) and FP32 for FP16 storage "
                          "(1e-3 bar)")
     ap.add_argument("--size", type=int, default=4096)
-    ap.add_argument("--workload", choices=["membrane", "batch512", "learned", "cylinder", "area"],
+    ap.add_argument("--workload", choices=["membrane", "batch512", "learned", "cylinder", "area",
+                                           "table1"],
                     default="membrane",
                     help="membrane: one L x L membrane (the bench line); batch512: 512 uneven "
                          "membrane instances advanced together; learned: 200 coarse membranes "
                          "with the learned correction every step against their fine runs (both "
                          "reported in the design notes)")
     ap.add_argument("--re", type=float, default=100.0, help="Reynolds number of the cylinder workload")
+    ap.add_argument("--table1-sizes", default="20,40,80,160",
+                    help="circle diameters D of the table1 workload (Sec. 4.1)")
     ap.add_argument("--area-sizes", default="80,160,240",
                     help="lattice sizes L of the area workload (the elastic membrane of Sec. 4.2)")
     ap.add_argument("--instances", type=int, default=None,
@@ -564,6 +659,8 @@ def main() -> int:
         return bench_cylinder(args, B, W)
     if args.workload == "area":
         return bench_area(args, B, W)
+    if args.workload == "table1":
+        return bench_table1(args, B, W)
     storage = W.STORE_FP16 if args.storage == "fp16" else W.STORE_FP32
     w = W.membrane_c3(L=args.size, storage=storage)
     p = w.problem

@@ -54,7 +54,7 @@ extern "C" {
 /* ---- problem description ----------------------------------------------- */
 enum { II_LBM_SRT = 0, II_LBM_MRT = 1 };
 enum { II_LBM_BC_PERIODIC = 0, II_LBM_BC_WALL = 1, II_LBM_BC_INLET = 2, II_LBM_BC_OUTLET = 3 };
-enum { II_LBM_IF_NONE = 0, II_LBM_IF_MEMBRANE = 1, II_LBM_IF_RIGID = 2 };
+enum { II_LBM_IF_NONE = 0, II_LBM_IF_MEMBRANE = 1, II_LBM_IF_RIGID = 2, II_LBM_IF_NORMAL = 3 };
 /* Force modes (how the interface force enters the fluid):
  *  II      the paper's method: jumps on cut links for the normal part, the
  *          tangential part g_par in the simple force term (Sec. 3.2);
@@ -84,16 +84,21 @@ enum { II_LBM_MATH_FP32 = 0, II_LBM_MATH_FP64 = 1 };
  *               extrapolation from the inward neighbour (as cited in Sec. 4):
  *               WALL (velocity u_wall along the side), INLET (parabola
  *               4 u_max y (H - y) / H^2 with H = ny - 1; x-low only), OUTLET
- *               (zero gradient; x-high only).  Corner nodes follow the y side.
+ *               (zero gradient, the velocity of the inward neighbour; any
+ *               side).  Corner nodes follow the y side.
  *  body_force   uniform Eulerian force density added to the force term.
  *  force_mode   II_LBM_FORCE_II, _IB, _IB_GUO or _II_GUO (above).
  *  interface_kind  NONE, MEMBRANE (spring force kappa (X_{k+1} - 2 X_k +
  *               X_{k-1}) / dX^2, Sec. 2.2.2 Eq. (19)) or RIGID (fixed circle
  *               with direct forcing G = U^D - U*, eta = 1, U^D = 0, Sec. 2.2.2
- *               Eq. (18); cut links from the circle's level set, Sec. 3.2).
+ *               Eq. (18); cut links from the circle's level set, Sec. 3.2) or
+ *               NORMAL (fixed circle carrying the prescribed force G = F n per
+ *               unit length along its outward normal n, Sec. 4.1; level-set
+ *               cut links as for RIGID).
  *  n_markers    3 <= N <= 1<<20 markers.
  *  kappa, dX    spring constant and marker spacing Delta X (> 0, <= 2).
- *  center, radius  the rigid circle (RIGID only).
+ *  center, radius  the circle (RIGID and NORMAL).
+ *  f_normal     F of the NORMAL interface.
  *  storage      II_LBM_FP32 or II_LBM_FP16: distributions are stored as
  *               deviations d_i = f_i - w_i rho0 (rho0 = 1).
  *  fp16_log2_scale  FP16 storage holds d_i * 2^-fp16_log2_scale; 0 lets the
@@ -122,6 +127,7 @@ typedef struct ii_lbm_problem {
     int32_t storage;
     int32_t fp16_log2_scale;
     int32_t math;
+    double f_normal;
 } ii_lbm_problem;
 
 /* One cut link (see ii_lbm_cutlinks for which step): the link from source

@@ -30,7 +30,7 @@ class Problem(C.Structure):
                 ("interface_kind", C.c_int32), ("force_mode", C.c_int32), ("n_markers", C.c_int32),
                 ("kappa", C.c_double), ("dX", C.c_double), ("center", C.c_double * 2),
                 ("radius", C.c_double), ("storage", C.c_int32), ("fp16_log2_scale", C.c_int32),
-                ("math", C.c_int32)]
+                ("math", C.c_int32), ("f_normal", C.c_double)]
 
 
 class Link(C.Structure):
@@ -145,6 +145,7 @@ def make_problem(w) -> Problem:
     p.storage = int(w.storage)
     p.fp16_log2_scale = int(getattr(w, "fp16_log2_scale", 0))
     p.math = int(getattr(w, "math", 0))
+    p.f_normal = float(getattr(w, "f_normal", 0.0))
     return p
 
 

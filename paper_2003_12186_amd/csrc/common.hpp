@@ -71,6 +71,7 @@ struct InstDev {
     float body[2];
     float scale, inv_scale;  // FP16: value = stored * scale
     double kappa, dX, cx, cy, radius;
+    double f_normal;      // prescribed normal force per unit length (NORMAL circle)
 };
 
 // Device buffers of a handle (all carved from one workspace).

@@ -168,6 +168,13 @@ __device__ __forceinline__ void markers_body(const InstDev& I, const DevPtrs& P,
             const double lp = hypot(Xp.x - Xk.x, Xp.y - Xk.y);
             const double lm = hypot(Xk.x - Xm.x, Xk.y - Xm.y);
             jac = (lp + lm) / (2.0 * I.dX);
+        } else if (I.iface == II_LBM_IF_NORMAL) {
+            // prescribed uniform normal force F n on the fixed circle (Sec. 4.1)
+            nx_ = (Xk.x - I.cx) / I.radius;
+            ny_ = (Xk.y - I.cy) / I.radius;
+            gx = I.f_normal * nx_;
+            gy = I.f_normal * ny_;
+            jac = 1.0;
         } else {
             // direct forcing to U^D = 0 with eta = 1 (Sec. 2.2.2, Eq. (18));
             // |dX/ds| = 1 and the radial normal of the rigid circle (Sec. 3.1)

@@ -47,17 +47,19 @@ int validate(const ii_lbm_problem& p, const double* X0)
     if ((p.bc[2] == II_LBM_BC_PERIODIC) != (p.bc[3] == II_LBM_BC_PERIODIC)) return II_LBM_EINVAL;
     if (p.bc[1] == II_LBM_BC_INLET || p.bc[2] == II_LBM_BC_INLET || p.bc[3] == II_LBM_BC_INLET)
         return II_LBM_EINVAL;
-    if (p.bc[0] == II_LBM_BC_OUTLET || p.bc[2] == II_LBM_BC_OUTLET || p.bc[3] == II_LBM_BC_OUTLET)
-        return II_LBM_EINVAL;
     if (p.storage != II_LBM_FP32 && p.storage != II_LBM_FP16) return II_LBM_EINVAL;
     if (p.math != II_LBM_MATH_FP32 && p.math != II_LBM_MATH_FP64) return II_LBM_EINVAL;
     if (p.force_mode < II_LBM_FORCE_II || p.force_mode > II_LBM_FORCE_II_GUO) return II_LBM_EINVAL;
     if (p.interface_kind == II_LBM_IF_NONE) return II_LBM_OK;
-    if (p.interface_kind != II_LBM_IF_MEMBRANE && p.interface_kind != II_LBM_IF_RIGID)
+    if (p.interface_kind != II_LBM_IF_MEMBRANE && p.interface_kind != II_LBM_IF_RIGID &&
+        p.interface_kind != II_LBM_IF_NORMAL)
         return II_LBM_EINVAL;
     if (p.n_markers < 3 || p.n_markers > (1 << 20)) return II_LBM_EINVAL;
     if (!(p.dX > 0.0) || p.dX > 2.0 || !(p.kappa >= 0.0)) return II_LBM_EINVAL;
-    if (p.interface_kind == II_LBM_IF_RIGID && !(p.radius > 0.0)) return II_LBM_EINVAL;
+    if ((p.interface_kind == II_LBM_IF_RIGID || p.interface_kind == II_LBM_IF_NORMAL) &&
+        !(p.radius > 0.0))
+        return II_LBM_EINVAL;
+    if (p.interface_kind == II_LBM_IF_NORMAL && !isfinite(p.f_normal)) return II_LBM_EINVAL;
     if (!X0) return II_LBM_EINVAL;
     double area = 0.0;
     const int N = p.n_markers;
@@ -91,6 +93,7 @@ int auto_fp16_exp(const ii_lbm_problem& p, const double* X0)
             est = std::max(est, 3.0 * hypot(gx, gy));
         }
     }
+    if (p.interface_kind == II_LBM_IF_NORMAL) est = std::max(est, 3.0 * fabs(p.f_normal));
     est = std::max(est, 1e-7);
     return (int)floor(log2(est)) - 12;
 }
@@ -144,6 +147,7 @@ int build_layout(const ii_lbm_problem* p, int n_inst, Layout& L)
         I.cx = q.center[0];
         I.cy = q.center[1];
         I.radius = q.radius;
+        I.f_normal = q.f_normal;
         I.mk_off = mk;
         mk += I.n_markers;
         I.tiles_x = (q.nx + kTile - 1) / kTile;

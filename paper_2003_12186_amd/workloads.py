@@ -223,6 +223,18 @@ def normal_force_circle_e1(D: int, force_mode: int = FORCE_II_LBM, storage: int 
     return Workload(p, X0, int(round(D / U)), {"U": U, "D": D})
 
 
+def normal_force_jump_state(w: Workload) -> np.ndarray:
+    """The exact solution of the normal-force circle as an initial state: the
+    fluid at rest with the force's pressure jump, rho = 1 - 3 F inside the
+    circle's level set (p = rho / 3) and 1 outside, f_i = w_i rho."""
+    p = w.problem
+    wt = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    y, x = np.mgrid[0:p.ny, 0:p.nx]
+    inside = (x - p.center[0]) ** 2 + (y - p.center[1]) ** 2 - p.radius ** 2 < 0.0
+    rho = np.where(inside, 1.0 - 3.0 * p.f_normal, 1.0)
+    return np.ascontiguousarray(wt[:, None, None] * rho[None])
+
+
 def elastic_membrane_e2(L: int, force_mode: int = FORCE_II_LBM, storage: int = STORE_FP32) -> Workload:
     """Thin elastic membrane of Sec. 4.2: ellipse a = 0.35 L, b = 0.25^2/0.35 L
     centred in a walled L x L box, MRT, kappa_bar = kappa/(U^2 L) = 0.1,

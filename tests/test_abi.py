@@ -75,6 +75,9 @@ def test_workspace_size_scales_with_lattice():
     (lambda p, X: setattr(p, "n_markers", 2), B.EINVAL),
     (lambda p, X: setattr(p, "storage", 5), B.EINVAL),
     (lambda p, X: setattr(p, "force_mode", 4), B.EINVAL),
+    (lambda p, X: (setattr(p, "interface_kind", 3), setattr(p, "radius", 0.0)), B.EINVAL),
+    (lambda p, X: (setattr(p, "interface_kind", 3), setattr(p, "radius", 8.0),
+                   setattr(p, "f_normal", float("nan"))), B.EINVAL),
     (lambda p, X: setattr(p, "force_mode", -1), B.EINVAL),
     (lambda p, X: X.__setitem__(slice(None), X[::-1].copy()), B.EGEOMETRY),  # clockwise
     (lambda p, X: X.__setitem__((0, 0), 61.5), B.EGEOMETRY),          # near the edge / long chord
