@@ -19,7 +19,7 @@ _SRC = os.path.join(_HERE, "iilbm_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 SRT, MRT = 0, 1
-PERIODIC, WALL, INLET, OUTLET = 0, 1, 2, 3
+PERIODIC, WALL, INLET, OUTLET, INLET_UNIFORM = 0, 1, 2, 3, 4
 IF_NONE, IF_MEMBRANE, IF_RIGID, IF_NORMAL = 0, 1, 2, 3
 II_LBM, IB_LBM, IB_LBM_GUO, II_LBM_GUO = 0, 1, 2, 3
 
@@ -40,7 +40,21 @@ class Problem(C.Structure):
                 ("u_max", C.c_double), ("u_wall", C.c_double * 4), ("body", C.c_double * 2),
                 ("interface", C.c_int32), ("force_mode", C.c_int32), ("n_markers", C.c_int32),
                 ("kappa", C.c_double), ("dX", C.c_double), ("cx", C.c_double),
-                ("cy", C.c_double), ("radius", C.c_double), ("f_normal", C.c_double)]
+                ("cy", C.c_double), ("radius", C.c_double), ("f_normal", C.c_double),
+                ("ud", C.c_double * 3), ("theta", C.c_double)]
+
+
+class BodyParams(C.Structure):
+    _fields_ = [("free_dofs", C.c_int32), ("pad", C.c_int32), ("rho_star", C.c_double),
+                ("spring", C.c_double * 2), ("damping", C.c_double * 2),
+                ("presc_amp", C.c_double * 2), ("presc_umax", C.c_double * 2)]
+
+
+class Body(C.Structure):
+    _fields_ = [("c", C.c_double * 2), ("U", C.c_double * 2), ("a", C.c_double * 2),
+                ("theta", C.c_double), ("W", C.c_double), ("wdot", C.c_double),
+                ("Uprev", C.c_double * 2), ("Wprev", C.c_double), ("F", C.c_double * 2),
+                ("T", C.c_double), ("c0", C.c_double * 2), ("n", C.c_int64)]
 
 
 class Link(C.Structure):
@@ -92,12 +106,17 @@ def lib():
             "or_sizeof_link": (C.c_int, []),
             "or_sizeof_problem": (C.c_int, []),
             "or_num_threads": (C.c_int, []),
+            "or_step_body": (C.c_int, [P, C.POINTER(BodyParams), C.POINTER(Body), d, d]),
+            "or_sizeof_body": (C.c_int, []),
+            "or_sizeof_body_params": (C.c_int, []),
         }
         for name, (res, args) in sig.items():
             fn = getattr(_lib, name)
             fn.restype = res
             fn.argtypes = args
         assert _lib.or_sizeof_link() == C.sizeof(Link) == LINK_DTYPE.itemsize
+        assert _lib.or_sizeof_body() == C.sizeof(Body)
+        assert _lib.or_sizeof_body_params() == C.sizeof(BodyParams)
         assert _lib.or_sizeof_problem() == C.sizeof(Problem)
     return _lib
 
@@ -272,6 +291,36 @@ def run(p: Problem, f: np.ndarray, X: np.ndarray, n_steps: int, force_hist: bool
     if rc != 0:
         raise RuntimeError("oracle run: a cut link left the lattice")
     return fh
+
+
+def body_params(w) -> BodyParams:
+    """Rigid-body parameters from a ``workloads.Problem``."""
+    bp = BodyParams()
+    bp.free_dofs = int(w.body_free)
+    bp.rho_star = float(w.rho_star)
+    for a in range(2):
+        bp.spring[a], bp.damping[a] = float(w.spring[a]), float(w.damping[a])
+        bp.presc_amp[a], bp.presc_umax[a] = float(w.presc_amp[a]), float(w.presc_umax[a])
+    return bp
+
+
+def new_body(p: Problem) -> Body:
+    b = Body()
+    b.c[0] = b.c0[0] = p.cx
+    b.c[1] = b.c0[1] = p.cy
+    return b
+
+
+def run_body(p: Problem, bp: BodyParams, b: Body, f: np.ndarray, X: np.ndarray, n_steps: int):
+    """Steps with a moving circle (Sec. 2.3); returns the per-step history
+    [n, (cx, cy, Ux, Uy, theta, W, Fx, Fy, T)] after each step."""
+    assert f.dtype == np.float64 and f.flags["C_CONTIGUOUS"] and f.shape == (9, p.ny, p.nx)
+    hist = np.zeros((n_steps, 9))
+    for s in range(n_steps):
+        if lib().or_step_body(C.byref(p), C.byref(bp), C.byref(b), _ptr(f), _ptr(X)) != 0:
+            raise RuntimeError("oracle run: a cut link left the lattice")
+        hist[s] = (b.c[0], b.c[1], b.U[0], b.U[1], b.theta, b.W, b.F[0], b.F[1], b.T)
+    return hist
 
 
 def num_threads() -> int:

@@ -34,7 +34,8 @@
  *      to a 2^-16 grid, tested with exact integer orientations and the node
  *      perturbation tie rule; [[p]] is linear along each chord;
  *  R11 marker velocity from u = sum e_i f_i of the pre-collision field;
- *  R12 non-equilibrium extrapolation on non-periodic sides, corners as walls;
+ *  R12 non-equilibrium extrapolation on non-periodic sides, corners as walls
+ *      (a uniform inflow side takes u_b = (u_max, 0));
  *  R24 under Guo's force term (the comparison method of Sec. 2.2.2) the
  *      collision uses the compressible equilibrium and the velocity
  *      u = (sum e_i f_i + g/2) / rho the paper gives with it, g the whole
@@ -52,7 +53,7 @@
 /* Problem description (the oracle's own struct; filled from Python).        */
 /* ------------------------------------------------------------------------ */
 enum { OR_SRT = 0, OR_MRT = 1 };
-enum { OR_PERIODIC = 0, OR_WALL = 1, OR_INLET = 2, OR_OUTLET = 3 };
+enum { OR_PERIODIC = 0, OR_WALL = 1, OR_INLET = 2, OR_OUTLET = 3, OR_INLET_UNIFORM = 4 };
 /* Interfaces: a spring membrane, a fixed circle with direct forcing, and a
  * fixed circle with a prescribed uniform normal force (Sec. 4.1). */
 enum { OR_IF_NONE = 0, OR_IF_MEMBRANE = 1, OR_IF_RIGID = 2, OR_IF_NORMAL = 3 };
@@ -77,6 +78,11 @@ typedef struct {
     double kappa, dX;
     double cx, cy, radius; /* rigid circle */
     double f_normal;       /* prescribed force per unit length along the outward normal */
+    /* a moving rigid circle (Sec. 2.3): the body velocity U_c, W that direct
+     * forcing drives the markers to (U^D = U_c + W x (X - X_c)), and the
+     * orientation theta (marker k sits at angle theta + 2 pi k / N) */
+    double ud[3];
+    double theta;
 } or_problem;
 
 static int has_jumps(const or_problem *p) { return p->force_mode == OR_II_LBM || p->force_mode == OR_II_LBM_GUO; }
@@ -368,10 +374,11 @@ void or_marker_forces(const or_problem *p, const double *X, const double *U,
             gy = p->f_normal * ny_;
             jac = 1.0;
         } else {
-            gx = 0.0 - U[2 * k];
-            gy = 0.0 - U[2 * k + 1];
-            nx_ = (X[2 * k] - p->cx) / p->radius;
-            ny_ = (X[2 * k + 1] - p->cy) / p->radius;
+            double rx = X[2 * k] - p->cx, ry = X[2 * k + 1] - p->cy;
+            gx = (p->ud[0] - p->ud[2] * ry) - U[2 * k];
+            gy = (p->ud[1] + p->ud[2] * rx) - U[2 * k + 1];
+            nx_ = rx / p->radius;
+            ny_ = ry / p->radius;
             jac = 1.0;
         }
         double gn = gx * nx_ + gy * ny_;
@@ -501,8 +508,10 @@ static int cutlinks_rigid(const or_problem *p, const double *jp, or_link *rec, i
                 double disc = sqrt(de * de - ee * dd);
                 double q = inP ? (-de + disc) / ee : (-de - disc) / ee;
                 double cxp = x + q * EX[i] - p->cx, cyp = y + q * EY[i] - p->cy;
-                double ang = atan2(cyp, cxp);
+                double ang = atan2(cyp, cxp) - p->theta;   /* theta in [0, 2 pi) */
                 if (ang < 0.0) ang += 2.0 * M_PI;
+                if (ang < 0.0) ang += 2.0 * M_PI;
+                if (ang >= 2.0 * M_PI) ang -= 2.0 * M_PI;
                 double s = ang * N / (2.0 * M_PI);
                 int k = (int)floor(s);
                 if (k >= N) k = N - 1;
@@ -607,6 +616,9 @@ static void nee_node(const or_problem *p, double *f, int x, int y)
     if (side_type == OR_INLET) {
         double H = p->ny - 1;
         ubx = 4.0 * p->u_max * y * (H - y) / (H * H);
+        uby = 0.0;
+    } else if (side_type == OR_INLET_UNIFORM) {
+        ubx = p->u_max;
         uby = 0.0;
     } else if (side_type == OR_OUTLET) {
         ubx = uxf; uby = uyf;
@@ -779,6 +791,112 @@ int or_run(const or_problem *p, double *f, double *X, int n_steps, double *force
     free(G);
     return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Rigid-body dynamics of a circle (Sec. 2.3).                               */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t free_dofs;     /* bit 0: x, bit 1: y, bit 2: rotation */
+    int32_t pad;
+    double rho_star;       /* rho_s / rho_f */
+    double spring[2];      /* k_s per axis, about the initial centre */
+    double damping[2];     /* c per axis */
+    double presc_amp[2];   /* prescribed harmonic motion D_c = -A sin(U_max t / A) ... */
+    double presc_umax[2];  /* ... U_c = -U_max cos(U_max t / A) (Sec. 4.4); 0: none */
+} or_body_params;
+
+typedef struct {
+    double c[2], U[2], a[2];   /* centre, velocity, acceleration of the centre */
+    double theta, W, wdot;     /* orientation, angular velocity and acceleration */
+    double Uprev[2], Wprev;    /* the previous step's velocities (interior inertia) */
+    double F[2], T;            /* F^ext and T^ext of the last step */
+    double c0[2];              /* initial centre */
+    int64_t n;                 /* steps taken */
+} or_body;
+
+/* One step with a moving circle:
+ *  - the prescribed axes take U_c(n) and X_c(n) from the harmonic motion;
+ *  - the step runs with U^D = U_c + W x (X - X_c) at the markers (Sec. 2.2.2, Eq. (18));
+ *  - F^ext = -sum G dX + rho_f V_s (U_c^n - U_c^{n-1}) and
+ *    T^ext = -sum (X - X_c) x G dX + (rho_f/rho_s) I_s (W^n - W^{n-1})
+ *    (Sec. 2.3, the total force and torque; rho_f = 1, V_s = pi R^2,
+ *    m = rho_s V_s, I_s = m R^2 / 2), plus spring and damper on free axes;
+ *  - m a^{n+1} = F, I_s w^{n+1} = T; U^{n+1} = U^n + a^{n+1};
+ *    X_c^{n+1} = X_c^n + U^n + (a^n + a^{n+1}) / 2, the same for theta;
+ *  - the markers are placed rigidly: X_k = X_c + R (cos, sin)(theta + 2 pi k / N). */
+int or_step_body(const or_problem *p0, const or_body_params *bp, or_body *b, double *f, double *X)
+{
+    int N = p0->n_markers;
+    double t = (double)b->n;
+    for (int ax = 0; ax < 2; ax++)
+        if (bp->presc_umax[ax] != 0.0) {
+            double A = bp->presc_amp[ax], Um = bp->presc_umax[ax];
+            b->U[ax] = -Um * cos(Um * t / A);
+            b->c[ax] = b->c0[ax] - A * sin(Um * t / A);
+        }
+    if (b->n == 0) {
+        b->Uprev[0] = b->U[0]; b->Uprev[1] = b->U[1]; b->Wprev = b->W;
+    }
+    for (int k = 0; k < N; k++) {
+        double ang = b->theta + 2.0 * M_PI * k / N;
+        X[2 * k] = b->c[0] + p0->radius * cos(ang);
+        X[2 * k + 1] = b->c[1] + p0->radius * sin(ang);
+    }
+    or_problem p = *p0;
+    p.cx = b->c[0]; p.cy = b->c[1];
+    p.ud[0] = b->U[0]; p.ud[1] = b->U[1]; p.ud[2] = b->W;
+    p.theta = b->theta - 2.0 * M_PI * floor(b->theta / (2.0 * M_PI));
+    double *G = calloc(2 * N + 2, sizeof(double));
+    or_step_out o;
+    memset(&o, 0, sizeof o);
+    o.G = G;
+    int rc = or_step(&p, f, X, &o);
+    double R = p0->radius, Vs = M_PI * R * R;
+    double m = bp->rho_star * Vs, Is = 0.5 * m * R * R;
+    double Fx = 0.0, Fy = 0.0, T = 0.0;
+    for (int k = 0; k < N; k++) {
+        double rx = X[2 * k] - b->c[0], ry = X[2 * k + 1] - b->c[1];
+        Fx -= G[2 * k] * p0->dX;
+        Fy -= G[2 * k + 1] * p0->dX;
+        T -= (rx * G[2 * k + 1] - ry * G[2 * k]) * p0->dX;
+    }
+    Fx += Vs * (b->U[0] - b->Uprev[0]);
+    Fy += Vs * (b->U[1] - b->Uprev[1]);
+    T += Is / bp->rho_star * (b->W - b->Wprev);
+    b->F[0] = Fx; b->F[1] = Fy; b->T = T;
+    double Fa[2] = {Fx, Fy};
+    double Unew[2] = {b->U[0], b->U[1]};
+    for (int ax = 0; ax < 2; ax++) {
+        b->Uprev[ax] = b->U[ax];
+        if (!(bp->free_dofs & (1 << ax)) || bp->presc_umax[ax] != 0.0) continue;
+        double Fext = Fa[ax] - bp->spring[ax] * (b->c[ax] - b->c0[ax]) - bp->damping[ax] * b->U[ax];
+        double anew = Fext / m;
+        Unew[ax] = b->U[ax] + anew;
+        b->c[ax] = b->c[ax] + b->U[ax] + 0.5 * (b->a[ax] + anew);
+        b->a[ax] = anew;
+    }
+    b->U[0] = Unew[0]; b->U[1] = Unew[1];
+    b->Wprev = b->W;
+    if (bp->free_dofs & 4) {
+        double wnew = T / Is;
+        double Wn = b->W + wnew;
+        b->theta = b->theta + b->W + 0.5 * (b->wdot + wnew);
+        b->wdot = wnew;
+        b->W = Wn;
+    }
+    b->n++;
+    /* markers of the next step */
+    for (int k = 0; k < N; k++) {
+        double ang = b->theta + 2.0 * M_PI * k / N;
+        X[2 * k] = b->c[0] + p0->radius * cos(ang);
+        X[2 * k + 1] = b->c[1] + p0->radius * sin(ang);
+    }
+    free(G);
+    return rc;
+}
+
+int or_sizeof_body(void) { return (int)sizeof(or_body); }
+int or_sizeof_body_params(void) { return (int)sizeof(or_body_params); }
 
 /* ------------------------------------------------------------------------ */
 /* Diagnostics.                                                              */

@@ -98,7 +98,7 @@ class SplitMix64:
 # Problem description (plain data, mirrored field by field into the C structs)
 # ---------------------------------------------------------------------------
 SRT, MRT = 0, 1
-BC_PERIODIC, BC_WALL, BC_INLET, BC_OUTLET = 0, 1, 2, 3
+BC_PERIODIC, BC_WALL, BC_INLET, BC_OUTLET, BC_INLET_UNIFORM = 0, 1, 2, 3, 4
 IF_NONE, IF_MEMBRANE, IF_RIGID, IF_NORMAL = 0, 1, 2, 3
 FORCE_II_LBM, FORCE_IB_LBM, FORCE_IB_LBM_GUO, FORCE_II_LBM_GUO = 0, 1, 2, 3
 STORE_FP32, STORE_FP16 = 0, 1
@@ -128,6 +128,12 @@ class Problem:
     center: Sequence[float] = (0.0, 0.0)      # rigid circle centre
     radius: float = 0.0                       # rigid circle radius
     f_normal: float = 0.0                     # prescribed normal force per unit length (IF_NORMAL)
+    body_free: int = 0                        # moving circle: bit 0 x, bit 1 y, bit 2 rotation free
+    rho_star: float = 1.0                     # density ratio rho_s / rho_f of the body
+    spring: Sequence[float] = (0.0, 0.0)      # k_s per axis, about the initial centre
+    damping: Sequence[float] = (0.0, 0.0)     # c per axis
+    presc_amp: Sequence[float] = (0.0, 0.0)   # prescribed harmonic motion: amplitude A ...
+    presc_umax: Sequence[float] = (0.0, 0.0)  # ... and U_max per axis (0: not prescribed)
     storage: int = STORE_FP32
     math: int = MATH_FP32                     # collision arithmetic
     name: str = ""
