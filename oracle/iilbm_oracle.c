@@ -868,7 +868,14 @@ int or_step_body(const or_problem *p0, const or_body_params *bp, or_body *b, dou
     double Unew[2] = {b->U[0], b->U[1]};
     for (int ax = 0; ax < 2; ax++) {
         b->Uprev[ax] = b->U[ax];
-        if (!(bp->free_dofs & (1 << ax)) || bp->presc_umax[ax] != 0.0) continue;
+        if (bp->presc_umax[ax] != 0.0) {
+            /* the state left for the next step, as on a free axis */
+            double A = bp->presc_amp[ax], Um = bp->presc_umax[ax];
+            Unew[ax] = -Um * cos(Um * (t + 1.0) / A);
+            b->c[ax] = b->c0[ax] - A * sin(Um * (t + 1.0) / A);
+            continue;
+        }
+        if (!(bp->free_dofs & (1 << ax))) continue;
         double Fext = Fa[ax] - bp->spring[ax] * (b->c[ax] - b->c0[ax]) - bp->damping[ax] * b->U[ax];
         double anew = Fext / m;
         Unew[ax] = b->U[ax] + anew;

@@ -136,11 +136,11 @@ def test_prescribed_harmonic_motion_and_its_drag():
     b = O.new_body(p)
     n = int(round(2 * math.pi * A / Um))
     h = O.run_body(p, O.body_params(prob), b, f, X, n)
-    t = np.arange(n)
+    t = np.arange(1, n + 1)            # the state after a step is that of the next step
     assert np.allclose(h[:, 0], 32.0 - A * np.sin(Um * t / A), atol=1e-13)
     assert np.allclose(h[:, 2], -Um * np.cos(Um * t / A), atol=1e-15)
     assert np.all(h[:, 1] == 32.0)
-    work = (h[:, 6] * h[:, 2]).sum()
+    work = (h[:, 6] * (-Um * np.cos(Um * (t - 1) / A))).sum()   # F of step s with U_c of step s
     assert work < 0.0
 
 
