@@ -53,7 +53,8 @@ extern "C" {
 
 /* ---- problem description ----------------------------------------------- */
 enum { II_LBM_SRT = 0, II_LBM_MRT = 1 };
-enum { II_LBM_BC_PERIODIC = 0, II_LBM_BC_WALL = 1, II_LBM_BC_INLET = 2, II_LBM_BC_OUTLET = 3 };
+enum { II_LBM_BC_PERIODIC = 0, II_LBM_BC_WALL = 1, II_LBM_BC_INLET = 2, II_LBM_BC_OUTLET = 3,
+       II_LBM_BC_INLET_UNIFORM = 4 };
 enum { II_LBM_IF_NONE = 0, II_LBM_IF_MEMBRANE = 1, II_LBM_IF_RIGID = 2, II_LBM_IF_NORMAL = 3 };
 /* Force modes (how the interface force enters the fluid):
  *  II      the paper's method: jumps on cut links for the normal part, the
@@ -85,7 +86,8 @@ enum { II_LBM_MATH_FP32 = 0, II_LBM_MATH_FP64 = 1 };
  *               WALL (velocity u_wall along the side), INLET (parabola
  *               4 u_max y (H - y) / H^2 with H = ny - 1; x-low only), OUTLET
  *               (zero gradient, the velocity of the inward neighbour; any
- *               side).  Corner nodes follow the y side.
+ *               side), INLET_UNIFORM (velocity (u_max, 0); x-low only).
+ *               Corner nodes follow the y side.
  *  body_force   uniform Eulerian force density added to the force term.
  *  force_mode   II_LBM_FORCE_II, _IB, _IB_GUO or _II_GUO (above).
  *  interface_kind  NONE, MEMBRANE (spring force kappa (X_{k+1} - 2 X_k +
@@ -99,6 +101,17 @@ enum { II_LBM_MATH_FP32 = 0, II_LBM_MATH_FP64 = 1 };
  *  kappa, dX    spring constant and marker spacing Delta X (> 0, <= 2).
  *  center, radius  the circle (RIGID and NORMAL).
  *  f_normal     F of the NORMAL interface.
+ *  body_free, rho_star, spring, damping, presc_amp, presc_umax
+ *               a moving RIGID circle (Sec. 2.3; one instance per handle):
+ *               body_free bit 0 / 1 / 2 frees x / y / rotation; rho_star is
+ *               rho_s / rho_f (> 0 when any axis is free; m = rho_star pi R^2,
+ *               I_s = m R^2 / 2); spring[a] and damping[a] act on a free axis
+ *               about the initial centre; presc_umax[a] != 0 prescribes axis a
+ *               as D_c = -A sin(U_max t / A), U_c = -U_max cos(U_max t / A)
+ *               with A = presc_amp[a] (Sec. 4.4).  Direct forcing drives the
+ *               markers to U_c + W x (X - X_c); each step ends with the body
+ *               update of Sec. 2.3 (F^ext and T^ext with their interior-inertia
+ *               terms, velocity, position and angle) on the device.
  *  storage      II_LBM_FP32 or II_LBM_FP16: distributions are stored as
  *               deviations d_i = f_i - w_i rho0 (rho0 = 1).
  *  fp16_log2_scale  FP16 storage holds d_i * 2^-fp16_log2_scale; 0 lets the
@@ -128,6 +141,12 @@ typedef struct ii_lbm_problem {
     int32_t fp16_log2_scale;
     int32_t math;
     double f_normal;
+    int32_t body_free;
+    double rho_star;
+    double spring[2];
+    double damping[2];
+    double presc_amp[2];
+    double presc_umax[2];
 } ii_lbm_problem;
 
 /* One cut link (see ii_lbm_cutlinks for which step): the link from source
@@ -152,6 +171,14 @@ typedef struct ii_lbm_diag_t {
 } ii_lbm_diag_t;
 
 typedef struct ii_lbm_handle ii_lbm_handle;
+
+/* State of a moving RIGID circle after the last step (Sec. 2.3), 14 doubles:
+ * centre (2), velocity U_c (2), angle theta, angular velocity W, F^ext (2)
+ * and T^ext of the last step, acceleration (2), angular acceleration, the
+ * step count, and 0.  Synchronises the handle's stream.  EINVAL for an
+ * instance whose body does not move.  The checkpoint of ii_lbm_save_state
+ * carries this state too. */
+int ii_lbm_body(ii_lbm_handle* h, int32_t inst, double* out14);
 
 /* Device bytes that init needs for n_inst instances (problems p[0..n_inst-1]).
  * Pure function of its arguments; no device access. */

@@ -30,7 +30,9 @@ class Problem(C.Structure):
                 ("interface_kind", C.c_int32), ("force_mode", C.c_int32), ("n_markers", C.c_int32),
                 ("kappa", C.c_double), ("dX", C.c_double), ("center", C.c_double * 2),
                 ("radius", C.c_double), ("storage", C.c_int32), ("fp16_log2_scale", C.c_int32),
-                ("math", C.c_int32), ("f_normal", C.c_double)]
+                ("math", C.c_int32), ("f_normal", C.c_double), ("body_free", C.c_int32),
+                ("rho_star", C.c_double), ("spring", C.c_double * 2), ("damping", C.c_double * 2),
+                ("presc_amp", C.c_double * 2), ("presc_umax", C.c_double * 2)]
 
 
 class Link(C.Structure):
@@ -56,7 +58,7 @@ EXPORTS = [
     "ii_lbm_save_state", "ii_lbm_load_state", "ii_lbm_cutlinks", "ii_lbm_diag",
     "ii_lbm_set_timing", "ii_lbm_get_timing", "ii_lbm_sweep_bytes", "ii_lbm_set_graph",
     "ii_lbm_set_overlap", "ii_lbm_autotune", "ii_lbm_destroy", "ii_lbm_strerror",
-    "ii_lbm_set_isolation", "ii_lbm_instance_errors",
+    "ii_lbm_set_isolation", "ii_lbm_instance_errors", "ii_lbm_body",
 ]
 
 _lib = None
@@ -97,6 +99,7 @@ def load():
         "ii_lbm_set_graph": [v, i32],
         "ii_lbm_set_isolation": [v, i32],
         "ii_lbm_instance_errors": [v, v, i32],
+        "ii_lbm_body": [v, i32, v],
         "ii_lbm_set_overlap": [v, i32],
         "ii_lbm_autotune": [v, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(d)],
         "ii_lbm_destroy": [v],
@@ -146,6 +149,13 @@ def make_problem(w) -> Problem:
     p.fp16_log2_scale = int(getattr(w, "fp16_log2_scale", 0))
     p.math = int(getattr(w, "math", 0))
     p.f_normal = float(getattr(w, "f_normal", 0.0))
+    p.body_free = int(getattr(w, "body_free", 0))
+    p.rho_star = float(getattr(w, "rho_star", 1.0))
+    for a in range(2):
+        p.spring[a] = float(getattr(w, "spring", (0.0, 0.0))[a])
+        p.damping[a] = float(getattr(w, "damping", (0.0, 0.0))[a])
+        p.presc_amp[a] = float(getattr(w, "presc_amp", (0.0, 0.0))[a])
+        p.presc_umax[a] = float(getattr(w, "presc_umax", (0.0, 0.0))[a])
     return p
 
 
@@ -265,6 +275,14 @@ class Sim:
         out = np.zeros(self.n_inst, dtype=np.int32)
         check(load().ii_lbm_instance_errors(self.h, out.ctypes.data, self.n_inst), "instance_errors")
         return out
+
+    def body(self, inst: int = 0) -> dict:
+        """State of a moving rigid circle after the last step (synchronises)."""
+        out = np.zeros(14)
+        check(load().ii_lbm_body(self.h, inst, out.ctypes.data), "body")
+        return {"c": out[0:2].copy(), "U": out[2:4].copy(), "theta": out[4], "W": out[5],
+                "F": out[6:8].copy(), "T": out[8], "a": out[9:11].copy(), "wdot": out[11],
+                "steps": int(out[12])}
 
     def set_overlap(self, mode: int) -> None:
         """Membrane step schedule (OVERLAP_SERIAL / _FULL / _INTERP_FIRST)."""

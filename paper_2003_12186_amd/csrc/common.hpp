@@ -72,6 +72,20 @@ struct InstDev {
     float scale, inv_scale;  // FP16: value = stored * scale
     double kappa, dX, cx, cy, radius;
     double f_normal;      // prescribed normal force per unit length (NORMAL circle)
+    int moving;           // a moving rigid circle (body state on the device)
+    int body_free;        // bit 0 x, bit 1 y, bit 2 rotation
+    double rho_star, spring[2], damping[2], presc_amp[2], presc_umax[2];
+};
+
+// State of a moving rigid circle (Sec. 2.3) for the step about to run.
+struct BodyDev {
+    double c[2], U[2], a[2];   // centre, velocity, acceleration
+    double theta, W, wdot;     // angle, angular velocity and acceleration
+    double Uprev[2], Wprev;    // the previous step's velocities
+    double F[2], T;            // F^ext, T^ext of the last step
+    double c0[2];              // initial centre (the springs' rest point)
+    double theta_mod;          // theta reduced to [0, 2 pi)
+    long long n;               // steps taken
 };
 
 // Device buffers of a handle (all carved from one workspace).
@@ -95,6 +109,7 @@ struct DevPtrs {
     int* rec_count;        // [2 * n_inst]
     int* err;              // [n_inst] error bits
     double* diag;          // reduction partials
+    BodyDev* body;         // [n_inst] moving-body states
 };
 
 // ---------------------------------------------------------------------------
@@ -302,6 +317,9 @@ __device__ void nee(const InstDev& I, const T* __restrict__ A, int x, int y, M d
     if (type == II_LBM_BC_INLET) {
         const M H = (M)(I.ny - 1);
         ubx = (M)4 * (M)I.u_max * (M)y * (H - (M)y) / (H * H);
+        uby = 0;
+    } else if (type == II_LBM_BC_INLET_UNIFORM) {
+        ubx = (M)I.u_max;
         uby = 0;
     } else if (type == II_LBM_BC_OUTLET) {
         ubx = ux;
@@ -527,6 +545,7 @@ hipError_t launch_slot_reset_batch(const Batch& b, int n_inst, const DevPtrs& P,
                                    hipStream_t s);
 hipError_t launch_tiles(const InstDev& I, const DevPtrs& P, int parity, bool records, hipStream_t s);
 hipError_t launch_fill_ints(int* p, long long n, int value, hipStream_t s);
+hipError_t launch_body(const InstDev& I, const DevPtrs& P, int par, hipStream_t s);
 hipError_t launch_markers_batch(const Batch& b, const DevPtrs& P, const void* A, int par, int mode,
                                 hipStream_t s);
 hipError_t launch_tiles_batch(const Batch& b, const DevPtrs& P, int parity, bool records,

@@ -176,12 +176,20 @@ __device__ __forceinline__ void markers_body(const InstDev& I, const DevPtrs& P,
             gy = I.f_normal * ny_;
             jac = 1.0;
         } else {
-            // direct forcing to U^D = 0 with eta = 1 (Sec. 2.2.2, Eq. (18));
-            // |dX/ds| = 1 and the radial normal of the rigid circle (Sec. 3.1)
-            gx = 0.0 - us;
-            gy = 0.0 - vs;
-            nx_ = (Xk.x - I.cx) / I.radius;
-            ny_ = (Xk.y - I.cy) / I.radius;
+            // direct forcing to U^D with eta = 1 (Sec. 2.2.2, Eq. (18)): U^D = 0
+            // for a fixed circle, U_c + W x (X - X_c) for a moving one;
+            // |dX/ds| = 1 and the radial normal of the circle (Sec. 3.1)
+            double ccx = I.cx, ccy = I.cy, ux_d = 0.0, uy_d = 0.0, wd = 0.0;
+            if (I.moving) {
+                const BodyDev& bd = P.body[I.inst];
+                ccx = bd.c[0]; ccy = bd.c[1];
+                ux_d = bd.U[0]; uy_d = bd.U[1]; wd = bd.W;
+            }
+            const double rx = Xk.x - ccx, ry = Xk.y - ccy;
+            gx = (ux_d - wd * ry) - us;
+            gy = (uy_d + wd * rx) - vs;
+            nx_ = rx / I.radius;
+            ny_ = ry / I.radius;
             jac = 1.0;
         }
         // [[p]] = G.n / |dX/ds| (Sec. 3.1, Eq. (40)); G_par = G - (G.n) n (Eq. (46))
@@ -399,20 +407,25 @@ __device__ __forceinline__ bool link_crossing(int x, int y, int i, const Chord& 
 // |x - c| = R (the root of |P + q e_i - c|^2 = R^2 inside the link), and the
 // marker interval that brackets it by angle: [[p]] there is linear in the
 // angle between markers k and k+1.
-__device__ __forceinline__ void rigid_cut(const InstDev& I, int x, int y, int i, bool inP,
-                                          double& q, double& th, int& k)
+// (cx, cy, th0): the circle's centre and orientation this step (a moving
+// body's marker k sits at angle th0 + 2 pi k / N, th0 in [0, 2 pi)).
+__device__ __forceinline__ void rigid_cut(const InstDev& I, double cx, double cy, double th0,
+                                          int x, int y, int i, bool inP, double& q, double& th,
+                                          int& k)
 {
     const int N = I.n_markers;
     const double R2 = I.radius * I.radius;
-    const double dx = (double)x - I.cx, dy = (double)y - I.cy;
+    const double dx = (double)x - cx, dy = (double)y - cy;
     const double ee = (double)(EX[i] * EX[i] + EY[i] * EY[i]);
     const double de = dx * EX[i] + dy * EY[i];
     const double dd = dx * dx + dy * dy - R2;
     const double disc = sqrt(de * de - ee * dd);
     q = inP ? (-de + disc) / ee : (-de - disc) / ee;
-    const double cxp = (double)x + q * EX[i] - I.cx, cyp = (double)y + q * EY[i] - I.cy;
-    double ang = atan2(cyp, cxp);
+    const double cxp = (double)x + q * EX[i] - cx, cyp = (double)y + q * EY[i] - cy;
+    double ang = atan2(cyp, cxp) - th0;
     if (ang < 0.0) ang += 2.0 * M_PI;
+    if (ang < 0.0) ang += 2.0 * M_PI;
+    if (ang >= 2.0 * M_PI) ang -= 2.0 * M_PI;
     const double sN = ang * N / (2.0 * M_PI);
     k = (sN >= 0.0 && sN < (double)N) ? (int)floor(sN) : 0;
     th = sN - k;
@@ -607,17 +620,23 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
             }
             if (IFACE == II_LBM_IF_RIGID && I.jumps) {
                 // Rigid circle: level set phi = |x - c|^2 - R^2, interior phi < 0.
+                double ccx = I.cx, ccy = I.cy, th0 = 0.0;
+                if (I.moving) {
+                    ccx = P.body[I.inst].c[0];
+                    ccy = P.body[I.inst].c[1];
+                    th0 = P.body[I.inst].theta_mod;
+                }
                 const double R2 = I.radius * I.radius;
-                const double dx = (double)x - I.cx, dy = (double)y - I.cy;
+                const double dx = (double)x - ccx, dy = (double)y - ccy;
                 const double phP = dx * dx + dy * dy - R2;
                 for (int i = 1; i < 9; i++) {
                     const double qxd = (double)(x + EX[i]), qyd = (double)(y + EY[i]);
-                    const double phQ = (qxd - I.cx) * (qxd - I.cx) + (qyd - I.cy) * (qyd - I.cy) - R2;
+                    const double phQ = (qxd - ccx) * (qxd - ccx) + (qyd - ccy) * (qyd - ccy) - R2;
                     const bool inP = phP < 0.0, inQ = phQ < 0.0;
                     if (inP == inQ) continue;
                     double q, th;
                     int k;
-                    rigid_cut(I, x, y, i, inP, q, th, k);
+                    rigid_cut(I, ccx, ccy, th0, x, y, i, inP, q, th, k);
                     const double jpc =
                         (1.0 - th) * P.jp[I.mk_off + k] + th * P.jp[I.mk_off + (k + 1) % N];
                     add_jump(S, tid, i, inP ? 1 : -1, jpc);
@@ -677,11 +696,17 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
                     L.sigma = sg; L.seg = S.key[j]; L.q = qq; L.theta = th;
                     L.jp = (1.0 - th) * S.jpa[j] + th * S.jpb[j];
                 } else {
-                    const double dx = (double)x - I.cx, dy = (double)y - I.cy;
+                    double ccx = I.cx, ccy = I.cy, th0 = 0.0;
+                    if (I.moving) {
+                        ccx = P.body[I.inst].c[0];
+                        ccy = P.body[I.inst].c[1];
+                        th0 = P.body[I.inst].theta_mod;
+                    }
+                    const double dx = (double)x - ccx, dy = (double)y - ccy;
                     const bool inP = dx * dx + dy * dy - I.radius * I.radius < 0.0;
                     double q, th;
                     int k;
-                    rigid_cut(I, x, y, i, inP, q, th, k);
+                    rigid_cut(I, ccx, ccy, th0, x, y, i, inP, q, th, k);
                     L.sigma = inP ? 1 : -1; L.seg = k; L.q = q; L.theta = th;
                     L.jp = (1.0 - th) * P.jp[I.mk_off + k] + th * P.jp[I.mk_off + (k + 1) % N];
                 }
@@ -849,6 +874,85 @@ hipError_t launch_tiles_batch(const Batch& b, const DevPtrs& P, int parity, bool
     return b.iface == II_LBM_IF_MEMBRANE
                ? tiles_batch_i<II_LBM_IF_MEMBRANE>(b, P, parity, records, s)
                : tiles_batch_i<II_LBM_IF_RIGID>(b, P, parity, records, s);
+}
+
+// ---------------------------------------------------------------------------
+// Moving rigid circle: the body update that ends step m (Sec. 2.3).
+//   F^ext = -sum_k G_k dX + rho_f V_s (U_c^m - U_c^{m-1}),
+//   T^ext = -sum_k (X_k - X_c) x G_k dX + (rho_f / rho_s) I_s (W^m - W^{m-1}),
+// rho_f = 1, V_s = pi R^2, m = rho* V_s, I_s = m R^2 / 2; on a free axis
+// m a^{m+1} = F (+ spring and damper), U^{m+1} = U^m + a^{m+1},
+// X_c^{m+1} = X_c^m + U^m + (a^m + a^{m+1}) / 2, and the same for the angle; a
+// prescribed axis takes U_c and X_c of step m+1 from its harmonic motion.
+// The sums run in marker order on one lane; then every lane places the
+// markers of step m+1 rigidly at X_c + R (cos, sin)(theta + 2 pi k / N).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_body(InstDev I, DevPtrs P, int par)
+{
+    BodyDev& b = P.body[I.inst];
+    const int N = I.n_markers;
+    const double2* X = P.X[par] + I.mk_off;
+    if (threadIdx.x == 0) {
+        double Fx = 0.0, Fy = 0.0, T = 0.0;
+        for (int k = 0; k < N; k++) {
+            const double2 G = P.G[I.mk_off + k];
+            const double rx = X[k].x - b.c[0], ry = X[k].y - b.c[1];
+            Fx -= G.x * I.dX;
+            Fy -= G.y * I.dX;
+            T -= (rx * G.y - ry * G.x) * I.dX;
+        }
+        const double R = I.radius, Vs = M_PI * R * R;
+        const double m = I.rho_star * Vs, Is = 0.5 * m * R * R;
+        Fx += Vs * (b.U[0] - b.Uprev[0]);
+        Fy += Vs * (b.U[1] - b.Uprev[1]);
+        T += Is / I.rho_star * (b.W - b.Wprev);
+        b.F[0] = Fx;
+        b.F[1] = Fy;
+        b.T = T;
+        const double Fa[2] = {Fx, Fy};
+        double Unew[2] = {b.U[0], b.U[1]};
+        const double tn = (double)(b.n + 1);
+        for (int ax = 0; ax < 2; ax++) {
+            b.Uprev[ax] = b.U[ax];
+            if (I.presc_umax[ax] != 0.0) {
+                const double A = I.presc_amp[ax], Um = I.presc_umax[ax];
+                Unew[ax] = -Um * cos(Um * tn / A);
+                b.c[ax] = b.c0[ax] - A * sin(Um * tn / A);
+                continue;
+            }
+            if (!(I.body_free & (1 << ax))) continue;
+            const double Fe = Fa[ax] - I.spring[ax] * (b.c[ax] - b.c0[ax]) - I.damping[ax] * b.U[ax];
+            const double an = Fe / m;
+            Unew[ax] = b.U[ax] + an;
+            b.c[ax] = b.c[ax] + b.U[ax] + 0.5 * (b.a[ax] + an);
+            b.a[ax] = an;
+        }
+        b.U[0] = Unew[0];
+        b.U[1] = Unew[1];
+        b.Wprev = b.W;
+        if (I.body_free & 4) {
+            const double wn = T / Is;
+            const double Wn = b.W + wn;
+            b.theta = b.theta + b.W + 0.5 * (b.wdot + wn);
+            b.wdot = wn;
+            b.W = Wn;
+        }
+        b.theta_mod = b.theta - 2.0 * M_PI * floor(b.theta / (2.0 * M_PI));
+        b.n += 1;
+    }
+    __syncthreads();
+    double2* Xn = P.X[par ^ 1] + I.mk_off;
+    const double cx = b.c[0], cy = b.c[1], th = b.theta;
+    for (int k = threadIdx.x; k < N; k += blockDim.x) {
+        const double ang = th + 2.0 * M_PI * k / N;
+        Xn[k] = make_double2(cx + I.radius * cos(ang), cy + I.radius * sin(ang));
+    }
+}
+
+hipError_t launch_body(const InstDev& I, const DevPtrs& P, int par, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_body, dim3(1), dim3(256), 0, s, I, P, par);
+    return hipGetLastError();
 }
 
 }  // namespace iilbm

@@ -29,7 +29,7 @@ struct Layout {
     size_t off_X[2] = {0, 0}, off_U = 0, off_G = 0, off_Gt = 0, off_jp = 0, off_wx = 0, off_wy = 0, off_f0 = 0;
     size_t off_tile_count = 0, off_tile_list = 0, off_tile_slot[2] = {0, 0}, off_corr[2] = {0, 0};
     size_t off_act_list[2] = {0, 0}, off_act_count = 0;
-    size_t off_rec = 0, off_rec_count = 0, off_err = 0, off_diag = 0;
+    size_t off_rec = 0, off_rec_count = 0, off_err = 0, off_diag = 0, off_body = 0;
     size_t off_insts = 0, off_mk_table = 0, off_tile_table = 0, off_sweep_table = 0;
     int mk_units = 0, tile_units = 0, sweep_units_max = 0;
     size_t total = 0;
@@ -42,11 +42,11 @@ int validate(const ii_lbm_problem& p, const double* X0)
     if (!(p.tau > 0.5) || !isfinite(p.tau)) return II_LBM_EINVAL;
     if (p.collision != II_LBM_SRT && p.collision != II_LBM_MRT) return II_LBM_EINVAL;
     for (int i = 0; i < 4; i++)
-        if (p.bc[i] < II_LBM_BC_PERIODIC || p.bc[i] > II_LBM_BC_OUTLET) return II_LBM_EINVAL;
+        if (p.bc[i] < II_LBM_BC_PERIODIC || p.bc[i] > II_LBM_BC_INLET_UNIFORM) return II_LBM_EINVAL;
     if ((p.bc[0] == II_LBM_BC_PERIODIC) != (p.bc[1] == II_LBM_BC_PERIODIC)) return II_LBM_EINVAL;
     if ((p.bc[2] == II_LBM_BC_PERIODIC) != (p.bc[3] == II_LBM_BC_PERIODIC)) return II_LBM_EINVAL;
-    if (p.bc[1] == II_LBM_BC_INLET || p.bc[2] == II_LBM_BC_INLET || p.bc[3] == II_LBM_BC_INLET)
-        return II_LBM_EINVAL;
+    for (int q = 1; q < 4; q++)
+        if (p.bc[q] == II_LBM_BC_INLET || p.bc[q] == II_LBM_BC_INLET_UNIFORM) return II_LBM_EINVAL;
     if (p.storage != II_LBM_FP32 && p.storage != II_LBM_FP16) return II_LBM_EINVAL;
     if (p.math != II_LBM_MATH_FP32 && p.math != II_LBM_MATH_FP64) return II_LBM_EINVAL;
     if (p.force_mode < II_LBM_FORCE_II || p.force_mode > II_LBM_FORCE_II_GUO) return II_LBM_EINVAL;
@@ -60,6 +60,15 @@ int validate(const ii_lbm_problem& p, const double* X0)
         !(p.radius > 0.0))
         return II_LBM_EINVAL;
     if (p.interface_kind == II_LBM_IF_NORMAL && !isfinite(p.f_normal)) return II_LBM_EINVAL;
+    const bool moving = p.body_free != 0 || p.presc_umax[0] != 0.0 || p.presc_umax[1] != 0.0;
+    if (moving) {
+        if (p.interface_kind != II_LBM_IF_RIGID || (p.body_free & ~7)) return II_LBM_EINVAL;
+        if (p.body_free && !(p.rho_star > 0.0 && isfinite(p.rho_star))) return II_LBM_EINVAL;
+        for (int a = 0; a < 2; a++) {
+            if (!isfinite(p.spring[a]) || !isfinite(p.damping[a])) return II_LBM_EINVAL;
+            if (p.presc_umax[a] != 0.0 && !(fabs(p.presc_amp[a]) > 0.0)) return II_LBM_EINVAL;
+        }
+    }
     if (!X0) return II_LBM_EINVAL;
     double area = 0.0;
     const int N = p.n_markers;
@@ -94,6 +103,7 @@ int auto_fp16_exp(const ii_lbm_problem& p, const double* X0)
         }
     }
     if (p.interface_kind == II_LBM_IF_NORMAL) est = std::max(est, 3.0 * fabs(p.f_normal));
+    est = std::max(est, 3.0 * std::max(fabs(p.presc_umax[0]), fabs(p.presc_umax[1])));
     est = std::max(est, 1e-7);
     return (int)floor(log2(est)) - 12;
 }
@@ -148,6 +158,16 @@ int build_layout(const ii_lbm_problem* p, int n_inst, Layout& L)
         I.cy = q.center[1];
         I.radius = q.radius;
         I.f_normal = q.f_normal;
+        I.moving = q.interface_kind == II_LBM_IF_RIGID &&
+                   (q.body_free != 0 || q.presc_umax[0] != 0.0 || q.presc_umax[1] != 0.0);
+        I.body_free = q.body_free;
+        I.rho_star = q.rho_star;
+        for (int a = 0; a < 2; a++) {
+            I.spring[a] = q.spring[a];
+            I.damping[a] = q.damping[a];
+            I.presc_amp[a] = q.presc_amp[a];
+            I.presc_umax[a] = q.presc_umax[a];
+        }
         I.mk_off = mk;
         mk += I.n_markers;
         I.tiles_x = (q.nx + kTile - 1) / kTile;
@@ -209,6 +229,7 @@ int build_layout(const ii_lbm_problem* p, int n_inst, Layout& L)
     L.off_rec_count = take((size_t)2 * n_inst * sizeof(int));
     L.off_err = take((size_t)n_inst * sizeof(int));
     L.off_diag = take((size_t)4 * kDiagBlocks * sizeof(double));
+    L.off_body = take((size_t)n_inst * sizeof(BodyDev));
     // batched launches: descriptors and work tables (tile table sized for the
     // largest per-instance block count)
     int tile_units = 0;
@@ -488,6 +509,8 @@ static hipError_t enqueue_step(ii_lbm_handle* h, int par, hipStream_t s, bool ti
     }
     e = enqueue_interface(h, par, kModeFull, s, true);
     if (e == hipSuccess) e = enqueue_sweep(h, par, s, timed);
+    for (size_t j = 0; j < h->L.inst.size() && e == hipSuccess; j++)
+        if (h->L.inst[j].moving) e = launch_body(h->L.inst[j], h->P, par, s);
     return e;
 }
 
@@ -668,6 +691,7 @@ int ii_lbm_init(const ii_lbm_problem* p, int32_t n_inst, const double* const* X0
     P.rec_count = (int*)(h->ws + L.off_rec_count);
     P.err = (int*)(h->ws + L.off_err);
     P.diag = (double*)(h->ws + L.off_diag);
+    P.body = (BodyDev*)(h->ws + L.off_body);
 
     hipError_t e = hipSuccess;
     for (int j = 0; j < n_inst && e == hipSuccess; j++) {
@@ -689,14 +713,31 @@ int ii_lbm_init(const ii_lbm_problem* p, int32_t n_inst, const double* const* X0
             e = hipMemcpyAsync(P.X[1] + I.mk_off, X0[j], (size_t)I.n_markers * sizeof(double2),
                                hipMemcpyHostToDevice, h->stream);
     }
+    // Moving bodies start at their initial centre, at rest (a prescribed axis
+    // at its velocity of t = 0), in orientation 0.
+    {
+        std::vector<BodyDev> bodies(n_inst);
+        for (int j = 0; j < n_inst; j++) {
+            BodyDev& b = bodies[j];
+            memset(&b, 0, sizeof b);
+            b.c[0] = b.c0[0] = p[j].center[0];
+            b.c[1] = b.c0[1] = p[j].center[1];
+            for (int a = 0; a < 2; a++)
+                if (p[j].presc_umax[a] != 0.0) b.U[a] = b.Uprev[a] = -p[j].presc_umax[a];
+        }
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(P.body, bodies.data(), n_inst * sizeof(BodyDev),
+                               hipMemcpyHostToDevice, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    }
     // Several instances advance together through the batched launches; they
     // share storage precision, collision arithmetic, force mode and interface
-    // kind.
+    // kind; a moving body has a handle of its own.
     if (e == hipSuccess && n_inst > 1) {
         int iface = II_LBM_IF_NONE;
         for (int j = 0; j < n_inst; j++) {
             if (p[j].storage != p[0].storage || p[j].math != p[0].math ||
-                p[j].force_mode != p[0].force_mode) {
+                p[j].force_mode != p[0].force_mode || h->L.inst[j].moving) {
                 e = hipErrorInvalidValue;
                 break;
             }
@@ -1013,7 +1054,7 @@ int ii_lbm_state_size(ii_lbm_handle* h, int32_t inst, size_t* bytes)
     if (!h || !bytes || inst < 0 || inst >= (int)h->prob.size()) return II_LBM_EINVAL;
     const InstDev& I = h->L.inst[inst];
     *bytes = sizeof(int64_t) + (size_t)I.n_markers * sizeof(double2) +
-             (size_t)9 * I.plane * storage_bytes(I.storage);
+             (size_t)9 * I.plane * storage_bytes(I.storage) + (I.moving ? sizeof(BodyDev) : 0);
     return II_LBM_OK;
 }
 
@@ -1037,6 +1078,9 @@ int ii_lbm_save_state(ii_lbm_handle* h, int32_t inst, void* host_buf, size_t byt
     if (e == hipSuccess)
         e = hipMemcpy(b, (char*)h->P.lat[h->parity] + I.lat_off * eb, (size_t)9 * I.plane * eb,
                       hipMemcpyDeviceToHost);
+    b += (size_t)9 * I.plane * eb;
+    if (e == hipSuccess && I.moving)
+        e = hipMemcpy(b, h->P.body + I.inst, sizeof(BodyDev), hipMemcpyDeviceToHost);
     return hip_fail(h, e);
 }
 
@@ -1061,9 +1105,28 @@ int ii_lbm_load_state(ii_lbm_handle* h, int32_t inst, const void* host_buf, size
     if (e == hipSuccess)
         e = hipMemcpy((char*)h->P.lat[h->parity] + I.lat_off * eb, b, (size_t)9 * I.plane * eb,
                       hipMemcpyHostToDevice);
+    b += (size_t)9 * I.plane * eb;
+    if (e == hipSuccess && I.moving)
+        e = hipMemcpy(h->P.body + I.inst, b, sizeof(BodyDev), hipMemcpyHostToDevice);
     h->rec_valid = false;
     if (e == hipSuccess) e = prime(h);
     return hip_fail(h, e);
+}
+
+int ii_lbm_body(ii_lbm_handle* h, int32_t inst, double* out)
+{
+    if (!h || !out || inst < 0 || inst >= (int)h->prob.size()) return II_LBM_EINVAL;
+    const InstDev& I = h->L.inst[inst];
+    if (!I.moving) return II_LBM_EINVAL;
+    const int rc = sync_and_check(h);
+    if (rc) return rc;
+    BodyDev b;
+    const hipError_t e = hipMemcpy(&b, h->P.body + I.inst, sizeof b, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(h, e);
+    const double v[14] = {b.c[0], b.c[1], b.U[0], b.U[1], b.theta, b.W, b.F[0], b.F[1],
+                          b.T, b.a[0], b.a[1], b.wdot, (double)b.n, 0.0};
+    memcpy(out, v, sizeof v);
+    return II_LBM_OK;
 }
 
 int ii_lbm_cutlinks(ii_lbm_handle* h, int32_t inst, ii_lbm_link* out, int32_t cap, int32_t* count)
