@@ -14,7 +14,8 @@ and the FP64 CPU oracle timed on a bounded sample of the same workload.
 
 Other workloads (--workload): batch512, learned, cylinder, area (the
 elastic-membrane area comparison of Sec. 4.2 under the four force modes) and
-table1 (the normal-force circle of Sec. 4.1, II-LBM against IB-LBM).
+table1 (the normal-force circle of Sec. 4.1, II-LBM against IB-LBM) and viv (the
+freely vibrating cylinder of Sec. 4.5).
 """
 from __future__ import annotations
 
@@ -524,6 +525,105 @@ def bench_table1(args, B, W) -> int:
     return 0
 
 
+# Sec. 4.5: maximum transverse amplitude / D of the freely vibrating cylinder
+# (rho* = 8/pi, zeta = 0) for U_red = 3 .. 8.
+PAPER_VIV = {3.0: 0.075, 4.0: 0.551, 5.0: 0.520, 6.0: 0.459, 7.0: 0.370, 8.0: 0.084}
+
+
+def bench_viv(args, B, W) -> int:
+    """Vortex-induced vibration of a spring-mounted cylinder free across a
+    uniform stream (Sec. 4.5) for U_red = 3 .. 8: the body state is read every
+    `sample` steps (HIP graphs between the reads) and the amplitude is the
+    largest |y - y0| / D over the last 40 % of the run.  Then the sweep of the
+    channel, HIP-event timed."""
+    import numpy as np
+    import torch
+    math_ = W.MATH_FP64 if args.math == "fp64" else W.MATH_FP32
+    u_reds = [float(v) for v in args.viv_ured.split(",") if v.strip()]
+    rows, lu_all, t_all = [], 0, 0.0
+    sample = 100
+    n_samples = max(args.steps // sample, 10)
+    for ur in u_reds:
+        w = W.viv_cylinder_e4(args.viv_d, ur)
+        p = w.problem
+        p.math = math_
+        sim = B.Sim([p], [w.X0], device="cuda:0")
+        sim.set_graph(args.graph == "on")
+        ys = np.zeros(n_samples)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(n_samples):
+            sim.step(sample)
+            ys[k] = sim.body()["c"][1]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        D = w.meta["D"]
+        y = (ys - p.center[1]) / D
+        tail = y[int(0.6 * n_samples):]
+        lu = p.nx * p.ny * n_samples * sample
+        lu_all += lu
+        t_all += dt
+        rows.append({"u_red": ur, "A_max_over_D": float(np.abs(tail).max()),
+                     "A_rms_over_D": float(np.sqrt((tail ** 2).mean())),
+                     "paper": PAPER_VIV.get(ur), "steps": n_samples * sample,
+                     "mlups": round(lu / dt / 1e6, 1), "error_bits": sim.diag()["error_bits"],
+                     "history": [round(float(v), 5) for v in y[::max(1, n_samples // 60)]]})
+        print(f"[viv] U_red={ur:g}: A/D {rows[-1]['A_max_over_D']:.3f} (paper {PAPER_VIV.get(ur)}) "
+              f"{rows[-1]['mlups']} MLUPS", file=sys.stderr, flush=True)
+        sim.close()
+    w = W.viv_cylinder_e4(args.viv_d, 5.0)
+    w.problem.math = math_
+    sim = B.Sim([w.problem], [w.X0], device="cuda:0")
+    sim.step(20)
+    sim.sync()
+    sim.set_timing(True)
+    sim.step(200)
+    sim.sync()
+    ms, launches = sim.get_timing()
+    sim.set_timing(False)
+    avg = ms / 1e3 / max(launches, 1)
+    bpl = sim.sweep_bytes()
+    sim.close()
+    n_steps = sum(r["steps"] for r in rows)
+    out = {
+        "metric": "MLUPS & %HBM peak; learned 2x-coarse vs fine II-LBM time at <=1e-2 L2 err",
+        "value": round(lu_all / t_all / 1e6, 1) if rows else None, "unit": "MLUPS", "n_gpus": 1,
+        "steps": n_steps, "warmup": 0,
+        "ms_per_step": round(t_all * 1e3 / n_steps, 5) if rows else None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 storage / " + args.math + " collision", "data": "synthetic",
+        "config": {"workload": "viv_cylinder", "D": args.viv_d, "re": 100.0,
+                   "nx": w.problem.nx, "ny": w.problem.ny, "rows": rows},
+        "roofline": {"bound": "hbm", "kernel": f"k_sweep ({w.problem.nx}x{w.problem.ny})",
+                     "achieved": round(bpl / avg / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(bpl / avg / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                     "cache_resident": True, "bytes_per_launch": bpl,
+                     "avg_launch_us": round(avg * 1e6, 2), "timed_launches": launches},
+    }
+    if not args.no_cpu:
+        w = W.viv_cylinder_e4(8, 5.0)
+        out["cpu_baseline"] = cpu_baseline_body(w, 25 * args.cpu_steps)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def cpu_baseline_body(w, steps: int):
+    import oracle as O
+    p = O.make_problem(w.problem)
+    bp = O.body_params(w.problem)
+    b = O.new_body(p)
+    f = O.rest_state(p)
+    X = w.X0.copy()
+    O.run_body(p, bp, b, f, X, 1)
+    t0 = time.perf_counter()
+    O.run_body(p, bp, b, f, X, steps)
+    dt = time.perf_counter() - t0
+    return {"value": round(p.nx * p.ny * steps / dt / 1e6, 3), "unit": "MLUPS",
+            "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"{steps} FP64 oracle steps of the {p.nx}x{p.ny} (D = 8) vibrating cylinder "
+                      f"after 1 untimed step ({dt:.1f} s)"}
+
+
 def set_overlap(sim, B, args) -> None:
     modes = {"serial": B.OVERLAP_SERIAL, "full": B.OVERLAP_FULL,
              "interp_first": B.OVERLAP_INTERP_FIRST}
@@ -606,13 +706,16 @@ def main() -> int:
                          "(1e-3 bar)")
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--workload", choices=["membrane", "batch512", "learned", "cylinder", "area",
-                                           "table1"],
+                                           "table1", "viv"],
                     default="membrane",
                     help="membrane: one L x L membrane (the bench line); batch512: 512 uneven "
                          "membrane instances advanced together; learned: 200 coarse membranes "
                          "with the learned correction every step against their fine runs (both "
                          "reported in the design notes)")
     ap.add_argument("--re", type=float, default=100.0, help="Reynolds number of the cylinder workload")
+    ap.add_argument("--viv-ured", default="3,4,5,6,7,8",
+                    help="reduced velocities of the viv workload (Sec. 4.5)")
+    ap.add_argument("--viv-d", type=int, default=20, help="cylinder diameter of the viv workload")
     ap.add_argument("--table1-sizes", default="20,40,80,160",
                     help="circle diameters D of the table1 workload (Sec. 4.1)")
     ap.add_argument("--area-sizes", default="80,160,240",
@@ -630,7 +733,7 @@ def main() -> int:
                          "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.steps is None:
-        args.steps = {"batch512": 4000, "cylinder": 20000}.get(args.workload, 2000)
+        args.steps = {"batch512": 4000, "cylinder": 20000, "viv": 150000}.get(args.workload, 2000)
     if args.math is None:
         args.math = "fp32" if args.storage == "fp16" else "fp64"
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -661,6 +764,8 @@ def main() -> int:
         return bench_area(args, B, W)
     if args.workload == "table1":
         return bench_table1(args, B, W)
+    if args.workload == "viv":
+        return bench_viv(args, B, W)
     storage = W.STORE_FP16 if args.storage == "fp16" else W.STORE_FP32
     w = W.membrane_c3(L=args.size, storage=storage)
     p = w.problem

@@ -241,6 +241,28 @@ def normal_force_jump_state(w: Workload) -> np.ndarray:
     return np.ascontiguousarray(wt[:, None, None] * rho[None])
 
 
+def viv_cylinder_e4(D: int, u_red: float, force_mode: int = FORCE_II_LBM, re: float = 100.0,
+                    U: float = 0.05, storage: int = STORE_FP32) -> Workload:
+    """Vortex-induced vibration of a circular cylinder free to move across a
+    uniform stream (Sec. 4.5): domain [0, 40D] x [0, 20D], centre (10D, 10D),
+    uniform inflow U on the left, outflow on the right, the sides moving with
+    the stream; rho* = 8/pi, no damping, spring k = m (2 pi f_N)^2 with
+    U_red = U / (f_N D); MRT with nu = U D / Re.  Markers at most 1 lu apart."""
+    R = D / 2.0
+    n = int(math.ceil(math.pi * D - 1e-9))
+    rho_star = 8.0 / math.pi
+    m = rho_star * math.pi * R * R
+    fN = U / (u_red * D)
+    cx, cy = 10.0 * D, 10.0 * D
+    p = Problem(nx=40 * D, ny=20 * D, tau=0.5 + 3.0 * U * D / re, collision=MRT,
+                bc=(BC_INLET_UNIFORM, BC_OUTLET, BC_WALL, BC_WALL), u_max=U,
+                u_wall=(0.0, 0.0, U, U), interface=IF_RIGID, force_mode=force_mode, n_markers=n,
+                dX=math.pi * D / n, center=(cx, cy), radius=R, body_free=2, rho_star=rho_star,
+                spring=(0.0, m * (2.0 * math.pi * fN) ** 2), storage=storage,
+                name=f"viv{D}_ured{u_red:g}")
+    return Workload(p, circle_markers(cx, cy, R, n), 0, {"U": U, "D": D, "u_red": u_red, "re": re})
+
+
 def elastic_membrane_e2(L: int, force_mode: int = FORCE_II_LBM, storage: int = STORE_FP32) -> Workload:
     """Thin elastic membrane of Sec. 4.2: ellipse a = 0.35 L, b = 0.25^2/0.35 L
     centred in a walled L x L box, MRT, kappa_bar = kappa/(U^2 L) = 0.1,
