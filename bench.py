@@ -14,8 +14,9 @@ and the FP64 CPU oracle timed on a bounded sample of the same workload.
 
 Other workloads (--workload): batch512, learned, cylinder, area (the
 elastic-membrane area comparison of Sec. 4.2 under the four force modes) and
-table1 (the normal-force circle of Sec. 4.1, II-LBM against IB-LBM) and viv (the
-freely vibrating cylinder of Sec. 4.5).
+table1 (the normal-force circle of Sec. 4.1, II-LBM against IB-LBM), cyltables
+(uniform flow past a cylinder, Sec. 4.3) and viv (the freely vibrating cylinder
+of Sec. 4.5).
 """
 from __future__ import annotations
 
@@ -525,6 +526,134 @@ def bench_table1(args, B, W) -> int:
     return 0
 
 
+# Sec. 4.3, Tables 3 and 4 (II-LBM rows): C_D, R_l / D, separation angle
+# (deg) at Re = 20, 40; mean C_D, lift amplitude, St at Re = 100, 200.
+PAPER_TABLE3 = {(20.0, 20): (2.220, 1.000, 42.4), (20.0, 40): (2.195, 0.968, 43.4),
+                (20.0, 80): (2.189, 0.953, 44.3), (40.0, 20): (1.663, 2.481, 50.1),
+                (40.0, 40): (1.642, 2.380, 52.6), (40.0, 80): (1.632, 2.321, 53.1)}
+PAPER_TABLE4 = {(100.0, 20): (1.458, 0.357, 0.163), (100.0, 40): (1.436, 0.344, 0.167),
+                (100.0, 80): (1.417, 0.344, 0.169), (200.0, 20): (1.471, 0.654, 0.193),
+                (200.0, 40): (1.442, 0.718, 0.197), (200.0, 80): (1.419, 0.713, 0.199)}
+
+
+def _wake_metrics(ux, uy, cx, cy, R, D):
+    """Recirculation length behind the cylinder (first zero of u_x on the
+    centre line downstream of the rear point, over D) and the separation angle
+    (from the rear stagnation point, where the tangential velocity one lattice
+    unit outside the surface turns from the bubble's flow toward the
+    separation point to the outer flow toward the rear, bilinear), in degrees."""
+    import numpy as np
+    row = ux[int(round(cy)), :]
+    x0 = cx + R
+    xs = np.arange(int(np.ceil(x0)), ux.shape[1] - 1)
+    rl = None
+    for a, b in zip(xs[:-1], xs[1:]):
+        if row[a] < 0.0 <= row[b]:
+            rl = (a + (0.0 - row[a]) / (row[b] - row[a]) - x0) / D
+            break
+
+    def bil(f, x, y):
+        i, j = int(np.floor(x)), int(np.floor(y))
+        tx, ty = x - i, y - j
+        return ((1 - tx) * (1 - ty) * f[j, i] + tx * (1 - ty) * f[j, i + 1]
+                + (1 - tx) * ty * f[j + 1, i] + tx * ty * f[j + 1, i + 1])
+
+    r = R + 1.0
+    ang = None
+    prev = None
+    for deg in np.arange(0.5, 120.0, 0.25):
+        th = np.radians(deg)
+        x, y = cx + r * np.cos(th), cy + r * np.sin(th)
+        ut = -np.sin(th) * bil(ux, x, y) + np.cos(th) * bil(uy, x, y)
+        if prev is not None and prev[1] > 0.0 >= ut:
+            ang = prev[0] + (deg - prev[0]) * (0.0 - prev[1]) / (ut - prev[1])
+            break
+        prev = (deg, ut)
+    return rl, ang
+
+
+def bench_cylinder_tables(args, B, W) -> int:
+    """Uniform flow around a fixed cylinder (Sec. 4.3, Tables 3 and 4): for
+    each diameter and Re, steps in HIP-graph chunks with the force read after
+    every chunk; steady cases report C_D and the wake's recirculation length
+    and separation angle at the end, unsteady ones the mean C_D, the lift
+    amplitude and the Strouhal number over the second half of the run: the frequency of the lift spectrum's
+    shedding peak and the amplitude of the sinusoid fitted at it."""
+    import numpy as np
+    import torch
+    math_ = W.MATH_FP64 if args.math == "fp64" else W.MATH_FP32
+    sizes = [int(v) for v in args.cyl_sizes.split(",") if v.strip()]
+    rows, lu_all, t_all = [], 0, 0.0
+    for D in sizes:
+        for re in (20.0, 40.0, 100.0, 200.0):
+            w = W.cylinder_uniform_e3(D, re)
+            p = w.problem
+            p.math = math_
+            U = w.meta["U"]
+            # steady cases: 120 D/U; unsteady: 400 D/U (the second half sampled)
+            n_flow = 120.0 if re < 50 else 400.0
+            chunk = max(1, int(round(D / U / 20.0)))
+            n_chunks = int(round(n_flow * D / U / chunk))
+            sim = B.Sim([p], [w.X0], device="cuda:0")
+            sim.set_graph(args.graph == "on")
+            F = np.zeros((n_chunks, 2))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(n_chunks):
+                sim.step(chunk)
+                F[k] = sim.diag()["force"]
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            c = 2.0 / (U * U * D)
+            cd, cl = F[:, 0] * c, F[:, 1] * c
+            row = {"D": D, "re": re, "steps": n_chunks * chunk, "mlups": round(p.nx * p.ny * n_chunks * chunk / dt / 1e6, 1)}
+            if re < 50:
+                ux, uy = sim.fields(B.F_UX | B.F_UY)
+                rl, ang = _wake_metrics(ux, uy, p.center[0], p.center[1], p.radius, D)
+                row.update({"C_D": float(cd[-1]), "R_l_over_D": rl, "sep_angle_deg": ang,
+                            "C_D_drift_last_10pct": float(abs(cd[-1] - cd[int(0.9 * n_chunks)])),
+                            "paper": list(PAPER_TABLE3.get((re, D), ())) or None})
+            else:
+                # the shedding peak of the lift spectrum over the second half
+                # (a Hann window, the peak refined by a parabola through the
+                # log magnitudes): St = f D / U, amplitude from the peak height
+                h = n_chunks // 2
+                cl2 = cl[h:] - cl[h:].mean()
+                win = np.hanning(len(cl2))
+                spec = np.abs(np.fft.rfft(cl2 * win))
+                k = 1 + int(np.argmax(spec[1:]))
+                off = 0.0
+                if 1 <= k < len(spec) - 1:
+                    a, b, c2 = np.log(spec[k - 1:k + 2] + 1e-300)
+                    off = 0.5 * (a - c2) / (a - 2 * b + c2)
+                freq = (k + off) / (len(cl2) * chunk)
+                # amplitude of the least-squares sinusoid at that frequency
+                ph = np.exp(-2j * np.pi * freq * chunk * np.arange(len(cl2)))
+                amp = 2.0 * abs((cl2 * ph).sum()) / len(cl2)
+                row.update({"C_D_mean": float(cd[h:].mean()), "C_L_amp": float(amp),
+                            "C_L_maxmin_half": float(0.5 * (cl[h:].max() - cl[h:].min())),
+                            "St": float(freq * D / U), "paper": list(PAPER_TABLE4.get((re, D), ())) or None,
+                            "C_L_history": [round(float(v), 4) for v in cl[h::max(1, (n_chunks - h) // 200)]]})
+            lu_all += p.nx * p.ny * n_chunks * chunk
+            t_all += dt
+            rows.append(row)
+            print(f"[cyl] D={D} Re={re:g}: {json.dumps({k: v for k, v in row.items() if k not in ('D', 're')})}",
+                  file=sys.stderr, flush=True)
+            sim.close()
+    n_steps = sum(r["steps"] for r in rows)
+    out = {
+        "metric": "MLUPS & %HBM peak; learned 2x-coarse vs fine II-LBM time at <=1e-2 L2 err",
+        "value": round(lu_all / t_all / 1e6, 1) if rows else None, "unit": "MLUPS", "n_gpus": 1,
+        "steps": n_steps, "warmup": 0,
+        "ms_per_step": round(t_all * 1e3 / n_steps, 5) if rows else None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 storage / " + args.math + " collision", "data": "synthetic",
+        "config": {"workload": "cylinder_uniform_tables34", "sizes": args.cyl_sizes, "rows": rows},
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 # Sec. 4.5: maximum transverse amplitude / D of the freely vibrating cylinder
 # (rho* = 8/pi, zeta = 0) for U_red = 3 .. 8.
 PAPER_VIV = {3.0: 0.075, 4.0: 0.551, 5.0: 0.520, 6.0: 0.459, 7.0: 0.370, 8.0: 0.084}
@@ -706,13 +835,15 @@ def main() -> int:
                          "(1e-3 bar)")
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--workload", choices=["membrane", "batch512", "learned", "cylinder", "area",
-                                           "table1", "viv"],
+                                           "table1", "viv", "cyltables"],
                     default="membrane",
                     help="membrane: one L x L membrane (the bench line); batch512: 512 uneven "
                          "membrane instances advanced together; learned: 200 coarse membranes "
                          "with the learned correction every step against their fine runs (both "
                          "reported in the design notes)")
     ap.add_argument("--re", type=float, default=100.0, help="Reynolds number of the cylinder workload")
+    ap.add_argument("--cyl-sizes", default="20,40",
+                    help="cylinder diameters D of the cyltables workload (Sec. 4.3; 80 is the paper's finest)")
     ap.add_argument("--viv-ured", default="3,4,5,6,7,8",
                     help="reduced velocities of the viv workload (Sec. 4.5)")
     ap.add_argument("--viv-d", type=int, default=20, help="cylinder diameter of the viv workload")
@@ -766,6 +897,8 @@ def main() -> int:
         return bench_table1(args, B, W)
     if args.workload == "viv":
         return bench_viv(args, B, W)
+    if args.workload == "cyltables":
+        return bench_cylinder_tables(args, B, W)
     storage = W.STORE_FP16 if args.storage == "fp16" else W.STORE_FP32
     w = W.membrane_c3(L=args.size, storage=storage)
     p = w.problem

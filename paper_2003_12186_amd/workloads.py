@@ -241,6 +241,24 @@ def normal_force_jump_state(w: Workload) -> np.ndarray:
     return np.ascontiguousarray(wt[:, None, None] * rho[None])
 
 
+def cylinder_uniform_e3(D: int, re: float, storage: int = STORE_FP32) -> Workload:
+    """Uniform flow around a fixed circular cylinder (Sec. 4.3): domain
+    [0, 40D] x [0, 20D], centre (10D, 10D), uniform inflow U on the left,
+    outflow on the right, the sides moving with the stream (freestream); MRT
+    with the viscosity the paper gives per Re (0.1, 0.05, 0.02, 0.01 for
+    Re = 20, 40, 100, 200) and U = Re nu / D.  Markers at most 1 lu apart."""
+    nu = {20.0: 0.1, 40.0: 0.05, 100.0: 0.02, 200.0: 0.01}[float(re)]
+    U = re * nu / D
+    R = D / 2.0
+    n = int(math.ceil(math.pi * D - 1e-9))
+    cx = cy = 10.0 * D
+    p = Problem(nx=40 * D, ny=20 * D, tau=0.5 + 3.0 * nu, collision=MRT,
+                bc=(BC_INLET_UNIFORM, BC_OUTLET, BC_WALL, BC_WALL), u_max=U,
+                u_wall=(0.0, 0.0, U, U), interface=IF_RIGID, n_markers=n, dX=math.pi * D / n,
+                center=(cx, cy), radius=R, storage=storage, name=f"cyl_uniform{D}_Re{re:g}")
+    return Workload(p, circle_markers(cx, cy, R, n), 0, {"U": U, "D": D, "re": re, "nu": nu})
+
+
 def viv_cylinder_e4(D: int, u_red: float, force_mode: int = FORCE_II_LBM, re: float = 100.0,
                     U: float = 0.05, storage: int = STORE_FP32) -> Workload:
     """Vortex-induced vibration of a circular cylinder free to move across a
