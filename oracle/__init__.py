@@ -41,7 +41,8 @@ class Problem(C.Structure):
                 ("interface", C.c_int32), ("force_mode", C.c_int32), ("n_markers", C.c_int32),
                 ("kappa", C.c_double), ("dX", C.c_double), ("cx", C.c_double),
                 ("cy", C.c_double), ("radius", C.c_double), ("f_normal", C.c_double),
-                ("ud", C.c_double * 3), ("theta", C.c_double)]
+                ("ud", C.c_double * 3), ("theta", C.c_double), ("geometry", C.c_int32),
+                ("pad2", C.c_int32)]
 
 
 class BodyParams(C.Structure):
@@ -107,6 +108,8 @@ def lib():
             "or_sizeof_problem": (C.c_int, []),
             "or_num_threads": (C.c_int, []),
             "or_step_body": (C.c_int, [P, C.POINTER(BodyParams), C.POINTER(Body), d, d]),
+            "or_spline": (None, [P, d, d]),
+            "or_cutlinks_spline": (C.c_int, [P, d, d, d, C.c_int]),
             "or_sizeof_body": (C.c_int, []),
             "or_sizeof_body_params": (C.c_int, []),
         }
@@ -146,6 +149,7 @@ def make_problem(w) -> Problem:
     p.cx, p.cy = float(w.center[0]), float(w.center[1])
     p.radius = float(w.radius)
     p.f_normal = float(getattr(w, "f_normal", 0.0))
+    p.geometry = int(getattr(w, "geometry", 0))
     return p
 
 
@@ -231,6 +235,24 @@ def cutlinks(p: Problem, X, jp=None) -> np.ndarray:
     cap = 64 * N + 4096
     rec = np.zeros(cap, dtype=LINK_DTYPE)
     n = lib().or_cutlinks(C.byref(p), _ptr(X), _ptr(jp), _ptr(rec), cap)
+    assert n <= cap
+    return rec[:n].copy()
+
+
+def spline_second_derivs(p: Problem, X) -> np.ndarray:
+    """M_k of the periodic cubic spline through the markers (reading R27)."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    M = np.zeros_like(X)
+    lib().or_spline(C.byref(p), _ptr(X), _ptr(M))
+    return M
+
+
+def cutlinks_spline(p: Problem, X, G) -> np.ndarray:
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    cap = 64 * X.shape[0] + 4096
+    rec = np.zeros(cap, dtype=LINK_DTYPE)
+    n = lib().or_cutlinks_spline(C.byref(p), _ptr(X), _ptr(G), _ptr(rec), cap)
     assert n <= cap
     return rec[:n].copy()
 

@@ -36,6 +36,10 @@
  *  R11 marker velocity from u = sum e_i f_i of the pre-collision field;
  *  R12 non-equilibrium extrapolation on non-periodic sides, corners as walls
  *      (a uniform inflow side takes u_b = (u_max, 0));
+ *  R27 (geometry 1) the membrane is the periodic cubic spline through the
+ *      markers in the marker index; crossings are the roots of a cubic found
+ *      by a fixed bisection, [[p]] at a crossing from the spline normal and
+ *      |dX/ds| with G linear between the markers;
  *  R24 under Guo's force term (the comparison method of Sec. 2.2.2) the
  *      collision uses the compressible equilibrium and the velocity
  *      u = (sum e_i f_i + g/2) / rho the paper gives with it, g the whole
@@ -83,6 +87,8 @@ typedef struct {
      * orientation theta (marker k sits at angle theta + 2 pi k / N) */
     double ud[3];
     double theta;
+    int32_t geometry;      /* membrane representation: 0 polygon (R10), 1 cubic spline (R27) */
+    int32_t pad2;
 } or_problem;
 
 static int has_jumps(const or_problem *p) { return p->force_mode == OR_II_LBM || p->force_mode == OR_II_LBM_GUO; }
@@ -338,6 +344,141 @@ void or_spread(const or_problem *p, const double *X, const double *V, double *gx
 }
 
 /* ------------------------------------------------------------------------ */
+/* Periodic cubic spline through the markers (reading R27; Sec. 3.2 names a   */
+/* cubic spline for flexible interfaces).                                    */
+/* ------------------------------------------------------------------------ */
+
+/* Second derivatives M_k of the periodic cubic spline in the marker index:
+ * M_{k-1} + 4 M_k + M_{k+1} = 6 (X_{k+1} - 2 X_k + X_{k-1}), one component at a
+ * time (stride 2), solved as a cyclic tridiagonal system (Sherman-Morrison
+ * around the Thomas algorithm). */
+static void spline_second_derivs(int N, const double *X, int comp, double *M)
+{
+    double *r = malloc(N * sizeof(double)), *y = malloc(N * sizeof(double));
+    double *z = malloc(N * sizeof(double)), *cp = malloc(N * sizeof(double));
+    double *u = calloc(N, sizeof(double));
+    for (int k = 0; k < N; k++) {
+        int km = (k + N - 1) % N, kp = (k + 1) % N;
+        r[k] = 6.0 * (X[2 * kp + comp] - 2.0 * X[2 * k + comp] + X[2 * km + comp]);
+    }
+    /* A = T + u v^T with gamma = -4: T_00 = 4 - gamma, T_nn = 4 - 1/gamma,
+     * u = (gamma, 0, .., 0, 1), v = (1, 0, .., 0, 1/gamma) */
+    double gamma = -4.0;
+    u[0] = gamma; u[N - 1] = 1.0;
+    for (int pass = 0; pass < 2; pass++) {
+        const double *rhs = pass == 0 ? r : u;
+        double *out = pass == 0 ? y : z;
+        /* Thomas on the tridiagonal T (sub = super = 1) */
+        double b0 = 4.0 - gamma;
+        cp[0] = 1.0 / b0;
+        out[0] = rhs[0] / b0;
+        for (int k = 1; k < N; k++) {
+            double bk = (k == N - 1) ? 4.0 - 1.0 / gamma : 4.0;
+            double den = bk - cp[k - 1];
+            cp[k] = 1.0 / den;
+            out[k] = (rhs[k] - out[k - 1]) / den;
+        }
+        for (int k = N - 2; k >= 0; k--) out[k] -= cp[k] * out[k + 1];
+    }
+    double vy = y[0] + y[N - 1] / gamma, vz = z[0] + z[N - 1] / gamma;
+    for (int k = 0; k < N; k++) M[2 * k + comp] = y[k] - vy / (1.0 + vz) * z[k];
+    free(r); free(y); free(z); free(cp); free(u);
+}
+
+/* Segment k of the spline, S(t) = a + b t + c t^2 + d t^3 on t in [0, 1]:
+ * a = X_k, b = X_{k+1} - X_k - (2 M_k + M_{k+1}) / 6, c = M_k / 2,
+ * d = (M_{k+1} - M_k) / 6; coef[8] = (ax, ay, bx, by, cx, cy, dx, dy). */
+static void spline_segment(int N, const double *X, const double *M, int k, double *coef)
+{
+    int kp = (k + 1) % N;
+    for (int c = 0; c < 2; c++) {
+        coef[0 + c] = X[2 * k + c];
+        coef[2 + c] = X[2 * kp + c] - X[2 * k + c] - (2.0 * M[2 * k + c] + M[2 * kp + c]) / 6.0;
+        coef[4 + c] = 0.5 * M[2 * k + c];
+        coef[6 + c] = (M[2 * kp + c] - M[2 * k + c]) / 6.0;
+    }
+}
+
+void or_spline(const or_problem *p, const double *X, double *M)
+{
+    spline_second_derivs(p->n_markers, X, 0, M);
+    spline_second_derivs(p->n_markers, X, 1, M);
+}
+
+static double cubic_at(const double F[4], double t) { return ((F[3] * t + F[2]) * t + F[1]) * t + F[0]; }
+
+/* Crossings of the link P -> P + e with spline segment coef (reading R27).
+ * f(t) = e x (S(t) - P) is a cubic; [0, 1] is split at the critical points
+ * inside it, each piece with a sign change of f (f >= 0 counts as positive;
+ * f(1) is e x (X_{k+1} - P) as the next segment's f(0)) holds one root,
+ * found by 64 bisections.  A root at link parameter q in [0, 1) is a
+ * crossing; sigma = +1 when f rises through it (P on the interior side).
+ * Writes up to 3 (t, q, sigma); returns their count. */
+static int spline_link_crossings(const double *coef, const double *Xnext, double px, double py,
+                                 int ex, int ey, double *ts, double *qs, int *sg)
+{
+    double F[4];
+    F[0] = ex * (coef[1] - py) - ey * (coef[0] - px);
+    F[1] = ex * coef[3] - ey * coef[2];
+    F[2] = ex * coef[5] - ey * coef[4];
+    F[3] = ex * coef[7] - ey * coef[6];
+    double f1 = ex * (Xnext[1] - py) - ey * (Xnext[0] - px);
+    /* critical points: 3 F3 t^2 + 2 F2 t + F1 = 0 */
+    double br[4];
+    int nb = 0;
+    br[nb++] = 0.0;
+    double A = 3.0 * F[3], Bq = 2.0 * F[2], Cq = F[1];
+    double r1 = -1.0, r2 = -1.0;
+    if (A == 0.0) {
+        if (Bq != 0.0) r1 = -Cq / Bq;
+    } else {
+        double disc = Bq * Bq - 4.0 * A * Cq;
+        if (disc > 0.0) {
+            double sq = sqrt(disc);
+            double qq = Bq >= 0.0 ? -0.5 * (Bq + sq) : -0.5 * (Bq - sq);
+            r1 = qq / A;
+            r2 = qq != 0.0 ? Cq / qq : -1.0;
+            if (r2 < r1) { double tt = r1; r1 = r2; r2 = tt; }
+        }
+    }
+    if (r1 > 0.0 && r1 < 1.0) br[nb++] = r1;
+    if (r2 > 0.0 && r2 < 1.0 && r2 != r1) br[nb++] = r2;
+    br[nb] = 1.0;
+    int n = 0;
+    double ee = (double)(ex * ex + ey * ey);
+    for (int j = 0; j < nb; j++) {
+        double lo = br[j], hi = br[j + 1];
+        double flo = cubic_at(F, lo), fhi = (j == nb - 1) ? f1 : cubic_at(F, hi);
+        int slo = flo >= 0.0, shi = fhi >= 0.0;
+        if (slo == shi) continue;
+        for (int it = 0; it < 64; it++) {
+            double mid = 0.5 * (lo + hi);
+            if ((cubic_at(F, mid) >= 0.0) == slo) lo = mid; else hi = mid;
+        }
+        double t = 0.5 * (lo + hi);
+        double sx = ((coef[6] * t + coef[4]) * t + coef[2]) * t + coef[0];
+        double sy = ((coef[7] * t + coef[5]) * t + coef[3]) * t + coef[1];
+        double q = ((sx - px) * ex + (sy - py) * ey) / ee;
+        if (!(q >= 0.0 && q < 1.0)) continue;
+        ts[n] = t; qs[n] = q; sg[n] = slo ? -1 : 1;
+        n++;
+    }
+    return n;
+}
+
+/* [[p]] at spline parameter t of segment k (reading R27): G linear between
+ * the markers, n and |dX/ds| from S'(t): [[p]] = dX (G x T) / |T|^2 with
+ * G x T = G_x T_y - G_y T_x. */
+static double spline_jump(const or_problem *p, const double *coef, const double *G, int k, double t)
+{
+    int kp = (k + 1) % p->n_markers;
+    double Gx = (1.0 - t) * G[2 * k] + t * G[2 * kp], Gy = (1.0 - t) * G[2 * k + 1] + t * G[2 * kp + 1];
+    double Tx = (3.0 * coef[6] * t + 2.0 * coef[4]) * t + coef[2];
+    double Ty = (3.0 * coef[7] * t + 2.0 * coef[5]) * t + coef[3];
+    return p->dX * (Gx * Ty - Gy * Tx) / (Tx * Tx + Ty * Ty);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Marker force and interface geometry.                                      */
 /* ------------------------------------------------------------------------ */
 
@@ -352,6 +493,11 @@ void or_marker_forces(const or_problem *p, const double *X, const double *U,
                       double *G, double *nrm, double *J, double *jp, double *Gt)
 {
     int N = p->n_markers;
+    double *Msp = NULL;
+    if (p->interface == OR_IF_MEMBRANE && p->geometry == 1) {
+        Msp = malloc(2 * N * sizeof(double));
+        or_spline(p, X, Msp);
+    }
     for (int k = 0; k < N; k++) {
         int km = (k + N - 1) % N, kp = (k + 1) % N;
         double gx, gy, nx_, ny_, jac;
@@ -359,13 +505,23 @@ void or_marker_forces(const or_problem *p, const double *X, const double *U,
             double d2 = p->dX * p->dX;
             gx = p->kappa * (X[2 * kp] - 2.0 * X[2 * k] + X[2 * km]) / d2;
             gy = p->kappa * (X[2 * kp + 1] - 2.0 * X[2 * k + 1] + X[2 * km + 1]) / d2;
-            double tx = X[2 * kp] - X[2 * km], ty = X[2 * kp + 1] - X[2 * km + 1];
-            double tl = sqrt(tx * tx + ty * ty);
-            nx_ = ty / tl;
-            ny_ = -tx / tl;
-            double lp = hypot(X[2 * kp] - X[2 * k], X[2 * kp + 1] - X[2 * k + 1]);
-            double lm = hypot(X[2 * k] - X[2 * km], X[2 * k + 1] - X[2 * km + 1]);
-            jac = (lp + lm) / (2.0 * p->dX);
+            if (p->geometry == 1) {
+                /* spline tangent at the knot, T = S_k'(0) (reading R27) */
+                double tx = X[2 * kp] - X[2 * k] - (2.0 * Msp[2 * k] + Msp[2 * kp]) / 6.0;
+                double ty = X[2 * kp + 1] - X[2 * k + 1] - (2.0 * Msp[2 * k + 1] + Msp[2 * kp + 1]) / 6.0;
+                double tl = sqrt(tx * tx + ty * ty);
+                nx_ = ty / tl;
+                ny_ = -tx / tl;
+                jac = tl / p->dX;
+            } else {
+                double tx = X[2 * kp] - X[2 * km], ty = X[2 * kp + 1] - X[2 * km + 1];
+                double tl = sqrt(tx * tx + ty * ty);
+                nx_ = ty / tl;
+                ny_ = -tx / tl;
+                double lp = hypot(X[2 * kp] - X[2 * k], X[2 * kp + 1] - X[2 * k + 1]);
+                double lm = hypot(X[2 * k] - X[2 * km], X[2 * k + 1] - X[2 * km + 1]);
+                jac = (lp + lm) / (2.0 * p->dX);
+            }
         } else if (p->interface == OR_IF_NORMAL) {
             /* a uniform normal force G = F n on a fixed circle (Sec. 4.1) */
             nx_ = (X[2 * k] - p->cx) / p->radius;
@@ -389,6 +545,7 @@ void or_marker_forces(const or_problem *p, const double *X, const double *U,
         Gt[2 * k] = gx - gn * nx_;
         Gt[2 * k + 1] = gy - gn * ny_;
     }
+    free(Msp);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -477,6 +634,51 @@ static int cutlinks_membrane(const or_problem *p, const double *X, const double 
                     n++;
                 }
     }
+    return n;
+}
+
+/* Every crossing of every link with the spline (reading R27), segment by
+ * segment; the source nodes tested are those within one lattice spacing of
+ * the bounding box of the segment's Bezier control points (the segment lies
+ * in their hull).  theta is the spline parameter t of the crossing. */
+int or_cutlinks_spline(const or_problem *p, const double *X, const double *G, or_link *rec, int cap)
+{
+    int N = p->n_markers, n = 0;
+    double *M = malloc(2 * N * sizeof(double));
+    or_spline(p, X, M);
+    for (int k = 0; k < N; k++) {
+        int kp = (k + 1) % N;
+        double cf[8];
+        spline_segment(N, X, M, k, cf);
+        double hx[4], hy[4];
+        hx[0] = cf[0]; hy[0] = cf[1];
+        hx[1] = cf[0] + cf[2] / 3.0; hy[1] = cf[1] + cf[3] / 3.0;
+        double t1x = cf[2] + 2.0 * cf[4] + 3.0 * cf[6], t1y = cf[3] + 2.0 * cf[5] + 3.0 * cf[7];
+        hx[3] = X[2 * kp]; hy[3] = X[2 * kp + 1];
+        hx[2] = hx[3] - t1x / 3.0; hy[2] = hy[3] - t1y / 3.0;
+        double xmin = hx[0], xmax = hx[0], ymin = hy[0], ymax = hy[0];
+        for (int j = 1; j < 4; j++) {
+            xmin = fmin(xmin, hx[j]); xmax = fmax(xmax, hx[j]);
+            ymin = fmin(ymin, hy[j]); ymax = fmax(ymax, hy[j]);
+        }
+        for (int y = (int)floor(ymin) - 1; y <= (int)ceil(ymax) + 1; y++)
+            for (int x = (int)floor(xmin) - 1; x <= (int)ceil(xmax) + 1; x++)
+                for (int i = 1; i < 9; i++) {
+                    double ts[3], qs[3];
+                    int sg[3];
+                    int c = spline_link_crossings(cf, &X[2 * kp], x, y, EX[i], EY[i], ts, qs, sg);
+                    for (int j = 0; j < c; j++) {
+                        if (n < cap) {
+                            or_link *r = &rec[n];
+                            r->x = x; r->y = y; r->dir = i; r->sigma = sg[j]; r->seg = k; r->pad = 0;
+                            r->q = qs[j]; r->theta = ts[j];
+                            r->jp = spline_jump(p, cf, G, k, ts[j]);
+                        }
+                        n++;
+                    }
+                }
+    }
+    free(M);
     return n;
 }
 
@@ -708,7 +910,10 @@ int or_step(const or_problem *p, double *f, double *X, or_step_out *out)
         if (has_jumps(p)) {
             int cap = 64 * N + 4096;
             links = calloc(cap, sizeof(or_link));
-            nl = or_cutlinks(p, X, jp, links, cap);
+            if (p->interface == OR_IF_MEMBRANE && p->geometry == 1)
+                nl = or_cutlinks_spline(p, X, G, links, cap);
+            else
+                nl = or_cutlinks(p, X, jp, links, cap);
             if (nl > cap) nl = cap;
             for (int l = 0; l < nl; l++) {
                 const or_link *r = &links[l];

@@ -102,6 +102,7 @@ BC_PERIODIC, BC_WALL, BC_INLET, BC_OUTLET, BC_INLET_UNIFORM = 0, 1, 2, 3, 4
 IF_NONE, IF_MEMBRANE, IF_RIGID, IF_NORMAL = 0, 1, 2, 3
 FORCE_II_LBM, FORCE_IB_LBM, FORCE_IB_LBM_GUO, FORCE_II_LBM_GUO = 0, 1, 2, 3
 STORE_FP32, STORE_FP16 = 0, 1
+GEOM_POLYGON, GEOM_SPLINE = 0, 1
 MATH_FP32, MATH_FP64 = 0, 1
 
 # D2Q9 MRT relaxation rates printed in Sec. 2.2.1 for the non-conserved moments
@@ -128,6 +129,7 @@ class Problem:
     center: Sequence[float] = (0.0, 0.0)      # rigid circle centre
     radius: float = 0.0                       # rigid circle radius
     f_normal: float = 0.0                     # prescribed normal force per unit length (IF_NORMAL)
+    geometry: int = 0                         # membrane: 0 polygon through the markers, 1 cubic spline
     body_free: int = 0                        # moving circle: bit 0 x, bit 1 y, bit 2 rotation free
     rho_star: float = 1.0                     # density ratio rho_s / rho_f of the body
     spring: Sequence[float] = (0.0, 0.0)      # k_s per axis, about the initial centre
