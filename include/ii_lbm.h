@@ -101,6 +101,13 @@ enum { II_LBM_MATH_FP32 = 0, II_LBM_MATH_FP64 = 1 };
  *  kappa, dX    spring constant and marker spacing Delta X (> 0, <= 2).
  *  center, radius  the circle (RIGID and NORMAL).
  *  f_normal     F of the NORMAL interface.
+ *  geometry     MEMBRANE representation: 0 the closed polygon through the
+ *               markers (exact integer crossing tests), 1 the periodic cubic
+ *               spline through them (Sec. 3.2 names a cubic spline for
+ *               flexible interfaces): normals and |dX/ds| from the spline,
+ *               crossings as roots of a cubic per link and segment, [[p]] at
+ *               each crossing from the spline normal with G linear between the
+ *               markers.  One instance per handle.
  *  body_free, rho_star, spring, damping, presc_amp, presc_umax
  *               a moving RIGID circle (Sec. 2.3; one instance per handle):
  *               body_free bit 0 / 1 / 2 frees x / y / rotation; rho_star is
@@ -147,6 +154,7 @@ typedef struct ii_lbm_problem {
     double damping[2];
     double presc_amp[2];
     double presc_umax[2];
+    int32_t geometry;
 } ii_lbm_problem;
 
 /* One cut link (see ii_lbm_cutlinks for which step): the link from source

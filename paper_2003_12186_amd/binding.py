@@ -32,7 +32,8 @@ class Problem(C.Structure):
                 ("radius", C.c_double), ("storage", C.c_int32), ("fp16_log2_scale", C.c_int32),
                 ("math", C.c_int32), ("f_normal", C.c_double), ("body_free", C.c_int32),
                 ("rho_star", C.c_double), ("spring", C.c_double * 2), ("damping", C.c_double * 2),
-                ("presc_amp", C.c_double * 2), ("presc_umax", C.c_double * 2)]
+                ("presc_amp", C.c_double * 2), ("presc_umax", C.c_double * 2),
+                ("geometry", C.c_int32)]
 
 
 class Link(C.Structure):
@@ -149,6 +150,7 @@ def make_problem(w) -> Problem:
     p.fp16_log2_scale = int(getattr(w, "fp16_log2_scale", 0))
     p.math = int(getattr(w, "math", 0))
     p.f_normal = float(getattr(w, "f_normal", 0.0))
+    p.geometry = int(getattr(w, "geometry", 0))
     p.body_free = int(getattr(w, "body_free", 0))
     p.rho_star = float(getattr(w, "rho_star", 1.0))
     for a in range(2):

@@ -72,6 +72,9 @@ struct InstDev {
     float scale, inv_scale;  // FP16: value = stored * scale
     double kappa, dX, cx, cy, radius;
     double f_normal;      // prescribed normal force per unit length (NORMAL circle)
+    int geometry;         // membrane: 0 polygon through the markers, 1 cubic spline
+    int spl_periodic;     // spline taps: 1 = periodic sum over all N, 0 = |j| <= 32
+    int tap_off;          // offset of this instance's taps
     int moving;           // a moving rigid circle (body state on the device)
     int body_free;        // bit 0 x, bit 1 y, bit 2 rotation
     double rho_star, spring[2], damping[2], presc_amp[2], presc_umax[2];
@@ -110,6 +113,8 @@ struct DevPtrs {
     int* err;              // [n_inst] error bits
     double* diag;          // reduction partials
     BodyDev* body;         // [n_inst] moving-body states
+    double2* M;            // spline second derivatives per marker
+    const double* spline_taps;
 };
 
 // ---------------------------------------------------------------------------
@@ -546,6 +551,7 @@ hipError_t launch_slot_reset_batch(const Batch& b, int n_inst, const DevPtrs& P,
 hipError_t launch_tiles(const InstDev& I, const DevPtrs& P, int parity, bool records, hipStream_t s);
 hipError_t launch_fill_ints(int* p, long long n, int value, hipStream_t s);
 hipError_t launch_body(const InstDev& I, const DevPtrs& P, int par, hipStream_t s);
+hipError_t launch_spline(const InstDev& I, const DevPtrs& P, int par, hipStream_t s);
 hipError_t launch_markers_batch(const Batch& b, const DevPtrs& P, const void* A, int par, int mode,
                                 hipStream_t s);
 hipError_t launch_tiles_batch(const Batch& b, const DevPtrs& P, int parity, bool records,

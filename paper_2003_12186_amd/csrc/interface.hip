@@ -159,15 +159,26 @@ __device__ __forceinline__ void markers_body(const InstDev& I, const DevPtrs& P,
             const double d2 = I.dX * I.dX;
             gx = I.kappa * (Xp.x - 2.0 * Xk.x + Xm.x) / d2;
             gy = I.kappa * (Xp.y - 2.0 * Xk.y + Xm.y) / d2;
-            // outward normal of the counter-clockwise curve, from the central chord
-            const double tx = Xp.x - Xm.x, ty = Xp.y - Xm.y;
-            const double tl = sqrt(tx * tx + ty * ty);
-            nx_ = ty / tl;
-            ny_ = -tx / tl;
-            // |dX/ds|: mean length of the two chords at the marker over Delta X
-            const double lp = hypot(Xp.x - Xk.x, Xp.y - Xk.y);
-            const double lm = hypot(Xk.x - Xm.x, Xk.y - Xm.y);
-            jac = (lp + lm) / (2.0 * I.dX);
+            if (I.geometry == 1) {
+                // spline tangent at the knot, T = S_k'(0), its normal and |T| / dX
+                const double2 Mk = P.M[m], Mp = P.M[I.mk_off + kp];
+                const double tx = Xp.x - Xk.x - (2.0 * Mk.x + Mp.x) / 6.0;
+                const double ty = Xp.y - Xk.y - (2.0 * Mk.y + Mp.y) / 6.0;
+                const double tl = sqrt(tx * tx + ty * ty);
+                nx_ = ty / tl;
+                ny_ = -tx / tl;
+                jac = tl / I.dX;
+            } else {
+                // outward normal of the counter-clockwise curve, from the central chord
+                const double tx = Xp.x - Xm.x, ty = Xp.y - Xm.y;
+                const double tl = sqrt(tx * tx + ty * ty);
+                nx_ = ty / tl;
+                ny_ = -tx / tl;
+                // |dX/ds|: mean length of the two chords at the marker over Delta X
+                const double lp = hypot(Xp.x - Xk.x, Xp.y - Xk.y);
+                const double lm = hypot(Xk.x - Xm.x, Xk.y - Xm.y);
+                jac = (lp + lm) / (2.0 * I.dX);
+            }
         } else if (I.iface == II_LBM_IF_NORMAL) {
             // prescribed uniform normal force F n on the fixed circle (Sec. 4.1)
             nx_ = (Xk.x - I.cx) / I.radius;
@@ -202,8 +213,22 @@ __device__ __forceinline__ void markers_body(const InstDev& I, const DevPtrs& P,
     // Bin chord (k, k+1) into every tile within 2.5 lu of it (those tiles hold
     // the nodes whose links it can cut and the support of marker k's delta),
     // one tile per lane of the group.
-    const double xmin = fmin(Xk.x, Xp.x) - 2.5, xmax = fmax(Xk.x, Xp.x) + 2.5;
-    const double ymin = fmin(Xk.y, Xp.y) - 2.5, ymax = fmax(Xk.y, Xp.y) + 2.5;
+    double xmin = fmin(Xk.x, Xp.x) - 2.5, xmax = fmax(Xk.x, Xp.x) + 2.5;
+    double ymin = fmin(Xk.y, Xp.y) - 2.5, ymax = fmax(Xk.y, Xp.y) + 2.5;
+    if (I.geometry == 1) {
+        // the spline segment lies in the hull of its Bezier control points
+        const double2 Mk = P.M[m], Mp = P.M[I.mk_off + kp];
+        const double bx = Xp.x - Xk.x - (2.0 * Mk.x + Mp.x) / 6.0;
+        const double by = Xp.y - Xk.y - (2.0 * Mk.y + Mp.y) / 6.0;
+        const double ex_ = Xp.x - Xk.x + (Mk.x + 2.0 * Mp.x) / 6.0;   // S'(1)
+        const double ey_ = Xp.y - Xk.y + (Mk.y + 2.0 * Mp.y) / 6.0;
+        const double c1x = Xk.x + bx / 3.0, c1y = Xk.y + by / 3.0;
+        const double c2x = Xp.x - ex_ / 3.0, c2y = Xp.y - ey_ / 3.0;
+        xmin = fmin(xmin, fmin(c1x, c2x) - 2.5);
+        xmax = fmax(xmax, fmax(c1x, c2x) + 2.5);
+        ymin = fmin(ymin, fmin(c1y, c2y) - 2.5);
+        ymax = fmax(ymax, fmax(c1y, c2y) + 2.5);
+    }
     if (!(xmin == xmin) || !(ymin == ymin) || !(xmax == xmax) || !(ymax == ymax)) return;
     const int tx0 = max(0, (int)floor(fmax(xmin, 0.0) / kTile));
     const int tx1 = min(I.tiles_x - 1, (int)floor(fmin(xmax, (double)I.nx) / kTile));
@@ -718,6 +743,313 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
 }
 
 // ---------------------------------------------------------------------------
+// Cubic-spline membranes.
+//   k_spline  M_k of the periodic cubic spline through the markers, from the
+//             closed-form inverse of the cyclic system M_{k-1} + 4 M_k +
+//             M_{k+1} = r_k, r_k = 6 (X_{k+1} - 2 X_k + X_{k-1}): M_k =
+//             sum_j g_j r_{k+j} with g_j = lambda^|j| / (2 sqrt 3), lambda =
+//             sqrt 3 - 2, truncated at |j| <= 32 (|lambda|^33 < 1e-18), or, for
+//             N <= 64 markers, its periodic sum over every j (taps from the host).
+//   k_tiles_spline  the tile pass on the spline: the crossings of each link
+//             with each segment are the roots of the cubic e x (S(t) - P),
+//             split at its critical points and bisected 64 times; [[p]] at a
+//             crossing is dX (G x T) / |T|^2 with T = S'(t), G linear between
+//             the markers.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_spline(InstDev I, DevPtrs P, int par)
+{
+    const int N = I.n_markers;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const double2* X = P.X[par] + I.mk_off;
+    const double* g = P.spline_taps + I.tap_off;
+    double mx = 0.0, my = 0.0;
+    const int j0 = I.spl_periodic ? 0 : -32, j1 = I.spl_periodic ? N - 1 : 32;
+    for (int j = j0; j <= j1; j++) {
+        const int q = ((k + j) % N + N) % N;
+        const int qm = (q + N - 1) % N, qp = (q + 1) % N;
+        const double rx = 6.0 * (X[qp].x - 2.0 * X[q].x + X[qm].x);
+        const double ry = 6.0 * (X[qp].y - 2.0 * X[q].y + X[qm].y);
+        const double gj = g[j - j0];
+        mx += gj * rx;
+        my += gj * ry;
+    }
+    P.M[I.mk_off + k] = make_double2(mx, my);
+}
+
+hipError_t launch_spline(const InstDev& I, const DevPtrs& P, int par, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_spline, dim3((I.n_markers + 255) / 256), dim3(256), 0, s, I, P, par);
+    return hipGetLastError();
+}
+
+__device__ __forceinline__ double spl_cubic(const double F[4], double t)
+{
+    return ((F[3] * t + F[2]) * t + F[1]) * t + F[0];
+}
+
+// Crossings of link (px, py) -> + (ex, ey) with a segment: cf = (ax, ay, bx,
+// by, cx, cy, dx, dy, X_{k+1}x, X_{k+1}y).  Writes up to 3 (t, q, sigma).
+__device__ int spl_crossings(const double* cf, double px, double py, int ex, int ey, double* ts,
+                             double* qs, int* sg)
+{
+    double F[4];
+    F[0] = ex * (cf[1] - py) - ey * (cf[0] - px);
+    F[1] = ex * cf[3] - ey * cf[2];
+    F[2] = ex * cf[5] - ey * cf[4];
+    F[3] = ex * cf[7] - ey * cf[6];
+    const double f1 = ex * (cf[9] - py) - ey * (cf[8] - px);
+    double br[4];
+    int nb = 0;
+    br[nb++] = 0.0;
+    const double A = 3.0 * F[3], Bq = 2.0 * F[2], Cq = F[1];
+    double r1 = -1.0, r2 = -1.0;
+    if (A == 0.0) {
+        if (Bq != 0.0) r1 = -Cq / Bq;
+    } else {
+        const double disc = Bq * Bq - 4.0 * A * Cq;
+        if (disc > 0.0) {
+            const double sq = sqrt(disc);
+            const double qq = Bq >= 0.0 ? -0.5 * (Bq + sq) : -0.5 * (Bq - sq);
+            r1 = qq / A;
+            r2 = qq != 0.0 ? Cq / qq : -1.0;
+            if (r2 < r1) { const double tt = r1; r1 = r2; r2 = tt; }
+        }
+    }
+    if (r1 > 0.0 && r1 < 1.0) br[nb++] = r1;
+    if (r2 > 0.0 && r2 < 1.0 && r2 != r1) br[nb++] = r2;
+    br[nb] = 1.0;
+    int n = 0;
+    const double ee = (double)(ex * ex + ey * ey);
+    for (int j = 0; j < nb; j++) {
+        double lo = br[j], hi = br[j + 1];
+        const double flo = spl_cubic(F, lo), fhi = (j == nb - 1) ? f1 : spl_cubic(F, hi);
+        const bool slo = flo >= 0.0, shi = fhi >= 0.0;
+        if (slo == shi) continue;
+        for (int it = 0; it < 64; it++) {
+            const double mid = 0.5 * (lo + hi);
+            if ((spl_cubic(F, mid) >= 0.0) == slo) lo = mid; else hi = mid;
+        }
+        const double t = 0.5 * (lo + hi);
+        const double sx = ((cf[6] * t + cf[4]) * t + cf[2]) * t + cf[0];
+        const double sy = ((cf[7] * t + cf[5]) * t + cf[3]) * t + cf[1];
+        const double q = ((sx - px) * ex + (sy - py) * ey) / ee;
+        if (!(q >= 0.0 && q < 1.0)) continue;
+        ts[n] = t;
+        qs[n] = q;
+        sg[n] = slo ? -1 : 1;
+        n++;
+    }
+    return n;
+}
+
+__device__ __forceinline__ double spl_jump(const double* cf, const double* gk, double dX, double t)
+{
+    const double Gx = (1.0 - t) * gk[0] + t * gk[2], Gy = (1.0 - t) * gk[1] + t * gk[3];
+    const double Tx = (3.0 * cf[6] * t + 2.0 * cf[4]) * t + cf[2];
+    const double Ty = (3.0 * cf[7] * t + 2.0 * cf[5]) * t + cf[3];
+    return dX * (Gx * Ty - Gy * Tx) / (Tx * Tx + Ty * Ty);
+}
+
+template <bool REC>
+struct TileSharedSpl {
+    int raw[kTileCap];
+    int start[kTileCap];
+    int key[kTileCap];
+    double cf[kTileCap][10];     // segment coefficients and X_{k+1}
+    double gk[kTileCap][4];      // G_k, G_{k+1}
+    short box[kTileCap][4];
+    float wx[kTileCap][4], wy[kTileCap][4];
+    int2 f0[kTileCap];
+    double gtx[kTileCap], gty[kTileCap];
+    float acc[8][kTileNodes];
+    unsigned rec[REC ? kTileRec : 1];   // (node, direction, chord, root)
+    int cnt, total, nrec, base;
+};
+
+template <bool REC>
+__device__ void tiles_spline_body(const InstDev& I, const DevPtrs& P, int parity, int blk, int nblk)
+{
+    __shared__ TileSharedSpl<REC> S;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int N = I.n_markers;
+    const double2* X = P.X[parity] + I.mk_off;
+    const int nact = min(P.act_count[2 * I.inst + parity], I.act_cap);
+    for (int a = blk; a < nact; a += nblk) {
+        const int t = P.act_list[parity][I.act_off + a].y;
+        const int gt = I.tile_off + t;
+        const int tx = t % I.tiles_x, ty = t / I.tiles_x;
+        const int x0 = tx * kTile, y0 = ty * kTile;
+        if (tid < kTileCap) S.raw[tid] = P.tile_list[I.list_off + (long long)t * kTileCap + tid];
+        if (tid == 0) {
+            S.cnt = min(P.tile_count[gt], kTileCap);
+            S.nrec = 0;
+        }
+#pragma unroll
+        for (int i = 0; i < 8; i++) S.acc[i][tid] = 0.f;
+        __syncthreads();
+        const int c = S.cnt;
+        if (tid == 0) {
+            P.tile_count[gt] = 0;
+            P.tile_slot[parity][gt] = I.act_off + a;
+        }
+        if (tid < c) {
+            const int k = S.raw[tid];
+            int r = 0;
+            for (int m = 0; m < c; m++) r += (S.raw[m] < k) ? 1 : 0;
+            const int kp = (k + 1) % N, mk = I.mk_off + k, mp = I.mk_off + kp;
+            const double2 Xk = X[k], Xp = X[kp], Mk = P.M[mk], Mp = P.M[mp];
+            const double2 Gk = P.G[mk], Gp = P.G[mp];
+            double* cf = S.cf[r];
+            cf[0] = Xk.x;
+            cf[1] = Xk.y;
+            cf[2] = Xp.x - Xk.x - (2.0 * Mk.x + Mp.x) / 6.0;
+            cf[3] = Xp.y - Xk.y - (2.0 * Mk.y + Mp.y) / 6.0;
+            cf[4] = 0.5 * Mk.x;
+            cf[5] = 0.5 * Mk.y;
+            cf[6] = (Mp.x - Mk.x) / 6.0;
+            cf[7] = (Mp.y - Mk.y) / 6.0;
+            cf[8] = Xp.x;
+            cf[9] = Xp.y;
+            S.gk[r][0] = Gk.x; S.gk[r][1] = Gk.y; S.gk[r][2] = Gp.x; S.gk[r][3] = Gp.y;
+            S.key[r] = k;
+            // candidate source nodes: within one spacing of the control-point hull
+            const double t1x = cf[2] + 2.0 * cf[4] + 3.0 * cf[6], t1y = cf[3] + 2.0 * cf[5] + 3.0 * cf[7];
+            const double hx1 = cf[0] + cf[2] / 3.0, hy1 = cf[1] + cf[3] / 3.0;
+            const double hx2 = Xp.x - t1x / 3.0, hy2 = Xp.y - t1y / 3.0;
+            const double xmn = fmin(fmin(Xk.x, Xp.x), fmin(hx1, hx2));
+            const double xmx = fmax(fmax(Xk.x, Xp.x), fmax(hx1, hx2));
+            const double ymn = fmin(fmin(Xk.y, Xp.y), fmin(hy1, hy2));
+            const double ymx = fmax(fmax(Xk.y, Xp.y), fmax(hy1, hy2));
+            const int bx0 = max((int)floor(xmn) - 1, x0);
+            const int bx1 = min((int)ceil(xmx) + 1, min(x0 + kTile, I.nx) - 1);
+            const int by0 = max((int)floor(ymn) - 1, y0);
+            const int by1 = min((int)ceil(ymx) + 1, min(y0 + kTile, I.ny) - 1);
+            S.box[r][0] = (short)bx0; S.box[r][1] = (short)bx1;
+            S.box[r][2] = (short)by0; S.box[r][3] = (short)by1;
+            S.start[r] = (bx0 <= bx1 && by0 <= by1) ? (bx1 - bx0 + 1) * (by1 - by0 + 1) : 0;
+            S.f0[r] = P.f0[mk];
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                S.wx[r][q] = (float)P.wx[4 * mk + q];
+                S.wy[r][q] = (float)P.wy[4 * mk + q];
+            }
+            const double2 gtk = P.Gt[mk];
+            S.gtx[r] = gtk.x;
+            S.gty[r] = gtk.y;
+        }
+        __syncthreads();
+        if (wid == 0) {
+            const int v0 = 2 * lane < c ? S.start[2 * lane] : 0;
+            const int v1 = 2 * lane + 1 < c ? S.start[2 * lane + 1] : 0;
+            int sc = v0 + v1;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int u = __shfl_up(sc, off);
+                if (lane >= off) sc += u;
+            }
+            if (2 * lane < c) S.start[2 * lane] = sc - v0 - v1;
+            if (2 * lane + 1 < c) S.start[2 * lane + 1] = sc - v1;
+            if (lane == 63) S.total = sc;
+        }
+        __syncthreads();
+        const int total = S.total;
+        for (int g = tid; g < total; g += blockDim.x) {
+            int lo = 0, hi = c - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (S.start[mid] <= g) lo = mid; else hi = mid - 1;
+            }
+            const int j = lo, q = g - S.start[j];
+            const int bx0 = S.box[j][0], by0 = S.box[j][2];
+            const int w = S.box[j][1] - bx0 + 1;
+            const int x = bx0 + q % w, y = by0 + q / w;
+            const int node = (y - y0) * kTile + (x - x0);
+            for (int i = 1; i < 9; i++) {
+                double ts[3], qs[3];
+                int sg[3];
+                const int nr = spl_crossings(S.cf[j], (double)x, (double)y, EX[i], EY[i], ts, qs, sg);
+                for (int rr = 0; rr < nr; rr++) {
+                    add_jump(S, node, i, sg[rr], spl_jump(S.cf[j], S.gk[j], I.dX, ts[rr]));
+                    if constexpr (REC) {
+                        const int e = atomicAdd(&S.nrec, 1);
+                        if (e < kTileRec)
+                            S.rec[e] = (unsigned)node | ((unsigned)(i - 1) << 8) | ((unsigned)j << 11) |
+                                       ((unsigned)rr << 18);
+                    }
+                }
+            }
+        }
+        const int lx = tid & (kTile - 1), ly = tid / kTile;
+        const int x = x0 + lx, y = y0 + ly;
+        const bool valid = x < I.nx && y < I.ny;
+        double gx = 0.0, gy = 0.0;
+        if (valid) {
+#pragma unroll 4
+            for (int j = 0; j < c; j++) {
+                const int2 f = S.f0[j];
+                const int ix = x - f.x, iy = y - f.y;
+                const bool in = (unsigned)ix <= 3u && (unsigned)iy <= 3u;
+                const double wgt = in ? (double)S.wx[j][ix & 3] * (double)S.wy[j][iy & 3] : 0.0;
+                gx += S.gtx[j] * wgt * I.dX;
+                gy += S.gty[j] * wgt * I.dX;
+            }
+        }
+        __syncthreads();
+        {
+            float* cr = P.corr[parity] + (long long)(I.act_off + a) * kCorrPlanes * kTileNodes + tid;
+            const double fs = I.guo ? 0.0 : 3.0;
+#pragma unroll
+            for (int i = 1; i < 9; i++) {
+                const double delta =
+                    valid ? fs * WD[i] * ((double)EX[i] * gx + (double)EY[i] * gy) +
+                                (double)S.acc[i - 1][tid]
+                          : 0.0;
+                cr[(i - 1) * kTileNodes] = (float)delta;
+            }
+            if (I.guo) {
+                cr[8 * kTileNodes] = valid ? (float)gx : 0.f;
+                cr[9 * kTileNodes] = valid ? (float)gy : 0.f;
+            }
+        }
+        if constexpr (REC) {
+            const int nr = min(S.nrec, kTileRec);
+            if (tid == 0) {
+                S.base = nr > 0 ? atomicAdd(&P.rec_count[2 * I.inst + parity], nr) : 0;
+                if (S.nrec > kTileRec) atomicOr(&P.err[I.inst], (int)kErrRecords);
+            }
+            __syncthreads();
+            const int base = S.base;
+            for (int e = tid; e < nr; e += blockDim.x) {
+                if (base + e >= I.rec_cap) {
+                    atomicOr(&P.err[I.inst], (int)kErrRecords);
+                    continue;
+                }
+                const unsigned pk = S.rec[e];
+                const int node = pk & 255, i = 1 + ((pk >> 8) & 7), j = (pk >> 11) & 127,
+                          rr = (pk >> 18) & 3;
+                const int x = x0 + (node & (kTile - 1)), y = y0 + node / kTile;
+                double ts[3], qs[3];
+                int sg[3];
+                (void)spl_crossings(S.cf[j], (double)x, (double)y, EX[i], EY[i], ts, qs, sg);
+                ii_lbm_link L;
+                L.x = x; L.y = y; L.dir = i; L.inst = I.inst;
+                L.sigma = sg[rr]; L.seg = S.key[j]; L.q = qs[rr]; L.theta = ts[rr];
+                L.jp = spl_jump(S.cf[j], S.gk[j], I.dX, ts[rr]);
+                P.rec[I.rec_off + base + e] = L;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <bool REC>
+__global__ __launch_bounds__(256) void k_tiles_spline(InstDev I, DevPtrs P, int parity)
+{
+    tiles_spline_body<REC>(I, P, parity, blockIdx.x, gridDim.x);
+}
+
+// ---------------------------------------------------------------------------
 // IB-LBM tile pass: no cut links, so a tile only gathers the force of the
 // markers binned to it, G spread with the delta weights of the marker pass
 // (Sec. 2.2.2), summed in increasing marker order.  The comparison method
@@ -840,6 +1172,13 @@ static hipError_t tiles_i(const InstDev& I, const DevPtrs& P, int parity, bool r
 
 hipError_t launch_tiles(const InstDev& I, const DevPtrs& P, int parity, bool records, hipStream_t s)
 {
+    if (I.jumps && I.iface == II_LBM_IF_MEMBRANE && I.geometry == 1) {
+        if (records)
+            hipLaunchKernelGGL(k_tiles_spline<true>, dim3(I.tile_blocks), dim3(256), 0, s, I, P, parity);
+        else
+            hipLaunchKernelGGL(k_tiles_spline<false>, dim3(I.tile_blocks), dim3(256), 0, s, I, P, parity);
+        return hipGetLastError();
+    }
     if (!I.jumps) {
         hipLaunchKernelGGL(k_tiles_ib, dim3(I.tile_blocks), dim3(256), 0, s, I, P, parity);
         return hipGetLastError();

@@ -30,6 +30,8 @@ struct Layout {
     size_t off_tile_count = 0, off_tile_list = 0, off_tile_slot[2] = {0, 0}, off_corr[2] = {0, 0};
     size_t off_act_list[2] = {0, 0}, off_act_count = 0;
     size_t off_rec = 0, off_rec_count = 0, off_err = 0, off_diag = 0, off_body = 0;
+    size_t off_M = 0, off_taps = 0;
+    int taps_total = 0;
     size_t off_insts = 0, off_mk_table = 0, off_tile_table = 0, off_sweep_table = 0;
     int mk_units = 0, tile_units = 0, sweep_units_max = 0;
     size_t total = 0;
@@ -60,6 +62,8 @@ int validate(const ii_lbm_problem& p, const double* X0)
         !(p.radius > 0.0))
         return II_LBM_EINVAL;
     if (p.interface_kind == II_LBM_IF_NORMAL && !isfinite(p.f_normal)) return II_LBM_EINVAL;
+    if (p.geometry != 0 && p.geometry != 1) return II_LBM_EINVAL;
+    if (p.geometry == 1 && p.interface_kind != II_LBM_IF_MEMBRANE) return II_LBM_EINVAL;
     const bool moving = p.body_free != 0 || p.presc_umax[0] != 0.0 || p.presc_umax[1] != 0.0;
     if (moving) {
         if (p.interface_kind != II_LBM_IF_RIGID || (p.body_free & ~7)) return II_LBM_EINVAL;
@@ -112,7 +116,7 @@ int build_layout(const ii_lbm_problem* p, int n_inst, Layout& L)
 {
     L.inst.resize(n_inst);
     size_t lat = 0;
-    int mk = 0, tiles = 0, act = 0, rec = 0;
+    int mk = 0, tiles = 0, act = 0, rec = 0, taps = 0;
     long long list = 0;
     for (int j = 0; j < n_inst; j++) {
         const ii_lbm_problem& q = p[j];
@@ -158,6 +162,10 @@ int build_layout(const ii_lbm_problem* p, int n_inst, Layout& L)
         I.cy = q.center[1];
         I.radius = q.radius;
         I.f_normal = q.f_normal;
+        I.geometry = q.interface_kind == II_LBM_IF_MEMBRANE ? q.geometry : 0;
+        I.spl_periodic = I.n_markers <= 64;
+        I.tap_off = taps;
+        if (I.geometry == 1) taps += I.spl_periodic ? I.n_markers : 65;
         I.moving = q.interface_kind == II_LBM_IF_RIGID &&
                    (q.body_free != 0 || q.presc_umax[0] != 0.0 || q.presc_umax[1] != 0.0);
         I.body_free = q.body_free;
@@ -230,6 +238,9 @@ int build_layout(const ii_lbm_problem* p, int n_inst, Layout& L)
     L.off_err = take((size_t)n_inst * sizeof(int));
     L.off_diag = take((size_t)4 * kDiagBlocks * sizeof(double));
     L.off_body = take((size_t)n_inst * sizeof(BodyDev));
+    L.off_M = take(nm * sizeof(double2));
+    L.taps_total = taps;
+    L.off_taps = take((size_t)std::max(taps, 1) * sizeof(double));
     // batched launches: descriptors and work tables (tile table sized for the
     // largest per-instance block count)
     int tile_units = 0;
@@ -397,6 +408,7 @@ static hipError_t enqueue_interface(ii_lbm_handle* h, int par, int mode, hipStre
         const InstDev& I = h->L.inst[j];
         if (I.n_markers == 0) continue;
         e = launch_slot_reset(I, h->P, par, s);
+        if (e == hipSuccess && I.geometry == 1) e = launch_spline(I, h->P, par, s);
         if (e == hipSuccess) e = launch_markers(I, h->P, A, par, mode, s);
         if (e == hipSuccess) e = launch_tiles(I, h->P, par, records, s);
     }
@@ -692,6 +704,8 @@ int ii_lbm_init(const ii_lbm_problem* p, int32_t n_inst, const double* const* X0
     P.err = (int*)(h->ws + L.off_err);
     P.diag = (double*)(h->ws + L.off_diag);
     P.body = (BodyDev*)(h->ws + L.off_body);
+    P.M = (double2*)(h->ws + L.off_M);
+    P.spline_taps = (const double*)(h->ws + L.off_taps);
 
     hipError_t e = hipSuccess;
     for (int j = 0; j < n_inst && e == hipSuccess; j++) {
@@ -712,6 +726,28 @@ int ii_lbm_init(const ii_lbm_problem* p, int32_t n_inst, const double* const* X0
         if (e == hipSuccess)
             e = hipMemcpyAsync(P.X[1] + I.mk_off, X0[j], (size_t)I.n_markers * sizeof(double2),
                                hipMemcpyHostToDevice, h->stream);
+    }
+    // Spline taps: the inverse of the cyclic system M_{k-1} + 4 M_k + M_{k+1},
+    // g_j = lambda^|j| / (2 sqrt 3) with lambda = sqrt 3 - 2 for |j| <= 32, or
+    // its periodic sum (lambda^j + lambda^(N-j)) / (2 sqrt 3 (1 - lambda^N)),
+    // j = 0 .. N-1, for N <= 64 markers.
+    if (e == hipSuccess && L.taps_total > 0) {
+        std::vector<double> taps(L.taps_total);
+        const double lam = sqrt(3.0) - 2.0, c0 = 1.0 / (2.0 * sqrt(3.0));
+        for (int j = 0; j < n_inst; j++) {
+            const InstDev& I = L.inst[j];
+            if (I.geometry != 1) continue;
+            const int N = I.n_markers;
+            if (I.spl_periodic) {
+                const double lN = pow(lam, N);
+                for (int q = 0; q < N; q++)
+                    taps[I.tap_off + q] = (pow(lam, q) + pow(lam, N - q)) * c0 / (1.0 - lN);
+            } else {
+                for (int q = -32; q <= 32; q++) taps[I.tap_off + q + 32] = pow(lam, abs(q)) * c0;
+            }
+        }
+        e = hipMemcpyAsync((void*)P.spline_taps, taps.data(), taps.size() * sizeof(double),
+                           hipMemcpyHostToDevice, h->stream);
     }
     // Moving bodies start at their initial centre, at rest (a prescribed axis
     // at its velocity of t = 0), in orientation 0.
@@ -737,7 +773,8 @@ int ii_lbm_init(const ii_lbm_problem* p, int32_t n_inst, const double* const* X0
         int iface = II_LBM_IF_NONE;
         for (int j = 0; j < n_inst; j++) {
             if (p[j].storage != p[0].storage || p[j].math != p[0].math ||
-                p[j].force_mode != p[0].force_mode || h->L.inst[j].moving) {
+                p[j].force_mode != p[0].force_mode || h->L.inst[j].moving ||
+                h->L.inst[j].geometry != 0) {
                 e = hipErrorInvalidValue;
                 break;
             }

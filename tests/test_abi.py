@@ -75,6 +75,9 @@ def test_workspace_size_scales_with_lattice():
     (lambda p, X: setattr(p, "n_markers", 2), B.EINVAL),
     (lambda p, X: setattr(p, "storage", 5), B.EINVAL),
     (lambda p, X: setattr(p, "force_mode", 4), B.EINVAL),
+    (lambda p, X: setattr(p, "geometry", 2), B.EINVAL),
+    (lambda p, X: (setattr(p, "interface_kind", 2), setattr(p, "radius", 8.0),
+                   setattr(p, "geometry", 1)), B.EINVAL),
     (lambda p, X: (setattr(p, "interface_kind", 3), setattr(p, "radius", 0.0)), B.EINVAL),
     (lambda p, X: (setattr(p, "interface_kind", 3), setattr(p, "radius", 8.0),
                    setattr(p, "f_normal", float("nan"))), B.EINVAL),
