@@ -829,6 +829,9 @@ def main() -> int:
                     help="timed steps (default 2000; 4000 for the batch512 workload, as configured)")
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--storage", choices=["fp32", "fp16"], default="fp32")
+    ap.add_argument("--geometry", choices=["polygon", "spline"], default="polygon",
+                    help="membrane representation: the polygon through the markers (the bench "
+                         "line) or the cubic spline")
     ap.add_argument("--math", choices=["fp32", "fp64"], default=None,
                     help="collision arithmetic (storage keeps its own precision); default FP64 "
                          "for FP32 storage (its 1e-6 parity bar) and FP32 for FP16 storage "
@@ -903,6 +906,7 @@ def main() -> int:
     w = W.membrane_c3(L=args.size, storage=storage)
     p = w.problem
     p.math = W.MATH_FP64 if args.math == "fp64" else W.MATH_FP32
+    p.geometry = W.GEOM_SPLINE if args.geometry == "spline" else W.GEOM_POLYGON
     sim = B.Sim([p], [w.X0], device="cuda:0")
     set_overlap(sim, B, args)
     graph = args.graph == "on"
@@ -949,7 +953,8 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": ("f32" if storage == W.STORE_FP32 else "f16") + " storage / " + args.math + " collision",
         "data": "synthetic",
-        "config": {"workload": f"membrane{p.nx}_periodic_srt_{args.storage}",
+        "config": {"workload": f"membrane{p.nx}_periodic_srt_{args.storage}"
+                               + ("_spline" if args.geometry == "spline" else ""),
                    "nx": p.nx, "ny": p.ny, "markers": p.n_markers, "tau": round(p.tau, 6),
                    "kappa": p.kappa, "storage": args.storage, "collision_math": args.math,
                    "cut_links": d["n_cut_links"], "graph": graph},

@@ -38,7 +38,7 @@
  *      (a uniform inflow side takes u_b = (u_max, 0));
  *  R27 (geometry 1) the membrane is the periodic cubic spline through the
  *      markers in the marker index; crossings are the roots of a cubic found
- *      by a fixed bisection, [[p]] at a crossing from the spline normal and
+ *      by a fixed bisection after a control-point hull test, [[p]] at a crossing from the spline normal and
  *      |dX/ds| with G linear between the markers;
  *  R24 under Guo's force term (the comparison method of Sec. 2.2.2) the
  *      collision uses the compressible equilibrium and the velocity
@@ -417,6 +417,19 @@ static double cubic_at(const double F[4], double t) { return ((F[3] * t + F[2]) 
 static int spline_link_crossings(const double *coef, const double *Xnext, double px, double py,
                                  int ex, int ey, double *ts, double *qs, int *sg)
 {
+    /* the segment lies in the hull of its Bezier control points
+     * B0 = a, B1 = a + b/3, B2 = a + (2b + c)/3, B3 = X_{k+1}: when e x (B_i - P)
+     * has one strict sign for all four, the line of the link misses it */
+    double b1x = coef[0] + coef[2] / 3.0, b1y = coef[1] + coef[3] / 3.0;
+    double b2x = coef[0] + (2.0 * coef[2] + coef[4]) / 3.0, b2y = coef[1] + (2.0 * coef[3] + coef[5]) / 3.0;
+    double bz[4];
+    bz[0] = ex * (coef[1] - py) - ey * (coef[0] - px);
+    bz[1] = ex * (b1y - py) - ey * (b1x - px);
+    bz[2] = ex * (b2y - py) - ey * (b2x - px);
+    bz[3] = ex * (Xnext[1] - py) - ey * (Xnext[0] - px);
+    if ((bz[0] > 0.0 && bz[1] > 0.0 && bz[2] > 0.0 && bz[3] > 0.0) ||
+        (bz[0] < 0.0 && bz[1] < 0.0 && bz[2] < 0.0 && bz[3] < 0.0))
+        return 0;
     double F[4];
     F[0] = ex * (coef[1] - py) - ey * (coef[0] - px);
     F[1] = ex * coef[3] - ey * coef[2];

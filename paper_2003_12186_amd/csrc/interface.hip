@@ -756,30 +756,37 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
 //             crossing is dX (G x T) / |T|^2 with T = S'(t), G linear between
 //             the markers.
 // ---------------------------------------------------------------------------
+// One 64-lane wave per marker, one or two taps per lane, summed by shuffles.
 __global__ __launch_bounds__(256) void k_spline(InstDev I, DevPtrs P, int par)
 {
     const int N = I.n_markers;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= N) return;
+    const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (k >= N) return;   // whole waves leave together
     const double2* X = P.X[par] + I.mk_off;
     const double* g = P.spline_taps + I.tap_off;
+    const int j0 = I.spl_periodic ? 0 : -32, ntap = I.spl_periodic ? N : 65;
     double mx = 0.0, my = 0.0;
-    const int j0 = I.spl_periodic ? 0 : -32, j1 = I.spl_periodic ? N - 1 : 32;
-    for (int j = j0; j <= j1; j++) {
+    for (int u = lane; u < ntap; u += 64) {
+        const int j = j0 + u;
         const int q = ((k + j) % N + N) % N;
-        const int qm = (q + N - 1) % N, qp = (q + 1) % N;
-        const double rx = 6.0 * (X[qp].x - 2.0 * X[q].x + X[qm].x);
-        const double ry = 6.0 * (X[qp].y - 2.0 * X[q].y + X[qm].y);
-        const double gj = g[j - j0];
-        mx += gj * rx;
-        my += gj * ry;
+        const int qm = q == 0 ? N - 1 : q - 1, qp = q == N - 1 ? 0 : q + 1;
+        const double2 a = X[qm], b = X[q], c = X[qp];
+        const double gj = g[u];
+        mx += gj * (6.0 * (c.x - 2.0 * b.x + a.x));
+        my += gj * (6.0 * (c.y - 2.0 * b.y + a.y));
     }
-    P.M[I.mk_off + k] = make_double2(mx, my);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        mx += __shfl_xor(mx, off, 64);
+        my += __shfl_xor(my, off, 64);
+    }
+    if (lane == 0) P.M[I.mk_off + k] = make_double2(mx, my);
 }
 
 hipError_t launch_spline(const InstDev& I, const DevPtrs& P, int par, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_spline, dim3((I.n_markers + 255) / 256), dim3(256), 0, s, I, P, par);
+    hipLaunchKernelGGL(k_spline, dim3((I.n_markers + 3) / 4), dim3(256), 0, s, I, P, par);
     return hipGetLastError();
 }
 
@@ -789,10 +796,20 @@ __device__ __forceinline__ double spl_cubic(const double F[4], double t)
 }
 
 // Crossings of link (px, py) -> + (ex, ey) with a segment: cf = (ax, ay, bx,
-// by, cx, cy, dx, dy, X_{k+1}x, X_{k+1}y).  Writes up to 3 (t, q, sigma).
+// by, cx, cy, dx, dy, X_{k+1}x, X_{k+1}y, B1x, B1y, B2x, B2y) with the inner
+// Bezier control points B1 = a + b/3, B2 = a + (2b + c)/3.  Writes up to 3
+// (t, q, sigma).
 __device__ int spl_crossings(const double* cf, double px, double py, int ex, int ey, double* ts,
                              double* qs, int* sg)
 {
+    // control-point hull test: B0 = a, B1, B2, B3 = X_{k+1}
+    const double b0 = ex * (cf[1] - py) - ey * (cf[0] - px);
+    const double b1 = ex * (cf[11] - py) - ey * (cf[10] - px);
+    const double b2 = ex * (cf[13] - py) - ey * (cf[12] - px);
+    const double b3 = ex * (cf[9] - py) - ey * (cf[8] - px);
+    if ((b0 > 0.0 && b1 > 0.0 && b2 > 0.0 && b3 > 0.0) ||
+        (b0 < 0.0 && b1 < 0.0 && b2 < 0.0 && b3 < 0.0))
+        return 0;
     double F[4];
     F[0] = ex * (cf[1] - py) - ey * (cf[0] - px);
     F[1] = ex * cf[3] - ey * cf[2];
@@ -856,7 +873,7 @@ struct TileSharedSpl {
     int raw[kTileCap];
     int start[kTileCap];
     int key[kTileCap];
-    double cf[kTileCap][10];     // segment coefficients and X_{k+1}
+    double cf[kTileCap][14];     // segment coefficients, X_{k+1}, inner control points
     double gk[kTileCap][4];      // G_k, G_{k+1}
     short box[kTileCap][4];
     float wx[kTileCap][4], wy[kTileCap][4];
@@ -911,6 +928,10 @@ __device__ void tiles_spline_body(const InstDev& I, const DevPtrs& P, int parity
             cf[7] = (Mp.y - Mk.y) / 6.0;
             cf[8] = Xp.x;
             cf[9] = Xp.y;
+            cf[10] = cf[0] + cf[2] / 3.0;
+            cf[11] = cf[1] + cf[3] / 3.0;
+            cf[12] = cf[0] + (2.0 * cf[2] + cf[4]) / 3.0;
+            cf[13] = cf[1] + (2.0 * cf[3] + cf[5]) / 3.0;
             S.gk[r][0] = Gk.x; S.gk[r][1] = Gk.y; S.gk[r][2] = Gp.x; S.gk[r][3] = Gp.y;
             S.key[r] = k;
             // candidate source nodes: within one spacing of the control-point hull

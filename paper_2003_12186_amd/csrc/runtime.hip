@@ -593,9 +593,11 @@ static void size_tile_blocks(ii_lbm_handle* h)
 {
     if (h->batched) return;
     const bool beside = h->lookahead && h->overlap != II_LBM_OVERLAP_SERIAL;
+    // the spline's tile pass carries root finding and is the step's critical
+    // path even beside the sweep: it keeps every block
     for (InstDev& I : h->L.inst)
         if (I.n_markers > 0)
-            I.tile_blocks = std::max(1, std::min(I.act_cap, beside ? h->n_cu : 2048));
+            I.tile_blocks = std::max(1, std::min(I.act_cap, beside && I.geometry != 1 ? h->n_cu : 2048));
 }
 
 static void release(ii_lbm_handle* h)
