@@ -329,7 +329,7 @@ PAPER_TABLE2 = {
 def bench_area(args, B, W) -> int:
     """The area comparison of Sec. 4.2 (Table 2): the elastic membrane under
     IB-LBM with the simple and with Guo's force term and under II-LBM (also
-    with Guo's term), L = 80, 160, 240, to t = 30 L/U, the enclosed area read
+    with Guo's term, and on the cubic spline), L = 80, 160, 240, to t = 30 L/U, the enclosed area read
     after every L/U (HIP graphs between the reads).  Reports the loss rate
     (least-squares slope of the area loss over t = 1..30 L/U, and the total
     over 30) and the throughput of every run.  Then the sweep with Guo's term
@@ -340,11 +340,14 @@ def bench_area(args, B, W) -> int:
              W.FORCE_II_LBM: "II-LBM", W.FORCE_II_LBM_GUO: "II-LBM (G)"}
     math_ = W.MATH_FP64 if args.math == "fp64" else W.MATH_FP32
     rows, lu_all, t_all = [], 0, 0.0
+    methods = [(mode, W.GEOM_POLYGON, name) for mode, name in names.items()]
+    methods.append((W.FORCE_II_LBM, W.GEOM_SPLINE, "II-LBM (spline)"))
     for L in [int(v) for v in args.area_sizes.split(",") if v.strip()]:
-        for mode, name in names.items():
+        for mode, geom, name in methods:
             w = W.elastic_membrane_e2(L, mode)
             p = w.problem
             p.math = math_
+            p.geometry = geom
             sim = B.Sim([p], [w.X0], device="cuda:0")
             sim.set_graph(args.graph == "on")
             A0 = sim.diag()["area"]
