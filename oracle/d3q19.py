@@ -1,0 +1,126 @@
+"""ctypes binding of the FP64 CPU oracle of the D3Q19 step (``iilbm3_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/`` and the CPU-baseline leg of
+``bench.py``.  The GPU library never imports, links or calls it.
+
+Arrays: f[19][nz][ny][nx] float64 (C order), sphere markers X[N][3].
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "iilbm3_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle3.so")
+
+
+def build(force: bool = False) -> str:
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Problem3(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("force_mode", C.c_int32),
+                ("tau", C.c_double), ("cx", C.c_double), ("cy", C.c_double), ("cz", C.c_double),
+                ("radius", C.c_double), ("f_normal", C.c_double), ("n_markers", C.c_int32),
+                ("pad", C.c_int32), ("body", C.c_double * 3)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        d = C.c_void_p
+        P = C.POINTER(Problem3)
+        sig = {
+            "or3_lattice": (None, [d, d, d, d]),
+            "or3_equilibrium": (None, [C.c_double] * 4 + [d]),
+            "or3_moments": (None, [P, d, d, d, d, d]),
+            "or3_peskin": (C.c_double, [C.c_double]),
+            "or3_spread": (None, [P, d, d]),
+            "or3_count_cut_links": (C.c_long, [P]),
+            "or3_step": (C.c_int, [P, d, d]),
+            "or3_run": (C.c_int, [P, d, d, C.c_int]),
+            "or3_sizeof_problem": (C.c_int, []),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(_lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        assert _lib.or3_sizeof_problem() == C.sizeof(Problem3)
+    return _lib
+
+
+def _ptr(a):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def make_problem(w) -> Problem3:
+    p = Problem3()
+    p.nx, p.ny, p.nz = int(w.nx), int(w.ny), int(w.nz)
+    p.force_mode = int(w.force_mode)
+    p.tau = float(w.tau)
+    p.cx, p.cy, p.cz = (float(v) for v in w.center)
+    p.radius, p.f_normal = float(w.radius), float(w.f_normal)
+    p.n_markers = int(w.n_markers)
+    for a in range(3):
+        p.body[a] = float(w.body_force[a])
+    return p
+
+
+def lattice():
+    ex = np.zeros(19, np.int32); ey = np.zeros(19, np.int32); ez = np.zeros(19, np.int32)
+    w = np.zeros(19)
+    lib().or3_lattice(_ptr(ex), _ptr(ey), _ptr(ez), _ptr(w))
+    return ex, ey, ez, w
+
+
+def equilibrium(rho, ux, uy, uz):
+    out = np.zeros(19)
+    lib().or3_equilibrium(float(rho), float(ux), float(uy), float(uz), _ptr(out))
+    return out
+
+
+def rest_state(p: Problem3, rho: float = 1.0) -> np.ndarray:
+    feq = equilibrium(rho, 0.0, 0.0, 0.0)
+    return np.ascontiguousarray(np.broadcast_to(feq[:, None, None, None], (19, p.nz, p.ny, p.nx))).copy()
+
+
+def moments(p: Problem3, f):
+    n = p.nx * p.ny * p.nz
+    out = [np.zeros((p.nz, p.ny, p.nx)) for _ in range(4)]
+    lib().or3_moments(C.byref(p), _ptr(f), *(_ptr(o) for o in out))
+    return out
+
+
+def peskin(r: float) -> float:
+    return lib().or3_peskin(float(r))
+
+
+def spread(p: Problem3, X):
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    g = np.zeros((3, p.nz, p.ny, p.nx))
+    lib().or3_spread(C.byref(p), _ptr(X), _ptr(g))
+    return g
+
+
+def count_cut_links(p: Problem3) -> int:
+    return int(lib().or3_count_cut_links(C.byref(p)))
+
+
+def run(p: Problem3, f, X, steps: int):
+    assert f.dtype == np.float64 and f.flags["C_CONTIGUOUS"] and f.shape == (19, p.nz, p.ny, p.nx)
+    Xp = np.ascontiguousarray(X if X is not None else np.zeros((1, 3)), dtype=np.float64)
+    lib().or3_run(C.byref(p), _ptr(f), _ptr(Xp), int(steps))

@@ -1,0 +1,185 @@
+/*
+ * Plain FP64 CPU oracle of a D3Q19 immersed interface-lattice Boltzmann step
+ * (the three-dimensional form the paper's conclusion calls straightforward;
+ * reading R28): a periodic box, single-relaxation-time collision with the
+ * He-Luo equilibrium and the simple force term (Sec. 2.2.1-2.2.2 written for
+ * nineteen velocities), and a fixed sphere carrying a uniform normal force F
+ * per unit area, entered either
+ *   - II-LBM: through the jump [[f_i]] = sigma w_i [[p]] / c_s^2 with
+ *     [[p]] = F on every link the sphere's level set cuts (Sec. 3.1,
+ *     Eq. (32); Sec. 3.2, Eq. (47)), or
+ *   - IB-LBM: spread from surface markers with the three-dimensional product of
+ *     Peskin's four-point delta (Sec. 2.2.2, Eq. (17)).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may call, link or
+ * load this file.  It shares no code, header, table or helper with the GPU
+ * library.
+ *
+ * Lattice units, f[i][z][y][x] with x fastest; markers X[k][3].
+ */
+#define _GNU_SOURCE
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define Q 19
+static const int EX3[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+static const int EY3[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+static const int EZ3[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+static const double CS2 = 1.0 / 3.0;
+
+static double wt3(int i)
+{
+    if (i == 0) return 1.0 / 3.0;
+    if (i <= 6) return 1.0 / 18.0;
+    return 1.0 / 36.0;
+}
+
+typedef struct {
+    int32_t nx, ny, nz, force_mode;   /* 0 II-LBM, 1 IB-LBM */
+    double tau;
+    double cx, cy, cz, radius;         /* the sphere */
+    double f_normal;                   /* F per unit area along the outward normal */
+    int32_t n_markers, pad;            /* IB-LBM markers on the sphere */
+    double body[3];                    /* uniform body force */
+} or3_problem;
+
+static long id3(const or3_problem *p, int i, int x, int y, int z)
+{
+    return (((long)i * p->nz + z) * p->ny + y) * p->nx + x;
+}
+
+static int wrap(int v, int n) { return ((v % n) + n) % n; }
+
+void or3_lattice(int *ex, int *ey, int *ez, double *w)
+{
+    for (int i = 0; i < Q; i++) { ex[i] = EX3[i]; ey[i] = EY3[i]; ez[i] = EZ3[i]; w[i] = wt3(i); }
+}
+
+/* He-Luo incompressible equilibrium, w_i [rho + e.u / c_s^2 + (e.u)^2 / (2 c_s^4)
+ * - u.u / (2 c_s^2)] (Sec. 2.2.1 with nineteen velocities). */
+void or3_equilibrium(double rho, double ux, double uy, double uz, double *feq)
+{
+    double uu = ux * ux + uy * uy + uz * uz;
+    for (int i = 0; i < Q; i++) {
+        double eu = EX3[i] * ux + EY3[i] * uy + EZ3[i] * uz;
+        feq[i] = wt3(i) * (rho + eu / CS2 + eu * eu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
+    }
+}
+
+void or3_moments(const or3_problem *p, const double *f, double *rho, double *ux, double *uy, double *uz)
+{
+    long n = (long)p->nx * p->ny * p->nz;
+    for (long c = 0; c < n; c++) {
+        double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+        for (int i = 0; i < Q; i++) {
+            double v = f[(long)i * n + c];
+            r += v; jx += EX3[i] * v; jy += EY3[i] * v; jz += EZ3[i] * v;
+        }
+        rho[c] = r; ux[c] = jx; uy[c] = jy; uz[c] = jz;
+    }
+}
+
+/* Peskin's four-point regularized delta, one axis (cited in Sec. 2.1.2). */
+static double peskin(double r)
+{
+    double a = fabs(r);
+    if (a <= 1.0) return (3.0 - 2.0 * a + sqrt(1.0 + 4.0 * a - 4.0 * a * a)) / 8.0;
+    if (a <= 2.0) return (5.0 - 2.0 * a - sqrt(-7.0 + 12.0 * a - 4.0 * a * a)) / 8.0;
+    return 0.0;
+}
+
+double or3_peskin(double r) { return peskin(r); }
+
+/* g(x) = sum_k G_k delta_h(x - X_k) dA with G_k = F n_k, n_k the outward radial
+ * normal, dA = 4 pi R^2 / N (Sec. 2.2.2, Eq. (17) on a surface), added to g. */
+void or3_spread(const or3_problem *p, const double *X, double *g)
+{
+    long n = (long)p->nx * p->ny * p->nz;
+    double dA = 4.0 * M_PI * p->radius * p->radius / p->n_markers;
+    for (int k = 0; k < p->n_markers; k++) {
+        double X0 = X[3 * k], Y0 = X[3 * k + 1], Z0 = X[3 * k + 2];
+        double nx_ = (X0 - p->cx) / p->radius, ny_ = (Y0 - p->cy) / p->radius, nz_ = (Z0 - p->cz) / p->radius;
+        double G[3] = {p->f_normal * nx_, p->f_normal * ny_, p->f_normal * nz_};
+        int x0 = (int)floor(X0) - 1, y0 = (int)floor(Y0) - 1, z0 = (int)floor(Z0) - 1;
+        for (int dz = 0; dz < 4; dz++)
+            for (int dy = 0; dy < 4; dy++)
+                for (int dx = 0; dx < 4; dx++) {
+                    int x = x0 + dx, y = y0 + dy, z = z0 + dz;
+                    double wgt = peskin(x - X0) * peskin(y - Y0) * peskin(z - Z0);
+                    long c = ((long)wrap(z, p->nz) * p->ny + wrap(y, p->ny)) * p->nx + wrap(x, p->nx);
+                    for (int a = 0; a < 3; a++) g[a * n + c] += G[a] * wgt * dA;
+                }
+    }
+}
+
+static double phi(const or3_problem *p, double x, double y, double z)
+{
+    return (x - p->cx) * (x - p->cx) + (y - p->cy) * (y - p->cy) + (z - p->cz) * (z - p->cz) -
+           p->radius * p->radius;
+}
+
+/* Cut links of the sphere's level set phi = |x - c|^2 - R^2 (phi < 0 inside):
+ * counts every (x, i) with phi(x) and phi(x + e_i) on different sides. */
+long or3_count_cut_links(const or3_problem *p)
+{
+    long n = 0;
+    for (int z = 0; z < p->nz; z++)
+        for (int y = 0; y < p->ny; y++)
+            for (int x = 0; x < p->nx; x++)
+                for (int i = 1; i < Q; i++) {
+                    int inP = phi(p, x, y, z) < 0.0;
+                    int inQ = phi(p, x + EX3[i], y + EY3[i], z + EZ3[i]) < 0.0;
+                    n += inP != inQ;
+                }
+    return n;
+}
+
+/* One step:
+ *   1. moments of f^n and the force: body force plus (IB-LBM) the spread F n;
+ *   2. SRT collision f* = f - (f - f_eq)/tau + w_i e_i.g / c_s^2;
+ *   3. stream f_i(x) = f*_i(x - e_i) + sigma w_i [[p]] / c_s^2 on every link
+ *      x - e_i -> x that the level set cuts (II-LBM; sigma = +1 from the
+ *      interior), periodic in all three axes. */
+int or3_step(const or3_problem *p, double *f, const double *X)
+{
+    int nx = p->nx, ny = p->ny, nz = p->nz;
+    long n = (long)nx * ny * nz;
+    double *g = calloc(3 * n, sizeof(double)), *fp = malloc((size_t)Q * n * sizeof(double));
+    for (long c = 0; c < n; c++) { g[c] = p->body[0]; g[n + c] = p->body[1]; g[2 * n + c] = p->body[2]; }
+    if (p->force_mode == 1 && p->n_markers > 0) or3_spread(p, X, g);
+    for (long c = 0; c < n; c++) {
+        double fn[Q], r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0, feq[Q];
+        for (int i = 0; i < Q; i++) {
+            fn[i] = f[(long)i * n + c];
+            r += fn[i]; jx += EX3[i] * fn[i]; jy += EY3[i] * fn[i]; jz += EZ3[i] * fn[i];
+        }
+        or3_equilibrium(r, jx, jy, jz, feq);
+        for (int i = 0; i < Q; i++)
+            fp[(long)i * n + c] = fn[i] - (fn[i] - feq[i]) / p->tau +
+                                  wt3(i) * (EX3[i] * g[c] + EY3[i] * g[n + c] + EZ3[i] * g[2 * n + c]) / CS2;
+    }
+    for (int i = 0; i < Q; i++)
+        for (int z = 0; z < nz; z++)
+            for (int y = 0; y < ny; y++)
+                for (int x = 0; x < nx; x++) {
+                    int xs = x - EX3[i], ys = y - EY3[i], zs = z - EZ3[i];
+                    double v = fp[id3(p, i, wrap(xs, nx), wrap(ys, ny), wrap(zs, nz))];
+                    if (p->force_mode == 0) {
+                        int inP = phi(p, xs, ys, zs) < 0.0, inQ = phi(p, x, y, z) < 0.0;
+                        if (inP != inQ) v += (inP ? 1.0 : -1.0) * wt3(i) * p->f_normal / CS2;
+                    }
+                    f[id3(p, i, x, y, z)] = v;
+                }
+    free(g); free(fp);
+    return 0;
+}
+
+int or3_run(const or3_problem *p, double *f, const double *X, int steps)
+{
+    for (int s = 0; s < steps; s++) or3_step(p, f, X);
+    return 0;
+}
+
+int or3_sizeof_problem(void) { return (int)sizeof(or3_problem); }

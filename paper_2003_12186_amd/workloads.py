@@ -283,6 +283,58 @@ def viv_cylinder_e4(D: int, u_red: float, force_mode: int = FORCE_II_LBM, re: fl
     return Workload(p, circle_markers(cx, cy, R, n), 0, {"U": U, "D": D, "u_red": u_red, "re": re})
 
 
+@dataclasses.dataclass
+class Problem3:
+    """A D3Q19 box with a fixed sphere carrying a uniform normal force."""
+    nx: int
+    ny: int
+    nz: int
+    tau: float
+    center: Sequence[float] = (0.0, 0.0, 0.0)
+    radius: float = 0.0
+    f_normal: float = 0.0                      # F per unit area along the outward normal
+    force_mode: int = FORCE_II_LBM             # FORCE_II_LBM (jumps) or FORCE_IB_LBM (spread)
+    n_markers: int = 0                         # IB-LBM markers on the sphere
+    body_force: Sequence[float] = (0.0, 0.0, 0.0)
+
+
+def sphere_markers(c: Sequence[float], R: float, n: int) -> np.ndarray:
+    """n points spread evenly over a sphere (the Fibonacci lattice)."""
+    k = np.arange(n) + 0.5
+    z = 1.0 - 2.0 * k / n
+    r = np.sqrt(1.0 - z * z)
+    ph = np.pi * (3.0 - math.sqrt(5.0)) * k
+    return np.stack([c[0] + R * r * np.cos(ph), c[1] + R * r * np.sin(ph), c[2] + R * z], 1)
+
+
+def normal_force_sphere(D: int, force_mode: int = FORCE_II_LBM) -> Tuple[Problem3, np.ndarray, dict]:
+    """The uniform normal force on a fixed sphere, the three-dimensional form of
+    Sec. 4.1: a periodic box of side 2D + 2 with the sphere of diameter D at
+    its centre, nu = 0.05, U = nu 100 / D, F = U^2, run to t = D/U; IB-LBM
+    markers about 1 lu apart."""
+    nu = 0.05
+    U = nu * 100.0 / D
+    L = 2 * D + 2
+    R = D / 2.0
+    n = int(math.ceil(4.0 * math.pi * R * R))
+    c = (L / 2.0, L / 2.0, L / 2.0)
+    p = Problem3(nx=L, ny=L, nz=L, tau=0.5 + 3.0 * nu, center=c, radius=R, f_normal=U * U,
+                 force_mode=force_mode, n_markers=n if force_mode == FORCE_IB_LBM else 0)
+    X = sphere_markers(c, R, n) if force_mode == FORCE_IB_LBM else np.zeros((1, 3))
+    return p, X, {"U": U, "D": D, "steps": int(round(D / U))}
+
+
+def normal_force_sphere_state(p: Problem3) -> np.ndarray:
+    """The exact solution as a state: at rest, rho = 1 - 3 F inside the sphere's
+    level set and 1 outside, f_i = w_i rho."""
+    w = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+    z, y, x = np.mgrid[0:p.nz, 0:p.ny, 0:p.nx]
+    c = p.center
+    inside = (x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2 - p.radius ** 2 < 0.0
+    rho = np.where(inside, 1.0 - 3.0 * p.f_normal, 1.0)
+    return np.ascontiguousarray(w[:, None, None, None] * rho[None])
+
+
 def elastic_membrane_e2(L: int, force_mode: int = FORCE_II_LBM, storage: int = STORE_FP32) -> Workload:
     """Thin elastic membrane of Sec. 4.2: ellipse a = 0.35 L, b = 0.25^2/0.35 L
     centred in a walled L x L box, MRT, kappa_bar = kappa/(U^2 L) = 0.1,
