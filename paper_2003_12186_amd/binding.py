@@ -310,3 +310,101 @@ class Sim:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# The D3Q19 form (include/ii_lbm3.h).
+# ---------------------------------------------------------------------------
+class Problem3C(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("force_mode", C.c_int32),
+                ("tau", C.c_double), ("body_force", C.c_double * 3), ("center", C.c_double * 3),
+                ("radius", C.c_double), ("f_normal", C.c_double), ("n_markers", C.c_int32),
+                ("pad", C.c_int32)]
+
+
+EXPORTS3 = ["ii_lbm3_init", "ii_lbm3_step", "ii_lbm3_set_distrib", "ii_lbm3_fields",
+            "ii_lbm3_set_timing", "ii_lbm3_get_timing", "ii_lbm3_sweep_bytes", "ii_lbm3_destroy"]
+
+
+def _lib3():
+    lib = load()
+    if not getattr(lib, "_iilbm3_sigs", False):
+        v, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        sigs = {
+            "ii_lbm3_init": [C.POINTER(Problem3C), v, v, C.POINTER(v)],
+            "ii_lbm3_step": [v, i64],
+            "ii_lbm3_set_distrib": [v, v],
+            "ii_lbm3_fields": [v, v],
+            "ii_lbm3_set_timing": [v, i32],
+            "ii_lbm3_get_timing": [v, C.POINTER(d), C.POINTER(i64)],
+            "ii_lbm3_sweep_bytes": [v, C.POINTER(d)],
+            "ii_lbm3_destroy": [v],
+        }
+        for name, args in sigs.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = C.c_int
+        lib._iilbm3_sigs = True
+    return lib
+
+
+def make_problem3(w) -> Problem3C:
+    p = Problem3C()
+    p.nx, p.ny, p.nz = int(w.nx), int(w.ny), int(w.nz)
+    p.force_mode = int(w.force_mode)
+    p.tau = float(w.tau)
+    for a in range(3):
+        p.body_force[a] = float(w.body_force[a])
+        p.center[a] = float(w.center[a])
+    p.radius, p.f_normal = float(w.radius), float(w.f_normal)
+    p.n_markers = int(w.n_markers)
+    return p
+
+
+class Sim3:
+    """A D3Q19 handle: a periodic box with an optional normal-force sphere."""
+
+    def __init__(self, problem, X0=None):
+        self.p = problem if isinstance(problem, Problem3C) else make_problem3(problem)
+        self.h = C.c_void_p()
+        X = None if X0 is None else np.ascontiguousarray(X0, dtype=np.float64)
+        self._X = X
+        check(_lib3().ii_lbm3_init(C.byref(self.p), None if X is None else X.ctypes.data, None,
+                                   C.byref(self.h)), "init3")
+
+    def step(self, n: int) -> None:
+        check(_lib3().ii_lbm3_step(self.h, int(n)), "step3")
+
+    def set_distrib(self, f: np.ndarray) -> None:
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        assert f.shape == (19, self.p.nz, self.p.ny, self.p.nx)
+        check(_lib3().ii_lbm3_set_distrib(self.h, f.ctypes.data), "set_distrib3")
+
+    def fields(self) -> np.ndarray:
+        out = np.zeros((4, self.p.nz, self.p.ny, self.p.nx))
+        check(_lib3().ii_lbm3_fields(self.h, out.ctypes.data), "fields3")
+        return out
+
+    def set_timing(self, on: bool) -> None:
+        check(_lib3().ii_lbm3_set_timing(self.h, 1 if on else 0), "set_timing3")
+
+    def get_timing(self):
+        ms = C.c_double(); n = C.c_int64()
+        check(_lib3().ii_lbm3_get_timing(self.h, C.byref(ms), C.byref(n)), "get_timing3")
+        return ms.value, n.value
+
+    def sweep_bytes(self) -> float:
+        b = C.c_double()
+        check(_lib3().ii_lbm3_sweep_bytes(self.h, C.byref(b)), "sweep_bytes3")
+        return b.value
+
+    def close(self) -> None:
+        if getattr(self, "h", None) is not None and self.h.value:
+            _lib3().ii_lbm3_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

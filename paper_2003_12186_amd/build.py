@@ -28,6 +28,7 @@ UNITS = {
     "interface.hip": ["-ffp-contract=off"],
     "runtime.hip": [],
     "learned.hip": [],
+    "d3q19.hip": ["-ffp-contract=off"],
 }
 
 

@@ -1,0 +1,389 @@
+// D3Q19 form of the II-LBM on one MI355X: a periodic box, SRT with the He-Luo
+// equilibrium and the simple force term, and a fixed sphere with a uniform
+// normal force entered as jumps on the links its level set cuts (II-LBM) or as
+// a force field spread from surface markers (IB-LBM).
+//
+// Storage: FP32 deviations d_i = f_i - w_i, planes [19][nz][ny][pitch].  The
+// sweep pulls d_i from x - e_i, collides, adds the force term and (II-LBM) the
+// jumps of the links this node sends, and stores once at x, so the next pull
+// reads f^{n+1}_i(x + e_i) with its jump already in place.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <vector>
+
+#include "../../include/ii_lbm3.h"
+
+namespace iilbm3 {
+
+constexpr int kQ = 19;
+constexpr int E3X[kQ] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int E3Y[kQ] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int E3Z[kQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+constexpr double W3D[kQ] = {1.0 / 3.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,
+                            1.0 / 18.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+                            1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+                            1.0 / 36.0};
+constexpr int kBX = 256;
+
+struct Box {
+    int nx, ny, nz, pitch;
+    long long plane;        // elements per population (pitch * ny * nz)
+    double omega;
+    double g[3];            // body force
+    int sphere, ib;
+    double cx, cy, cz, R, F;
+};
+
+__device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// Level set of the sphere, |x - c|^2 - R^2 (interior < 0), in FP64.
+__device__ __forceinline__ double sphere_phi(const Box& b, double x, double y, double z)
+{
+    const double dx = x - b.cx, dy = y - b.cy, dz = z - b.cz;
+    return dx * dx + dy * dy + dz * dz - b.R * b.R;
+}
+
+template <bool IB>
+__global__ __launch_bounds__(kBX) void k_sweep3(Box b, const float* __restrict__ A,
+                                                float* __restrict__ B,
+                                                const double* __restrict__ gfield)
+{
+    const int x = blockIdx.x * kBX + threadIdx.x;
+    const int y = blockIdx.y, z = blockIdx.z;
+    if (x >= b.nx) return;
+    const long long row = ((long long)z * b.ny + y) * b.pitch;
+    double d[kQ];
+#pragma unroll
+    for (int i = 0; i < kQ; i++) {
+        const int xs = wrapi(x - E3X[i], b.nx), ys = wrapi(y - E3Y[i], b.ny), zs = wrapi(z - E3Z[i], b.nz);
+        d[i] = (double)A[i * b.plane + ((long long)zs * b.ny + ys) * b.pitch + xs];
+    }
+    // moments of the deviations: rho - 1 and j = sum e d
+    double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+    for (int i = 0; i < kQ; i++) {
+        r += d[i];
+        jx += E3X[i] * d[i];
+        jy += E3Y[i] * d[i];
+        jz += E3Z[i] * d[i];
+    }
+    double gx = b.g[0], gy = b.g[1], gz = b.g[2];
+    if (IB) {
+        const long long c = ((long long)z * b.ny + y) * b.nx + x;
+        const long long n = (long long)b.nx * b.ny * b.nz;
+        gx += gfield[c];
+        gy += gfield[n + c];
+        gz += gfield[2 * n + c];
+    }
+    const double jj = jx * jx + jy * jy + jz * jz;
+    // He-Luo equilibrium deviation w_i [dr + 3 e.j + 4.5 (e.j)^2 - 1.5 j.j],
+    // SRT relaxation and the force term 3 w_i e.g
+#pragma unroll
+    for (int i = 0; i < kQ; i++) {
+        const double ej = E3X[i] * jx + E3Y[i] * jy + E3Z[i] * jz;
+        const double eg = E3X[i] * gx + E3Y[i] * gy + E3Z[i] * gz;
+        const double deq = W3D[i] * (r + 3.0 * ej + 4.5 * ej * ej - 1.5 * jj);
+        d[i] = d[i] + b.omega * (deq - d[i]) + 3.0 * W3D[i] * eg;
+    }
+    if (!IB && b.sphere) {
+        // jumps of the links this node sends (Sec. 3.1, Eq. (32)): only a node
+        // within sqrt 2 of the sphere can send a cut link
+        const double ph = sphere_phi(b, x, y, z);
+        const double dist = fabs(sqrt(ph + b.R * b.R) - b.R);
+        if (dist <= 1.5) {
+            const bool inP = ph < 0.0;
+#pragma unroll
+            for (int i = 1; i < kQ; i++) {
+                const bool inQ = sphere_phi(b, x + E3X[i], y + E3Y[i], z + E3Z[i]) < 0.0;
+                if (inP != inQ) d[i] += (inP ? 1.0 : -1.0) * W3D[i] * 3.0 * b.F;
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < kQ; i++) __builtin_nontemporal_store((float)d[i], B + i * b.plane + row + x);
+}
+
+// IB-LBM force field g(x) = sum_k F n_k delta_h(x - X_k) dA, one thread per
+// (marker, stencil node); FP64 atomics (the field is built once).
+__device__ __forceinline__ double peskin1(double r)
+{
+    const double a = fabs(r);
+    if (a <= 1.0) return (3.0 - 2.0 * a + sqrt(1.0 + 4.0 * a - 4.0 * a * a)) * 0.125;
+    if (a <= 2.0) return (5.0 - 2.0 * a - sqrt(-7.0 + 12.0 * a - 4.0 * a * a)) * 0.125;
+    return 0.0;
+}
+
+__global__ void k_spread3(Box b, const double* __restrict__ X, int N, double dA,
+                          double* __restrict__ g)
+{
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t >= (long long)N * 64) return;
+    const int k = (int)(t >> 6), s = (int)(t & 63);
+    const double X0 = X[3 * k], Y0 = X[3 * k + 1], Z0 = X[3 * k + 2];
+    const int x = (int)floor(X0) - 1 + (s & 3), y = (int)floor(Y0) - 1 + ((s >> 2) & 3),
+              z = (int)floor(Z0) - 1 + (s >> 4);
+    const double w = peskin1(x - X0) * peskin1(y - Y0) * peskin1(z - Z0);
+    if (w == 0.0) return;
+    const double nx_ = (X0 - b.cx) / b.R, ny_ = (Y0 - b.cy) / b.R, nz_ = (Z0 - b.cz) / b.R;
+    const long long n = (long long)b.nx * b.ny * b.nz;
+    const long long c = ((long long)wrapi(z, b.nz) * b.ny + wrapi(y, b.ny)) * b.nx + wrapi(x, b.nx);
+    atomicAdd(&g[c], b.F * nx_ * w * dA);
+    atomicAdd(&g[n + c], b.F * ny_ * w * dA);
+    atomicAdd(&g[2 * n + c], b.F * nz_ * w * dA);
+}
+
+// rho, u of f^n (the pulled populations) into out[4][nz][ny][nx] (device).
+__global__ void k_fields3(Box b, const float* __restrict__ A, double* __restrict__ out)
+{
+    const long long n = (long long)b.nx * b.ny * b.nz;
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
+         c += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(c % b.nx), y = (int)((c / b.nx) % b.ny), z = (int)(c / ((long long)b.nx * b.ny));
+        double r = 1.0, ux = 0.0, uy = 0.0, uz = 0.0;
+        for (int i = 0; i < kQ; i++) {
+            const int xs = wrapi(x - E3X[i], b.nx), ys = wrapi(y - E3Y[i], b.ny), zs = wrapi(z - E3Z[i], b.nz);
+            const double v = (double)A[i * b.plane + ((long long)zs * b.ny + ys) * b.pitch + xs];
+            r += v;
+            ux += E3X[i] * v;
+            uy += E3Y[i] * v;
+            uz += E3Z[i] * v;
+        }
+        out[c] = r;
+        out[n + c] = ux;
+        out[2 * n + c] = uy;
+        out[3 * n + c] = uz;
+    }
+}
+
+// stored_i(x) = f_i(x + e_i) - w_i, so that the next pull yields f.
+__global__ void k_set3(Box b, const double* __restrict__ f, float* __restrict__ A)
+{
+    const long long n = (long long)b.nx * b.ny * b.nz;
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
+         c += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(c % b.nx), y = (int)((c / b.nx) % b.ny), z = (int)(c / ((long long)b.nx * b.ny));
+        for (int i = 0; i < kQ; i++) {
+            const int xd = wrapi(x + E3X[i], b.nx), yd = wrapi(y + E3Y[i], b.ny), zd = wrapi(z + E3Z[i], b.nz);
+            const double v = f[i * n + ((long long)zd * b.ny + yd) * b.nx + xd] - W3D[i];
+            A[i * b.plane + ((long long)z * b.ny + y) * b.pitch + x] = (float)v;
+        }
+    }
+}
+
+__global__ void k_zero3(float* p, long long n)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = 0.f;
+}
+
+}  // namespace iilbm3
+
+using namespace iilbm3;
+
+struct ii_lbm3_handle {
+    Box b;
+    hipStream_t stream;
+    float* lat[2] = {nullptr, nullptr};
+    double* g = nullptr;
+    int parity = 0;
+    bool timing = false;
+    std::vector<hipEvent_t> ev;
+    int ev_used = 0;
+    double ms = 0.0;
+    long long launches = 0;
+};
+
+static int fail3(hipError_t e) { return e == hipSuccess ? II_LBM_OK : II_LBM_EDEVICE; }
+
+extern "C" {
+
+int ii_lbm3_init(const ii_lbm3_problem* p, const double* X0, void* hip_stream, ii_lbm3_handle** out)
+{
+    if (!p || !out) return II_LBM_EINVAL;
+    *out = nullptr;
+    if (p->nx < 8 || p->ny < 8 || p->nz < 8 || p->nx > 1024 || p->ny > 1024 || p->nz > 1024)
+        return II_LBM_EINVAL;
+    if (!(p->tau > 0.5) || !isfinite(p->tau)) return II_LBM_EINVAL;
+    if (p->force_mode != II_LBM_FORCE_II && p->force_mode != II_LBM_FORCE_IB) return II_LBM_EINVAL;
+    const bool sphere = p->radius > 0.0;
+    if (sphere) {
+        const double c[3] = {p->center[0], p->center[1], p->center[2]};
+        const int n[3] = {p->nx, p->ny, p->nz};
+        for (int a = 0; a < 3; a++)
+            if (!(c[a] - p->radius >= 3.0 && c[a] + p->radius <= n[a] - 4.0)) return II_LBM_EGEOMETRY;
+        if (!isfinite(p->f_normal)) return II_LBM_EINVAL;
+        if (p->force_mode == II_LBM_FORCE_IB) {
+            if (p->n_markers < 4 || !X0) return II_LBM_EINVAL;
+            // the spread's 4 x 4 x 4 stencil must stay one wrap from the box
+            for (int k = 0; k < p->n_markers; k++)
+                for (int a = 0; a < 3; a++) {
+                    const double v = X0[3 * k + a];
+                    if (!isfinite(v)) return II_LBM_EINVAL;
+                    if (!(v >= 2.0 && v <= n[a] - 3.0)) return II_LBM_EGEOMETRY;
+                }
+        }
+    }
+    ii_lbm3_handle* h = new ii_lbm3_handle();
+    Box& b = h->b;
+    b.nx = p->nx; b.ny = p->ny; b.nz = p->nz;
+    b.pitch = (p->nx + 63) / 64 * 64;
+    b.plane = (long long)b.pitch * b.ny * b.nz;
+    b.omega = 1.0 / p->tau;
+    for (int a = 0; a < 3; a++) b.g[a] = p->body_force[a];
+    b.sphere = sphere;
+    b.ib = sphere && p->force_mode == II_LBM_FORCE_IB;
+    b.cx = p->center[0]; b.cy = p->center[1]; b.cz = p->center[2];
+    b.R = p->radius; b.F = p->f_normal;
+    h->stream = (hipStream_t)hip_stream;
+    const size_t lat = (size_t)kQ * b.plane * sizeof(float);
+    hipError_t e = hipMalloc(&h->lat[0], lat);
+    if (e == hipSuccess) e = hipMalloc(&h->lat[1], lat);
+    const long long n = (long long)b.nx * b.ny * b.nz;
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_zero3, dim3(2048), dim3(256), 0, h->stream, h->lat[0], (long long)kQ * b.plane);
+        hipLaunchKernelGGL(k_zero3, dim3(2048), dim3(256), 0, h->stream, h->lat[1], (long long)kQ * b.plane);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && b.ib) {
+        e = hipMalloc(&h->g, (size_t)3 * n * sizeof(double));
+        double* dX = nullptr;
+        if (e == hipSuccess) e = hipMemsetAsync(h->g, 0, (size_t)3 * n * sizeof(double), h->stream);
+        if (e == hipSuccess) e = hipMalloc(&dX, (size_t)3 * p->n_markers * sizeof(double));
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(dX, X0, (size_t)3 * p->n_markers * sizeof(double), hipMemcpyHostToDevice,
+                               h->stream);
+        if (e == hipSuccess) {
+            const double dA = 4.0 * M_PI * b.R * b.R / p->n_markers;
+            const long long threads = (long long)p->n_markers * 64;
+            hipLaunchKernelGGL(k_spread3, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, h->stream, b,
+                               dX, p->n_markers, dA, h->g);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (dX) (void)hipFree(dX);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+        ii_lbm3_destroy(h);
+        return II_LBM_EDEVICE;
+    }
+    *out = h;
+    return II_LBM_OK;
+}
+
+int ii_lbm3_step(ii_lbm3_handle* h, int64_t n_steps)
+{
+    if (!h || n_steps < 0) return II_LBM_EINVAL;
+    const Box& b = h->b;
+    const dim3 grid((b.nx + kBX - 1) / kBX, b.ny, b.nz);
+    for (int64_t s = 0; s < n_steps; s++) {
+        const bool t = h->timing;
+        if (t) {
+            if (h->ev_used + 2 > (int)h->ev.size()) {
+                hipEvent_t a, c;
+                if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&c) != hipSuccess) return II_LBM_EDEVICE;
+                h->ev.push_back(a);
+                h->ev.push_back(c);
+            }
+            (void)hipEventRecord(h->ev[h->ev_used], h->stream);
+        }
+        if (b.ib)
+            hipLaunchKernelGGL(k_sweep3<true>, grid, dim3(kBX), 0, h->stream, b, h->lat[h->parity],
+                               h->lat[h->parity ^ 1], h->g);
+        else
+            hipLaunchKernelGGL(k_sweep3<false>, grid, dim3(kBX), 0, h->stream, b, h->lat[h->parity],
+                               h->lat[h->parity ^ 1], h->g);
+        if (t) {
+            (void)hipEventRecord(h->ev[h->ev_used + 1], h->stream);
+            h->ev_used += 2;
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return II_LBM_EDEVICE;
+        h->parity ^= 1;
+    }
+    return II_LBM_OK;
+}
+
+int ii_lbm3_set_distrib(ii_lbm3_handle* h, const double* f)
+{
+    if (!h || !f) return II_LBM_EINVAL;
+    const Box& b = h->b;
+    const long long n = (long long)b.nx * b.ny * b.nz;
+    double* df = nullptr;
+    hipError_t e = hipMalloc(&df, (size_t)kQ * n * sizeof(double));
+    if (e == hipSuccess) e = hipMemcpyAsync(df, f, (size_t)kQ * n * sizeof(double), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_set3, dim3(1024), dim3(256), 0, h->stream, b, df, h->lat[h->parity]);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (df) (void)hipFree(df);
+    return fail3(e);
+}
+
+int ii_lbm3_fields(ii_lbm3_handle* h, double* out)
+{
+    if (!h || !out) return II_LBM_EINVAL;
+    const Box& b = h->b;
+    const long long n = (long long)b.nx * b.ny * b.nz;
+    double* d = nullptr;
+    hipError_t e = hipMalloc(&d, (size_t)4 * n * sizeof(double));
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_fields3, dim3(1024), dim3(256), 0, h->stream, b, h->lat[h->parity], d);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(out, d, (size_t)4 * n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (d) (void)hipFree(d);
+    return fail3(e);
+}
+
+int ii_lbm3_set_timing(ii_lbm3_handle* h, int32_t enable)
+{
+    if (!h) return II_LBM_EINVAL;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return II_LBM_EDEVICE;
+    h->timing = enable != 0;
+    h->ev_used = 0;
+    return II_LBM_OK;
+}
+
+int ii_lbm3_get_timing(ii_lbm3_handle* h, double* ms, int64_t* launches)
+{
+    if (!h || !ms || !launches) return II_LBM_EINVAL;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return II_LBM_EDEVICE;
+    double total = 0.0;
+    for (int k = 0; k + 1 < h->ev_used; k += 2) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, h->ev[k], h->ev[k + 1]) != hipSuccess) return II_LBM_EDEVICE;
+        total += t;
+    }
+    *ms = total;
+    *launches = h->ev_used / 2;
+    return II_LBM_OK;
+}
+
+int ii_lbm3_sweep_bytes(ii_lbm3_handle* h, double* bytes)
+{
+    if (!h || !bytes) return II_LBM_EINVAL;
+    const double n = (double)h->b.nx * h->b.ny * h->b.nz;
+    *bytes = n * (2.0 * kQ * 4.0 + (h->b.ib ? 24.0 : 0.0));
+    return II_LBM_OK;
+}
+
+int ii_lbm3_destroy(ii_lbm3_handle* h)
+{
+    if (!h) return II_LBM_EINVAL;
+    (void)hipStreamSynchronize(h->stream);
+    for (auto& p : h->lat)
+        if (p) (void)hipFree(p);
+    if (h->g) (void)hipFree(h->g);
+    for (auto& ev : h->ev) (void)hipEventDestroy(ev);
+    delete h;
+    return II_LBM_OK;
+}
+
+}  // extern "C"

@@ -307,13 +307,14 @@ def sphere_markers(c: Sequence[float], R: float, n: int) -> np.ndarray:
     return np.stack([c[0] + R * r * np.cos(ph), c[1] + R * r * np.sin(ph), c[2] + R * z], 1)
 
 
-def normal_force_sphere(D: int, force_mode: int = FORCE_II_LBM) -> Tuple[Problem3, np.ndarray, dict]:
+def normal_force_sphere(D: int, force_mode: int = FORCE_II_LBM,
+                        re: float = 100.0) -> Tuple[Problem3, np.ndarray, dict]:
     """The uniform normal force on a fixed sphere, the three-dimensional form of
     Sec. 4.1: a periodic box of side 2D + 2 with the sphere of diameter D at
-    its centre, nu = 0.05, U = nu 100 / D, F = U^2, run to t = D/U; IB-LBM
-    markers about 1 lu apart."""
+    its centre, nu = 0.05, U = nu Re / D (Re = 100 in Sec. 4.1), F = U^2, run
+    to t = D/U; IB-LBM markers about 1 lu apart."""
     nu = 0.05
-    U = nu * 100.0 / D
+    U = nu * re / D
     L = 2 * D + 2
     R = D / 2.0
     n = int(math.ceil(4.0 * math.pi * R * R))

@@ -139,3 +139,38 @@ def test_learned_calls_reject_null_arguments_without_a_device():
     assert lib.ii_lbm_learned_tiles(None, 16, None, None) == B.EINVAL
     assert lib.ii_lbm_learned_infer(None, None, None, None, 16, None, None, None, None, None) == B.EINVAL
     assert lib.ii_lbm_set_learned(None, None, None, None, 16, None, None, None, None, None) == B.EINVAL
+
+
+HEADER3 = os.path.join(ROOT, "include", "ii_lbm3.h")
+
+
+def test_d3q19_header_calls_are_exported_and_sized(tmp_path):
+    src = open(HEADER3).read()
+    names = sorted(set(re.findall(r"\b(ii_lbm3_[a-z_]+)\s*\(", src)))
+    lib = B.load()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(B.EXPORTS3) == names
+    prog = tmp_path / "sz3.c"
+    prog.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "ii_lbm3.h"\n'
+        "int main(void){printf(\"%zu %zu %zu\\n\", sizeof(ii_lbm3_problem),"
+        " offsetof(ii_lbm3_problem, radius), offsetof(ii_lbm3_problem, n_markers));return 0;}\n")
+    exe = tmp_path / "sz3"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.dirname(HEADER3), str(prog), "-o", str(exe)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    assert got == [C.sizeof(B.Problem3C), B.Problem3C.radius.offset, B.Problem3C.n_markers.offset]
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (lambda p: setattr(p, "nx", 4), B.EINVAL),
+    (lambda p: setattr(p, "tau", 0.5), B.EINVAL),
+    (lambda p: setattr(p, "force_mode", 2), B.EINVAL),
+    (lambda p: p.center.__setitem__(0, 2.0), B.EGEOMETRY),      # sphere too near a side
+])
+def test_d3q19_init_validation_rejects_before_device_access(mutate, code):
+    prob, _, _ = W.normal_force_sphere(16, W.FORCE_II_LBM, re=20.0)
+    p = B.make_problem3(prob)
+    mutate(p)
+    h = C.c_void_p()
+    assert B._lib3().ii_lbm3_init(C.byref(p), None, None, C.byref(h)) == code
