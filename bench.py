@@ -15,8 +15,8 @@ and the FP64 CPU oracle timed on a bounded sample of the same workload.
 Other workloads (--workload): batch512, learned, cylinder, area (the
 elastic-membrane area comparison of Sec. 4.2 under the four force modes) and
 table1 (the normal-force circle of Sec. 4.1, II-LBM against IB-LBM), cyltables
-(uniform flow past a cylinder, Sec. 4.3) and viv (the freely vibrating cylinder
-of Sec. 4.5).
+(uniform flow past a cylinder, Sec. 4.3), viv (the freely vibrating cylinder
+of Sec. 4.5) and d3q19 (the three-dimensional form with a normal-force sphere).
 """
 from __future__ import annotations
 
@@ -41,9 +41,12 @@ PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "sweep_traffic_membrane4096.jso
 SWEEP_SOURCES = [os.path.join(ROOT, "paper_2003_12186_amd", "csrc", n) for n in ("sweep.hip", "common.hpp")]
 
 
-def sweep_source_hash() -> str:
+D3_SOURCES = [os.path.join(ROOT, "paper_2003_12186_amd", "csrc", "d3q19.hip")]
+
+
+def sweep_source_hash(sources=None) -> str:
     h = hashlib.sha256()
-    for p in SWEEP_SOURCES:
+    for p in (sources or SWEEP_SOURCES):
         h.update(open(p, "rb").read())
     return h.hexdigest()[:16]
 
@@ -56,7 +59,8 @@ def measured_traffic(storage: str):
     except (OSError, ValueError):
         return None
     ent = d.get(storage)
-    if not ent or ent.get("source_hash") != sweep_source_hash():
+    srcs = D3_SOURCES if storage.startswith("d3q19") else None
+    if not ent or ent.get("source_hash") != sweep_source_hash(srcs):
         return None
     return ent.get("bytes_per_launch")
 
@@ -657,6 +661,80 @@ def bench_cylinder_tables(args, B, W) -> int:
     return 0
 
 
+def bench_d3q19(args, B, W) -> int:
+    """The D3Q19 form: the sweep on a 256^3 periodic box holding a sphere of
+    diameter 128 with a uniform normal force (II-LBM jumps fused into the
+    sweep), timed with HIP events against its algorithmic bytes (19 loads + 19
+    stores of 4 bytes per node); then the three-dimensional form of Table 1
+    (Sec. 4.1): the normal-force sphere at D = 32 and 64 (Re = 100) under
+    II-LBM and IB-LBM to t = D/U, from rest and from the exact state, with the
+    L2 and Linf velocity errors over U."""
+    import numpy as np
+    import torch
+    L = args.d3_size
+    c = (L / 2.0, L / 2.0, L / 2.0)
+    big = W.Problem3(nx=L, ny=L, nz=L, tau=0.8, center=c, radius=L / 4.0, f_normal=1e-3)
+    sim = B.Sim3(big)
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    sim.set_timing(True)
+    sim.step(min(args.steps, 200))
+    ms, launches = sim.get_timing()
+    sim.set_timing(False)
+    avg = ms / 1e3 / max(launches, 1)
+    bpl = sim.sweep_bytes()
+    sim.close()
+    nodes = float(L) ** 3
+    rows = []
+    for start in (("exact", "rest") if args.d3_table == "on" else ()):
+        for D in (32, 64):
+            for mode, name in ((W.FORCE_II_LBM, "II-LBM"), (W.FORCE_IB_LBM, "IB-LBM")):
+                prob, X, meta = W.normal_force_sphere(D, mode)
+                s3 = B.Sim3(prob, X if mode == W.FORCE_IB_LBM else None)
+                if start == "exact":
+                    s3.set_distrib(W.normal_force_sphere_state(prob))
+                s3.step(meta["steps"])
+                g = s3.fields()
+                U = meta["U"]
+                rows.append({"start": start, "D": D, "method": name, "steps": meta["steps"],
+                             "L2": float(np.sqrt((g[1] ** 2 + g[2] ** 2 + g[3] ** 2).mean()) / U),
+                             "Linf": float(max(np.abs(g[a]).max() for a in (1, 2, 3)) / U)})
+                print(f"[d3q19] {start} D={D} {name}: L2 {rows[-1]['L2']:.3e} Linf {rows[-1]['Linf']:.3e}",
+                      file=sys.stderr, flush=True)
+                s3.close()
+    out = {
+        "metric": "MLUPS & %HBM peak; learned 2x-coarse vs fine II-LBM time at <=1e-2 L2 err",
+        "value": round(nodes * args.steps / dt / 1e6, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3 / args.steps, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 storage / fp64 collision", "data": "synthetic",
+        "config": {"workload": f"d3q19_sphere{L}", "nx": L, "ny": L, "nz": L, "sphere_D": L // 2,
+                   "table1_3d": rows},
+        "roofline": {"bound": "hbm", "kernel": "k_sweep3", "achieved": round(bpl / avg / 1e9, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(bpl / avg / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(f"d3q19_{L}"), "bytes_per_launch": bpl,
+                     "avg_launch_us": round(avg * 1e6, 2), "timed_launches": launches},
+    }
+    if not args.no_cpu:
+        from oracle import d3q19 as O3
+        prob, X, meta = W.normal_force_sphere(16, W.FORCE_II_LBM, re=20.0)
+        p = O3.make_problem(prob)
+        f = O3.rest_state(p)
+        n = 4 * args.cpu_steps
+        t0 = time.perf_counter()
+        O3.run(p, f, X, n)
+        dtc = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(prob.nx ** 3 * n / dtc / 1e6, 3), "unit": "MLUPS", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"{n} FP64 oracle steps of the D = 16 sphere ({prob.nx}^3) ({dtc:.1f} s)"}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 # Sec. 4.5: maximum transverse amplitude / D of the freely vibrating cylinder
 # (rho* = 8/pi, zeta = 0) for U_red = 3 .. 8.
 PAPER_VIV = {3.0: 0.075, 4.0: 0.551, 5.0: 0.520, 6.0: 0.459, 7.0: 0.370, 8.0: 0.084}
@@ -841,13 +919,16 @@ def main() -> int:
                          "(1e-3 bar)")
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--workload", choices=["membrane", "batch512", "learned", "cylinder", "area",
-                                           "table1", "viv", "cyltables"],
+                                           "table1", "viv", "cyltables", "d3q19"],
                     default="membrane",
                     help="membrane: one L x L membrane (the bench line); batch512: 512 uneven "
                          "membrane instances advanced together; learned: 200 coarse membranes "
                          "with the learned correction every step against their fine runs (both "
                          "reported in the design notes)")
     ap.add_argument("--re", type=float, default=100.0, help="Reynolds number of the cylinder workload")
+    ap.add_argument("--d3-size", type=int, default=256, help="box side of the d3q19 workload")
+    ap.add_argument("--d3-table", choices=["on", "off"], default="on",
+                    help="run the three-dimensional Table 1 cases after the d3q19 sweep timing")
     ap.add_argument("--cyl-sizes", default="20,40",
                     help="cylinder diameters D of the cyltables workload (Sec. 4.3; 80 is the paper's finest)")
     ap.add_argument("--viv-ured", default="3,4,5,6,7,8",
@@ -905,6 +986,8 @@ def main() -> int:
         return bench_viv(args, B, W)
     if args.workload == "cyltables":
         return bench_cylinder_tables(args, B, W)
+    if args.workload == "d3q19":
+        return bench_d3q19(args, B, W)
     storage = W.STORE_FP16 if args.storage == "fp16" else W.STORE_FP32
     w = W.membrane_c3(L=args.size, storage=storage)
     p = w.problem
