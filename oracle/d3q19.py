@@ -3,7 +3,9 @@
 TEST INFRASTRUCTURE ONLY: imported by ``tests/`` and the CPU-baseline leg of
 ``bench.py``.  The GPU library never imports, links or calls it.
 
-Arrays: f[19][nz][ny][nx] float64 (C order), sphere markers X[N][3].
+Arrays: f[19][nz][ny][nx] float64 (C order), sphere markers X[N][3]; a
+triangulated surface is vertices X[nv][3] float64, triangles tri[nt][3] int32
+(counter-clockwise seen from outside) and vertex jump values pv[nv].
 """
 from __future__ import annotations
 
@@ -53,6 +55,9 @@ def lib():
             "or3_step": (C.c_int, [P, d, d]),
             "or3_run": (C.c_int, [P, d, d, C.c_int]),
             "or3_sizeof_problem": (C.c_int, []),
+            "or3_mesh_links": (C.c_long, [P, C.c_int, d, C.c_int, d, d, d, d, C.c_long]),
+            "or3_step_mesh": (C.c_int, [P, d, C.c_int, d, C.c_int, d, d]),
+            "or3_run_mesh": (C.c_int, [P, d, C.c_int, d, C.c_int, d, d, C.c_int]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(_lib, name)
@@ -124,3 +129,33 @@ def run(p: Problem3, f, X, steps: int):
     assert f.dtype == np.float64 and f.flags["C_CONTIGUOUS"] and f.shape == (19, p.nz, p.ny, p.nx)
     Xp = np.ascontiguousarray(X if X is not None else np.zeros((1, 3)), dtype=np.float64)
     lib().or3_run(C.byref(p), _ptr(f), _ptr(Xp), int(steps))
+
+
+def _mesh_args(X, tri, pv):
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    pv = np.ascontiguousarray(np.broadcast_to(np.asarray(pv, dtype=np.float64), (len(X),)))
+    return X, tri, pv
+
+
+def mesh_links(p: Problem3, X, tri, pv) -> dict:
+    """Cut links of a closed triangulated surface (reading R29): sending node
+    (x, y, z), direction, sigma (+1 from the inside), triangle, [[p]] and the
+    barycentric weights of the crossing."""
+    X, tri, pv = _mesh_args(X, tri, pv)
+    cap = 64 * len(tri) + 4096
+    rec = np.zeros((cap, 6), np.int32)
+    val = np.zeros((cap, 4))
+    n = lib().or3_mesh_links(C.byref(p), len(X), _ptr(X), len(tri), _ptr(tri), _ptr(pv), _ptr(rec),
+                             _ptr(val), cap)
+    assert n >= 0
+    r, v = rec[:n], val[:n]
+    return {"x": r[:, 0], "y": r[:, 1], "z": r[:, 2], "dir": r[:, 3], "sigma": r[:, 4], "tri": r[:, 5],
+            "jp": v[:, 0], "lam": v[:, 1:4]}
+
+
+def run_mesh(p: Problem3, f, X, tri, pv, steps: int):
+    assert f.dtype == np.float64 and f.flags["C_CONTIGUOUS"] and f.shape == (19, p.nz, p.ny, p.nx)
+    X, tri, pv = _mesh_args(X, tri, pv)
+    assert lib().or3_run_mesh(C.byref(p), _ptr(f), len(X), _ptr(X), len(tri), _ptr(tri), _ptr(pv),
+                              int(steps)) == 0

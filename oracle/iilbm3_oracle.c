@@ -9,7 +9,10 @@
  *     [[p]] = F on every link the sphere's level set cuts (Sec. 3.1,
  *     Eq. (32); Sec. 3.2, Eq. (47)), or
  *   - IB-LBM: spread from surface markers with the three-dimensional product of
- *     Peskin's four-point delta (Sec. 2.2.2, Eq. (17)).
+ *     Peskin's four-point delta (Sec. 2.2.2, Eq. (17));
+ * and the same jumps on the links that cross a fixed closed triangulated
+ * surface with a pressure jump given at its vertices (reading R29, at the end
+ * of this file).
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may call, link or
  * load this file.  It shares no code, header, table or helper with the GPU
@@ -183,3 +186,154 @@ int or3_run(const or3_problem *p, double *f, const double *X, int steps)
 }
 
 int or3_sizeof_problem(void) { return (int)sizeof(or3_problem); }
+
+/* ------------------------------------------------------------------------
+ * A fixed closed triangulated surface (reading R29): the jump conditions of
+ * Sec. 3.1 (Eq. (32)) and Sec. 3.2 (Eq. (47)) on the links that cross a
+ * triangle mesh, the surface form the paper's conclusion asks of a
+ * three-dimensional extension.
+ *
+ * Vertices are snapped to multiples of 2^-16; every side test is an exact
+ * integer determinant.  Ties (a node on a face's plane, a link through an
+ * edge or a vertex) are broken by translating the lattice by (e, e^2, e^3)
+ * with e -> 0+, which keeps a closed surface closed: every perturbed link
+ * meets it in exactly one triangle per crossing.  A link that ends on an
+ * edge may clip it (in through one face, out through the other): two
+ * records of opposite sigma at the same point, whose jumps cancel.  Triangles are (a, b, c)
+ * counter-clockwise seen from outside, so (b - a) x (c - a) points out.
+ * A link is P -> P + e_i, keyed by its sending node P; sigma = +1 when P is
+ * inside.  [[p]] at the crossing is the barycentric interpolation of the
+ * vertex values, the weight of a vertex proportional to the signed volume
+ * the link spans with the opposite edge.
+ * ---------------------------------------------------------------------- */
+typedef __int128 i128;
+
+static int64_t snap16(double v) { return (int64_t)llrint(v * 65536.0); }
+
+static int sgn128(i128 v) { return (v > 0) - (v < 0); }
+
+/* det[u, v, w] = u . (v x w) */
+static i128 det3(const int64_t *u, const int64_t *v, const int64_t *w)
+{
+    return (i128)u[0] * ((i128)v[1] * w[2] - (i128)v[2] * w[1]) -
+           (i128)u[1] * ((i128)v[0] * w[2] - (i128)v[2] * w[0]) +
+           (i128)u[2] * ((i128)v[0] * w[1] - (i128)v[1] * w[0]);
+}
+
+static void sub3(const int64_t *a, const int64_t *b, int64_t *out)
+{
+    for (int k = 0; k < 3; k++) out[k] = a[k] - b[k];
+}
+
+/* Side of the perturbed point P + t of the plane through A, B, C: the sign of
+ * det[B - A, C - A, P - A] + t . ((B - A) x (C - A)). */
+static int plane_side(const int64_t *A, const int64_t *B, const int64_t *C, const int64_t *P)
+{
+    int64_t u[3], v[3], w[3];
+    sub3(B, A, u); sub3(C, A, v); sub3(P, A, w);
+    int s = sgn128(det3(u, v, w));
+    if (s) return s;
+    i128 n[3] = {(i128)u[1] * v[2] - (i128)u[2] * v[1], (i128)u[2] * v[0] - (i128)u[0] * v[2],
+                 (i128)u[0] * v[1] - (i128)u[1] * v[0]};
+    for (int k = 0; k < 3; k++)
+        if (n[k]) return sgn128(n[k]);
+    return 0;
+}
+
+/* Orientation of the edge A -> B seen along the perturbed link P -> R:
+ * det[R - P, A - P, B - P] + t . ((R - P) x (B - A)); *raw gets the
+ * unperturbed determinant (the barycentric weight). */
+static int edge_side(const int64_t *P, const int64_t *R, const int64_t *A, const int64_t *B, i128 *raw)
+{
+    int64_t d[3], a[3], b[3], ba[3];
+    sub3(R, P, d); sub3(A, P, a); sub3(B, P, b); sub3(B, A, ba);
+    *raw = det3(d, a, b);
+    int s = sgn128(*raw);
+    if (s) return s;
+    i128 c[3] = {(i128)d[1] * ba[2] - (i128)d[2] * ba[1], (i128)d[2] * ba[0] - (i128)d[0] * ba[2],
+                 (i128)d[0] * ba[1] - (i128)d[1] * ba[0]};
+    for (int k = 0; k < 3; k++)
+        if (c[k]) return sgn128(c[k]);
+    return 0;
+}
+
+/* Every cut link of the surface.  rec[k] = {x, y, z, dir, sigma, tri} of the
+ * sending node; val[k] = {[[p]], lambda_a, lambda_b, lambda_c}.  Returns the
+ * number of links, or -1 when there are more than cap. */
+long or3_mesh_links(const or3_problem *p, int nv, const double *X, int nt, const int32_t *tri,
+                    const double *pv, int32_t *rec, double *val, long cap)
+{
+    (void)p;
+    int64_t *S = malloc((size_t)3 * nv * sizeof(int64_t));
+    for (int k = 0; k < 3 * nv; k++) S[k] = snap16(X[k]);
+    long n = 0;
+    for (int t = 0; t < nt; t++) {
+        const int ia = tri[3 * t], ib = tri[3 * t + 1], ic = tri[3 * t + 2];
+        const int64_t *A = S + 3 * ia, *B = S + 3 * ib, *C = S + 3 * ic;
+        int lo[3], hi[3];
+        for (int k = 0; k < 3; k++) {
+            int64_t mn = A[k], mx = A[k];
+            if (B[k] < mn) mn = B[k];
+            if (C[k] < mn) mn = C[k];
+            if (B[k] > mx) mx = B[k];
+            if (C[k] > mx) mx = C[k];
+            lo[k] = (int)floor((double)mn / 65536.0) - 1;
+            hi[k] = (int)ceil((double)mx / 65536.0) + 1;
+        }
+        for (int z = lo[2]; z <= hi[2]; z++)
+            for (int y = lo[1]; y <= hi[1]; y++)
+                for (int x = lo[0]; x <= hi[0]; x++)
+                    for (int i = 1; i < Q; i++) {
+                        const int64_t P[3] = {(int64_t)x << 16, (int64_t)y << 16, (int64_t)z << 16};
+                        const int64_t Qn[3] = {(int64_t)(x + EX3[i]) << 16, (int64_t)(y + EY3[i]) << 16,
+                                               (int64_t)(z + EZ3[i]) << 16};
+                        const int sp = plane_side(A, B, C, P), sq = plane_side(A, B, C, Qn);
+                        if (sp == sq) continue;
+                        i128 wc, wa, wb;
+                        const int e1 = edge_side(P, Qn, A, B, &wc);
+                        const int e2 = edge_side(P, Qn, B, C, &wa);
+                        const int e3 = edge_side(P, Qn, C, A, &wb);
+                        if (!(e1 == e2 && e2 == e3)) continue;
+                        if (n >= cap) { free(S); return -1; }
+                        const double la = (double)wa, lb = (double)wb, lc = (double)wc;
+                        const double s = la + lb + lc;
+                        int32_t *r = rec + 6 * n;
+                        r[0] = x; r[1] = y; r[2] = z; r[3] = i; r[4] = sp < 0 ? 1 : -1; r[5] = t;
+                        double *v = val + 4 * n;
+                        v[1] = la / s; v[2] = lb / s; v[3] = lc / s;
+                        v[0] = (la * pv[ia] + lb * pv[ib] + lc * pv[ic]) / s;
+                        n++;
+                    }
+    }
+    free(S);
+    return n;
+}
+
+/* One step with the surface's jumps: the step above (no sphere), then
+ * f_i(P + e_i) += sigma w_i [[p]] / c_s^2 on every cut link. */
+int or3_step_mesh(const or3_problem *p, double *f, int nv, const double *X, int nt, const int32_t *tri,
+                  const double *pv)
+{
+    long cap = 64L * nt + 4096;
+    int32_t *rec = malloc((size_t)6 * cap * sizeof(int32_t));
+    double *val = malloc((size_t)4 * cap * sizeof(double));
+    long n = or3_mesh_links(p, nv, X, nt, tri, pv, rec, val, cap);
+    if (n < 0) { free(rec); free(val); return -1; }
+    or3_step(p, f, NULL);
+    for (long k = 0; k < n; k++) {
+        const int32_t *r = rec + 6 * k;
+        const int i = r[3];
+        const int x = wrap(r[0] + EX3[i], p->nx), y = wrap(r[1] + EY3[i], p->ny), z = wrap(r[2] + EZ3[i], p->nz);
+        f[id3(p, i, x, y, z)] += r[4] * wt3(i) * val[4 * k] / CS2;
+    }
+    free(rec); free(val);
+    return 0;
+}
+
+int or3_run_mesh(const or3_problem *p, double *f, int nv, const double *X, int nt, const int32_t *tri,
+                 const double *pv, int steps)
+{
+    for (int s = 0; s < steps; s++)
+        if (or3_step_mesh(p, f, nv, X, nt, tri, pv)) return -1;
+    return 0;
+}

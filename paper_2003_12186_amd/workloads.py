@@ -336,6 +336,124 @@ def normal_force_sphere_state(p: Problem3) -> np.ndarray:
     return np.ascontiguousarray(w[:, None, None, None] * rho[None])
 
 
+def snap_2m16(X) -> np.ndarray:
+    """Coordinates rounded to multiples of 2^-16, where a triangulated surface's
+    exact side tests take its vertices."""
+    return np.rint(np.asarray(X, dtype=np.float64) * 65536.0) / 65536.0
+
+
+def icosphere(c: Sequence[float], R: float, max_edge: float = 2.2) -> Tuple[np.ndarray, np.ndarray]:
+    """A geodesic sphere: the icosahedron's faces split into four until every
+    edge is at most max_edge, vertices pushed out to radius R and snapped to
+    2^-16; triangles counter-clockwise seen from outside."""
+    g = (1.0 + math.sqrt(5.0)) / 2.0
+    V = [(-1, g, 0), (1, g, 0), (-1, -g, 0), (1, -g, 0), (0, -1, g), (0, 1, g), (0, -1, -g), (0, 1, -g),
+         (g, 0, -1), (g, 0, 1), (-g, 0, -1), (-g, 0, 1)]
+    V = [np.array(v, float) / np.linalg.norm(v) for v in V]
+    T = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4), (11, 10, 2),
+         (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9), (4, 9, 5),
+         (2, 4, 11), (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+
+    def longest(V, T):
+        return max(np.linalg.norm(V[a] - V[b]) for t in T for a, b in ((t[0], t[1]), (t[1], t[2]), (t[2], t[0])))
+
+    while R * longest(V, T) > max_edge:
+        mid = {}
+
+        def m(a, b):
+            k = (min(a, b), max(a, b))
+            if k not in mid:
+                v = V[a] + V[b]
+                V.append(v / np.linalg.norm(v))
+                mid[k] = len(V) - 1
+            return mid[k]
+
+        T = [u for a, b, cc in T for u in ((a, m(a, b), m(cc, a)), (b, m(b, cc), m(a, b)),
+                                           (cc, m(cc, a), m(b, cc)), (m(a, b), m(b, cc), m(cc, a)))]
+    X = snap_2m16(np.asarray(c, float) + R * np.array(V))
+    tri = np.array(T, np.int32)
+    n = np.cross(X[tri[:, 1]] - X[tri[:, 0]], X[tri[:, 2]] - X[tri[:, 0]])
+    assert (np.einsum("ij,ij->i", n, X[tri].mean(1) - np.asarray(c, float)) > 0).all()
+    return X, tri
+
+
+def box_mesh(lo: Sequence[float], hi: Sequence[float], m: int) -> Tuple[np.ndarray, np.ndarray]:
+    """The surface of the box [lo, hi] with each face cut into m x m rectangles
+    and each rectangle into two triangles (diagonals alternating), counter-
+    clockwise seen from outside."""
+    lo, hi = np.asarray(lo, float), np.asarray(hi, float)
+    verts, index, tris = [], {}, []
+
+    def vid(ijk):
+        if ijk not in index:
+            index[ijk] = len(verts)
+            verts.append(lo + (hi - lo) * np.array(ijk, float) / m)
+        return index[ijk]
+
+    for ax in range(3):
+        u, v = (ax + 1) % 3, (ax + 2) % 3
+        for side in (0, m):
+            for a in range(m):
+                for b in range(m):
+                    q = []
+                    for da, db in ((0, 0), (1, 0), (1, 1), (0, 1)):
+                        k = [0, 0, 0]
+                        k[ax], k[u], k[v] = side, a + da, b + db
+                        q.append(vid(tuple(k)))
+                    if side == 0:
+                        q = q[::-1]
+                    if (a + b) % 2:
+                        tris += [(q[0], q[1], q[2]), (q[0], q[2], q[3])]
+                    else:
+                        tris += [(q[1], q[2], q[3]), (q[1], q[3], q[0])]
+    return snap_2m16(np.array(verts)), np.array(tris, np.int32)
+
+
+def mesh_inside(X, tri, pts, shift=(1e-7, 0.0, 0.0), chunk: int = 4096) -> np.ndarray:
+    """Whether points lie inside a closed triangulated surface: the winding
+    number, the sum of the triangles' solid angles (Van Oosterom and Strackee)
+    over 4 pi, above one half.  ``shift`` moves the points off the faces."""
+    X = np.asarray(X, float)
+    A, B, Cc = X[tri[:, 0]], X[tri[:, 1]], X[tri[:, 2]]
+    pts = np.asarray(pts, float) + np.asarray(shift, float)
+    out = np.zeros(len(pts), bool)
+    for s in range(0, len(pts), chunk):
+        q = pts[s:s + chunk, None, :]
+        a, b, c = A[None] - q, B[None] - q, Cc[None] - q
+        la, lb, lc = (np.linalg.norm(v, axis=2) for v in (a, b, c))
+        num = np.einsum("pti,pti->pt", a, np.cross(b, c))
+        den = (la * lb * lc + np.einsum("pti,pti->pt", a, b) * lc + np.einsum("pti,pti->pt", a, c) * lb
+               + np.einsum("pti,pti->pt", b, c) * la)
+        out[s:s + chunk] = (2.0 * np.arctan2(num, den)).sum(1) / (4.0 * np.pi) > 0.5
+    return out
+
+
+def normal_force_mesh(D: int, re: float = 100.0, offset=(0.0, 0.0, 0.0)):
+    """The normal-force sphere of Sec. 4.1 in three dimensions, with the sphere
+    given as a triangulated surface (edges at most 2.2 lu) carrying [[p]] = F
+    at every vertex; the same box, viscosity and F = U^2 as the level-set form."""
+    p, _, meta = normal_force_sphere(D, FORCE_II_LBM, re)
+    c = tuple(float(a) + float(o) for a, o in zip(p.center, offset))
+    X, tri = icosphere(c, D / 2.0)
+    F = p.f_normal
+    p.radius, p.f_normal = 0.0, 0.0                 # the jumps come from the surface only
+    meta = dict(meta, F=F, center=c)
+    return p, X, tri, np.full(len(X), F), meta
+
+
+def normal_force_mesh_state(p: Problem3, X, tri, F: float) -> np.ndarray:
+    """At rest, rho = 1 - 3 F inside the triangulated surface and 1 outside."""
+    w = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+    z, y, x = np.mgrid[0:p.nz, 0:p.ny, 0:p.nx]
+    pts = np.stack([x.ravel(), y.ravel(), z.ravel()], 1).astype(float)
+    lo, hi = np.asarray(X).min(0) - 1, np.asarray(X).max(0) + 1
+    near = np.all((pts >= lo) & (pts <= hi), 1)
+    inside = np.zeros(len(pts), bool)
+    inside[near] = mesh_inside(X, tri, pts[near])
+    rho = np.where(inside, 1.0 - 3.0 * F, 1.0).reshape(p.nz, p.ny, p.nx)
+    return np.ascontiguousarray(w[:, None, None, None] * rho[None])
+
+
 def elastic_membrane_e2(L: int, force_mode: int = FORCE_II_LBM, storage: int = STORE_FP32) -> Workload:
     """Thin elastic membrane of Sec. 4.2: ellipse a = 0.35 L, b = 0.25^2/0.35 L
     centred in a walled L x L box, MRT, kappa_bar = kappa/(U^2 L) = 0.1,
