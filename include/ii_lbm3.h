@@ -83,6 +83,47 @@ int ii_lbm3_get_timing(ii_lbm3_handle* h, double* ms, int64_t* launches);
  * node, plus 24 bytes per node of force field under IB-LBM. */
 int ii_lbm3_sweep_bytes(ii_lbm3_handle* h, double* bytes);
 
+/*
+ * A fixed closed triangulated surface carrying a pressure jump [[p]] given at
+ * its vertices: on every link P -> P + e_i that crosses a triangle, the jump
+ * [[f_i]] = sigma w_i [[p]] / c_s^2 of Sec. 3.1 (Eq. (32)) and Sec. 3.2
+ * (Eq. (47)), sigma = +1 when P is inside, with [[p]] interpolated
+ * barycentrically at the crossing.  The surface is the triangulation the
+ * paper's conclusion names for three dimensions; its links are found once
+ * here and their jumps applied after every sweep.
+ *
+ * Vertices X[n_vert][3] (FP64, lattice units) are snapped to multiples of
+ * 2^-16 and every side test is an exact integer determinant; ties (a node on
+ * a face's plane, a link through an edge or vertex) are broken by translating
+ * the lattice by (e, e^2, e^3) with e -> 0+.  Triangles tri[n_tri][3] index
+ * the vertices counter-clockwise seen from outside.  A link that runs into the
+ * surface through one face and out through another has two records.
+ *
+ * ii_lbm3_check_mesh validates without touching the GPU; ii_lbm3_set_mesh
+ * validates the same way and installs the surface:
+ *   EINVAL     force mode not II_LBM_FORCE_II, a NULL array, fewer than 4 or
+ *              more than 2^20 vertices or triangles, an index out of range or
+ *              repeated in a triangle, a non-finite coordinate or jump value;
+ *   EGEOMETRY  a vertex outside [2, n - 3] on some axis, an edge longer than
+ *              4 lattice units, a degenerate triangle, a surface that is not
+ *              closed and consistently oriented (every directed edge once and
+ *              its reverse once), or one whose enclosed volume is not positive;
+ *   ECAPACITY  more cut links than 64 n_tri + 4096.
+ * The library copies every array.  set_mesh synchronises and replaces any
+ * surface installed before; n_vert = n_tri = 0 removes it.  *n_links (may be
+ * NULL) receives the number of cut-link records.
+ */
+int ii_lbm3_check_mesh(const ii_lbm3_problem* p, int32_t n_vert, const double* X, int32_t n_tri,
+                       const int32_t* tri);
+int ii_lbm3_set_mesh(ii_lbm3_handle* h, int32_t n_vert, const double* X, int32_t n_tri,
+                     const int32_t* tri, const double* jump_p, int64_t* n_links);
+
+/* The installed surface's cut links, in no particular order: rec[k] =
+ * {x, y, z, dir, sigma, tri} of the sending node, jp[k] = [[p]] at the
+ * crossing.  *n_links receives the count; ECAPACITY (nothing copied) when cap
+ * is smaller.  Synchronises. */
+int ii_lbm3_mesh_links(ii_lbm3_handle* h, int64_t cap, int32_t* rec, double* jp, int64_t* n_links);
+
 int ii_lbm3_destroy(ii_lbm3_handle* h);
 
 #ifdef __cplusplus

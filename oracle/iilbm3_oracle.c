@@ -309,31 +309,33 @@ long or3_mesh_links(const or3_problem *p, int nv, const double *X, int nt, const
     return n;
 }
 
-/* One step with the surface's jumps: the step above (no sphere), then
- * f_i(P + e_i) += sigma w_i [[p]] / c_s^2 on every cut link. */
-int or3_step_mesh(const or3_problem *p, double *f, int nv, const double *X, int nt, const int32_t *tri,
-                  const double *pv)
+/* Steps with the surface's jumps: each is the step above (no sphere), then
+ * f_i(P + e_i) += sigma w_i [[p]] / c_s^2 on every cut link.  The surface is
+ * fixed, so its links are found once. */
+int or3_run_mesh(const or3_problem *p, double *f, int nv, const double *X, int nt, const int32_t *tri,
+                 const double *pv, int steps)
 {
     long cap = 64L * nt + 4096;
     int32_t *rec = malloc((size_t)6 * cap * sizeof(int32_t));
     double *val = malloc((size_t)4 * cap * sizeof(double));
     long n = or3_mesh_links(p, nv, X, nt, tri, pv, rec, val, cap);
     if (n < 0) { free(rec); free(val); return -1; }
-    or3_step(p, f, NULL);
-    for (long k = 0; k < n; k++) {
-        const int32_t *r = rec + 6 * k;
-        const int i = r[3];
-        const int x = wrap(r[0] + EX3[i], p->nx), y = wrap(r[1] + EY3[i], p->ny), z = wrap(r[2] + EZ3[i], p->nz);
-        f[id3(p, i, x, y, z)] += r[4] * wt3(i) * val[4 * k] / CS2;
+    for (int s = 0; s < steps; s++) {
+        or3_step(p, f, NULL);
+        for (long k = 0; k < n; k++) {
+            const int32_t *r = rec + 6 * k;
+            const int i = r[3];
+            const int x = wrap(r[0] + EX3[i], p->nx), y = wrap(r[1] + EY3[i], p->ny),
+                      z = wrap(r[2] + EZ3[i], p->nz);
+            f[id3(p, i, x, y, z)] += r[4] * wt3(i) * val[4 * k] / CS2;
+        }
     }
     free(rec); free(val);
     return 0;
 }
 
-int or3_run_mesh(const or3_problem *p, double *f, int nv, const double *X, int nt, const int32_t *tri,
-                 const double *pv, int steps)
+int or3_step_mesh(const or3_problem *p, double *f, int nv, const double *X, int nt, const int32_t *tri,
+                  const double *pv)
 {
-    for (int s = 0; s < steps; s++)
-        if (or3_step_mesh(p, f, nv, X, nt, tri, pv)) return -1;
-    return 0;
+    return or3_run_mesh(p, f, nv, X, nt, tri, pv, 1);
 }

@@ -323,7 +323,8 @@ class Problem3C(C.Structure):
 
 
 EXPORTS3 = ["ii_lbm3_init", "ii_lbm3_step", "ii_lbm3_set_distrib", "ii_lbm3_fields",
-            "ii_lbm3_set_timing", "ii_lbm3_get_timing", "ii_lbm3_sweep_bytes", "ii_lbm3_destroy"]
+            "ii_lbm3_set_timing", "ii_lbm3_get_timing", "ii_lbm3_sweep_bytes", "ii_lbm3_check_mesh",
+            "ii_lbm3_set_mesh", "ii_lbm3_mesh_links", "ii_lbm3_destroy"]
 
 
 def _lib3():
@@ -338,6 +339,9 @@ def _lib3():
             "ii_lbm3_set_timing": [v, i32],
             "ii_lbm3_get_timing": [v, C.POINTER(d), C.POINTER(i64)],
             "ii_lbm3_sweep_bytes": [v, C.POINTER(d)],
+            "ii_lbm3_check_mesh": [C.POINTER(Problem3C), i32, v, i32, v],
+            "ii_lbm3_set_mesh": [v, i32, v, i32, v, v, C.POINTER(i64)],
+            "ii_lbm3_mesh_links": [v, i64, v, v, C.POINTER(i64)],
             "ii_lbm3_destroy": [v],
         }
         for name, args in sigs.items():
@@ -359,6 +363,20 @@ def make_problem3(w) -> Problem3C:
     p.radius, p.f_normal = float(w.radius), float(w.f_normal)
     p.n_markers = int(w.n_markers)
     return p
+
+
+def _mesh3_args(X, tri, jump_p):
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    pv = np.ascontiguousarray(np.broadcast_to(np.asarray(jump_p, dtype=np.float64), (len(X),)))
+    return X, tri, pv
+
+
+def check_mesh3(problem, X, tri) -> int:
+    """Host-only validation of a triangulated surface (no GPU); the return code."""
+    p = problem if isinstance(problem, Problem3C) else make_problem3(problem)
+    X, tri, _ = _mesh3_args(X, tri, 0.0)
+    return int(_lib3().ii_lbm3_check_mesh(C.byref(p), len(X), X.ctypes.data, len(tri), tri.ctypes.data))
 
 
 class Sim3:
@@ -397,6 +415,29 @@ class Sim3:
         b = C.c_double()
         check(_lib3().ii_lbm3_sweep_bytes(self.h, C.byref(b)), "sweep_bytes3")
         return b.value
+
+    def set_mesh(self, X, tri, jump_p) -> int:
+        """Installs a fixed closed triangulated surface with vertex jump values;
+        returns the number of cut-link records."""
+        X, tri, pv = _mesh3_args(X, tri, jump_p)
+        self._mesh = (X, tri, pv)
+        n = C.c_int64()
+        check(_lib3().ii_lbm3_set_mesh(self.h, len(X), X.ctypes.data, len(tri), tri.ctypes.data,
+                                       pv.ctypes.data, C.byref(n)), "set_mesh3")
+        return n.value
+
+    def mesh_links(self) -> dict:
+        n = C.c_int64()
+        rc = _lib3().ii_lbm3_mesh_links(self.h, 0, None, None, C.byref(n))   # the count
+        if rc not in (OK, ECAPACITY):
+            check(rc, "mesh_links3")
+        rec = np.zeros((max(n.value, 1), 6), np.int32)
+        jp = np.zeros(max(n.value, 1))
+        check(_lib3().ii_lbm3_mesh_links(self.h, n.value, rec.ctypes.data, jp.ctypes.data, C.byref(n)),
+              "mesh_links3")
+        r, jp = rec[:n.value], jp[:n.value]
+        return {"x": r[:, 0], "y": r[:, 1], "z": r[:, 2], "dir": r[:, 3], "sigma": r[:, 4], "tri": r[:, 5],
+                "jp": jp}
 
     def close(self) -> None:
         if getattr(self, "h", None) is not None and self.h.value:

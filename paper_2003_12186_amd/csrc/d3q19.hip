@@ -12,6 +12,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "../../include/ii_lbm3.h"
@@ -180,13 +181,133 @@ __global__ void k_zero3(float* p, long long n)
         p[i] = 0.f;
 }
 
+// ---------------------------------------------------------------------------
+// A fixed closed triangulated surface.  Vertices snapped to 2^-16 lu arrive as
+// int64; side tests are exact integer determinants.  The host's validation
+// (edges at most 4 lu, vertices in [2, n - 3]) keeps every coordinate
+// difference below 2^19 and so every determinant below 2^58.  Ties are broken
+// by translating the lattice by (e, e^2, e^3), e -> 0+: a node in a face's
+// plane takes the side of the plane normal's first non-zero component, a link
+// through an edge the side of the first non-zero component of
+// (link x edge), so each perturbed crossing of a closed surface is seen by
+// exactly one triangle.
+struct MeshRec3 {
+    int16_t x, y, z;        // sending node
+    int8_t dir, sigma;      // population, +1 when the sending node is inside
+    int32_t tri;
+    float delta;            // sigma w_i [[p]] / c_s^2, added to the stored population
+    double jp;              // [[p]] at the crossing
+};
+static_assert(sizeof(MeshRec3) == 24, "record layout");
+
+constexpr int kMeshWaves = 4;   // triangles per 256-thread block
+
+__device__ __forceinline__ long long det3i(long long ux, long long uy, long long uz, long long vx,
+                                           long long vy, long long vz, long long wx, long long wy,
+                                           long long wz)
+{
+    return ux * (vy * wz - vz * wy) - uy * (vx * wz - vz * wx) + uz * (vx * wy - vy * wx);
+}
+
+__device__ __forceinline__ int sgn64(long long v) { return (v > 0) - (v < 0); }
+
+// Perturbed side of node (px, py, pz) (snapped units) of the plane of A, B, C.
+__device__ __forceinline__ int mesh_plane_side(const long long* A, const long long* B, const long long* C,
+                                               long long px, long long py, long long pz)
+{
+    const long long ux = B[0] - A[0], uy = B[1] - A[1], uz = B[2] - A[2];
+    const long long vx = C[0] - A[0], vy = C[1] - A[1], vz = C[2] - A[2];
+    const int s = sgn64(det3i(ux, uy, uz, vx, vy, vz, px - A[0], py - A[1], pz - A[2]));
+    if (s) return s;
+    const long long nx = uy * vz - uz * vy, ny = uz * vx - ux * vz, nz = ux * vy - uy * vx;
+    return nx ? sgn64(nx) : (ny ? sgn64(ny) : sgn64(nz));
+}
+
+// Perturbed orientation of edge E0 -> E1 seen along the link from P with
+// step d; *w gets the unperturbed determinant.
+__device__ __forceinline__ int mesh_edge_side(long long px, long long py, long long pz, long long dx,
+                                              long long dy, long long dz, const long long* E0,
+                                              const long long* E1, long long* w)
+{
+    *w = det3i(dx, dy, dz, E0[0] - px, E0[1] - py, E0[2] - pz, E1[0] - px, E1[1] - py, E1[2] - pz);
+    if (*w) return sgn64(*w);
+    const long long bx = E1[0] - E0[0], by = E1[1] - E0[1], bz = E1[2] - E0[2];
+    const long long cx = dy * bz - dz * by, cy = dz * bx - dx * bz, cz = dx * by - dy * bx;
+    return cx ? sgn64(cx) : (cy ? sgn64(cy) : sgn64(cz));
+}
+
+// One wave per triangle: every link P -> P + e_i with P in the triangle's
+// node box widened by one.
+__global__ __launch_bounds__(256) void k_mesh_links3(const long long* __restrict__ S,
+                                                     const int* __restrict__ tri,
+                                                     const double* __restrict__ pv, int nt,
+                                                     MeshRec3* __restrict__ out, int cap,
+                                                     int* __restrict__ count)
+{
+    const int t = blockIdx.x * kMeshWaves + threadIdx.x / 64;
+    const int lane = threadIdx.x % 64;
+    if (t >= nt) return;
+    const int ia = tri[3 * t], ib = tri[3 * t + 1], ic = tri[3 * t + 2];
+    long long A[3], B[3], C[3];
+    int lo[3], n[3];
+    for (int k = 0; k < 3; k++) {
+        A[k] = S[3 * ia + k]; B[k] = S[3 * ib + k]; C[k] = S[3 * ic + k];
+        const long long mn = min(A[k], min(B[k], C[k])), mx = max(A[k], max(B[k], C[k]));
+        lo[k] = (int)(mn >> 16) - 1;
+        n[k] = (int)((mx + 65535) >> 16) + 1 - lo[k] + 1;
+    }
+    const int total = n[0] * n[1] * n[2] * (kQ - 1);
+    for (int k = lane; k < total; k += 64) {
+        const int node = k / (kQ - 1), i = 1 + k % (kQ - 1);
+        const int x = lo[0] + node % n[0], y = lo[1] + (node / n[0]) % n[1], z = lo[2] + node / (n[0] * n[1]);
+        const long long px = (long long)x << 16, py = (long long)y << 16, pz = (long long)z << 16;
+        const long long dx = (long long)E3X[i] << 16, dy = (long long)E3Y[i] << 16, dz = (long long)E3Z[i] << 16;
+        const int sp = mesh_plane_side(A, B, C, px, py, pz);
+        const int sq = mesh_plane_side(A, B, C, px + dx, py + dy, pz + dz);
+        if (sp == sq) continue;
+        long long wc, wa, wb;
+        const int e1 = mesh_edge_side(px, py, pz, dx, dy, dz, A, B, &wc);
+        const int e2 = mesh_edge_side(px, py, pz, dx, dy, dz, B, C, &wa);
+        const int e3 = mesh_edge_side(px, py, pz, dx, dy, dz, C, A, &wb);
+        if (e1 != e2 || e2 != e3) continue;
+        const double la = (double)wa, lb = (double)wb, lc = (double)wc;
+        const double jp = (la * pv[ia] + lb * pv[ib] + lc * pv[ic]) / (la + lb + lc);
+        const int sigma = sp < 0 ? 1 : -1;
+        const int slot = atomicAdd(count, 1);
+        if (slot >= cap) continue;
+        MeshRec3 r;
+        r.x = (int16_t)x; r.y = (int16_t)y; r.z = (int16_t)z;
+        r.dir = (int8_t)i; r.sigma = (int8_t)sigma; r.tri = t;
+        r.delta = (float)(sigma * W3D[i] * jp * 3.0);
+        r.jp = jp;
+        out[slot] = r;
+    }
+}
+
+// After the sweep: the stored population of every cut link's sending node
+// takes the link's jump, so the next pull carries it across.
+__global__ void k_mesh_apply3(Box b, const MeshRec3* __restrict__ r, int n, float* __restrict__ B)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const MeshRec3 q = r[k];
+    atomicAdd(&B[q.dir * b.plane + ((long long)q.z * b.ny + q.y) * b.pitch + q.x], q.delta);
+}
+
 }  // namespace iilbm3
 
 using namespace iilbm3;
 
 struct ii_lbm3_handle {
     Box b;
+    ii_lbm3_problem prob;
     hipStream_t stream;
+    long long* mesh_S = nullptr;      // snapped vertices, int64 [3 n_vert]
+    int* mesh_tri = nullptr;
+    double* mesh_pv = nullptr;
+    MeshRec3* mesh_rec = nullptr;
+    int* mesh_count = nullptr;
+    int mesh_links = 0;
     float* lat[2] = {nullptr, nullptr};
     double* g = nullptr;
     int parity = 0;
@@ -198,6 +319,17 @@ struct ii_lbm3_handle {
 };
 
 static int fail3(hipError_t e) { return e == hipSuccess ? II_LBM_OK : II_LBM_EDEVICE; }
+
+static void free_mesh(ii_lbm3_handle* h)
+{
+    for (void* q : {(void*)h->mesh_S, (void*)h->mesh_tri, (void*)h->mesh_pv, (void*)h->mesh_rec,
+                    (void*)h->mesh_count})
+        if (q) (void)hipFree(q);
+    h->mesh_S = nullptr; h->mesh_tri = nullptr; h->mesh_pv = nullptr; h->mesh_rec = nullptr;
+    h->mesh_count = nullptr; h->mesh_links = 0;
+}
+
+static long long snap_2m16(double v) { return llrint(v * 65536.0); }
 
 extern "C" {
 
@@ -228,6 +360,7 @@ int ii_lbm3_init(const ii_lbm3_problem* p, const double* X0, void* hip_stream, i
         }
     }
     ii_lbm3_handle* h = new ii_lbm3_handle();
+    h->prob = *p;
     Box& b = h->b;
     b.nx = p->nx; b.ny = p->ny; b.nz = p->nz;
     b.pitch = (p->nx + 63) / 64 * 64;
@@ -301,6 +434,9 @@ int ii_lbm3_step(ii_lbm3_handle* h, int64_t n_steps)
             (void)hipEventRecord(h->ev[h->ev_used + 1], h->stream);
             h->ev_used += 2;
         }
+        if (h->mesh_links > 0)
+            hipLaunchKernelGGL(k_mesh_apply3, dim3((h->mesh_links + 255) / 256), dim3(256), 0, h->stream, b,
+                               h->mesh_rec, h->mesh_links, h->lat[h->parity ^ 1]);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return II_LBM_EDEVICE;
         h->parity ^= 1;
@@ -374,10 +510,141 @@ int ii_lbm3_sweep_bytes(ii_lbm3_handle* h, double* bytes)
     return II_LBM_OK;
 }
 
+int ii_lbm3_check_mesh(const ii_lbm3_problem* p, int32_t n_vert, const double* X, int32_t n_tri,
+                       const int32_t* tri)
+{
+    if (!p || !X || !tri || n_vert < 4 || n_tri < 4 || n_vert > (1 << 20) || n_tri > (1 << 20))
+        return II_LBM_EINVAL;
+    if (p->force_mode != II_LBM_FORCE_II) return II_LBM_EINVAL;
+    const int n[3] = {p->nx, p->ny, p->nz};
+    std::vector<long long> S((size_t)3 * n_vert);
+    for (int v = 0; v < n_vert; v++)
+        for (int a = 0; a < 3; a++) {
+            const double c = X[3 * v + a];
+            if (!isfinite(c)) return II_LBM_EINVAL;
+            if (!(c >= 2.0 && c <= n[a] - 3.0)) return II_LBM_EGEOMETRY;
+            S[3 * v + a] = snap_2m16(c);
+        }
+    const long long lim = 4LL << 16;
+    std::vector<unsigned long long> edges;
+    edges.reserve((size_t)3 * n_tri);
+    double vol = 0.0;
+    for (int t = 0; t < n_tri; t++) {
+        const int v[3] = {tri[3 * t], tri[3 * t + 1], tri[3 * t + 2]};
+        for (int k = 0; k < 3; k++)
+            if (v[k] < 0 || v[k] >= n_vert) return II_LBM_EINVAL;
+        if (v[0] == v[1] || v[1] == v[2] || v[0] == v[2]) return II_LBM_EINVAL;
+        for (int k = 0; k < 3; k++) {
+            const long long* a = &S[3 * v[k]];
+            const long long* c = &S[3 * v[(k + 1) % 3]];
+            double len2 = 0.0;
+            for (int j = 0; j < 3; j++) len2 += (double)(c[j] - a[j]) * (double)(c[j] - a[j]);
+            if (len2 > (double)lim * (double)lim) return II_LBM_EGEOMETRY;
+            edges.push_back((unsigned long long)v[k] * (unsigned long long)n_vert + (unsigned long long)v[(k + 1) % 3]);
+        }
+        const long long* A = &S[3 * v[0]];
+        const long long* B = &S[3 * v[1]];
+        const long long* C = &S[3 * v[2]];
+        const long long ux = B[0] - A[0], uy = B[1] - A[1], uz = B[2] - A[2];
+        const long long wx = C[0] - A[0], wy = C[1] - A[1], wz = C[2] - A[2];
+        const long long cx = uy * wz - uz * wy, cy = uz * wx - ux * wz, cz = ux * wy - uy * wx;
+        if (!cx && !cy && !cz) return II_LBM_EGEOMETRY;          // degenerate triangle
+        // signed volume of the tetrahedron (vertex 0, A, B, C), in lu^3 * 6
+        const double* X0 = X;
+        double a0[3], b0[3], c0[3];
+        for (int j = 0; j < 3; j++) {
+            a0[j] = X[3 * v[0] + j] - X0[j]; b0[j] = X[3 * v[1] + j] - X0[j]; c0[j] = X[3 * v[2] + j] - X0[j];
+        }
+        vol += a0[0] * (b0[1] * c0[2] - b0[2] * c0[1]) - a0[1] * (b0[0] * c0[2] - b0[2] * c0[0]) +
+               a0[2] * (b0[0] * c0[1] - b0[1] * c0[0]);
+    }
+    // closed and consistently oriented: every directed edge once, and its reverse once
+    std::vector<unsigned long long> sorted(edges);
+    std::sort(sorted.begin(), sorted.end());
+    for (size_t k = 1; k < sorted.size(); k++)
+        if (sorted[k] == sorted[k - 1]) return II_LBM_EGEOMETRY;
+    for (unsigned long long e : sorted) {
+        const unsigned long long r = (e % (unsigned long long)n_vert) * (unsigned long long)n_vert +
+                                     e / (unsigned long long)n_vert;
+        if (!std::binary_search(sorted.begin(), sorted.end(), r)) return II_LBM_EGEOMETRY;
+    }
+    if (!(vol > 0.0)) return II_LBM_EGEOMETRY;                   // outward orientation
+    return II_LBM_OK;
+}
+
+int ii_lbm3_set_mesh(ii_lbm3_handle* h, int32_t n_vert, const double* X, int32_t n_tri, const int32_t* tri,
+                     const double* jump_p, int64_t* n_links)
+{
+    if (!h) return II_LBM_EINVAL;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return II_LBM_EDEVICE;
+    free_mesh(h);
+    if (n_links) *n_links = 0;
+    if (n_vert == 0 && n_tri == 0) return II_LBM_OK;            // surface removed
+    const int rc = ii_lbm3_check_mesh(&h->prob, n_vert, X, n_tri, tri);
+    if (rc != II_LBM_OK) return rc;
+    if (!jump_p) return II_LBM_EINVAL;
+    for (int v = 0; v < n_vert; v++)
+        if (!isfinite(jump_p[v])) return II_LBM_EINVAL;
+    std::vector<long long> S((size_t)3 * n_vert);
+    for (size_t k = 0; k < S.size(); k++) S[k] = snap_2m16(X[k]);
+    const long long cap = 64LL * n_tri + 4096;
+    hipError_t e = hipMalloc(&h->mesh_S, S.size() * sizeof(long long));
+    if (e == hipSuccess) e = hipMalloc(&h->mesh_tri, (size_t)3 * n_tri * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&h->mesh_pv, (size_t)n_vert * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&h->mesh_rec, (size_t)cap * sizeof(MeshRec3));
+    if (e == hipSuccess) e = hipMalloc(&h->mesh_count, sizeof(int));
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->mesh_S, S.data(), S.size() * sizeof(long long), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->mesh_tri, tri, (size_t)3 * n_tri * sizeof(int), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->mesh_pv, jump_p, (size_t)n_vert * sizeof(double), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(h->mesh_count, 0, sizeof(int), h->stream);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_mesh_links3, dim3((n_tri + kMeshWaves - 1) / kMeshWaves), dim3(256), 0, h->stream,
+                           h->mesh_S, h->mesh_tri, h->mesh_pv, n_tri, h->mesh_rec, (int)cap, h->mesh_count);
+        e = hipGetLastError();
+    }
+    int count = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&count, h->mesh_count, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+        free_mesh(h);
+        return II_LBM_EDEVICE;
+    }
+    if (count > cap) {
+        free_mesh(h);
+        return II_LBM_ECAPACITY;
+    }
+    h->mesh_links = count;
+    if (n_links) *n_links = count;
+    return II_LBM_OK;
+}
+
+int ii_lbm3_mesh_links(ii_lbm3_handle* h, int64_t cap, int32_t* rec, double* jp, int64_t* n_links)
+{
+    if (!h || !n_links || cap < 0 || (cap > 0 && (!rec || !jp))) return II_LBM_EINVAL;
+    *n_links = h->mesh_links;
+    if (h->mesh_links == 0) return II_LBM_OK;
+    if (cap < h->mesh_links) return II_LBM_ECAPACITY;
+    std::vector<MeshRec3> r(h->mesh_links);
+    hipError_t e = hipMemcpyAsync(r.data(), h->mesh_rec, r.size() * sizeof(MeshRec3), hipMemcpyDeviceToHost,
+                                  h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return II_LBM_EDEVICE;
+    for (size_t k = 0; k < r.size(); k++) {
+        int32_t* o = rec + 6 * k;
+        o[0] = r[k].x; o[1] = r[k].y; o[2] = r[k].z; o[3] = r[k].dir; o[4] = r[k].sigma; o[5] = r[k].tri;
+        jp[k] = r[k].jp;
+    }
+    return II_LBM_OK;
+}
+
 int ii_lbm3_destroy(ii_lbm3_handle* h)
 {
     if (!h) return II_LBM_EINVAL;
     (void)hipStreamSynchronize(h->stream);
+    free_mesh(h);
     for (auto& p : h->lat)
         if (p) (void)hipFree(p);
     if (h->g) (void)hipFree(h->g);

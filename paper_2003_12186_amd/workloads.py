@@ -437,19 +437,23 @@ def normal_force_mesh(D: int, re: float = 100.0, offset=(0.0, 0.0, 0.0)):
     X, tri = icosphere(c, D / 2.0)
     F = p.f_normal
     p.radius, p.f_normal = 0.0, 0.0                 # the jumps come from the surface only
-    meta = dict(meta, F=F, center=c)
+    meta = dict(meta, F=F, center=c, R=D / 2.0)
     return p, X, tri, np.full(len(X), F), meta
 
 
-def normal_force_mesh_state(p: Problem3, X, tri, F: float) -> np.ndarray:
-    """At rest, rho = 1 - 3 F inside the triangulated surface and 1 outside."""
+def normal_force_mesh_state(p: Problem3, X, tri, F: float, center, R: float) -> np.ndarray:
+    """At rest, rho = 1 - 3 F inside the triangulated sphere (vertices on the
+    sphere of centre c and radius R, faces within 1 lu inside it) and 1
+    outside.  Nodes more than 1 lu inside the sphere are inside, nodes outside
+    it (beyond the vertices' 2^-17 snap) are outside; the shell between takes
+    the winding number."""
     w = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
     z, y, x = np.mgrid[0:p.nz, 0:p.ny, 0:p.nx]
     pts = np.stack([x.ravel(), y.ravel(), z.ravel()], 1).astype(float)
-    lo, hi = np.asarray(X).min(0) - 1, np.asarray(X).max(0) + 1
-    near = np.all((pts >= lo) & (pts <= hi), 1)
-    inside = np.zeros(len(pts), bool)
-    inside[near] = mesh_inside(X, tri, pts[near])
+    r = np.linalg.norm(pts - np.asarray(center, float), axis=1)
+    inside = r < R - 1.0
+    shell = (r >= R - 1.0) & (r <= R + 1e-4)
+    inside[shell] = mesh_inside(X, tri, pts[shell])
     rho = np.where(inside, 1.0 - 3.0 * F, 1.0).reshape(p.nz, p.ny, p.nx)
     return np.ascontiguousarray(w[:, None, None, None] * rho[None])
 

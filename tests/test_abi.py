@@ -174,3 +174,52 @@ def test_d3q19_init_validation_rejects_before_device_access(mutate, code):
     mutate(p)
     h = C.c_void_p()
     assert B._lib3().ii_lbm3_init(C.byref(p), None, None, C.byref(h)) == code
+
+
+def _mesh_problem():
+    from paper_2003_12186_amd import workloads as W
+    return W.Problem3(nx=24, ny=24, nz=24, tau=0.8)
+
+
+def test_d3q19_mesh_validation_accepts_closed_surfaces():
+    from paper_2003_12186_amd import workloads as W
+    p = _mesh_problem()
+    X, tri = W.icosphere((12.27, 11.69, 12.13), 6.0)
+    assert B.check_mesh3(p, X, tri) == B.OK
+    Xb, tb = W.box_mesh((5, 5, 5), (15, 15, 15), 4)
+    assert B.check_mesh3(p, Xb, tb) == B.OK
+
+
+def _bad_meshes():
+    from paper_2003_12186_amd import workloads as W
+    X, tri = W.icosphere((12.27, 11.69, 12.13), 6.0)
+    cases = {}
+    cases["open"] = (X, tri[1:], B.EGEOMETRY)                     # a triangle missing
+    cases["flipped_one"] = (X, np.concatenate([tri[:1, ::-1], tri[1:]]), B.EGEOMETRY)
+    cases["inside_out"] = (X, np.ascontiguousarray(tri[:, ::-1]), B.EGEOMETRY)
+    Xs = X.copy(); Xs[:, 0] += 6.0
+    cases["near_side"] = (Xs, tri, B.EGEOMETRY)                   # x beyond n - 3
+    Xb, tb = W.box_mesh((5, 5, 5), (15, 15, 15), 2)               # edges 5 and 7.1 lu
+    cases["long_edge"] = (Xb, tb, B.EGEOMETRY)
+    t = tri.copy(); t[0, 1] = t[0, 0]
+    cases["repeated_index"] = (X, t, B.EINVAL)
+    t = tri.copy(); t[3, 2] = len(X)
+    cases["index_range"] = (X, t, B.EINVAL)
+    Xn = X.copy(); Xn[5, 1] = np.nan
+    cases["nan"] = (Xn, tri, B.EINVAL)
+    return cases
+
+
+@pytest.mark.parametrize("case", ["open", "flipped_one", "inside_out", "near_side", "long_edge",
+                                  "repeated_index", "index_range", "nan"])
+def test_d3q19_mesh_validation_rejects(case):
+    X, tri, code = _bad_meshes()[case]
+    assert B.check_mesh3(_mesh_problem(), X, tri) == code
+
+
+def test_d3q19_mesh_needs_the_jump_force_mode():
+    from paper_2003_12186_amd import workloads as W
+    p = _mesh_problem()
+    p.force_mode = W.FORCE_IB_LBM
+    X, tri = W.icosphere((12.27, 11.69, 12.13), 6.0)
+    assert B.check_mesh3(p, X, tri) == B.EINVAL

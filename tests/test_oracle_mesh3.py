@@ -143,7 +143,7 @@ def test_exact_state_of_the_normal_force_mesh_is_fixed():
     c, R, F = (9.27, 8.69, 10.13), 5.3, 4e-3
     X, tri = W.icosphere(c, R)
     p = O3.make_problem(W.Problem3(nx=20, ny=19, nz=21, tau=0.8))
-    f = W.normal_force_mesh_state(W.Problem3(nx=20, ny=19, nz=21, tau=0.8), X, tri, F)
+    f = W.normal_force_mesh_state(W.Problem3(nx=20, ny=19, nz=21, tau=0.8), X, tri, F, c, R)
     f0 = f.copy()
     O3.run_mesh(p, f, X, tri, F, 6)
     assert np.abs(f - f0).max() < 1e-14
