@@ -673,8 +673,21 @@ def bench_d3q19(args, B, W) -> int:
     import torch
     L = args.d3_size
     c = (L / 2.0, L / 2.0, L / 2.0)
-    big = W.Problem3(nx=L, ny=L, nz=L, tau=0.8, center=c, radius=L / 4.0, f_normal=1e-3)
-    sim = B.Sim3(big)
+    mesh_info = None
+    if args.d3_surface == "mesh":
+        # the same sphere as a geodesic triangulation (edges <= 2.2 lu), its
+        # jumps applied after each sweep by k_mesh_apply3
+        big = W.Problem3(nx=L, ny=L, nz=L, tau=0.8)
+        sim = B.Sim3(big)
+        Xm, tm = W.icosphere((c[0] + 0.27, c[1] - 0.31, c[2] + 0.13), L / 4.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nl = sim.set_mesh(Xm, tm, 1e-3)
+        mesh_info = {"vertices": int(len(Xm)), "triangles": int(len(tm)), "cut_links": int(nl),
+                     "set_mesh_ms": round((time.perf_counter() - t0) * 1e3, 2)}
+    else:
+        big = W.Problem3(nx=L, ny=L, nz=L, tau=0.8, center=c, radius=L / 4.0, f_normal=1e-3)
+        sim = B.Sim3(big)
     sim.step(args.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -706,14 +719,30 @@ def bench_d3q19(args, B, W) -> int:
                 print(f"[d3q19] {start} D={D} {name}: L2 {rows[-1]['L2']:.3e} Linf {rows[-1]['Linf']:.3e}",
                       file=sys.stderr, flush=True)
                 s3.close()
+            # II-LBM on the triangulated sphere, exact state from the mesh's own inside
+            prob, Xm, tm, pv, meta = W.normal_force_mesh(D, offset=(0.27, -0.31, 0.13))
+            s3 = B.Sim3(prob)
+            s3.set_mesh(Xm, tm, pv)
+            if start == "exact":
+                s3.set_distrib(W.normal_force_mesh_state(prob, Xm, tm, meta["F"], meta["center"], meta["R"]))
+            s3.step(meta["steps"])
+            g = s3.fields()
+            U = meta["U"]
+            rows.append({"start": start, "D": D, "method": "II-LBM mesh", "steps": meta["steps"],
+                         "triangles": int(len(tm)),
+                         "L2": float(np.sqrt((g[1] ** 2 + g[2] ** 2 + g[3] ** 2).mean()) / U),
+                         "Linf": float(max(np.abs(g[a]).max() for a in (1, 2, 3)) / U)})
+            print(f"[d3q19] {start} D={D} II-LBM mesh: L2 {rows[-1]['L2']:.3e} Linf {rows[-1]['Linf']:.3e}",
+                  file=sys.stderr, flush=True)
+            s3.close()
     out = {
         "metric": "MLUPS & %HBM peak; learned 2x-coarse vs fine II-LBM time at <=1e-2 L2 err",
         "value": round(nodes * args.steps / dt / 1e6, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3 / args.steps, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 storage / fp64 collision", "data": "synthetic",
-        "config": {"workload": f"d3q19_sphere{L}", "nx": L, "ny": L, "nz": L, "sphere_D": L // 2,
-                   "table1_3d": rows},
+        "config": {"workload": f"d3q19_sphere{L}" + ("_mesh" if mesh_info else ""), "nx": L, "ny": L, "nz": L,
+                   "sphere_D": L // 2, "surface": args.d3_surface, "mesh": mesh_info, "table1_3d": rows},
         "roofline": {"bound": "hbm", "kernel": "k_sweep3", "achieved": round(bpl / avg / 1e9, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(bpl / avg / 1e9 / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(f"d3q19_{L}"), "bytes_per_launch": bpl,
@@ -927,6 +956,8 @@ def main() -> int:
                          "reported in the design notes)")
     ap.add_argument("--re", type=float, default=100.0, help="Reynolds number of the cylinder workload")
     ap.add_argument("--d3-size", type=int, default=256, help="box side of the d3q19 workload")
+    ap.add_argument("--d3-surface", choices=["levelset", "mesh"], default="levelset",
+                    help="d3q19: the sphere as a level set (jumps fused in the sweep) or as a triangulation")
     ap.add_argument("--d3-table", choices=["on", "off"], default="on",
                     help="run the three-dimensional Table 1 cases after the d3q19 sweep timing")
     ap.add_argument("--cyl-sizes", default="20,40",

@@ -285,13 +285,17 @@ __global__ __launch_bounds__(256) void k_mesh_links3(const long long* __restrict
 }
 
 // After the sweep: the stored population of every cut link's sending node
-// takes the link's jump, so the next pull carries it across.
-__global__ void k_mesh_apply3(Box b, const MeshRec3* __restrict__ r, int n, float* __restrict__ B)
+// takes the link's jump, so the next pull carries it across.  The targets are
+// distinct (links that cross twice were merged on the host) and in address
+// order, so a plain read-modify-write suffices and neighbouring lanes share
+// cache lines.
+__global__ void k_mesh_apply3(const long long* __restrict__ off, const float* __restrict__ delta, int n,
+                              float* __restrict__ B)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    const MeshRec3 q = r[k];
-    atomicAdd(&B[q.dir * b.plane + ((long long)q.z * b.ny + q.y) * b.pitch + q.x], q.delta);
+    const long long o = off[k];
+    B[o] += delta[k];
 }
 
 }  // namespace iilbm3
@@ -308,6 +312,9 @@ struct ii_lbm3_handle {
     MeshRec3* mesh_rec = nullptr;
     int* mesh_count = nullptr;
     int mesh_links = 0;
+    long long* apply_off = nullptr;   // distinct target offsets in the lattice, ascending
+    float* apply_delta = nullptr;     // summed jumps per target
+    int apply_n = 0;
     float* lat[2] = {nullptr, nullptr};
     double* g = nullptr;
     int parity = 0;
@@ -323,10 +330,11 @@ static int fail3(hipError_t e) { return e == hipSuccess ? II_LBM_OK : II_LBM_EDE
 static void free_mesh(ii_lbm3_handle* h)
 {
     for (void* q : {(void*)h->mesh_S, (void*)h->mesh_tri, (void*)h->mesh_pv, (void*)h->mesh_rec,
-                    (void*)h->mesh_count})
+                    (void*)h->mesh_count, (void*)h->apply_off, (void*)h->apply_delta})
         if (q) (void)hipFree(q);
     h->mesh_S = nullptr; h->mesh_tri = nullptr; h->mesh_pv = nullptr; h->mesh_rec = nullptr;
     h->mesh_count = nullptr; h->mesh_links = 0;
+    h->apply_off = nullptr; h->apply_delta = nullptr; h->apply_n = 0;
 }
 
 static long long snap_2m16(double v) { return llrint(v * 65536.0); }
@@ -434,9 +442,9 @@ int ii_lbm3_step(ii_lbm3_handle* h, int64_t n_steps)
             (void)hipEventRecord(h->ev[h->ev_used + 1], h->stream);
             h->ev_used += 2;
         }
-        if (h->mesh_links > 0)
-            hipLaunchKernelGGL(k_mesh_apply3, dim3((h->mesh_links + 255) / 256), dim3(256), 0, h->stream, b,
-                               h->mesh_rec, h->mesh_links, h->lat[h->parity ^ 1]);
+        if (h->apply_n > 0)
+            hipLaunchKernelGGL(k_mesh_apply3, dim3((h->apply_n + 255) / 256), dim3(256), 0, h->stream,
+                               h->apply_off, h->apply_delta, h->apply_n, h->lat[h->parity ^ 1]);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return II_LBM_EDEVICE;
         h->parity ^= 1;
@@ -616,7 +624,53 @@ int ii_lbm3_set_mesh(ii_lbm3_handle* h, int32_t n_vert, const double* X, int32_t
         free_mesh(h);
         return II_LBM_ECAPACITY;
     }
+    // The per-step apply list: target offsets sorted, links that hit the same
+    // population (a link crossing twice) merged in a fixed order.
+    std::vector<MeshRec3> r(count);
+    e = hipMemcpyAsync(r.data(), h->mesh_rec, r.size() * sizeof(MeshRec3), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    const Box& b = h->b;
+    std::vector<std::pair<long long, long long>> key(count);   // (offset, record's own order key)
+    for (int k = 0; k < count; k++) {
+        const MeshRec3& q = r[k];
+        if (q.x < 0 || q.x >= b.nx || q.y < 0 || q.y >= b.ny || q.z < 0 || q.z >= b.nz || q.dir < 1 ||
+            q.dir >= kQ || q.tri < 0 || q.tri >= n_tri) {
+            free_mesh(h);
+            return II_LBM_EDEVICE;
+        }
+        key[k] = {q.dir * b.plane + ((long long)q.z * b.ny + q.y) * b.pitch + q.x,
+                  (long long)q.tri * 32 + q.dir};
+        key[k].second = key[k].second * (1LL << 31) + k;     // ties: triangle, then slot
+    }
+    std::vector<int> order(count);
+    for (int k = 0; k < count; k++) order[k] = k;
+    std::sort(order.begin(), order.end(), [&](int a, int c) { return key[a] < key[c]; });
+    std::vector<long long> off;
+    std::vector<float> delta;
+    for (int k = 0; k < count; k++) {
+        const int j = order[k];
+        if (!off.empty() && off.back() == key[j].first)
+            delta.back() += r[j].delta;
+        else {
+            off.push_back(key[j].first);
+            delta.push_back(r[j].delta);
+        }
+    }
+    if (e == hipSuccess && !off.empty()) e = hipMalloc(&h->apply_off, off.size() * sizeof(long long));
+    if (e == hipSuccess && !off.empty()) e = hipMalloc(&h->apply_delta, delta.size() * sizeof(float));
+    if (e == hipSuccess && !off.empty())
+        e = hipMemcpyAsync(h->apply_off, off.data(), off.size() * sizeof(long long), hipMemcpyHostToDevice,
+                           h->stream);
+    if (e == hipSuccess && !off.empty())
+        e = hipMemcpyAsync(h->apply_delta, delta.data(), delta.size() * sizeof(float), hipMemcpyHostToDevice,
+                           h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+        free_mesh(h);
+        return II_LBM_EDEVICE;
+    }
     h->mesh_links = count;
+    h->apply_n = (int)off.size();
     if (n_links) *n_links = count;
     return II_LBM_OK;
 }

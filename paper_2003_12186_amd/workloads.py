@@ -409,7 +409,7 @@ def box_mesh(lo: Sequence[float], hi: Sequence[float], m: int) -> Tuple[np.ndarr
     return snap_2m16(np.array(verts)), np.array(tris, np.int32)
 
 
-def mesh_inside(X, tri, pts, shift=(1e-7, 0.0, 0.0), chunk: int = 4096) -> np.ndarray:
+def mesh_inside(X, tri, pts, shift=(1e-7, 0.0, 0.0), chunk: int = 0) -> np.ndarray:
     """Whether points lie inside a closed triangulated surface: the winding
     number, the sum of the triangles' solid angles (Van Oosterom and Strackee)
     over 4 pi, above one half.  ``shift`` moves the points off the faces."""
@@ -417,6 +417,7 @@ def mesh_inside(X, tri, pts, shift=(1e-7, 0.0, 0.0), chunk: int = 4096) -> np.nd
     A, B, Cc = X[tri[:, 0]], X[tri[:, 1]], X[tri[:, 2]]
     pts = np.asarray(pts, float) + np.asarray(shift, float)
     out = np.zeros(len(pts), bool)
+    chunk = chunk or max(1, 2_000_000 // len(tri))
     for s in range(0, len(pts), chunk):
         q = pts[s:s + chunk, None, :]
         a, b, c = A[None] - q, B[None] - q, Cc[None] - q
@@ -425,6 +426,37 @@ def mesh_inside(X, tri, pts, shift=(1e-7, 0.0, 0.0), chunk: int = 4096) -> np.nd
         den = (la * lb * lc + np.einsum("pti,pti->pt", a, b) * lc + np.einsum("pti,pti->pt", a, c) * lb
                + np.einsum("pti,pti->pt", b, c) * la)
         out[s:s + chunk] = (2.0 * np.arctan2(num, den)).sum(1) / (4.0 * np.pi) > 0.5
+    return out
+
+
+def star_mesh_inside(X, tri, c, pts, shift=(1e-7, 0.0, 0.0)) -> np.ndarray:
+    """Whether points lie inside a closed surface that is star-shaped about c
+    (every ray from c leaves it once): the triangle whose cone from c holds the
+    point's direction, then the side of that triangle's plane.  Candidate
+    triangles come from a k-d tree of the triangles' directions; a point no
+    candidate holds falls back to the winding number."""
+    from scipy.spatial import cKDTree
+    X = np.asarray(X, float)
+    c = np.asarray(c, float)
+    pts = np.asarray(pts, float) + np.asarray(shift, float)
+    A, B, Cc = X[tri[:, 0]] - c, X[tri[:, 1]] - c, X[tri[:, 2]] - c
+    dirs = A + B + Cc
+    dirs /= np.linalg.norm(dirs, axis=1)[:, None]
+    d = pts - c
+    dn = d / np.maximum(np.linalg.norm(d, axis=1), 1e-300)[:, None]
+    _, cand = cKDTree(dirs).query(dn, k=min(12, len(tri)))
+    out = np.zeros(len(pts), bool)
+    done = np.zeros(len(pts), bool)
+    n = np.cross(B - A, Cc - A)
+    for j in range(cand.shape[1]):
+        t = cand[:, j]
+        hold = (~done & (np.einsum("ij,ij->i", np.cross(A[t], B[t]), d) >= 0)
+                & (np.einsum("ij,ij->i", np.cross(B[t], Cc[t]), d) >= 0)
+                & (np.einsum("ij,ij->i", np.cross(Cc[t], A[t]), d) >= 0))
+        out[hold] = np.einsum("ij,ij->i", d[hold] - A[t[hold]], n[t[hold]]) < 0
+        done |= hold
+    if (~done).any():
+        out[~done] = mesh_inside(X, tri, pts[~done] - np.asarray(shift, float), shift)
     return out
 
 
@@ -445,15 +477,15 @@ def normal_force_mesh_state(p: Problem3, X, tri, F: float, center, R: float) -> 
     """At rest, rho = 1 - 3 F inside the triangulated sphere (vertices on the
     sphere of centre c and radius R, faces within 1 lu inside it) and 1
     outside.  Nodes more than 1 lu inside the sphere are inside, nodes outside
-    it (beyond the vertices' 2^-17 snap) are outside; the shell between takes
-    the winding number."""
+    it (beyond the vertices' 2^-17 snap) are outside; the shell between is
+    classified through the triangle in each node's direction."""
     w = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
     z, y, x = np.mgrid[0:p.nz, 0:p.ny, 0:p.nx]
     pts = np.stack([x.ravel(), y.ravel(), z.ravel()], 1).astype(float)
     r = np.linalg.norm(pts - np.asarray(center, float), axis=1)
     inside = r < R - 1.0
     shell = (r >= R - 1.0) & (r <= R + 1e-4)
-    inside[shell] = mesh_inside(X, tri, pts[shell])
+    inside[shell] = star_mesh_inside(X, tri, center, pts[shell])
     rho = np.where(inside, 1.0 - 3.0 * F, 1.0).reshape(p.nz, p.ny, p.nx)
     return np.ascontiguousarray(w[:, None, None, None] * rho[None])
 

@@ -151,3 +151,17 @@ def test_exact_state_of_the_normal_force_mesh_is_fixed():
     g = f0.copy()
     O3.run_mesh(p, g, X, tri, -F, 1)
     assert np.abs(g - f0).max() > 1e-3
+
+
+def test_star_shaped_inside_test_agrees_with_winding_numbers():
+    # the fast classification the normal-force mesh state uses, against the
+    # winding number, on every node near a geodesic sphere
+    c, R = (10.27, 9.69, 11.13), 6.7
+    X, tri = W.icosphere(c, R)
+    z, y, x = np.mgrid[0:22, 0:21, 0:23]
+    pts = np.stack([x.ravel(), y.ravel(), z.ravel()], 1).astype(float)
+    r = np.linalg.norm(pts - np.array(c), axis=1)
+    sel = pts[(r > R - 2) & (r < R + 1)]
+    a = W.mesh_inside(X, tri, sel)
+    b = W.star_mesh_inside(X, tri, c, sel)
+    assert (a == b).all() and a.any() and (~a).any() and len(sel) > 500
