@@ -33,7 +33,16 @@ class Problem3(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("force_mode", C.c_int32),
                 ("tau", C.c_double), ("cx", C.c_double), ("cy", C.c_double), ("cz", C.c_double),
                 ("radius", C.c_double), ("f_normal", C.c_double), ("n_markers", C.c_int32),
-                ("pad", C.c_int32), ("body", C.c_double * 3)]
+                ("collision", C.c_int32), ("body", C.c_double * 3), ("s", C.c_double * 19)]
+
+
+def mrt_rates(tau: float):
+    """Relaxation rates of the 19 moments (reading R30): 0 for the conserved
+    rho and j, 1/tau for the viscous stresses (3pxx, pww, pxy, pyz, pxz),
+    1.19 for e, 1.4 for eps, 3pixx and piww, 1.2 for the heat fluxes q,
+    1.98 for the third-order m."""
+    sv = 1.0 / tau
+    return [0.0, 1.19, 1.4, 0.0, 1.2, 0.0, 1.2, 0.0, 1.2, sv, 1.4, sv, 1.4, sv, sv, sv, 1.98, 1.98, 1.98]
 
 
 _lib = None
@@ -55,6 +64,7 @@ def lib():
             "or3_step": (C.c_int, [P, d, d]),
             "or3_run": (C.c_int, [P, d, d, C.c_int]),
             "or3_sizeof_problem": (C.c_int, []),
+            "or3_basis": (None, [d]),
             "or3_mesh_links": (C.c_long, [P, C.c_int, d, C.c_int, d, d, d, d, C.c_long]),
             "or3_step_mesh": (C.c_int, [P, d, C.c_int, d, C.c_int, d, d]),
             "or3_run_mesh": (C.c_int, [P, d, C.c_int, d, C.c_int, d, d, C.c_int]),
@@ -82,7 +92,18 @@ def make_problem(w) -> Problem3:
     p.n_markers = int(w.n_markers)
     for a in range(3):
         p.body[a] = float(w.body_force[a])
+    p.collision = int(getattr(w, "collision", 0))
+    rates = getattr(w, "mrt_s", None) or mrt_rates(p.tau)
+    for k in range(19):
+        p.s[k] = float(rates[k])
     return p
+
+
+def basis():
+    """The 19 x 19 moment matrix, row k = moment k at the 19 velocities."""
+    M = np.zeros((19, 19))
+    lib().or3_basis(_ptr(M))
+    return M
 
 
 def lattice():

@@ -1,9 +1,10 @@
 /*
  * Plain FP64 CPU oracle of a D3Q19 immersed interface-lattice Boltzmann step
  * (the three-dimensional form the paper's conclusion calls straightforward;
- * reading R28): a periodic box, single-relaxation-time collision with the
- * He-Luo equilibrium and the simple force term (Sec. 2.2.1-2.2.2 written for
- * nineteen velocities), and a fixed sphere carrying a uniform normal force F
+ * reading R28): a periodic box, single- or multiple-relaxation-time collision
+ * (reading R30) with the He-Luo equilibrium and the simple force term
+ * (Sec. 2.2.1-2.2.2 written for nineteen velocities), and a fixed sphere
+ * carrying a uniform normal force F
  * per unit area, entered either
  *   - II-LBM: through the jump [[f_i]] = sigma w_i [[p]] / c_s^2 with
  *     [[p]] = F on every link the sphere's level set cuts (Sec. 3.1,
@@ -44,8 +45,10 @@ typedef struct {
     double tau;
     double cx, cy, cz, radius;         /* the sphere */
     double f_normal;                   /* F per unit area along the outward normal */
-    int32_t n_markers, pad;            /* IB-LBM markers on the sphere */
+    int32_t n_markers;                 /* IB-LBM markers on the sphere */
+    int32_t collision;                 /* 0 SRT, 1 MRT (reading R30) */
     double body[3];                    /* uniform body force */
+    double s[19];                      /* MRT relaxation rates of the moments below */
 } or3_problem;
 
 static long id3(const or3_problem *p, int i, int x, int y, int z)
@@ -69,6 +72,48 @@ void or3_equilibrium(double rho, double ux, double uy, double uz, double *feq)
         double eu = EX3[i] * ux + EY3[i] * uy + EZ3[i] * uz;
         feq[i] = wt3(i) * (rho + eu / CS2 + eu * eu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
     }
+}
+
+/* The orthogonal D3Q19 moment basis of d'Humieres et al. (2002), the 3-D
+ * counterpart of the Lallemand-Luo basis the paper's MRT uses (Sec. 2.2.1;
+ * reading R30), row k as a polynomial in e = (cx, cy, cz), c2 = |e|^2:
+ *   0 rho: 1            1 e: 19 c2 - 30        2 eps: (21 c2^2 - 53 c2 + 24) / 2
+ *   3 jx: cx            4 qx: (5 c2 - 9) cx    5 jy: cy       6 qy: (5 c2 - 9) cy
+ *   7 jz: cz            8 qz: (5 c2 - 9) cz
+ *   9 3pxx: 3 cx^2 - c2                     10 3pixx: (3 c2 - 5)(3 cx^2 - c2)
+ *  11 pww: cy^2 - cz^2                      12 piww: (3 c2 - 5)(cy^2 - cz^2)
+ *  13 pxy: cx cy   14 pyz: cy cz   15 pxz: cx cz
+ *  16 mx: cx (cy^2 - cz^2)   17 my: cy (cz^2 - cx^2)   18 mz: cz (cx^2 - cy^2) */
+static double basis3(int k, int cx, int cy, int cz)
+{
+    const double x = cx, y = cy, z = cz, c2 = x * x + y * y + z * z;
+    switch (k) {
+    case 0: return 1.0;
+    case 1: return 19.0 * c2 - 30.0;
+    case 2: return (21.0 * c2 * c2 - 53.0 * c2 + 24.0) / 2.0;
+    case 3: return x;
+    case 4: return (5.0 * c2 - 9.0) * x;
+    case 5: return y;
+    case 6: return (5.0 * c2 - 9.0) * y;
+    case 7: return z;
+    case 8: return (5.0 * c2 - 9.0) * z;
+    case 9: return 3.0 * x * x - c2;
+    case 10: return (3.0 * c2 - 5.0) * (3.0 * x * x - c2);
+    case 11: return y * y - z * z;
+    case 12: return (3.0 * c2 - 5.0) * (y * y - z * z);
+    case 13: return x * y;
+    case 14: return y * z;
+    case 15: return x * z;
+    case 16: return x * (y * y - z * z);
+    case 17: return y * (z * z - x * x);
+    default: return z * (x * x - y * y);
+    }
+}
+
+void or3_basis(double *M)
+{
+    for (int k = 0; k < Q; k++)
+        for (int i = 0; i < Q; i++) M[k * Q + i] = basis3(k, EX3[i], EY3[i], EZ3[i]);
 }
 
 void or3_moments(const or3_problem *p, const double *f, double *rho, double *ux, double *uy, double *uz)
@@ -159,8 +204,30 @@ int or3_step(const or3_problem *p, double *f, const double *X)
             r += fn[i]; jx += EX3[i] * fn[i]; jy += EY3[i] * fn[i]; jz += EZ3[i] * fn[i];
         }
         or3_equilibrium(r, jx, jy, jz, feq);
+        double fs[Q];
+        if (p->collision == 1) {
+            /* m = M f, m_eq = M f_eq, m* = m - S (m - m_eq), f* = M^-1 m*, with
+             * M^-1 = M^T diag(1 / |row k|^2) for the orthogonal rows */
+            double dm[Q];
+            for (int k = 0; k < Q; k++) {
+                double a = 0.0, nk = 0.0;
+                for (int i = 0; i < Q; i++) {
+                    const double b = basis3(k, EX3[i], EY3[i], EZ3[i]);
+                    a += b * (fn[i] - feq[i]);
+                    nk += b * b;
+                }
+                dm[k] = p->s[k] * a / nk;
+            }
+            for (int i = 0; i < Q; i++) {
+                double a = 0.0;
+                for (int k = 0; k < Q; k++) a += basis3(k, EX3[i], EY3[i], EZ3[i]) * dm[k];
+                fs[i] = fn[i] - a;
+            }
+        } else {
+            for (int i = 0; i < Q; i++) fs[i] = fn[i] - (fn[i] - feq[i]) / p->tau;
+        }
         for (int i = 0; i < Q; i++)
-            fp[(long)i * n + c] = fn[i] - (fn[i] - feq[i]) / p->tau +
+            fp[(long)i * n + c] = fs[i] +
                                   wt3(i) * (EX3[i] * g[c] + EY3[i] * g[n + c] + EZ3[i] * g[2 * n + c]) / CS2;
     }
     for (int i = 0; i < Q; i++)

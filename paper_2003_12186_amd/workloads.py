@@ -296,6 +296,7 @@ class Problem3:
     force_mode: int = FORCE_II_LBM             # FORCE_II_LBM (jumps) or FORCE_IB_LBM (spread)
     n_markers: int = 0                         # IB-LBM markers on the sphere
     body_force: Sequence[float] = (0.0, 0.0, 0.0)
+    collision: int = SRT                       # SRT or MRT (reading R30)
 
 
 def sphere_markers(c: Sequence[float], R: float, n: int) -> np.ndarray:
