@@ -4,8 +4,8 @@
  * (arXiv:2003.12186), whose conclusion calls the extension to three
  * dimensions straightforward, on one MI355X (gfx950).
  *
- * The library advances a periodic box with nineteen velocities, a
- * single-relaxation-time collision with the He-Luo equilibrium and the simple
+ * The library advances a periodic box with nineteen velocities, a single- or
+ * multiple-relaxation-time collision with the He-Luo equilibrium and the simple
  * force term (Sec. 2.2.1-2.2.2 written for D3Q19), and an optional fixed sphere
  * carrying a uniform normal force F per unit area along its outward normal:
  *   - II_LBM_FORCE_II: the jump [[f_i]] = sigma w_i [[p]] / c_s^2 with [[p]] = F
@@ -41,6 +41,13 @@ extern "C" {
  * center, radius, f_normal  the sphere (radius 0: none); it must stay at least
  *              3 lattice units from every side of the box.
  * n_markers    IB-LBM only: markers on the sphere, X0 holds 3 n_markers doubles.
+ * collision    II_LBM_SRT, or II_LBM_MRT: the orthogonal 19-moment basis of
+ *              d'Humieres et al. (2002), the three-dimensional counterpart of
+ *              the basis behind the paper's MRT (Sec. 2.2.1), m_eq = M f_eq,
+ *              rates 0 for rho and j, 1/tau for the five viscous stresses,
+ *              1.19 (e), 1.4 (eps and the two fourth-order stresses), 1.2 (the
+ *              heat fluxes), 1.98 (the three third-order moments); the force
+ *              term stays in velocity space.
  */
 typedef struct ii_lbm3_problem {
     int32_t nx, ny, nz;
@@ -51,7 +58,7 @@ typedef struct ii_lbm3_problem {
     double radius;
     double f_normal;
     int32_t n_markers;
-    int32_t pad;
+    int32_t collision;
 } ii_lbm3_problem;
 
 typedef struct ii_lbm3_handle ii_lbm3_handle;

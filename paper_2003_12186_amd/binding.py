@@ -319,7 +319,7 @@ class Problem3C(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("force_mode", C.c_int32),
                 ("tau", C.c_double), ("body_force", C.c_double * 3), ("center", C.c_double * 3),
                 ("radius", C.c_double), ("f_normal", C.c_double), ("n_markers", C.c_int32),
-                ("pad", C.c_int32)]
+                ("collision", C.c_int32)]
 
 
 EXPORTS3 = ["ii_lbm3_init", "ii_lbm3_step", "ii_lbm3_set_distrib", "ii_lbm3_fields",
@@ -362,6 +362,7 @@ def make_problem3(w) -> Problem3C:
         p.center[a] = float(w.center[a])
     p.radius, p.f_normal = float(w.radius), float(w.f_normal)
     p.n_markers = int(w.n_markers)
+    p.collision = int(getattr(w, "collision", 0))
     return p
 
 

@@ -29,6 +29,50 @@ constexpr double W3D[kQ] = {1.0 / 3.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 /
                             1.0 / 36.0};
 constexpr int kBX = 256;
 
+// The orthogonal 19-moment basis of d'Humieres et al. (2002), the 3-D form of
+// the Lallemand-Luo basis behind the paper's MRT (Sec. 2.2.1): row k is a
+// polynomial in the velocity (cx, cy, cz), evaluated at compile time so the
+// unrolled transforms keep only the non-zero integer coefficients.
+constexpr int basis_row(int k, int x, int y, int z)
+{
+    const int c2 = x * x + y * y + z * z;
+    switch (k) {
+    case 0: return 1;
+    case 1: return 19 * c2 - 30;
+    case 2: return (21 * c2 * c2 - 53 * c2 + 24) / 2;
+    case 3: return x;
+    case 4: return (5 * c2 - 9) * x;
+    case 5: return y;
+    case 6: return (5 * c2 - 9) * y;
+    case 7: return z;
+    case 8: return (5 * c2 - 9) * z;
+    case 9: return 3 * x * x - c2;
+    case 10: return (3 * c2 - 5) * (3 * x * x - c2);
+    case 11: return y * y - z * z;
+    case 12: return (3 * c2 - 5) * (y * y - z * z);
+    case 13: return x * y;
+    case 14: return y * z;
+    case 15: return x * z;
+    case 16: return x * (y * y - z * z);
+    case 17: return y * (z * z - x * x);
+    default: return z * (x * x - y * y);
+    }
+}
+
+struct Basis3 {
+    int m[kQ][kQ];
+};
+
+constexpr Basis3 make_basis3()
+{
+    Basis3 b{};
+    for (int k = 0; k < kQ; k++)
+        for (int i = 0; i < kQ; i++) b.m[k][i] = basis_row(k, E3X[i], E3Y[i], E3Z[i]);
+    return b;
+}
+
+constexpr Basis3 kM3 = make_basis3();
+
 struct Box {
     int nx, ny, nz, pitch;
     long long plane;        // elements per population (pitch * ny * nz)
@@ -36,6 +80,7 @@ struct Box {
     double g[3];            // body force
     int sphere, ib;
     double cx, cy, cz, R, F;
+    double sk[kQ];          // MRT: rate of moment k over the squared norm of its row
 };
 
 __device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
@@ -47,7 +92,7 @@ __device__ __forceinline__ double sphere_phi(const Box& b, double x, double y, d
     return dx * dx + dy * dy + dz * dz - b.R * b.R;
 }
 
-template <bool IB>
+template <bool IB, bool MRT>
 __global__ __launch_bounds__(kBX) void k_sweep3(Box b, const float* __restrict__ A,
                                                 float* __restrict__ B,
                                                 const double* __restrict__ gfield)
@@ -81,13 +126,45 @@ __global__ __launch_bounds__(kBX) void k_sweep3(Box b, const float* __restrict__
     }
     const double jj = jx * jx + jy * jy + jz * jz;
     // He-Luo equilibrium deviation w_i [dr + 3 e.j + 4.5 (e.j)^2 - 1.5 j.j],
-    // SRT relaxation and the force term 3 w_i e.g
+    // SRT or MRT relaxation and the force term 3 w_i e.g
+    if (MRT) {
+        // m - m_eq = M (f - f_eq); f* = f - M^T diag(s_k / |row k|^2) (m - m_eq);
+        // rho and j (rows 0, 3, 5, 7) are conserved and skipped
+        double dev[kQ];
 #pragma unroll
-    for (int i = 0; i < kQ; i++) {
-        const double ej = E3X[i] * jx + E3Y[i] * jy + E3Z[i] * jz;
-        const double eg = E3X[i] * gx + E3Y[i] * gy + E3Z[i] * gz;
-        const double deq = W3D[i] * (r + 3.0 * ej + 4.5 * ej * ej - 1.5 * jj);
-        d[i] = d[i] + b.omega * (deq - d[i]) + 3.0 * W3D[i] * eg;
+        for (int i = 0; i < kQ; i++) {
+            const double ej = E3X[i] * jx + E3Y[i] * jy + E3Z[i] * jz;
+            dev[i] = d[i] - W3D[i] * (r + 3.0 * ej + 4.5 * ej * ej - 1.5 * jj);
+        }
+        double m[kQ];
+#pragma unroll
+        for (int k = 0; k < kQ; k++) {
+            m[k] = 0.0;
+            if (k == 0 || k == 3 || k == 5 || k == 7) continue;
+#pragma unroll
+            for (int i = 0; i < kQ; i++)
+                if (kM3.m[k][i] != 0) m[k] += kM3.m[k][i] * dev[i];
+            m[k] *= b.sk[k];
+        }
+#pragma unroll
+        for (int i = 0; i < kQ; i++) {
+            double a = 0.0;
+#pragma unroll
+            for (int k = 0; k < kQ; k++) {
+                if (k == 0 || k == 3 || k == 5 || k == 7) continue;
+                if (kM3.m[k][i] != 0) a += kM3.m[k][i] * m[k];
+            }
+            const double eg = E3X[i] * gx + E3Y[i] * gy + E3Z[i] * gz;
+            d[i] = d[i] - a + 3.0 * W3D[i] * eg;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kQ; i++) {
+            const double ej = E3X[i] * jx + E3Y[i] * jy + E3Z[i] * jz;
+            const double eg = E3X[i] * gx + E3Y[i] * gy + E3Z[i] * gz;
+            const double deq = W3D[i] * (r + 3.0 * ej + 4.5 * ej * ej - 1.5 * jj);
+            d[i] = d[i] + b.omega * (deq - d[i]) + 3.0 * W3D[i] * eg;
+        }
     }
     if (!IB && b.sphere) {
         // jumps of the links this node sends (Sec. 3.1, Eq. (32)): only a node
@@ -305,6 +382,7 @@ using namespace iilbm3;
 struct ii_lbm3_handle {
     Box b;
     ii_lbm3_problem prob;
+    bool mrt = false;
     hipStream_t stream;
     long long* mesh_S = nullptr;      // snapped vertices, int64 [3 n_vert]
     int* mesh_tri = nullptr;
@@ -349,6 +427,7 @@ int ii_lbm3_init(const ii_lbm3_problem* p, const double* X0, void* hip_stream, i
         return II_LBM_EINVAL;
     if (!(p->tau > 0.5) || !isfinite(p->tau)) return II_LBM_EINVAL;
     if (p->force_mode != II_LBM_FORCE_II && p->force_mode != II_LBM_FORCE_IB) return II_LBM_EINVAL;
+    if (p->collision != II_LBM_SRT && p->collision != II_LBM_MRT) return II_LBM_EINVAL;
     const bool sphere = p->radius > 0.0;
     if (sphere) {
         const double c[3] = {p->center[0], p->center[1], p->center[2]};
@@ -379,6 +458,19 @@ int ii_lbm3_init(const ii_lbm3_problem* p, const double* X0, void* hip_stream, i
     b.ib = sphere && p->force_mode == II_LBM_FORCE_IB;
     b.cx = p->center[0]; b.cy = p->center[1]; b.cz = p->center[2];
     b.R = p->radius; b.F = p->f_normal;
+    {
+        // rates of the 19 moments: conserved 0; e 1.19; eps, 3pixx, piww 1.4;
+        // q 1.2; the viscous stresses 1/tau; m 1.98
+        const double sv = 1.0 / p->tau;
+        const double rate[kQ] = {0.0, 1.19, 1.4, 0.0, 1.2, 0.0, 1.2, 0.0, 1.2, sv,
+                                 1.4, sv,   1.4, sv,  sv,  sv,  1.98, 1.98, 1.98};
+        for (int k = 0; k < kQ; k++) {
+            double n2 = 0.0;
+            for (int i = 0; i < kQ; i++) n2 += (double)kM3.m[k][i] * kM3.m[k][i];
+            b.sk[k] = rate[k] / n2;
+        }
+    }
+    h->mrt = p->collision == II_LBM_MRT;
     h->stream = (hipStream_t)hip_stream;
     const size_t lat = (size_t)kQ * b.plane * sizeof(float);
     hipError_t e = hipMalloc(&h->lat[0], lat);
@@ -432,12 +524,16 @@ int ii_lbm3_step(ii_lbm3_handle* h, int64_t n_steps)
             }
             (void)hipEventRecord(h->ev[h->ev_used], h->stream);
         }
-        if (b.ib)
-            hipLaunchKernelGGL(k_sweep3<true>, grid, dim3(kBX), 0, h->stream, b, h->lat[h->parity],
-                               h->lat[h->parity ^ 1], h->g);
+        float* src = h->lat[h->parity];
+        float* dst = h->lat[h->parity ^ 1];
+        if (b.ib && h->mrt)
+            hipLaunchKernelGGL((k_sweep3<true, true>), grid, dim3(kBX), 0, h->stream, b, src, dst, h->g);
+        else if (b.ib)
+            hipLaunchKernelGGL((k_sweep3<true, false>), grid, dim3(kBX), 0, h->stream, b, src, dst, h->g);
+        else if (h->mrt)
+            hipLaunchKernelGGL((k_sweep3<false, true>), grid, dim3(kBX), 0, h->stream, b, src, dst, h->g);
         else
-            hipLaunchKernelGGL(k_sweep3<false>, grid, dim3(kBX), 0, h->stream, b, h->lat[h->parity],
-                               h->lat[h->parity ^ 1], h->g);
+            hipLaunchKernelGGL((k_sweep3<false, false>), grid, dim3(kBX), 0, h->stream, b, src, dst, h->g);
         if (t) {
             (void)hipEventRecord(h->ev[h->ev_used + 1], h->stream);
             h->ev_used += 2;

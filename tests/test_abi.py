@@ -155,17 +155,18 @@ def test_d3q19_header_calls_are_exported_and_sized(tmp_path):
     prog.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "ii_lbm3.h"\n'
         "int main(void){printf(\"%zu %zu %zu\\n\", sizeof(ii_lbm3_problem),"
-        " offsetof(ii_lbm3_problem, radius), offsetof(ii_lbm3_problem, n_markers));return 0;}\n")
+        " offsetof(ii_lbm3_problem, radius), offsetof(ii_lbm3_problem, collision));return 0;}\n")
     exe = tmp_path / "sz3"
     subprocess.check_call(["gcc", "-std=c11", "-I", os.path.dirname(HEADER3), str(prog), "-o", str(exe)])
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
-    assert got == [C.sizeof(B.Problem3C), B.Problem3C.radius.offset, B.Problem3C.n_markers.offset]
+    assert got == [C.sizeof(B.Problem3C), B.Problem3C.radius.offset, B.Problem3C.collision.offset]
 
 
 @pytest.mark.parametrize("mutate,code", [
     (lambda p: setattr(p, "nx", 4), B.EINVAL),
     (lambda p: setattr(p, "tau", 0.5), B.EINVAL),
     (lambda p: setattr(p, "force_mode", 2), B.EINVAL),
+    (lambda p: setattr(p, "collision", 2), B.EINVAL),
     (lambda p: p.center.__setitem__(0, 2.0), B.EGEOMETRY),      # sphere too near a side
 ])
 def test_d3q19_init_validation_rejects_before_device_access(mutate, code):

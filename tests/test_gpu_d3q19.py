@@ -1,6 +1,7 @@
-"""GPU parity of the D3Q19 form (reading R28; through the C ABI of
+"""GPU parity of the D3Q19 form (readings R28, R30; through the C ABI of
 ii_lbm3.h) against the FP64 CPU oracle: a noisy periodic box with a body
-force, and the normal-force sphere under II-LBM and IB-LBM from rest, with
+force, and the normal-force sphere under II-LBM and IB-LBM from rest, each
+with SRT and MRT, with
 relative L2 velocity <= 1e-6 (FP32 storage, FP64 arithmetic); the sphere's
 exact state held by II-LBM on the GPU.
 """
@@ -31,8 +32,9 @@ def _rel(g, o):
     return np.sqrt(sum(((g[a] - o[a]) ** 2).sum() for a in (1, 2, 3)) / sum((o[a] ** 2).sum() for a in (1, 2, 3)))
 
 
-def test_periodic_box_with_body_force(B):
-    prob = W.Problem3(nx=40, ny=24, nz=20, tau=0.7, body_force=(2e-6, -1e-6, 3e-6))
+@pytest.mark.parametrize("coll", [W.SRT, W.MRT])
+def test_periodic_box_with_body_force(B, coll):
+    prob = W.Problem3(nx=40, ny=24, nz=20, tau=0.7, body_force=(2e-6, -1e-6, 3e-6), collision=coll)
     _, _, _, w = O3.lattice()
     f0 = np.ascontiguousarray(w[:, None, None, None] * (1.0 + 1e-3 * W.seeded_noise((19, 20, 24, 40), 62, 0)))
     sim = B.Sim3(prob)
@@ -44,17 +46,19 @@ def test_periodic_box_with_body_force(B):
     O3.run(p, f, None, 200)
     o = O3.moments(p, f)
     err = _rel(g, o)
-    _say(f"D3Q19 periodic 40x24x20, 200 steps: rel L2 u = {err:.3e}")
+    _say(f"D3Q19 periodic 40x24x20 collision={coll}, 200 steps: rel L2 u = {err:.3e}")
     assert err <= 1e-6
     assert np.abs(g[0] - o[0]).max() < 1e-6
     sim.close()
 
 
-@pytest.mark.parametrize("mode", [W.FORCE_II_LBM, W.FORCE_IB_LBM])
-def test_normal_force_sphere_from_rest(B, mode):
+@pytest.mark.parametrize("mode,coll", [(W.FORCE_II_LBM, W.SRT), (W.FORCE_IB_LBM, W.SRT),
+                                       (W.FORCE_II_LBM, W.MRT), (W.FORCE_IB_LBM, W.MRT)])
+def test_normal_force_sphere_from_rest(B, mode, coll):
     prob, X, meta = W.normal_force_sphere(16, mode, re=20.0)
+    prob.collision = coll
     steps = meta["steps"]
-    _say(f"D3Q19 normal-force sphere D=16 ({prob.nx}^3, Re 20) force_mode={mode}, {steps} steps")
+    _say(f"D3Q19 normal-force sphere D=16 ({prob.nx}^3, Re 20) force_mode={mode} collision={coll}, {steps} steps")
     sim = B.Sim3(prob, X if mode == W.FORCE_IB_LBM else None)
     sim.step(steps)
     g = sim.fields()

@@ -64,14 +64,15 @@ def test_mesh_links_match_oracle(B, name):
     sim.close()
 
 
-def test_mesh_flow_from_a_noisy_state(B):
+@pytest.mark.parametrize("coll", [W.SRT, W.MRT])
+def test_mesh_flow_from_a_noisy_state(B, coll):
     X, tri = _surfaces()["sphere"]
-    prob = W.Problem3(nx=24, ny=25, nz=26, tau=0.7, body_force=(1e-6, 0.0, -2e-6))
+    prob = W.Problem3(nx=24, ny=25, nz=26, tau=0.7, body_force=(1e-6, 0.0, -2e-6), collision=coll)
     pv = 2e-3 * (1.0 + 0.3 * np.sin(0.7 * X[:, 1]))
     _, _, _, w = O3.lattice()
     f0 = np.ascontiguousarray(w[:, None, None, None] * (1.0 + 1e-3 * W.seeded_noise((19, 26, 25, 24), 63, 0)))
     steps = 200
-    _say(f"D3Q19 mesh sphere, noisy start, {steps} steps")
+    _say(f"D3Q19 mesh sphere, noisy start, collision={coll}, {steps} steps")
     sim = B.Sim3(prob)
     sim.set_mesh(X, tri, pv)
     sim.set_distrib(f0)
