@@ -673,11 +673,12 @@ def bench_d3q19(args, B, W) -> int:
     import torch
     L = args.d3_size
     c = (L / 2.0, L / 2.0, L / 2.0)
+    coll = W.MRT if args.d3_collision == "mrt" else W.SRT
     mesh_info = None
     if args.d3_surface == "mesh":
         # the same sphere as a geodesic triangulation (edges <= 2.2 lu), its
         # jumps applied after each sweep by k_mesh_apply3
-        big = W.Problem3(nx=L, ny=L, nz=L, tau=0.8)
+        big = W.Problem3(nx=L, ny=L, nz=L, tau=0.8, collision=coll)
         sim = B.Sim3(big)
         Xm, tm = W.icosphere((c[0] + 0.27, c[1] - 0.31, c[2] + 0.13), L / 4.0)
         torch.cuda.synchronize()
@@ -686,7 +687,7 @@ def bench_d3q19(args, B, W) -> int:
         mesh_info = {"vertices": int(len(Xm)), "triangles": int(len(tm)), "cut_links": int(nl),
                      "set_mesh_ms": round((time.perf_counter() - t0) * 1e3, 2)}
     else:
-        big = W.Problem3(nx=L, ny=L, nz=L, tau=0.8, center=c, radius=L / 4.0, f_normal=1e-3)
+        big = W.Problem3(nx=L, ny=L, nz=L, tau=0.8, center=c, radius=L / 4.0, f_normal=1e-3, collision=coll)
         sim = B.Sim3(big)
     sim.step(args.warmup)
     torch.cuda.synchronize()
@@ -707,6 +708,7 @@ def bench_d3q19(args, B, W) -> int:
         for D in (32, 64):
             for mode, name in ((W.FORCE_II_LBM, "II-LBM"), (W.FORCE_IB_LBM, "IB-LBM")):
                 prob, X, meta = W.normal_force_sphere(D, mode)
+                prob.collision = coll
                 s3 = B.Sim3(prob, X if mode == W.FORCE_IB_LBM else None)
                 if start == "exact":
                     s3.set_distrib(W.normal_force_sphere_state(prob))
@@ -721,6 +723,7 @@ def bench_d3q19(args, B, W) -> int:
                 s3.close()
             # II-LBM on the triangulated sphere, exact state from the mesh's own inside
             prob, Xm, tm, pv, meta = W.normal_force_mesh(D, offset=(0.27, -0.31, 0.13))
+            prob.collision = coll
             s3 = B.Sim3(prob)
             s3.set_mesh(Xm, tm, pv)
             if start == "exact":
@@ -741,11 +744,14 @@ def bench_d3q19(args, B, W) -> int:
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3 / args.steps, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 storage / fp64 collision", "data": "synthetic",
-        "config": {"workload": f"d3q19_sphere{L}" + ("_mesh" if mesh_info else ""), "nx": L, "ny": L, "nz": L,
-                   "sphere_D": L // 2, "surface": args.d3_surface, "mesh": mesh_info, "table1_3d": rows},
+        "config": {"workload": f"d3q19_sphere{L}" + ("_mesh" if mesh_info else "")
+                   + ("_mrt" if coll == W.MRT else ""), "nx": L, "ny": L, "nz": L,
+                   "sphere_D": L // 2, "surface": args.d3_surface, "collision": args.d3_collision,
+                   "mesh": mesh_info, "table1_3d": rows},
         "roofline": {"bound": "hbm", "kernel": "k_sweep3", "achieved": round(bpl / avg / 1e9, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(bpl / avg / 1e9 / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(f"d3q19_{L}"), "bytes_per_launch": bpl,
+                     "traffic": measured_traffic(f"d3q19_{L}" + ("_mrt" if coll == W.MRT else "")),
+                     "bytes_per_launch": bpl,
                      "avg_launch_us": round(avg * 1e6, 2), "timed_launches": launches},
     }
     if not args.no_cpu:
@@ -956,6 +962,8 @@ def main() -> int:
                          "reported in the design notes)")
     ap.add_argument("--re", type=float, default=100.0, help="Reynolds number of the cylinder workload")
     ap.add_argument("--d3-size", type=int, default=256, help="box side of the d3q19 workload")
+    ap.add_argument("--d3-collision", choices=["srt", "mrt"], default="srt",
+                    help="d3q19: collision of the timed box and of the Table 1 cases")
     ap.add_argument("--d3-surface", choices=["levelset", "mesh"], default="levelset",
                     help="d3q19: the sphere as a level set (jumps fused in the sweep) or as a triangulation")
     ap.add_argument("--d3-table", choices=["on", "off"], default="on",

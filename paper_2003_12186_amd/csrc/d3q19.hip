@@ -73,6 +73,25 @@ constexpr Basis3 make_basis3()
 
 constexpr Basis3 kM3 = make_basis3();
 
+// Rows odd in the velocity: j, q and the third-order m.
+constexpr bool kOddRow[kQ] = {false, false, false, true, true, true, true, true, true, false,
+                              false, false, false, false, false, false, true, true, true};
+
+// Populations 2p - 1 and 2p are opposite, and each row is even or odd.
+constexpr bool check_pairs()
+{
+    for (int p = 1; p < 10; p++) {
+        if (E3X[2 * p - 1] != -E3X[2 * p] || E3Y[2 * p - 1] != -E3Y[2 * p] || E3Z[2 * p - 1] != -E3Z[2 * p])
+            return false;
+        for (int k = 0; k < kQ; k++)
+            if (kM3.m[k][2 * p - 1] != (kOddRow[k] ? -kM3.m[k][2 * p] : kM3.m[k][2 * p])) return false;
+    }
+    for (int k = 0; k < kQ; k++)
+        if (kOddRow[k] && kM3.m[k][0] != 0) return false;
+    return true;
+}
+static_assert(check_pairs(), "opposite populations and row parity");
+
 struct Box {
     int nx, ny, nz, pitch;
     long long plane;        // elements per population (pitch * ny * nz)
@@ -129,31 +148,53 @@ __global__ __launch_bounds__(kBX) void k_sweep3(Box b, const float* __restrict__
     // SRT or MRT relaxation and the force term 3 w_i e.g
     if (MRT) {
         // m - m_eq = M (f - f_eq); f* = f - M^T diag(s_k / |row k|^2) (m - m_eq);
-        // rho and j (rows 0, 3, 5, 7) are conserved and skipped
+        // rho and j (rows 0, 3, 5, 7) are conserved and skipped.  Populations
+        // 2p-1 and 2p are opposite (p = 1..9), and every row is even or odd in
+        // the velocity, so even rows see only the pair sums, odd rows only the
+        // pair differences, and the update of a pair is (E + O, E - O).
         double dev[kQ];
 #pragma unroll
         for (int i = 0; i < kQ; i++) {
             const double ej = E3X[i] * jx + E3Y[i] * jy + E3Z[i] * jz;
             dev[i] = d[i] - W3D[i] * (r + 3.0 * ej + 4.5 * ej * ej - 1.5 * jj);
         }
+        double sp[10], dp[10];            // pair sums / differences; sp[0] = rest
+        sp[0] = dev[0];
+        dp[0] = 0.0;
+#pragma unroll
+        for (int q = 1; q < 10; q++) {
+            sp[q] = dev[2 * q - 1] + dev[2 * q];
+            dp[q] = dev[2 * q - 1] - dev[2 * q];
+        }
         double m[kQ];
 #pragma unroll
         for (int k = 0; k < kQ; k++) {
             m[k] = 0.0;
             if (k == 0 || k == 3 || k == 5 || k == 7) continue;
+            const bool odd = kOddRow[k];
+            if (!odd && kM3.m[k][0] != 0) m[k] += kM3.m[k][0] * sp[0];
 #pragma unroll
-            for (int i = 0; i < kQ; i++)
-                if (kM3.m[k][i] != 0) m[k] += kM3.m[k][i] * dev[i];
+            for (int q = 1; q < 10; q++)
+                if (kM3.m[k][2 * q - 1] != 0) m[k] += kM3.m[k][2 * q - 1] * (odd ? dp[q] : sp[q]);
             m[k] *= b.sk[k];
+        }
+        double ev[10], od[10];
+#pragma unroll
+        for (int q = 0; q < 10; q++) {
+            const int i = q == 0 ? 0 : 2 * q - 1;
+            ev[q] = 0.0;
+            od[q] = 0.0;
+#pragma unroll
+            for (int k = 0; k < kQ; k++) {
+                if (k == 0 || k == 3 || k == 5 || k == 7 || kM3.m[k][i] == 0) continue;
+                if (kOddRow[k]) od[q] += kM3.m[k][i] * m[k];
+                else ev[q] += kM3.m[k][i] * m[k];
+            }
         }
 #pragma unroll
         for (int i = 0; i < kQ; i++) {
-            double a = 0.0;
-#pragma unroll
-            for (int k = 0; k < kQ; k++) {
-                if (k == 0 || k == 3 || k == 5 || k == 7) continue;
-                if (kM3.m[k][i] != 0) a += kM3.m[k][i] * m[k];
-            }
+            const int q = (i + 1) / 2;
+            const double a = i == 0 ? ev[0] : ((i & 1) ? ev[q] + od[q] : ev[q] - od[q]);
             const double eg = E3X[i] * gx + E3Y[i] * gy + E3Z[i] * gz;
             d[i] = d[i] - a + 3.0 * W3D[i] * eg;
         }
