@@ -65,6 +65,9 @@ def lib():
             "or3_run": (C.c_int, [P, d, d, C.c_int]),
             "or3_sizeof_problem": (C.c_int, []),
             "or3_basis": (None, [d]),
+            "or3_membrane_forces": (C.c_int, [C.c_int, d, C.c_int, d, C.c_double, d, d, d, d, d]),
+            "or3_interp": (None, [P, d, C.c_int, d, d]),
+            "or3_run_membrane": (C.c_int, [P, d, C.c_int, d, C.c_int, d, C.c_double, C.c_int, d]),
             "or3_mesh_links": (C.c_long, [P, C.c_int, d, C.c_int, d, d, d, d, C.c_long]),
             "or3_step_mesh": (C.c_int, [P, d, C.c_int, d, C.c_int, d, d]),
             "or3_run_mesh": (C.c_int, [P, d, C.c_int, d, C.c_int, d, d, C.c_int]),
@@ -180,3 +183,36 @@ def run_mesh(p: Problem3, f, X, tri, pv, steps: int):
     X, tri, pv = _mesh_args(X, tri, pv)
     assert lib().or3_run_mesh(C.byref(p), _ptr(f), len(X), _ptr(X), len(tri), _ptr(tri), _ptr(pv),
                               int(steps)) == 0
+
+
+def membrane_forces(X, tri, gamma: float) -> dict:
+    """Surface-tension forces of a triangulated membrane (reading R31): G
+    (force on the fluid per vertex), outward normals n, vertex areas A,
+    [[p]] = G.n/A and the tangential parts Gt."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    nv = len(X)
+    G, n, Gt = (np.zeros((nv, 3)) for _ in range(3))
+    A, jp = np.zeros(nv), np.zeros(nv)
+    assert lib().or3_membrane_forces(nv, _ptr(X), len(tri), _ptr(tri), float(gamma), _ptr(G), _ptr(n),
+                                     _ptr(A), _ptr(jp), _ptr(Gt)) == 0
+    return {"G": G, "n": n, "A": A, "jp": jp, "Gt": Gt}
+
+
+def interp(p: Problem3, f, X) -> np.ndarray:
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    U = np.zeros_like(X)
+    lib().or3_interp(C.byref(p), _ptr(f), len(X), _ptr(X), _ptr(U))
+    return U
+
+
+def run_membrane(p: Problem3, f, X, tri, gamma: float, steps: int) -> np.ndarray:
+    """Advances f and the vertices X (in place) by steps membrane steps;
+    returns the last step's vertex velocities."""
+    assert f.dtype == np.float64 and f.flags["C_CONTIGUOUS"] and f.shape == (19, p.nz, p.ny, p.nx)
+    assert X.dtype == np.float64 and X.flags["C_CONTIGUOUS"]
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    U = np.zeros_like(X)
+    assert lib().or3_run_membrane(C.byref(p), _ptr(f), len(X), _ptr(X), len(tri), _ptr(tri), float(gamma),
+                                  int(steps), _ptr(U)) == 0
+    return U

@@ -406,3 +406,179 @@ int or3_step_mesh(const or3_problem *p, double *f, int nv, const double *X, int 
 {
     return or3_run_mesh(p, f, nv, X, nt, tri, pv, 1);
 }
+
+/* ------------------------------------------------------------------------
+ * A deformable closed triangulated membrane under surface tension gamma
+ * (reading R31): the three-dimensional counterpart of the flexible interface
+ * of Sec. 2.1 and Sec. 3.2, stepped in the paper's order:
+ *   1. U_v = sum_x u^n(x) delta_h(x - X_v), u from the moments of f^n;
+ *   2. the force on the fluid at vertex v, G_v = -gamma dA/dX_v (A the total
+ *      area), the vertex area A_v (a third of the adjacent triangles), the
+ *      outward normal n_v (area-weighted), [[p]]_v = G_v . n_v / A_v and the
+ *      tangential part G_v - (G_v . n_v) n_v;
+ *   3. the tangential parts spread as g(x) = sum_v Gt_v delta_h(x - X_v);
+ *   4. the cut links of the surface at X^n carry [[p]] (as above);
+ *   5. collision with g, streaming, the jumps;
+ *   6. X^{n+1} = X^n + U^n.
+ * ---------------------------------------------------------------------- */
+
+/* dA/da of a triangle (a, b, c) is (1/2) nhat x (c - b), and cyclically. */
+int or3_membrane_forces(int nv, const double *X, int nt, const int32_t *tri, double gamma, double *G,
+                        double *nrm, double *Av, double *jp, double *Gt)
+{
+    memset(G, 0, sizeof(double) * 3 * nv);
+    memset(nrm, 0, sizeof(double) * 3 * nv);
+    memset(Av, 0, sizeof(double) * nv);
+    for (int t = 0; t < nt; t++) {
+        const int v[3] = {tri[3 * t], tri[3 * t + 1], tri[3 * t + 2]};
+        const double *a = X + 3 * v[0], *b = X + 3 * v[1], *c = X + 3 * v[2];
+        double u[3], w[3], N[3];
+        for (int k = 0; k < 3; k++) { u[k] = b[k] - a[k]; w[k] = c[k] - a[k]; }
+        N[0] = u[1] * w[2] - u[2] * w[1];
+        N[1] = u[2] * w[0] - u[0] * w[2];
+        N[2] = u[0] * w[1] - u[1] * w[0];
+        const double len = sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+        if (!(len > 0.0)) return -1;
+        const double nh[3] = {N[0] / len, N[1] / len, N[2] / len};
+        for (int j = 0; j < 3; j++) {
+            const double *p = X + 3 * v[(j + 1) % 3], *q = X + 3 * v[(j + 2) % 3];
+            const double e[3] = {q[0] - p[0], q[1] - p[1], q[2] - p[2]};
+            const double dA[3] = {0.5 * (nh[1] * e[2] - nh[2] * e[1]), 0.5 * (nh[2] * e[0] - nh[0] * e[2]),
+                                  0.5 * (nh[0] * e[1] - nh[1] * e[0])};
+            for (int k = 0; k < 3; k++) {
+                G[3 * v[j] + k] -= gamma * dA[k];
+                nrm[3 * v[j] + k] += N[k];
+            }
+            Av[v[j]] += len / 6.0;
+        }
+    }
+    for (int i = 0; i < nv; i++) {
+        double *n = nrm + 3 * i;
+        const double l = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        for (int k = 0; k < 3; k++) n[k] /= l;
+        const double *g = G + 3 * i;
+        const double gn = g[0] * n[0] + g[1] * n[1] + g[2] * n[2];
+        jp[i] = gn / Av[i];
+        for (int k = 0; k < 3; k++) Gt[3 * i + k] = g[k] - gn * n[k];
+    }
+    return 0;
+}
+
+/* U_v = sum over the 4 x 4 x 4 nodes around X_v of u(x) delta_h(x - X_v),
+ * u = sum e_i f_i of the state f (which holds f^n, jumps included). */
+void or3_interp(const or3_problem *p, const double *f, int nv, const double *X, double *U)
+{
+    long n = (long)p->nx * p->ny * p->nz;
+    for (int v = 0; v < nv; v++) {
+        const double X0 = X[3 * v], Y0 = X[3 * v + 1], Z0 = X[3 * v + 2];
+        const int x0 = (int)floor(X0) - 1, y0 = (int)floor(Y0) - 1, z0 = (int)floor(Z0) - 1;
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int dz = 0; dz < 4; dz++)
+            for (int dy = 0; dy < 4; dy++)
+                for (int dx = 0; dx < 4; dx++) {
+                    const int x = wrap(x0 + dx, p->nx), y = wrap(y0 + dy, p->ny), z = wrap(z0 + dz, p->nz);
+                    const double wgt = peskin(x0 + dx - X0) * peskin(y0 + dy - Y0) * peskin(z0 + dz - Z0);
+                    const long c = ((long)z * p->ny + y) * p->nx + x;
+                    double jx = 0.0, jy = 0.0, jz = 0.0;
+                    for (int i = 0; i < Q; i++) {
+                        const double fv = f[(long)i * n + c];
+                        jx += EX3[i] * fv; jy += EY3[i] * fv; jz += EZ3[i] * fv;
+                    }
+                    acc[0] += jx * wgt; acc[1] += jy * wgt; acc[2] += jz * wgt;
+                }
+        for (int k = 0; k < 3; k++) U[3 * v + k] = acc[k];
+    }
+}
+
+/* One step of the body force, the force field g (added to the body force),
+ * the collision and the streaming: the step above with g given. */
+static void step_with_field(const or3_problem *p, double *f, const double *gext)
+{
+    int nx = p->nx, ny = p->ny, nz = p->nz;
+    long n = (long)nx * ny * nz;
+    double *fp = malloc((size_t)Q * n * sizeof(double));
+    double M[Q][Q], nk[Q];
+    for (int k = 0; k < Q; k++) {
+        nk[k] = 0.0;
+        for (int i = 0; i < Q; i++) { M[k][i] = basis3(k, EX3[i], EY3[i], EZ3[i]); nk[k] += M[k][i] * M[k][i]; }
+    }
+    for (long c = 0; c < n; c++) {
+        double fn[Q], r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0, feq[Q], fs[Q];
+        for (int i = 0; i < Q; i++) {
+            fn[i] = f[(long)i * n + c];
+            r += fn[i]; jx += EX3[i] * fn[i]; jy += EY3[i] * fn[i]; jz += EZ3[i] * fn[i];
+        }
+        or3_equilibrium(r, jx, jy, jz, feq);
+        if (p->collision == 1) {
+            double dm[Q];
+            for (int k = 0; k < Q; k++) {
+                double a = 0.0;
+                for (int i = 0; i < Q; i++) a += M[k][i] * (fn[i] - feq[i]);
+                dm[k] = p->s[k] * a / nk[k];
+            }
+            for (int i = 0; i < Q; i++) {
+                double a = 0.0;
+                for (int k = 0; k < Q; k++) a += M[k][i] * dm[k];
+                fs[i] = fn[i] - a;
+            }
+        } else {
+            for (int i = 0; i < Q; i++) fs[i] = fn[i] - (fn[i] - feq[i]) / p->tau;
+        }
+        const double gx = p->body[0] + gext[c], gy = p->body[1] + gext[n + c], gz = p->body[2] + gext[2 * n + c];
+        for (int i = 0; i < Q; i++)
+            fp[(long)i * n + c] = fs[i] + wt3(i) * (EX3[i] * gx + EY3[i] * gy + EZ3[i] * gz) / CS2;
+    }
+    for (int i = 0; i < Q; i++)
+        for (int z = 0; z < nz; z++)
+            for (int y = 0; y < ny; y++)
+                for (int x = 0; x < nx; x++)
+                    f[id3(p, i, x, y, z)] = fp[id3(p, i, wrap(x - EX3[i], nx), wrap(y - EY3[i], ny), wrap(z - EZ3[i], nz))];
+    free(fp);
+}
+
+/* Steps of the membrane; X (3 nv) is advanced in place.  U (3 nv, may be
+ * NULL) receives the last step's vertex velocities.  Returns -1 when the
+ * surface degenerates or overflows the link buffer. */
+int or3_run_membrane(const or3_problem *p, double *f, int nv, double *X, int nt, const int32_t *tri,
+                     double gamma, int steps, double *Uout)
+{
+    long n = (long)p->nx * p->ny * p->nz;
+    long cap = 64L * nt + 4096;
+    double *G = malloc(sizeof(double) * 3 * nv), *nrm = malloc(sizeof(double) * 3 * nv);
+    double *Av = malloc(sizeof(double) * nv), *jp = malloc(sizeof(double) * nv);
+    double *Gt = malloc(sizeof(double) * 3 * nv), *U = malloc(sizeof(double) * 3 * nv);
+    double *g = malloc(sizeof(double) * 3 * n);
+    int32_t *rec = malloc((size_t)6 * cap * sizeof(int32_t));
+    double *val = malloc((size_t)4 * cap * sizeof(double));
+    int rc = 0;
+    for (int s = 0; s < steps && rc == 0; s++) {
+        or3_interp(p, f, nv, X, U);
+        if (or3_membrane_forces(nv, X, nt, tri, gamma, G, nrm, Av, jp, Gt)) { rc = -1; break; }
+        memset(g, 0, sizeof(double) * 3 * n);
+        for (int v = 0; v < nv; v++) {
+            const double X0 = X[3 * v], Y0 = X[3 * v + 1], Z0 = X[3 * v + 2];
+            const int x0 = (int)floor(X0) - 1, y0 = (int)floor(Y0) - 1, z0 = (int)floor(Z0) - 1;
+            for (int dz = 0; dz < 4; dz++)
+                for (int dy = 0; dy < 4; dy++)
+                    for (int dx = 0; dx < 4; dx++) {
+                        const double wgt = peskin(x0 + dx - X0) * peskin(y0 + dy - Y0) * peskin(z0 + dz - Z0);
+                        const long c = ((long)wrap(z0 + dz, p->nz) * p->ny + wrap(y0 + dy, p->ny)) * p->nx +
+                                       wrap(x0 + dx, p->nx);
+                        for (int k = 0; k < 3; k++) g[k * n + c] += Gt[3 * v + k] * wgt;
+                    }
+        }
+        const long nl = or3_mesh_links(p, nv, X, nt, tri, jp, rec, val, cap);
+        if (nl < 0) { rc = -1; break; }
+        step_with_field(p, f, g);
+        for (long k = 0; k < nl; k++) {
+            const int32_t *r = rec + 6 * k;
+            const int i = r[3];
+            const int x = wrap(r[0] + EX3[i], p->nx), y = wrap(r[1] + EY3[i], p->ny), z = wrap(r[2] + EZ3[i], p->nz);
+            f[id3(p, i, x, y, z)] += r[4] * wt3(i) * val[4 * k] / CS2;
+        }
+        for (int k = 0; k < 3 * nv; k++) X[k] += U[k];
+    }
+    if (Uout && rc == 0) memcpy(Uout, U, sizeof(double) * 3 * nv);
+    free(G); free(nrm); free(Av); free(jp); free(Gt); free(U); free(g); free(rec); free(val);
+    return rc;
+}

@@ -461,6 +461,14 @@ def star_mesh_inside(X, tri, c, pts, shift=(1e-7, 0.0, 0.0)) -> np.ndarray:
     return out
 
 
+def ellipsoid_membrane(c: Sequence[float], radii: Sequence[float], max_edge: float = 2.2):
+    """A geodesic sphere stretched to the ellipsoid with semi-axes radii about
+    c (vertices snapped to 2^-16): the start of a relaxing drop."""
+    X, tri = icosphere((0.0, 0.0, 0.0), 1.0, max_edge / max(radii))
+    X = snap_2m16(np.asarray(c, float) + X * np.asarray(radii, float))
+    return X, tri
+
+
 def normal_force_mesh(D: int, re: float = 100.0, offset=(0.0, 0.0, 0.0)):
     """The normal-force sphere of Sec. 4.1 in three dimensions, with the sphere
     given as a triangulated surface (edges at most 2.2 lu) carrying [[p]] = F

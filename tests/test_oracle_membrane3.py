@@ -1,0 +1,126 @@
+"""Pins of the oracle's deformable triangulated membrane under surface
+tension in D3Q19 (reading R31), no GPU: the forces are minus gamma times the
+area gradient (central differences), sum to zero with zero torque, and on a
+sphere give [[p]] -> -2 gamma / R; the interpolation is exact for a linear
+velocity; each step's momentum change is the spread tangential force plus
+the jumps; a stretched drop relaxes at constant volume to Laplace's law.
+"""
+import numpy as np
+import pytest
+
+from oracle import d3q19 as O3
+from paper_2003_12186_amd import workloads as W
+
+
+def _area(X, tri):
+    a, b, c = X[tri[:, 0]], X[tri[:, 1]], X[tri[:, 2]]
+    return 0.5 * np.linalg.norm(np.cross(b - a, c - a), axis=1).sum()
+
+
+def _volume(X, tri):
+    a, b, c = X[tri[:, 0]], X[tri[:, 1]], X[tri[:, 2]]
+    return np.einsum("ij,ij->i", a, np.cross(b, c)).sum() / 6.0
+
+
+def test_tension_force_is_minus_gamma_grad_area():
+    X, tri = W.ellipsoid_membrane((12.1, 11.7, 12.4), (6.0, 4.5, 5.2))
+    X = X + 0.1 * W.seeded_noise(X.shape, 70, 0)
+    gamma = 0.02
+    d = O3.membrane_forces(X, tri, gamma)
+    h = 1e-6
+    for v in (0, 7, 41, 100):
+        for k in range(3):
+            Xp, Xm = X.copy(), X.copy()
+            Xp[v, k] += h
+            Xm[v, k] -= h
+            fd = -gamma * (_area(Xp, tri) - _area(Xm, tri)) / (2 * h)
+            assert d["G"][v, k] == pytest.approx(fd, abs=1e-9)
+    assert np.abs(d["G"].sum(0)).max() < 1e-13
+    assert np.abs(np.cross(X, d["G"]).sum(0)).max() < 1e-12
+    assert d["A"].sum() == pytest.approx(_area(X, tri), rel=1e-13)
+    n = d["n"]
+    assert np.allclose(np.linalg.norm(n, axis=1), 1.0)
+    assert np.allclose(np.einsum("ij,ij->i", d["Gt"], n), 0.0, atol=1e-15)
+    assert np.allclose(d["Gt"] + d["jp"][:, None] * d["A"][:, None] * n, d["G"], atol=1e-15)
+
+
+@pytest.mark.parametrize("R", [5.0, 9.0])
+def test_sphere_pressure_jump_is_laplace(R):
+    X, tri = W.icosphere((12.3, 11.8, 12.6), R)
+    gamma = 0.01
+    d = O3.membrane_forces(X, tri, gamma)
+    assert (d["jp"] < 0).all()
+    # the polyhedron's jump is within the mesh's curvature error of -2 gamma/R
+    assert np.mean(d["jp"]) == pytest.approx(-2 * gamma / R, rel=0.02)
+    assert np.abs(np.mean(d["G"] * (X - np.array([12.3, 11.8, 12.6])), 1)).max() > 0
+
+
+def test_interpolation_is_exact_for_a_linear_velocity():
+    prob = W.Problem3(nx=20, ny=21, nz=22, tau=0.8)
+    p = O3.make_problem(prob)
+    a = np.array([1e-3, -2e-3, 5e-4])
+    Bm = 1e-4 * np.array([[1.0, 2.0, -1.0], [0.5, -1.0, 3.0], [2.0, 0.0, 1.0]])
+    z, y, x = np.mgrid[0:22, 0:21, 0:20].astype(float)
+    pos = np.stack([x, y, z], -1)
+    u = a + pos @ Bm.T
+    f = np.zeros((19, 22, 21, 20))
+    ex, ey, ez, w = O3.lattice()
+    e = np.stack([ex, ey, ez], 1).astype(float)
+    eu = np.einsum("ia,zyxa->izyx", e, u)
+    uu = (u ** 2).sum(-1)
+    f[:] = w[:, None, None, None] * (1.0 + 3 * eu + 4.5 * eu ** 2 - 1.5 * uu[None])
+    f = np.ascontiguousarray(f)
+    X = np.array([[9.3, 10.1, 11.7], [5.5, 6.25, 8.0], [14.9, 13.3, 4.2]])
+    U = O3.interp(p, f, X)
+    assert np.abs(U - (a + X @ Bm.T)).max() < 1e-15
+
+
+def test_membrane_step_momentum_budget():
+    prob = W.Problem3(nx=24, ny=24, nz=24, tau=0.8)
+    p = O3.make_problem(prob)
+    X, tri = W.ellipsoid_membrane((12.1, 11.7, 12.4), (6.0, 4.5, 5.2))
+    gamma = 0.01
+    ex, ey, ez, w = O3.lattice()
+    f = np.ascontiguousarray(w[:, None, None, None]
+                             * (1.0 + 1e-3 * W.seeded_noise((19, 24, 24, 24), 71, 0)))
+    for _ in range(2):
+        d = O3.membrane_forces(X, tri, gamma)
+        L = O3.mesh_links(p, X, tri, d["jp"])
+        m0 = [q.sum() for q in O3.moments(p, f)]
+        X0 = X.copy()
+        U = O3.run_membrane(p, f, X, tri, gamma, 1)
+        m1 = [q.sum() for q in O3.moments(p, f)]
+        # round-off of sums over 24^3 nodes: 1e-16 of the summed magnitudes
+        assert abs(m1[0] - m0[0]) < 1e-14 * m0[0]
+        coef = L["sigma"] * w[L["dir"]] * 3.0 * L["jp"]
+        for k, e in enumerate((ex, ey, ez)):
+            # the spread conserves the total tangential force (partition of unity)
+            want = d["Gt"][:, k].sum() + (coef * e[L["dir"]]).sum()
+            assert m1[k + 1] - m0[k + 1] == pytest.approx(want, abs=1e-12)
+        assert np.allclose(X, X0 + U, atol=1e-15)
+
+
+def test_stretched_drop_relaxes_to_laplace_law():
+    # ellipsoid 6 x 4.5 x 5.2 in a periodic 26^3 box, gamma = 0.01, tau = 1:
+    # after 500 steps it is round to 2 %, its volume kept within 1.5 % (the
+    # loss happens in the first transient and then stays), and the pressure
+    # inside exceeds the pressure outside by 2 gamma / R_eq within 3 % (the
+    # mesh's curvature and the interface's smearing)
+    n = 26
+    c = (13.1, 12.7, 13.4)
+    prob = W.Problem3(nx=n, ny=n, nz=n, tau=1.0)
+    p = O3.make_problem(prob)
+    X, tri = W.ellipsoid_membrane(c, (6.0, 4.5, 5.2))
+    V0 = _volume(X, tri)
+    f = O3.rest_state(p)
+    O3.run_membrane(p, f, X, tri, 0.01, 500)
+    V1 = _volume(X, tri)
+    assert V1 == pytest.approx(V0, rel=0.015)
+    r = np.linalg.norm(X - X.mean(0), axis=1)
+    assert r.std() / r.mean() < 0.02
+    Req = (3 * V1 / (4 * np.pi)) ** (1 / 3)
+    rho = O3.moments(p, f)[0]
+    z, y, x = np.mgrid[0:n, 0:n, 0:n]
+    dist = np.sqrt((x - X.mean(0)[0]) ** 2 + (y - X.mean(0)[1]) ** 2 + (z - X.mean(0)[2]) ** 2)
+    dp = (rho[dist < Req - 2].mean() - rho[dist > Req + 2].mean()) / 3.0
+    assert dp == pytest.approx(2 * 0.01 / Req, rel=0.03)
