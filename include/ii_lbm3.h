@@ -131,6 +131,37 @@ int ii_lbm3_set_mesh(ii_lbm3_handle* h, int32_t n_vert, const double* X, int32_t
  * is smaller.  Synchronises. */
 int ii_lbm3_mesh_links(ii_lbm3_handle* h, int64_t cap, int32_t* rec, double* jp, int64_t* n_links);
 
+/*
+ * A deformable closed triangulated membrane under surface tension gamma (>= 0),
+ * the three-dimensional counterpart of the flexible interfaces of Sec. 2.1 and
+ * Sec. 3.2.  Each step, in the paper's order:
+ *   1. U_v = sum_x u^n(x) delta_h(x - X_v) (Peskin's four-point delta in each
+ *      axis, Sec. 2.1.2, Eq. (10));
+ *   2. the force on the fluid at vertex v, G_v = -gamma dA/dX_v (A the total
+ *      area); the vertex area A_v (a third of its triangles'), the
+ *      area-weighted outward normal n_v, [[p]]_v = G_v . n_v / A_v and the
+ *      tangential part G_v - (G_v . n_v) n_v (Sec. 3.2, Eq. (47)-(49));
+ *   3. the tangential parts spread as a force field (Sec. 2.2.2, Eq. (17));
+ *   4. the links the surface cuts at X^n carry the jumps (as for the fixed
+ *      surface above, found again every step);
+ *   5. X^{n+1} = X^n + U^n (Sec. 2.1.2, Eq. (11)).
+ * Validation as ii_lbm3_check_mesh, plus EINVAL for a non-finite or negative
+ * gamma or an IB-LBM sphere in the problem (the force field is shared).  The
+ * library copies the arrays; a fixed surface installed before is removed, as
+ * a membrane is by a later ii_lbm3_set_mesh; n_vert = n_tri = 0 removes it.
+ * Synchronises.
+ *
+ * On the device, a vertex that leaves [2, n - 3] on some axis, an edge longer
+ * than 4 lu or a degenerate triangle stops the membrane (the fluid keeps
+ * stepping without it); so do more cut links than 64 n_tri + 4096.
+ * ii_lbm3_membrane copies the vertices X[n_vert][3] and the last step's
+ * velocities U[n_vert][3] (either may be NULL) and reports such a stop as
+ * EGEOMETRY or ECAPACITY; ESTATE without a membrane.  Synchronises.
+ */
+int ii_lbm3_set_membrane(ii_lbm3_handle* h, int32_t n_vert, const double* X, int32_t n_tri,
+                         const int32_t* tri, double gamma);
+int ii_lbm3_membrane(ii_lbm3_handle* h, double* X, double* U);
+
 int ii_lbm3_destroy(ii_lbm3_handle* h);
 
 #ifdef __cplusplus

@@ -324,7 +324,8 @@ class Problem3C(C.Structure):
 
 EXPORTS3 = ["ii_lbm3_init", "ii_lbm3_step", "ii_lbm3_set_distrib", "ii_lbm3_fields",
             "ii_lbm3_set_timing", "ii_lbm3_get_timing", "ii_lbm3_sweep_bytes", "ii_lbm3_check_mesh",
-            "ii_lbm3_set_mesh", "ii_lbm3_mesh_links", "ii_lbm3_destroy"]
+            "ii_lbm3_set_mesh", "ii_lbm3_mesh_links", "ii_lbm3_set_membrane", "ii_lbm3_membrane",
+            "ii_lbm3_destroy"]
 
 
 def _lib3():
@@ -342,6 +343,8 @@ def _lib3():
             "ii_lbm3_check_mesh": [C.POINTER(Problem3C), i32, v, i32, v],
             "ii_lbm3_set_mesh": [v, i32, v, i32, v, v, C.POINTER(i64)],
             "ii_lbm3_mesh_links": [v, i64, v, v, C.POINTER(i64)],
+            "ii_lbm3_set_membrane": [v, i32, v, i32, v, d],
+            "ii_lbm3_membrane": [v, v, v],
             "ii_lbm3_destroy": [v],
         }
         for name, args in sigs.items():
@@ -426,6 +429,20 @@ class Sim3:
         check(_lib3().ii_lbm3_set_mesh(self.h, len(X), X.ctypes.data, len(tri), tri.ctypes.data,
                                        pv.ctypes.data, C.byref(n)), "set_mesh3")
         return n.value
+
+    def set_membrane(self, X, tri, gamma: float) -> None:
+        """Installs a deformable triangulated membrane under surface tension."""
+        X, tri, _ = _mesh3_args(X, tri, 0.0)
+        self._memb_nv = len(X)
+        check(_lib3().ii_lbm3_set_membrane(self.h, len(X), X.ctypes.data, len(tri), tri.ctypes.data,
+                                           float(gamma)), "set_membrane3")
+
+    def membrane(self):
+        """The membrane's vertices and the last step's vertex velocities."""
+        X = np.zeros((self._memb_nv, 3))
+        U = np.zeros((self._memb_nv, 3))
+        check(_lib3().ii_lbm3_membrane(self.h, X.ctypes.data, U.ctypes.data), "membrane3")
+        return X, U
 
     def mesh_links(self) -> dict:
         n = C.c_int64()

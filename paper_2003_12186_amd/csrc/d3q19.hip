@@ -360,11 +360,12 @@ __global__ __launch_bounds__(256) void k_mesh_links3(const long long* __restrict
                                                      const int* __restrict__ tri,
                                                      const double* __restrict__ pv, int nt,
                                                      MeshRec3* __restrict__ out, int cap,
-                                                     int* __restrict__ count)
+                                                     int* __restrict__ count, const int* err)
 {
     const int t = blockIdx.x * kMeshWaves + threadIdx.x / 64;
     const int lane = threadIdx.x % 64;
     if (t >= nt) return;
+    if (err && *(volatile const int*)err) return;
     const int ia = tri[3 * t], ib = tri[3 * t + 1], ic = tri[3 * t + 2];
     long long A[3], B[3], C[3];
     int lo[3], n[3];
@@ -416,6 +417,179 @@ __global__ void k_mesh_apply3(const long long* __restrict__ off, const float* __
     B[o] += delta[k];
 }
 
+// ---------------------------------------------------------------------------
+// A deformable triangulated membrane under surface tension.  Every kernel
+// reads the sticky error word first and does nothing once it is set, so a
+// surface that leaves the supported region stops the membrane work of every
+// later step (the fluid sweep still runs).  err: 1 geometry, 2 capacity.
+__device__ __forceinline__ bool memb_failed(const int* err) { return *(volatile const int*)err != 0; }
+
+__device__ __forceinline__ bool memb_inside(const Box& b, double x, double y, double z)
+{
+    return x >= 2.0 && x <= b.nx - 3.0 && y >= 2.0 && y <= b.ny - 3.0 && z >= 2.0 && z <= b.nz - 3.0;
+}
+
+// U_v = sum of u(x) delta_h(x - X_v) over the 4 x 4 x 4 nodes around X_v: one
+// wave per vertex, one lane per node, u from the pulled deviations.
+__global__ __launch_bounds__(256) void k_memb_interp3(Box b, const float* __restrict__ A,
+                                                      const double* __restrict__ X, int nv,
+                                                      double* __restrict__ U, int* err)
+{
+    const int v = blockIdx.x * 4 + threadIdx.x / 64;
+    const int lane = threadIdx.x % 64;
+    if (v >= nv || memb_failed(err)) return;
+    const double X0 = X[3 * v], Y0 = X[3 * v + 1], Z0 = X[3 * v + 2];
+    if (!memb_inside(b, X0, Y0, Z0)) {
+        if (lane == 0) atomicOr(err, 1);
+        return;
+    }
+    const int x0 = (int)floor(X0) - 1, y0 = (int)floor(Y0) - 1, z0 = (int)floor(Z0) - 1;
+    const int x = x0 + (lane & 3), y = y0 + ((lane >> 2) & 3), z = z0 + (lane >> 4);
+    const double w = peskin1(x - X0) * peskin1(y - Y0) * peskin1(z - Z0);
+    double jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+    for (int i = 0; i < kQ; i++) {
+        const int xs = wrapi(x - E3X[i], b.nx), ys = wrapi(y - E3Y[i], b.ny), zs = wrapi(z - E3Z[i], b.nz);
+        const double d = (double)A[i * b.plane + ((long long)zs * b.ny + ys) * b.pitch + xs];
+        jx += E3X[i] * d;
+        jy += E3Y[i] * d;
+        jz += E3Z[i] * d;
+    }
+    double ux = jx * w, uy = jy * w, uz = jz * w;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        ux += __shfl_xor(ux, o, 64);
+        uy += __shfl_xor(uy, o, 64);
+        uz += __shfl_xor(uz, o, 64);
+    }
+    if (lane == 0) {
+        U[3 * v] = ux;
+        U[3 * v + 1] = uy;
+        U[3 * v + 2] = uz;
+    }
+}
+
+// Vertices snapped to 2^-16 for the exact link tests, after the bounds check.
+__global__ void k_memb_snap3(Box b, const double* __restrict__ X, int nv, long long* __restrict__ S, int* err)
+{
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nv || memb_failed(err)) return;
+    const double x = X[3 * v], y = X[3 * v + 1], z = X[3 * v + 2];
+    if (!memb_inside(b, x, y, z)) {
+        atomicOr(err, 1);
+        return;
+    }
+    S[3 * v] = __double2ll_rn(x * 65536.0);
+    S[3 * v + 1] = __double2ll_rn(y * 65536.0);
+    S[3 * v + 2] = __double2ll_rn(z * 65536.0);
+}
+
+// Per vertex, over its triangles in ascending order: the tension force on the
+// fluid G_v = -gamma sum dA_t/dX_v with dA/da = (1/2) nhat x (c - b) for a
+// triangle (a, b, c), cyclically; the area-weighted normal; the vertex area
+// (a third of each triangle); then [[p]]_v = G.n / A_v and the tangential
+// part.  Edges longer than 4 lu or a degenerate triangle set the error.
+__global__ void k_memb_forces3(const double* __restrict__ X, const int* __restrict__ tri,
+                               const int* __restrict__ vt_off, const int* __restrict__ vt, int nv,
+                               double gamma, double* __restrict__ jp, double* __restrict__ Gt, int* err)
+{
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nv || memb_failed(err)) return;
+    double G[3] = {0.0, 0.0, 0.0}, nr[3] = {0.0, 0.0, 0.0}, Av = 0.0;
+    for (int q = vt_off[v]; q < vt_off[v + 1]; q++) {
+        const int t = vt[q];
+        const int c3[3] = {tri[3 * t], tri[3 * t + 1], tri[3 * t + 2]};
+        const int j = c3[0] == v ? 0 : (c3[1] == v ? 1 : 2);
+        const double* a = X + 3 * c3[0];
+        const double* bb = X + 3 * c3[1];
+        const double* c = X + 3 * c3[2];
+        double u[3], w[3];
+        for (int k = 0; k < 3; k++) {
+            u[k] = bb[k] - a[k];
+            w[k] = c[k] - a[k];
+        }
+        const double l2c = (c[0] - bb[0]) * (c[0] - bb[0]) + (c[1] - bb[1]) * (c[1] - bb[1]) +
+                           (c[2] - bb[2]) * (c[2] - bb[2]);
+        if (u[0] * u[0] + u[1] * u[1] + u[2] * u[2] > 16.0 || w[0] * w[0] + w[1] * w[1] + w[2] * w[2] > 16.0 ||
+            l2c > 16.0) {
+            atomicOr(err, 1);
+            return;
+        }
+        const double N[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
+        const double len = sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+        if (!(len > 0.0)) {
+            atomicOr(err, 1);
+            return;
+        }
+        const double nh[3] = {N[0] / len, N[1] / len, N[2] / len};
+        const double* p = X + 3 * c3[(j + 1) % 3];
+        const double* qq = X + 3 * c3[(j + 2) % 3];
+        const double e[3] = {qq[0] - p[0], qq[1] - p[1], qq[2] - p[2]};
+        const double dA[3] = {0.5 * (nh[1] * e[2] - nh[2] * e[1]), 0.5 * (nh[2] * e[0] - nh[0] * e[2]),
+                              0.5 * (nh[0] * e[1] - nh[1] * e[0])};
+        for (int k = 0; k < 3; k++) {
+            G[k] -= gamma * dA[k];
+            nr[k] += N[k];
+        }
+        Av += len / 6.0;
+    }
+    const double l = sqrt(nr[0] * nr[0] + nr[1] * nr[1] + nr[2] * nr[2]);
+    for (int k = 0; k < 3; k++) nr[k] /= l;
+    const double gn = G[0] * nr[0] + G[1] * nr[1] + G[2] * nr[2];
+    jp[v] = gn / Av;
+    for (int k = 0; k < 3; k++) Gt[3 * v + k] = G[k] - gn * nr[k];
+}
+
+// g(x) += Gt_v delta_h(x - X_v): one thread per (vertex, stencil node).
+__global__ void k_memb_spread3(Box b, const double* __restrict__ X, const double* __restrict__ Gt, int nv,
+                               double* __restrict__ g, const int* err)
+{
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t >= (long long)nv * 64 || memb_failed(err)) return;
+    const int v = (int)(t / 64), lane = (int)(t % 64);
+    const double X0 = X[3 * v], Y0 = X[3 * v + 1], Z0 = X[3 * v + 2];
+    const int x = (int)floor(X0) - 1 + (lane & 3), y = (int)floor(Y0) - 1 + ((lane >> 2) & 3),
+              z = (int)floor(Z0) - 1 + (lane >> 4);
+    const double w = peskin1(x - X0) * peskin1(y - Y0) * peskin1(z - Z0);
+    const long long n = (long long)b.nx * b.ny * b.nz;
+    const long long c = ((long long)z * b.ny + y) * b.nx + x;
+    atomicAdd(&g[c], Gt[3 * v] * w);
+    atomicAdd(&g[n + c], Gt[3 * v + 1] * w);
+    atomicAdd(&g[2 * n + c], Gt[3 * v + 2] * w);
+}
+
+__global__ void k_zero_count3(int* count) { *count = 0; }
+
+__global__ void k_zero_f64(double* p, long long n)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+// The step's jumps, straight from the records (several may share a target).
+__global__ void k_memb_apply3(Box b, const MeshRec3* __restrict__ r, const int* __restrict__ count, int cap,
+                              float* __restrict__ B, int* err)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (memb_failed(err)) return;
+    const int n = *count;
+    if (n > cap) {
+        if (k == 0) atomicOr(err, 2);
+        return;
+    }
+    if (k >= n) return;
+    const MeshRec3 q = r[k];
+    atomicAdd(&B[q.dir * b.plane + ((long long)q.z * b.ny + q.y) * b.pitch + q.x], q.delta);
+}
+
+__global__ void k_memb_move3(double* __restrict__ X, const double* __restrict__ U, int n3, const int* err)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n3 || memb_failed(err)) return;
+    X[k] += U[k];
+}
+
 }  // namespace iilbm3
 
 using namespace iilbm3;
@@ -434,6 +608,21 @@ struct ii_lbm3_handle {
     long long* apply_off = nullptr;   // distinct target offsets in the lattice, ascending
     float* apply_delta = nullptr;     // summed jumps per target
     int apply_n = 0;
+    // deformable membrane (the surface above is then unused)
+    bool memb = false;
+    int memb_nv = 0, memb_nt = 0, memb_cap = 0;
+    double memb_gamma = 0.0;
+    double* memb_X = nullptr;         // vertices [3 nv]
+    double* memb_U = nullptr;         // velocities of the last step [3 nv]
+    double* memb_jp = nullptr;        // [[p]] per vertex
+    double* memb_Gt = nullptr;        // tangential force per vertex [3 nv]
+    long long* memb_S = nullptr;      // snapped vertices
+    int* memb_tri = nullptr;
+    int* memb_vt_off = nullptr;       // triangles of each vertex (CSR, ascending)
+    int* memb_vt = nullptr;
+    MeshRec3* memb_rec = nullptr;
+    int* memb_count = nullptr;
+    int* memb_err = nullptr;
     float* lat[2] = {nullptr, nullptr};
     double* g = nullptr;
     int parity = 0;
@@ -457,6 +646,50 @@ static void free_mesh(ii_lbm3_handle* h)
 }
 
 static long long snap_2m16(double v) { return llrint(v * 65536.0); }
+
+static void free_membrane(ii_lbm3_handle* h)
+{
+    for (void* q : {(void*)h->memb_X, (void*)h->memb_U, (void*)h->memb_jp, (void*)h->memb_Gt, (void*)h->memb_S,
+                    (void*)h->memb_tri, (void*)h->memb_vt_off, (void*)h->memb_vt, (void*)h->memb_rec,
+                    (void*)h->memb_count, (void*)h->memb_err})
+        if (q) (void)hipFree(q);
+    h->memb_X = h->memb_U = h->memb_jp = h->memb_Gt = nullptr;
+    h->memb_S = nullptr;
+    h->memb_tri = h->memb_vt_off = h->memb_vt = h->memb_count = h->memb_err = nullptr;
+    h->memb_rec = nullptr;
+    h->memb = false;
+    h->memb_nv = h->memb_nt = h->memb_cap = 0;
+}
+
+// One membrane step's work before the sweep (interpolation, forces, spread,
+// links) and after it (jumps, motion).
+static void memb_before_sweep(ii_lbm3_handle* h, const float* A)
+{
+    const Box& b = h->b;
+    const int nv = h->memb_nv, nt = h->memb_nt;
+    const long long n = (long long)b.nx * b.ny * b.nz;
+    hipLaunchKernelGGL(k_memb_interp3, dim3((nv + 3) / 4), dim3(256), 0, h->stream, b, A, h->memb_X, nv,
+                       h->memb_U, h->memb_err);
+    hipLaunchKernelGGL(k_memb_snap3, dim3((nv + 255) / 256), dim3(256), 0, h->stream, b, h->memb_X, nv,
+                       h->memb_S, h->memb_err);
+    hipLaunchKernelGGL(k_memb_forces3, dim3((nv + 255) / 256), dim3(256), 0, h->stream, h->memb_X, h->memb_tri,
+                       h->memb_vt_off, h->memb_vt, nv, h->memb_gamma, h->memb_jp, h->memb_Gt, h->memb_err);
+    hipLaunchKernelGGL(k_zero_f64, dim3(1024), dim3(256), 0, h->stream, h->g, 3 * n);
+    hipLaunchKernelGGL(k_memb_spread3, dim3((unsigned)(((long long)nv * 64 + 255) / 256)), dim3(256), 0, h->stream,
+                       b, h->memb_X, h->memb_Gt, nv, h->g, h->memb_err);
+    hipLaunchKernelGGL(k_zero_count3, dim3(1), dim3(1), 0, h->stream, h->memb_count);
+    hipLaunchKernelGGL(k_mesh_links3, dim3((nt + kMeshWaves - 1) / kMeshWaves), dim3(256), 0, h->stream,
+                       h->memb_S, h->memb_tri, h->memb_jp, nt, h->memb_rec, h->memb_cap, h->memb_count,
+                       (const int*)h->memb_err);
+}
+
+static void memb_after_sweep(ii_lbm3_handle* h, float* B)
+{
+    hipLaunchKernelGGL(k_memb_apply3, dim3((h->memb_cap + 255) / 256), dim3(256), 0, h->stream, h->b,
+                       h->memb_rec, h->memb_count, h->memb_cap, B, h->memb_err);
+    hipLaunchKernelGGL(k_memb_move3, dim3((3 * h->memb_nv + 255) / 256), dim3(256), 0, h->stream, h->memb_X,
+                       h->memb_U, 3 * h->memb_nv, h->memb_err);
+}
 
 extern "C" {
 
@@ -567,7 +800,13 @@ int ii_lbm3_step(ii_lbm3_handle* h, int64_t n_steps)
         }
         float* src = h->lat[h->parity];
         float* dst = h->lat[h->parity ^ 1];
-        if (b.ib && h->mrt)
+        if (h->memb) {
+            memb_before_sweep(h, src);
+            if (h->mrt)
+                hipLaunchKernelGGL((k_sweep3<true, true>), grid, dim3(kBX), 0, h->stream, b, src, dst, h->g);
+            else
+                hipLaunchKernelGGL((k_sweep3<true, false>), grid, dim3(kBX), 0, h->stream, b, src, dst, h->g);
+        } else if (b.ib && h->mrt)
             hipLaunchKernelGGL((k_sweep3<true, true>), grid, dim3(kBX), 0, h->stream, b, src, dst, h->g);
         else if (b.ib)
             hipLaunchKernelGGL((k_sweep3<true, false>), grid, dim3(kBX), 0, h->stream, b, src, dst, h->g);
@@ -579,6 +818,7 @@ int ii_lbm3_step(ii_lbm3_handle* h, int64_t n_steps)
             (void)hipEventRecord(h->ev[h->ev_used + 1], h->stream);
             h->ev_used += 2;
         }
+        if (h->memb) memb_after_sweep(h, dst);
         if (h->apply_n > 0)
             hipLaunchKernelGGL(k_mesh_apply3, dim3((h->apply_n + 255) / 256), dim3(256), 0, h->stream,
                                h->apply_off, h->apply_delta, h->apply_n, h->lat[h->parity ^ 1]);
@@ -651,7 +891,7 @@ int ii_lbm3_sweep_bytes(ii_lbm3_handle* h, double* bytes)
 {
     if (!h || !bytes) return II_LBM_EINVAL;
     const double n = (double)h->b.nx * h->b.ny * h->b.nz;
-    *bytes = n * (2.0 * kQ * 4.0 + (h->b.ib ? 24.0 : 0.0));
+    *bytes = n * (2.0 * kQ * 4.0 + ((h->b.ib || h->memb) ? 24.0 : 0.0));
     return II_LBM_OK;
 }
 
@@ -724,6 +964,7 @@ int ii_lbm3_set_mesh(ii_lbm3_handle* h, int32_t n_vert, const double* X, int32_t
     if (hipStreamSynchronize(h->stream) != hipSuccess) return II_LBM_EDEVICE;
     free_mesh(h);
     if (n_links) *n_links = 0;
+    if (n_vert != 0 || n_tri != 0) free_membrane(h);             // one surface at a time
     if (n_vert == 0 && n_tri == 0) return II_LBM_OK;            // surface removed
     const int rc = ii_lbm3_check_mesh(&h->prob, n_vert, X, n_tri, tri);
     if (rc != II_LBM_OK) return rc;
@@ -747,7 +988,8 @@ int ii_lbm3_set_mesh(ii_lbm3_handle* h, int32_t n_vert, const double* X, int32_t
     if (e == hipSuccess) e = hipMemsetAsync(h->mesh_count, 0, sizeof(int), h->stream);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_mesh_links3, dim3((n_tri + kMeshWaves - 1) / kMeshWaves), dim3(256), 0, h->stream,
-                           h->mesh_S, h->mesh_tri, h->mesh_pv, n_tri, h->mesh_rec, (int)cap, h->mesh_count);
+                           h->mesh_S, h->mesh_tri, h->mesh_pv, n_tri, h->mesh_rec, (int)cap, h->mesh_count,
+                           (const int*)nullptr);
         e = hipGetLastError();
     }
     int count = 0;
@@ -812,6 +1054,80 @@ int ii_lbm3_set_mesh(ii_lbm3_handle* h, int32_t n_vert, const double* X, int32_t
     return II_LBM_OK;
 }
 
+int ii_lbm3_set_membrane(ii_lbm3_handle* h, int32_t n_vert, const double* X, int32_t n_tri, const int32_t* tri,
+                         double gamma)
+{
+    if (!h) return II_LBM_EINVAL;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return II_LBM_EDEVICE;
+    free_membrane(h);
+    if (n_vert == 0 && n_tri == 0) return II_LBM_OK;             // membrane removed
+    if (h->b.ib || !isfinite(gamma) || gamma < 0.0) return II_LBM_EINVAL;
+    const int rc = ii_lbm3_check_mesh(&h->prob, n_vert, X, n_tri, tri);
+    if (rc != II_LBM_OK) return rc;
+    free_mesh(h);                                                 // one surface at a time
+    std::vector<int> off(n_vert + 1, 0), vt((size_t)3 * n_tri);
+    for (int t = 0; t < n_tri; t++)
+        for (int k = 0; k < 3; k++) off[tri[3 * t + k] + 1]++;
+    for (int v = 0; v < n_vert; v++) off[v + 1] += off[v];
+    std::vector<int> fill(off.begin(), off.end() - 1);
+    for (int t = 0; t < n_tri; t++)                               // ascending triangle order per vertex
+        for (int k = 0; k < 3; k++) vt[fill[tri[3 * t + k]]++] = t;
+    const long long n = (long long)h->b.nx * h->b.ny * h->b.nz;
+    const int cap = 64 * n_tri + 4096;
+    hipError_t e = hipSuccess;
+    if (!h->g) e = hipMalloc(&h->g, (size_t)3 * n * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&h->memb_X, (size_t)3 * n_vert * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&h->memb_U, (size_t)3 * n_vert * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&h->memb_jp, (size_t)n_vert * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&h->memb_Gt, (size_t)3 * n_vert * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&h->memb_S, (size_t)3 * n_vert * sizeof(long long));
+    if (e == hipSuccess) e = hipMalloc(&h->memb_tri, (size_t)3 * n_tri * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&h->memb_vt_off, (size_t)(n_vert + 1) * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&h->memb_vt, vt.size() * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&h->memb_rec, (size_t)cap * sizeof(MeshRec3));
+    if (e == hipSuccess) e = hipMalloc(&h->memb_count, sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&h->memb_err, sizeof(int));
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->memb_X, X, (size_t)3 * n_vert * sizeof(double), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->memb_tri, tri, (size_t)3 * n_tri * sizeof(int), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->memb_vt_off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->memb_vt, vt.data(), vt.size() * sizeof(int), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(h->memb_U, 0, (size_t)3 * n_vert * sizeof(double), h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(h->memb_count, 0, sizeof(int), h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(h->memb_err, 0, sizeof(int), h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+        free_membrane(h);
+        return II_LBM_EDEVICE;
+    }
+    h->memb = true;
+    h->memb_nv = n_vert;
+    h->memb_nt = n_tri;
+    h->memb_cap = cap;
+    h->memb_gamma = gamma;
+    return II_LBM_OK;
+}
+
+int ii_lbm3_membrane(ii_lbm3_handle* h, double* X, double* U)
+{
+    if (!h) return II_LBM_EINVAL;
+    if (!h->memb) return II_LBM_ESTATE;
+    int err = 0;
+    hipError_t e = hipMemcpyAsync(&err, h->memb_err, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess && X)
+        e = hipMemcpyAsync(X, h->memb_X, (size_t)3 * h->memb_nv * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess && U)
+        e = hipMemcpyAsync(U, h->memb_U, (size_t)3 * h->memb_nv * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return II_LBM_EDEVICE;
+    if (err & 2) return II_LBM_ECAPACITY;
+    if (err & 1) return II_LBM_EGEOMETRY;
+    return II_LBM_OK;
+}
+
 int ii_lbm3_mesh_links(ii_lbm3_handle* h, int64_t cap, int32_t* rec, double* jp, int64_t* n_links)
 {
     if (!h || !n_links || cap < 0 || (cap > 0 && (!rec || !jp))) return II_LBM_EINVAL;
@@ -836,6 +1152,7 @@ int ii_lbm3_destroy(ii_lbm3_handle* h)
     if (!h) return II_LBM_EINVAL;
     (void)hipStreamSynchronize(h->stream);
     free_mesh(h);
+    free_membrane(h);
     for (auto& p : h->lat)
         if (p) (void)hipFree(p);
     if (h->g) (void)hipFree(h->g);
