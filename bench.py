@@ -510,6 +510,18 @@ def bench_table1(args, B, W) -> int:
     sim.set_timing(False)
     avg = ms / 1e3 / max(launches, 1)
     bpl = sim.sweep_bytes()
+    if memb is not None:
+        Xn, _ = sim.membrane()
+        tri = memb[1]
+        def vol(X):
+            a, b_, c_ = X[tri[:, 0]], X[tri[:, 1]], X[tri[:, 2]]
+            return float(np.einsum("ij,ij->i", a, np.cross(b_, c_)).sum() / 6.0)
+        r = np.linalg.norm(Xn - Xn.mean(0), axis=1)
+        r0 = np.linalg.norm(memb[0] - memb[0].mean(0), axis=1)
+        total = args.warmup + args.steps + min(args.steps, 200)
+        mesh_info.update({"steps_run": total, "volume_change": round(vol(Xn) / vol(memb[0]) - 1.0, 5),
+                          "radius_spread_start": round(float(r0.std() / r0.mean()), 4),
+                          "radius_spread_end": round(float(r.std() / r.mean()), 4)})
     sim.close()
     n_steps = sum(r["steps"] for r in rows)
     out = {
@@ -675,7 +687,17 @@ def bench_d3q19(args, B, W) -> int:
     c = (L / 2.0, L / 2.0, L / 2.0)
     coll = W.MRT if args.d3_collision == "mrt" else W.SRT
     mesh_info = None
-    if args.d3_surface == "mesh":
+    memb = None
+    if args.d3_surface == "membrane":
+        # a stretched drop (semi-axes 0.25, 0.1875 and 0.21875 of the box)
+        # under surface tension, its links found again every step
+        big = W.Problem3(nx=L, ny=L, nz=L, tau=0.8, collision=coll)
+        sim = B.Sim3(big)
+        Xm, tm = W.ellipsoid_membrane((c[0] + 0.27, c[1] - 0.31, c[2] + 0.13), (L / 4.0, 0.1875 * L, 0.21875 * L))
+        sim.set_membrane(Xm, tm, 0.01)
+        memb = (Xm, tm)
+        mesh_info = {"vertices": int(len(Xm)), "triangles": int(len(tm)), "gamma": 0.01}
+    elif args.d3_surface == "mesh":
         # the same sphere as a geodesic triangulation (edges <= 2.2 lu), its
         # jumps applied after each sweep by k_mesh_apply3
         big = W.Problem3(nx=L, ny=L, nz=L, tau=0.8, collision=coll)
@@ -701,6 +723,18 @@ def bench_d3q19(args, B, W) -> int:
     sim.set_timing(False)
     avg = ms / 1e3 / max(launches, 1)
     bpl = sim.sweep_bytes()
+    if memb is not None:
+        Xn, _ = sim.membrane()
+        tri = memb[1]
+        def vol(X):
+            a, b_, c_ = X[tri[:, 0]], X[tri[:, 1]], X[tri[:, 2]]
+            return float(np.einsum("ij,ij->i", a, np.cross(b_, c_)).sum() / 6.0)
+        r = np.linalg.norm(Xn - Xn.mean(0), axis=1)
+        r0 = np.linalg.norm(memb[0] - memb[0].mean(0), axis=1)
+        total = args.warmup + args.steps + min(args.steps, 200)
+        mesh_info.update({"steps_run": total, "volume_change": round(vol(Xn) / vol(memb[0]) - 1.0, 5),
+                          "radius_spread_start": round(float(r0.std() / r0.mean()), 4),
+                          "radius_spread_end": round(float(r.std() / r.mean()), 4)})
     sim.close()
     nodes = float(L) ** 3
     rows = []
@@ -744,7 +778,8 @@ def bench_d3q19(args, B, W) -> int:
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3 / args.steps, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 storage / fp64 collision", "data": "synthetic",
-        "config": {"workload": f"d3q19_sphere{L}" + ("_mesh" if mesh_info else "")
+        "config": {"workload": (f"d3q19_membrane{L}" if memb is not None else
+                                f"d3q19_sphere{L}" + ("_mesh" if mesh_info else ""))
                    + ("_mrt" if coll == W.MRT else ""), "nx": L, "ny": L, "nz": L,
                    "sphere_D": L // 2, "surface": args.d3_surface, "collision": args.d3_collision,
                    "mesh": mesh_info, "table1_3d": rows},
@@ -828,6 +863,18 @@ def bench_viv(args, B, W) -> int:
     sim.set_timing(False)
     avg = ms / 1e3 / max(launches, 1)
     bpl = sim.sweep_bytes()
+    if memb is not None:
+        Xn, _ = sim.membrane()
+        tri = memb[1]
+        def vol(X):
+            a, b_, c_ = X[tri[:, 0]], X[tri[:, 1]], X[tri[:, 2]]
+            return float(np.einsum("ij,ij->i", a, np.cross(b_, c_)).sum() / 6.0)
+        r = np.linalg.norm(Xn - Xn.mean(0), axis=1)
+        r0 = np.linalg.norm(memb[0] - memb[0].mean(0), axis=1)
+        total = args.warmup + args.steps + min(args.steps, 200)
+        mesh_info.update({"steps_run": total, "volume_change": round(vol(Xn) / vol(memb[0]) - 1.0, 5),
+                          "radius_spread_start": round(float(r0.std() / r0.mean()), 4),
+                          "radius_spread_end": round(float(r.std() / r.mean()), 4)})
     sim.close()
     n_steps = sum(r["steps"] for r in rows)
     out = {
@@ -964,8 +1011,9 @@ def main() -> int:
     ap.add_argument("--d3-size", type=int, default=256, help="box side of the d3q19 workload")
     ap.add_argument("--d3-collision", choices=["srt", "mrt"], default="srt",
                     help="d3q19: collision of the timed box and of the Table 1 cases")
-    ap.add_argument("--d3-surface", choices=["levelset", "mesh"], default="levelset",
-                    help="d3q19: the sphere as a level set (jumps fused in the sweep) or as a triangulation")
+    ap.add_argument("--d3-surface", choices=["levelset", "mesh", "membrane"], default="levelset",
+                    help="d3q19: the sphere as a level set (jumps fused in the sweep) or as a fixed "
+                         "triangulation, or a deformable drop under surface tension")
     ap.add_argument("--d3-table", choices=["on", "off"], default="on",
                     help="run the three-dimensional Table 1 cases after the d3q19 sweep timing")
     ap.add_argument("--cyl-sizes", default="20,40",

@@ -320,87 +320,139 @@ static_assert(sizeof(MeshRec3) == 24, "record layout");
 
 constexpr int kMeshWaves = 4;   // triangles per 256-thread block
 
-__device__ __forceinline__ long long det3i(long long ux, long long uy, long long uz, long long vx,
-                                           long long vy, long long vz, long long wx, long long wy,
-                                           long long wz)
-{
-    return ux * (vy * wz - vz * wy) - uy * (vx * wz - vz * wx) + uz * (vx * wy - vy * wx);
-}
-
 __device__ __forceinline__ int sgn64(long long v) { return (v > 0) - (v < 0); }
 
-// Perturbed side of node (px, py, pz) (snapped units) of the plane of A, B, C.
-__device__ __forceinline__ int mesh_plane_side(const long long* A, const long long* B, const long long* C,
-                                               long long px, long long py, long long pz)
-{
-    const long long ux = B[0] - A[0], uy = B[1] - A[1], uz = B[2] - A[2];
-    const long long vx = C[0] - A[0], vy = C[1] - A[1], vz = C[2] - A[2];
-    const int s = sgn64(det3i(ux, uy, uz, vx, vy, vz, px - A[0], py - A[1], pz - A[2]));
-    if (s) return s;
-    const long long nx = uy * vz - uz * vy, ny = uz * vx - ux * vz, nz = ux * vy - uy * vx;
-    return nx ? sgn64(nx) : (ny ? sgn64(ny) : sgn64(nz));
-}
-
-// Perturbed orientation of edge E0 -> E1 seen along the link from P with
-// step d; *w gets the unperturbed determinant.
-__device__ __forceinline__ int mesh_edge_side(long long px, long long py, long long pz, long long dx,
-                                              long long dy, long long dz, const long long* E0,
-                                              const long long* E1, long long* w)
-{
-    *w = det3i(dx, dy, dz, E0[0] - px, E0[1] - py, E0[2] - pz, E1[0] - px, E1[1] - py, E1[2] - pz);
-    if (*w) return sgn64(*w);
-    const long long bx = E1[0] - E0[0], by = E1[1] - E0[1], bz = E1[2] - E0[2];
-    const long long cx = dy * bz - dz * by, cy = dz * bx - dx * bz, cz = dx * by - dy * bx;
-    return cx ? sgn64(cx) : (cy ? sgn64(cy) : sgn64(cz));
-}
-
 // One wave per triangle: every link P -> P + e_i with P in the triangle's
-// node box widened by one.
+// node box widened by one.  The wave first finds the plane side of every node
+// of the box widened by two (one determinant N . (P - A) per node, N the
+// triangle's normal) and keeps it in LDS; a link then needs the edge tests
+// only when its two ends lie on different sides.
+constexpr int kSideBox = 10;      // nodes per axis: bbox side <= 4 lu -> <= 8 senders + 2
+constexpr int kBlockRecs = 256;   // records staged in LDS per block before one global reservation
+
 __global__ __launch_bounds__(256) void k_mesh_links3(const long long* __restrict__ S,
                                                      const int* __restrict__ tri,
                                                      const double* __restrict__ pv, int nt,
                                                      MeshRec3* __restrict__ out, int cap,
                                                      int* __restrict__ count, const int* err)
 {
-    const int t = blockIdx.x * kMeshWaves + threadIdx.x / 64;
+    __shared__ int8_t side[kMeshWaves][kSideBox * kSideBox * kSideBox];
+    __shared__ MeshRec3 stage[kBlockRecs];
+    __shared__ int n_stage, g_base;
+    const int wv = threadIdx.x / 64;
+    const int t = blockIdx.x * kMeshWaves + wv;
     const int lane = threadIdx.x % 64;
-    if (t >= nt) return;
-    if (err && *(volatile const int*)err) return;
-    const int ia = tri[3 * t], ib = tri[3 * t + 1], ic = tri[3 * t + 2];
-    long long A[3], B[3], C[3];
-    int lo[3], n[3];
-    for (int k = 0; k < 3; k++) {
-        A[k] = S[3 * ia + k]; B[k] = S[3 * ib + k]; C[k] = S[3 * ic + k];
-        const long long mn = min(A[k], min(B[k], C[k])), mx = max(A[k], max(B[k], C[k]));
-        lo[k] = (int)(mn >> 16) - 1;
-        n[k] = (int)((mx + 65535) >> 16) + 1 - lo[k] + 1;
+    if (threadIdx.x == 0) n_stage = 0;
+    bool active = t < nt && !(err && *(volatile const int*)err);
+    int ia = 0, ib = 0, ic = 0;
+    long long A[3] = {0, 0, 0}, B[3] = {0, 0, 0}, C[3] = {0, 0, 0};
+    int lo[3] = {0, 0, 0}, n[3] = {0, 0, 0};
+    if (active) {
+        ia = tri[3 * t]; ib = tri[3 * t + 1]; ic = tri[3 * t + 2];
+        for (int k = 0; k < 3; k++) {
+            A[k] = S[3 * ia + k]; B[k] = S[3 * ib + k]; C[k] = S[3 * ic + k];
+            const long long mn = min(A[k], min(B[k], C[k])), mx = max(A[k], max(B[k], C[k]));
+            lo[k] = (int)(mn >> 16) - 1;
+            n[k] = (int)((mx + 65535) >> 16) + 1 - lo[k] + 1;
+            if (n[k] > kSideBox - 2) active = false;     // span over 4 lu: the caller's bound broken
+        }
+        if (!active && err) atomicOr((int*)err, 1);
     }
-    const int total = n[0] * n[1] * n[2] * (kQ - 1);
-    for (int k = lane; k < total; k += 64) {
-        const int node = k / (kQ - 1), i = 1 + k % (kQ - 1);
-        const int x = lo[0] + node % n[0], y = lo[1] + (node / n[0]) % n[1], z = lo[2] + node / (n[0] * n[1]);
-        const long long px = (long long)x << 16, py = (long long)y << 16, pz = (long long)z << 16;
-        const long long dx = (long long)E3X[i] << 16, dy = (long long)E3Y[i] << 16, dz = (long long)E3Z[i] << 16;
-        const int sp = mesh_plane_side(A, B, C, px, py, pz);
-        const int sq = mesh_plane_side(A, B, C, px + dx, py + dy, pz + dz);
-        if (sp == sq) continue;
-        long long wc, wa, wb;
-        const int e1 = mesh_edge_side(px, py, pz, dx, dy, dz, A, B, &wc);
-        const int e2 = mesh_edge_side(px, py, pz, dx, dy, dz, B, C, &wa);
-        const int e3 = mesh_edge_side(px, py, pz, dx, dy, dz, C, A, &wb);
-        if (e1 != e2 || e2 != e3) continue;
-        const double la = (double)wa, lb = (double)wb, lc = (double)wc;
-        const double jp = (la * pv[ia] + lb * pv[ib] + lc * pv[ic]) / (la + lb + lc);
-        const int sigma = sp < 0 ? 1 : -1;
-        const int slot = atomicAdd(count, 1);
-        if (slot >= cap) continue;
-        MeshRec3 r;
-        r.x = (int16_t)x; r.y = (int16_t)y; r.z = (int16_t)z;
-        r.dir = (int8_t)i; r.sigma = (int8_t)sigma; r.tri = t;
-        r.delta = (float)(sigma * W3D[i] * jp * 3.0);
-        r.jp = jp;
-        out[slot] = r;
+    if (active) {
+        // sides of the nodes lo - 1 .. lo + n (every end of every link)
+        const long long ux = B[0] - A[0], uy = B[1] - A[1], uz = B[2] - A[2];
+        const long long vx = C[0] - A[0], vy = C[1] - A[1], vz = C[2] - A[2];
+        const long long Nx = uy * vz - uz * vy, Ny = uz * vx - ux * vz, Nz = ux * vy - uy * vx;
+        const int tie = Nx ? sgn64(Nx) : (Ny ? sgn64(Ny) : sgn64(Nz));
+        const int m0 = n[0] + 2, m1 = n[1] + 2, m2 = n[2] + 2;
+        for (int k = lane; k < m0 * m1 * m2; k += 64) {
+            const int ex = k % m0, ey = (k / m0) % m1, ez = k / (m0 * m1);
+            const long long px = ((long long)(lo[0] - 1 + ex) << 16) - A[0];
+            const long long py = ((long long)(lo[1] - 1 + ey) << 16) - A[1];
+            const long long pz = ((long long)(lo[2] - 1 + ez) << 16) - A[2];
+            const int sd = sgn64(Nx * px + Ny * py + Nz * pz);
+            side[wv][(ez * kSideBox + ey) * kSideBox + ex] = (int8_t)(sd ? sd : tie);
+        }
     }
+    __syncthreads();
+    if (active) {
+        // Edge tests.  With P = 2^16 p and E = B - A, the determinant
+        // det[2^16 d, A - P, B - P] is 2^16 d . (A x B - 2^16 (p x E)): A x B
+        // once per triangle, p x E once per node, then only sums of components
+        // for the directions d (entries 0, +-1).  The weights below lack the
+        // common factor 2^16, which scales [[p]]'s numerator and denominator
+        // alike (exactly).
+        const long long* V[3] = {A, B, C};
+        long long AB[3][3], E[3][3];
+#pragma unroll
+        for (int q = 0; q < 3; q++) {
+            const long long* a = V[q];
+            const long long* b = V[(q + 1) % 3];
+            AB[q][0] = a[1] * b[2] - a[2] * b[1];
+            AB[q][1] = a[2] * b[0] - a[0] * b[2];
+            AB[q][2] = a[0] * b[1] - a[1] * b[0];
+            for (int k = 0; k < 3; k++) E[q][k] = b[k] - a[k];
+        }
+        const int nn = n[0] * n[1] * n[2];
+        for (int node = lane; node < nn; node += 64) {
+            const int ox = node % n[0], oy = (node / n[0]) % n[1], oz = node / (n[0] * n[1]);
+            const int x = lo[0] + ox, y = lo[1] + oy, z = lo[2] + oz;
+            const int sp = side[wv][((oz + 1) * kSideBox + oy + 1) * kSideBox + ox + 1];
+            long long cr[3][3];        // (A - P) x (B - P) per edge, exact
+#pragma unroll
+            for (int q = 0; q < 3; q++) {
+                const long long pe0 = (long long)y * E[q][2] - (long long)z * E[q][1];
+                const long long pe1 = (long long)z * E[q][0] - (long long)x * E[q][2];
+                const long long pe2 = (long long)x * E[q][1] - (long long)y * E[q][0];
+                cr[q][0] = AB[q][0] - (pe0 << 16);
+                cr[q][1] = AB[q][1] - (pe1 << 16);
+                cr[q][2] = AB[q][2] - (pe2 << 16);
+            }
+#pragma unroll 1
+            for (int i = 1; i < kQ; i++) {
+                const int dx = E3X[i], dy = E3Y[i], dz = E3Z[i];
+                const int sq = side[wv][((oz + 1 + dz) * kSideBox + oy + 1 + dy) * kSideBox + ox + 1 + dx];
+                if (sp == sq) continue;
+                long long wq[3];
+                int es[3];
+#pragma unroll
+                for (int q = 0; q < 3; q++) {
+                    wq[q] = dx * cr[q][0] + dy * cr[q][1] + dz * cr[q][2];
+                    if (wq[q]) {
+                        es[q] = sgn64(wq[q]);
+                    } else {      // tie: the sign of d x E, first non-zero component
+                        const long long c0 = dy * E[q][2] - dz * E[q][1];
+                        const long long c1 = dz * E[q][0] - dx * E[q][2];
+                        const long long c2 = dx * E[q][1] - dy * E[q][0];
+                        es[q] = c0 ? sgn64(c0) : (c1 ? sgn64(c1) : sgn64(c2));
+                    }
+                }
+                if (es[0] != es[1] || es[1] != es[2]) continue;
+                // edge (A, B) weighs C, (B, C) weighs A, (C, A) weighs B
+                const double lc = (double)wq[0], la = (double)wq[1], lb = (double)wq[2];
+                const double jp = (la * pv[ia] + lb * pv[ib] + lc * pv[ic]) / (la + lb + lc);
+                const int sigma = sp < 0 ? 1 : -1;
+                MeshRec3 r;
+                r.x = (int16_t)x; r.y = (int16_t)y; r.z = (int16_t)z;
+                r.dir = (int8_t)i; r.sigma = (int8_t)sigma; r.tri = t;
+                r.delta = (float)(sigma * W3D[i] * jp * 3.0);
+                r.jp = jp;
+                const int sl = atomicAdd(&n_stage, 1);
+                if (sl < kBlockRecs) {
+                    stage[sl] = r;
+                } else {                 // a crowded block: straight to global memory
+                    const int slot = atomicAdd(count, 1);
+                    if (slot < cap) out[slot] = r;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const int staged = min(n_stage, kBlockRecs);
+    if (threadIdx.x == 0) g_base = staged ? atomicAdd(count, staged) : 0;
+    __syncthreads();
+    for (int k = threadIdx.x; k < staged; k += blockDim.x)
+        if (g_base + k < cap) out[g_base + k] = stage[k];
 }
 
 // After the sweep: the stored population of every cut link's sending node
@@ -510,8 +562,9 @@ __global__ void k_memb_forces3(const double* __restrict__ X, const int* __restri
         }
         const double l2c = (c[0] - bb[0]) * (c[0] - bb[0]) + (c[1] - bb[1]) * (c[1] - bb[1]) +
                            (c[2] - bb[2]) * (c[2] - bb[2]);
-        if (u[0] * u[0] + u[1] * u[1] + u[2] * u[2] > 16.0 || w[0] * w[0] + w[1] * w[1] + w[2] * w[2] > 16.0 ||
-            l2c > 16.0) {
+        // 15.9 lu^2 keeps the snapped span of every triangle within 4 lu per axis
+        if (u[0] * u[0] + u[1] * u[1] + u[2] * u[2] > 15.9 || w[0] * w[0] + w[1] * w[1] + w[2] * w[2] > 15.9 ||
+            l2c > 15.9) {
             atomicOr(err, 1);
             return;
         }
