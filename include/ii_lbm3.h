@@ -146,7 +146,8 @@ int ii_lbm3_mesh_links(ii_lbm3_handle* h, int64_t cap, int32_t* rec, double* jp,
  *      surface above, found again every step);
  *   5. X^{n+1} = X^n + U^n (Sec. 2.1.2, Eq. (11)).
  * Validation as ii_lbm3_check_mesh, plus EINVAL for a non-finite or negative
- * gamma or an IB-LBM sphere in the problem (the force field is shared).  The
+ * gamma or a sphere in the problem (radius > 0: the membrane's sweep reads the
+ * force field and applies no level-set jumps).  The
  * library copies the arrays; a fixed surface installed before is removed, as
  * a membrane is by a later ii_lbm3_set_mesh; n_vert = n_tri = 0 removes it.
  * Synchronises.

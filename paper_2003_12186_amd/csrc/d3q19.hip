@@ -1114,7 +1114,8 @@ int ii_lbm3_set_membrane(ii_lbm3_handle* h, int32_t n_vert, const double* X, int
     if (hipStreamSynchronize(h->stream) != hipSuccess) return II_LBM_EDEVICE;
     free_membrane(h);
     if (n_vert == 0 && n_tri == 0) return II_LBM_OK;             // membrane removed
-    if (h->b.ib || !isfinite(gamma) || gamma < 0.0) return II_LBM_EINVAL;
+    // the membrane's sweep reads the force field and carries no level-set jumps
+    if (h->b.sphere || !isfinite(gamma) || gamma < 0.0) return II_LBM_EINVAL;
     const int rc = ii_lbm3_check_mesh(&h->prob, n_vert, X, n_tri, tri);
     if (rc != II_LBM_OK) return rc;
     free_mesh(h);                                                 // one surface at a time

@@ -82,3 +82,13 @@ def test_membrane_stops_when_it_leaves_the_region(B):
     g = sim.fields()
     assert np.isfinite(g).all() and g[1].mean() > 0.01
     sim.close()
+
+
+def test_membrane_refuses_a_problem_with_a_sphere(B):
+    prob, _, _ = W.normal_force_sphere(16, W.FORCE_II_LBM, re=20.0)
+    X, tri = W.icosphere((10.3, 10.2, 10.1), 3.0)
+    sim = B.Sim3(prob)
+    Xc, tc, _ = B._mesh3_args(X, tri, 0.0)
+    rc = B._lib3().ii_lbm3_set_membrane(sim.h, len(Xc), Xc.ctypes.data, len(tc), tc.ctypes.data, 0.01)
+    assert rc == B.EINVAL
+    sim.close()
