@@ -68,6 +68,7 @@ def lib():
             "or3_membrane_forces": (C.c_int, [C.c_int, d, C.c_int, d, C.c_double, d, d, d, d, d]),
             "or3_interp": (None, [P, d, C.c_int, d, d]),
             "or3_run_membrane": (C.c_int, [P, d, C.c_int, d, C.c_int, d, C.c_double, C.c_int, d]),
+            "or3_run_surface": (C.c_int, [P, d, C.c_int, d, C.c_int, d, C.c_int, C.c_double, C.c_int, d, d]),
             "or3_mesh_links": (C.c_long, [P, C.c_int, d, C.c_int, d, d, d, d, C.c_long]),
             "or3_step_mesh": (C.c_int, [P, d, C.c_int, d, C.c_int, d, d]),
             "or3_run_mesh": (C.c_int, [P, d, C.c_int, d, C.c_int, d, d, C.c_int]),
@@ -216,3 +217,17 @@ def run_membrane(p: Problem3, f, X, tri, gamma: float, steps: int) -> np.ndarray
     assert lib().or3_run_membrane(C.byref(p), _ptr(f), len(X), _ptr(X), len(tri), _ptr(tri), float(gamma),
                                   int(steps), _ptr(U)) == 0
     return U
+
+
+def run_rigid_surface(p: Problem3, f, X, tri, steps: int):
+    """Steps of a fixed rigid triangulated surface with direct forcing to rest
+    (reading R32); returns the last step's vertex velocities and the force on
+    the surface F = -sum G."""
+    assert f.dtype == np.float64 and f.flags["C_CONTIGUOUS"] and f.shape == (19, p.nz, p.ny, p.nx)
+    X = np.ascontiguousarray(X, dtype=np.float64).copy()
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    U = np.zeros_like(X)
+    F = np.zeros(3)
+    assert lib().or3_run_surface(C.byref(p), _ptr(f), len(X), _ptr(X), len(tri), _ptr(tri), 1, 0.0, int(steps),
+                                 _ptr(U), _ptr(F)) == 0
+    return U, F

@@ -536,11 +536,15 @@ static void step_with_field(const or3_problem *p, double *f, const double *gext)
     free(fp);
 }
 
-/* Steps of the membrane; X (3 nv) is advanced in place.  U (3 nv, may be
- * NULL) receives the last step's vertex velocities.  Returns -1 when the
+/* Steps of a triangulated surface, law 0: the membrane under tension gamma,
+ * X (3 nv) advanced in place; law 1: a fixed rigid surface with the direct
+ * forcing of Sec. 2.1.2 (Eq. (9) with eta = 1 and U^D = 0, reading R32), the
+ * force on the fluid at a vertex G_v = (U^D - U_v) A_v, X unchanged.  U (3 nv)
+ * and F (3) (either may be NULL) receive the last step's vertex velocities and
+ * the force on the surface, F = -sum_v G_v (Sec. 2.1.3).  Returns -1 when the
  * surface degenerates or overflows the link buffer. */
-int or3_run_membrane(const or3_problem *p, double *f, int nv, double *X, int nt, const int32_t *tri,
-                     double gamma, int steps, double *Uout)
+int or3_run_surface(const or3_problem *p, double *f, int nv, double *X, int nt, const int32_t *tri, int law,
+                    double gamma, int steps, double *Uout, double *Fout)
 {
     long n = (long)p->nx * p->ny * p->nz;
     long cap = 64L * nt + 4096;
@@ -553,7 +557,24 @@ int or3_run_membrane(const or3_problem *p, double *f, int nv, double *X, int nt,
     int rc = 0;
     for (int s = 0; s < steps && rc == 0; s++) {
         or3_interp(p, f, nv, X, U);
-        if (or3_membrane_forces(nv, X, nt, tri, gamma, G, nrm, Av, jp, Gt)) { rc = -1; break; }
+        if (or3_membrane_forces(nv, X, nt, tri, law == 1 ? 0.0 : gamma, G, nrm, Av, jp, Gt)) { rc = -1; break; }
+        if (law == 1)
+            for (int v = 0; v < nv; v++) {
+                const double *n = nrm + 3 * v;
+                double g3[3];
+                for (int k = 0; k < 3; k++) g3[k] = (0.0 - U[3 * v + k]) * Av[v];
+                const double gn = g3[0] * n[0] + g3[1] * n[1] + g3[2] * n[2];
+                jp[v] = gn / Av[v];
+                for (int k = 0; k < 3; k++) {
+                    G[3 * v + k] = g3[k];
+                    Gt[3 * v + k] = g3[k] - gn * n[k];
+                }
+            }
+        if (Fout) {
+            Fout[0] = Fout[1] = Fout[2] = 0.0;
+            for (int v = 0; v < nv; v++)
+                for (int k = 0; k < 3; k++) Fout[k] -= G[3 * v + k];
+        }
         memset(g, 0, sizeof(double) * 3 * n);
         for (int v = 0; v < nv; v++) {
             const double X0 = X[3 * v], Y0 = X[3 * v + 1], Z0 = X[3 * v + 2];
@@ -576,9 +597,16 @@ int or3_run_membrane(const or3_problem *p, double *f, int nv, double *X, int nt,
             const int x = wrap(r[0] + EX3[i], p->nx), y = wrap(r[1] + EY3[i], p->ny), z = wrap(r[2] + EZ3[i], p->nz);
             f[id3(p, i, x, y, z)] += r[4] * wt3(i) * val[4 * k] / CS2;
         }
-        for (int k = 0; k < 3 * nv; k++) X[k] += U[k];
+        if (law == 0)
+            for (int k = 0; k < 3 * nv; k++) X[k] += U[k];
     }
     if (Uout && rc == 0) memcpy(Uout, U, sizeof(double) * 3 * nv);
     free(G); free(nrm); free(Av); free(jp); free(Gt); free(U); free(g); free(rec); free(val);
     return rc;
+}
+
+int or3_run_membrane(const or3_problem *p, double *f, int nv, double *X, int nt, const int32_t *tri,
+                     double gamma, int steps, double *Uout)
+{
+    return or3_run_surface(p, f, nv, X, nt, tri, 0, gamma, steps, Uout, NULL);
 }
