@@ -163,6 +163,24 @@ int ii_lbm3_set_membrane(ii_lbm3_handle* h, int32_t n_vert, const double* X, int
                          const int32_t* tri, double gamma);
 int ii_lbm3_membrane(ii_lbm3_handle* h, double* X, double* U);
 
+/*
+ * A fixed rigid closed triangulated surface held at rest by direct forcing
+ * (Sec. 2.1.2, Eq. (9) with eta = 1 and U^D = 0): each step the force on the
+ * fluid at vertex v is G_v = (U^D - U_v) A_v, entered as for the membrane
+ * above (jump of the normal part on the cut links, spread of the tangential
+ * part); the vertices do not move.  Same validation, storage and replacement
+ * rules as ii_lbm3_set_membrane; ii_lbm3_membrane reads its vertices and
+ * velocities.  Synchronises.
+ *
+ * ii_lbm3_surface_force writes the force the fluid exerted on the membrane or
+ * surface in the last step, F = -sum_v G_v (Sec. 2.1.3), into F[3] (host);
+ * ESTATE without a surface, EGEOMETRY / ECAPACITY after a stop (F still
+ * written).  Synchronises.
+ */
+int ii_lbm3_set_rigid_surface(ii_lbm3_handle* h, int32_t n_vert, const double* X, int32_t n_tri,
+                              const int32_t* tri);
+int ii_lbm3_surface_force(ii_lbm3_handle* h, double* F);
+
 int ii_lbm3_destroy(ii_lbm3_handle* h);
 
 #ifdef __cplusplus

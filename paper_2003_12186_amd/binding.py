@@ -325,7 +325,7 @@ class Problem3C(C.Structure):
 EXPORTS3 = ["ii_lbm3_init", "ii_lbm3_step", "ii_lbm3_set_distrib", "ii_lbm3_fields",
             "ii_lbm3_set_timing", "ii_lbm3_get_timing", "ii_lbm3_sweep_bytes", "ii_lbm3_check_mesh",
             "ii_lbm3_set_mesh", "ii_lbm3_mesh_links", "ii_lbm3_set_membrane", "ii_lbm3_membrane",
-            "ii_lbm3_destroy"]
+            "ii_lbm3_set_rigid_surface", "ii_lbm3_surface_force", "ii_lbm3_destroy"]
 
 
 def _lib3():
@@ -345,6 +345,8 @@ def _lib3():
             "ii_lbm3_mesh_links": [v, i64, v, v, C.POINTER(i64)],
             "ii_lbm3_set_membrane": [v, i32, v, i32, v, d],
             "ii_lbm3_membrane": [v, v, v],
+            "ii_lbm3_set_rigid_surface": [v, i32, v, i32, v],
+            "ii_lbm3_surface_force": [v, v],
             "ii_lbm3_destroy": [v],
         }
         for name, args in sigs.items():
@@ -436,6 +438,18 @@ class Sim3:
         self._memb_nv = len(X)
         check(_lib3().ii_lbm3_set_membrane(self.h, len(X), X.ctypes.data, len(tri), tri.ctypes.data,
                                            float(gamma)), "set_membrane3")
+
+    def set_rigid_surface(self, X, tri) -> None:
+        """Installs a fixed rigid triangulated surface held at rest by direct forcing."""
+        X, tri, _ = _mesh3_args(X, tri, 0.0)
+        self._memb_nv = len(X)
+        check(_lib3().ii_lbm3_set_rigid_surface(self.h, len(X), X.ctypes.data, len(tri), tri.ctypes.data),
+              "set_rigid_surface3")
+
+    def surface_force(self) -> np.ndarray:
+        F = np.zeros(3)
+        check(_lib3().ii_lbm3_surface_force(self.h, F.ctypes.data), "surface_force3")
+        return F
 
     def membrane(self):
         """The membrane's vertices and the last step's vertex velocities."""

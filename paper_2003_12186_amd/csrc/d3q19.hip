@@ -541,9 +541,13 @@ __global__ void k_memb_snap3(Box b, const double* __restrict__ X, int nv, long l
 // triangle (a, b, c), cyclically; the area-weighted normal; the vertex area
 // (a third of each triangle); then [[p]]_v = G.n / A_v and the tangential
 // part.  Edges longer than 4 lu or a degenerate triangle set the error.
+// law 1 (a fixed rigid surface, direct forcing to rest): G_v = (0 - U_v) A_v
+// instead of the tension force.  G (the force on the fluid) is kept for the
+// force on the surface.
 __global__ void k_memb_forces3(const double* __restrict__ X, const int* __restrict__ tri,
                                const int* __restrict__ vt_off, const int* __restrict__ vt, int nv,
-                               double gamma, double* __restrict__ jp, double* __restrict__ Gt, int* err)
+                               double gamma, int law, const double* __restrict__ U, double* __restrict__ jp,
+                               double* __restrict__ Gt, double* __restrict__ Gout, int* err)
 {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= nv || memb_failed(err)) return;
@@ -588,9 +592,14 @@ __global__ void k_memb_forces3(const double* __restrict__ X, const int* __restri
     }
     const double l = sqrt(nr[0] * nr[0] + nr[1] * nr[1] + nr[2] * nr[2]);
     for (int k = 0; k < 3; k++) nr[k] /= l;
+    if (law == 1)
+        for (int k = 0; k < 3; k++) G[k] = (0.0 - U[3 * v + k]) * Av;
     const double gn = G[0] * nr[0] + G[1] * nr[1] + G[2] * nr[2];
     jp[v] = gn / Av;
-    for (int k = 0; k < 3; k++) Gt[3 * v + k] = G[k] - gn * nr[k];
+    for (int k = 0; k < 3; k++) {
+        Gt[3 * v + k] = G[k] - gn * nr[k];
+        Gout[3 * v + k] = G[k];
+    }
 }
 
 // g(x) += Gt_v delta_h(x - X_v): one thread per (vertex, stencil node).
@@ -669,6 +678,8 @@ struct ii_lbm3_handle {
     double* memb_U = nullptr;         // velocities of the last step [3 nv]
     double* memb_jp = nullptr;        // [[p]] per vertex
     double* memb_Gt = nullptr;        // tangential force per vertex [3 nv]
+    double* memb_G = nullptr;         // force on the fluid per vertex [3 nv]
+    int memb_law = 0;                 // 0 tension membrane, 1 fixed rigid surface
     long long* memb_S = nullptr;      // snapped vertices
     int* memb_tri = nullptr;
     int* memb_vt_off = nullptr;       // triangles of each vertex (CSR, ascending)
@@ -702,11 +713,13 @@ static long long snap_2m16(double v) { return llrint(v * 65536.0); }
 
 static void free_membrane(ii_lbm3_handle* h)
 {
-    for (void* q : {(void*)h->memb_X, (void*)h->memb_U, (void*)h->memb_jp, (void*)h->memb_Gt, (void*)h->memb_S,
+    for (void* q : {(void*)h->memb_X, (void*)h->memb_U, (void*)h->memb_jp, (void*)h->memb_Gt, (void*)h->memb_G,
+                    (void*)h->memb_S,
                     (void*)h->memb_tri, (void*)h->memb_vt_off, (void*)h->memb_vt, (void*)h->memb_rec,
                     (void*)h->memb_count, (void*)h->memb_err})
         if (q) (void)hipFree(q);
-    h->memb_X = h->memb_U = h->memb_jp = h->memb_Gt = nullptr;
+    h->memb_X = h->memb_U = h->memb_jp = h->memb_Gt = h->memb_G = nullptr;
+    h->memb_law = 0;
     h->memb_S = nullptr;
     h->memb_tri = h->memb_vt_off = h->memb_vt = h->memb_count = h->memb_err = nullptr;
     h->memb_rec = nullptr;
@@ -726,7 +739,8 @@ static void memb_before_sweep(ii_lbm3_handle* h, const float* A)
     hipLaunchKernelGGL(k_memb_snap3, dim3((nv + 255) / 256), dim3(256), 0, h->stream, b, h->memb_X, nv,
                        h->memb_S, h->memb_err);
     hipLaunchKernelGGL(k_memb_forces3, dim3((nv + 255) / 256), dim3(256), 0, h->stream, h->memb_X, h->memb_tri,
-                       h->memb_vt_off, h->memb_vt, nv, h->memb_gamma, h->memb_jp, h->memb_Gt, h->memb_err);
+                       h->memb_vt_off, h->memb_vt, nv, h->memb_law == 1 ? 0.0 : h->memb_gamma, h->memb_law,
+                       (const double*)h->memb_U, h->memb_jp, h->memb_Gt, h->memb_G, h->memb_err);
     hipLaunchKernelGGL(k_zero_f64, dim3(1024), dim3(256), 0, h->stream, h->g, 3 * n);
     hipLaunchKernelGGL(k_memb_spread3, dim3((unsigned)(((long long)nv * 64 + 255) / 256)), dim3(256), 0, h->stream,
                        b, h->memb_X, h->memb_Gt, nv, h->g, h->memb_err);
@@ -740,8 +754,9 @@ static void memb_after_sweep(ii_lbm3_handle* h, float* B)
 {
     hipLaunchKernelGGL(k_memb_apply3, dim3((h->memb_cap + 255) / 256), dim3(256), 0, h->stream, h->b,
                        h->memb_rec, h->memb_count, h->memb_cap, B, h->memb_err);
-    hipLaunchKernelGGL(k_memb_move3, dim3((3 * h->memb_nv + 255) / 256), dim3(256), 0, h->stream, h->memb_X,
-                       h->memb_U, 3 * h->memb_nv, h->memb_err);
+    if (h->memb_law == 0)
+        hipLaunchKernelGGL(k_memb_move3, dim3((3 * h->memb_nv + 255) / 256), dim3(256), 0, h->stream, h->memb_X,
+                           h->memb_U, 3 * h->memb_nv, h->memb_err);
 }
 
 extern "C" {
@@ -1107,8 +1122,8 @@ int ii_lbm3_set_mesh(ii_lbm3_handle* h, int32_t n_vert, const double* X, int32_t
     return II_LBM_OK;
 }
 
-int ii_lbm3_set_membrane(ii_lbm3_handle* h, int32_t n_vert, const double* X, int32_t n_tri, const int32_t* tri,
-                         double gamma)
+static int set_surface(ii_lbm3_handle* h, int32_t n_vert, const double* X, int32_t n_tri, const int32_t* tri,
+                       double gamma, int law)
 {
     if (!h) return II_LBM_EINVAL;
     if (hipStreamSynchronize(h->stream) != hipSuccess) return II_LBM_EDEVICE;
@@ -1134,6 +1149,8 @@ int ii_lbm3_set_membrane(ii_lbm3_handle* h, int32_t n_vert, const double* X, int
     if (e == hipSuccess) e = hipMalloc(&h->memb_U, (size_t)3 * n_vert * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&h->memb_jp, (size_t)n_vert * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&h->memb_Gt, (size_t)3 * n_vert * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&h->memb_G, (size_t)3 * n_vert * sizeof(double));
+    if (e == hipSuccess) e = hipMemsetAsync(h->memb_G, 0, (size_t)3 * n_vert * sizeof(double), h->stream);
     if (e == hipSuccess) e = hipMalloc(&h->memb_S, (size_t)3 * n_vert * sizeof(long long));
     if (e == hipSuccess) e = hipMalloc(&h->memb_tri, (size_t)3 * n_tri * sizeof(int));
     if (e == hipSuccess) e = hipMalloc(&h->memb_vt_off, (size_t)(n_vert + 1) * sizeof(int));
@@ -1162,6 +1179,37 @@ int ii_lbm3_set_membrane(ii_lbm3_handle* h, int32_t n_vert, const double* X, int
     h->memb_nt = n_tri;
     h->memb_cap = cap;
     h->memb_gamma = gamma;
+    h->memb_law = law;
+    return II_LBM_OK;
+}
+
+int ii_lbm3_set_membrane(ii_lbm3_handle* h, int32_t n_vert, const double* X, int32_t n_tri, const int32_t* tri,
+                         double gamma)
+{
+    return set_surface(h, n_vert, X, n_tri, tri, gamma, 0);
+}
+
+int ii_lbm3_set_rigid_surface(ii_lbm3_handle* h, int32_t n_vert, const double* X, int32_t n_tri,
+                              const int32_t* tri)
+{
+    return set_surface(h, n_vert, X, n_tri, tri, 0.0, 1);
+}
+
+int ii_lbm3_surface_force(ii_lbm3_handle* h, double* F)
+{
+    if (!h || !F) return II_LBM_EINVAL;
+    if (!h->memb) return II_LBM_ESTATE;
+    std::vector<double> G((size_t)3 * h->memb_nv);
+    int err = 0;
+    hipError_t e = hipMemcpyAsync(G.data(), h->memb_G, G.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&err, h->memb_err, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return II_LBM_EDEVICE;
+    F[0] = F[1] = F[2] = 0.0;
+    for (int v = 0; v < h->memb_nv; v++)
+        for (int k = 0; k < 3; k++) F[k] -= G[3 * v + k];
+    if (err & 2) return II_LBM_ECAPACITY;
+    if (err & 1) return II_LBM_EGEOMETRY;
     return II_LBM_OK;
 }
 
