@@ -510,7 +510,11 @@ def bench_table1(args, B, W) -> int:
     sim.set_timing(False)
     avg = ms / 1e3 / max(launches, 1)
     bpl = sim.sweep_bytes()
-    if memb is not None:
+    if memb is not None and args.d3_surface == "rigid":
+        F = sim.surface_force()
+        mesh_info.update({"steps_run": args.warmup + args.steps + min(args.steps, 200),
+                          "force_over_gL3": round(float(F[0] / (1e-7 * L ** 3)), 5)})
+    elif memb is not None:
         Xn, _ = sim.membrane()
         tri = memb[1]
         def vol(X):
@@ -688,7 +692,17 @@ def bench_d3q19(args, B, W) -> int:
     coll = W.MRT if args.d3_collision == "mrt" else W.SRT
     mesh_info = None
     memb = None
-    if args.d3_surface == "membrane":
+    if args.d3_surface == "rigid":
+        # the D = L/2 sphere as a fixed rigid triangulation held by direct
+        # forcing, in a stream driven along x by a uniform body force
+        big = W.Problem3(nx=L, ny=L, nz=L, tau=0.8, collision=coll, body_force=(1e-7, 0.0, 0.0))
+        sim = B.Sim3(big)
+        Xm, tm = W.icosphere((c[0] + 0.27, c[1] - 0.31, c[2] + 0.13), L / 4.0)
+        sim.set_rigid_surface(Xm, tm)
+        memb = (Xm, tm)
+        mesh_info = {"vertices": int(len(Xm)), "triangles": int(len(tm)), "law": "rigid direct forcing",
+                     "body_force": 1e-7}
+    elif args.d3_surface == "membrane":
         # a stretched drop (semi-axes 0.25, 0.1875 and 0.21875 of the box)
         # under surface tension, its links found again every step
         big = W.Problem3(nx=L, ny=L, nz=L, tau=0.8, collision=coll)
@@ -723,7 +737,11 @@ def bench_d3q19(args, B, W) -> int:
     sim.set_timing(False)
     avg = ms / 1e3 / max(launches, 1)
     bpl = sim.sweep_bytes()
-    if memb is not None:
+    if memb is not None and args.d3_surface == "rigid":
+        F = sim.surface_force()
+        mesh_info.update({"steps_run": args.warmup + args.steps + min(args.steps, 200),
+                          "force_over_gL3": round(float(F[0] / (1e-7 * L ** 3)), 5)})
+    elif memb is not None:
         Xn, _ = sim.membrane()
         tri = memb[1]
         def vol(X):
@@ -778,7 +796,8 @@ def bench_d3q19(args, B, W) -> int:
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3 / args.steps, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 storage / fp64 collision", "data": "synthetic",
-        "config": {"workload": (f"d3q19_membrane{L}" if memb is not None else
+        "config": {"workload": (f"d3q19_{'rigid' if args.d3_surface == 'rigid' else 'membrane'}{L}"
+                                if memb is not None else
                                 f"d3q19_sphere{L}" + ("_mesh" if mesh_info else ""))
                    + ("_mrt" if coll == W.MRT else ""), "nx": L, "ny": L, "nz": L,
                    "sphere_D": L // 2, "surface": args.d3_surface, "collision": args.d3_collision,
@@ -863,7 +882,11 @@ def bench_viv(args, B, W) -> int:
     sim.set_timing(False)
     avg = ms / 1e3 / max(launches, 1)
     bpl = sim.sweep_bytes()
-    if memb is not None:
+    if memb is not None and args.d3_surface == "rigid":
+        F = sim.surface_force()
+        mesh_info.update({"steps_run": args.warmup + args.steps + min(args.steps, 200),
+                          "force_over_gL3": round(float(F[0] / (1e-7 * L ** 3)), 5)})
+    elif memb is not None:
         Xn, _ = sim.membrane()
         tri = memb[1]
         def vol(X):
@@ -1011,9 +1034,10 @@ def main() -> int:
     ap.add_argument("--d3-size", type=int, default=256, help="box side of the d3q19 workload")
     ap.add_argument("--d3-collision", choices=["srt", "mrt"], default="srt",
                     help="d3q19: collision of the timed box and of the Table 1 cases")
-    ap.add_argument("--d3-surface", choices=["levelset", "mesh", "membrane"], default="levelset",
+    ap.add_argument("--d3-surface", choices=["levelset", "mesh", "membrane", "rigid"], default="levelset",
                     help="d3q19: the sphere as a level set (jumps fused in the sweep) or as a fixed "
-                         "triangulation, or a deformable drop under surface tension")
+                         "triangulation, a deformable drop under surface tension, or a fixed rigid "
+                         "triangulated sphere held by direct forcing in a driven stream")
     ap.add_argument("--d3-table", choices=["on", "off"], default="on",
                     help="run the three-dimensional Table 1 cases after the d3q19 sweep timing")
     ap.add_argument("--cyl-sizes", default="20,40",
