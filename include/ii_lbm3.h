@@ -145,9 +145,12 @@ int ii_lbm3_mesh_links(ii_lbm3_handle* h, int64_t cap, int32_t* rec, double* jp,
  *   4. the links the surface cuts at X^n carry the jumps (as for the fixed
  *      surface above, found again every step);
  *   5. X^{n+1} = X^n + U^n (Sec. 2.1.2, Eq. (11)).
- * Validation as ii_lbm3_check_mesh, plus EINVAL for a non-finite or negative
- * gamma or a sphere in the problem (radius > 0: the membrane's sweep reads the
- * force field and applies no level-set jumps).  The
+ * With the problem's force_mode II_LBM_FORCE_IB the membrane runs as IB-LBM
+ * instead: the whole G_v is spread and no links carry jumps (Sec. 2.2.2).
+ * Validation as ii_lbm3_check_mesh's geometry rules (either force mode), plus
+ * EINVAL for a non-finite or negative gamma or a sphere in the problem
+ * (radius > 0: the membrane's sweep reads the force field and applies no
+ * level-set jumps).  The
  * library copies the arrays; a fixed surface installed before is removed, as
  * a membrane is by a later ii_lbm3_set_mesh; n_vert = n_tri = 0 removes it.
  * Synchronises.
@@ -170,7 +173,8 @@ int ii_lbm3_membrane(ii_lbm3_handle* h, double* X, double* U);
  * above (jump of the normal part on the cut links, spread of the tangential
  * part); the vertices do not move.  Same validation, storage and replacement
  * rules as ii_lbm3_set_membrane; ii_lbm3_membrane reads its vertices and
- * velocities.  Synchronises.
+ * velocities.  The problem's force mode must be II_LBM_FORCE_II (EINVAL
+ * otherwise).  Synchronises.
  *
  * ii_lbm3_surface_force writes the force the fluid exerted on the membrane or
  * surface in the last step, F = -sum_v G_v (Sec. 2.1.3), into F[3] (host);

@@ -208,14 +208,18 @@ def interp(p: Problem3, f, X) -> np.ndarray:
 
 
 def run_membrane(p: Problem3, f, X, tri, gamma: float, steps: int) -> np.ndarray:
-    """Advances f and the vertices X (in place) by steps membrane steps;
-    returns the last step's vertex velocities."""
+    """Advances f and the vertices X (in place) by steps membrane steps, II-LBM
+    or (p.force_mode IB-LBM) the whole force spread; returns the last step's
+    vertex velocities."""
     assert f.dtype == np.float64 and f.flags["C_CONTIGUOUS"] and f.shape == (19, p.nz, p.ny, p.nx)
     assert X.dtype == np.float64 and X.flags["C_CONTIGUOUS"]
     tri = np.ascontiguousarray(tri, dtype=np.int32)
     U = np.zeros_like(X)
-    assert lib().or3_run_membrane(C.byref(p), _ptr(f), len(X), _ptr(X), len(tri), _ptr(tri), float(gamma),
-                                  int(steps), _ptr(U)) == 0
+    law = 2 if p.force_mode == 1 else 0
+    q = Problem3.from_buffer_copy(p)
+    q.force_mode = 0                    # the surface's own law decides; no sphere markers
+    assert lib().or3_run_surface(C.byref(q), _ptr(f), len(X), _ptr(X), len(tri), _ptr(tri), law, float(gamma),
+                                 int(steps), _ptr(U), None) == 0
     return U
 
 

@@ -537,7 +537,8 @@ static void step_with_field(const or3_problem *p, double *f, const double *gext)
 }
 
 /* Steps of a triangulated surface, law 0: the membrane under tension gamma,
- * X (3 nv) advanced in place; law 1: a fixed rigid surface with the direct
+ * X (3 nv) advanced in place; law 2: the same membrane under IB-LBM (the whole
+ * G_v spread, no jumps; Sec. 2.2.2); law 1: a fixed rigid surface with the direct
  * forcing of Sec. 2.1.2 (Eq. (9) with eta = 1 and U^D = 0, reading R32), the
  * force on the fluid at a vertex G_v = (U^D - U_v) A_v, X unchanged.  U (3 nv)
  * and F (3) (either may be NULL) receive the last step's vertex velocities and
@@ -570,6 +571,11 @@ int or3_run_surface(const or3_problem *p, double *f, int nv, double *X, int nt, 
                     Gt[3 * v + k] = g3[k] - gn * n[k];
                 }
             }
+        if (law == 2)
+            for (int v = 0; v < nv; v++) {
+                jp[v] = 0.0;
+                for (int k = 0; k < 3; k++) Gt[3 * v + k] = G[3 * v + k];
+            }
         if (Fout) {
             Fout[0] = Fout[1] = Fout[2] = 0.0;
             for (int v = 0; v < nv; v++)
@@ -588,7 +594,7 @@ int or3_run_surface(const or3_problem *p, double *f, int nv, double *X, int nt, 
                         for (int k = 0; k < 3; k++) g[k * n + c] += Gt[3 * v + k] * wgt;
                     }
         }
-        const long nl = or3_mesh_links(p, nv, X, nt, tri, jp, rec, val, cap);
+        const long nl = law == 2 ? 0 : or3_mesh_links(p, nv, X, nt, tri, jp, rec, val, cap);
         if (nl < 0) { rc = -1; break; }
         step_with_field(p, f, g);
         for (long k = 0; k < nl; k++) {
@@ -597,7 +603,7 @@ int or3_run_surface(const or3_problem *p, double *f, int nv, double *X, int nt, 
             const int x = wrap(r[0] + EX3[i], p->nx), y = wrap(r[1] + EY3[i], p->ny), z = wrap(r[2] + EZ3[i], p->nz);
             f[id3(p, i, x, y, z)] += r[4] * wt3(i) * val[4 * k] / CS2;
         }
-        if (law == 0)
+        if (law != 1)
             for (int k = 0; k < 3 * nv; k++) X[k] += U[k];
     }
     if (Uout && rc == 0) memcpy(Uout, U, sizeof(double) * 3 * nv);

@@ -595,9 +595,10 @@ __global__ void k_memb_forces3(const double* __restrict__ X, const int* __restri
     if (law == 1)
         for (int k = 0; k < 3; k++) G[k] = (0.0 - U[3 * v + k]) * Av;
     const double gn = G[0] * nr[0] + G[1] * nr[1] + G[2] * nr[2];
-    jp[v] = gn / Av;
+    // law 2 (IB-LBM membrane): the whole force is spread and there is no jump
+    jp[v] = law == 2 ? 0.0 : gn / Av;
     for (int k = 0; k < 3; k++) {
-        Gt[3 * v + k] = G[k] - gn * nr[k];
+        Gt[3 * v + k] = law == 2 ? G[k] : G[k] - gn * nr[k];
         Gout[3 * v + k] = G[k];
     }
 }
@@ -744,6 +745,7 @@ static void memb_before_sweep(ii_lbm3_handle* h, const float* A)
     hipLaunchKernelGGL(k_zero_f64, dim3(1024), dim3(256), 0, h->stream, h->g, 3 * n);
     hipLaunchKernelGGL(k_memb_spread3, dim3((unsigned)(((long long)nv * 64 + 255) / 256)), dim3(256), 0, h->stream,
                        b, h->memb_X, h->memb_Gt, nv, h->g, h->memb_err);
+    if (h->memb_law == 2) return;                                 // IB-LBM: no jumps
     hipLaunchKernelGGL(k_zero_count3, dim3(1), dim3(1), 0, h->stream, h->memb_count);
     hipLaunchKernelGGL(k_mesh_links3, dim3((nt + kMeshWaves - 1) / kMeshWaves), dim3(256), 0, h->stream,
                        h->memb_S, h->memb_tri, h->memb_jp, nt, h->memb_rec, h->memb_cap, h->memb_count,
@@ -752,9 +754,10 @@ static void memb_before_sweep(ii_lbm3_handle* h, const float* A)
 
 static void memb_after_sweep(ii_lbm3_handle* h, float* B)
 {
-    hipLaunchKernelGGL(k_memb_apply3, dim3((h->memb_cap + 255) / 256), dim3(256), 0, h->stream, h->b,
+    if (h->memb_law != 2)
+        hipLaunchKernelGGL(k_memb_apply3, dim3((h->memb_cap + 255) / 256), dim3(256), 0, h->stream, h->b,
                        h->memb_rec, h->memb_count, h->memb_cap, B, h->memb_err);
-    if (h->memb_law == 0)
+    if (h->memb_law != 1)
         hipLaunchKernelGGL(k_memb_move3, dim3((3 * h->memb_nv + 255) / 256), dim3(256), 0, h->stream, h->memb_X,
                            h->memb_U, 3 * h->memb_nv, h->memb_err);
 }
@@ -1131,7 +1134,9 @@ static int set_surface(ii_lbm3_handle* h, int32_t n_vert, const double* X, int32
     if (n_vert == 0 && n_tri == 0) return II_LBM_OK;             // membrane removed
     // the membrane's sweep reads the force field and carries no level-set jumps
     if (h->b.sphere || !isfinite(gamma) || gamma < 0.0) return II_LBM_EINVAL;
-    const int rc = ii_lbm3_check_mesh(&h->prob, n_vert, X, n_tri, tri);
+    ii_lbm3_problem geo = h->prob;
+    geo.force_mode = II_LBM_FORCE_II;                             // the geometry rules only
+    const int rc = ii_lbm3_check_mesh(&geo, n_vert, X, n_tri, tri);
     if (rc != II_LBM_OK) return rc;
     free_mesh(h);                                                 // one surface at a time
     std::vector<int> off(n_vert + 1, 0), vt((size_t)3 * n_tri);
@@ -1186,12 +1191,15 @@ static int set_surface(ii_lbm3_handle* h, int32_t n_vert, const double* X, int32
 int ii_lbm3_set_membrane(ii_lbm3_handle* h, int32_t n_vert, const double* X, int32_t n_tri, const int32_t* tri,
                          double gamma)
 {
-    return set_surface(h, n_vert, X, n_tri, tri, gamma, 0);
+    if (!h) return II_LBM_EINVAL;
+    return set_surface(h, n_vert, X, n_tri, tri, gamma, h->prob.force_mode == II_LBM_FORCE_IB ? 2 : 0);
 }
 
 int ii_lbm3_set_rigid_surface(ii_lbm3_handle* h, int32_t n_vert, const double* X, int32_t n_tri,
                               const int32_t* tri)
 {
+    if (!h) return II_LBM_EINVAL;
+    if (h->prob.force_mode != II_LBM_FORCE_II) return II_LBM_EINVAL;
     return set_surface(h, n_vert, X, n_tri, tri, 0.0, 1);
 }
 

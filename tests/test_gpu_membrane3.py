@@ -31,12 +31,14 @@ def _rel(g, o):
     return np.sqrt(sum(((g[a] - o[a]) ** 2).sum() for a in (1, 2, 3)) / sum((o[a] ** 2).sum() for a in (1, 2, 3)))
 
 
-@pytest.mark.parametrize("coll", [W.SRT, W.MRT])
-def test_relaxing_drop_matches_oracle(B, coll):
+@pytest.mark.parametrize("coll,mode", [(W.SRT, W.FORCE_II_LBM), (W.MRT, W.FORCE_II_LBM),
+                                       (W.SRT, W.FORCE_IB_LBM)])
+def test_relaxing_drop_matches_oracle(B, coll, mode):
     n, steps, gamma = 26, 200, 0.01
-    prob = W.Problem3(nx=n, ny=n + 1, nz=n + 2, tau=1.0, collision=coll)
+    prob = W.Problem3(nx=n, ny=n + 1, nz=n + 2, tau=1.0, collision=coll, force_mode=mode)
     X0, tri = W.ellipsoid_membrane((13.1, 12.7, 13.4), (6.0, 4.5, 5.2))
-    _say(f"D3Q19 membrane drop {len(X0)} vertices {len(tri)} triangles, collision={coll}, {steps} steps")
+    _say(f"D3Q19 membrane drop {len(X0)} vertices {len(tri)} triangles, collision={coll} force_mode={mode}, "
+         f"{steps} steps")
     sim = B.Sim3(prob)
     sim.set_membrane(X0, tri, gamma)
     sim.step(steps)

@@ -124,3 +124,26 @@ def test_stretched_drop_relaxes_to_laplace_law():
     dist = np.sqrt((x - X.mean(0)[0]) ** 2 + (y - X.mean(0)[1]) ** 2 + (z - X.mean(0)[2]) ** 2)
     dp = (rho[dist < Req - 2].mean() - rho[dist > Req + 2].mean()) / 3.0
     assert dp == pytest.approx(2 * 0.01 / Req, rel=0.03)
+
+
+def test_ib_membrane_drifts_where_ii_keeps_the_volume():
+    # The same drop under IB-LBM (the whole tension force spread, no jumps,
+    # simple force term): the vertex velocities lack the force's half-step
+    # correction and the inward force makes them drift outward (reading R18,
+    # as in two dimensions), so the volume grows steadily; II-LBM keeps it.
+    n, c = 26, (13.1, 12.7, 13.4)
+    vols = {}
+    for mode in (W.FORCE_II_LBM, W.FORCE_IB_LBM):
+        p = O3.make_problem(W.Problem3(nx=n, ny=n, nz=n, tau=1.0, force_mode=mode))
+        X, tri = W.ellipsoid_membrane(c, (6.0, 4.5, 5.2))
+        V0 = _volume(X, tri)
+        f = O3.rest_state(p)
+        m0 = [q.sum() for q in O3.moments(p, f)][1:]
+        O3.run_membrane(p, f, X, tri, 0.01, 250)
+        vols[mode] = _volume(X, tri) / V0 - 1.0
+        if mode == W.FORCE_IB_LBM:
+            # the tension forces sum to zero, so the spread adds no momentum
+            m1 = [q.sum() for q in O3.moments(p, f)][1:]
+            assert np.abs(np.array(m1) - np.array(m0)).max() < 1e-12
+    assert abs(vols[W.FORCE_II_LBM]) < 0.015
+    assert vols[W.FORCE_IB_LBM] > 0.05
