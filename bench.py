@@ -705,12 +705,14 @@ def bench_d3q19(args, B, W) -> int:
     elif args.d3_surface == "membrane":
         # a stretched drop (semi-axes 0.25, 0.1875 and 0.21875 of the box)
         # under surface tension, its links found again every step
-        big = W.Problem3(nx=L, ny=L, nz=L, tau=0.8, collision=coll)
+        big = W.Problem3(nx=L, ny=L, nz=L, tau=0.8, collision=coll,
+                         force_mode=W.FORCE_IB_LBM if args.d3_membrane_ib else W.FORCE_II_LBM)
         sim = B.Sim3(big)
         Xm, tm = W.ellipsoid_membrane((c[0] + 0.27, c[1] - 0.31, c[2] + 0.13), (L / 4.0, 0.1875 * L, 0.21875 * L))
         sim.set_membrane(Xm, tm, 0.01)
         memb = (Xm, tm)
-        mesh_info = {"vertices": int(len(Xm)), "triangles": int(len(tm)), "gamma": 0.01}
+        mesh_info = {"vertices": int(len(Xm)), "triangles": int(len(tm)), "gamma": 0.01,
+                     "method": "IB-LBM" if args.d3_membrane_ib else "II-LBM"}
     elif args.d3_surface == "mesh":
         # the same sphere as a geodesic triangulation (edges <= 2.2 lu), its
         # jumps applied after each sweep by k_mesh_apply3
@@ -1032,6 +1034,8 @@ def main() -> int:
                          "reported in the design notes)")
     ap.add_argument("--re", type=float, default=100.0, help="Reynolds number of the cylinder workload")
     ap.add_argument("--d3-size", type=int, default=256, help="box side of the d3q19 workload")
+    ap.add_argument("--d3-membrane-ib", action="store_true",
+                    help="d3q19 membrane: IB-LBM (the whole force spread, no jumps) instead of II-LBM")
     ap.add_argument("--d3-collision", choices=["srt", "mrt"], default="srt",
                     help="d3q19: collision of the timed box and of the Table 1 cases")
     ap.add_argument("--d3-surface", choices=["levelset", "mesh", "membrane", "rigid"], default="levelset",
