@@ -69,6 +69,8 @@ def lib():
             "or3_interp": (None, [P, d, C.c_int, d, d]),
             "or3_run_membrane": (C.c_int, [P, d, C.c_int, d, C.c_int, d, C.c_double, C.c_int, d]),
             "or3_run_surface": (C.c_int, [P, d, C.c_int, d, C.c_int, d, C.c_int, C.c_double, C.c_int, d, d]),
+            "or3_run_free_sphere": (C.c_int, [P, d, C.c_int, d, C.c_int, d, C.c_double, C.c_double, d, C.c_int,
+                                              d, d]),
             "or3_mesh_links": (C.c_long, [P, C.c_int, d, C.c_int, d, d, d, d, C.c_long]),
             "or3_step_mesh": (C.c_int, [P, d, C.c_int, d, C.c_int, d, d]),
             "or3_run_mesh": (C.c_int, [P, d, C.c_int, d, C.c_int, d, d, C.c_int]),
@@ -235,3 +237,24 @@ def run_rigid_surface(p: Problem3, f, X, tri, steps: int):
     assert lib().or3_run_surface(C.byref(p), _ptr(f), len(X), _ptr(X), len(tri), _ptr(tri), 1, 0.0, int(steps),
                                  _ptr(U), _ptr(F)) == 0
     return U, F
+
+
+def new_body3(center, U=(0.0, 0.0, 0.0), W=(0.0, 0.0, 0.0)) -> np.ndarray:
+    """State of a free sphere: c, U, a, W, wdot, Uprev, Wprev (21 doubles);
+    the first step takes Uprev = U and Wprev = W."""
+    b = np.zeros(21)
+    b[0:3], b[3:6], b[9:12] = center, U, W
+    b[15:18], b[18:21] = U, W
+    return b
+
+
+def run_free_sphere(p: Problem3, f, X, tri, radius: float, rho_star: float, body, steps: int):
+    """Steps of a free rigid sphere (reading R33); X and body advance in
+    place; returns the last step's force and torque."""
+    assert f.dtype == np.float64 and f.flags["C_CONTIGUOUS"] and f.shape == (19, p.nz, p.ny, p.nx)
+    assert X.dtype == np.float64 and X.flags["C_CONTIGUOUS"] and body.flags["C_CONTIGUOUS"]
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    F, T = np.zeros(3), np.zeros(3)
+    assert lib().or3_run_free_sphere(C.byref(p), _ptr(f), len(X), _ptr(X), len(tri), _ptr(tri), float(radius),
+                                     float(rho_star), _ptr(body), int(steps), _ptr(F), _ptr(T)) == 0
+    return F, T

@@ -544,8 +544,19 @@ static void step_with_field(const or3_problem *p, double *f, const double *gext)
  * and F (3) (either may be NULL) receive the last step's vertex velocities and
  * the force on the surface, F = -sum_v G_v (Sec. 2.1.3).  Returns -1 when the
  * surface degenerates or overflows the link buffer. */
+static int run_surface_ud(const or3_problem *p, double *f, int nv, double *X, int nt, const int32_t *tri, int law,
+                          double gamma, int steps, double *Uout, double *Fout, const double *UD, double *Gout);
+
 int or3_run_surface(const or3_problem *p, double *f, int nv, double *X, int nt, const int32_t *tri, int law,
                     double gamma, int steps, double *Uout, double *Fout)
+{
+    return run_surface_ud(p, f, nv, X, nt, tri, law, gamma, steps, Uout, Fout, NULL, NULL);
+}
+
+/* As above; the rigid law holds the vertices at UD (3 nv, NULL: rest), and
+ * Gout (3 nv, may be NULL) receives the last step's G. */
+static int run_surface_ud(const or3_problem *p, double *f, int nv, double *X, int nt, const int32_t *tri, int law,
+                          double gamma, int steps, double *Uout, double *Fout, const double *UD, double *Gout)
 {
     long n = (long)p->nx * p->ny * p->nz;
     long cap = 64L * nt + 4096;
@@ -563,7 +574,7 @@ int or3_run_surface(const or3_problem *p, double *f, int nv, double *X, int nt, 
             for (int v = 0; v < nv; v++) {
                 const double *n = nrm + 3 * v;
                 double g3[3];
-                for (int k = 0; k < 3; k++) g3[k] = (0.0 - U[3 * v + k]) * Av[v];
+                for (int k = 0; k < 3; k++) g3[k] = ((UD ? UD[3 * v + k] : 0.0) - U[3 * v + k]) * Av[v];
                 const double gn = g3[0] * n[0] + g3[1] * n[1] + g3[2] * n[2];
                 jp[v] = gn / Av[v];
                 for (int k = 0; k < 3; k++) {
@@ -607,6 +618,7 @@ int or3_run_surface(const or3_problem *p, double *f, int nv, double *X, int nt, 
             for (int k = 0; k < 3 * nv; k++) X[k] += U[k];
     }
     if (Uout && rc == 0) memcpy(Uout, U, sizeof(double) * 3 * nv);
+    if (Gout && rc == 0) memcpy(Gout, G, sizeof(double) * 3 * nv);
     free(G); free(nrm); free(Av); free(jp); free(Gt); free(U); free(g); free(rec); free(val);
     return rc;
 }
@@ -615,4 +627,72 @@ int or3_run_membrane(const or3_problem *p, double *f, int nv, double *X, int nt,
                      double gamma, int steps, double *Uout)
 {
     return or3_run_surface(p, f, nv, X, nt, tri, 0, gamma, steps, Uout, NULL);
+}
+
+/* ------------------------------------------------------------------------
+ * A free rigid sphere (reading R33): the rigid-body update of Sec. 2.3 in
+ * three dimensions.  The vertices keep their offsets r_v from the centre (a
+ * rotation leaves a sphere's surface the same set) and move with it.  Per
+ * step:
+ *   1. the surface step with U^D_v = U + W x r_v;
+ *   2. F = -sum G_v + rho_f V_s (U^n - U^{n-1}),
+ *      T = -sum r_v x G_v + (I_s / rho*) (W^n - W^{n-1}),
+ *      with rho_f = 1, V_s = 4 pi R^3 / 3, m = rho* V_s, I_s = 2 m R^2 / 5;
+ *   3. a^{n+1} = F / m, U^{n+1} = U^n + a^{n+1},
+ *      c^{n+1} = c^n + U^n + (a^n + a^{n+1}) / 2; w^{n+1} = T / I_s,
+ *      W^{n+1} = W^n + w^{n+1}.
+ * body[21] = {c[3], U[3], a[3], W[3], wdot[3], Uprev[3], Wprev[3]}, updated in
+ * place; F and T (3 each, may be NULL) receive the last step's force and
+ * torque.  The first step takes Uprev = U, Wprev = W.
+ * ---------------------------------------------------------------------- */
+int or3_run_free_sphere(const or3_problem *p, double *f, int nv, double *X, int nt, const int32_t *tri,
+                        double radius, double rho_star, double *body, int steps, double *Fout, double *Tout)
+{
+    double *c = body, *Ub = body + 3, *a = body + 6, *W = body + 9, *wd = body + 12, *Up = body + 15,
+           *Wp = body + 18;
+    const double Vs = 4.0 * M_PI * radius * radius * radius / 3.0, m = rho_star * Vs,
+                 Is = 0.4 * m * radius * radius;
+    double *r = malloc(sizeof(double) * 3 * nv), *UD = malloc(sizeof(double) * 3 * nv),
+           *G = malloc(sizeof(double) * 3 * nv);
+    for (int v = 0; v < nv; v++)
+        for (int k = 0; k < 3; k++) r[3 * v + k] = X[3 * v + k] - c[k];
+    int rc = 0;
+    for (int s = 0; s < steps && rc == 0; s++) {
+        for (int v = 0; v < nv; v++) {
+            const double *q = r + 3 * v;
+            UD[3 * v] = Ub[0] + W[1] * q[2] - W[2] * q[1];
+            UD[3 * v + 1] = Ub[1] + W[2] * q[0] - W[0] * q[2];
+            UD[3 * v + 2] = Ub[2] + W[0] * q[1] - W[1] * q[0];
+        }
+        rc = run_surface_ud(p, f, nv, X, nt, tri, 1, 0.0, 1, NULL, NULL, UD, G);
+        if (rc) break;
+        double F[3] = {0.0, 0.0, 0.0}, T[3] = {0.0, 0.0, 0.0};
+        for (int v = 0; v < nv; v++) {
+            const double *q = r + 3 * v, *g = G + 3 * v;
+            for (int k = 0; k < 3; k++) F[k] -= g[k];
+            T[0] -= q[1] * g[2] - q[2] * g[1];
+            T[1] -= q[2] * g[0] - q[0] * g[2];
+            T[2] -= q[0] * g[1] - q[1] * g[0];
+        }
+        for (int k = 0; k < 3; k++) {
+            F[k] += Vs * (Ub[k] - Up[k]);
+            T[k] += Is / rho_star * (W[k] - Wp[k]);
+        }
+        for (int k = 0; k < 3; k++) {
+            const double an = F[k] / m, wn = T[k] / Is;
+            Up[k] = Ub[k];
+            Wp[k] = W[k];
+            const double dc = Ub[k] + 0.5 * (a[k] + an);
+            c[k] += dc;
+            for (int v = 0; v < nv; v++) X[3 * v + k] += dc;
+            Ub[k] += an;
+            a[k] = an;
+            W[k] += wn;
+            wd[k] = wn;
+        }
+        if (Fout) memcpy(Fout, F, sizeof F);
+        if (Tout) memcpy(Tout, T, sizeof T);
+    }
+    free(r); free(UD); free(G);
+    return rc;
 }
