@@ -185,6 +185,34 @@ int ii_lbm3_set_rigid_surface(ii_lbm3_handle* h, int32_t n_vert, const double* X
                               const int32_t* tri);
 int ii_lbm3_surface_force(ii_lbm3_handle* h, double* F);
 
+/*
+ * A free rigid sphere, triangulated by X / tri about center (host, 3
+ * doubles), of radius and density ratio rho_star = rho_s / rho_f, starting
+ * with velocity U0 and angular velocity W0 (host, 3 doubles each): the
+ * rigid-body dynamics of Sec. 2.3 in three dimensions.  Each step the
+ * surface is held at U^D = U + W x (X_v - c) by direct forcing (as the rigid
+ * surface above); then
+ *   F = -sum G_v + rho_f V_s (U^n - U^{n-1}),
+ *   T = -sum (X_v - c) x G_v + (I_s / rho*) (W^n - W^{n-1})
+ * (rho_f = 1, V_s = 4 pi R^3 / 3, m = rho* V_s, I_s = 2 m R^2 / 5);
+ * a^{n+1} = F / m, U^{n+1} = U^n + a^{n+1}, c^{n+1} = c^n + U^n +
+ * (a^n + a^{n+1}) / 2, W^{n+1} = W^n + T / I_s; every vertex moves with c (a
+ * rotation leaves a sphere's surface the same set).  The first step takes
+ * U^{n-1} = U0 and W^{n-1} = W0.  Same validation and replacement rules as
+ * ii_lbm3_set_membrane, plus EINVAL for a non-positive radius or rho_star,
+ * non-finite vectors, or the IB-LBM force mode.  The sphere stops like a
+ * membrane when it leaves [2, n - 3].  Synchronises.
+ *
+ * ii_lbm3_body writes out[27] = {c, U, a, W, wdot, U^{n-1}, W^{n-1}, F, T}
+ * (3 each; F and T of the last step) to host memory; ESTATE without a free
+ * sphere, EGEOMETRY / ECAPACITY after a stop (out still written).
+ * Synchronises.
+ */
+int ii_lbm3_set_free_sphere(ii_lbm3_handle* h, int32_t n_vert, const double* X, int32_t n_tri,
+                            const int32_t* tri, const double* center, double radius, double rho_star,
+                            const double* U0, const double* W0);
+int ii_lbm3_body(ii_lbm3_handle* h, double* out);
+
 int ii_lbm3_destroy(ii_lbm3_handle* h);
 
 #ifdef __cplusplus

@@ -325,7 +325,8 @@ class Problem3C(C.Structure):
 EXPORTS3 = ["ii_lbm3_init", "ii_lbm3_step", "ii_lbm3_set_distrib", "ii_lbm3_fields",
             "ii_lbm3_set_timing", "ii_lbm3_get_timing", "ii_lbm3_sweep_bytes", "ii_lbm3_check_mesh",
             "ii_lbm3_set_mesh", "ii_lbm3_mesh_links", "ii_lbm3_set_membrane", "ii_lbm3_membrane",
-            "ii_lbm3_set_rigid_surface", "ii_lbm3_surface_force", "ii_lbm3_destroy"]
+            "ii_lbm3_set_rigid_surface", "ii_lbm3_surface_force", "ii_lbm3_set_free_sphere", "ii_lbm3_body",
+            "ii_lbm3_destroy"]
 
 
 def _lib3():
@@ -347,6 +348,8 @@ def _lib3():
             "ii_lbm3_membrane": [v, v, v],
             "ii_lbm3_set_rigid_surface": [v, i32, v, i32, v],
             "ii_lbm3_surface_force": [v, v],
+            "ii_lbm3_set_free_sphere": [v, i32, v, i32, v, v, d, d, v, v],
+            "ii_lbm3_body": [v, v],
             "ii_lbm3_destroy": [v],
         }
         for name, args in sigs.items():
@@ -445,6 +448,23 @@ class Sim3:
         self._memb_nv = len(X)
         check(_lib3().ii_lbm3_set_rigid_surface(self.h, len(X), X.ctypes.data, len(tri), tri.ctypes.data),
               "set_rigid_surface3")
+
+    def set_free_sphere(self, X, tri, center, radius: float, rho_star: float, U0=(0.0, 0.0, 0.0),
+                        W0=(0.0, 0.0, 0.0)) -> None:
+        """Installs a free rigid sphere (triangulated) with the rigid-body update."""
+        X, tri, _ = _mesh3_args(X, tri, 0.0)
+        self._memb_nv = len(X)
+        c, u, w = (np.ascontiguousarray(v, dtype=np.float64) for v in (center, U0, W0))
+        self._body_args = (c, u, w)
+        check(_lib3().ii_lbm3_set_free_sphere(self.h, len(X), X.ctypes.data, len(tri), tri.ctypes.data,
+                                              c.ctypes.data, float(radius), float(rho_star), u.ctypes.data,
+                                              w.ctypes.data), "set_free_sphere3")
+
+    def body(self) -> np.ndarray:
+        """c, U, a, W, wdot, U^{n-1}, W^{n-1}, F, T (27 doubles)."""
+        out = np.zeros(27)
+        check(_lib3().ii_lbm3_body(self.h, out.ctypes.data), "body3")
+        return out
 
     def surface_force(self) -> np.ndarray:
         F = np.zeros(3)

@@ -481,6 +481,13 @@ __device__ __forceinline__ bool memb_inside(const Box& b, double x, double y, do
     return x >= 2.0 && x <= b.nx - 3.0 && y >= 2.0 && y <= b.ny - 3.0 && z >= 2.0 && z <= b.nz - 3.0;
 }
 
+// A free rigid sphere: state c, U, a, W, wdot, Uprev, Wprev; the last step's
+// force and torque; dc, the centre's step (the vertices follow it).
+struct Body3 {
+    double c[3], U[3], a[3], W[3], wd[3], Up[3], Wp[3];
+    double F[3], T[3], dc[3];
+};
+
 // U_v = sum of u(x) delta_h(x - X_v) over the 4 x 4 x 4 nodes around X_v: one
 // wave per vertex, one lane per node, u from the pulled deviations.
 __global__ __launch_bounds__(256) void k_memb_interp3(Box b, const float* __restrict__ A,
@@ -547,7 +554,8 @@ __global__ void k_memb_snap3(Box b, const double* __restrict__ X, int nv, long l
 __global__ void k_memb_forces3(const double* __restrict__ X, const int* __restrict__ tri,
                                const int* __restrict__ vt_off, const int* __restrict__ vt, int nv,
                                double gamma, int law, const double* __restrict__ U, double* __restrict__ jp,
-                               double* __restrict__ Gt, double* __restrict__ Gout, int* err)
+                               double* __restrict__ Gt, double* __restrict__ Gout, const Body3* __restrict__ body,
+                               int* err)
 {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= nv || memb_failed(err)) return;
@@ -594,6 +602,13 @@ __global__ void k_memb_forces3(const double* __restrict__ X, const int* __restri
     for (int k = 0; k < 3; k++) nr[k] /= l;
     if (law == 1)
         for (int k = 0; k < 3; k++) G[k] = (0.0 - U[3 * v + k]) * Av;
+    if (law == 3) {   // free rigid sphere: U^D = U_b + W x (X_v - c)
+        const double rx = X[3 * v] - body->c[0], ry = X[3 * v + 1] - body->c[1], rz = X[3 * v + 2] - body->c[2];
+        const double ud[3] = {body->U[0] + body->W[1] * rz - body->W[2] * ry,
+                              body->U[1] + body->W[2] * rx - body->W[0] * rz,
+                              body->U[2] + body->W[0] * ry - body->W[1] * rx};
+        for (int k = 0; k < 3; k++) G[k] = (ud[k] - U[3 * v + k]) * Av;
+    }
     const double gn = G[0] * nr[0] + G[1] * nr[1] + G[2] * nr[2];
     // law 2 (IB-LBM membrane): the whole force is spread and there is no jump
     jp[v] = law == 2 ? 0.0 : gn / Av;
@@ -619,6 +634,62 @@ __global__ void k_memb_spread3(Box b, const double* __restrict__ X, const double
     atomicAdd(&g[c], Gt[3 * v] * w);
     atomicAdd(&g[n + c], Gt[3 * v + 1] * w);
     atomicAdd(&g[2 * n + c], Gt[3 * v + 2] * w);
+}
+
+// One block: F = -sum G_v + V_s (U - Uprev), T = -sum r_v x G_v +
+// (I_s / rho*) (W - Wprev) over the vertices (a fixed reduction order), then
+// the update of Sec. 2.3: a = F / m, U += a, c += U + (a_old + a) / 2,
+// W += T / I_s.
+__global__ __launch_bounds__(1024) void k_body3(const double* __restrict__ X, const double* __restrict__ G, int nv,
+                                                double radius, double rho_star, Body3* __restrict__ b, const int* err)
+{
+    __shared__ double red[6][1024];
+    if (memb_failed(err)) return;
+    const double cx = b->c[0], cy = b->c[1], cz = b->c[2];
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+        const double rx = X[3 * v] - cx, ry = X[3 * v + 1] - cy, rz = X[3 * v + 2] - cz;
+        const double gx = G[3 * v], gy = G[3 * v + 1], gz = G[3 * v + 2];
+        acc[0] -= gx;
+        acc[1] -= gy;
+        acc[2] -= gz;
+        acc[3] -= ry * gz - rz * gy;
+        acc[4] -= rz * gx - rx * gz;
+        acc[5] -= rx * gy - ry * gx;
+    }
+    for (int k = 0; k < 6; k++) red[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o)
+            for (int k = 0; k < 6; k++) red[k][threadIdx.x] += red[k][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double Vs = 4.0 * M_PI * radius * radius * radius / 3.0, m = rho_star * Vs;
+    const double Is = 0.4 * m * radius * radius;
+    for (int k = 0; k < 3; k++) {
+        const double F = red[k][0] + Vs * (b->U[k] - b->Up[k]);
+        const double T = red[3 + k][0] + Is / rho_star * (b->W[k] - b->Wp[k]);
+        const double an = F / m, wn = T / Is;
+        b->F[k] = F;
+        b->T[k] = T;
+        b->Up[k] = b->U[k];
+        b->Wp[k] = b->W[k];
+        const double dc = b->U[k] + 0.5 * (b->a[k] + an);
+        b->dc[k] = dc;
+        b->c[k] += dc;
+        b->U[k] += an;
+        b->a[k] = an;
+        b->W[k] += wn;
+        b->wd[k] = wn;
+    }
+}
+
+__global__ void k_body_move3(double* __restrict__ X, int nv, const Body3* __restrict__ b, const int* err)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= 3 * nv || memb_failed(err)) return;
+    X[k] += b->dc[k % 3];
 }
 
 __global__ void k_zero_count3(int* count) { *count = 0; }
@@ -680,7 +751,9 @@ struct ii_lbm3_handle {
     double* memb_jp = nullptr;        // [[p]] per vertex
     double* memb_Gt = nullptr;        // tangential force per vertex [3 nv]
     double* memb_G = nullptr;         // force on the fluid per vertex [3 nv]
-    int memb_law = 0;                 // 0 tension membrane, 1 fixed rigid surface
+    int memb_law = 0;                 // 0 tension membrane, 1 fixed rigid surface, 2 IB membrane, 3 free sphere
+    Body3* body3 = nullptr;           // law 3: the sphere's state
+    double body3_radius = 0.0, body3_rho = 0.0;
     long long* memb_S = nullptr;      // snapped vertices
     int* memb_tri = nullptr;
     int* memb_vt_off = nullptr;       // triangles of each vertex (CSR, ascending)
@@ -721,6 +794,8 @@ static void free_membrane(ii_lbm3_handle* h)
         if (q) (void)hipFree(q);
     h->memb_X = h->memb_U = h->memb_jp = h->memb_Gt = h->memb_G = nullptr;
     h->memb_law = 0;
+    if (h->body3) (void)hipFree(h->body3);
+    h->body3 = nullptr;
     h->memb_S = nullptr;
     h->memb_tri = h->memb_vt_off = h->memb_vt = h->memb_count = h->memb_err = nullptr;
     h->memb_rec = nullptr;
@@ -740,8 +815,9 @@ static void memb_before_sweep(ii_lbm3_handle* h, const float* A)
     hipLaunchKernelGGL(k_memb_snap3, dim3((nv + 255) / 256), dim3(256), 0, h->stream, b, h->memb_X, nv,
                        h->memb_S, h->memb_err);
     hipLaunchKernelGGL(k_memb_forces3, dim3((nv + 255) / 256), dim3(256), 0, h->stream, h->memb_X, h->memb_tri,
-                       h->memb_vt_off, h->memb_vt, nv, h->memb_law == 1 ? 0.0 : h->memb_gamma, h->memb_law,
-                       (const double*)h->memb_U, h->memb_jp, h->memb_Gt, h->memb_G, h->memb_err);
+                       h->memb_vt_off, h->memb_vt, nv, (h->memb_law == 1 || h->memb_law == 3) ? 0.0 : h->memb_gamma,
+                       h->memb_law, (const double*)h->memb_U, h->memb_jp, h->memb_Gt, h->memb_G,
+                       (const Body3*)h->body3, h->memb_err);
     hipLaunchKernelGGL(k_zero_f64, dim3(1024), dim3(256), 0, h->stream, h->g, 3 * n);
     hipLaunchKernelGGL(k_memb_spread3, dim3((unsigned)(((long long)nv * 64 + 255) / 256)), dim3(256), 0, h->stream,
                        b, h->memb_X, h->memb_Gt, nv, h->g, h->memb_err);
@@ -757,9 +833,16 @@ static void memb_after_sweep(ii_lbm3_handle* h, float* B)
     if (h->memb_law != 2)
         hipLaunchKernelGGL(k_memb_apply3, dim3((h->memb_cap + 255) / 256), dim3(256), 0, h->stream, h->b,
                        h->memb_rec, h->memb_count, h->memb_cap, B, h->memb_err);
-    if (h->memb_law != 1)
+    if (h->memb_law == 0 || h->memb_law == 2)
         hipLaunchKernelGGL(k_memb_move3, dim3((3 * h->memb_nv + 255) / 256), dim3(256), 0, h->stream, h->memb_X,
                            h->memb_U, 3 * h->memb_nv, h->memb_err);
+    if (h->memb_law == 3) {
+        hipLaunchKernelGGL(k_body3, dim3(1), dim3(1024), 0, h->stream, (const double*)h->memb_X,
+                           (const double*)h->memb_G, h->memb_nv, h->body3_radius, h->body3_rho, h->body3,
+                           h->memb_err);
+        hipLaunchKernelGGL(k_body_move3, dim3((3 * h->memb_nv + 255) / 256), dim3(256), 0, h->stream, h->memb_X,
+                           h->memb_nv, (const Body3*)h->body3, h->memb_err);
+    }
 }
 
 extern "C" {
@@ -1201,6 +1284,54 @@ int ii_lbm3_set_rigid_surface(ii_lbm3_handle* h, int32_t n_vert, const double* X
     if (!h) return II_LBM_EINVAL;
     if (h->prob.force_mode != II_LBM_FORCE_II) return II_LBM_EINVAL;
     return set_surface(h, n_vert, X, n_tri, tri, 0.0, 1);
+}
+
+int ii_lbm3_set_free_sphere(ii_lbm3_handle* h, int32_t n_vert, const double* X, int32_t n_tri,
+                            const int32_t* tri, const double* center, double radius, double rho_star,
+                            const double* U0, const double* W0)
+{
+    if (!h || !center || !U0 || !W0) return II_LBM_EINVAL;
+    if (h->prob.force_mode != II_LBM_FORCE_II) return II_LBM_EINVAL;
+    if (!(radius > 0.0) || !isfinite(radius) || !(rho_star > 0.0) || !isfinite(rho_star)) return II_LBM_EINVAL;
+    for (int k = 0; k < 3; k++)
+        if (!isfinite(center[k]) || !isfinite(U0[k]) || !isfinite(W0[k])) return II_LBM_EINVAL;
+    int rc = set_surface(h, n_vert, X, n_tri, tri, 0.0, 3);
+    if (rc != II_LBM_OK) return rc;
+    Body3 b;
+    memset(&b, 0, sizeof b);
+    for (int k = 0; k < 3; k++) {
+        b.c[k] = center[k];
+        b.U[k] = b.Up[k] = U0[k];
+        b.W[k] = b.Wp[k] = W0[k];
+    }
+    hipError_t e = hipMalloc(&h->body3, sizeof(Body3));
+    if (e == hipSuccess) e = hipMemcpyAsync(h->body3, &b, sizeof b, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+        free_membrane(h);
+        return II_LBM_EDEVICE;
+    }
+    h->body3_radius = radius;
+    h->body3_rho = rho_star;
+    return II_LBM_OK;
+}
+
+int ii_lbm3_body(ii_lbm3_handle* h, double* out)
+{
+    if (!h || !out) return II_LBM_EINVAL;
+    if (!h->memb || h->memb_law != 3 || !h->body3) return II_LBM_ESTATE;
+    Body3 b;
+    int err = 0;
+    hipError_t e = hipMemcpyAsync(&b, h->body3, sizeof b, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&err, h->memb_err, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return II_LBM_EDEVICE;
+    const double* src[9] = {b.c, b.U, b.a, b.W, b.wd, b.Up, b.Wp, b.F, b.T};
+    for (int q = 0; q < 9; q++)
+        for (int k = 0; k < 3; k++) out[3 * q + k] = src[q][k];
+    if (err & 2) return II_LBM_ECAPACITY;
+    if (err & 1) return II_LBM_EGEOMETRY;
+    return II_LBM_OK;
 }
 
 int ii_lbm3_surface_force(ii_lbm3_handle* h, double* F)
