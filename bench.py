@@ -510,7 +510,12 @@ def bench_table1(args, B, W) -> int:
     sim.set_timing(False)
     avg = ms / 1e3 / max(launches, 1)
     bpl = sim.sweep_bytes()
-    if memb is not None and args.d3_surface == "rigid":
+    if memb is not None and args.d3_surface == "free":
+        bs = sim.body()
+        mesh_info.update({"steps_run": args.warmup + args.steps + min(args.steps, 200),
+                          "centre_shift": [round(float(bs[k] - cf[k]), 6) for k in range(3)],
+                          "velocity": [float(v) for v in bs[3:6]]})
+    elif memb is not None and args.d3_surface == "rigid":
         F = sim.surface_force()
         mesh_info.update({"steps_run": args.warmup + args.steps + min(args.steps, 200),
                           "force_over_gL3": round(float(F[0] / (1e-7 * L ** 3)), 5)})
@@ -692,7 +697,18 @@ def bench_d3q19(args, B, W) -> int:
     coll = W.MRT if args.d3_collision == "mrt" else W.SRT
     mesh_info = None
     memb = None
-    if args.d3_surface == "rigid":
+    if args.d3_surface == "free":
+        # a free rigid sphere (rho* = 2, diameter L/2) released at rest in a
+        # stream driven along x by a uniform body force
+        big = W.Problem3(nx=L, ny=L, nz=L, tau=0.8, collision=coll, body_force=(1e-7, 0.0, 0.0))
+        sim = B.Sim3(big)
+        cf = (c[0] + 0.27, c[1] - 0.31, c[2] + 0.13)
+        Xm, tm = W.icosphere(cf, L / 4.0)
+        sim.set_free_sphere(Xm, tm, cf, L / 4.0, 2.0)
+        memb = (Xm, tm)
+        mesh_info = {"vertices": int(len(Xm)), "triangles": int(len(tm)), "law": "free rigid sphere",
+                     "rho_star": 2.0, "body_force": 1e-7}
+    elif args.d3_surface == "rigid":
         # the D = L/2 sphere as a fixed rigid triangulation held by direct
         # forcing, in a stream driven along x by a uniform body force
         big = W.Problem3(nx=L, ny=L, nz=L, tau=0.8, collision=coll, body_force=(1e-7, 0.0, 0.0))
@@ -739,7 +755,12 @@ def bench_d3q19(args, B, W) -> int:
     sim.set_timing(False)
     avg = ms / 1e3 / max(launches, 1)
     bpl = sim.sweep_bytes()
-    if memb is not None and args.d3_surface == "rigid":
+    if memb is not None and args.d3_surface == "free":
+        bs = sim.body()
+        mesh_info.update({"steps_run": args.warmup + args.steps + min(args.steps, 200),
+                          "centre_shift": [round(float(bs[k] - cf[k]), 6) for k in range(3)],
+                          "velocity": [float(v) for v in bs[3:6]]})
+    elif memb is not None and args.d3_surface == "rigid":
         F = sim.surface_force()
         mesh_info.update({"steps_run": args.warmup + args.steps + min(args.steps, 200),
                           "force_over_gL3": round(float(F[0] / (1e-7 * L ** 3)), 5)})
@@ -798,7 +819,7 @@ def bench_d3q19(args, B, W) -> int:
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3 / args.steps, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 storage / fp64 collision", "data": "synthetic",
-        "config": {"workload": (f"d3q19_{'rigid' if args.d3_surface == 'rigid' else 'membrane'}{L}"
+        "config": {"workload": (f"d3q19_{args.d3_surface if args.d3_surface in ('rigid', 'free') else 'membrane'}{L}"
                                 if memb is not None else
                                 f"d3q19_sphere{L}" + ("_mesh" if mesh_info else ""))
                    + ("_mrt" if coll == W.MRT else ""), "nx": L, "ny": L, "nz": L,
@@ -884,7 +905,12 @@ def bench_viv(args, B, W) -> int:
     sim.set_timing(False)
     avg = ms / 1e3 / max(launches, 1)
     bpl = sim.sweep_bytes()
-    if memb is not None and args.d3_surface == "rigid":
+    if memb is not None and args.d3_surface == "free":
+        bs = sim.body()
+        mesh_info.update({"steps_run": args.warmup + args.steps + min(args.steps, 200),
+                          "centre_shift": [round(float(bs[k] - cf[k]), 6) for k in range(3)],
+                          "velocity": [float(v) for v in bs[3:6]]})
+    elif memb is not None and args.d3_surface == "rigid":
         F = sim.surface_force()
         mesh_info.update({"steps_run": args.warmup + args.steps + min(args.steps, 200),
                           "force_over_gL3": round(float(F[0] / (1e-7 * L ** 3)), 5)})
@@ -1038,10 +1064,11 @@ def main() -> int:
                     help="d3q19 membrane: IB-LBM (the whole force spread, no jumps) instead of II-LBM")
     ap.add_argument("--d3-collision", choices=["srt", "mrt"], default="srt",
                     help="d3q19: collision of the timed box and of the Table 1 cases")
-    ap.add_argument("--d3-surface", choices=["levelset", "mesh", "membrane", "rigid"], default="levelset",
+    ap.add_argument("--d3-surface", choices=["levelset", "mesh", "membrane", "rigid", "free"], default="levelset",
                     help="d3q19: the sphere as a level set (jumps fused in the sweep) or as a fixed "
                          "triangulation, a deformable drop under surface tension, or a fixed rigid "
-                         "triangulated sphere held by direct forcing in a driven stream")
+                         "triangulated sphere held by direct forcing in a driven stream, or a free rigid "
+                         "sphere released in it")
     ap.add_argument("--d3-table", choices=["on", "off"], default="on",
                     help="run the three-dimensional Table 1 cases after the d3q19 sweep timing")
     ap.add_argument("--cyl-sizes", default="20,40",
