@@ -692,29 +692,44 @@ __global__ void k_body_move3(double* __restrict__ X, int nv, const Body3* __rest
     X[k] += b->dc[k % 3];
 }
 
-__global__ void k_zero_count3(int* count) { *count = 0; }
-
-__global__ void k_zero_f64(double* p, long long n)
+// After the sweep has read the force field: zero the stencils the spread of
+// this step wrote (the same vertices, before they move), so the field starts
+// the next step at zero without clearing the whole box.  It ignores the
+// error word (a stop after the spread must not leave its forces behind) and
+// skips vertices outside the region, which were never spread.
+__global__ void k_memb_unspread3(Box b, const double* __restrict__ X, int nv, double* __restrict__ g)
 {
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x)
-        p[i] = 0.0;
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t >= (long long)nv * 64) return;
+    const int v = (int)(t / 64), lane = (int)(t % 64);
+    const double X0 = X[3 * v], Y0 = X[3 * v + 1], Z0 = X[3 * v + 2];
+    if (!memb_inside(b, X0, Y0, Z0)) return;
+    const int x = (int)floor(X0) - 1 + (lane & 3), y = (int)floor(Y0) - 1 + ((lane >> 2) & 3),
+              z = (int)floor(Z0) - 1 + (lane >> 4);
+    const long long n = (long long)b.nx * b.ny * b.nz;
+    const long long c = ((long long)z * b.ny + y) * b.nx + x;
+    g[c] = 0.0;
+    g[n + c] = 0.0;
+    g[2 * n + c] = 0.0;
 }
 
-// The step's jumps, straight from the records (several may share a target).
+__global__ void k_zero_count3(int* count) { *count = 0; }
+
+// The step's jumps, straight from the records (several may share a target);
+// a grid-stride loop over the device-side count.
 __global__ void k_memb_apply3(Box b, const MeshRec3* __restrict__ r, const int* __restrict__ count, int cap,
                               float* __restrict__ B, int* err)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (memb_failed(err)) return;
     const int n = *count;
     if (n > cap) {
-        if (k == 0) atomicOr(err, 2);
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(err, 2);
         return;
     }
-    if (k >= n) return;
-    const MeshRec3 q = r[k];
-    atomicAdd(&B[q.dir * b.plane + ((long long)q.z * b.ny + q.y) * b.pitch + q.x], q.delta);
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+        const MeshRec3 q = r[k];
+        atomicAdd(&B[q.dir * b.plane + ((long long)q.z * b.ny + q.y) * b.pitch + q.x], q.delta);
+    }
 }
 
 __global__ void k_memb_move3(double* __restrict__ X, const double* __restrict__ U, int n3, const int* err)
@@ -809,7 +824,6 @@ static void memb_before_sweep(ii_lbm3_handle* h, const float* A)
 {
     const Box& b = h->b;
     const int nv = h->memb_nv, nt = h->memb_nt;
-    const long long n = (long long)b.nx * b.ny * b.nz;
     hipLaunchKernelGGL(k_memb_interp3, dim3((nv + 3) / 4), dim3(256), 0, h->stream, b, A, h->memb_X, nv,
                        h->memb_U, h->memb_err);
     hipLaunchKernelGGL(k_memb_snap3, dim3((nv + 255) / 256), dim3(256), 0, h->stream, b, h->memb_X, nv,
@@ -818,7 +832,6 @@ static void memb_before_sweep(ii_lbm3_handle* h, const float* A)
                        h->memb_vt_off, h->memb_vt, nv, (h->memb_law == 1 || h->memb_law == 3) ? 0.0 : h->memb_gamma,
                        h->memb_law, (const double*)h->memb_U, h->memb_jp, h->memb_Gt, h->memb_G,
                        (const Body3*)h->body3, h->memb_err);
-    hipLaunchKernelGGL(k_zero_f64, dim3(1024), dim3(256), 0, h->stream, h->g, 3 * n);
     hipLaunchKernelGGL(k_memb_spread3, dim3((unsigned)(((long long)nv * 64 + 255) / 256)), dim3(256), 0, h->stream,
                        b, h->memb_X, h->memb_Gt, nv, h->g, h->memb_err);
     if (h->memb_law == 2) return;                                 // IB-LBM: no jumps
@@ -831,8 +844,10 @@ static void memb_before_sweep(ii_lbm3_handle* h, const float* A)
 static void memb_after_sweep(ii_lbm3_handle* h, float* B)
 {
     if (h->memb_law != 2)
-        hipLaunchKernelGGL(k_memb_apply3, dim3((h->memb_cap + 255) / 256), dim3(256), 0, h->stream, h->b,
-                       h->memb_rec, h->memb_count, h->memb_cap, B, h->memb_err);
+        hipLaunchKernelGGL(k_memb_apply3, dim3(std::min((h->memb_cap + 255) / 256, 2048)), dim3(256), 0,
+                           h->stream, h->b, h->memb_rec, h->memb_count, h->memb_cap, B, h->memb_err);
+    hipLaunchKernelGGL(k_memb_unspread3, dim3((unsigned)(((long long)h->memb_nv * 64 + 255) / 256)), dim3(256), 0,
+                       h->stream, h->b, (const double*)h->memb_X, h->memb_nv, h->g);
     if (h->memb_law == 0 || h->memb_law == 2)
         hipLaunchKernelGGL(k_memb_move3, dim3((3 * h->memb_nv + 255) / 256), dim3(256), 0, h->stream, h->memb_X,
                            h->memb_U, 3 * h->memb_nv, h->memb_err);
@@ -1233,6 +1248,8 @@ static int set_surface(ii_lbm3_handle* h, int32_t n_vert, const double* X, int32
     const int cap = 64 * n_tri + 4096;
     hipError_t e = hipSuccess;
     if (!h->g) e = hipMalloc(&h->g, (size_t)3 * n * sizeof(double));
+    // the force field starts at zero; each step then clears what it spread
+    if (e == hipSuccess) e = hipMemsetAsync(h->g, 0, (size_t)3 * n * sizeof(double), h->stream);
     if (e == hipSuccess) e = hipMalloc(&h->memb_X, (size_t)3 * n_vert * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&h->memb_U, (size_t)3 * n_vert * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&h->memb_jp, (size_t)n_vert * sizeof(double));
