@@ -1,12 +1,20 @@
-// D3Q19 form of the II-LBM on one MI355X: a periodic box, SRT with the He-Luo
-// equilibrium and the simple force term, and a fixed sphere with a uniform
-// normal force entered as jumps on the links its level set cuts (II-LBM) or as
-// a force field spread from surface markers (IB-LBM).
+// D3Q19 form of the II-LBM on one MI355X: a periodic box, SRT or MRT with the
+// He-Luo equilibrium and the simple force term, and one immersed surface:
+//   - a fixed sphere with a uniform normal force, entered as jumps on the links
+//     its level set cuts (II-LBM) or as a force field spread from surface
+//     markers (IB-LBM);
+//   - a fixed closed triangulation with vertex jumps (exact link search once,
+//     jumps applied after every sweep);
+//   - a deformable triangulated membrane under surface tension (II-LBM or
+//     IB-LBM), a fixed rigid triangulated surface held by direct forcing, or a
+//     free rigid sphere; these find their links again every step.
 //
 // Storage: FP32 deviations d_i = f_i - w_i, planes [19][nz][ny][pitch].  The
 // sweep pulls d_i from x - e_i, collides, adds the force term and (II-LBM) the
 // jumps of the links this node sends, and stores once at x, so the next pull
-// reads f^{n+1}_i(x + e_i) with its jump already in place.
+// reads f^{n+1}_i(x + e_i) with its jump already in place.  The triangulated
+// surfaces add their jumps to the stored populations of the sending nodes
+// after the sweep, to the same effect.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
