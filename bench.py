@@ -847,6 +847,55 @@ def bench_d3q19(args, B, W) -> int:
     return 0
 
 
+def bench_boundaries(args, B, W) -> int:
+    """The outer boundaries (extrapolation walls, parabolic inlet, outlet;
+    Sec. 4.3's channel) fused into the sweep's edge nodes, on an 8192 x 4096
+    box whose FP32 lattice pair (2.4 GB) is far larger than the caches: the
+    sweep's time by HIP events with those boundaries against the same box
+    periodic, for SRT and MRT, with no interface."""
+    import torch
+    rows = []
+    for coll, cname in ((W.SRT, "srt"), (W.MRT, "mrt")):
+        for bc, bname in (((W.BC_PERIODIC,) * 4, "periodic"),
+                          ((W.BC_INLET, W.BC_OUTLET, W.BC_WALL, W.BC_WALL), "channel")):
+            p = W.Problem(nx=8192, ny=4096, tau=0.8, collision=coll, bc=bc, u_max=0.05)
+            sim = B.Sim([p], [None], device="cuda:0")
+            sim.step(args.warmup)
+            sim.sync()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.step(args.steps)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            sim.set_timing(True)
+            sim.step(min(args.steps, 100))
+            sim.sync()
+            ms, n = sim.get_timing()
+            sim.set_timing(False)
+            avg = ms / 1e3 / max(n, 1)
+            bpl = sim.sweep_bytes()
+            rows.append({"collision": cname, "boundaries": bname, "sweep_us": round(avg * 1e6, 2),
+                         "GB_s": round(bpl / avg / 1e9, 1), "frac": round(bpl / avg / 1e9 / HBM_PEAK_GBS, 4),
+                         "MLUPS": round(p.nx * p.ny * args.steps / dt / 1e6, 1)})
+            print(f"[boundaries] {cname} {bname}: sweep {rows[-1]['sweep_us']} us ({rows[-1]['frac']:.3f}), "
+                  f"{rows[-1]['MLUPS']} MLUPS", file=sys.stderr, flush=True)
+            del sim
+            torch.cuda.empty_cache()
+    ch = [r for r in rows if r["boundaries"] == "channel" and r["collision"] == "mrt"][0]
+    out = {
+        "metric": "MLUPS & %HBM peak; learned 2x-coarse vs fine II-LBM time at <=1e-2 L2 err",
+        "value": ch["MLUPS"], "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(8192 * 4096 / ch["MLUPS"] / 1e3, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 storage / fp64 collision", "data": "synthetic",
+        "config": {"workload": "channel8192x4096_boundaries", "nx": 8192, "ny": 4096, "rows": rows},
+        "roofline": {"bound": "hbm", "kernel": "k_sweep (channel, MRT)", "achieved": ch["GB_s"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ch["frac"], "traffic": None,
+                     "avg_launch_us": ch["sweep_us"]},
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 # Sec. 4.5: maximum transverse amplitude / D of the freely vibrating cylinder
 # (rho* = 8/pi, zeta = 0) for U_red = 3 .. 8.
 PAPER_VIV = {3.0: 0.075, 4.0: 0.551, 5.0: 0.520, 6.0: 0.459, 7.0: 0.370, 8.0: 0.084}
@@ -1052,7 +1101,7 @@ def main() -> int:
                          "(1e-3 bar)")
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--workload", choices=["membrane", "batch512", "learned", "cylinder", "area",
-                                           "table1", "viv", "cyltables", "d3q19"],
+                                           "table1", "viv", "cyltables", "d3q19", "boundaries"],
                     default="membrane",
                     help="membrane: one L x L membrane (the bench line); batch512: 512 uneven "
                          "membrane instances advanced together; learned: 200 coarse membranes "
@@ -1130,6 +1179,8 @@ def main() -> int:
         return bench_cylinder_tables(args, B, W)
     if args.workload == "d3q19":
         return bench_d3q19(args, B, W)
+    if args.workload == "boundaries":
+        return bench_boundaries(args, B, W)
     storage = W.STORE_FP16 if args.storage == "fp16" else W.STORE_FP32
     w = W.membrane_c3(L=args.size, storage=storage)
     p = w.problem
