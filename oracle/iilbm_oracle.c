@@ -33,7 +33,13 @@
  *  R10 the flexible interface is the closed polygon through the markers, snapped
  *      to a 2^-16 grid, tested with exact integer orientations and the node
  *      perturbation tie rule; [[p]] is linear along each chord;
- *  R11 marker velocity from u = sum e_i f_i of the pre-collision field;
+ *  R11 marker velocity from u = sum e_i f_i of the pre-collision field
+ *      (II-LBM);
+ *  R18 the IB-LBM comparison modes (the whole force spread, no jumps) move a
+ *      membrane with the velocity its distributions carry after the step's
+ *      collision and force term, sum e_i f_i + g (divided by rho under Guo's
+ *      term); Table 2 fixes this: it is the reading under which both IB-LBM
+ *      columns lose area at the printed rates;
  *  R12 non-equilibrium extrapolation on non-periodic sides, corners as walls
  *      (a uniform inflow side takes u_b = (u_max, 0));
  *  R27 (geometry 1) the membrane is the periodic cubic spline through the
@@ -44,8 +50,9 @@
  *      collision uses the compressible equilibrium and the velocity
  *      u = (sum e_i f_i + g/2) / rho the paper gives with it, g the whole
  *      Eulerian force (g_par plus the body force for II-LBM, Sec. 3.2); the
- *      markers move with that u (R11 holds for the simple force term); the
- *      direct-forcing u* carries the body force only.
+ *      II-LBM markers move with that u (R11 holds for the simple force term,
+ *      R18 for the IB-LBM modes); the direct-forcing u* carries the body force
+ *      only.
  */
 #define _GNU_SOURCE
 #include <math.h>
@@ -868,8 +875,10 @@ typedef struct {
  * f* = collide(f) + w_i e_i.g_par / c_s^2, g_par the spread tangential force;
  * then X^{n+1} = X^n + U^n (Sec. 2.2.2, Eq. (20)).
  * Under the IB-LBM force modes the full G is spread and no jump is applied
- * (Sec. 2.2.2, Eq. (16)-(17)), the comparison method of the paper; the Guo
- * modes collide with Guo's term of the spread force (reading R24). */
+ * (Sec. 2.2.2, Eq. (16)-(17)), the comparison method of the paper, and a
+ * membrane then moves with the velocity its distributions carry after this
+ * step's force (reading R18); the Guo modes collide with Guo's term of the
+ * spread force (reading R24). */
 int or_step(const or_problem *p, double *f, double *X, or_step_out *out)
 {
     int nx = p->nx, ny = p->ny, N = p->n_markers;
@@ -910,12 +919,19 @@ int or_step(const or_problem *p, double *f, double *X, or_step_out *out)
         or_marker_forces(p, X, U, G, nrm, J, jp, Gt);
         /* 3. spread the tangential force (the full force under IB-LBM) */
         or_spread(p, X, has_jumps(p) ? Gt : G, gx, gy);
-        /* 3b. Guo's term: a membrane moves with u = (j + g/2) / rho of the
-         *     whole force (a membrane's force depends on X alone) */
-        if (uses_guo(p) && p->interface == OR_IF_MEMBRANE) {
+        /* 3b. the velocity a membrane moves with, now that the whole force g
+         *     of this step is known (a membrane's force depends on X alone):
+         *     - II-LBM with Guo's term: u = (j + g/2) / rho (Sec. 2.2.2);
+         *     - the IB-LBM comparison modes: the velocity of the distributions
+         *       after this step's collision and force term, j + g (per unit
+         *       density under Guo's term), reading R18 */
+        if (p->interface == OR_IF_MEMBRANE && (uses_guo(p) || !has_jumps(p))) {
+            double c = has_jumps(p) ? 0.5 : 1.0;
             for (long n = 0; n < nn; n++) {
-                ux[n] = (jx[n] + 0.5 * gx[n]) / rho[n];
-                uy[n] = (jy[n] + 0.5 * gy[n]) / rho[n];
+                double j0 = uses_guo(p) ? jx[n] : ux[n], j1 = uses_guo(p) ? jy[n] : uy[n];
+                double r = uses_guo(p) ? rho[n] : 1.0;
+                ux[n] = (j0 + c * gx[n]) / r;
+                uy[n] = (j1 + c * gy[n]) / r;
             }
             or_interp(p, ux, uy, X, U);
         }
@@ -1177,7 +1193,9 @@ int or_sizeof_link(void) { return (int)sizeof(or_link); }
 #ifdef _OPENMP
 #include <omp.h>
 int or_num_threads(void) { return omp_get_max_threads(); }
+void or_set_num_threads(int n) { if (n > 0) omp_set_num_threads(n); }
 #else
 int or_num_threads(void) { return 1; }
+void or_set_num_threads(int n) { (void)n; }
 #endif
 int or_sizeof_problem(void) { return (int)sizeof(or_problem); }

@@ -238,20 +238,27 @@ def _e2_area_history(L, mode, spans):
 
 def test_area_conservation_ii_lbm_against_ib_lbm():
     # The paper's comparison (Sec. 4.2, Table 2): after the first oscillation
-    # the II-LBM membrane keeps its area, while the IB-LBM membrane with Guo's
-    # term steadily loses area through its regularised interface.  Under the
-    # simple force term the markers move with sum e f, which lacks the
-    # half-force shift, so that membrane drifts outward instead: a steady
-    # change of area in the other direction, as large.
-    # At L = 48 (coarser than the paper's 80) the rates per L/U over
-    # t = 2..5 L/U are about -4e-6 and -5e-6 (II-LBM, both terms), -1e-4
-    # (IB-LBM, Guo) and +3e-2 (IB-LBM, simple term).
+    # the II-LBM membrane keeps its area, while both IB-LBM membranes steadily
+    # lose area.  In the comparison modes the markers move with the velocity
+    # their distributions carry after the step's force, j + g (reading R18),
+    # which runs ahead of the fluid by half a force step: the regularised force
+    # points inward, so the markers slip inward and the area shrinks.
+    # Table 2 gives the loss per unit time in units of L U (the area per step
+    # over L U, so the loss per L/U over L^2): 2.42e-3 (simple term) and
+    # 3.70e-3 (Guo's term) at L = 80, falling as the grid is refined.  At
+    # L = 48, coarser than the paper's coarsest grid, the rates over
+    # t = 2..5 L/U must therefore be losses at least the paper's L = 80 rate
+    # and within 2.5 times it (measured 4.73e-3 for both terms); II-LBM, with
+    # either force term, stays below 1e-5 of the area per L/U (measured
+    # -4e-6 and -5e-6).
     L = 48
-    rate = {}
+    rate, rate_l2 = {}, {}
     for mode in (W.FORCE_II_LBM, W.FORCE_IB_LBM, W.FORCE_IB_LBM_GUO, W.FORCE_II_LBM_GUO):
         A = _e2_area_history(L, mode, (2.0, 3.0))
         rate[mode] = (A[2] - A[1]) / A[0] / 3.0          # per L/U after t = 2 L/U
+        rate_l2[mode] = -(A[2] - A[1]) / L ** 2 / 3.0     # loss per L/U over L^2
     ii = max(abs(rate[W.FORCE_II_LBM]), abs(rate[W.FORCE_II_LBM_GUO]))
     assert ii < 1e-5
-    assert rate[W.FORCE_IB_LBM_GUO] < -10 * ii
-    assert rate[W.FORCE_IB_LBM] > 1000 * ii
+    for mode, paper in ((W.FORCE_IB_LBM, 2.42e-3), (W.FORCE_IB_LBM_GUO, 3.70e-3)):
+        assert rate[mode] < -100 * ii
+        assert paper <= rate_l2[mode] <= 2.5 * paper, (mode, rate_l2[mode])
