@@ -65,9 +65,7 @@ def measured_traffic(storage: str):
     return ent.get("bytes_per_launch")
 
 
-def cpu_baseline(w, steps: int):
-    import numpy as np  # noqa: F401
-    import oracle as O
+def _oracle_leg(O, w, steps: int):
     p = O.make_problem(w.problem)
     f = O.rest_state(p)
     X = w.X0.copy()
@@ -75,10 +73,27 @@ def cpu_baseline(w, steps: int):
     t0 = time.perf_counter()
     O.run(p, f, X, steps)
     dt = time.perf_counter() - t0
-    mlups = p.nx * p.ny * steps / dt / 1e6
-    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"{steps} FP64 oracle steps of the same {p.nx}x{p.ny} workload after 1 untimed step "
-                      f"({dt:.1f} s)"}
+    return p.nx * p.ny * steps / dt / 1e6, dt
+
+
+def cpu_baseline(w, steps: int, single_steps: int = None):
+    """The FP64 oracle with its default thread count (OpenMP over lattice rows,
+    OMP_NUM_THREADS when set), then on one thread over a sample 1/16 as long."""
+    import oracle as O
+    cores = O.num_threads()
+    mlups, dt = _oracle_leg(O, w, steps)
+    out = {"value": round(mlups, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+           "sample": f"{steps} FP64 oracle steps of the same {w.problem.nx}x{w.problem.ny} workload "
+                     f"after 1 untimed step ({dt:.1f} s)"}
+    n1 = single_steps if single_steps is not None else max(1, steps // 16)
+    O.set_num_threads(1)
+    try:
+        m1, dt1 = _oracle_leg(O, w, n1)
+    finally:
+        O.set_num_threads(cores)
+    out["single_thread"] = {"value": round(m1, 3), "unit": "MLUPS", "cores": 1,
+                            "sample": f"{n1} FP64 oracle steps, one thread ({dt1:.1f} s)"}
+    return out
 
 
 def cnn_flops(flags, listed):

@@ -60,12 +60,16 @@ enum { II_LBM_IF_NONE = 0, II_LBM_IF_MEMBRANE = 1, II_LBM_IF_RIGID = 2, II_LBM_I
  *  II      the paper's method: jumps on cut links for the normal part, the
  *          tangential part g_par in the simple force term (Sec. 3.2);
  *  IB      the comparison IB-LBM: the whole force G spread into the simple
- *          force term, no jumps (Sec. 2.2.2, Eqs. (16)-(17));
+ *          force term, no jumps (Sec. 2.2.2, Eqs. (16)-(17)); a membrane's
+ *          markers move with the velocity of the distributions after the
+ *          step's force, sum e_i f_i + g;
  *  IB_GUO  IB-LBM with Guo's force term (Sec. 2.2.2, the SRT and MRT forms):
  *          compressible equilibrium w_i rho [1 + e.u/c_s^2 + (e.u)^2/(2 c_s^4)
- *          - u.u/(2 c_s^2)] with rho u = sum e_i f_i + g/2, and the markers
- *          move with that u;
- *  II_GUO  II-LBM with Guo's term of g_par (Sec. 3.2).
+ *          - u.u/(2 c_s^2)] with rho u = sum e_i f_i + g/2; a membrane's
+ *          markers move with (sum e_i f_i + g) / rho, the velocity after the
+ *          step's force, as under IB;
+ *  II_GUO  II-LBM with Guo's term of g_par (Sec. 3.2); the markers move with
+ *          rho u = sum e_i f_i + g/2.
  * The body force joins g in every mode; direct forcing's u* carries the body
  * force only.  Field readouts report u = sum e_i f_i in every mode. */
 enum { II_LBM_FORCE_II = 0, II_LBM_FORCE_IB = 1, II_LBM_FORCE_IB_GUO = 2, II_LBM_FORCE_II_GUO = 3 };
@@ -176,6 +180,14 @@ typedef struct ii_lbm_diag_t {
     double force[2];       /* force on the body F = -sum_k G_k dX (Sec. 2.3 Eq. (25)) */
     int32_t n_cut_links;   /* directed (link, chord) crossings, as ii_lbm_cutlinks counts them */
     int32_t error_bits;    /* device error flags (0 when healthy) */
+    /* Mean pressure p = rho c_s^2 over the nodes farther than 3 lu from the
+     * marker polygon, inside (p_in) and outside (p_out) it, with the node
+     * counts: p_in - p_out is the pressure jump across the interface
+     * (Sec. 3.1), Laplace's T / R at equilibrium for a tensioned circle.
+     * NaN (and count 0) where a side has no such node or there are no
+     * markers.  Sums in FP64, in a fixed order. */
+    double p_in, p_out;
+    int64_t n_in, n_out;
 } ii_lbm_diag_t;
 
 typedef struct ii_lbm_handle ii_lbm_handle;
@@ -268,7 +280,11 @@ int ii_lbm_load_state(ii_lbm_handle* h, int32_t inst, const void* host_buf, size
  * are in no particular order. */
 int ii_lbm_cutlinks(ii_lbm_handle* h, int32_t inst, ii_lbm_link* out, int32_t cap, int32_t* count);
 
-/* Synchronises and fills FP64 diagnostics of one instance. */
+/* Synchronises and fills FP64 diagnostics of one instance (the fields of
+ * ii_lbm_diag_t): mass, momentum, area, force, cut-link count and the
+ * pressure on either side of the interface.  The sums over the lattice are
+ * taken in FP64 per block and added on the host in block order, so repeated
+ * calls on one state return identical values. */
 int ii_lbm_diag(ii_lbm_handle* h, int32_t inst, ii_lbm_diag_t* out);
 
 /* Kernel timing of the dense collide-and-stream sweep: while enabled, every
@@ -282,9 +298,12 @@ int ii_lbm_get_timing(ii_lbm_handle* h, double* sweep_ms, int64_t* launches);
  * move: nine loads and nine stores of the stored deviation per node. */
 int ii_lbm_sweep_bytes(ii_lbm_handle* h, int32_t inst, double* bytes);
 
-/* Replays the step as a HIP graph (two steps per graph launch, captured on
- * first use and after re-tuning) when enable != 0.  Timing mode uses direct
- * launches.  Results are identical either way. */
+/* Replays the step as a HIP graph (two steps per graph launch) when
+ * enable != 0.  Enabling captures and instantiates the two graphs (one per
+ * starting lattice buffer) at once, without running them; a later change of
+ * schedule, learned correction or tuning drops them and the next step
+ * rebuilds both, so no replay ever captures.  Timing mode uses direct
+ * launches.  Results are identical either way.  ESTATE on a failed handle. */
 int ii_lbm_set_graph(ii_lbm_handle* h, int32_t enable);
 
 /* Schedule of a membrane step (rigid bodies always run in order).  The sweep

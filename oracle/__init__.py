@@ -107,6 +107,7 @@ def lib():
             "or_sizeof_link": (C.c_int, []),
             "or_sizeof_problem": (C.c_int, []),
             "or_num_threads": (C.c_int, []),
+            "or_set_num_threads": (None, [C.c_int]),
             "or_step_body": (C.c_int, [P, C.POINTER(BodyParams), C.POINTER(Body), d, d]),
             "or_spline": (None, [P, d, d]),
             "or_cutlinks_spline": (C.c_int, [P, d, d, d, C.c_int]),
@@ -347,6 +348,11 @@ def run_body(p: Problem, bp: BodyParams, b: Body, f: np.ndarray, X: np.ndarray, 
 
 def num_threads() -> int:
     return int(lib().or_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the OpenMP loops from now on (the default: every core)."""
+    lib().or_set_num_threads(int(n))
 
 
 def polygon_area(X) -> float:

@@ -50,7 +50,8 @@ LINK_DTYPE = np.dtype([("x", "<i4"), ("y", "<i4"), ("dir", "<i4"), ("sigma", "<i
 class Diag(C.Structure):
     _fields_ = [("step", C.c_int64), ("mass", C.c_double), ("momentum", C.c_double * 2),
                 ("area", C.c_double), ("force", C.c_double * 2), ("n_cut_links", C.c_int32),
-                ("error_bits", C.c_int32)]
+                ("error_bits", C.c_int32), ("p_in", C.c_double), ("p_out", C.c_double),
+                ("n_in", C.c_int64), ("n_out", C.c_int64)]
 
 
 EXPORTS = [
@@ -255,7 +256,8 @@ class Sim:
         check(load().ii_lbm_diag(self.h, inst, C.byref(d)), "diag")
         return {"step": d.step, "mass": d.mass, "momentum": (d.momentum[0], d.momentum[1]),
                 "area": d.area, "force": (d.force[0], d.force[1]), "n_cut_links": d.n_cut_links,
-                "error_bits": d.error_bits}
+                "error_bits": d.error_bits, "p_in": d.p_in, "p_out": d.p_out,
+                "n_in": d.n_in, "n_out": d.n_out}
 
     # -- timing --------------------------------------------------------------
     def set_timing(self, enable: bool) -> None:

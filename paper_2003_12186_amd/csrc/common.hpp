@@ -540,6 +540,10 @@ hipError_t launch_fields(const InstDev& I, const void* A, uint32_t what, void* o
 hipError_t launch_set_distrib(const InstDev& I, const double* f, void* A, hipStream_t s);
 hipError_t launch_diag(const InstDev& I, const void* A, double* partials, int nblocks,
                        hipStream_t s);
+// Per-block (sum p, count) inside and outside the marker polygon over the
+// nodes farther than `margin` lu from it (X: the instance's markers).
+hipError_t launch_pjump(const InstDev& I, const void* A, const double2* X, double margin,
+                        double* part, int nblocks, hipStream_t s);
 // Marker pass modes (bit 1: interpolation and marker update, bit 2: force,
 // geometry, delta weights and tile binning).
 enum MarkerMode { kModeInterp = 1, kModeGeom = 2, kModeFull = 3 };

@@ -72,6 +72,9 @@ __device__ __forceinline__ void markers_body(const InstDev& I, const DevPtrs& P,
         // u = (sum e f + g/2) / rho (Sec. 2.2.2): g is the body force plus,
         // for a membrane, the force this step's tile pass spread (the node's
         // slot of plane `par`); direct forcing's u* has the body force only.
+        // A membrane under the IB-LBM comparison modes moves with the velocity
+        // of the distributions after this step's force, sum e f + g (per unit
+        // density under Guo's term).
         const double w = wx * wy;
         double cu = 0.0, cv = 0.0;
         if (w != 0.0) {
@@ -85,10 +88,13 @@ __device__ __forceinline__ void markers_body(const InstDev& I, const DevPtrs& P,
                 u += (double)EX[i] * (double)d[i];
                 v += (double)EY[i] * (double)d[i];
             }
-            if (I.guo) {
+            const bool ib_membrane = !I.jumps && I.iface == II_LBM_IF_MEMBRANE;
+            if (I.guo || ib_membrane) {
                 double r = 0.0;
+                if (I.guo) {
 #pragma unroll
-                for (int i = 0; i < 9; i++) r += (double)d[i];
+                    for (int i = 0; i < 9; i++) r += (double)d[i];
+                }
                 double gx = (double)I.body[0], gy = (double)I.body[1];
                 if (!(MODE & kModeGeom)) {
                     const int slot =
@@ -100,8 +106,9 @@ __device__ __forceinline__ void markers_body(const InstDev& I, const DevPtrs& P,
                         gy += (double)c[9 * kTileNodes];
                     }
                 }
-                u = (u + 0.5 * gx) / (1.0 + r);
-                v = (v + 0.5 * gy) / (1.0 + r);
+                const double c = ib_membrane ? 1.0 : 0.5;
+                u = (u + c * gx) / (1.0 + r);
+                v = (v + c * gy) / (1.0 + r);
             }
             cu = u * w;
             cv = v * w;
@@ -451,8 +458,10 @@ __device__ __forceinline__ void rigid_cut(const InstDev& I, double cx, double cy
     if (ang < 0.0) ang += 2.0 * M_PI;
     if (ang < 0.0) ang += 2.0 * M_PI;
     if (ang >= 2.0 * M_PI) ang -= 2.0 * M_PI;
+    // an angle an ulp below 2 pi can round sN up to exactly N: that crossing
+    // belongs to the last interval, at its far end (th = 1)
     const double sN = ang * N / (2.0 * M_PI);
-    k = (sN >= 0.0 && sN < (double)N) ? (int)floor(sN) : 0;
+    k = sN >= 0.0 ? min((int)floor(sN), N - 1) : 0;
     th = sN - k;
 }
 
@@ -476,19 +485,33 @@ struct TileShared {
     float wx[kTileCap][4], wy[kTileCap][4];
     int2 f0[kTileCap];
     double gtx[kTileCap], gty[kTileCap];
-    float acc[8][kTileNodes];    // jump sums of the eight outgoing populations per node
+    long long acc[8][kTileNodes];   // jump sums of the eight outgoing populations per node
     unsigned rec[REC ? kTileRec : 1];   // packed (node, direction, chord) of each cut link
     int cnt, total, nrec, base;
 };
 
 // [[f_i]] of one cut link into the node's accumulator: sigma w_i [[p]] / c_s^2
-// (Sec. 3.1, Eq. (32); Sec. 3.2, Eq. (47)).  A link cut by two chords gets two
-// terms, whose sum does not depend on their order.
+// (Sec. 3.1, Eq. (32); Sec. 3.2, Eq. (47)).  A link cut by several chords
+// (a wrinkled membrane) gets one term per crossing.  The sums are kept in
+// 64-bit fixed point with 2^-56 resolution, so that they are exact and do not
+// depend on the order in which the threads add their crossings; a term is at
+// most 64 in magnitude (a pressure jump of 576 lattice units), and a
+// non-finite one marks the instance unstable.
+constexpr double kJumpFix = 72057594037927936.0;   // 2^56
+
 template <class TS>
-__device__ __forceinline__ void add_jump(TS& S, int node, int i, int sigma, double jpc)
+__device__ __forceinline__ void add_jump(TS& S, int node, int i, int sigma, double jpc, int* err)
 {
-    atomicAdd(&S.acc[i - 1][node], (float)((double)sigma * WD[i] * jpc / kCs2));
+    const double v = (double)sigma * WD[i] * jpc / kCs2;
+    if (!isfinite(v)) {
+        atomicOr(err, (int)kErrUnstable);
+        return;
+    }
+    const long long q = __double2ll_rn(fmin(fmax(v, -64.0), 64.0) * kJumpFix);
+    atomicAdd((unsigned long long*)&S.acc[i - 1][node], (unsigned long long)q);
 }
+
+__device__ __forceinline__ double jump_sum(long long acc) { return (double)acc * (1.0 / kJumpFix); }
 
 template <class TS>
 __device__ __forceinline__ void stage_record(TS& S, int node, int i, int j)
@@ -521,7 +544,7 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
             S.nrec = 0;
         }
 #pragma unroll
-        for (int i = 0; i < 8; i++) S.acc[i][tid] = 0.f;
+        for (int i = 0; i < 8; i++) S.acc[i][tid] = 0;
         __syncthreads();
         const int c = S.cnt;
         if (tid == 0) {
@@ -620,7 +643,7 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
                     int sg;
                     double qq, th;
                     if (!link_crossing<false>(x, y, i, ch, oP, sP, sg, qq, th)) continue;
-                    add_jump(S, node, i, sg, (1.0 - th) * S.jpa[j] + th * S.jpb[j]);
+                    add_jump(S, node, i, sg, (1.0 - th) * S.jpa[j] + th * S.jpb[j], P.err + I.inst);
                     if constexpr (REC) stage_record(S, node, i, j);
                 }
             }
@@ -664,7 +687,7 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
                     rigid_cut(I, ccx, ccy, th0, x, y, i, inP, q, th, k);
                     const double jpc =
                         (1.0 - th) * P.jp[I.mk_off + k] + th * P.jp[I.mk_off + (k + 1) % N];
-                    add_jump(S, tid, i, inP ? 1 : -1, jpc);
+                    add_jump(S, tid, i, inP ? 1 : -1, jpc, P.err + I.inst);
                     if constexpr (REC) stage_record(S, tid, i, 0);
                 }
             }
@@ -682,7 +705,7 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
             for (int i = 1; i < 9; i++) {
                 const double delta =
                     valid ? fs * WD[i] * ((double)EX[i] * gx + (double)EY[i] * gy) +
-                                (double)S.acc[i - 1][tid]
+                                jump_sum(S.acc[i - 1][tid])
                           : 0.0;
                 cr[(i - 1) * kTileNodes] = (float)delta;
             }
@@ -879,7 +902,7 @@ struct TileSharedSpl {
     float wx[kTileCap][4], wy[kTileCap][4];
     int2 f0[kTileCap];
     double gtx[kTileCap], gty[kTileCap];
-    float acc[8][kTileNodes];
+    long long acc[8][kTileNodes];
     unsigned rec[REC ? kTileRec : 1];   // (node, direction, chord, root)
     int cnt, total, nrec, base;
 };
@@ -903,7 +926,7 @@ __device__ void tiles_spline_body(const InstDev& I, const DevPtrs& P, int parity
             S.nrec = 0;
         }
 #pragma unroll
-        for (int i = 0; i < 8; i++) S.acc[i][tid] = 0.f;
+        for (int i = 0; i < 8; i++) S.acc[i][tid] = 0;
         __syncthreads();
         const int c = S.cnt;
         if (tid == 0) {
@@ -991,7 +1014,7 @@ __device__ void tiles_spline_body(const InstDev& I, const DevPtrs& P, int parity
                 int sg[3];
                 const int nr = spl_crossings(S.cf[j], (double)x, (double)y, EX[i], EY[i], ts, qs, sg);
                 for (int rr = 0; rr < nr; rr++) {
-                    add_jump(S, node, i, sg[rr], spl_jump(S.cf[j], S.gk[j], I.dX, ts[rr]));
+                    add_jump(S, node, i, sg[rr], spl_jump(S.cf[j], S.gk[j], I.dX, ts[rr]), P.err + I.inst);
                     if constexpr (REC) {
                         const int e = atomicAdd(&S.nrec, 1);
                         if (e < kTileRec)
@@ -1024,7 +1047,7 @@ __device__ void tiles_spline_body(const InstDev& I, const DevPtrs& P, int parity
             for (int i = 1; i < 9; i++) {
                 const double delta =
                     valid ? fs * WD[i] * ((double)EX[i] * gx + (double)EY[i] * gy) +
-                                (double)S.acc[i - 1][tid]
+                                jump_sum(S.acc[i - 1][tid])
                           : 0.0;
                 cr[(i - 1) * kTileNodes] = (float)delta;
             }
@@ -1134,17 +1157,16 @@ __device__ __forceinline__ void tiles_ib_body(const InstDev& I, const DevPtrs& P
                 gy += S.gy[j] * wgt * I.dX;
             }
         }
-        // the simple force term of g, or (Guo's term) g itself for the sweep
+        // the simple force term of g for the sweep (none under Guo's term,
+        // whose sweep reads g itself), and g for the marker velocity
         float* cr = P.corr[parity] + (long long)(I.act_off + a) * kCorrPlanes * kTileNodes + tid;
         const double fs = I.guo ? 0.0 : 3.0;
 #pragma unroll
         for (int i = 1; i < 9; i++)
             cr[(i - 1) * kTileNodes] =
                 valid ? (float)(fs * WD[i] * ((double)EX[i] * gx + (double)EY[i] * gy)) : 0.f;
-        if (I.guo) {
-            cr[8 * kTileNodes] = valid ? (float)gx : 0.f;
-            cr[9 * kTileNodes] = valid ? (float)gy : 0.f;
-        }
+        cr[8 * kTileNodes] = valid ? (float)gx : 0.f;
+        cr[9 * kTileNodes] = valid ? (float)gy : 0.f;
         __syncthreads();
     }
 }
@@ -1313,6 +1335,115 @@ hipError_t launch_body(const InstDev& I, const DevPtrs& P, int par, hipStream_t 
 {
     hipLaunchKernelGGL(k_body, dim3(1), dim3(256), 0, s, I, P, par);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Pressure on either side of the interface: the mean of p = rho c_s^2 over the
+// nodes farther than `margin` lu from the marker polygon, inside and outside
+// (the pressure jump of Sec. 3.1, whose equilibrium value across a tensioned
+// circle is Laplace's T / R).  One block per row (grid stride): the block
+// walks the chords in batches of 256; a node's inside parity counts the
+// chords that cross its row to the right of it (half-open in y), and a node
+// is left out when some chord lies within `margin` of it.  Nodes that far
+// from the curve are classified the same by every correct even-odd rule.
+// Per block: (sum p inside, count inside, sum p outside, count outside).
+// ---------------------------------------------------------------------------
+constexpr int kPjRow = 8192 / 256;   // nodes per thread of a row (nx <= 8192)
+
+template <typename T, typename M>
+__global__ __launch_bounds__(256) void k_pjump(InstDev I, const T* __restrict__ A,
+                                               const double2* __restrict__ X, double margin,
+                                               double* __restrict__ part)
+{
+    __shared__ double xc[256];
+    __shared__ int near[256];
+    __shared__ int ncross, nnear;
+    __shared__ double sh[4][256];
+    const int t = threadIdx.x, N = I.n_markers;
+    double s_in = 0.0, c_in = 0.0, s_out = 0.0, c_out = 0.0;
+    for (int y = blockIdx.x; y < I.ny; y += gridDim.x) {
+        unsigned par_bits = 0u, near_bits = 0u;
+        const double yd = (double)y;
+        for (int base = 0; base < N; base += 256) {
+            if (t == 0) { ncross = 0; nnear = 0; }
+            __syncthreads();
+            const int k = base + t;
+            if (k < N) {
+                const double2 a = X[k], b = X[k + 1 < N ? k + 1 : 0];
+                if ((a.y > yd) != (b.y > yd))
+                    xc[atomicAdd(&ncross, 1)] = a.x + (yd - a.y) * (b.x - a.x) / (b.y - a.y);
+                if (fmin(a.y, b.y) - margin < yd && yd < fmax(a.y, b.y) + margin)
+                    near[atomicAdd(&nnear, 1)] = k;
+            }
+            __syncthreads();
+            const int nc = ncross, nn = nnear;
+            for (int j = 0; j < kPjRow; j++) {
+                const int x = t + 256 * j;
+                if (x >= I.nx) break;
+                const double xd = (double)x;
+                for (int c = 0; c < nc; c++)
+                    if (xc[c] > xd) par_bits ^= 1u << j;
+                if (near_bits & (1u << j)) continue;
+                for (int c = 0; c < nn; c++) {
+                    const int q = near[c];
+                    const double2 a = X[q], b = X[q + 1 < N ? q + 1 : 0];
+                    if (xd <= fmin(a.x, b.x) - margin || xd >= fmax(a.x, b.x) + margin) continue;
+                    const double vx = b.x - a.x, vy = b.y - a.y, wx = xd - a.x, wy = yd - a.y;
+                    double u = (vx * wx + vy * wy) / (vx * vx + vy * vy);
+                    if (u < 0.0) u = 0.0;
+                    if (u > 1.0) u = 1.0;
+                    const double dx = xd - (a.x + u * vx), dy = yd - (a.y + u * vy);
+                    if (sqrt(dx * dx + dy * dy) < margin) {
+                        near_bits |= 1u << j;
+                        break;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        for (int j = 0; j < kPjRow; j++) {
+            const int x = t + 256 * j;
+            if (x >= I.nx) break;
+            if (near_bits & (1u << j)) continue;
+            M d[9];
+            gather<T, M>(I, A, x, y, d);
+            double r = 0.0;
+#pragma unroll
+            for (int i = 0; i < 9; i++) r += (double)d[i];
+            const double pr = (1.0 + r) * kCs2;
+            if (par_bits & (1u << j)) { s_in += pr; c_in += 1.0; }
+            else { s_out += pr; c_out += 1.0; }
+        }
+    }
+    sh[0][t] = s_in; sh[1][t] = c_in; sh[2][t] = s_out; sh[3][t] = c_out;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w)
+            for (int c = 0; c < 4; c++) sh[c][t] += sh[c][t + w];
+        __syncthreads();
+    }
+    if (t == 0)
+        for (int c = 0; c < 4; c++) part[4 * blockIdx.x + c] = sh[c][0];
+}
+
+template <typename T, typename M>
+static hipError_t pjump_t(const InstDev& I, const void* A, const double2* X, double margin,
+                          double* part, int nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_pjump<T, M>), dim3(nblocks), dim3(256), 0, s, I, (const T*)A, X, margin,
+                       part);
+    return hipGetLastError();
+}
+
+hipError_t launch_pjump(const InstDev& I, const void* A, const double2* X, double margin,
+                        double* part, int nblocks, hipStream_t s)
+{
+    if (I.n_markers < 3 || I.nx > kPjRow * 256) return hipErrorInvalidValue;
+    if (I.storage == II_LBM_FP16)
+        return I.math == II_LBM_MATH_FP64 ? pjump_t<_Float16, double>(I, A, X, margin, part, nblocks, s)
+                                          : pjump_t<_Float16, float>(I, A, X, margin, part, nblocks, s);
+    return I.math == II_LBM_MATH_FP64 ? pjump_t<float, double>(I, A, X, margin, part, nblocks, s)
+                                      : pjump_t<float, float>(I, A, X, margin, part, nblocks, s);
 }
 
 }  // namespace iilbm

@@ -236,7 +236,7 @@ int build_layout(const ii_lbm_problem* p, int n_inst, Layout& L)
     L.off_rec = take((size_t)std::max(rec, 1) * sizeof(ii_lbm_link));
     L.off_rec_count = take((size_t)2 * n_inst * sizeof(int));
     L.off_err = take((size_t)n_inst * sizeof(int));
-    L.off_diag = take((size_t)4 * kDiagBlocks * sizeof(double));
+    L.off_diag = take((size_t)8 * kDiagBlocks * sizeof(double));
     L.off_body = take((size_t)n_inst * sizeof(BodyDev));
     L.off_M = take(nm * sizeof(double2));
     L.taps_total = taps;
@@ -578,6 +578,19 @@ static hipError_t build_graph(ii_lbm_handle* h, int par)
     return e;
 }
 
+// Both graphs (one per starting parity) at once: an odd number of direct
+// steps between replays flips the parity, and the other graph must not be
+// captured and instantiated in the middle of a caller's timed loop.
+static hipError_t ensure_graphs(ii_lbm_handle* h)
+{
+    for (int par = 0; par < 2; par++)
+        if (!h->gexec[par]) {
+            const hipError_t e = build_graph(h, par);
+            if (e != hipSuccess) return e;
+        }
+    return hipSuccess;
+}
+
 // Plane of the newest cut-link records: membranes hold those of the current
 // markers, rigid bodies those built by the last step (-1: none yet).
 static int record_parity(const ii_lbm_handle* h)
@@ -864,12 +877,12 @@ int ii_lbm_step(ii_lbm_handle* h, int64_t n_steps)
     if (h->failed) return II_LBM_ESTATE;
     int64_t left = n_steps;
     if (h->use_graph && !h->timing) {
+        if (left >= 2) {
+            const hipError_t e = ensure_graphs(h);
+            if (e != hipSuccess) return hip_fail(h, e);
+        }
         while (left >= 2) {
             const int par = h->parity;
-            if (!h->gexec[par]) {
-                const hipError_t e = build_graph(h, par);
-                if (e != hipSuccess) return hip_fail(h, e);
-            }
             const hipError_t e = hipGraphLaunch(h->gexec[par], h->stream);
             if (e != hipSuccess) return hip_fail(h, e);
             h->steps += 2;   // two parity flips leave the parity unchanged
@@ -960,8 +973,12 @@ int ii_lbm_set_graph(ii_lbm_handle* h, int32_t enable)
 {
     if (!h) return II_LBM_EINVAL;
     h->use_graph = enable != 0;
-    if (!h->use_graph) drop_graphs(h);
-    return II_LBM_OK;
+    if (!h->use_graph) {
+        drop_graphs(h);
+        return II_LBM_OK;
+    }
+    if (h->failed) return II_LBM_ESTATE;
+    return hip_fail(h, ensure_graphs(h));
 }
 
 int ii_lbm_autotune(ii_lbm_handle* h, int32_t trials, int32_t* unit, int32_t* order, double* best_us)
@@ -1241,6 +1258,25 @@ int ii_lbm_diag(ii_lbm_handle* h, int32_t inst, ii_lbm_diag_t* out)
         if (current && par >= 0)
             (void)hipMemcpy(&n, h->P.rec_count + 2 * inst + par, sizeof(int), hipMemcpyDeviceToHost);
         out->n_cut_links = n;
+        // pressure on either side, 3 lu away from the polygon
+        const int nb = std::min(I.ny, kDiagBlocks);
+        double* pp = h->P.diag + 4 * kDiagBlocks;
+        e = launch_pjump(I, h->P.lat[h->parity], h->P.X[h->parity] + I.mk_off, 3.0, pp, nb, h->stream);
+        std::vector<double> pj(4 * (size_t)nb);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(pj.data(), pp, pj.size() * sizeof(double), hipMemcpyDeviceToHost,
+                               h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return hip_fail(h, e);
+        double q[4] = {0, 0, 0, 0};
+        for (int b = 0; b < nb; b++)
+            for (int c = 0; c < 4; c++) q[c] += pj[4 * b + c];
+        out->n_in = (int64_t)q[1];
+        out->n_out = (int64_t)q[3];
+        out->p_in = q[1] > 0.0 ? q[0] / q[1] : NAN;
+        out->p_out = q[3] > 0.0 ? q[2] / q[3] : NAN;
+    } else {
+        out->p_in = out->p_out = NAN;
     }
     return h->failed;
 }

@@ -272,6 +272,54 @@ def test_determinism_and_checkpoint_restart(B):
         s.close()
 
 
+def _wrinkled_membrane():
+    """A closed polygon whose bottom side zigzags 0.25 lu apart in x between
+    y = 11.75 and 12.65, so that lattice links at y = 12 cross three, four or
+    five of its chords; the other sides are straight (0.5 lu spacing)."""
+    pts = [(x + 0.013, 12.2 + (0.45 if j % 2 else -0.45))
+           for j, x in enumerate(np.arange(12.0, 28.0, 0.25))]
+    pts += [(28.013, y) for y in np.arange(12.5, 28.0, 0.5)]
+    pts += [(x + 0.013, 28.0) for x in np.arange(28.0, 12.0, -0.5)]
+    pts += [(12.013, y) for y in np.arange(28.0, 12.0, -0.5)]
+    X = np.ascontiguousarray(pts, dtype=np.float64)
+    l = np.linalg.norm(np.roll(X, -1, 0) - X, axis=1)
+    prob = W.Problem(nx=40, ny=40, tau=0.8, interface=W.IF_MEMBRANE, n_markers=len(X),
+                     kappa=1e-4, dX=float(l.mean()), math=W.MATH_FP64)
+    return prob, X
+
+
+def test_multi_crossing_links_deterministic(B):
+    # Links cut by three or more chords: their jump terms are summed exactly
+    # (fixed point), so two runs are bitwise equal whatever order the threads
+    # add them in; the run agrees with the oracle.
+    _say("wrinkled membrane 40x40: links crossing 3-5 chords, determinism + parity, 30 steps")
+    prob, X = _wrinkled_membrane()
+    p = O.make_problem(prob)
+    want = O.cutlinks(p, X)
+    per_link = {}
+    for r in want:
+        key = (int(r["x"]), int(r["y"]), int(r["dir"]))
+        per_link[key] = per_link.get(key, 0) + 1
+    assert max(per_link.values()) >= 5 and sum(v >= 3 for v in per_link.values()) >= 30
+    runs = []
+    for _ in range(2):
+        sim = B.Sim([prob], [X])
+        got = sim.cutlinks()
+        key = lambda r: sorted(zip(r["x"].tolist(), r["y"].tolist(), r["dir"].tolist(),
+                                   r["sigma"].tolist(), r["seg"].tolist()))
+        assert key(got) == key(want)
+        sim.step(30)
+        runs.append((sim.fields(B.F_DISTRIB, dtype=np.float32), sim.markers()[0]))
+        g = sim.fields(B.F_UX | B.F_UY)
+        sim.close()
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+    o = _oracle_run(prob, X, 30)
+    err = _rel_l2(g[0], g[1], o["ux"], o["uy"])
+    dX = np.abs(runs[0][1] - o["X"]).max()
+    _say(f"  rel L2 u = {err:.3e}  max |dX| = {dX:.3e}")
+    assert err <= 1e-6 and dX <= 1e-6
+
+
 def test_unstable_state_is_reported(B):
     _say("non-finite state -> EUNSTABLE")
     w = W.membrane_c1()
@@ -305,6 +353,43 @@ def test_full_size_membrane4096_first_steps(B):
     assert dX <= 1e-9
     d = sim.diag()
     assert d["error_bits"] == 0 and d["n_cut_links"] > 10000
+    sim.close()
+
+
+def test_full_size_membrane4096_fp16_first_steps(B):
+    # The second run of the 4096^2 membrane: FP16 deviation storage with FP32
+    # collision arithmetic, as the bench's FP16 line runs it (the 512-wide
+    # row-segment sweep), two steps against the FP64 oracle at the
+    # reduced-precision bar.
+    _say("membrane 4096x4096 FP16 storage, FP32 math, 2 steps vs oracle")
+    w = W.membrane_c3(storage=W.STORE_FP16)
+    w.problem.math = W.MATH_FP32
+    sim, g = _gpu_run(B, w.problem, w.X0, 2)
+    o = _oracle_run(w.problem, w.X0, 2)
+    err = _rel_l2(g["ux"], g["uy"], o["ux"], o["uy"])
+    dX = np.abs(g["X"] - o["X"]).max()
+    _say(f"  rel L2 u = {err:.3e}  max |dX| = {dX:.3e}")
+    assert err <= 1e-3
+    assert dX <= 1e-6
+    d = sim.diag()
+    assert d["error_bits"] == 0 and d["n_cut_links"] > 10000
+    sim.close()
+
+
+@pytest.mark.parametrize("math_", [W.MATH_FP32, W.MATH_FP64])
+def test_membrane512_fp16_parity_1000_steps(B, math_):
+    # FP16 storage on a 512-wide lattice (the 512-node row-segment sweep the
+    # 4096^2 bench times), 1000 steps against the oracle at the
+    # reduced-precision bar, with both collision arithmetics.
+    _say(f"membrane 512x512 FP16 storage math={math_}, 1000 steps vs oracle")
+    w = W.membrane_c3(L=512, storage=W.STORE_FP16)
+    w.problem.math = math_
+    sim, g = _gpu_run(B, w.problem, w.X0, 1000)
+    o = _oracle_run(w.problem, w.X0, 1000)
+    err = _rel_l2(g["ux"], g["uy"], o["ux"], o["uy"])
+    dX = np.abs(g["X"] - o["X"]).max()
+    _say(f"  rel L2 u = {err:.3e}  max |dX| = {dX:.3e}")
+    assert err <= 1e-3
     sim.close()
 
 
