@@ -258,6 +258,22 @@ enum { II_LBM_DT_F32 = 0, II_LBM_DT_F64 = 1 };
 int ii_lbm_fields(ii_lbm_handle* h, int32_t inst, uint32_t what, void* out, int32_t dtype,
                   int32_t on_device);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * host-output form of ii_lbm_fields (on_device = 0) without its per-call
+ * staging allocation.  The planes are staged through a static device array
+ * of 64 MiB that the library holds on each GPU it runs on until the process
+ * ends; the call allocates nothing (no hipMalloc, hipFree or host heap).
+ * Same `what`, `dtype` and layout as ii_lbm_fields; `out` is host memory of
+ * planes * ny * nx elements.  II_LBM_ECAPACITY when the requested planes
+ * exceed 64 MiB (e.g. more than one FP32 plane of a 4096^2 lattice); the
+ * state is not touched then.  All calls on one GPU share its array: calls
+ * that overlap in time on one GPU (several host threads, or handles on
+ * different streams) race and must be serialised by the caller.
+ * Synchronises the handle's stream. */
+int ii_lbm_fields_noalloc(ii_lbm_handle* h, int32_t inst, uint32_t what, void* out,
+                          int32_t dtype);
+
 /* Sets the state of one instance from nine host planes f[9][ny][nx] (FP64,
  * full distributions): the next step collides exactly this field (periodic
  * axes; on non-periodic sides the boundary nodes are re-derived by the

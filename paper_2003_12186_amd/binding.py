@@ -56,7 +56,8 @@ class Diag(C.Structure):
 
 EXPORTS = [
     "ii_lbm_workspace_size", "ii_lbm_init", "ii_lbm_step", "ii_lbm_sync", "ii_lbm_markers",
-    "ii_lbm_set_markers", "ii_lbm_fields", "ii_lbm_set_distrib", "ii_lbm_state_size",
+    "ii_lbm_set_markers", "ii_lbm_fields", "ii_lbm_fields_noalloc", "ii_lbm_set_distrib",
+    "ii_lbm_state_size",
     "ii_lbm_save_state", "ii_lbm_load_state", "ii_lbm_cutlinks", "ii_lbm_diag",
     "ii_lbm_set_timing", "ii_lbm_get_timing", "ii_lbm_sweep_bytes", "ii_lbm_set_graph",
     "ii_lbm_set_overlap", "ii_lbm_autotune", "ii_lbm_destroy", "ii_lbm_strerror",
@@ -89,6 +90,7 @@ def load():
         "ii_lbm_markers": [v, i32, v, v, v],
         "ii_lbm_set_markers": [v, i32, v],
         "ii_lbm_fields": [v, i32, C.c_uint32, v, i32, i32],
+        "ii_lbm_fields_noalloc": [v, i32, C.c_uint32, v, i32],
         "ii_lbm_set_distrib": [v, i32, v],
         "ii_lbm_state_size": [v, i32, C.POINTER(sz)],
         "ii_lbm_save_state": [v, i32, v, sz],
@@ -220,6 +222,18 @@ class Sim:
         out = np.zeros((planes, p.ny, p.nx), dtype=dtype)
         dt = DT_F64 if dtype == np.float64 else DT_F32
         check(load().ii_lbm_fields(self.h, inst, what, out.ctypes.data, dt, 0), "fields")
+        return out
+
+    def fields_noalloc(self, what: int = F_RHO | F_UX | F_UY, inst: int = 0,
+                       dtype=np.float64) -> np.ndarray:
+        """As fields(), staged through the library's static device array
+        (no device allocation in the call)."""
+        p = self.problems[inst]
+        planes = sum((what >> b) & 1 for b in range(4)) + (9 if what & F_DISTRIB else 0)
+        out = np.zeros((planes, p.ny, p.nx), dtype=dtype)
+        dt = DT_F64 if dtype == np.float64 else DT_F32
+        check(load().ii_lbm_fields_noalloc(self.h, inst, what, out.ctypes.data, dt),
+              "fields_noalloc")
         return out
 
     def fields_device(self, what: int, out, inst: int = 0) -> None:

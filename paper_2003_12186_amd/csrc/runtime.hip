@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -21,6 +22,41 @@ constexpr int kEventPool = 16384;
 constexpr int kXcds = 8;   // MI355X: eight accelerator complex dies, one L2 each
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+
+}  // namespace
+
+// Staging array of ii_lbm_fields_noalloc: one copy per GPU, held until the
+// process ends.  In host code `scratch` names a host-side stand-in, not a
+// device address: its address on each device comes from
+// hipGetSymbolAddress, taken once per device at ii_lbm_init and kept in the
+// handle.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's `scratch` (the current device).
+hipError_t scratch_address(void** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 struct Layout {
     std::vector<InstDev> inst;
@@ -299,6 +335,8 @@ struct ii_lbm_handle {
     LearnedCfg learned;
     hipStream_t lrn = nullptr;
     hipEvent_t ev_x = nullptr, ev_b = nullptr, ev_g = nullptr;
+    // this device's static staging array (ii_lbm_fields_noalloc)
+    void* scratch = nullptr;
 };
 
 static int hip_fail(ii_lbm_handle* h, hipError_t e)
@@ -310,14 +348,19 @@ static int hip_fail(ii_lbm_handle* h, hipError_t e)
 
 static int check_device_errors(ii_lbm_handle* h)
 {
+    // the instances' error words in chunks through a stack buffer (no
+    // allocation, so the allocation-free readout can use this too)
     const int n = (int)h->prob.size();
-    std::vector<int> err(n);
-    hipError_t e = hipMemcpyAsync(err.data(), h->P.err, n * sizeof(int), hipMemcpyDeviceToHost,
-                                  h->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) return hip_fail(h, e);
     int bits = 0;
-    for (int v : err) bits |= v;
+    for (int j0 = 0; j0 < n; j0 += 64) {
+        int err[64];
+        const int m = std::min(64, n - j0);
+        hipError_t e = hipMemcpyAsync(err, h->P.err + j0, m * sizeof(int), hipMemcpyDeviceToHost,
+                                      h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return hip_fail(h, e);
+        for (int q = 0; q < m; q++) bits |= err[q];
+    }
     if (h->isolate) return h->failed;
     if (bits & kErrUnstable) h->failed = II_LBM_EUNSTABLE;
     else if (bits & kErrGeometry) h->failed = II_LBM_EGEOMETRY;
@@ -856,6 +899,7 @@ int ii_lbm_init(const ii_lbm_problem* p, int32_t n_inst, const double* const* X0
             h->n_cu = cus;
     }
     size_tile_blocks(h);
+    if (e == hipSuccess) e = scratch_address(&h->scratch);
     if (e == hipSuccess && h->lookahead) {
         e = hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming);
@@ -1087,6 +1131,26 @@ int ii_lbm_fields(ii_lbm_handle* h, int32_t inst, uint32_t what, void* out, int3
         e = hipMemcpyAsync(out, dst, bytes, hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (!on_device) (void)hipFree(dst);
+    return hip_fail(h, e);
+}
+
+int ii_lbm_fields_noalloc(ii_lbm_handle* h, int32_t inst, uint32_t what, void* out, int32_t dtype)
+{
+    if (!h || !out || inst < 0 || inst >= (int)h->prob.size()) return II_LBM_EINVAL;
+    if (dtype != II_LBM_DT_F32 && dtype != II_LBM_DT_F64) return II_LBM_EINVAL;
+    if (what == 0 || (what & ~31u)) return II_LBM_EINVAL;
+    const InstDev& I = h->L.inst[inst];
+    int planes = 0;
+    for (int b = 0; b < 4; b++) planes += (what >> b) & 1;
+    if (what & II_LBM_F_DISTRIB) planes += 9;
+    const size_t bytes = (size_t)planes * I.nx * I.ny * (dtype == II_LBM_DT_F64 ? 8 : 4);
+    if (bytes > kScratchBytes) return II_LBM_ECAPACITY;
+    if (!h->scratch) return II_LBM_EDEVICE;
+    const int rc = sync_and_check(h);
+    if (rc) return rc;
+    hipError_t e = launch_fields(I, h->P.lat[h->parity], what, h->scratch, dtype, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, h->scratch, bytes, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     return hip_fail(h, e);
 }
 
