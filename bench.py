@@ -349,10 +349,11 @@ def bench_area(args, B, W) -> int:
     """The area comparison of Sec. 4.2 (Table 2): the elastic membrane under
     IB-LBM with the simple and with Guo's force term and under II-LBM (also
     with Guo's term, and on the cubic spline), L = 80, 160, 240, to t = 30 L/U, the enclosed area read
-    after every L/U (HIP graphs between the reads).  Reports the loss rate
-    (least-squares slope of the area loss over t = 1..30 L/U, and the total
-    over 30) and the throughput of every run.  Then the sweep with Guo's term
-    against the plain one on the 4096^2 membrane, HIP-event timed."""
+    after every L/U (HIP graphs between the reads).  Reports, in the paper's
+    normalisation (area over L^2, time in L/U), the loss rate (least-squares
+    slope of the area loss over t = 1..30 L/U) and the total loss at 30 L/U,
+    and the throughput of every run.  Then the sweep with Guo's term against
+    the plain one on the 4096^2 membrane, HIP-event timed."""
     import numpy as np
     import torch
     names = {W.FORCE_IB_LBM: "IB-LBM", W.FORCE_IB_LBM_GUO: "IB-LBM (G)",
@@ -379,11 +380,10 @@ def bench_area(args, B, W) -> int:
                 try:
                     d = sim.diag()
                 except B.IILBMError as err:
-                    # a run that leaves the supported region (the simple-term
-                    # IB-LBM membrane drifts outward and buckles) ends here
+                    # a run that leaves the supported region ends here
                     failed = {"at_L_over_U": k + 1, "error": str(err)}
                     break
-                loss.append((A0 - d["area"]) / A0)
+                loss.append((A0 - d["area"]) / L ** 2)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             n_ok = len(loss)

@@ -66,8 +66,9 @@ enum { II_LBM_IF_NONE = 0, II_LBM_IF_MEMBRANE = 1, II_LBM_IF_RIGID = 2, II_LBM_I
  *  IB_GUO  IB-LBM with Guo's force term (Sec. 2.2.2, the SRT and MRT forms):
  *          compressible equilibrium w_i rho [1 + e.u/c_s^2 + (e.u)^2/(2 c_s^4)
  *          - u.u/(2 c_s^2)] with rho u = sum e_i f_i + g/2; a membrane's
- *          markers move with (sum e_i f_i + g) / rho, the velocity after the
- *          step's force, as under IB;
+ *          markers move with that velocity taken from the distributions
+ *          after the step's force (momentum sum e_i f_i + g):
+ *          (sum e_i f_i + 3 g / 2) / rho;
  *  II_GUO  II-LBM with Guo's term of g_par (Sec. 3.2); the markers move with
  *          rho u = sum e_i f_i + g/2.
  * The body force joins g in every mode; direct forcing's u* carries the body

@@ -36,10 +36,11 @@
  *  R11 marker velocity from u = sum e_i f_i of the pre-collision field
  *      (II-LBM);
  *  R18 the IB-LBM comparison modes (the whole force spread, no jumps) move a
- *      membrane with the velocity its distributions carry after the step's
- *      collision and force term, sum e_i f_i + g (divided by rho under Guo's
- *      term); Table 2 fixes this: it is the reading under which both IB-LBM
- *      columns lose area at the printed rates;
+ *      membrane with the scheme's own velocity taken from the distributions
+ *      after the step's collision and force term (momentum sum e_i f_i + g):
+ *      u = sum e_i f_i + g under the simple term, (sum e_i f_i + 3 g / 2) / rho
+ *      under Guo's; Table 2 fixes this: it is the reading under which both
+ *      IB-LBM columns lose area at the printed rates;
  *  R12 non-equilibrium extrapolation on non-periodic sides, corners as walls
  *      (a uniform inflow side takes u_b = (u_max, 0));
  *  R27 (geometry 1) the membrane is the periodic cubic spline through the
@@ -922,11 +923,12 @@ int or_step(const or_problem *p, double *f, double *X, or_step_out *out)
         /* 3b. the velocity a membrane moves with, now that the whole force g
          *     of this step is known (a membrane's force depends on X alone):
          *     - II-LBM with Guo's term: u = (j + g/2) / rho (Sec. 2.2.2);
-         *     - the IB-LBM comparison modes: the velocity of the distributions
-         *       after this step's collision and force term, j + g (per unit
-         *       density under Guo's term), reading R18 */
+         *     - the IB-LBM comparison modes (reading R18): each scheme's own
+         *       velocity taken from the distributions after this step's
+         *       collision and force term, whose momentum is j + g: the simple
+         *       term's u = j + g, Guo's u = (j + g + g/2) / rho */
         if (p->interface == OR_IF_MEMBRANE && (uses_guo(p) || !has_jumps(p))) {
-            double c = has_jumps(p) ? 0.5 : 1.0;
+            double c = has_jumps(p) ? 0.5 : (uses_guo(p) ? 1.5 : 1.0);
             for (long n = 0; n < nn; n++) {
                 double j0 = uses_guo(p) ? jx[n] : ux[n], j1 = uses_guo(p) ? jy[n] : uy[n];
                 double r = uses_guo(p) ? rho[n] : 1.0;

@@ -72,9 +72,10 @@ __device__ __forceinline__ void markers_body(const InstDev& I, const DevPtrs& P,
         // u = (sum e f + g/2) / rho (Sec. 2.2.2): g is the body force plus,
         // for a membrane, the force this step's tile pass spread (the node's
         // slot of plane `par`); direct forcing's u* has the body force only.
-        // A membrane under the IB-LBM comparison modes moves with the velocity
-        // of the distributions after this step's force, sum e f + g (per unit
-        // density under Guo's term).
+        // A membrane under the IB-LBM comparison modes moves with its scheme's
+        // velocity taken from the distributions after this step's force
+        // (momentum sum e f + g): sum e f + g under the simple term,
+        // (sum e f + 3 g / 2) / rho under Guo's.
         const double w = wx * wy;
         double cu = 0.0, cv = 0.0;
         if (w != 0.0) {
@@ -106,7 +107,7 @@ __device__ __forceinline__ void markers_body(const InstDev& I, const DevPtrs& P,
                         gy += (double)c[9 * kTileNodes];
                     }
                 }
-                const double c = ib_membrane ? 1.0 : 0.5;
+                const double c = ib_membrane ? (I.guo ? 1.5 : 1.0) : 0.5;
                 u = (u + c * gx) / (1.0 + r);
                 v = (v + c * gy) / (1.0 + r);
             }
