@@ -96,10 +96,22 @@ def cpu_baseline(w, steps: int, single_steps: int = None):
     return out
 
 
+CNN_FLOP_PER_PIXEL = 2 * 9 * (4 * 32 + 32 * 32 + 32 * 32 + 32 * 9)   # 44,352
+
+
+def band_pixels(flags, listed):
+    """Output pixels with a band node (|sd| <= 4) over the listed tiles: the
+    network's algorithmic work is CNN_FLOP_PER_PIXEL for each."""
+    import torch
+    band = (flags[:, 4:20, 4:20] & 2) != 0
+    return (band.reshape(band.shape[0], -1).sum(dim=1) * listed).sum().to(torch.float64)
+
+
 def cnn_flops(flags, listed):
-    """Algorithmic FLOPs of the network kernel over the listed band tiles:
-    per layer, the pixel tiles (16 outputs) that hold a row feeding an output
-    row with a band node, each output pixel 2 x 9 x c_in x c_out FLOP."""
+    """FLOPs the network kernel computes over the listed band tiles: per
+    layer, the pixel tiles (16 outputs) that hold a row feeding an output row
+    with a band node, each output pixel 2 x 9 x c_in x c_out FLOP (the halo
+    rows of the valid convolutions included)."""
     import torch
     band = (flags[:, 4:20, 4:20] & 2) != 0
     rows = [band.any(dim=2) & listed[:, None]]          # output rows with a band node
@@ -161,6 +173,50 @@ def cpu_baseline_learned(w, net_file: str, steps: int):
                       f"({n_tiles} band tiles through the network) after 1 untimed step ({dt:.1f} s)"}
 
 
+def learned_accuracy(B, sl, sp, sf, n: int, steps: int) -> dict:
+    """Relative L2 velocity of the corrected (sl) and plain (sp) coarse runs
+    against the fine run (sf) at the same physical time, fine restricted to
+    the coarse nodes and doubled (diffusive scaling); also the error of the
+    divergence-free part alone (periodic Helmholtz split by FFT)."""
+    import numpy as np
+    bits = sl.instance_errors()
+
+    def split_sol(u, v):
+        k = np.fft.fftfreq(u.shape[0]) * 2 * np.pi
+        ky, kx = np.meshgrid(k, k, indexing="ij")
+        k2 = kx ** 2 + ky ** 2
+        k2[0, 0] = 1.0
+        U, V = np.fft.fft2(u), np.fft.fft2(v)
+        dv = kx * U + ky * V
+        return u - np.real(np.fft.ifft2(kx * dv / k2)), v - np.real(np.fft.ifft2(ky * dv / k2))
+
+    e = {"plain": [], "learned": [], "plain_divfree": [], "learned_divfree": []}
+    for j in range(n):
+        r = 2.0 * sf.fields(B.F_UX | B.F_UY, inst=j)[:, ::2, ::2]
+        nr = np.sqrt((r ** 2).sum())
+        rs = split_sol(r[0], r[1])
+        nrs = np.sqrt((rs[0] ** 2 + rs[1] ** 2).sum())
+        for name, s, ok in (("plain", sp, True), ("learned", sl, bits[j] == 0)):
+            g = s.fields(B.F_UX | B.F_UY, inst=j)
+            if not ok or not np.isfinite(g).all():
+                e[name].append(float("nan"))
+                e[name + "_divfree"].append(float("nan"))
+                continue
+            e[name].append(float(np.sqrt(((g - r) ** 2).sum()) / nr))
+            gs = split_sol(g[0], g[1])
+            e[name + "_divfree"].append(float(np.sqrt(((gs[0] - rs[0]) ** 2 + (gs[1] - rs[1]) ** 2).sum()) / nrs))
+    a = {k: np.array(v) for k, v in e.items()}
+    med = lambda x: float(np.median(x)) if np.isfinite(x).all() else (
+        float(np.nanmedian(x)) if np.isfinite(x).any() else None)
+    return {"coarse_step": steps, "instances_finite_learned": int(np.isfinite(a["learned"]).sum()),
+            "median_rel_l2_plain": med(a["plain"]), "median_rel_l2_learned": med(a["learned"]),
+            "frac_within_1e-2_plain": float((a["plain"] <= 1e-2).mean()),
+            "frac_within_1e-2_learned": float((a["learned"] <= 1e-2).mean()),
+            "frac_learned_better": float((a["learned"] < a["plain"]).mean()),
+            "median_divfree_rel_l2_plain": med(a["plain_divfree"]),
+            "median_divfree_rel_l2_learned": med(a["learned_divfree"])}
+
+
 def bench_learned(args, B, W) -> int:
     """Learned correction of 2x-coarsened membranes: held-out coarse/fine
     pairs (256^2 / 512^2, 512 markers, diffusive scaling) batched in one
@@ -169,10 +225,14 @@ def bench_learned(args, B, W) -> int:
     inside every step, direct launches), next to 4K fine steps (HIP graphs)
     covering the same physical time; beside them, the same K steps with the
     correction called after each step from the host.  The correction is
-    scaled by alpha = 0: every kernel runs in full and adds zero, so the
-    trajectory and the timing do not depend on the network's stability.  The
-    network kernel's roofline comes from a last pass with HIP events around
-    each of its launches."""
+    scaled by --alpha (default 0.1: at full strength the committed network
+    drives every held-out rollout non-finite within 250 steps, at 0.1 all
+    stay finite), with failure isolation on, so that an instance the
+    correction drives non-finite is reported on its own.  After the timed steps the coarse
+    runs are compared with the fine ones at the same physical time (relative
+    L2 velocity, fine restricted to the coarse nodes, times 2; also its
+    divergence-free part).  The network kernel's roofline comes from a last
+    pass with HIP events around each of its launches."""
     import numpy as np
     import torch
     from paper_2003_12186_amd import learned as LN
@@ -181,9 +241,11 @@ def bench_learned(args, B, W) -> int:
     pairs = [W.learned_pair_c5(s) for s in seeds]
     d = np.load(LEARNED_WEIGHTS)
     net = LN.Net(d["params"])
-    sc = LN.make_scales(d["in_scale"], 0.0)
+    sc = LN.make_scales(d["in_scale"], float(d["out_scale"]) * args.alpha)
     sl = B.Sim([c.problem for c, _ in pairs], [c.X0 for c, _ in pairs], device="cuda:0")
     sm = B.Sim([c.problem for c, _ in pairs], [c.X0 for c, _ in pairs], device="cuda:0")
+    for s in (sl, sm):
+        s.set_isolation(True)
     sp = B.Sim([c.problem for c, _ in pairs], [c.X0 for c, _ in pairs], device="cuda:0")
     sf = B.Sim([f.problem for _, f in pairs], [f.X0 for _, f in pairs], device="cuda:0")
     # the handle's three streams overlap when launched directly; graph
@@ -222,12 +284,14 @@ def bench_learned(args, B, W) -> int:
     sf.step(4 * args.steps)
     torch.cuda.synchronize()
     dt_fine = time.perf_counter() - t0
+    accuracy = learned_accuracy(B, sl, sp, sf, n, args.warmup + args.steps)
     # event-timed network launches on the same trajectory
     band.detach()
     n_t = min(args.steps, 200)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_t)]
     run_tiles = torch.zeros((), dtype=torch.int64, device="cuda:0")
     run_flop = torch.zeros((), dtype=torch.float64, device="cuda:0")
+    run_band = torch.zeros((), dtype=torch.float64, device="cuda:0")
     pix = torch.arange(band.cap, device="cuda:0")
     for k in range(n_t):
         sl.step(1)
@@ -242,13 +306,16 @@ def bench_learned(args, B, W) -> int:
         fl, nt = cnn_flops(band.flags, listed)
         run_flop += fl
         run_tiles += nt
+        run_band += band_pixels(band.flags, listed)
     torch.cuda.synchronize()
     sl.sync()
     t_infer = sum(a.elapsed_time(b) for a, b in ev) / 1e3
     tiles = int(run_tiles.item())
     flop = float(run_flop.item())
+    alg_flop = float(run_band.item()) * CNN_FLOP_PER_PIXEL
     avg = t_infer / n_t
-    achieved = flop / n_t / avg / 1e12
+    achieved = alg_flop / n_t / avg / 1e12
+    computed = flop / n_t / avg / 1e12
     nodes = sum(c.problem.nx * c.problem.ny for c, _ in pairs)
     nodes_f = sum(f.problem.nx * f.problem.ny for _, f in pairs)
     out = {
@@ -259,7 +326,10 @@ def bench_learned(args, B, W) -> int:
         "dtype": "f32 storage / fp32 collision; bf16 MFMA network, f32 accumulation",
         "data": "synthetic",
         "config": {"workload": f"learned_c5_{n}", "instances": n, "coarse": 256, "fine": 512,
-                   "markers": 512, "fine_steps_per_coarse": 4, "alpha": 0.0,
+                   "markers": 512, "fine_steps_per_coarse": 4, "alpha": args.alpha,
+                   "accuracy": accuracy,
+                   "target_met": bool(accuracy["frac_within_1e-2_learned"] >= 0.95
+                                      and dt_fine / dt >= 4.0),
                    "t_corrected_coarse_s": round(dt, 4),
                    "t_corrected_coarse_host_calls_s": round(dt_manual, 4),
                    "t_plain_coarse_s": round(dt_plain, 4),
@@ -269,7 +339,13 @@ def bench_learned(args, B, W) -> int:
         "roofline": {"bound": "mfma", "kernel": "k_correct", "achieved": round(achieved, 2),
                      "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / BF16_PEAK_TFLOPS, 4), "traffic": None,
-                     "flop_per_launch": round(flop / n_t), "dense_flop_per_tile": CNN_FLOP_PER_TILE,
+                     "algorithmic_flop_per_launch": round(alg_flop / n_t),
+                     "band_pixels_per_launch": round(float(run_band.item()) / n_t, 1),
+                     "flop_per_pixel": CNN_FLOP_PER_PIXEL,
+                     "computed_flop_per_launch": round(flop / n_t),
+                     "computed_tflops": round(computed, 2),
+                     "computed_frac": round(computed / BF16_PEAK_TFLOPS, 4),
+                     "dense_flop_per_tile": CNN_FLOP_PER_TILE,
                      "tiles_per_launch": round(tiles / n_t, 1),
                      "avg_launch_us": round(avg * 1e6, 2), "timed_launches": n_t},
     }
@@ -1144,6 +1220,8 @@ def main() -> int:
                     help="circle diameters D of the table1 workload (Sec. 4.1)")
     ap.add_argument("--area-sizes", default="80,160,240",
                     help="lattice sizes L of the area workload (the elastic membrane of Sec. 4.2)")
+    ap.add_argument("--alpha", type=float, default=0.1,
+                    help="learned workload: strength of the correction (1 = as trained)")
     ap.add_argument("--instances", type=int, default=None,
                     help="instances of the batch512 (default 512) or learned (200) workload")
     ap.add_argument("--graph", choices=["on", "off"], default="on",

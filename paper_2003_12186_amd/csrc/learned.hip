@@ -110,7 +110,9 @@ constexpr int kWl = 9 * 2 * 512;
 
 // `rows`: bit r set when output row r is needed; a pixel tile none of whose
 // rows is needed is skipped (its outputs are left as they are).
-template <int HSRC, int HDST, int CIN, int KS, int NT, bool FULL, class Epi>
+// PS: elements between consecutive pixels of a 32-channel `src` (32 packed,
+// or padded so that the lanes' 16-byte reads spread over the LDS banks).
+template <int HSRC, int HDST, int CIN, int KS, int NT, bool FULL, class Epi, int PS = 32>
 __device__ __forceinline__ void conv_mfma(const u16* src, const u16* __restrict__ frag, u16* wl,
                                           Epi epi, unsigned rows = ~0u)
 {
@@ -155,7 +157,7 @@ __device__ __forceinline__ void conv_mfma(const u16* src, const u16* __restrict_
         const int p = min(pix, M - 1);
         const int py = p / HDST, px = p % HDST;
         // the pixel's own source position; taps add compile-time offsets
-        const u16* sp = src + (py * HSRC + px) * CIN + (CIN == 32 ? 8 * g : 0);
+        const u16* sp = src + (py * HSRC + px) * (CIN == 32 ? PS : CIN) + (CIN == 32 ? 8 * g : 0);
         f32x4 acc[NT];
 #pragma unroll
         for (int nt = 0; nt < NT; nt++) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -172,9 +174,9 @@ __device__ __forceinline__ void conv_mfma(const u16* src, const u16* __restrict_
                     ok = sy >= 0 && sy < HSRC && sx >= 0 && sx < HSRC;
                 }
                 if (!FULL) {
-                    a = *(const bf16x8*)(sp + (dy * HSRC + dx) * 32);
+                    a = *(const bf16x8*)(sp + (dy * HSRC + dx) * PS);
                 } else if (ok) {
-                    a = *(const bf16x8*)(src + (sy * HSRC + sx) * 32 + 8 * g);
+                    a = *(const bf16x8*)(src + (sy * HSRC + sx) * PS + 8 * g);
                 } else {
 #pragma unroll
                     for (int j = 0; j < 8; j++) a[j] = (__bf16)0.0f;
@@ -204,20 +206,23 @@ __device__ __forceinline__ void conv_mfma(const u16* src, const u16* __restrict_
 
 // Forward layer l (0..3) of the network from LDS src to LDS dst (layers
 // 0-2, ReLU, BF16) and, when `save` is set, to the saved activations.
-template <int L>
+// PSS / PSD: pixel strides (elements) of src and dst in LDS; the saved
+// activations are always packed (32 per pixel).
+template <int L, int PSS = 32, int PSD = 32>
 __device__ __forceinline__ void hidden_layer(const u16* src, u16* dst, const u16* __restrict__ packed,
                                              const float* __restrict__ prm, u16* save, u16* wl,
                                              unsigned rows = ~0u)
 {
     const float* bias = prm + OFF_B[L];
-    conv_mfma<HS[L], HS[L + 1], CI[L], FKS[L], FNT[L], false>(
-        src, packed + FOFF[L], wl, [&](int pix, int n0, f32x4 v) {
-            const float4 bb = *(const float4*)(bias + n0);
-            const uint2 h = make_uint2(pack_bf16(fmaxf(v[0] + bb.x, 0.f), fmaxf(v[1] + bb.y, 0.f)),
-                                       pack_bf16(fmaxf(v[2] + bb.z, 0.f), fmaxf(v[3] + bb.w, 0.f)));
-            *(uint2*)(dst + pix * 32 + n0) = h;
-            if (save) *(uint2*)(save + pix * 32 + n0) = h;
-        }, rows);
+    auto epi = [&](int pix, int n0, f32x4 v) {
+        const float4 bb = *(const float4*)(bias + n0);
+        const uint2 h = make_uint2(pack_bf16(fmaxf(v[0] + bb.x, 0.f), fmaxf(v[1] + bb.y, 0.f)),
+                                   pack_bf16(fmaxf(v[2] + bb.z, 0.f), fmaxf(v[3] + bb.w, 0.f)));
+        *(uint2*)(dst + pix * PSD + n0) = h;
+        if (save) *(uint2*)(save + pix * 32 + n0) = h;
+    };
+    conv_mfma<HS[L], HS[L + 1], CI[L], FKS[L], FNT[L], false, decltype(epi), PSS>(
+        src, packed + FOFF[L], wl, epi, rows);
 }
 
 // ---------------------------------------------------------------------------
@@ -742,6 +747,7 @@ __global__ void k_targets(const InstDev* __restrict__ ic, const void* Ac,
 constexpr int kMaxInstLds = 4096;   // instances whose tile offsets fit in LDS
 constexpr int kFwdFrag = FOFF[3] + 9 * 512;
 constexpr int kCorrThreads = 768;   // twelve waves: three per SIMD
+constexpr int kPadPix = 40;         // LDS elements per activation pixel in k_correct
 
 template <typename T>
 __global__ __launch_bounds__(kCorrThreads) void k_correct(const InstDev* __restrict__ insts, int n_inst,
@@ -753,8 +759,11 @@ __global__ __launch_bounds__(kCorrThreads) void k_correct(const InstDev* __restr
                                                  const uint8_t* __restrict__ flags,
                                                  const float* __restrict__ pscale)
 {
-    __shared__ __align__(16) u16 bx[20 * 20 * 32];
-    __shared__ __align__(16) u16 by[22 * 22 * 32];
+    // activations with each pixel's 32 channels padded to kPadPix elements
+    // (80 bytes), so that the 16 pixels of an MFMA operand read, and the
+    // epilogue's 8-byte stores, fall on distinct LDS banks
+    __shared__ __align__(16) u16 bx[20 * 20 * kPadPix];
+    __shared__ __align__(16) u16 by[22 * 22 * kPadPix];
     __shared__ __align__(16) u16 wf[kFwdFrag];
     __shared__ int first[kMaxInstLds + 1];   // first[j]: band tiles of instances < j
     __shared__ __align__(16) u16 pin[2][kPatch * kPatch * 4];   // input patches, double buffered
@@ -851,15 +860,15 @@ __global__ __launch_bounds__(kCorrThreads) void k_correct(const InstDev* __restr
         const unsigned m2 = (m3 | m3 << 1 | m3 << 2) & 0xfffffu;
         const unsigned m1 = (m2 | m2 << 1 | m2 << 2) & 0x3fffffu;
         if (m4) {
-            hidden_layer<0>(pin[cur], by, wf, prm, nullptr, nullptr, m1);
+            hidden_layer<0, 32, kPadPix>(pin[cur], by, wf, prm, nullptr, nullptr, m1);
             __syncthreads();
-            hidden_layer<1>(by, bx, wf, prm, nullptr, nullptr, m2);
+            hidden_layer<1, kPadPix, kPadPix>(by, bx, wf, prm, nullptr, nullptr, m2);
             __syncthreads();
-            hidden_layer<2>(bx, by, wf, prm, nullptr, nullptr, m3);
+            hidden_layer<2, kPadPix, kPadPix>(bx, by, wf, prm, nullptr, nullptr, m3);
             __syncthreads();
             const float* b4 = prm + OFF_B[3];
             T* base = A + I.lat_off;
-            conv_mfma<18, 16, 32, 9, 1, false>(by, wf + FOFF[3], nullptr, [&](int pix, int n0, f32x4 v) {
+            auto epi4 = [&](int pix, int n0, f32x4 v) {
                 if (n0 >= 9) return;
                 const int oy = pix / kOut, ox = pix % kOut;
                 const int q = (oy + kHalo) * kPatch + ox + kHalo;
@@ -881,7 +890,9 @@ __global__ __launch_bounds__(kCorrThreads) void k_correct(const InstDev* __restr
                     T* p = base + c * I.plane + (long long)y * I.pitch + x;
                     Store<T>::st(p, Store<T>::ld(p, I.scale) + os * (v[j] + b4[c]), I.inv_scale);
                 }
-            }, m4);
+            };
+            conv_mfma<18, 16, 32, 9, 1, false, decltype(epi4), kPadPix>(by, wf + FOFF[3], nullptr,
+                                                                        epi4, m4);
         }
         if (kn < total) stage(cur ^ 1);
         cur ^= 1;

@@ -268,6 +268,110 @@ def evaluate(net, sc: LN.Scales, seeds, L: int = 256, n_markers: int = 512, chec
     return res
 
 
+def _split_divfree(u, v):
+    """Divergence-free part of a periodic 2-D field (Helmholtz split by FFT)."""
+    k = np.fft.fftfreq(u.shape[0]) * 2 * np.pi
+    ky, kx = np.meshgrid(k, k, indexing="ij")
+    k2 = kx ** 2 + ky ** 2
+    k2[0, 0] = 1.0
+    U, V = np.fft.fft2(u), np.fft.fft2(v)
+    dv = kx * U + ky * V
+    return u - np.real(np.fft.ifft2(kx * dv / k2)), v - np.real(np.fft.ifft2(ky * dv / k2))
+
+
+def ceiling(net, sc: LN.Scales, seeds, alphas=(1.0, 0.1), checkpoints=(250, 500, 1000, 2000)):
+    """What a correction of this form can reach, on held-out seeds: the plain
+    coarse run, the exact targets of the fine run applied every coarse step
+    on the band (|sd| <= 4) and on the whole lattice, and the network at each
+    alpha; at every checkpoint the relative L2 velocity error against the
+    fine run, split into its curl-free (acoustic) and divergence-free parts
+    (each over the norm of the whole fine field)."""
+    import torch
+    seeds = list(seeds)
+    n = len(seeds)
+    pairs = [W.learned_pair_c5(s) for s in seeds]
+    mk = lambda k: B.Sim([p[k].problem for p in pairs], [p[k].X0 for p in pairs])
+    sf, sp, sb, sw = mk(1), mk(0), mk(0), mk(0)
+    nets = {}
+    for a in alphas:
+        s = mk(0)
+        s.set_isolation(True)
+        bd = LN.Band(s)
+        bd.attach(net, LN.make_scales(list(sc.in_scale), sc.out_scale * a))
+        nets[a] = (s, bd)
+    unit = LN.make_scales(IN_SCALE, 1.0)
+    bb, bw = LN.Band(sb), LN.Band(sw)
+    tx, ty = np.meshgrid(np.arange(16), np.arange(16))
+    every = np.stack([tx.ravel(), ty.ravel()], 1).astype(np.int32).ravel()
+    bw.tiles.copy_(torch.tensor(np.tile(every, n), dtype=torch.int32, device=bw.tiles.device))
+    bw.count.fill_(256)
+
+    def errs(s, j, ref, rs, ok=True):
+        g = s.fields(B.F_UX | B.F_UY, inst=j)
+        if not ok or not np.isfinite(g).all():
+            return (float("nan"),) * 3
+        d = g - ref
+        gs = _split_divfree(g[0], g[1])
+        nrm = np.sqrt((ref ** 2).sum())
+        sol = np.sqrt(((gs[0] - rs[0]) ** 2 + (gs[1] - rs[1]) ** 2).sum()) / nrm
+        tot = np.sqrt((d ** 2).sum()) / nrm
+        return float(tot), float(np.sqrt(max(tot ** 2 - sol ** 2, 0.0))), float(sol)
+
+    names = ["plain", "exact_band", "exact_whole"] + [f"net_alpha_{a}" for a in alphas]
+    res = {"seeds": seeds, "kappa": [c.problem.kappa for c, _ in pairs],
+           "tau": [c.problem.tau for c, _ in pairs], "checkpoints": list(checkpoints),
+           "runs": {k: {"total": [], "curl_free": [], "div_free": []} for k in names}}
+    step = 0
+    for cp in checkpoints:
+        while step < cp:
+            sf.step(FINE_PER_COARSE)
+            for s in (sp, sb, sw):
+                s.step(1)
+            for s, _ in nets.values():
+                s.step(1)
+            bb.find()
+            bb.patches(unit)
+            tg, _ = bb.targets(sf, unit)
+            bb.apply(tg, unit)
+            bw.patches(unit)
+            bw.flags |= 2                       # every node of every tile
+            tg, _ = bw.targets(sf, unit)
+            bw.apply(tg, unit)
+            step += 1
+        bits = {a: s.instance_errors() for a, (s, _) in nets.items()}
+        rows = {k: [] for k in names}
+        for j in range(n):
+            ref = 2.0 * sf.fields(B.F_UX | B.F_UY, inst=j)[:, ::2, ::2]
+            rs = _split_divfree(ref[0], ref[1])
+            rows["plain"].append(errs(sp, j, ref, rs))
+            rows["exact_band"].append(errs(sb, j, ref, rs))
+            rows["exact_whole"].append(errs(sw, j, ref, rs))
+            for a, (s, _) in nets.items():
+                rows[f"net_alpha_{a}"].append(errs(s, j, ref, rs, bits[a][j] == 0))
+        for k in names:
+            arr = np.array(rows[k])
+            for q, key in enumerate(("total", "curl_free", "div_free")):
+                res["runs"][k][key].append(arr[:, q].tolist())
+        log(f"ceiling, coarse step {cp}: " + "; ".join(
+            f"{k} {np.nanmedian(np.array(rows[k])[:, 0]) if np.isfinite(np.array(rows[k])[:, 0]).any() else float('nan'):.4f}"
+            for k in names))
+    for s in [sf, sp, sb, sw] + [s for s, _ in nets.values()]:
+        s.close()
+    summ = {}
+    for k in names:
+        r = res["runs"][k]
+        summ[k] = {}
+        for key in ("total", "div_free"):
+            fin = np.array(r[key][-1])
+            summ[k][key] = {
+                "median": [float(np.nanmedian(x)) if np.isfinite(x).any() else None for x in map(np.array, r[key])],
+                "p95_at_end": float(np.nanpercentile(fin, 95)) if np.isfinite(fin).any() else None,
+                "frac_within_1e-2_at_end": float((fin <= 1e-2).mean()),
+                "finite_at_end": int(np.isfinite(fin).sum())}
+    res["summary"] = summ
+    return res
+
+
 def main(argv=None) -> int:
     import torch
     ap = argparse.ArgumentParser()
@@ -292,6 +396,10 @@ def main(argv=None) -> int:
     ap.add_argument("--dagger-alpha", type=float, default=0.1)
     ap.add_argument("--eval-only", default=None, metavar="NPZ",
                     help="skip data generation and training; evaluate these weights")
+    ap.add_argument("--ceiling", default=None, metavar="JSON",
+                    help="with --eval-only: run the ceiling study on the held-out seeds (exact "
+                         "band and whole-lattice targets, the network at each --alpha, errors "
+                         "split into curl-free and divergence-free parts) and write it here")
     a = ap.parse_args(argv)
     B.load()
     LN.lib()
@@ -333,6 +441,12 @@ def main(argv=None) -> int:
                                   "teacher": a.teacher}))
         log(f"saved {a.out}")
     held = list(W.LEARNED_HELDOUT_SEEDS)[:a.heldout]
+    if a.ceiling:
+        res = ceiling(net, sc, held, alphas=tuple(a.alpha))
+        with open(a.ceiling, "w") as fh:
+            json.dump(res, fh)
+        log(json.dumps(res["summary"]))
+        return 0
     teacher = a.teacher
     if a.eval_only:
         teacher = bool(json.loads(str(d["meta"])).get("teacher", False)) if "meta" in d else False
