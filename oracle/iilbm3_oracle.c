@@ -605,6 +605,24 @@ static int run_surface_ud(const or3_problem *p, double *f, int nv, double *X, in
                         for (int k = 0; k < 3; k++) g[k * n + c] += Gt[3 * v + k] * wgt;
                     }
         }
+        /* IB-LBM membrane (reading R18, as in two dimensions): the vertices
+         * move with the velocity of the distributions after the step's force,
+         * u + g, so the spread force and the body force join U_v */
+        if (law == 2)
+            for (int v = 0; v < nv; v++) {
+                const double X0 = X[3 * v], Y0 = X[3 * v + 1], Z0 = X[3 * v + 2];
+                const int x0 = (int)floor(X0) - 1, y0 = (int)floor(Y0) - 1, z0 = (int)floor(Z0) - 1;
+                double acc[3] = {p->body[0], p->body[1], p->body[2]};
+                for (int dz = 0; dz < 4; dz++)
+                    for (int dy = 0; dy < 4; dy++)
+                        for (int dx = 0; dx < 4; dx++) {
+                            const double wgt = peskin(x0 + dx - X0) * peskin(y0 + dy - Y0) * peskin(z0 + dz - Z0);
+                            const long c = ((long)wrap(z0 + dz, p->nz) * p->ny + wrap(y0 + dy, p->ny)) * p->nx +
+                                           wrap(x0 + dx, p->nx);
+                            for (int k = 0; k < 3; k++) acc[k] += g[k * n + c] * wgt;
+                        }
+                for (int k = 0; k < 3; k++) U[3 * v + k] += acc[k];
+            }
         const long nl = law == 2 ? 0 : or3_mesh_links(p, nv, X, nt, tri, jp, rec, val, cap);
         if (nl < 0) { rc = -1; break; }
         step_with_field(p, f, g);

@@ -644,6 +644,37 @@ __global__ void k_memb_spread3(Box b, const double* __restrict__ X, const double
     atomicAdd(&g[2 * n + c], Gt[3 * v + 2] * w);
 }
 
+// IB-LBM membrane (law 2): the vertices move with the velocity of the
+// distributions after the step's force, so the spread force g (and the
+// uniform body force) interpolated at each vertex joins U_v; one wave per
+// vertex, one lane per stencil node.
+__global__ __launch_bounds__(256) void k_memb_addg3(Box b, const double* __restrict__ X, int nv,
+                                                    const double* __restrict__ g, double bx, double by,
+                                                    double bz, double* __restrict__ U, const int* err)
+{
+    const int v = blockIdx.x * 4 + threadIdx.x / 64;
+    const int lane = threadIdx.x % 64;
+    if (v >= nv || memb_failed(err)) return;
+    const double X0 = X[3 * v], Y0 = X[3 * v + 1], Z0 = X[3 * v + 2];
+    const int x = (int)floor(X0) - 1 + (lane & 3), y = (int)floor(Y0) - 1 + ((lane >> 2) & 3),
+              z = (int)floor(Z0) - 1 + (lane >> 4);
+    const double w = peskin1(x - X0) * peskin1(y - Y0) * peskin1(z - Z0);
+    const long long n = (long long)b.nx * b.ny * b.nz;
+    const long long c = ((long long)z * b.ny + y) * b.nx + x;
+    double gx = g[c] * w, gy = g[n + c] * w, gz = g[2 * n + c] * w;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        gx += __shfl_xor(gx, o, 64);
+        gy += __shfl_xor(gy, o, 64);
+        gz += __shfl_xor(gz, o, 64);
+    }
+    if (lane == 0) {
+        U[3 * v] += gx + bx;
+        U[3 * v + 1] += gy + by;
+        U[3 * v + 2] += gz + bz;
+    }
+}
+
 // One block: F = -sum G_v + V_s (U - Uprev), T = -sum r_v x G_v +
 // (I_s / rho*) (W - Wprev) over the vertices (a fixed reduction order), then
 // the update of Sec. 2.3: a = F / m, U += a, c += U + (a_old + a) / 2,
@@ -842,7 +873,12 @@ static void memb_before_sweep(ii_lbm3_handle* h, const float* A)
                        (const Body3*)h->body3, h->memb_err);
     hipLaunchKernelGGL(k_memb_spread3, dim3((unsigned)(((long long)nv * 64 + 255) / 256)), dim3(256), 0, h->stream,
                        b, h->memb_X, h->memb_Gt, nv, h->g, h->memb_err);
-    if (h->memb_law == 2) return;                                 // IB-LBM: no jumps
+    if (h->memb_law == 2) {                                       // IB-LBM: no jumps
+        hipLaunchKernelGGL(k_memb_addg3, dim3((nv + 3) / 4), dim3(256), 0, h->stream, b,
+                           (const double*)h->memb_X, nv, (const double*)h->g, b.g[0], b.g[1],
+                           b.g[2], h->memb_U, (const int*)h->memb_err);
+        return;
+    }
     hipLaunchKernelGGL(k_zero_count3, dim3(1), dim3(1), 0, h->stream, h->memb_count);
     hipLaunchKernelGGL(k_mesh_links3, dim3((nt + kMeshWaves - 1) / kMeshWaves), dim3(256), 0, h->stream,
                        h->memb_S, h->memb_tri, h->memb_jp, nt, h->memb_rec, h->memb_cap, h->memb_count,

@@ -451,3 +451,30 @@ def test_trained_network_gains_over_no_correction(mods):
     _say(f"held-out seeds {held[0]}..{held[-1]}: one-step band loss network {l_net:.4e} "
          f"vs no correction {l_zero:.4e}")
     assert l_net < 0.7 * l_zero
+
+
+def test_ceiling_gap_is_acoustic_and_band_bound(mods):
+    # The ceiling study on 16 held-out seeds to coarse step 1000: the plain
+    # coarse run's error against the fine run is at least 95 % curl-free
+    # (acoustic) in energy; the exact targets applied every step on the band
+    # leave it above 1e-2, on the whole lattice below.  This is why the
+    # learned band correction cannot reach a 1e-2 rollout (measured on 200
+    # seeds: 16.7 % / 8.9 % / 0.08 % medians at step 1000).
+    import os
+    _, LN = mods
+    from paper_2003_12186_amd import train_learned as TL
+    d = np.load(os.path.join(os.path.dirname(LN.__file__), "data", "cnn_c5.npz"))
+    net = LN.Net(d["params"])
+    sc = LN.make_scales(d["in_scale"], float(d["out_scale"]))
+    held = list(W.LEARNED_HELDOUT_SEEDS)[:16]
+    res = TL.ceiling(net, sc, held, alphas=(0.1,), checkpoints=(500, 1000))
+    r = res["runs"]
+    tot = np.array(r["plain"]["total"][-1])
+    div = np.array(r["plain"]["div_free"][-1])
+    band = np.median(r["exact_band"]["total"][-1])
+    whole = np.median(r["exact_whole"]["total"][-1])
+    share = np.median(div ** 2 / tot ** 2)
+    _say(f"16 held-out seeds, coarse step 1000: plain {np.median(tot):.4f} (divergence-free energy "
+         f"share {share:.4f}), exact band {band:.4f}, exact whole lattice {whole:.2e}")
+    assert share < 0.05
+    assert whole < 1e-2 < band < np.median(tot)
