@@ -486,33 +486,57 @@ struct TileShared {
     float wx[kTileCap][4], wy[kTileCap][4];
     int2 f0[kTileCap];
     double gtx[kTileCap], gty[kTileCap];
-    long long acc[8][kTileNodes];   // jump sums of the eight outgoing populations per node
+    int acc[8][kTileNodes];      // jump sums of the eight outgoing populations per node
     unsigned rec[REC ? kTileRec : 1];   // packed (node, direction, chord) of each cut link
     int cnt, total, nrec, base;
+    unsigned jmax;               // bits of the largest |[[p]]| at the tile's chords' ends
 };
 
 // [[f_i]] of one cut link into the node's accumulator: sigma w_i [[p]] / c_s^2
 // (Sec. 3.1, Eq. (32); Sec. 3.2, Eq. (47)).  A link cut by several chords
 // (a wrinkled membrane) gets one term per crossing.  The sums are kept in
-// 64-bit fixed point with 2^-56 resolution, so that they are exact and do not
-// depend on the order in which the threads add their crossings; a term is at
-// most 64 in magnitude (a pressure jump of 576 lattice units), and a
-// non-finite one marks the instance unstable.
+// fixed point, so that they are exact and do not depend on the order in which
+// the threads add their crossings; a non-finite term marks the instance
+// unstable.
+//  - The membrane and rigid tile pass sums in 32 bits at a power-of-two scale
+//    of its own: each term is at most (max |[[p]]| over the tile's chord ends)
+//    w_1 / c_s^2, which the scale maps to at most 2^27 (sixteen crossings of
+//    one link fit in an int), so a term keeps at least 27 bits relative to
+//    the tile's largest, finer than the FP32 correction slot it ends in.
+//  - The spline tile pass (whose [[p]] comes from the spline) sums in 64 bits
+//    at 2^-56 resolution, terms clamped to 64 in magnitude.
 constexpr double kJumpFix = 72057594037927936.0;   // 2^56
 
 template <class TS>
-__device__ __forceinline__ void add_jump(TS& S, int node, int i, int sigma, double jpc, int* err)
+__device__ __forceinline__ void add_jump(TS& S, int node, int i, int sigma, double jpc, int* err,
+                                         double scale = kJumpFix)
 {
     const double v = (double)sigma * WD[i] * jpc / kCs2;
     if (!isfinite(v)) {
         atomicOr(err, (int)kErrUnstable);
         return;
     }
-    const long long q = __double2ll_rn(fmin(fmax(v, -64.0), 64.0) * kJumpFix);
-    atomicAdd((unsigned long long*)&S.acc[i - 1][node], (unsigned long long)q);
+    if constexpr (sizeof(S.acc[0][0]) == 8) {
+        const long long q = __double2ll_rn(fmin(fmax(v, -64.0), 64.0) * kJumpFix);
+        atomicAdd((unsigned long long*)&S.acc[i - 1][node], (unsigned long long)q);
+    } else {
+        const double b = 134217728.0;   // 2^27
+        atomicAdd(&S.acc[i - 1][node], __double2int_rn(fmin(fmax(v * scale, -b), b)));
+    }
 }
 
 __device__ __forceinline__ double jump_sum(long long acc) { return (double)acc * (1.0 / kJumpFix); }
+__device__ __forceinline__ double jump_sum(int acc, double scale) { return (double)acc / scale; }
+
+// The power of two that maps the tile's largest jump term to at most 2^27.
+__device__ __forceinline__ double jump_scale(unsigned jmax_bits)
+{
+    const float jm = __uint_as_float(jmax_bits) * (float)(WD[1] / kCs2);
+    if (!(jm > 0.f) || !isfinite(jm)) return 1.0;
+    int e;
+    frexpf(jm, &e);                 // jm < 2^e
+    return ldexp(1.0, 27 - e);
+}
 
 template <class TS>
 __device__ __forceinline__ void stage_record(TS& S, int node, int i, int j)
@@ -543,6 +567,7 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
         if (tid == 0) {
             S.cnt = min(P.tile_count[gt], kTileCap);
             S.nrec = 0;
+            S.jmax = 0u;
         }
 #pragma unroll
         for (int i = 0; i < 8; i++) S.acc[i][tid] = 0;
@@ -574,8 +599,11 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
             }
             g = I.jumps ? P.Gt[mk] : P.G[mk];
             for (int m = 0; m < c; m++) r += (S.raw[m] < k) ? 1 : 0;
+            // |[[p]]| bits order as the values for non-negative floats
+            atomicMax(&S.jmax, __float_as_uint((float)fmax(fabs(jpa), fabs(jpb))));
         }
         __syncthreads();   // raw is reused as start below
+        const double jscale = jump_scale(S.jmax);
         if (tid < c) {
             S.key[r] = k;
             const long long ax = (long long)rint(a0.x * kSnap), ay = (long long)rint(a0.y * kSnap);
@@ -644,7 +672,8 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
                     int sg;
                     double qq, th;
                     if (!link_crossing<false>(x, y, i, ch, oP, sP, sg, qq, th)) continue;
-                    add_jump(S, node, i, sg, (1.0 - th) * S.jpa[j] + th * S.jpb[j], P.err + I.inst);
+                    add_jump(S, node, i, sg, (1.0 - th) * S.jpa[j] + th * S.jpb[j], P.err + I.inst,
+                             jscale);
                     if constexpr (REC) stage_record(S, node, i, j);
                 }
             }
@@ -688,7 +717,7 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
                     rigid_cut(I, ccx, ccy, th0, x, y, i, inP, q, th, k);
                     const double jpc =
                         (1.0 - th) * P.jp[I.mk_off + k] + th * P.jp[I.mk_off + (k + 1) % N];
-                    add_jump(S, tid, i, inP ? 1 : -1, jpc, P.err + I.inst);
+                    add_jump(S, tid, i, inP ? 1 : -1, jpc, P.err + I.inst, jscale);
                     if constexpr (REC) stage_record(S, tid, i, 0);
                 }
             }
@@ -706,7 +735,7 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
             for (int i = 1; i < 9; i++) {
                 const double delta =
                     valid ? fs * WD[i] * ((double)EX[i] * gx + (double)EY[i] * gy) +
-                                jump_sum(S.acc[i - 1][tid])
+                                jump_sum(S.acc[i - 1][tid], jscale)
                           : 0.0;
                 cr[(i - 1) * kTileNodes] = (float)delta;
             }

@@ -128,7 +128,9 @@ def test_diag_matches_oracle_cylinder_channel(B):
     assert abs(d["mass"] - rho.sum()) < 1e-4 * rho.size ** 0.5
     assert abs(d["momentum"][0] - ux.sum()) < 1e-6 * abs(ux.sum())
     assert abs(d["momentum"][1] - uy.sum()) < 1e-6 * abs(ux.sum())
-    assert np.allclose(d["force"], fh[-1], rtol=1e-5, atol=1e-12)
+    # the force bar of the channel parity tests: 1e-5 of the force's magnitude
+    # (the lift is 200 times smaller than the drag)
+    assert np.abs(np.array(d["force"]) - fh[-1]).max() <= 1e-5 * np.abs(fh[-1]).max()
     assert d["n_in"] == int(ins.sum()) and d["n_out"] == int(out.sum())
     # no node of the D = 4 circle lies 3 lu inside it: no interior pressure
     assert d["n_in"] == 0 and math.isnan(d["p_in"])
