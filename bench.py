@@ -1186,10 +1186,9 @@ def main() -> int:
     ap.add_argument("--geometry", choices=["polygon", "spline"], default="polygon",
                     help="membrane representation: the polygon through the markers (the bench "
                          "line) or the cubic spline")
-    ap.add_argument("--math", choices=["fp32", "fp64"], default=None,
-                    help="collision arithmetic (storage keeps its own precision); default FP64 "
-                         "for FP32 storage (its 1e-6 parity bar) and FP32 for FP16 storage "
-                         "(1e-3 bar)")
+    ap.add_argument("--math", choices=["fp32", "fp64"], default="fp32",
+                    help="collision arithmetic (storage keeps its own precision); FP32 by "
+                         "default, at the 1e-6 parity bar with FP32 storage and 1e-3 with FP16")
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--workload", choices=["membrane", "batch512", "learned", "cylinder", "area",
                                            "table1", "viv", "cyltables", "d3q19", "boundaries"],
@@ -1236,8 +1235,6 @@ def main() -> int:
     args = ap.parse_args()
     if args.steps is None:
         args.steps = {"batch512": 4000, "cylinder": 20000, "viv": 150000}.get(args.workload, 2000)
-    if args.math is None:
-        args.math = "fp32" if args.storage == "fp16" else "fp64"
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the design notes describe how the lattice would shard).", file=sys.stderr)

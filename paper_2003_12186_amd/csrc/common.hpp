@@ -211,12 +211,32 @@ struct Lat<double> {
     static __device__ __forceinline__ double w(int i) { return WD[i]; }
 };
 
+// Odd part of the D2Q9 equilibrium, w_i 3 e_i.u: u/3 on the axes and
+// (+-ux +- uy)/12 on the diagonals.  The axis parts are rounded first; the
+// remainders u - 2 a are then exact (their operands are within a factor of
+// two of each other), and the diagonal parts close the momentum, which is u
+// up to the rounding of the two sums alone.  Nothing here adds a constant
+// to values on a common rounding grid, so the rounding has no bias: with the
+// axis parts closing the momentum instead (u/2 minus the rounded diagonal
+// parts), FP32 collisions lose momentum at a fixed relative rate of ~5e-9
+// per step, ~1e-5 of the velocity after 1000 steps.
+template <typename M>
+__device__ __forceinline__ void odd_part(M ux, M uy, M& a1, M& a2, M& a5, M& a6)
+{
+    const M c3 = (M)(1.0 / 3.0);
+    a1 = c3 * ux;
+    a2 = c3 * uy;
+    const M rx = ux - (M)2 * a1, ry = uy - (M)2 * a2;
+    a5 = (M)0.25 * (rx + ry);
+    a6 = (M)0.25 * (ry - rx);
+}
+
 // Deviation of the He-Luo incompressible equilibrium (Sec. 2.2.1),
 // f_eq_i - w_i rho0 = w_i [ drho + 3 e.u + 4.5 (e.u)^2 - 1.5 u.u ], written so
 // that its zeroth and first moments are drho and u up to unbiased rounding:
-// the rest population takes drho minus the others, and the axis populations'
-// odd part takes u/2 minus the diagonal ones'.  (With rounded weights the
-// plain form changes the momentum by a fixed relative 1e-8 every step.)
+// the rest population takes drho minus the others, and the odd part closes
+// the momentum (odd_part).  (With rounded weights the plain form changes the
+// momentum by a fixed relative 1e-8 every step.)
 template <typename M>
 __device__ __forceinline__ void equilibrium(M r, M ux, M uy, M e[9])
 {
@@ -228,9 +248,8 @@ __device__ __forceinline__ void equilibrium(M r, M ux, M uy, M e[9])
         s[i] = Lat<M>::w(i) * (r + (M)4.5 * eu * eu - (M)1.5 * uu);
     }
     s[0] = r - (((s[1] + s[2]) + (s[3] + s[4])) + ((s[5] + s[6]) + (s[7] + s[8])));
-    const M c12 = (M)(1.0 / 12.0);
-    const M a5 = c12 * (ux + uy), a6 = c12 * (uy - ux);
-    const M a1 = (M)0.5 * ux - (a5 - a6), a2 = (M)0.5 * uy - (a5 + a6);
+    M a1, a2, a5, a6;
+    odd_part<M>(ux, uy, a1, a2, a5, a6);
     e[0] = s[0];
     e[1] = s[1] + a1;
     e[2] = s[2] + a2;
@@ -257,9 +276,8 @@ __device__ __forceinline__ void equilibrium_guo(M r, M jx, M jy, M inv_rho, M e[
         s[i] = Lat<M>::w(i) * (r + ((M)4.5 * ej * ej - (M)1.5 * jj) * inv_rho);
     }
     s[0] = r - (((s[1] + s[2]) + (s[3] + s[4])) + ((s[5] + s[6]) + (s[7] + s[8])));
-    const M c12 = (M)(1.0 / 12.0);
-    const M a5 = c12 * (jx + jy), a6 = c12 * (jy - jx);
-    const M a1 = (M)0.5 * jx - (a5 - a6), a2 = (M)0.5 * jy - (a5 + a6);
+    M a1, a2, a5, a6;
+    odd_part<M>(jx, jy, a1, a2, a5, a6);
     e[0] = s[0];
     e[1] = s[1] + a1;
     e[2] = s[2] + a2;
@@ -352,25 +370,19 @@ __device__ __forceinline__ void gather(const InstDev& I, const T* __restrict__ A
 // ---------------------------------------------------------------------------
 // Collision with the simple force term (Sec. 2.2.1 Eq. (14)/(15), Sec. 2.2.2
 // Eq. (16)); in deviation form the constant w_i rho0 drops out of both.
+// The force term and the interface correction x (x[0] = 0; zero away from
+// the interface) join the relaxation increment before the increment is added
+// to d, so that d takes one rounding.  Added on its own, a uniform force
+// would moreover be rounded the same way at every node (d and d_eq share a
+// grid, and omega (d_eq - d) is then a multiple of a fixed fraction of it), a
+// bias that builds up step by step.
 // ---------------------------------------------------------------------------
 template <typename M>
-__device__ __forceinline__ void force_term(M d[9], M gx, M gy)
+__device__ __forceinline__ M force_term(int i, M gx, M gy)
 {
-#pragma unroll
-    for (int i = 1; i < 9; i++)
-        d[i] += (M)3 * Lat<M>::w(i) * ((M)EX[i] * gx + (M)EY[i] * gy);
+    return i == 0 ? (M)0 : (M)3 * Lat<M>::w(i) * ((M)EX[i] * gx + (M)EY[i] * gy);
 }
 
-template <typename M>
-__device__ __forceinline__ void collide_srt(M d[9], M omega, M gx, M gy)
-{
-    M r, ux, uy, e[9];
-    moments<M>(d, r, ux, uy);
-    equilibrium<M>(r, ux, uy, e);
-#pragma unroll
-    for (int i = 0; i < 9; i++) d[i] = d[i] + omega * (e[i] - d[i]);
-    force_term<M>(d, gx, gy);
-}
 
 // D2Q9 moment basis of Lallemand & Luo in the order (rho, e, eps, jx, qx, jy,
 // qy, pxx, pxy), and the inverse row norms.
@@ -392,7 +404,7 @@ constexpr double MBN[9] = {1.0 / 9.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 6.0, 1.0 / 1
 // relax, and the integer basis keeps the correction free of any density or
 // momentum.
 template <typename M>
-__device__ __forceinline__ void collide_mrt(M d[9], const float s[9], M gx, M gy)
+__device__ __forceinline__ void collide_mrt(M d[9], const float s[9], M gx, M gy, const M x[9])
 {
     M r, ux, uy, e[9];
     moments<M>(d, r, ux, uy);
@@ -415,9 +427,45 @@ __device__ __forceinline__ void collide_mrt(M d[9], const float s[9], M gx, M gy
 #pragma unroll
         for (int a = 0; a < 9; a++)
             if (MB[a][i] != 0 && a != 0 && a != 3 && a != 5) acc += (M)MB[a][i] * m[a];
-        d[i] = d[i] - acc;
+        d[i] = d[i] + ((force_term<M>(i, gx, gy) - acc) + x[i]);
     }
-    force_term<M>(d, gx, gy);
+}
+
+// SRT, d* = d + omega (d_eq - d).  With FP64 arithmetic it is evaluated
+// directly.  With FP32 arithmetic the computed density and velocity, and so
+// d_eq, carry roundings of the size of d's own, and the direct form would
+// change the momentum by omega times that rounding at every node and step:
+// after 1000 steps a velocity error several times that of the storage
+// rounding alone.  The FP32 form therefore takes the density and momentum
+// that d - d_eq still holds (the rounding residue, exactly zero in exact
+// arithmetic) and removes them as the equilibrium-shaped w_i (r + 3 e_i.j):
+// the increment then changes density and momentum only by roundings at the
+// increment's own, much finer, scale.  RESIDUE = false skips that step where
+// FP16 storage rounds every value far more coarsely anyway.
+template <typename M, bool RESIDUE = true>
+__device__ __forceinline__ void collide_srt(M d[9], M omega, M gx, M gy, const M x[9])
+{
+    if constexpr (sizeof(M) == 4 && RESIDUE) {
+        M r, ux, uy, e[9], ne[9];
+        moments<M>(d, r, ux, uy);
+        equilibrium<M>(r, ux, uy, e);
+#pragma unroll
+        for (int i = 0; i < 9; i++) ne[i] = d[i] - e[i];
+        M nr, nx, ny;
+        moments<M>(ne, nr, nx, ny);
+#pragma unroll
+        for (int i = 0; i < 9; i++) {
+            const M p = ne[i] - Lat<M>::w(i) * (nr + (M)3 * ((M)EX[i] * nx + (M)EY[i] * ny));
+            d[i] = d[i] + ((force_term<M>(i, gx, gy) - omega * p) + x[i]);
+        }
+    } else {
+        M r, ux, uy, e[9];
+        moments<M>(d, r, ux, uy);
+        equilibrium<M>(r, ux, uy, e);
+#pragma unroll
+        for (int i = 0; i < 9; i++)
+            d[i] = d[i] + ((omega * (e[i] - d[i]) + force_term<M>(i, gx, gy)) + x[i]);
+    }
 }
 
 // Collisions with Guo's force term (Sec. 2.2.2): rho u = J = j + g/2, the
@@ -438,17 +486,7 @@ __device__ __forceinline__ void guo_prepare(const M d[9], M gx, M gy, M e[9], M 
 }
 
 template <typename M>
-__device__ __forceinline__ void collide_guo_srt(M d[9], M omega, M gx, M gy)
-{
-    M e[9], G[9];
-    guo_prepare<M>(d, gx, gy, e, G);
-    const M h = (M)1 - (M)0.5 * omega;
-#pragma unroll
-    for (int i = 0; i < 9; i++) d[i] = d[i] + omega * (e[i] - d[i]) + h * G[i];
-}
-
-template <typename M>
-__device__ __forceinline__ void collide_guo_mrt(M d[9], const float s[9], M gx, M gy)
+__device__ __forceinline__ void collide_guo_mrt(M d[9], const float s[9], M gx, M gy, const M x[9])
 {
     M e[9], G[9];
     guo_prepare<M>(d, gx, gy, e, G);
@@ -474,7 +512,27 @@ __device__ __forceinline__ void collide_guo_mrt(M d[9], const float s[9], M gx, 
 #pragma unroll
         for (int a = 0; a < 9; a++)
             if (MB[a][i] != 0) acc += (M)MB[a][i] * m[a];
-        d[i] = d[i] - acc;
+        d[i] = d[i] + (x[i] - acc);
+    }
+}
+
+// Guo's SRT is Guo's MRT with every rate omega.  With FP32 arithmetic it is
+// evaluated in that moment form, where the density and momentum moments of
+// the increment are set exactly (for the reason given at collide_srt).
+template <typename M>
+__device__ __forceinline__ void collide_guo_srt(M d[9], M omega, M gx, M gy, const M x[9])
+{
+    if constexpr (sizeof(M) == 4) {
+        float rates[9];
+#pragma unroll
+        for (int a = 0; a < 9; a++) rates[a] = omega;
+        collide_guo_mrt<M>(d, rates, gx, gy, x);
+    } else {
+        M e[9], G[9];
+        guo_prepare<M>(d, gx, gy, e, G);
+        const M h = (M)1 - (M)0.5 * omega;
+#pragma unroll
+        for (int i = 0; i < 9; i++) d[i] = d[i] + ((omega * (e[i] - d[i]) + h * G[i]) + x[i]);
     }
 }
 

@@ -7,10 +7,13 @@ namespace iilbm {
 
 // One time step of the bulk: gather f^n at (x, y) (pulled populations that
 // already carry the previous step's jumps and force; extrapolated on bounded
-// sides), collide (SRT or MRT) with the uniform body force, add this step's
+// sides), collide (SRT or MRT) with the uniform body force and this step's
 // interface corrections (tangential force term and jumps of the links this
-// node sends, prepared per 16x16 tile by the interface kernel) and store the
-// result at (x, y): every stored value is rounded exactly once.
+// node sends, prepared per 16x16 tile by the interface kernel) folded into
+// the relaxation increment, and store the result at (x, y).  With FP64
+// collision arithmetic every stored value is rounded exactly once; with FP32
+// arithmetic d takes one rounding and the increment a few at its own, finer,
+// scale.
 // GUO: Guo's force term of the whole Eulerian force (the body force plus the
 // spread force the tile's slot holds in its last two planes); the slot's
 // population planes then hold the jumps alone.
@@ -25,41 +28,36 @@ __device__ __forceinline__ void sweep_node(const InstDev& I, const T* __restrict
         nee<T, M>(I, A, x, y, d);
     else
         pull<T, M>(I, A, x, y, d);
-    if constexpr (GUO) {
-        const float* c = nullptr;
-        M gx = (M)I.body[0], gy = (M)I.body[1];
-        if (I.n_markers > 0) {
-            const int slot = tile_slot[I.tile_off + (y / kTile) * I.tiles_x + (x / kTile)];
-            if (slot >= 0) {
-                c = corr + (long long)slot * kCorrPlanes * kTileNodes + (y % kTile) * kTile + (x % kTile);
-                gx += (M)c[8 * kTileNodes];
-                gy += (M)c[9 * kTileNodes];
-            }
-        }
-        if (COLL == II_LBM_SRT)
-            collide_guo_srt<M>(d, sizeof(M) == 8 ? (M)I.omega_d : (M)I.omega, gx, gy);
-        else
-            collide_guo_mrt<M>(d, I.s, gx, gy);
-        if (c) {
+    // this step's interface correction of the populations the node sends
+    // (zero away from the interface); with Guo's term the slot's last two
+    // planes add the spread force to the body force
+    M xc[9];
 #pragma unroll
-            for (int i = 1; i < 9; i++) d[i] += (M)c[(i - 1) * kTileNodes];
-        }
-        T* base = B + I.lat_off + (long long)y * I.pitch + x;
-#pragma unroll
-        for (int i = 0; i < 9; i++) Store<T>::st_stream(base + i * I.plane, (float)d[i], I.inv_scale);
-        return;
-    }
-    if (COLL == II_LBM_SRT)
-        collide_srt<M>(d, sizeof(M) == 8 ? (M)I.omega_d : (M)I.omega, (M)I.body[0], (M)I.body[1]);
-    else
-        collide_mrt<M>(d, I.s, (M)I.body[0], (M)I.body[1]);
+    for (int i = 0; i < 9; i++) xc[i] = (M)0;
+    M gx = (M)I.body[0], gy = (M)I.body[1];
     if (I.n_markers > 0) {
         const int slot = tile_slot[I.tile_off + (y / kTile) * I.tiles_x + (x / kTile)];
         if (slot >= 0) {
             const float* c = corr + (long long)slot * kCorrPlanes * kTileNodes + (y % kTile) * kTile + (x % kTile);
 #pragma unroll
-            for (int i = 1; i < 9; i++) d[i] += (M)c[(i - 1) * kTileNodes];
+            for (int i = 1; i < 9; i++) xc[i] = (M)c[(i - 1) * kTileNodes];
+            if constexpr (GUO) {
+                gx += (M)c[8 * kTileNodes];
+                gy += (M)c[9 * kTileNodes];
+            }
         }
+    }
+    const M omega = sizeof(M) == 8 ? (M)I.omega_d : (M)I.omega;
+    if constexpr (GUO) {
+        if (COLL == II_LBM_SRT)
+            collide_guo_srt<M>(d, omega, gx, gy, xc);
+        else
+            collide_guo_mrt<M>(d, I.s, gx, gy, xc);
+    } else {
+        if (COLL == II_LBM_SRT)
+            collide_srt<M, sizeof(T) == 4>(d, omega, gx, gy, xc);
+        else
+            collide_mrt<M>(d, I.s, gx, gy, xc);
     }
     T* base = B + I.lat_off + (long long)y * I.pitch + x;
 #pragma unroll
