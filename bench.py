@@ -1116,8 +1116,8 @@ def set_overlap(sim, B, args) -> None:
 
 def bench_batch(args, B, W) -> int:
     """Uneven ensemble: all instances advance through one launch per phase,
-    replayed as HIP graphs; the sweep slice size and instance order come from
-    the autotuner.  The sweep's average duration is taken in a second, event-
+    replayed as HIP graphs; the sweep slice size, the instance order and the
+    tile pass's blocks per CU come from the autotuner.  The sweep's average duration is taken in a second, event-
     timed pass of direct launches over the same state."""
     import numpy as np
     import torch

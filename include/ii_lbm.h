@@ -335,13 +335,35 @@ enum { II_LBM_OVERLAP_SERIAL = 0, II_LBM_OVERLAP_FULL = 1, II_LBM_OVERLAP_INTERP
 int ii_lbm_set_overlap(ii_lbm_handle* h, int32_t mode);
 
 /* Handles with several instances advance them all through one launch per
- * phase and step, driven by work tables.  This autotuner times the batched
- * sweep on the current state (writing only the buffer the next step
- * overwrites) for slices of 128, 256 and 512 nodes and two instance orders
- * (as given, largest first), `trials` launches each, and keeps the fastest.
- * Outputs (may be NULL): the slice size, the order and its time in us.  A
- * single-instance handle reports 0 and keeps its row-segment sweep. */
+ * phase and step, driven by work tables.  This autotuner picks their schedule
+ * on the current state, in two stages:
+ *  1. the batched sweep (writing only the buffer the next step overwrites)
+ *     for slices of 128, 256 and 512 nodes and two instance orders (as
+ *     given, largest first), `trials` launches each;
+ *  2. for membranes, whose interface pass runs beside the sweep, the
+ *     footprint of the tile pass (ii_lbm_set_tile_blocks: 0, 16, 8, 4, 2 and
+ *     1 blocks per CU), timed on `trials` whole steps each.  A step started
+ *     again from the same state recomputes the same results, so the state is
+ *     left as it was.
+ * It keeps the fastest of each.  Outputs (may be NULL): the slice size, the
+ * order and the sweep's time in us (ii_lbm_get_schedule reports the rest).
+ * A single-instance handle reports 0 and keeps its row-segment sweep. */
 int ii_lbm_autotune(ii_lbm_handle* h, int32_t trials, int32_t* unit, int32_t* order, double* best_us);
+
+/* Footprint of a batched handle's tile pass: about per_cu blocks per compute
+ * unit in all (1 ... 64), shared among the instances in proportion to their
+ * estimated interface tiles, each block walking several tiles; 0 (the
+ * initial setting) gives one block per estimated tile.  Results do not
+ * depend on it.  Synchronises the handle; a single-instance handle ignores
+ * it (EINVAL for per_cu outside 0 ... 64). */
+int ii_lbm_set_tile_blocks(ii_lbm_handle* h, int32_t per_cu);
+
+/* The batched schedule in use: sweep slice size, instance order, tile-pass
+ * blocks per CU, and the whole-step time in us that the autotuner measured
+ * for it (0 before ii_lbm_autotune or without its second stage).  Outputs may
+ * be NULL; a single-instance handle reports zeros. */
+int ii_lbm_get_schedule(ii_lbm_handle* h, int32_t* unit, int32_t* order, int32_t* tile_per_cu,
+                        double* step_us);
 
 /* Failure isolation of the instances of a handle.  Instances share no data,
  * so one that becomes non-finite (EUNSTABLE), leaves the lattice (EGEOMETRY)

@@ -60,7 +60,8 @@ EXPORTS = [
     "ii_lbm_state_size",
     "ii_lbm_save_state", "ii_lbm_load_state", "ii_lbm_cutlinks", "ii_lbm_diag",
     "ii_lbm_set_timing", "ii_lbm_get_timing", "ii_lbm_sweep_bytes", "ii_lbm_set_graph",
-    "ii_lbm_set_overlap", "ii_lbm_autotune", "ii_lbm_destroy", "ii_lbm_strerror",
+    "ii_lbm_set_overlap", "ii_lbm_autotune", "ii_lbm_set_tile_blocks", "ii_lbm_get_schedule",
+    "ii_lbm_destroy", "ii_lbm_strerror",
     "ii_lbm_set_isolation", "ii_lbm_instance_errors", "ii_lbm_body",
 ]
 
@@ -106,6 +107,8 @@ def load():
         "ii_lbm_body": [v, i32, v],
         "ii_lbm_set_overlap": [v, i32],
         "ii_lbm_autotune": [v, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(d)],
+        "ii_lbm_set_tile_blocks": [v, i32],
+        "ii_lbm_get_schedule": [v, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(d)],
         "ii_lbm_destroy": [v],
     }
     for name, args in sig.items():
@@ -309,7 +312,21 @@ class Sim:
     def autotune(self, trials: int = 5):
         u = C.c_int32(); o = C.c_int32(); us = C.c_double()
         check(load().ii_lbm_autotune(self.h, int(trials), C.byref(u), C.byref(o), C.byref(us)), "autotune")
-        return {"unit": u.value, "order": o.value, "sweep_us": us.value}
+        out = {"unit": u.value, "order": o.value, "sweep_us": us.value}
+        sch = self.schedule()
+        out["tile_blocks_per_cu"] = sch["tile_blocks_per_cu"]
+        out["step_us"] = sch["step_us"]
+        return out
+
+    def set_tile_blocks(self, per_cu: int) -> None:
+        """Tile-pass blocks per CU of a batched handle (0: one per estimated tile)."""
+        check(load().ii_lbm_set_tile_blocks(self.h, int(per_cu)), "set_tile_blocks")
+
+    def schedule(self) -> dict:
+        u = C.c_int32(); o = C.c_int32(); t = C.c_int32(); us = C.c_double()
+        check(load().ii_lbm_get_schedule(self.h, C.byref(u), C.byref(o), C.byref(t), C.byref(us)),
+              "get_schedule")
+        return {"unit": u.value, "order": o.value, "tile_blocks_per_cu": t.value, "step_us": us.value}
 
     def sweep_bytes(self, inst: int = 0) -> float:
         b = C.c_double()

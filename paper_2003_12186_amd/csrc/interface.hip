@@ -470,9 +470,10 @@ __device__ __forceinline__ void rigid_cut(const InstDev& I, double cx, double cy
 // Tiles.
 // ---------------------------------------------------------------------------
 constexpr int kTileRec = 1024;  // cut links recorded per tile (packed in LDS, then written)
+static_assert(kTileCap <= 256, "chord ranks of a tile are kept in bytes");
 
 // LDS of one tile block: about 24 KB (six blocks share a CU), and 4 KB more
-// with the cut-link record stage.
+// with the cut-link record stage.  kTileCap <= 256 (chord ranks fit a byte).
 template <bool REC>
 struct TileShared {
     union {
@@ -487,6 +488,8 @@ struct TileShared {
     int2 f0[kTileCap];
     double gtx[kTileCap], gty[kTileCap];
     int acc[8][kTileNodes];      // jump sums of the eight outgoing populations per node
+    unsigned char strip[4][kTileCap];   // per wave: chords whose stencil meets its 4 rows
+    int strip_n[4];
     unsigned rec[REC ? kTileRec : 1];   // packed (node, direction, chord) of each cut link
     int cnt, total, nrec, base;
     unsigned jmax;               // bits of the largest |[[p]]| at the tile's chords' ends
@@ -609,12 +612,15 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
             const long long ax = (long long)rint(a0.x * kSnap), ay = (long long)rint(a0.y * kSnap);
             const long long bx = (long long)rint(b0.x * kSnap), by = (long long)rint(b0.y * kSnap);
             S.ch[r].ax = ax; S.ch[r].ay = ay; S.ch[r].bx = bx; S.ch[r].by = by;
-            // any link the chord cuts leaves a node within one spacing of the
-            // chord's box; keep the part of that box inside this tile
-            const int bx0 = max((int)(min(ax, bx) >> 16) - 1, x0);
-            const int bx1 = min((int)(-((-max(ax, bx)) >> 16)) + 1, min(x0 + kTile, I.nx) - 1);
-            const int by0 = max((int)(min(ay, by) >> 16) - 1, y0);
-            const int by1 = min((int)(-((-max(ay, by)) >> 16)) + 1, min(y0 + kTile, I.ny) - 1);
+            // Source nodes of the links the chord can cut.  A link's span in x
+            // is [P.x, P.x + e_x] with the node shifted by the tie-breaking
+            // +eps; it meets the chord's [lo, hi] only if ceil(lo) - 1 <=
+            // P.x <= ceil(hi) (e_x = +1 gives the low end, e_x = -1 the high
+            // one), and likewise in y.  Keep that box's part in this tile.
+            const int bx0 = max((int)(-((-min(ax, bx)) >> 16)) - 1, x0);
+            const int bx1 = min((int)(-((-max(ax, bx)) >> 16)), min(x0 + kTile, I.nx) - 1);
+            const int by0 = max((int)(-((-min(ay, by)) >> 16)) - 1, y0);
+            const int by1 = min((int)(-((-max(ay, by)) >> 16)), min(y0 + kTile, I.ny) - 1);
             S.box[r][0] = (short)bx0; S.box[r][1] = (short)bx1;
             S.box[r][2] = (short)by0; S.box[r][3] = (short)by1;
             S.start[r] = (IFACE == II_LBM_IF_MEMBRANE && I.jumps && bx0 <= bx1 && by0 <= by1)
@@ -630,6 +636,23 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
             S.gtx[r] = g.x; S.gty[r] = g.y;
         }
         __syncthreads();
+
+        // Each wave spreads onto four rows of the tile (y0 + 4 wid ...): list,
+        // in rank order, the chords whose marker stencil (rows f0.y ...
+        // f0.y + 3) meets them.
+        {
+            const int r0 = y0 + 4 * wid;
+            int n = 0;
+            for (int base = 0; base < c; base += 64) {
+                const int j = base + lane;
+                const bool hit = j < c && S.f0[j].y <= r0 + 3 && S.f0[j].y + 3 >= r0;
+                const unsigned long long m = __ballot(hit);
+                if (hit) S.strip[wid][n + __popcll(m & ((1ull << lane) - 1ull))] = (unsigned char)j;
+                n += __popcll(m);
+            }
+            if (lane == 0) S.strip_n[wid] = n;
+        }
+        if (IFACE != II_LBM_IF_MEMBRANE) __syncthreads();
 
         // Cut links of a membrane.  The (chord, source node) candidates of all
         // chords are numbered consecutively and every thread of the block takes
@@ -685,10 +708,13 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
         double gx = 0.0, gy = 0.0;
         if (valid) {
             // tangential force g_par(x) = sum_k G_par,k delta_h(x - X_k) dX (Sec. 3.2, Eq. (46))
-            // with the delta weights of marker k from the marker pass; markers
-            // whose stencil misses this node add an exact zero
+            // with the delta weights of marker k from the marker pass, over
+            // the markers whose stencil meets the wave's rows; those that miss
+            // this node add an exact zero
+            const int nw = S.strip_n[wid];
 #pragma unroll 4
-            for (int j = 0; j < c; j++) {
+            for (int n = 0; n < nw; n++) {
+                const int j = S.strip[wid][n];
                 const int2 f = S.f0[j];
                 const int ix = x - f.x, iy = y - f.y;
                 const bool in = (unsigned)ix <= 3u && (unsigned)iy <= 3u;

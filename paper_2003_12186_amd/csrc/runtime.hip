@@ -317,6 +317,9 @@ struct ii_lbm_handle {
     Batch batch;
     int sweep_order = 0;           // 0: instance order, 1: largest instances first
     double tuned_us = 0.0;
+    std::vector<int> tile_est;     // estimated active tiles per instance (batched)
+    int tile_per_cu = 0;           // tile-pass blocks per CU (0: one per estimated tile)
+    double tuned_step_us = 0.0;    // the autotuner's fastest whole step
     // hipGraph replay of two steps (one graph per starting parity)
     bool use_graph = false;
     hipStream_t cap_stream = nullptr;
@@ -602,6 +605,43 @@ static void drop_graphs(ii_lbm_handle* h)
         }
 }
 
+// Blocks of the batched tile pass.  per_cu = 0: one block per estimated
+// active tile of each instance (plus a quarter), the fastest pass on its own;
+// per_cu > 0: about per_cu blocks per CU in all, shared in proportion to the
+// instances' estimates (at least one each), every block walking several of
+// its instance's tiles.  Beside the sweep a smaller footprint leaves the
+// sweep's waves more of each CU.  The caller has synchronised the handle.
+static hipError_t upload_tile_table(ii_lbm_handle* h, int per_cu)
+{
+    long long tot = 0;
+    for (size_t j = 0; j < h->L.inst.size(); j++)
+        if (h->L.inst[j].n_markers > 0) tot += h->tile_est[j];
+    std::vector<int2> tl;
+    for (size_t j = 0; j < h->L.inst.size(); j++) {
+        InstDev& I = h->L.inst[j];
+        if (I.n_markers == 0) continue;
+        const long long est = h->tile_est[j];
+        long long nb = est + est / 4 + 1;
+        if (per_cu > 0)
+            nb = std::min(nb, (long long)per_cu * h->n_cu * est / std::max(tot, 1LL));
+        I.tile_blocks = (int)std::max(1LL, std::min((long long)I.act_cap, nb));
+        for (int q = 0; q < I.tile_blocks; q++) tl.push_back(make_int2((int)j, q));
+    }
+    hipError_t e = hipSuccess;
+    if (!tl.empty())
+        e = hipMemcpy((void*)h->batch.tile_table, tl.data(), tl.size() * sizeof(int2),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy((void*)h->batch.insts, h->L.inst.data(), h->L.inst.size() * sizeof(InstDev),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        h->batch.tile_units = (int)tl.size();
+        h->tile_per_cu = per_cu;
+    }
+    drop_graphs(h);
+    return e;
+}
+
 // Two steps starting at parity `par`, captured on the handle's own stream.
 static hipError_t build_graph(ii_lbm_handle* h, int par)
 {
@@ -861,10 +901,12 @@ int ii_lbm_init(const ii_lbm_problem* p, int32_t n_inst, const double* const* X0
         b.guo = h->L.inst[0].guo;
         b.jumps = h->L.inst[0].jumps;
         std::vector<int2> mk, tl;
+        h->tile_est.assign(n_inst, 0);
         for (int j = 0; j < n_inst; j++) {
             InstDev& I = h->L.inst[j];
             if (I.n_markers == 0) continue;
             const int est = estimate_active_tiles(p[j], X0[j]);
+            h->tile_est[j] = est;
             I.tile_blocks = std::max(1, std::min(I.act_cap, est + est / 4 + 1));
             for (int q = 0; q < I.mk_blocks; q++) mk.push_back(make_int2(j, q));
             for (int q = 0; q < I.tile_blocks; q++) tl.push_back(make_int2(j, q));
@@ -1065,15 +1107,66 @@ int ii_lbm_autotune(ii_lbm_handle* h, int32_t trials, int32_t* unit, int32_t* or
                 bo = o;
             }
         }
+    if (e == hipSuccess) e = upload_sweep_table(h, bu, bo);
+    // Membranes whose interface pass runs beside the sweep: the footprint of
+    // the tile pass, timed on whole steps.  A step that starts again from the
+    // same parity recomputes the same results (each phase reads one plane and
+    // writes the other), so repeating it leaves the state as it was.
+    double best_step = 0.0;
+    if (e == hipSuccess && h->lookahead && h->overlap != II_LBM_OVERLAP_SERIAL) {
+        const int cands[6] = {0, 16, 8, 4, 2, 1};
+        int bc = 0;
+        best_step = 1e300;
+        for (int ci = 0; ci < 6 && e == hipSuccess; ci++) {
+            e = upload_tile_table(h, cands[ci]);
+            if (e == hipSuccess) e = enqueue_step(h, h->parity, h->stream, false);
+            if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+            for (int t = 0; t < trials && e == hipSuccess; t++)
+                e = enqueue_step(h, h->parity, h->stream, false);
+            if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            const double us = 1e3 * ms / trials;
+            if (e == hipSuccess && us < best_step) {
+                best_step = us;
+                bc = cands[ci];
+            }
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e == hipSuccess) e = upload_tile_table(h, bc);
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (e == hipSuccess) e = upload_sweep_table(h, bu, bo);
     if (e != hipSuccess) return hip_fail(h, e);
     drop_graphs(h);
     h->tuned_us = best;
+    h->tuned_step_us = best_step;
     if (unit) *unit = bu;
     if (order) *order = bo;
     if (best_us) *best_us = best;
+    return II_LBM_OK;
+}
+
+int ii_lbm_set_tile_blocks(ii_lbm_handle* h, int32_t per_cu)
+{
+    if (!h || per_cu < 0 || per_cu > 64) return II_LBM_EINVAL;
+    if (h->failed) return II_LBM_ESTATE;
+    if (!h->batched) return II_LBM_OK;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess && h->aux) e = hipStreamSynchronize(h->aux);
+    if (e == hipSuccess) e = upload_tile_table(h, per_cu);
+    return e == hipSuccess ? II_LBM_OK : hip_fail(h, e);
+}
+
+int ii_lbm_get_schedule(ii_lbm_handle* h, int32_t* unit, int32_t* order, int32_t* tile_per_cu,
+                        double* step_us)
+{
+    if (!h) return II_LBM_EINVAL;
+    if (unit) *unit = h->batched ? h->batch.sweep_unit : 0;
+    if (order) *order = h->batched ? h->sweep_order : 0;
+    if (tile_per_cu) *tile_per_cu = h->batched ? h->tile_per_cu : 0;
+    if (step_us) *step_us = h->tuned_step_us;
     return II_LBM_OK;
 }
 

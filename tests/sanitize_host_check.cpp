@@ -158,6 +158,8 @@ int main()
     EXPECT(ii_lbm_get_timing(nullptr, d2, &l1) == II_LBM_EINVAL);
     EXPECT(ii_lbm_set_graph(nullptr, 1) == II_LBM_EINVAL);
     EXPECT(ii_lbm_autotune(nullptr, 1, nullptr, nullptr, nullptr) == II_LBM_EINVAL);
+    EXPECT(ii_lbm_set_tile_blocks(nullptr, 4) == II_LBM_EINVAL);
+    EXPECT(ii_lbm_get_schedule(nullptr, nullptr, nullptr, nullptr, nullptr) == II_LBM_EINVAL);
     EXPECT(ii_lbm_destroy(nullptr) == II_LBM_EINVAL);
     for (int code = 1; code >= -8; code--) EXPECT(ii_lbm_strerror(code) != nullptr);
 

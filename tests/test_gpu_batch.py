@@ -110,6 +110,36 @@ def test_overlap_modes_are_bit_identical(B, batched):
             assert np.array_equal(fa, fb) and np.array_equal(xa, xb)
 
 
+def test_tile_footprint_and_autotune_keep_results(B):
+    # The tile pass's blocks per CU change only the schedule, and the
+    # autotuner's whole-step trials leave the state as they found it.
+    _say("tile-pass footprint 0 / 1 / 4 / 16 blocks per CU, then autotune mid-run")
+    ws = _small_batch(4)
+    probs, X0 = [w.problem for w in ws], [w.X0 for w in ws]
+    out = []
+    for per_cu in (0, 1, 4, 16):
+        s = B.Sim(probs, X0)
+        s.set_tile_blocks(per_cu)
+        assert s.schedule()["tile_blocks_per_cu"] == per_cu
+        s.step(41)
+        out.append([(s.fields(B.F_DISTRIB, inst=j, dtype=np.float32), s.markers(j)[0])
+                    for j in range(len(ws))])
+        s.close()
+    for other in out[1:]:
+        for (fa, xa), (fb, xb) in zip(out[0], other):
+            assert np.array_equal(fa, fb) and np.array_equal(xa, xb)
+    s = B.Sim(probs, X0)
+    s.step(20)
+    tune = s.autotune(2)
+    _say(f"  autotune: {tune}")
+    assert tune["tile_blocks_per_cu"] in (0, 16, 8, 4, 2, 1) and tune["step_us"] > 0.0
+    s.step(21)
+    for j in range(len(ws)):
+        assert np.array_equal(s.fields(B.F_DISTRIB, inst=j, dtype=np.float32), out[0][j][0])
+        assert np.array_equal(s.markers(j)[0], out[0][j][1])
+    s.close()
+
+
 def test_batch_rejects_mixed_storage(B):
     ws = _small_batch(2)
     ws[1].problem.storage = W.STORE_FP16
