@@ -63,13 +63,34 @@ typedef struct ii_lbm3_problem {
 
 typedef struct ii_lbm3_handle ii_lbm3_handle;
 
-/* Creates a handle; the library allocates its device memory (two lattices of
- * 19 FP32 deviation planes, plus three FP64 force planes under IB-LBM) and
- * frees it in ii_lbm3_destroy.  The fluid starts at rest.  hip_stream: the
- * stream for all work (NULL = default).  Synchronises before returning.
- * EINVAL for an invalid problem, EDEVICE when allocation fails. */
+/* Creates a handle; the library takes its device memory with hipMalloc (two
+ * lattices of 19 FP32 deviation planes, three 64-bit fixed-point force planes
+ * under IB-LBM or with a membrane, and the buffers of ii_lbm3_set_mesh,
+ * ii_lbm3_set_membrane and the rigid surfaces) and frees it in
+ * ii_lbm3_destroy.  The fluid starts at rest.  hip_stream: the stream for all
+ * work (NULL = default).  Synchronises before returning.  EINVAL for an
+ * invalid problem, EDEVICE when allocation fails. */
 int ii_lbm3_init(const ii_lbm3_problem* p, const double* X0, void* hip_stream,
                  ii_lbm3_handle** out);
+
+/* Device memory from the caller: a handle created by ii_lbm3_init_with takes
+ * every device buffer it ever needs (including the temporaries of
+ * ii_lbm3_set_distrib and ii_lbm3_fields) from alloc(bytes, ctx), which must
+ * return device memory aligned to 256 bytes or NULL, and hands each back
+ * through release(ptr, ctx) once the handle's stream has finished with it
+ * (at the latest in ii_lbm3_destroy).  Both are called from the host calls of
+ * the handle only, never during ii_lbm3_step.  For callers whose device
+ * memory is owned elsewhere, e.g. PyTorch's caching allocator. */
+typedef struct ii_lbm3_allocator {
+    void* (*alloc)(size_t bytes, void* ctx);
+    void (*release)(void* ptr, void* ctx);
+    void* ctx;
+} ii_lbm3_allocator;
+
+/* ii_lbm3_init with device memory from `alloc` (NULL: hipMalloc, as
+ * ii_lbm3_init).  EINVAL also when alloc has a NULL callback. */
+int ii_lbm3_init_with(const ii_lbm3_problem* p, const double* X0, void* hip_stream,
+                      const ii_lbm3_allocator* alloc, ii_lbm3_handle** out);
 
 /* Enqueues n_steps steps; returns without waiting. */
 int ii_lbm3_step(ii_lbm3_handle* h, int64_t n_steps);

@@ -359,7 +359,40 @@ EXPORTS3 = ["ii_lbm3_init", "ii_lbm3_step", "ii_lbm3_set_distrib", "ii_lbm3_fiel
             "ii_lbm3_set_timing", "ii_lbm3_get_timing", "ii_lbm3_sweep_bytes", "ii_lbm3_check_mesh",
             "ii_lbm3_set_mesh", "ii_lbm3_mesh_links", "ii_lbm3_set_membrane", "ii_lbm3_membrane",
             "ii_lbm3_set_rigid_surface", "ii_lbm3_surface_force", "ii_lbm3_set_free_sphere", "ii_lbm3_body",
-            "ii_lbm3_destroy"]
+            "ii_lbm3_destroy", "ii_lbm3_init_with"]
+
+_ALLOC3 = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_RELEASE3 = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class Allocator3C(C.Structure):
+    _fields_ = [("alloc", _ALLOC3), ("release", _RELEASE3), ("ctx", C.c_void_p)]
+
+
+class TorchMemory:
+    """Device memory of a D3Q19 handle taken from PyTorch's caching
+    allocator: each buffer is a uint8 tensor held here until the library
+    hands it back.  Argument marshalling only."""
+
+    def __init__(self, device="cuda"):
+        self.device = device
+        self.live = {}
+        self.c = Allocator3C(_ALLOC3(self._alloc), _RELEASE3(self._release), None)
+
+    def _alloc(self, nbytes, ctx):
+        try:
+            import torch
+            t = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=self.device)
+        except Exception:
+            return None
+        self.live[t.data_ptr()] = t
+        return t.data_ptr()
+
+    def _release(self, ptr, ctx):
+        self.live.pop(ptr, None)
+
+    def bytes_held(self) -> int:
+        return sum(t.numel() for t in self.live.values())
 
 
 def _lib3():
@@ -384,6 +417,7 @@ def _lib3():
             "ii_lbm3_set_free_sphere": [v, i32, v, i32, v, v, d, d, v, v],
             "ii_lbm3_body": [v, v],
             "ii_lbm3_destroy": [v],
+            "ii_lbm3_init_with": [C.POINTER(Problem3C), v, v, C.POINTER(Allocator3C), C.POINTER(v)],
         }
         for name, args in sigs.items():
             fn = getattr(lib, name)
@@ -422,15 +456,19 @@ def check_mesh3(problem, X, tri) -> int:
 
 
 class Sim3:
-    """A D3Q19 handle: a periodic box with an optional normal-force sphere."""
+    """A D3Q19 handle: a periodic box with an optional normal-force sphere.
+    Its device memory comes from PyTorch's allocator (``torch_memory``, the
+    default) or from the library's own hipMalloc."""
 
-    def __init__(self, problem, X0=None):
+    def __init__(self, problem, X0=None, torch_memory: bool = True):
         self.p = problem if isinstance(problem, Problem3C) else make_problem3(problem)
         self.h = C.c_void_p()
         X = None if X0 is None else np.ascontiguousarray(X0, dtype=np.float64)
         self._X = X
-        check(_lib3().ii_lbm3_init(C.byref(self.p), None if X is None else X.ctypes.data, None,
-                                   C.byref(self.h)), "init3")
+        self.mem = TorchMemory() if torch_memory else None
+        check(_lib3().ii_lbm3_init_with(C.byref(self.p), None if X is None else X.ctypes.data, None,
+                                        C.byref(self.mem.c) if self.mem else None, C.byref(self.h)),
+              "init3")
 
     def step(self, n: int) -> None:
         check(_lib3().ii_lbm3_step(self.h, int(n)), "step3")

@@ -119,10 +119,28 @@ __device__ __forceinline__ double sphere_phi(const Box& b, double x, double y, d
     return dx * dx + dy * dy + dz * dz - b.R * b.R;
 }
 
+// The spread force field is summed in 64-bit fixed point at 2^-56 (terms
+// clamped to 64 in magnitude), so that it is exact and does not depend on
+// the order in which the threads add their terms.
+constexpr double kFix3 = 72057594037927936.0;   // 2^56
+
+__device__ __forceinline__ long long fix3(double v)
+{
+    const double c = isfinite(v) ? fmin(fmax(v, -64.0), 64.0) : 64.0;
+    return __double2ll_rn(c * kFix3);
+}
+
+__device__ __forceinline__ void fix3_add(long long* p, double v)
+{
+    atomicAdd((unsigned long long*)p, (unsigned long long)fix3(v));
+}
+
+__device__ __forceinline__ double fix3_get(long long q) { return (double)q * (1.0 / kFix3); }
+
 template <bool IB, bool MRT>
 __global__ __launch_bounds__(kBX) void k_sweep3(Box b, const float* __restrict__ A,
                                                 float* __restrict__ B,
-                                                const double* __restrict__ gfield)
+                                                const long long* __restrict__ gfield)
 {
     const int x = blockIdx.x * kBX + threadIdx.x;
     const int y = blockIdx.y, z = blockIdx.z;
@@ -147,9 +165,9 @@ __global__ __launch_bounds__(kBX) void k_sweep3(Box b, const float* __restrict__
     if (IB) {
         const long long c = ((long long)z * b.ny + y) * b.nx + x;
         const long long n = (long long)b.nx * b.ny * b.nz;
-        gx += gfield[c];
-        gy += gfield[n + c];
-        gz += gfield[2 * n + c];
+        gx += fix3_get(gfield[c]);
+        gy += fix3_get(gfield[n + c]);
+        gz += fix3_get(gfield[2 * n + c]);
     }
     const double jj = jx * jx + jy * jy + jz * jz;
     // He-Luo equilibrium deviation w_i [dr + 3 e.j + 4.5 (e.j)^2 - 1.5 j.j],
@@ -234,7 +252,7 @@ __global__ __launch_bounds__(kBX) void k_sweep3(Box b, const float* __restrict__
 }
 
 // IB-LBM force field g(x) = sum_k F n_k delta_h(x - X_k) dA, one thread per
-// (marker, stencil node); FP64 atomics (the field is built once).
+// (marker, stencil node), summed in fixed point (the field is built once).
 __device__ __forceinline__ double peskin1(double r)
 {
     const double a = fabs(r);
@@ -244,7 +262,7 @@ __device__ __forceinline__ double peskin1(double r)
 }
 
 __global__ void k_spread3(Box b, const double* __restrict__ X, int N, double dA,
-                          double* __restrict__ g)
+                          long long* __restrict__ g)
 {
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (t >= (long long)N * 64) return;
@@ -257,9 +275,9 @@ __global__ void k_spread3(Box b, const double* __restrict__ X, int N, double dA,
     const double nx_ = (X0 - b.cx) / b.R, ny_ = (Y0 - b.cy) / b.R, nz_ = (Z0 - b.cz) / b.R;
     const long long n = (long long)b.nx * b.ny * b.nz;
     const long long c = ((long long)wrapi(z, b.nz) * b.ny + wrapi(y, b.ny)) * b.nx + wrapi(x, b.nx);
-    atomicAdd(&g[c], b.F * nx_ * w * dA);
-    atomicAdd(&g[n + c], b.F * ny_ * w * dA);
-    atomicAdd(&g[2 * n + c], b.F * nz_ * w * dA);
+    fix3_add(&g[c], b.F * nx_ * w * dA);
+    fix3_add(&g[n + c], b.F * ny_ * w * dA);
+    fix3_add(&g[2 * n + c], b.F * nz_ * w * dA);
 }
 
 // rho, u of f^n (the pulled populations) into out[4][nz][ny][nx] (device).
@@ -628,7 +646,7 @@ __global__ void k_memb_forces3(const double* __restrict__ X, const int* __restri
 
 // g(x) += Gt_v delta_h(x - X_v): one thread per (vertex, stencil node).
 __global__ void k_memb_spread3(Box b, const double* __restrict__ X, const double* __restrict__ Gt, int nv,
-                               double* __restrict__ g, const int* err)
+                               long long* __restrict__ g, const int* err)
 {
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (t >= (long long)nv * 64 || memb_failed(err)) return;
@@ -639,9 +657,9 @@ __global__ void k_memb_spread3(Box b, const double* __restrict__ X, const double
     const double w = peskin1(x - X0) * peskin1(y - Y0) * peskin1(z - Z0);
     const long long n = (long long)b.nx * b.ny * b.nz;
     const long long c = ((long long)z * b.ny + y) * b.nx + x;
-    atomicAdd(&g[c], Gt[3 * v] * w);
-    atomicAdd(&g[n + c], Gt[3 * v + 1] * w);
-    atomicAdd(&g[2 * n + c], Gt[3 * v + 2] * w);
+    fix3_add(&g[c], Gt[3 * v] * w);
+    fix3_add(&g[n + c], Gt[3 * v + 1] * w);
+    fix3_add(&g[2 * n + c], Gt[3 * v + 2] * w);
 }
 
 // IB-LBM membrane (law 2): the vertices move with the velocity of the
@@ -649,7 +667,7 @@ __global__ void k_memb_spread3(Box b, const double* __restrict__ X, const double
 // uniform body force) interpolated at each vertex joins U_v; one wave per
 // vertex, one lane per stencil node.
 __global__ __launch_bounds__(256) void k_memb_addg3(Box b, const double* __restrict__ X, int nv,
-                                                    const double* __restrict__ g, double bx, double by,
+                                                    const long long* __restrict__ g, double bx, double by,
                                                     double bz, double* __restrict__ U, const int* err)
 {
     const int v = blockIdx.x * 4 + threadIdx.x / 64;
@@ -661,7 +679,7 @@ __global__ __launch_bounds__(256) void k_memb_addg3(Box b, const double* __restr
     const double w = peskin1(x - X0) * peskin1(y - Y0) * peskin1(z - Z0);
     const long long n = (long long)b.nx * b.ny * b.nz;
     const long long c = ((long long)z * b.ny + y) * b.nx + x;
-    double gx = g[c] * w, gy = g[n + c] * w, gz = g[2 * n + c] * w;
+    double gx = fix3_get(g[c]) * w, gy = fix3_get(g[n + c]) * w, gz = fix3_get(g[2 * n + c]) * w;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         gx += __shfl_xor(gx, o, 64);
@@ -736,7 +754,7 @@ __global__ void k_body_move3(double* __restrict__ X, int nv, const Body3* __rest
 // the next step at zero without clearing the whole box.  It ignores the
 // error word (a stop after the spread must not leave its forces behind) and
 // skips vertices outside the region, which were never spread.
-__global__ void k_memb_unspread3(Box b, const double* __restrict__ X, int nv, double* __restrict__ g)
+__global__ void k_memb_unspread3(Box b, const double* __restrict__ X, int nv, long long* __restrict__ g)
 {
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (t >= (long long)nv * 64) return;
@@ -747,17 +765,29 @@ __global__ void k_memb_unspread3(Box b, const double* __restrict__ X, int nv, do
               z = (int)floor(Z0) - 1 + (lane >> 4);
     const long long n = (long long)b.nx * b.ny * b.nz;
     const long long c = ((long long)z * b.ny + y) * b.nx + x;
-    g[c] = 0.0;
-    g[n + c] = 0.0;
-    g[2 * n + c] = 0.0;
+    g[c] = 0;
+    g[n + c] = 0;
+    g[2 * n + c] = 0;
 }
 
 __global__ void k_zero_count3(int* count) { *count = 0; }
 
-// The step's jumps, straight from the records (several may share a target);
-// a grid-stride loop over the device-side count.
-__global__ void k_memb_apply3(Box b, const MeshRec3* __restrict__ r, const int* __restrict__ count, int cap,
-                              float* __restrict__ B, int* err)
+// The step's jumps, added to the stored populations independently of the
+// records' order: the deltas of the records (several may share a target
+// population) are summed per target in fixed point (fix3) in an open-
+// addressing table, then each distinct target takes its sum in one
+// read-modify-write, which also empties its table entry for the next step.
+constexpr unsigned long long kEmpty3 = ~0ull;
+constexpr int kProbe3 = 256;
+
+__device__ __forceinline__ unsigned hash3(unsigned long long key, int bits)
+{
+    return (unsigned)((key * 0x9E3779B97F4A7C15ull) >> (64 - bits));
+}
+
+__global__ void k_memb_accum3(Box b, const MeshRec3* __restrict__ r, const int* __restrict__ count, int cap,
+                              unsigned long long* __restrict__ keys, long long* __restrict__ sums, int bits,
+                              int* __restrict__ used, int* __restrict__ n_used, int* err)
 {
     if (memb_failed(err)) return;
     const int n = *count;
@@ -765,9 +795,49 @@ __global__ void k_memb_apply3(Box b, const MeshRec3* __restrict__ r, const int* 
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(err, 2);
         return;
     }
+    const unsigned mask = (1u << bits) - 1u;
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
         const MeshRec3 q = r[k];
-        atomicAdd(&B[q.dir * b.plane + ((long long)q.z * b.ny + q.y) * b.pitch + q.x], q.delta);
+        const unsigned long long key =
+            (unsigned long long)(q.dir * b.plane + ((long long)q.z * b.ny + q.y) * b.pitch + q.x);
+        // the table has twice as many entries as there can be records; a
+        // probe that finds neither the key nor a free entry within kProbe3
+        // steps (no realistic load comes near) reports a capacity error
+        unsigned sl = hash3(key, bits);
+        bool found = false;
+        for (int t = 0; t < kProbe3; t++) {
+            const unsigned long long prev = atomicCAS(&keys[sl], kEmpty3, key);
+            if (prev == kEmpty3) {
+                const int u = atomicAdd(n_used, 1);
+                if (u < cap) used[u] = (int)sl;
+                found = u < cap;
+                break;
+            }
+            if (prev == key) {
+                found = true;
+                break;
+            }
+            sl = (sl + 1u) & mask;
+        }
+        if (!found) {
+            atomicOr(err, 2);
+            continue;
+        }
+        fix3_add(&sums[sl], (double)q.delta);
+    }
+}
+
+__global__ void k_memb_addsums3(const int* __restrict__ n_used, int cap, const int* __restrict__ used,
+                                unsigned long long* __restrict__ keys, long long* __restrict__ sums,
+                                float* __restrict__ B)
+{
+    const int n = min(*n_used, cap);
+    for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
+        const int sl = used[u];
+        const long long off = (long long)keys[sl];
+        B[off] = (float)((double)B[off] + fix3_get(sums[sl]));
+        keys[sl] = kEmpty3;
+        sums[sl] = 0;
     }
 }
 
@@ -783,6 +853,7 @@ __global__ void k_memb_move3(double* __restrict__ X, const double* __restrict__ 
 using namespace iilbm3;
 
 struct ii_lbm3_handle {
+    ii_lbm3_allocator alloc{};   // device memory from the caller (alloc == NULL: hipMalloc)
     Box b;
     ii_lbm3_problem prob;
     bool mrt = false;
@@ -814,9 +885,15 @@ struct ii_lbm3_handle {
     int* memb_vt = nullptr;
     MeshRec3* memb_rec = nullptr;
     int* memb_count = nullptr;
+    // per-target sums of the jumps (k_memb_accum3): 2^memb_hbits entries
+    unsigned long long* memb_hkeys = nullptr;
+    long long* memb_hsums = nullptr;
+    int* memb_used = nullptr;       // table entries in use (memb_cap)
+    int* memb_nused = nullptr;
+    int memb_hbits = 0;
     int* memb_err = nullptr;
     float* lat[2] = {nullptr, nullptr};
-    double* g = nullptr;
+    long long* g = nullptr;    // spread force field, fixed point (fix3)
     int parity = 0;
     bool timing = false;
     std::vector<hipEvent_t> ev;
@@ -827,11 +904,31 @@ struct ii_lbm3_handle {
 
 static int fail3(hipError_t e) { return e == hipSuccess ? II_LBM_OK : II_LBM_EDEVICE; }
 
+// Every device buffer of a handle comes from here: the caller's allocator
+// when it gave one (ii_lbm3_init_with), hipMalloc otherwise.  Buffers are
+// returned only after the handle's stream has finished with them.
+template <class T>
+static hipError_t dmalloc(ii_lbm3_handle* h, T** p, size_t bytes)
+{
+    if (!h->alloc.alloc) return hipMalloc((void**)p, bytes);
+    *p = (T*)h->alloc.alloc(bytes, h->alloc.ctx);
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+
+static void dfree(ii_lbm3_handle* h, void* p)
+{
+    if (!p) return;
+    if (h->alloc.release)
+        h->alloc.release(p, h->alloc.ctx);
+    else
+        (void)hipFree(p);
+}
+
 static void free_mesh(ii_lbm3_handle* h)
 {
     for (void* q : {(void*)h->mesh_S, (void*)h->mesh_tri, (void*)h->mesh_pv, (void*)h->mesh_rec,
                     (void*)h->mesh_count, (void*)h->apply_off, (void*)h->apply_delta})
-        if (q) (void)hipFree(q);
+        dfree(h, q);
     h->mesh_S = nullptr; h->mesh_tri = nullptr; h->mesh_pv = nullptr; h->mesh_rec = nullptr;
     h->mesh_count = nullptr; h->mesh_links = 0;
     h->apply_off = nullptr; h->apply_delta = nullptr; h->apply_n = 0;
@@ -844,11 +941,16 @@ static void free_membrane(ii_lbm3_handle* h)
     for (void* q : {(void*)h->memb_X, (void*)h->memb_U, (void*)h->memb_jp, (void*)h->memb_Gt, (void*)h->memb_G,
                     (void*)h->memb_S,
                     (void*)h->memb_tri, (void*)h->memb_vt_off, (void*)h->memb_vt, (void*)h->memb_rec,
-                    (void*)h->memb_count, (void*)h->memb_err})
-        if (q) (void)hipFree(q);
+                    (void*)h->memb_count, (void*)h->memb_err, (void*)h->memb_hkeys, (void*)h->memb_hsums,
+                    (void*)h->memb_used, (void*)h->memb_nused})
+        dfree(h, q);
+    h->memb_hkeys = nullptr;
+    h->memb_hsums = nullptr;
+    h->memb_used = h->memb_nused = nullptr;
+    h->memb_hbits = 0;
     h->memb_X = h->memb_U = h->memb_jp = h->memb_Gt = h->memb_G = nullptr;
     h->memb_law = 0;
-    if (h->body3) (void)hipFree(h->body3);
+    dfree(h, h->body3);
     h->body3 = nullptr;
     h->memb_S = nullptr;
     h->memb_tri = h->memb_vt_off = h->memb_vt = h->memb_count = h->memb_err = nullptr;
@@ -875,7 +977,7 @@ static void memb_before_sweep(ii_lbm3_handle* h, const float* A)
                        b, h->memb_X, h->memb_Gt, nv, h->g, h->memb_err);
     if (h->memb_law == 2) {                                       // IB-LBM: no jumps
         hipLaunchKernelGGL(k_memb_addg3, dim3((nv + 3) / 4), dim3(256), 0, h->stream, b,
-                           (const double*)h->memb_X, nv, (const double*)h->g, b.g[0], b.g[1],
+                           (const double*)h->memb_X, nv, (const long long*)h->g, b.g[0], b.g[1],
                            b.g[2], h->memb_U, (const int*)h->memb_err);
         return;
     }
@@ -887,9 +989,15 @@ static void memb_before_sweep(ii_lbm3_handle* h, const float* A)
 
 static void memb_after_sweep(ii_lbm3_handle* h, float* B)
 {
-    if (h->memb_law != 2)
-        hipLaunchKernelGGL(k_memb_apply3, dim3(std::min((h->memb_cap + 255) / 256, 2048)), dim3(256), 0,
-                           h->stream, h->b, h->memb_rec, h->memb_count, h->memb_cap, B, h->memb_err);
+    if (h->memb_law != 2) {
+        const dim3 grid(std::min((h->memb_cap + 255) / 256, 2048));
+        hipLaunchKernelGGL(k_zero_count3, dim3(1), dim3(1), 0, h->stream, h->memb_nused);
+        hipLaunchKernelGGL(k_memb_accum3, grid, dim3(256), 0, h->stream, h->b, (const MeshRec3*)h->memb_rec,
+                           (const int*)h->memb_count, h->memb_cap, h->memb_hkeys, h->memb_hsums, h->memb_hbits,
+                           h->memb_used, h->memb_nused, h->memb_err);
+        hipLaunchKernelGGL(k_memb_addsums3, grid, dim3(256), 0, h->stream, (const int*)h->memb_nused,
+                           h->memb_cap, (const int*)h->memb_used, h->memb_hkeys, h->memb_hsums, B);
+    }
     hipLaunchKernelGGL(k_memb_unspread3, dim3((unsigned)(((long long)h->memb_nv * 64 + 255) / 256)), dim3(256), 0,
                        h->stream, h->b, (const double*)h->memb_X, h->memb_nv, h->g);
     if (h->memb_law == 0 || h->memb_law == 2)
@@ -908,8 +1016,15 @@ extern "C" {
 
 int ii_lbm3_init(const ii_lbm3_problem* p, const double* X0, void* hip_stream, ii_lbm3_handle** out)
 {
+    return ii_lbm3_init_with(p, X0, hip_stream, nullptr, out);
+}
+
+int ii_lbm3_init_with(const ii_lbm3_problem* p, const double* X0, void* hip_stream,
+                      const ii_lbm3_allocator* alloc, ii_lbm3_handle** out)
+{
     if (!p || !out) return II_LBM_EINVAL;
     *out = nullptr;
+    if (alloc && (!alloc->alloc || !alloc->release)) return II_LBM_EINVAL;
     if (p->nx < 8 || p->ny < 8 || p->nz < 8 || p->nx > 1024 || p->ny > 1024 || p->nz > 1024)
         return II_LBM_EINVAL;
     if (!(p->tau > 0.5) || !isfinite(p->tau)) return II_LBM_EINVAL;
@@ -934,6 +1049,7 @@ int ii_lbm3_init(const ii_lbm3_problem* p, const double* X0, void* hip_stream, i
         }
     }
     ii_lbm3_handle* h = new ii_lbm3_handle();
+    if (alloc) h->alloc = *alloc;
     h->prob = *p;
     Box& b = h->b;
     b.nx = p->nx; b.ny = p->ny; b.nz = p->nz;
@@ -960,8 +1076,8 @@ int ii_lbm3_init(const ii_lbm3_problem* p, const double* X0, void* hip_stream, i
     h->mrt = p->collision == II_LBM_MRT;
     h->stream = (hipStream_t)hip_stream;
     const size_t lat = (size_t)kQ * b.plane * sizeof(float);
-    hipError_t e = hipMalloc(&h->lat[0], lat);
-    if (e == hipSuccess) e = hipMalloc(&h->lat[1], lat);
+    hipError_t e = dmalloc(h, &h->lat[0], lat);
+    if (e == hipSuccess) e = dmalloc(h, &h->lat[1], lat);
     const long long n = (long long)b.nx * b.ny * b.nz;
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_zero3, dim3(2048), dim3(256), 0, h->stream, h->lat[0], (long long)kQ * b.plane);
@@ -969,10 +1085,10 @@ int ii_lbm3_init(const ii_lbm3_problem* p, const double* X0, void* hip_stream, i
         e = hipGetLastError();
     }
     if (e == hipSuccess && b.ib) {
-        e = hipMalloc(&h->g, (size_t)3 * n * sizeof(double));
+        e = dmalloc(h, &h->g, (size_t)3 * n * sizeof(long long));
         double* dX = nullptr;
-        if (e == hipSuccess) e = hipMemsetAsync(h->g, 0, (size_t)3 * n * sizeof(double), h->stream);
-        if (e == hipSuccess) e = hipMalloc(&dX, (size_t)3 * p->n_markers * sizeof(double));
+        if (e == hipSuccess) e = hipMemsetAsync(h->g, 0, (size_t)3 * n * sizeof(long long), h->stream);
+        if (e == hipSuccess) e = dmalloc(h, &dX, (size_t)3 * p->n_markers * sizeof(double));
         if (e == hipSuccess)
             e = hipMemcpyAsync(dX, X0, (size_t)3 * p->n_markers * sizeof(double), hipMemcpyHostToDevice,
                                h->stream);
@@ -984,7 +1100,8 @@ int ii_lbm3_init(const ii_lbm3_problem* p, const double* X0, void* hip_stream, i
             e = hipGetLastError();
         }
         if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-        if (dX) (void)hipFree(dX);
+        else (void)hipStreamSynchronize(h->stream);
+        dfree(h, dX);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) {
@@ -1048,14 +1165,15 @@ int ii_lbm3_set_distrib(ii_lbm3_handle* h, const double* f)
     const Box& b = h->b;
     const long long n = (long long)b.nx * b.ny * b.nz;
     double* df = nullptr;
-    hipError_t e = hipMalloc(&df, (size_t)kQ * n * sizeof(double));
+    hipError_t e = dmalloc(h, &df, (size_t)kQ * n * sizeof(double));
     if (e == hipSuccess) e = hipMemcpyAsync(df, f, (size_t)kQ * n * sizeof(double), hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_set3, dim3(1024), dim3(256), 0, h->stream, b, df, h->lat[h->parity]);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    if (df) (void)hipFree(df);
+    else (void)hipStreamSynchronize(h->stream);
+    dfree(h, df);
     return fail3(e);
 }
 
@@ -1065,14 +1183,15 @@ int ii_lbm3_fields(ii_lbm3_handle* h, double* out)
     const Box& b = h->b;
     const long long n = (long long)b.nx * b.ny * b.nz;
     double* d = nullptr;
-    hipError_t e = hipMalloc(&d, (size_t)4 * n * sizeof(double));
+    hipError_t e = dmalloc(h, &d, (size_t)4 * n * sizeof(double));
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_fields3, dim3(1024), dim3(256), 0, h->stream, b, h->lat[h->parity], d);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipMemcpyAsync(out, d, (size_t)4 * n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    if (d) (void)hipFree(d);
+    else (void)hipStreamSynchronize(h->stream);
+    dfree(h, d);
     return fail3(e);
 }
 
@@ -1187,11 +1306,11 @@ int ii_lbm3_set_mesh(ii_lbm3_handle* h, int32_t n_vert, const double* X, int32_t
     std::vector<long long> S((size_t)3 * n_vert);
     for (size_t k = 0; k < S.size(); k++) S[k] = snap_2m16(X[k]);
     const long long cap = 64LL * n_tri + 4096;
-    hipError_t e = hipMalloc(&h->mesh_S, S.size() * sizeof(long long));
-    if (e == hipSuccess) e = hipMalloc(&h->mesh_tri, (size_t)3 * n_tri * sizeof(int));
-    if (e == hipSuccess) e = hipMalloc(&h->mesh_pv, (size_t)n_vert * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&h->mesh_rec, (size_t)cap * sizeof(MeshRec3));
-    if (e == hipSuccess) e = hipMalloc(&h->mesh_count, sizeof(int));
+    hipError_t e = dmalloc(h, &h->mesh_S, S.size() * sizeof(long long));
+    if (e == hipSuccess) e = dmalloc(h, &h->mesh_tri, (size_t)3 * n_tri * sizeof(int));
+    if (e == hipSuccess) e = dmalloc(h, &h->mesh_pv, (size_t)n_vert * sizeof(double));
+    if (e == hipSuccess) e = dmalloc(h, &h->mesh_rec, (size_t)cap * sizeof(MeshRec3));
+    if (e == hipSuccess) e = dmalloc(h, &h->mesh_count, sizeof(int));
     if (e == hipSuccess)
         e = hipMemcpyAsync(h->mesh_S, S.data(), S.size() * sizeof(long long), hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess)
@@ -1248,8 +1367,8 @@ int ii_lbm3_set_mesh(ii_lbm3_handle* h, int32_t n_vert, const double* X, int32_t
             delta.push_back(r[j].delta);
         }
     }
-    if (e == hipSuccess && !off.empty()) e = hipMalloc(&h->apply_off, off.size() * sizeof(long long));
-    if (e == hipSuccess && !off.empty()) e = hipMalloc(&h->apply_delta, delta.size() * sizeof(float));
+    if (e == hipSuccess && !off.empty()) e = dmalloc(h, &h->apply_off, off.size() * sizeof(long long));
+    if (e == hipSuccess && !off.empty()) e = dmalloc(h, &h->apply_delta, delta.size() * sizeof(float));
     if (e == hipSuccess && !off.empty())
         e = hipMemcpyAsync(h->apply_off, off.data(), off.size() * sizeof(long long), hipMemcpyHostToDevice,
                            h->stream);
@@ -1291,22 +1410,35 @@ static int set_surface(ii_lbm3_handle* h, int32_t n_vert, const double* X, int32
     const long long n = (long long)h->b.nx * h->b.ny * h->b.nz;
     const int cap = 64 * n_tri + 4096;
     hipError_t e = hipSuccess;
-    if (!h->g) e = hipMalloc(&h->g, (size_t)3 * n * sizeof(double));
+    if (!h->g) e = dmalloc(h, &h->g, (size_t)3 * n * sizeof(long long));
     // the force field starts at zero; each step then clears what it spread
-    if (e == hipSuccess) e = hipMemsetAsync(h->g, 0, (size_t)3 * n * sizeof(double), h->stream);
-    if (e == hipSuccess) e = hipMalloc(&h->memb_X, (size_t)3 * n_vert * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&h->memb_U, (size_t)3 * n_vert * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&h->memb_jp, (size_t)n_vert * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&h->memb_Gt, (size_t)3 * n_vert * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&h->memb_G, (size_t)3 * n_vert * sizeof(double));
+    if (e == hipSuccess) e = hipMemsetAsync(h->g, 0, (size_t)3 * n * sizeof(long long), h->stream);
+    if (e == hipSuccess) e = dmalloc(h, &h->memb_X, (size_t)3 * n_vert * sizeof(double));
+    if (e == hipSuccess) e = dmalloc(h, &h->memb_U, (size_t)3 * n_vert * sizeof(double));
+    if (e == hipSuccess) e = dmalloc(h, &h->memb_jp, (size_t)n_vert * sizeof(double));
+    if (e == hipSuccess) e = dmalloc(h, &h->memb_Gt, (size_t)3 * n_vert * sizeof(double));
+    if (e == hipSuccess) e = dmalloc(h, &h->memb_G, (size_t)3 * n_vert * sizeof(double));
     if (e == hipSuccess) e = hipMemsetAsync(h->memb_G, 0, (size_t)3 * n_vert * sizeof(double), h->stream);
-    if (e == hipSuccess) e = hipMalloc(&h->memb_S, (size_t)3 * n_vert * sizeof(long long));
-    if (e == hipSuccess) e = hipMalloc(&h->memb_tri, (size_t)3 * n_tri * sizeof(int));
-    if (e == hipSuccess) e = hipMalloc(&h->memb_vt_off, (size_t)(n_vert + 1) * sizeof(int));
-    if (e == hipSuccess) e = hipMalloc(&h->memb_vt, vt.size() * sizeof(int));
-    if (e == hipSuccess) e = hipMalloc(&h->memb_rec, (size_t)cap * sizeof(MeshRec3));
-    if (e == hipSuccess) e = hipMalloc(&h->memb_count, sizeof(int));
-    if (e == hipSuccess) e = hipMalloc(&h->memb_err, sizeof(int));
+    if (e == hipSuccess) e = dmalloc(h, &h->memb_S, (size_t)3 * n_vert * sizeof(long long));
+    if (e == hipSuccess) e = dmalloc(h, &h->memb_tri, (size_t)3 * n_tri * sizeof(int));
+    if (e == hipSuccess) e = dmalloc(h, &h->memb_vt_off, (size_t)(n_vert + 1) * sizeof(int));
+    if (e == hipSuccess) e = dmalloc(h, &h->memb_vt, vt.size() * sizeof(int));
+    if (e == hipSuccess) e = dmalloc(h, &h->memb_rec, (size_t)cap * sizeof(MeshRec3));
+    if (e == hipSuccess) e = dmalloc(h, &h->memb_count, sizeof(int));
+    if (e == hipSuccess) e = dmalloc(h, &h->memb_err, sizeof(int));
+    // per-target sums: twice as many entries as records can be (a table
+    // sized for the usual 7 cut links per triangle was slower: its atomics
+    // share more cache lines)
+    int hbits = 1;
+    while ((1LL << hbits) < 2LL * cap) hbits++;
+    const size_t hn = (size_t)1 << hbits;
+    if (e == hipSuccess) e = dmalloc(h, &h->memb_hkeys, hn * sizeof(unsigned long long));
+    if (e == hipSuccess) e = dmalloc(h, &h->memb_hsums, hn * sizeof(long long));
+    if (e == hipSuccess) e = dmalloc(h, &h->memb_used, (size_t)cap * sizeof(int));
+    if (e == hipSuccess) e = dmalloc(h, &h->memb_nused, sizeof(int));
+    if (e == hipSuccess) e = hipMemsetAsync(h->memb_hkeys, 0xff, hn * sizeof(unsigned long long), h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(h->memb_hsums, 0, hn * sizeof(long long), h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(h->memb_nused, 0, sizeof(int), h->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(h->memb_X, X, (size_t)3 * n_vert * sizeof(double), hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess)
@@ -1327,6 +1459,7 @@ static int set_surface(ii_lbm3_handle* h, int32_t n_vert, const double* X, int32
     h->memb_nv = n_vert;
     h->memb_nt = n_tri;
     h->memb_cap = cap;
+    h->memb_hbits = hbits;
     h->memb_gamma = gamma;
     h->memb_law = law;
     return II_LBM_OK;
@@ -1365,7 +1498,7 @@ int ii_lbm3_set_free_sphere(ii_lbm3_handle* h, int32_t n_vert, const double* X, 
         b.U[k] = b.Up[k] = U0[k];
         b.W[k] = b.Wp[k] = W0[k];
     }
-    hipError_t e = hipMalloc(&h->body3, sizeof(Body3));
+    hipError_t e = dmalloc(h, &h->body3, sizeof(Body3));
     if (e == hipSuccess) e = hipMemcpyAsync(h->body3, &b, sizeof b, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) {
@@ -1455,9 +1588,8 @@ int ii_lbm3_destroy(ii_lbm3_handle* h)
     (void)hipStreamSynchronize(h->stream);
     free_mesh(h);
     free_membrane(h);
-    for (auto& p : h->lat)
-        if (p) (void)hipFree(p);
-    if (h->g) (void)hipFree(h->g);
+    for (auto& p : h->lat) dfree(h, p);
+    dfree(h, h->g);
     for (auto& ev : h->ev) (void)hipEventDestroy(ev);
     delete h;
     return II_LBM_OK;

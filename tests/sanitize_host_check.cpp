@@ -186,6 +186,9 @@ int main()
     ii_lbm3_problem bad3 = p3;
     bad3.nx = 4;
     EXPECT(ii_lbm3_init(&bad3, nullptr, nullptr, &h3) == II_LBM_EINVAL && h3 == nullptr);
+    ii_lbm3_allocator half = {nullptr, nullptr, nullptr};
+    EXPECT(ii_lbm3_init_with(&p3, nullptr, nullptr, &half, &h3) == II_LBM_EINVAL && h3 == nullptr);
+    EXPECT(ii_lbm3_init_with(&bad3, nullptr, nullptr, nullptr, &h3) == II_LBM_EINVAL && h3 == nullptr);
 
     if (failures) {
         fprintf(stderr, "%d expectation(s) failed\n", failures);

@@ -78,6 +78,32 @@ def test_normal_force_sphere_from_rest(B, mode, coll):
     sim.close()
 
 
+def test_device_memory_from_torch_or_hipmalloc(B):
+    # A handle on PyTorch's allocator (the binding's default) holds its
+    # buffers as torch tensors while it lives and returns all of them on
+    # destroy; its results equal those of a handle on the library's own
+    # hipMalloc bit for bit (IB-LBM sphere: lattices plus the force field).
+    import torch
+    prob, X, meta = W.normal_force_sphere(16, W.FORCE_IB_LBM, re=20.0)
+    _say(f"D3Q19 IB sphere {prob.nx}^3: device memory from torch vs hipMalloc, 50 steps")
+    before = torch.cuda.memory_allocated()
+    a = B.Sim3(prob, X, torch_memory=True)
+    lat = 2 * 19 * ((prob.nx + 63) // 64 * 64) * prob.ny * prob.nz * 4
+    held = a.mem.bytes_held()
+    assert held >= lat + 3 * prob.nx * prob.ny * prob.nz * 8
+    assert torch.cuda.memory_allocated() - before >= held
+    b = B.Sim3(prob, X, torch_memory=False)
+    a.step(50)
+    b.step(50)
+    ga, gb = a.fields(), b.fields()
+    assert all(np.array_equal(ga[k], gb[k]) for k in range(4))
+    assert np.abs(ga[1]).max() > 0.0
+    mem = a.mem
+    a.close()
+    b.close()
+    assert mem.bytes_held() == 0 and not mem.live
+
+
 def test_sphere_exact_state_holds_on_gpu(B):
     prob, _, meta = W.normal_force_sphere(16, W.FORCE_II_LBM, re=20.0)
     sim = B.Sim3(prob)
