@@ -285,8 +285,10 @@ class Sim:
         check(load().ii_lbm_get_timing(self.h, C.byref(ms), C.byref(n)), "get_timing")
         return ms.value, n.value
 
-    def set_graph(self, enable: bool) -> None:
-        check(load().ii_lbm_set_graph(self.h, 1 if enable else 0), "set_graph")
+    def set_graph(self, enable: bool, steps: int = 0) -> None:
+        """HIP-graph replay on or off; steps: length of the long graph (even,
+        0 = the library's default)."""
+        check(load().ii_lbm_set_graph(self.h, (int(steps) if steps else 1) if enable else 0), "set_graph")
 
     def set_isolation(self, enable: bool) -> None:
         check(load().ii_lbm_set_isolation(self.h, 1 if enable else 0), "set_isolation")

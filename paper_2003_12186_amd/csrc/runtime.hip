@@ -322,8 +322,10 @@ struct ii_lbm_handle {
     double tuned_step_us = 0.0;    // the autotuner's fastest whole step
     // hipGraph replay of two steps (one graph per starting parity)
     bool use_graph = false;
+    int graph_steps = 16;          // steps of the long graph (even; 2: the pair only)
     hipStream_t cap_stream = nullptr;
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};       // two steps, per starting parity
+    hipGraphExec_t gexec_long[2] = {nullptr, nullptr};  // graph_steps steps
     // Membranes: the interface work of step m+1 runs on `aux` while the
     // sweep of step m runs on the main stream (fork/join through events).
     bool lookahead = false;
@@ -603,6 +605,11 @@ static void drop_graphs(ii_lbm_handle* h)
             (void)hipGraphExecDestroy(g);
             g = nullptr;
         }
+    for (auto& g : h->gexec_long)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
 }
 
 // Blocks of the batched tile pass.  per_cu = 0: one block per estimated
@@ -642,8 +649,9 @@ static hipError_t upload_tile_table(ii_lbm_handle* h, int per_cu)
     return e;
 }
 
-// Two steps starting at parity `par`, captured on the handle's own stream.
-static hipError_t build_graph(ii_lbm_handle* h, int par)
+// n (even) steps starting at parity `par`, captured on the handle's own
+// stream into *out.
+static hipError_t build_graph(ii_lbm_handle* h, int par, int n, hipGraphExec_t* out)
 {
     if (!h->cap_stream) {
         hipError_t e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
@@ -652,25 +660,30 @@ static hipError_t build_graph(ii_lbm_handle* h, int par)
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
-    hipError_t e1 = enqueue_step(h, par, h->cap_stream, false);
-    if (e1 == hipSuccess) e1 = enqueue_step(h, par ^ 1, h->cap_stream, false);
+    hipError_t e1 = hipSuccess;
+    for (int k = 0; k < n && e1 == hipSuccess; k++) e1 = enqueue_step(h, par ^ (k & 1), h->cap_stream, false);
     e = hipStreamEndCapture(h->cap_stream, &g);
     if (e1 != hipSuccess) e = e1;
-    if (e == hipSuccess) e = hipGraphInstantiate(&h->gexec[par], g, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     if (g) (void)hipGraphDestroy(g);
     return e;
 }
 
-// Both graphs (one per starting parity) at once: an odd number of direct
-// steps between replays flips the parity, and the other graph must not be
-// captured and instantiated in the middle of a caller's timed loop.
+// Every graph (pair and long, one of each per starting parity) at once: an
+// odd number of direct steps between replays flips the parity, and no graph
+// may be captured and instantiated in the middle of a caller's timed loop.
 static hipError_t ensure_graphs(ii_lbm_handle* h)
 {
-    for (int par = 0; par < 2; par++)
+    for (int par = 0; par < 2; par++) {
         if (!h->gexec[par]) {
-            const hipError_t e = build_graph(h, par);
+            const hipError_t e = build_graph(h, par, 2, &h->gexec[par]);
             if (e != hipSuccess) return e;
         }
+        if (h->graph_steps > 2 && !h->gexec_long[par]) {
+            const hipError_t e = build_graph(h, par, h->graph_steps, &h->gexec_long[par]);
+            if (e != hipSuccess) return e;
+        }
+    }
     return hipSuccess;
 }
 
@@ -967,11 +980,17 @@ int ii_lbm_step(ii_lbm_handle* h, int64_t n_steps)
             const hipError_t e = ensure_graphs(h);
             if (e != hipSuccess) return hip_fail(h, e);
         }
-        while (left >= 2) {
-            const int par = h->parity;
-            const hipError_t e = hipGraphLaunch(h->gexec[par], h->stream);
+        // an even number of steps leaves the parity unchanged
+        while (h->graph_steps > 2 && left >= h->graph_steps) {
+            const hipError_t e = hipGraphLaunch(h->gexec_long[h->parity], h->stream);
             if (e != hipSuccess) return hip_fail(h, e);
-            h->steps += 2;   // two parity flips leave the parity unchanged
+            h->steps += h->graph_steps;
+            left -= h->graph_steps;
+        }
+        while (left >= 2) {
+            const hipError_t e = hipGraphLaunch(h->gexec[h->parity], h->stream);
+            if (e != hipSuccess) return hip_fail(h, e);
+            h->steps += 2;
             left -= 2;
         }
     }
@@ -1057,7 +1076,10 @@ int ii_lbm_instance_errors(ii_lbm_handle* h, int32_t* bits, int32_t n)
 
 int ii_lbm_set_graph(ii_lbm_handle* h, int32_t enable)
 {
-    if (!h) return II_LBM_EINVAL;
+    if (!h || enable < 0 || enable > 256 || (enable > 1 && enable % 2 != 0)) return II_LBM_EINVAL;
+    const int steps = enable <= 1 ? 16 : enable;
+    if (steps != h->graph_steps) drop_graphs(h);
+    h->graph_steps = steps;
     h->use_graph = enable != 0;
     if (!h->use_graph) {
         drop_graphs(h);

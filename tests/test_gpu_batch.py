@@ -74,20 +74,27 @@ def test_graph_replay_equals_direct_launches(B, case):
     a = B.Sim(probs, X0)
     b = B.Sim(probs, X0)
     b.set_graph(True)
-    for rep in range(4):                  # several replays with eager work in between
-        a.step(10)
-        b.step(10)
+    # several replays with eager work in between: pair graphs only (10), long
+    # graphs of 16 steps plus pairs (37, 16) and an odd count's direct step
+    # (37, 3)
+    done = 0
+    for rep, n in enumerate((10, 37, 16, 10, 3)):
+        a.step(n)
+        b.step(n)
+        done += n
         for j in range(len(ws)):
             fa = a.fields(B.F_DISTRIB, inst=j, dtype=np.float32)
             fb = b.fields(B.F_DISTRIB, inst=j, dtype=np.float32)
             assert np.array_equal(fa, fb), (rep, j)
-    a.step(3)                             # odd count: graph pairs plus one direct step
-    b.step(3)
+            assert np.array_equal(a.markers(j)[0], b.markers(j)[0])
+    assert b.diag()["step"] == done
+    b.set_graph(True, steps=4)            # another long-graph length
+    a.step(9)
+    b.step(9)
     for j in range(len(ws)):
         assert np.array_equal(a.fields(B.F_DISTRIB, inst=j, dtype=np.float32),
                               b.fields(B.F_DISTRIB, inst=j, dtype=np.float32))
-        assert np.array_equal(a.markers(j)[0], b.markers(j)[0])
-    assert b.diag()["step"] == 43
+    assert b.diag()["step"] == done + 9
     a.close()
     b.close()
 
