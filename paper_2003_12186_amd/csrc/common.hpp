@@ -106,6 +106,7 @@ struct DevPtrs {
     int* tile_list;        // chord ids per tile
     int* tile_slot[2];     // correction slot of a tile at step m (plane m & 1), -1 when none
     float* corr[2];        // per slot: kCorrPlanes x 256 (population additions, then g)
+    unsigned long long* cmask[2];   // per slot: 4 words, bit n set when node n has corrections
     int2* act_list[2];     // (instance, tile) of the tiles that hold chords, by parity
     int* act_count;        // [2 * n_inst], double-buffered by step parity
     ii_lbm_link* rec;      // cut-link records
@@ -534,6 +535,15 @@ __device__ __forceinline__ void collide_guo_srt(M d[9], M omega, M gx, M gy, con
 #pragma unroll
         for (int i = 0; i < 9; i++) d[i] = d[i] + ((omega * (e[i] - d[i]) + h * G[i]) + x[i]);
     }
+}
+
+// Whether node `node` (0 ... 255, row-major in its tile) of correction slot
+// `slot` holds corrections: only those nodes' planes are written by the tile
+// pass (most nodes of an interface tile have none).
+__device__ __forceinline__ bool corr_present(const unsigned long long* __restrict__ cmask, int slot,
+                                             int node)
+{
+    return (cmask[(long long)slot * 4 + (node >> 6)] >> (node & 63)) & 1ull;
 }
 
 // Work tables of the batched launches: one entry (instance, unit) per block.

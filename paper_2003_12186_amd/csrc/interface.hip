@@ -100,9 +100,9 @@ __device__ __forceinline__ void markers_body(const InstDev& I, const DevPtrs& P,
                 if (!(MODE & kModeGeom)) {
                     const int slot =
                         P.tile_slot[par][I.tile_off + (ys / kTile) * I.tiles_x + (xs / kTile)];
-                    if (slot >= 0) {
-                        const float* c = P.corr[par] + (long long)slot * kCorrPlanes * kTileNodes +
-                                         (ys % kTile) * kTile + (xs % kTile);
+                    const int node = (ys % kTile) * kTile + (xs % kTile);
+                    if (slot >= 0 && corr_present(P.cmask[par], slot, node)) {
+                        const float* c = P.corr[par] + (long long)slot * kCorrPlanes * kTileNodes + node;
                         gx += (double)c[8 * kTileNodes];
                         gy += (double)c[9 * kTileNodes];
                     }
@@ -754,20 +754,33 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
         // term of the spread force plus the jumps of the links it sends; the
         // sweep adds them before its single store.  Under Guo's term the
         // populations take the jumps alone and the force itself follows.
+        // Only nodes with a non-zero correction are written; the slot's mask
+        // tells the readers which.
         {
             float* cr = P.corr[parity] + (long long)(I.act_off + a) * kCorrPlanes * kTileNodes + tid;
             const double fs = I.guo ? 0.0 : 3.0;
+            float dl[8];
+            bool nz = false;
 #pragma unroll
             for (int i = 1; i < 9; i++) {
                 const double delta =
                     valid ? fs * WD[i] * ((double)EX[i] * gx + (double)EY[i] * gy) +
                                 jump_sum(S.acc[i - 1][tid], jscale)
                           : 0.0;
-                cr[(i - 1) * kTileNodes] = (float)delta;
+                dl[i - 1] = (float)delta;
+                nz = nz || dl[i - 1] != 0.f;
             }
-            if (I.guo) {
-                cr[8 * kTileNodes] = valid ? (float)gx : 0.f;
-                cr[9 * kTileNodes] = valid ? (float)gy : 0.f;
+            const float fgx = valid ? (float)gx : 0.f, fgy = valid ? (float)gy : 0.f;
+            if (I.guo) nz = nz || fgx != 0.f || fgy != 0.f;
+            const unsigned long long m = __ballot(nz);
+            if (lane == 0) P.cmask[parity][(long long)(I.act_off + a) * 4 + wid] = m;
+            if (nz) {
+#pragma unroll
+                for (int i = 0; i < 8; i++) cr[i * kTileNodes] = dl[i];
+                if (I.guo) {
+                    cr[8 * kTileNodes] = fgx;
+                    cr[9 * kTileNodes] = fgy;
+                }
             }
         }
         // Records of this tile: one global slice for the block; each is
@@ -1097,7 +1110,9 @@ __device__ void tiles_spline_body(const InstDev& I, const DevPtrs& P, int parity
         }
         __syncthreads();
         {
+            // every node written (the mask marks all of them)
             float* cr = P.corr[parity] + (long long)(I.act_off + a) * kCorrPlanes * kTileNodes + tid;
+            if (lane == 0) P.cmask[parity][(long long)(I.act_off + a) * 4 + wid] = ~0ull;
             const double fs = I.guo ? 0.0 : 3.0;
 #pragma unroll
             for (int i = 1; i < 9; i++) {
@@ -1214,8 +1229,10 @@ __device__ __forceinline__ void tiles_ib_body(const InstDev& I, const DevPtrs& P
             }
         }
         // the simple force term of g for the sweep (none under Guo's term,
-        // whose sweep reads g itself), and g for the marker velocity
+        // whose sweep reads g itself), and g for the marker velocity; every
+        // node written (the mask marks all of them)
         float* cr = P.corr[parity] + (long long)(I.act_off + a) * kCorrPlanes * kTileNodes + tid;
+        if ((tid & 63) == 0) P.cmask[parity][(long long)(I.act_off + a) * 4 + (tid >> 6)] = ~0ull;
         const double fs = I.guo ? 0.0 : 3.0;
 #pragma unroll
         for (int i = 1; i < 9; i++)

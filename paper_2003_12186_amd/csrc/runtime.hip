@@ -64,6 +64,7 @@ struct Layout {
     size_t off_lat[2] = {0, 0};
     size_t off_X[2] = {0, 0}, off_U = 0, off_G = 0, off_Gt = 0, off_jp = 0, off_wx = 0, off_wy = 0, off_f0 = 0;
     size_t off_tile_count = 0, off_tile_list = 0, off_tile_slot[2] = {0, 0}, off_corr[2] = {0, 0};
+    size_t off_cmask[2] = {0, 0};
     size_t off_act_list[2] = {0, 0}, off_act_count = 0;
     size_t off_rec = 0, off_rec_count = 0, off_err = 0, off_diag = 0, off_body = 0;
     size_t off_M = 0, off_taps = 0;
@@ -265,6 +266,7 @@ int build_layout(const ii_lbm_problem* p, int n_inst, Layout& L)
     for (int q = 0; q < 2; q++) {
         L.off_tile_slot[q] = take((size_t)tiles * sizeof(int));
         L.off_corr[q] = take((size_t)std::max(act, 1) * kCorrPlanes * kTileNodes * sizeof(float));
+        L.off_cmask[q] = take((size_t)std::max(act, 1) * 4 * sizeof(unsigned long long));
     }
     L.off_act_list[0] = take((size_t)std::max(act, 1) * sizeof(int2));
     L.off_act_list[1] = take((size_t)std::max(act, 1) * sizeof(int2));
@@ -806,6 +808,7 @@ int ii_lbm_init(const ii_lbm_problem* p, int32_t n_inst, const double* const* X0
     for (int q = 0; q < 2; q++) {
         P.tile_slot[q] = (int*)(h->ws + L.off_tile_slot[q]);
         P.corr[q] = (float*)(h->ws + L.off_corr[q]);
+        P.cmask[q] = (unsigned long long*)(h->ws + L.off_cmask[q]);
     }
     P.act_list[0] = (int2*)(h->ws + L.off_act_list[0]);
     P.act_list[1] = (int2*)(h->ws + L.off_act_list[1]);

@@ -21,7 +21,8 @@ template <typename T, typename M, int COLL, bool BOUNDED, bool GUO>
 __device__ __forceinline__ void sweep_node(const InstDev& I, const T* __restrict__ A,
                                            T* __restrict__ B, int x, int y,
                                            const int* __restrict__ tile_slot,
-                                           const float* __restrict__ corr)
+                                           const float* __restrict__ corr,
+                                           const unsigned long long* __restrict__ cmask)
 {
     M d[9];
     if (BOUNDED && is_edge(I, x, y))
@@ -37,8 +38,9 @@ __device__ __forceinline__ void sweep_node(const InstDev& I, const T* __restrict
     M gx = (M)I.body[0], gy = (M)I.body[1];
     if (I.n_markers > 0) {
         const int slot = tile_slot[I.tile_off + (y / kTile) * I.tiles_x + (x / kTile)];
-        if (slot >= 0) {
-            const float* c = corr + (long long)slot * kCorrPlanes * kTileNodes + (y % kTile) * kTile + (x % kTile);
+        const int node = (y % kTile) * kTile + (x % kTile);
+        if (slot >= 0 && corr_present(cmask, slot, node)) {
+            const float* c = corr + (long long)slot * kCorrPlanes * kTileNodes + node;
 #pragma unroll
             for (int i = 1; i < 9; i++) xc[i] = (M)c[(i - 1) * kTileNodes];
             if constexpr (GUO) {
@@ -68,7 +70,8 @@ template <typename T, typename M, int COLL, bool BOUNDED, int BX, bool GUO>
 __global__ __launch_bounds__(BX) void k_sweep(InstDev I, const T* __restrict__ A,
                                               T* __restrict__ B, int bx_count,
                                               const int* __restrict__ tile_slot,
-                                              const float* __restrict__ corr)
+                                              const float* __restrict__ corr,
+                                              const unsigned long long* __restrict__ cmask)
 {
     // the interface pass of the next step may share the CUs: the sweep's
     // waves issue first
@@ -76,7 +79,7 @@ __global__ __launch_bounds__(BX) void k_sweep(InstDev I, const T* __restrict__ A
     const int bx = blockIdx.x % bx_count, y = blockIdx.x / bx_count;
     const int x = bx * BX + threadIdx.x;
     if (x >= I.nx) return;
-    sweep_node<T, M, COLL, BOUNDED, GUO>(I, A, B, x, y, tile_slot, corr);
+    sweep_node<T, M, COLL, BOUNDED, GUO>(I, A, B, x, y, tile_slot, corr, cmask);
 }
 
 // Batched: block b sweeps `UNIT` consecutive nodes (row-major) of one
@@ -86,7 +89,8 @@ __global__ __launch_bounds__(UNIT) void k_sweep_batch(const InstDev* __restrict_
                                                       const int2* __restrict__ units,
                                                       const T* __restrict__ A, T* __restrict__ B,
                                                       const int* __restrict__ tile_slot,
-                                                      const float* __restrict__ corr)
+                                                      const float* __restrict__ corr,
+                                                      const unsigned long long* __restrict__ cmask)
 {
     __builtin_amdgcn_s_setprio(3);
     const int2 u = units[blockIdx.x];
@@ -97,14 +101,14 @@ __global__ __launch_bounds__(UNIT) void k_sweep_batch(const InstDev* __restrict_
     const int y = r / I.nx, x = r - y * I.nx;
     if (I.collision == II_LBM_SRT) {
         if (I.bounded)
-            sweep_node<T, M, II_LBM_SRT, true, GUO>(I, A, B, x, y, tile_slot, corr);
+            sweep_node<T, M, II_LBM_SRT, true, GUO>(I, A, B, x, y, tile_slot, corr, cmask);
         else
-            sweep_node<T, M, II_LBM_SRT, false, GUO>(I, A, B, x, y, tile_slot, corr);
+            sweep_node<T, M, II_LBM_SRT, false, GUO>(I, A, B, x, y, tile_slot, corr, cmask);
     } else {
         if (I.bounded)
-            sweep_node<T, M, II_LBM_MRT, true, GUO>(I, A, B, x, y, tile_slot, corr);
+            sweep_node<T, M, II_LBM_MRT, true, GUO>(I, A, B, x, y, tile_slot, corr, cmask);
         else
-            sweep_node<T, M, II_LBM_MRT, false, GUO>(I, A, B, x, y, tile_slot, corr);
+            sweep_node<T, M, II_LBM_MRT, false, GUO>(I, A, B, x, y, tile_slot, corr, cmask);
     }
 }
 
@@ -116,15 +120,18 @@ static hipError_t sweep_batch_g(const Batch& b, const DevPtrs& P, const void* A,
     switch (b.sweep_unit) {
     case 128:
         hipLaunchKernelGGL((k_sweep_batch<T, M, 128, GUO>), g, dim3(128), 0, s, b.insts,
-                           b.sweep_table, (const T*)A, (T*)B, P.tile_slot[par], P.corr[par]);
+                           b.sweep_table, (const T*)A, (T*)B, P.tile_slot[par], P.corr[par],
+                           P.cmask[par]);
         break;
     case 512:
         hipLaunchKernelGGL((k_sweep_batch<T, M, 512, GUO>), g, dim3(512), 0, s, b.insts,
-                           b.sweep_table, (const T*)A, (T*)B, P.tile_slot[par], P.corr[par]);
+                           b.sweep_table, (const T*)A, (T*)B, P.tile_slot[par], P.corr[par],
+                           P.cmask[par]);
         break;
     default:
         hipLaunchKernelGGL((k_sweep_batch<T, M, 256, GUO>), g, dim3(256), 0, s, b.insts,
-                           b.sweep_table, (const T*)A, (T*)B, P.tile_slot[par], P.corr[par]);
+                           b.sweep_table, (const T*)A, (T*)B, P.tile_slot[par], P.corr[par],
+                           P.cmask[par]);
     }
     return hipGetLastError();
 }
@@ -155,10 +162,12 @@ static hipError_t sweep_b(const InstDev& I, const DevPtrs& P, const void* A, voi
     const int bxn = (I.nx + BX - 1) / BX;
     if (I.guo)
         hipLaunchKernelGGL((k_sweep<T, M, COLL, BOUNDED, BX, true>), dim3(bxn * I.ny), dim3(BX), 0,
-                           s, I, (const T*)A, (T*)B, bxn, P.tile_slot[par], P.corr[par]);
+                           s, I, (const T*)A, (T*)B, bxn, P.tile_slot[par], P.corr[par],
+                           P.cmask[par]);
     else
         hipLaunchKernelGGL((k_sweep<T, M, COLL, BOUNDED, BX, false>), dim3(bxn * I.ny), dim3(BX),
-                           0, s, I, (const T*)A, (T*)B, bxn, P.tile_slot[par], P.corr[par]);
+                           0, s, I, (const T*)A, (T*)B, bxn, P.tile_slot[par], P.corr[par],
+                           P.cmask[par]);
     return hipGetLastError();
 }
 
