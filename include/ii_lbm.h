@@ -357,9 +357,10 @@ int ii_lbm_autotune(ii_lbm_handle* h, int32_t trials, int32_t* unit, int32_t* or
 /* Footprint of a batched handle's tile pass: about per_cu blocks per compute
  * unit in all (1 ... 64), shared among the instances in proportion to their
  * estimated interface tiles, each block walking several tiles; 0 (the
- * initial setting) gives one block per estimated tile.  Results do not
- * depend on it.  Synchronises the handle; a single-instance handle ignores
- * it (EINVAL for per_cu outside 0 ... 64). */
+ * initial setting) gives one block per estimated tile.  A single-instance
+ * membrane handle runs per_cu blocks per CU (0: one, the initial setting)
+ * when its tile pass runs beside the sweep.  Results do not depend on it.
+ * Synchronises a batched handle; EINVAL for per_cu outside 0 ... 64. */
 int ii_lbm_set_tile_blocks(ii_lbm_handle* h, int32_t per_cu);
 
 /* The batched schedule in use: sweep slice size, instance order, tile-pass

@@ -704,11 +704,13 @@ static void size_tile_blocks(ii_lbm_handle* h)
 {
     if (h->batched) return;
     const bool beside = h->lookahead && h->overlap != II_LBM_OVERLAP_SERIAL;
+    const int per_cu = h->tile_per_cu > 0 ? h->tile_per_cu : 1;
     // the spline's tile pass carries root finding and is the step's critical
     // path even beside the sweep: it keeps every block
     for (InstDev& I : h->L.inst)
         if (I.n_markers > 0)
-            I.tile_blocks = std::max(1, std::min(I.act_cap, beside && I.geometry != 1 ? h->n_cu : 2048));
+            I.tile_blocks =
+                std::max(1, std::min(I.act_cap, beside && I.geometry != 1 ? per_cu * h->n_cu : 2048));
 }
 
 static void release(ii_lbm_handle* h)
@@ -1177,7 +1179,13 @@ int ii_lbm_set_tile_blocks(ii_lbm_handle* h, int32_t per_cu)
 {
     if (!h || per_cu < 0 || per_cu > 64) return II_LBM_EINVAL;
     if (h->failed) return II_LBM_ESTATE;
-    if (!h->batched) return II_LBM_OK;
+    if (!h->batched) {
+        // single instance: per_cu blocks per CU beside the sweep (0: one)
+        h->tile_per_cu = per_cu;
+        drop_graphs(h);
+        size_tile_blocks(h);
+        return II_LBM_OK;
+    }
     hipError_t e = hipStreamSynchronize(h->stream);
     if (e == hipSuccess && h->aux) e = hipStreamSynchronize(h->aux);
     if (e == hipSuccess) e = upload_tile_table(h, per_cu);
@@ -1190,7 +1198,7 @@ int ii_lbm_get_schedule(ii_lbm_handle* h, int32_t* unit, int32_t* order, int32_t
     if (!h) return II_LBM_EINVAL;
     if (unit) *unit = h->batched ? h->batch.sweep_unit : 0;
     if (order) *order = h->batched ? h->sweep_order : 0;
-    if (tile_per_cu) *tile_per_cu = h->batched ? h->tile_per_cu : 0;
+    if (tile_per_cu) *tile_per_cu = h->tile_per_cu;
     if (step_us) *step_us = h->tuned_step_us;
     return II_LBM_OK;
 }
