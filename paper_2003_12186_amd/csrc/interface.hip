@@ -261,24 +261,6 @@ __device__ __forceinline__ void markers_body(const InstDev& I, const DevPtrs& P,
     }
 }
 
-template <typename T, typename M, int MODE>
-__global__ __launch_bounds__(256) void k_markers(InstDev I, DevPtrs P, const T* __restrict__ A,
-                                                 int par)
-{
-    markers_body<T, M, MODE>(I, P, A, par, blockIdx.x);
-}
-
-// Batched: every block looks its (instance, block) up in a work table.
-template <typename T, typename M, int MODE>
-__global__ __launch_bounds__(256) void k_markers_batch(const InstDev* __restrict__ insts,
-                                                       const int2* __restrict__ units, DevPtrs P,
-                                                       const T* __restrict__ A, int par)
-{
-    const int2 u = units[blockIdx.x];
-    const InstDev I = insts[u.x];
-    markers_body<T, M, MODE>(I, P, A, par, u.y);
-}
-
 // Before the tiles of step m are binned: the tiles of step m-2 (same slot
 // plane) give their correction slots back, and the active-tile and record
 // counts of that plane restart.  One block per instance.
@@ -293,6 +275,29 @@ __device__ __forceinline__ void slot_reset_body(const InstDev& I, const DevPtrs&
         P.act_count[2 * I.inst + par] = 0;
         P.rec_count[2 * I.inst + par] = 0;
     }
+}
+
+template <typename T, typename M, int MODE>
+__global__ __launch_bounds__(256) void k_markers(InstDev I, DevPtrs P, const T* __restrict__ A,
+                                                 int par)
+{
+    // The interpolation of step m also resets the slot plane of step m+1
+    // (last read by the sweep of step m-1, which has finished), saving the
+    // interface pass of step m+1 a launch of its own.
+    if (MODE == kModeInterp && blockIdx.x == 0) slot_reset_body(I, P, par ^ 1);
+    markers_body<T, M, MODE>(I, P, A, par, blockIdx.x);
+}
+
+// Batched: every block looks its (instance, block) up in a work table.
+template <typename T, typename M, int MODE>
+__global__ __launch_bounds__(256) void k_markers_batch(const InstDev* __restrict__ insts,
+                                                       const int2* __restrict__ units, DevPtrs P,
+                                                       const T* __restrict__ A, int par)
+{
+    const int2 u = units[blockIdx.x];
+    const InstDev I = insts[u.x];
+    if (MODE == kModeInterp && u.y == 0) slot_reset_body(I, P, par ^ 1);   // as in k_markers
+    markers_body<T, M, MODE>(I, P, A, par, u.y);
 }
 
 __global__ __launch_bounds__(256) void k_slot_reset(InstDev I, DevPtrs P, int par)

@@ -440,16 +440,17 @@ static hipError_t upload_sweep_table(ii_lbm_handle* h, int unit, int order)
     return e;
 }
 
-// Interface phases of one step on stream s: slot/count reset of plane `par`,
-// the marker pass (`mode`), then the tile pass (with the cut-link records
-// when `records`).
+// Interface phases of one step on stream s: slot/count reset of plane `par`
+// (unless the interpolation just before did it: `reset` false), the marker
+// pass (`mode`), then the tile pass (with the cut-link records when
+// `records`).
 static hipError_t enqueue_interface(ii_lbm_handle* h, int par, int mode, hipStream_t s,
-                                    bool records)
+                                    bool records, bool reset = true)
 {
     void* A = h->P.lat[par];
     hipError_t e = hipSuccess;
     if (h->batched) {
-        e = launch_slot_reset_batch(h->batch, (int)h->L.inst.size(), h->P, par, s);
+        if (reset) e = launch_slot_reset_batch(h->batch, (int)h->L.inst.size(), h->P, par, s);
         if (e == hipSuccess) e = launch_markers_batch(h->batch, h->P, A, par, mode, s);
         if (e == hipSuccess) e = launch_tiles_batch(h->batch, h->P, par, records, s);
         return e;
@@ -457,7 +458,7 @@ static hipError_t enqueue_interface(ii_lbm_handle* h, int par, int mode, hipStre
     for (size_t j = 0; j < h->L.inst.size() && e == hipSuccess; j++) {
         const InstDev& I = h->L.inst[j];
         if (I.n_markers == 0) continue;
-        e = launch_slot_reset(I, h->P, par, s);
+        if (reset) e = launch_slot_reset(I, h->P, par, s);
         if (e == hipSuccess && I.geometry == 1) e = launch_spline(I, h->P, par, s);
         if (e == hipSuccess) e = launch_markers(I, h->P, A, par, mode, s);
         if (e == hipSuccess) e = launch_tiles(I, h->P, par, records, s);
@@ -529,7 +530,7 @@ static hipError_t enqueue_step(ii_lbm_handle* h, int par, hipStream_t s, bool ti
     if (h->lookahead && h->overlap == II_LBM_OVERLAP_SERIAL) {
         e = enqueue_sweep(h, par, s, timed);
         if (e == hipSuccess) e = enqueue_interp(h, par, s);
-        if (e == hipSuccess) e = enqueue_interface(h, par ^ 1, kModeGeom, s, false);
+        if (e == hipSuccess) e = enqueue_interface(h, par ^ 1, kModeGeom, s, false, false);
         if (lrn) {
             if (e == hipSuccess) e = enqueue_learned(h, par ^ 1, s, learned_band);
             if (e == hipSuccess) e = enqueue_learned(h, par ^ 1, s, learned_geom);
@@ -555,7 +556,7 @@ static hipError_t enqueue_step(ii_lbm_handle* h, int par, hipStream_t s, bool ti
             if (e == hipSuccess) e = enqueue_learned(h, par ^ 1, h->lrn, learned_geom);
             if (e == hipSuccess) e = hipEventRecord(h->ev_g, h->lrn);
         }
-        if (e == hipSuccess) e = enqueue_interface(h, par ^ 1, kModeGeom, h->aux, false);
+        if (e == hipSuccess) e = enqueue_interface(h, par ^ 1, kModeGeom, h->aux, false, false);
         if (e == hipSuccess) e = enqueue_sweep(h, par, s, timed);
         if (lrn) {
             // patch flow and the network need the swept lattice; the interface
