@@ -1168,7 +1168,9 @@ def bench_batch(args, B, W) -> int:
                    "failed_instances": {str(j): int(bits[j]) for j in failed}},
         "roofline": {"bound": "hbm", "kernel": "k_sweep_batch", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "bytes_per_launch": bytes_per_launch,
+                     "traffic": (measured_traffic(f"batch512_{args.storage}_u{tune['unit']}")
+                                 if len(ws) == 512 else None),
+                     "bytes_per_launch": bytes_per_launch,
                      "avg_launch_us": round(avg * 1e6, 2), "timed_launches": launches},
     }
     sim.close()
