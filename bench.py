@@ -1238,7 +1238,7 @@ def main() -> int:
     if args.steps is None:
         args.steps = {"batch512": 4000, "cylinder": 20000, "viv": 150000}.get(args.workload, 2000)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the design notes describe how the lattice would shard).", file=sys.stderr)
         return 2
 
