@@ -601,27 +601,6 @@ def bench_table1(args, B, W) -> int:
     sim.set_timing(False)
     avg = ms / 1e3 / max(launches, 1)
     bpl = sim.sweep_bytes()
-    if memb is not None and args.d3_surface == "free":
-        bs = sim.body()
-        mesh_info.update({"steps_run": args.warmup + args.steps + min(args.steps, 200),
-                          "centre_shift": [round(float(bs[k] - cf[k]), 6) for k in range(3)],
-                          "velocity": [float(v) for v in bs[3:6]]})
-    elif memb is not None and args.d3_surface == "rigid":
-        F = sim.surface_force()
-        mesh_info.update({"steps_run": args.warmup + args.steps + min(args.steps, 200),
-                          "force_over_gL3": round(float(F[0] / (1e-7 * L ** 3)), 5)})
-    elif memb is not None:
-        Xn, _ = sim.membrane()
-        tri = memb[1]
-        def vol(X):
-            a, b_, c_ = X[tri[:, 0]], X[tri[:, 1]], X[tri[:, 2]]
-            return float(np.einsum("ij,ij->i", a, np.cross(b_, c_)).sum() / 6.0)
-        r = np.linalg.norm(Xn - Xn.mean(0), axis=1)
-        r0 = np.linalg.norm(memb[0] - memb[0].mean(0), axis=1)
-        total = args.warmup + args.steps + min(args.steps, 200)
-        mesh_info.update({"steps_run": total, "volume_change": round(vol(Xn) / vol(memb[0]) - 1.0, 5),
-                          "radius_spread_start": round(float(r0.std() / r0.mean()), 4),
-                          "radius_spread_end": round(float(r.std() / r.mean()), 4)})
     sim.close()
     n_steps = sum(r["steps"] for r in rows)
     out = {
@@ -1045,27 +1024,6 @@ def bench_viv(args, B, W) -> int:
     sim.set_timing(False)
     avg = ms / 1e3 / max(launches, 1)
     bpl = sim.sweep_bytes()
-    if memb is not None and args.d3_surface == "free":
-        bs = sim.body()
-        mesh_info.update({"steps_run": args.warmup + args.steps + min(args.steps, 200),
-                          "centre_shift": [round(float(bs[k] - cf[k]), 6) for k in range(3)],
-                          "velocity": [float(v) for v in bs[3:6]]})
-    elif memb is not None and args.d3_surface == "rigid":
-        F = sim.surface_force()
-        mesh_info.update({"steps_run": args.warmup + args.steps + min(args.steps, 200),
-                          "force_over_gL3": round(float(F[0] / (1e-7 * L ** 3)), 5)})
-    elif memb is not None:
-        Xn, _ = sim.membrane()
-        tri = memb[1]
-        def vol(X):
-            a, b_, c_ = X[tri[:, 0]], X[tri[:, 1]], X[tri[:, 2]]
-            return float(np.einsum("ij,ij->i", a, np.cross(b_, c_)).sum() / 6.0)
-        r = np.linalg.norm(Xn - Xn.mean(0), axis=1)
-        r0 = np.linalg.norm(memb[0] - memb[0].mean(0), axis=1)
-        total = args.warmup + args.steps + min(args.steps, 200)
-        mesh_info.update({"steps_run": total, "volume_change": round(vol(Xn) / vol(memb[0]) - 1.0, 5),
-                          "radius_spread_start": round(float(r0.std() / r0.mean()), 4),
-                          "radius_spread_end": round(float(r.std() / r.mean()), 4)})
     sim.close()
     n_steps = sum(r["steps"] for r in rows)
     out = {

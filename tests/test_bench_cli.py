@@ -44,3 +44,62 @@ def test_committed_traffic_table_is_well_formed():
                                               + e["write_kib_raw"] * e["write_scale"]) * 1024)
         # counters within a few per cent of the algorithmic bytes
         assert 0.99 < e["bytes_per_launch"] / e["algorithmic_bytes_per_launch"] < 1.1
+
+
+def _unbound_names(path):
+    """Names a function of `path` reads that no enclosing scope, the module
+    or the builtins bind (a NameError waiting for that code path)."""
+    import ast
+    import builtins
+    tree = ast.parse(open(path).read())
+    module = set(dir(builtins)) | {"__file__", "__name__"}
+    for node in tree.body:
+        if isinstance(node, (ast.FunctionDef, ast.ClassDef)):
+            module.add(node.name)
+        elif isinstance(node, (ast.Import, ast.ImportFrom)):
+            module.update((a.asname or a.name).split(".")[0] for a in node.names)
+        elif isinstance(node, (ast.Assign, ast.AnnAssign, ast.AugAssign)):
+            targets = node.targets if isinstance(node, ast.Assign) else [node.target]
+            module.update(n.id for t in targets for n in ast.walk(t) if isinstance(n, ast.Name))
+
+    def bound(fn):
+        b = {a.arg for a in ast.walk(fn.args) if isinstance(a, ast.arg)}
+        for n in ast.walk(fn):
+            if isinstance(n, ast.Name) and isinstance(n.ctx, (ast.Store, ast.Del)):
+                b.add(n.id)
+            elif isinstance(n, ast.FunctionDef) and n is not fn:
+                b.add(n.name)
+            elif isinstance(n, (ast.Import, ast.ImportFrom)):
+                b.update((a.asname or a.name).split(".")[0] for a in n.names)
+            elif isinstance(n, ast.ExceptHandler) and n.name:
+                b.add(n.name)
+            elif isinstance(n, ast.arg):
+                b.add(n.arg)
+        return b
+
+    bad = []
+
+    def visit(fn, outer):
+        scope = outer | bound(fn)
+        for n in ast.walk(fn):
+            if isinstance(n, ast.Name) and isinstance(n.ctx, ast.Load) and n.id not in scope:
+                bad.append((fn.name, n.id, n.lineno))
+        for n in ast.walk(fn):
+            if isinstance(n, ast.FunctionDef) and n is not fn:
+                visit(n, scope)
+
+    for node in tree.body:
+        if isinstance(node, ast.FunctionDef):
+            visit(node, module)
+    return sorted(set(bad))
+
+
+def test_bench_and_package_read_no_unbound_names():
+    # every workload of the bench is a separate code path that the default
+    # run never enters; a name left over from another function would only
+    # fail when that workload runs
+    for rel in ("bench.py", "__graft_entry__.py", os.path.join("paper_2003_12186_amd", "binding.py"),
+                os.path.join("paper_2003_12186_amd", "workloads.py"),
+                os.path.join("paper_2003_12186_amd", "train_learned.py"),
+                os.path.join("paper_2003_12186_amd", "learned.py")):
+        assert _unbound_names(os.path.join(ROOT, rel)) == [], rel
