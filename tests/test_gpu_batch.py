@@ -28,18 +28,20 @@ def B(require_gpu):
     return binding
 
 
-def _small_batch(n=6):
+def _small_batch(n=6, math_=W.MATH_FP64):
     ws = W.membrane_batch_c4(n_inst=64)
     ws = sorted(ws, key=lambda w: w.problem.nx)       # a spread of sizes
     pick = [ws[int(i)] for i in np.linspace(0, 63, n)]
     for w in pick:
-        w.problem.math = W.MATH_FP64
+        w.problem.math = math_
     return pick
 
 
-def test_batched_equals_single_and_oracle(B):
-    ws = _small_batch(6)
-    _say("batched membranes, sizes " + ", ".join(str(w.problem.nx) for w in ws) + ", 300 steps")
+@pytest.mark.parametrize("math_", [W.MATH_FP32, W.MATH_FP64])
+def test_batched_equals_single_and_oracle(B, math_):
+    ws = _small_batch(6, math_)
+    _say("batched membranes, sizes " + ", ".join(str(w.problem.nx) for w in ws) +
+         f", math={math_}, 300 steps")
     sim = B.Sim([w.problem for w in ws], [w.X0 for w in ws])
     tune = sim.autotune(3)
     _say(f"  autotune: {tune}")

@@ -47,11 +47,12 @@ def _oracle(prob, X0, steps, f0=None, force_hist=False):
     return {"X": X, "rho": rho, "ux": ux, "uy": uy, "fh": fh}
 
 
+@pytest.mark.parametrize("math_", [W.MATH_FP32, W.MATH_FP64])
 @pytest.mark.parametrize("collision", [W.SRT, W.MRT])
-def test_periodic_bulk_body_force_guo(B, collision):
+def test_periodic_bulk_body_force_guo(B, collision, math_):
     # Guo's collision alone: a noisy periodic bulk driven by a body force.
-    _say(f"periodic bulk 72x40 Guo body force collision={collision}, 300 steps")
-    prob = W.Problem(nx=72, ny=40, tau=0.7, collision=collision, math=W.MATH_FP64,
+    _say(f"periodic bulk 72x40 Guo body force collision={collision} math={math_}, 300 steps")
+    prob = W.Problem(nx=72, ny=40, tau=0.7, collision=collision, math=math_,
                      force_mode=W.FORCE_IB_LBM_GUO, body_force=(2e-6, -1e-6))
     _, _, w = O.d2q9()
     f0 = np.ascontiguousarray(w[:, None, None] * (1.0 + 1e-3 * W.seeded_noise((9, 40, 72), 51, collision)))
@@ -67,14 +68,15 @@ def test_periodic_bulk_body_force_guo(B, collision):
     sim.close()
 
 
+@pytest.mark.parametrize("math_", [W.MATH_FP32, W.MATH_FP64])
 @pytest.mark.parametrize("collision", [W.SRT, W.MRT])
 @pytest.mark.parametrize("mode", MODES)
-def test_membrane64_force_modes_1000_steps(B, mode, collision):
-    _say(f"membrane 64x64 force_mode={mode} collision={collision}, 1000 steps")
+def test_membrane64_force_modes_1000_steps(B, mode, collision, math_):
+    _say(f"membrane 64x64 force_mode={mode} collision={collision} math={math_}, 1000 steps")
     w = W.membrane_c1()
     w.problem.force_mode = mode
     w.problem.collision = collision
-    w.problem.math = W.MATH_FP64
+    w.problem.math = math_
     sim = B.Sim([w.problem], [w.X0])
     sim.step(1000)
     g = sim.fields(B.F_RHO | B.F_UX | B.F_UY)
@@ -96,14 +98,15 @@ def test_membrane64_force_modes_1000_steps(B, mode, collision):
     sim.close()
 
 
+@pytest.mark.parametrize("math_", [W.MATH_FP32, W.MATH_FP64])
 @pytest.mark.parametrize("mode", [W.FORCE_IB_LBM, W.FORCE_IB_LBM_GUO, W.FORCE_II_LBM_GUO])
-def test_cylinder_small_force_modes(B, mode):
+def test_cylinder_small_force_modes(B, mode, math_):
     # Direct forcing with the simple or Guo's term (u* of the body force only)
     # in the 128 x 64, D = 4 channel; velocity and drag/lift every 100 steps.
-    _say(f"cylinder channel 128x64 D=4 MRT Re=100 force_mode={mode}, 1000 steps")
+    _say(f"cylinder channel 128x64 D=4 MRT Re=100 force_mode={mode} math={math_}, 1000 steps")
     w = W.cylinder_c2(re=100.0, small=True)
     w.problem.force_mode = mode
-    w.problem.math = W.MATH_FP64
+    w.problem.math = math_
     sim = B.Sim([w.problem], [w.X0])
     fx = []
     for _ in range(10):

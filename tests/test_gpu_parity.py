@@ -1,10 +1,8 @@
 """GPU parity of the HIP II-LBM path (called through the C ABI) against the
 FP64 CPU oracle on the same seeded inputs.
 
-Tolerances: FP32 storage with FP64 collision arithmetic, relative L2 velocity
-<= 1e-6 after 1000 steps; FP32 storage with FP32 collision arithmetic
-<= 5e-6 (each stored value then carries about five FP32 roundings instead of
-one, measured 1.9e-6 .. 3.6e-6); scaled FP16 storage <= 1e-3; cut-link
+Tolerances: FP32 storage with FP32 or FP64 collision arithmetic, relative L2
+velocity <= 1e-6 after 1000 steps; scaled FP16 storage <= 1e-3; cut-link
 classification bit-exact (node, direction, sign and chord), with the FP64 cut
 fractions to 1e-12.
 """
