@@ -404,14 +404,15 @@ def test_membrane512_fp16_parity_1000_steps(B, math_):
     sim.close()
 
 
-def test_max_size_lattice_sampled_parity(B):
+@pytest.mark.parametrize("math_", [W.MATH_FP32, W.MATH_FP64])
+def test_max_size_lattice_sampled_parity(B, math_):
     # The largest lattice the library accepts (8192 x 8192, 604 M stored
     # values per buffer), one step from a structured state; every sampled node
     # (edges included, where the pull wraps) against the oracle's collision of
     # the nine upstream nodes.
-    _say("8192x8192 periodic bulk, 1 step, 96 sampled nodes vs oracle")
+    _say(f"8192x8192 periodic bulk, 1 step, 96 sampled nodes vs oracle, math={math_}")
     n = 8192
-    prob = W.Problem(nx=n, ny=n, tau=0.62, collision=W.SRT, body_force=(1e-6, -2e-6), math=W.MATH_FP64)
+    prob = W.Problem(nx=n, ny=n, tau=0.62, collision=W.SRT, body_force=(1e-6, -2e-6), math=math_)
     ex, ey, w = O.d2q9()
     xs = np.arange(n, dtype=np.float64)
     f0 = np.empty((9, n, n))
