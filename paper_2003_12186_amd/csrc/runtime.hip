@@ -603,6 +603,9 @@ static int ensure_records(ii_lbm_handle* h)
 
 static void drop_graphs(ii_lbm_handle* h)
 {
+    // replays run on the handle's stream: let any in flight finish first
+    if (h->gexec[0] || h->gexec[1] || h->gexec_long[0] || h->gexec_long[1])
+        (void)hipStreamSynchronize(h->stream);
     for (auto& g : h->gexec)
         if (g) {
             (void)hipGraphExecDestroy(g);
