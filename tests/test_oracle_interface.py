@@ -161,6 +161,29 @@ def test_cutlinks_chordwise_equals_bruteforce(k):
 
 
 @pytest.mark.parametrize("k", range(14))
+def test_cut_link_sources_lie_in_the_chord_candidate_box(k):
+    # The GPU tile pass tests, for chord (A, B) with snapped x-range [lo, hi],
+    # only source nodes P with ceil(lo) - 1 <= P.x <= ceil(hi) (and likewise
+    # in y): with the nodes shifted by the tie-breaking +eps, a link's x-span
+    # [P.x, P.x + e_x] + eps meets [lo, hi] only there.  Every cut link that
+    # the brute-force enumeration finds, ties included (vertices on nodes,
+    # edges along lattice lines and diagonals), must have its source in that
+    # box of the chord that cuts it.
+    X = _polys()[k]
+    n = len(X)
+    p = O.make_problem(W.Problem(nx=64, ny=64, tau=0.8, interface=W.IF_MEMBRANE,
+                                 n_markers=n, kappa=0.1, dX=1.0))
+    rec = O.cutlinks_bruteforce(p, X, (0, 50, 0, 50), np.linspace(-1, 1, n))
+    assert len(rec) > 0
+    S = np.rint(X * 65536.0) / 65536.0
+    for r in rec:
+        a, b = S[int(r["seg"])], S[(int(r["seg"]) + 1) % n]
+        for c, axis in ((int(r["x"]), 0), (int(r["y"]), 1)):
+            lo, hi = min(a[axis], b[axis]), max(a[axis], b[axis])
+            assert np.ceil(lo) - 1 <= c <= np.ceil(hi), (r, a, b)
+
+
+@pytest.mark.parametrize("k", range(14))
 def test_cutlinks_antisymmetric_and_match_inside_outside(k):
     X = _polys()[k]
     n = len(X)
