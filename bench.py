@@ -36,7 +36,7 @@ BF16_PEAK_TFLOPS = 2500.0   # dense MFMA
 # 24 -> 22 -> 20 -> 18 -> 16, channels 4 -> 32 -> 32 -> 32 -> 9
 CNN_FLOP_PER_TILE = 2 * (22 * 22 * 9 * 4 * 32 + 20 * 20 * 9 * 32 * 32 + 18 * 18 * 9 * 32 * 32
                          + 16 * 16 * 9 * 32 * 9)
-LEARNED_WEIGHTS = os.path.join(ROOT, "paper_2003_12186_amd", "data", "cnn_c5.npz")
+LEARNED_WEIGHTS = os.path.join(ROOT, "paper_2003_12186_amd", "data", "cnn_coarse256.npz")
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "sweep_traffic_membrane4096.json")
 SWEEP_SOURCES = [os.path.join(ROOT, "paper_2003_12186_amd", "csrc", n) for n in ("sweep.hip", "common.hpp")]
 
@@ -238,7 +238,7 @@ def bench_learned(args, B, W) -> int:
     from paper_2003_12186_amd import learned as LN
     n = args.instances or 200
     seeds = list(W.LEARNED_HELDOUT_SEEDS)[:n]
-    pairs = [W.learned_pair_c5(s) for s in seeds]
+    pairs = [W.learned_pair_coarse_fine(s) for s in seeds]
     d = np.load(LEARNED_WEIGHTS)
     net = LN.Net(d["params"])
     sc = LN.make_scales(d["in_scale"], float(d["out_scale"]) * args.alpha)
@@ -325,7 +325,7 @@ def bench_learned(args, B, W) -> int:
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 storage / fp32 collision; bf16 MFMA network, f32 accumulation",
         "data": "synthetic",
-        "config": {"workload": f"learned_c5_{n}", "instances": n, "coarse": 256, "fine": 512,
+        "config": {"workload": f"learned_coarse256_{n}", "instances": n, "coarse": 256, "fine": 512,
                    "markers": 512, "fine_steps_per_coarse": 4, "alpha": args.alpha,
                    "accuracy": accuracy,
                    "target_met": bool(accuracy["frac_within_1e-2_learned"] >= 0.95
@@ -365,7 +365,7 @@ def bench_cylinder(args, B, W) -> int:
     bandwidth is not an HBM figure."""
     import torch
     storage = W.STORE_FP16 if args.storage == "fp16" else W.STORE_FP32
-    w = W.cylinder_c2(re=args.re, storage=storage)
+    w = W.cylinder_channel(re=args.re, storage=storage)
     p = w.problem
     p.math = W.MATH_FP64 if args.math == "fp64" else W.MATH_FP32
     sim = B.Sim([p], [w.X0], device="cuda:0")
@@ -488,11 +488,11 @@ def bench_area(args, B, W) -> int:
     # the sweep with Guo's term on the HBM-bound 4096^2 membrane, beside the plain one
     sweeps = {}
     for mode in (W.FORCE_II_LBM, W.FORCE_II_LBM_GUO, W.FORCE_IB_LBM_GUO):
-        wm = W.membrane_c3(L=4096)
+        wm = W.membrane_seeded(L=4096)
         wm.problem.math = math_
         wm.problem.force_mode = mode
         if mode == W.FORCE_IB_LBM_GUO:
-            wm = W.membrane_c3(L=4096, n_markers=4096 * 6)   # 1/3 lu spacing
+            wm = W.membrane_seeded(L=4096, n_markers=4096 * 6)   # 1/3 lu spacing
             wm.problem.math = math_
             wm.problem.force_mode = mode
         sim = B.Sim([wm.problem], [wm.X0], device="cuda:0")
@@ -1079,7 +1079,7 @@ def bench_batch(args, B, W) -> int:
     timed pass of direct launches over the same state."""
     import numpy as np
     import torch
-    ws = W.membrane_batch_c4(n_inst=args.instances or 512)
+    ws = W.membrane_batch_uneven(n_inst=args.instances or 512)
     for w in ws:
         w.problem.math = W.MATH_FP64 if args.math == "fp64" else W.MATH_FP32
         w.problem.storage = W.STORE_FP16 if args.storage == "fp16" else W.STORE_FP32
@@ -1232,7 +1232,7 @@ def main() -> int:
     if args.workload == "boundaries":
         return bench_boundaries(args, B, W)
     storage = W.STORE_FP16 if args.storage == "fp16" else W.STORE_FP32
-    w = W.membrane_c3(L=args.size, storage=storage)
+    w = W.membrane_seeded(L=args.size, storage=storage)
     p = w.problem
     p.math = W.MATH_FP64 if args.math == "fp64" else W.MATH_FP32
     p.geometry = W.GEOM_SPLINE if args.geometry == "spline" else W.GEOM_POLYGON

@@ -1,7 +1,7 @@
 """Training data, training and evaluation of the learned coarse correction.
 
-Coarse/fine pairs are membrane runs of the config-3 generator at 256^2 and
-512^2 in diffusive scaling (``workloads.learned_pair_c5``); both advance on
+Coarse/fine pairs are membrane runs of the seeded membrane generator at 256^2 and
+512^2 in diffusive scaling (``workloads.learned_pair_coarse_fine``); both advance on
 the GPU through the library, many instances per handle.  Training patches
 are the band tiles of the uncorrected coarse run at seeded snapshot steps,
 with the equilibrium-change targets of the fine run at the same physical
@@ -10,7 +10,7 @@ the correction after every coarse step) and compares the coarse velocity
 with the fine one restricted to the coarse nodes (times 2).
 
     python -m paper_2003_12186_amd.train_learned --train 2000 --heldout 200 \
-        --out paper_2003_12186_amd/data/cnn_c5.npz
+        --out paper_2003_12186_amd/data/cnn_coarse256.npz
 """
 from __future__ import annotations
 
@@ -35,7 +35,7 @@ def log(msg: str) -> None:
 
 
 def _sims(seeds, L=256, n_markers=512):
-    pairs = [W.learned_pair_c5(s, L=L, n_markers=n_markers) for s in seeds]
+    pairs = [W.learned_pair_coarse_fine(s, L=L, n_markers=n_markers) for s in seeds]
     sc = B.Sim([c.problem for c, _ in pairs], [c.X0 for c, _ in pairs])
     sf = B.Sim([f.problem for _, f in pairs], [f.X0 for _, f in pairs])
     return sc, sf
@@ -223,7 +223,7 @@ def evaluate(net, sc: LN.Scales, seeds, L: int = 256, n_markers: int = 512, chec
     seeds = list(seeds)
     res = {"seeds": seeds, "checkpoints": list(checkpoints)}
     # fine reference
-    pairs = [W.learned_pair_c5(s, L=L, n_markers=n_markers) for s in seeds]
+    pairs = [W.learned_pair_coarse_fine(s, L=L, n_markers=n_markers) for s in seeds]
     sf = B.Sim([f.problem for _, f in pairs], [f.X0 for _, f in pairs])
     sp = B.Sim([c.problem for c, _ in pairs], [c.X0 for c, _ in pairs])
     sl = B.Sim([c.problem for c, _ in pairs], [c.X0 for c, _ in pairs])
@@ -289,7 +289,7 @@ def ceiling(net, sc: LN.Scales, seeds, alphas=(1.0, 0.1), checkpoints=(250, 500,
     import torch
     seeds = list(seeds)
     n = len(seeds)
-    pairs = [W.learned_pair_c5(s) for s in seeds]
+    pairs = [W.learned_pair_coarse_fine(s) for s in seeds]
     mk = lambda k: B.Sim([p[k].problem for p in pairs], [p[k].X0 for p in pairs])
     sf, sp, sb, sw = mk(1), mk(0), mk(0), mk(0)
     nets = {}
@@ -382,7 +382,7 @@ def main(argv=None) -> int:
     ap.add_argument("--batch", type=int, default=512)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--gen-batch", type=int, default=128)
-    ap.add_argument("--out", default=os.path.join(os.path.dirname(__file__), "data", "cnn_c5.npz"))
+    ap.add_argument("--out", default=os.path.join(os.path.dirname(__file__), "data", "cnn_coarse256.npz"))
     ap.add_argument("--report", default=None, help="JSON summary path")
     ap.add_argument("--alpha", type=float, nargs="*", default=[1.0],
                     help="evaluate the correction scaled by each factor")

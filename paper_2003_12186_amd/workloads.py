@@ -16,17 +16,17 @@ draw u in [0, 1) takes the top 53 bits of an output.  Stream (config, instance)
 starts from the state ``config * 2**32 + instance``.
 
 Workloads (lattice units, dx = dt = 1, Sec. 2.2):
-  * ``membrane_c1``  64x64 periodic, SRT tau=0.8, ellipse 12 x 8 centred at
+  * ``membrane_ellipse64``  64x64 periodic, SRT tau=0.8, ellipse 12 x 8 centred at
     (32, 32), 96 markers, spring constant 0.05 (the elastic-interface relaxation
     of Sec. 4.2 on a small periodic box).
-  * ``cylinder_c2``  1024x512 channel, MRT, no-slip walls, parabolic inflow
+  * ``cylinder_channel``  1024x512 channel, MRT, no-slip walls, parabolic inflow
     u_max=0.05, zero-gradient outflow, rigid circle D=32 at (256, 256) with 101
     direct-forcing markers (the fixed-cylinder problem of Sec. 4.3 in a channel).
-    ``cylinder_c2(small=True)`` is the 128x64, D=4 copy the oracle runs in full.
-  * ``membrane_c3``  LxL periodic (L=4096 by default), SRT with tau drawn in
+    ``cylinder_channel(small=True)`` is the 128x64, D=4 copy the oracle runs in full.
+  * ``membrane_seeded``  LxL periodic (L=4096 by default), SRT with tau drawn in
     [0.55, 1.5) and kappa log-uniform in [1e-3, 1e-1) from the seed; ellipse
     0.3L x 0.2L centred, N = L markers.
-  * ``membrane_batch_c4``  512 independent periodic membrane instances with side
+  * ``membrane_batch_uneven``  512 independent periodic membrane instances with side
     L in {64, 96, ..., 512}, aspect ratio in [1, 2), kappa log-uniform in
     [1e-3, 1e-1), tau in [0.55, 1.5) and N = round(2 x ellipse perimeter).
 
@@ -184,7 +184,7 @@ def ramanujan_perimeter(a: float, b: float) -> float:
 # ---------------------------------------------------------------------------
 # The workloads
 # ---------------------------------------------------------------------------
-def membrane_c1(storage: int = STORE_FP32) -> Workload:
+def membrane_ellipse64(storage: int = STORE_FP32) -> Workload:
     nx = ny = 64
     a, b, n = 12.0, 8.0, 96
     X0 = ellipse_markers(32.0, 32.0, a, b, n)
@@ -194,7 +194,7 @@ def membrane_c1(storage: int = STORE_FP32) -> Workload:
     return Workload(p, X0, 2000, {"a": a, "b": b})
 
 
-def cylinder_c2(re: float = 20.0, small: bool = False, storage: int = STORE_FP32) -> Workload:
+def cylinder_channel(re: float = 20.0, small: bool = False, storage: int = STORE_FP32) -> Workload:
     """Channel flow past a fixed circle; tau from Re = U_mean*D/nu with U_mean = 2/3 u_max."""
     if small:
         nx, ny, D, n, cx, cy = 128, 64, 4.0, 13, 32.0, 32.0
@@ -519,7 +519,7 @@ def elastic_membrane_e2(L: int, force_mode: int = FORCE_II_LBM, storage: int = S
     return Workload(p, X0, 30 * span, {"U": U, "span": span, "R": R})
 
 
-def membrane_c3(L: int = 4096, seed: int = 0, storage: int = STORE_FP32,
+def membrane_seeded(L: int = 4096, seed: int = 0, storage: int = STORE_FP32,
                 n_markers: Optional[int] = None) -> Workload:
     rng = SplitMix64(3, seed)
     u0, u1 = rng.uniform(), rng.uniform()
@@ -534,7 +534,7 @@ def membrane_c3(L: int = 4096, seed: int = 0, storage: int = STORE_FP32,
     return Workload(p, X0, 5000, {"a": a, "b": b, "seed": seed})
 
 
-def membrane_batch_c4(n_inst: int = 512, first: int = 0) -> List[Workload]:
+def membrane_batch_uneven(n_inst: int = 512, first: int = 0) -> List[Workload]:
     out = []
     for i in range(first, first + n_inst):
         rng = SplitMix64(4, i)
@@ -554,15 +554,15 @@ def membrane_batch_c4(n_inst: int = 512, first: int = 0) -> List[Workload]:
     return out
 
 
-def learned_pair_c5(seed: int, L: int = 256, n_markers: int = 512) -> Tuple[Workload, Workload]:
-    """Coarse/fine membrane pair for the learned correction: the config-3
-    generator (same seed, so the same tau and kappa draw) at L x L and at
+def learned_pair_coarse_fine(seed: int, L: int = 256, n_markers: int = 512) -> Tuple[Workload, Workload]:
+    """Coarse/fine membrane pair for the learned correction: the seeded
+    membrane generator (same seed, so the same tau and kappa draw) at L x L and at
     2L x 2L, with the fine run in diffusive scaling: the same tau (so the same
     lattice viscosity), markers at twice the coordinates (same count), half
     the lattice stiffness, four fine steps per coarse step and half the
     lattice velocity.  Coarse node (i, j) sits on fine node (2i, 2j)."""
-    c = membrane_c3(L=L, seed=seed, n_markers=n_markers)
-    f = membrane_c3(L=2 * L, seed=seed, n_markers=n_markers)
+    c = membrane_seeded(L=L, seed=seed, n_markers=n_markers)
+    f = membrane_seeded(L=2 * L, seed=seed, n_markers=n_markers)
     f.problem.kappa = c.problem.kappa / 2.0
     c.steps, f.steps = 2000, 8000
     c.meta["role"], f.meta["role"] = "coarse", "fine"

@@ -57,12 +57,12 @@ def _init_rc(prob, X0):
 
 
 def test_workspace_size_scales_with_lattice():
-    a = B.workspace_size([B.make_problem(W.membrane_c1().problem)])
-    b = B.workspace_size([B.make_problem(W.membrane_c3(L=256).problem)])
-    c = B.workspace_size([B.make_problem(W.membrane_c3(L=256, storage=W.STORE_FP16).problem)])
+    a = B.workspace_size([B.make_problem(W.membrane_ellipse64().problem)])
+    b = B.workspace_size([B.make_problem(W.membrane_seeded(L=256).problem)])
+    c = B.workspace_size([B.make_problem(W.membrane_seeded(L=256, storage=W.STORE_FP16).problem)])
     assert 0 < a < b
     assert c < b                                  # half-precision lattice
-    two = B.workspace_size([B.make_problem(W.membrane_c1().problem)] * 2)
+    two = B.workspace_size([B.make_problem(W.membrane_ellipse64().problem)] * 2)
     assert two > a
 
 
@@ -88,7 +88,7 @@ def test_workspace_size_scales_with_lattice():
     (lambda p, X: X.__setitem__((5, 1), np.nan), B.EINVAL),
 ])
 def test_init_validation_rejects_before_device_access(mutate, code):
-    w = W.membrane_c1()
+    w = W.membrane_ellipse64()
     p = B.make_problem(w.problem)
     X = w.X0.copy()
     mutate(p, X)

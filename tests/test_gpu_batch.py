@@ -29,7 +29,7 @@ def B(require_gpu):
 
 
 def _small_batch(n=6, math_=W.MATH_FP64):
-    ws = W.membrane_batch_c4(n_inst=64)
+    ws = W.membrane_batch_uneven(n_inst=64)
     ws = sorted(ws, key=lambda w: w.problem.nx)       # a spread of sizes
     pick = [ws[int(i)] for i in np.linspace(0, 63, n)]
     for w in pick:
@@ -70,8 +70,8 @@ def test_batched_equals_single_and_oracle(B, math_):
 @pytest.mark.parametrize("case", ["membrane", "membrane_batch", "rigid"])
 def test_graph_replay_equals_direct_launches(B, case):
     _say(f"graph replay vs direct launches, {case}")
-    ws = {"membrane": lambda: [W.membrane_c1()], "membrane_batch": lambda: _small_batch(3),
-          "rigid": lambda: [W.cylinder_c2(small=True)]}[case]()
+    ws = {"membrane": lambda: [W.membrane_ellipse64()], "membrane_batch": lambda: _small_batch(3),
+          "rigid": lambda: [W.cylinder_channel(small=True)]}[case]()
     probs, X0 = [w.problem for w in ws], [w.X0 for w in ws]
     a = B.Sim(probs, X0)
     b = B.Sim(probs, X0)
@@ -104,7 +104,7 @@ def test_graph_replay_equals_direct_launches(B, case):
 @pytest.mark.parametrize("batched", [False, True])
 def test_overlap_modes_are_bit_identical(B, batched):
     _say(f"overlap modes serial / full / interp-first, batched={batched}")
-    ws = _small_batch(3) if batched else [W.membrane_c1()]
+    ws = _small_batch(3) if batched else [W.membrane_ellipse64()]
     probs, X0 = [w.problem for w in ws], [w.X0 for w in ws]
     out = []
     for mode in (B.OVERLAP_SERIAL, B.OVERLAP_FULL, B.OVERLAP_INTERP_FIRST):
@@ -184,7 +184,7 @@ def test_full_batch512_sampled_instances_match_oracle(B):
     # The 512-instance workload in the launch configuration the bench times
     # (autotuned table, HIP graphs): 20 steps, then the smallest, the largest
     # and two other instances against the oracle.
-    ws = W.membrane_batch_c4(512)
+    ws = W.membrane_batch_uneven(512)
     for w in ws:
         w.problem.math = W.MATH_FP64
     _say("batch of 512 uneven membranes, 20 steps (graphs, autotuned), 4 sampled vs oracle")
@@ -213,7 +213,7 @@ def test_full_batch512_sampled_instances_match_oracle(B):
 def test_isolation_keeps_the_other_instances_running(B):
     # a non-finite state in one instance of a batch: with isolation on, that
     # instance carries the error bits and the others evolve exactly as alone
-    w = W.membrane_c1()
+    w = W.membrane_ellipse64()
     _say("isolation: NaN in instance 1 of 3; instances 0 and 2 vs a clean batch")
     sims = [B.Sim([w.problem] * 3, [w.X0] * 3) for _ in range(2)]
     bad, clean = sims

@@ -161,7 +161,7 @@ def test_moving_body_checkpoint_restart_and_fixed_body_has_no_state(B):
     assert np.array_equal(a.body()["c"], b.body()["c"]) and a.body()["steps"] == b.body()["steps"]
     a.close()
     b.close()
-    w = W.cylinder_c2(re=20.0, small=True)
+    w = W.cylinder_channel(re=20.0, small=True)
     fixed = B.Sim([w.problem], [w.X0])
     with pytest.raises(B.IILBMError) as e:
         fixed.body()

@@ -61,7 +61,7 @@ def _node_classes(p, X, margin=3.0):
 def test_diag_matches_oracle_membrane64(B, storage, tol_p):
     steps = 500
     _say(f"membrane 64x64, {steps} steps, diag vs oracle (storage={storage})")
-    w = W.membrane_c1()
+    w = W.membrane_ellipse64()
     w.problem.storage = storage
     w.problem.math = W.MATH_FP64 if storage == W.STORE_FP32 else W.MATH_FP32
     sim = B.Sim([w.problem], [w.X0])
@@ -111,7 +111,7 @@ def test_diag_matches_oracle_cylinder_channel(B):
     # the marker polygon, momentum with walls and inflow, drag and lift.
     steps = 400
     _say(f"cylinder channel 128x64 D=4, {steps} steps, diag vs oracle")
-    w = W.cylinder_c2(re=20.0, small=True)
+    w = W.cylinder_channel(re=20.0, small=True)
     w.problem.math = W.MATH_FP64
     sim = B.Sim([w.problem], [w.X0])
     sim.step(steps)
@@ -142,7 +142,7 @@ def test_diag_pressure_sides_cylinder_full_size(B):
     # The D = 32 cylinder of the 1024 x 512 channel: both sides populated.
     steps = 200
     _say(f"cylinder channel 1024x512 D=32, {steps} steps, pressure sides vs oracle")
-    w = W.cylinder_c2(re=20.0)
+    w = W.cylinder_channel(re=20.0)
     w.problem.math = W.MATH_FP64
     sim = B.Sim([w.problem], [w.X0])
     sim.step(steps)
@@ -179,7 +179,7 @@ def test_config1_laplace_law_on_gpu(B):
     # over steps 1000 .. 2000 within 1 % (the oracle's own pin of the same
     # run); the enclosed area after the initial transient (step 500) kept
     # within 0.5 %; mass conserved.
-    w = W.membrane_c1()
+    w = W.membrane_ellipse64()
     _say("membrane 64x64, 2000 steps: Laplace's law and area on the GPU")
     sim = B.Sim([w.problem], [w.X0])
     sim.step(500)

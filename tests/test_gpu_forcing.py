@@ -73,7 +73,7 @@ def test_periodic_bulk_body_force_guo(B, collision, math_):
 @pytest.mark.parametrize("mode", MODES)
 def test_membrane64_force_modes_1000_steps(B, mode, collision, math_):
     _say(f"membrane 64x64 force_mode={mode} collision={collision} math={math_}, 1000 steps")
-    w = W.membrane_c1()
+    w = W.membrane_ellipse64()
     w.problem.force_mode = mode
     w.problem.collision = collision
     w.problem.math = math_
@@ -104,7 +104,7 @@ def test_cylinder_small_force_modes(B, mode, math_):
     # Direct forcing with the simple or Guo's term (u* of the body force only)
     # in the 128 x 64, D = 4 channel; velocity and drag/lift every 100 steps.
     _say(f"cylinder channel 128x64 D=4 MRT Re=100 force_mode={mode} math={math_}, 1000 steps")
-    w = W.cylinder_c2(re=100.0, small=True)
+    w = W.cylinder_channel(re=100.0, small=True)
     w.problem.force_mode = mode
     w.problem.math = math_
     sim = B.Sim([w.problem], [w.X0])
@@ -180,7 +180,7 @@ def test_elastic_membrane_table2_total_loss_l80(B, mode):
 
 def test_batch_guo_matches_single_runs_and_rejects_mixed_modes(B):
     _say("batch of 3 membranes under IB-LBM with Guo's term, 400 steps; mixed modes rejected")
-    ws = [W.membrane_c3(L=128, seed=s) for s in (3, 4, 5)]
+    ws = [W.membrane_seeded(L=128, seed=s) for s in (3, 4, 5)]
     for w in ws:
         w.problem.force_mode = W.FORCE_IB_LBM_GUO
     sim = B.Sim([w.problem for w in ws], [w.X0 for w in ws])
@@ -194,9 +194,9 @@ def test_batch_guo_matches_single_runs_and_rejects_mixed_modes(B):
         assert np.array_equal(sim.markers(j)[0], one.markers()[0])
         one.close()
     sim.close()
-    mixed = [ws[0].problem, W.membrane_c3(L=128, seed=6).problem]
+    mixed = [ws[0].problem, W.membrane_seeded(L=128, seed=6).problem]
     with pytest.raises(B.IILBMError) as e:
-        B.Sim(mixed, [ws[0].X0, W.membrane_c3(L=128, seed=6).X0])
+        B.Sim(mixed, [ws[0].X0, W.membrane_seeded(L=128, seed=6).X0])
     assert e.value.code == B.EINVAL
 
 

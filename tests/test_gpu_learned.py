@@ -145,7 +145,7 @@ def test_adam_matches_oracle_and_repacks(mods):
 
 
 def _pair(steps_c=40, L=64, n=128, seed=10003):
-    c, f = W.learned_pair_c5(seed, L=L, n_markers=n)
+    c, f = W.learned_pair_coarse_fine(seed, L=L, n_markers=n)
     c.problem.math = W.MATH_FP64
     f.problem.math = W.MATH_FP64
     return c, f, steps_c
@@ -273,7 +273,7 @@ def test_infer_over_many_tiles_matches_forward_and_apply(mods):
     B, LN = mods
     # a 512^2 instance lists more band tiles than one block per instance
     # strides over, next to a 256^2 one
-    pairs = [W.learned_pair_c5(10003, L=256, n_markers=512), W.learned_pair_c5(10004, L=512, n_markers=1024)]
+    pairs = [W.learned_pair_coarse_fine(10003, L=256, n_markers=512), W.learned_pair_coarse_fine(10004, L=512, n_markers=1024)]
     for c, _ in pairs:
         c.problem.math = W.MATH_FP64
     _say("correct == tiles + patches + infer (bit-exact) == training forward + apply, 256^2 and 512^2")
@@ -324,7 +324,7 @@ def test_registered_correction_matches_manual_steps(mods, mode):
     B, LN = mods
     # the handle applying the correction inside its steps (other streams,
     # graph replays) gives the same state as step + correct called in turn
-    pairs = [W.learned_pair_c5(s, L=64, n_markers=128) for s in (10003, 10006)]
+    pairs = [W.learned_pair_coarse_fine(s, L=64, n_markers=128) for s in (10003, 10006)]
     for c, _ in pairs:
         c.problem.math = W.MATH_FP64
     modes = {"full": B.OVERLAP_FULL, "interp_first": B.OVERLAP_INTERP_FIRST, "serial": B.OVERLAP_SERIAL}
@@ -364,7 +364,7 @@ def test_fp16_storage_correction_paths_agree(mods):
     B, LN = mods
     # FP16 deviation storage: the registered correction, the host-called one
     # and the training forward + masked add give the same lattice
-    pairs = [W.learned_pair_c5(s, L=64, n_markers=128) for s in (10003, 10006)]
+    pairs = [W.learned_pair_coarse_fine(s, L=64, n_markers=128) for s in (10003, 10006)]
     for c, _ in pairs:
         c.problem.storage = W.STORE_FP16
         c.problem.math = W.MATH_FP32
@@ -405,7 +405,7 @@ def test_training_reduces_the_loss(mods):
     B, LN = mods
     _say("training: 2 coarse/fine pairs 64^2/128^2, patches every 20 coarse steps, 150 Adam steps")
     sc = LN.make_scales(**SC)
-    pairs = [W.learned_pair_c5(s, L=64, n_markers=128) for s in (0, 1)]
+    pairs = [W.learned_pair_coarse_fine(s, L=64, n_markers=128) for s in (0, 1)]
     sc_ = B.Sim([p[0].problem for p in pairs], [p[0].X0 for p in pairs])
     sf = B.Sim([p[1].problem for p in pairs], [p[1].X0 for p in pairs])
     band = LN.Band(sc_)
@@ -443,7 +443,7 @@ def test_trained_network_gains_over_no_correction(mods):
     import os
     _, LN = mods
     from paper_2003_12186_amd import train_learned as TL
-    d = np.load(os.path.join(os.path.dirname(LN.__file__), "data", "cnn_c5.npz"))
+    d = np.load(os.path.join(os.path.dirname(LN.__file__), "data", "cnn_coarse256.npz"))
     net = LN.Net(d["params"])
     sc = LN.make_scales(d["in_scale"], float(d["out_scale"]))
     held = list(W.LEARNED_HELDOUT_SEEDS)[:8]
@@ -463,7 +463,7 @@ def test_ceiling_gap_is_acoustic_and_band_bound(mods):
     import os
     _, LN = mods
     from paper_2003_12186_amd import train_learned as TL
-    d = np.load(os.path.join(os.path.dirname(LN.__file__), "data", "cnn_c5.npz"))
+    d = np.load(os.path.join(os.path.dirname(LN.__file__), "data", "cnn_coarse256.npz"))
     net = LN.Net(d["params"])
     sc = LN.make_scales(d["in_scale"], float(d["out_scale"]))
     held = list(W.LEARNED_HELDOUT_SEEDS)[:16]

@@ -78,7 +78,7 @@ def test_periodic_bulk_parity(B, collision, math_):
 @pytest.mark.parametrize("math_", [W.MATH_FP64, W.MATH_FP32])
 def test_membrane64_parity_1000_steps(B, math_):
     _say(f"membrane 64x64 (tau 0.8, 96 markers, kappa 0.05), 1000 steps, FP32 storage math={math_}")
-    w = W.membrane_c1()
+    w = W.membrane_ellipse64()
     w.problem.math = math_
     sim, g = _gpu_run(B, w.problem, w.X0, 1000)
     o = _oracle_run(w.problem, w.X0, 1000)
@@ -98,7 +98,7 @@ def test_membrane64_parity_1000_steps(B, math_):
 @pytest.mark.parametrize("steps", [0, 150])
 def test_membrane64_cutlinks_bitexact(B, steps):
     _say(f"membrane 64x64 cut links after {steps} steps")
-    w = W.membrane_c1()
+    w = W.membrane_ellipse64()
     sim = B.Sim([w.problem], [w.X0])
     sim.step(steps)
     Xn, _, _ = sim.markers()
@@ -125,7 +125,7 @@ def _oracle_cylinder(re, small, steps):
     # one oracle run per channel, shared by the FP32- and FP64-arithmetic cases
     key = (re, small, steps)
     if key not in _ORACLE_CACHE:
-        w = W.cylinder_c2(re=re, small=small)
+        w = W.cylinder_channel(re=re, small=small)
         _ORACLE_CACHE[key] = _oracle_run(w.problem, w.X0, steps, force_hist=True)
     return _ORACLE_CACHE[key]
 
@@ -134,7 +134,7 @@ def _oracle_cylinder(re, small, steps):
 @pytest.mark.parametrize("re", [20.0, 100.0])
 def test_cylinder_channel_small_parity(B, re, math_):
     _say(f"cylinder channel 128x64 D=4 MRT NEE Re={re} math={math_}, 1000 steps")
-    w = W.cylinder_c2(re=re, small=True)
+    w = W.cylinder_channel(re=re, small=True)
     w.problem.math = math_
     sim = B.Sim([w.problem], [w.X0])
     fx = []
@@ -160,7 +160,7 @@ def test_cylinder_channel_small_configured_length(B, re, math_):
     # 20000 steps: drag and lift every 1000 steps and the final velocity
     # against the FP64 oracle.
     _say(f"cylinder channel 128x64 D=4 MRT Re={re} math={math_}, 20000 steps, forces every 1000")
-    w = W.cylinder_c2(re=re, small=True)
+    w = W.cylinder_channel(re=re, small=True)
     w.problem.math = math_
     sim = B.Sim([w.problem], [w.X0])
     fx = []
@@ -184,7 +184,7 @@ def test_cylinder_channel_small_configured_length(B, re, math_):
 def test_set_markers_then_run_matches_oracle(B):
     # Replacing the markers rebuilds the interface data of the current step.
     _say("membrane 64x64: set_markers (shifted, rescaled curve) then 200 steps")
-    w = W.membrane_c1()
+    w = W.membrane_ellipse64()
     w.problem.math = W.MATH_FP64
     X1 = np.ascontiguousarray(32.0 + 1.05 * (w.X0 - 32.0) + np.array([0.37, -0.21]))
     sim = B.Sim([w.problem], [w.X0])
@@ -201,7 +201,7 @@ def test_set_markers_then_run_matches_oracle(B):
 
 def test_cylinder_small_cutlinks_bitexact(B):
     _say("cylinder D=4 level-set cut links")
-    w = W.cylinder_c2(small=True)
+    w = W.cylinder_channel(small=True)
     sim = B.Sim([w.problem], [w.X0])
     sim.step(10)
     got = sim.cutlinks()
@@ -219,7 +219,7 @@ def test_cylinder_small_cutlinks_bitexact(B):
 def test_membrane256_parity(B, storage, math_, tol):
     _say(f"membrane 256x256 (ellipse 0.3L x 0.2L, seeded tau/kappa) storage={storage} "
          f"math={math_}, 1000 steps")
-    w = W.membrane_c3(L=256, storage=storage)
+    w = W.membrane_seeded(L=256, storage=storage)
     w.problem.math = math_
     sim, g = _gpu_run(B, w.problem, w.X0, 1000)
     o = _oracle_run(w.problem, w.X0, 1000)
@@ -260,7 +260,7 @@ def test_laplace_fixed_point_on_gpu(B):
 
 def test_determinism_and_checkpoint_restart(B):
     _say("determinism + checkpoint/restart, membrane 64x64")
-    w = W.membrane_c1()
+    w = W.membrane_ellipse64()
     a = B.Sim([w.problem], [w.X0])
     a.step(120)
     blob = a.save_state()
@@ -333,7 +333,7 @@ def test_multi_crossing_links_deterministic(B):
 
 def test_unstable_state_is_reported(B):
     _say("non-finite state -> EUNSTABLE")
-    w = W.membrane_c1()
+    w = W.membrane_ellipse64()
     sim = B.Sim([w.problem], [w.X0])
     p = O.make_problem(w.problem)
     f = O.rest_state(p)
@@ -353,7 +353,7 @@ def test_full_size_membrane4096_first_steps(B):
     # The bench workload at its full size and launch configuration; the oracle
     # runs the same two steps in FP64.
     _say("membrane 4096x4096 (bench workload), 2 steps vs oracle")
-    w = W.membrane_c3()
+    w = W.membrane_seeded()
     w.problem.math = W.MATH_FP64
     sim, g = _gpu_run(B, w.problem, w.X0, 2)
     o = _oracle_run(w.problem, w.X0, 2)
@@ -373,7 +373,7 @@ def test_full_size_membrane4096_fp16_first_steps(B):
     # row-segment sweep), two steps against the FP64 oracle at the
     # reduced-precision bar.
     _say("membrane 4096x4096 FP16 storage, FP32 math, 2 steps vs oracle")
-    w = W.membrane_c3(storage=W.STORE_FP16)
+    w = W.membrane_seeded(storage=W.STORE_FP16)
     w.problem.math = W.MATH_FP32
     sim, g = _gpu_run(B, w.problem, w.X0, 2)
     o = _oracle_run(w.problem, w.X0, 2)
@@ -393,7 +393,7 @@ def test_membrane512_fp16_parity_1000_steps(B, math_):
     # 4096^2 bench times), 1000 steps against the oracle at the
     # reduced-precision bar, with both collision arithmetics.
     _say(f"membrane 512x512 FP16 storage math={math_}, 1000 steps vs oracle")
-    w = W.membrane_c3(L=512, storage=W.STORE_FP16)
+    w = W.membrane_seeded(L=512, storage=W.STORE_FP16)
     w.problem.math = math_
     sim, g = _gpu_run(B, w.problem, w.X0, 1000)
     o = _oracle_run(w.problem, w.X0, 1000)
@@ -477,7 +477,7 @@ def test_cylinder_full_size_first_steps(B, re, math_):
     # steps, long enough for the inflow's pressure front to pass the cylinder
     # at x = 256, against the oracle, with the drag/lift history.
     _say(f"cylinder channel 1024x512 D=32 MRT Re={re} math={math_}, 600 steps vs oracle")
-    w = W.cylinder_c2(re=re)
+    w = W.cylinder_channel(re=re)
     w.problem.math = math_
     sim = B.Sim([w.problem], [w.X0])
     fx = []

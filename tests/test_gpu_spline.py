@@ -66,7 +66,7 @@ def test_spline_crossings_match_oracle(B, n, seed):
 
 @pytest.mark.parametrize("collision", [W.SRT, W.MRT])
 def test_spline_membrane64_parity_1000_steps(B, collision):
-    w = W.membrane_c1()
+    w = W.membrane_ellipse64()
     w.problem.geometry = W.GEOM_SPLINE
     w.problem.collision = collision
     w.problem.math = W.MATH_FP64
@@ -91,7 +91,7 @@ def test_spline_membrane64_parity_1000_steps(B, collision):
 
 
 def test_spline_membrane_with_guo_term(B):
-    w = W.membrane_c1()
+    w = W.membrane_ellipse64()
     w.problem.geometry = W.GEOM_SPLINE
     w.problem.force_mode = W.FORCE_II_LBM_GUO
     w.problem.math = W.MATH_FP64

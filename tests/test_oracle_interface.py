@@ -84,7 +84,7 @@ def test_membrane_force_regular_polygon_laplace_value():
 
 
 def test_membrane_force_ellipse_orientation_and_split():
-    w = W.membrane_c1()
+    w = W.membrane_ellipse64()
     p = O.make_problem(w.problem)
     d = O.marker_forces(p, w.X0)
     c = np.array([32.0, 32.0])
@@ -99,7 +99,7 @@ def test_membrane_force_ellipse_orientation_and_split():
 
 def test_direct_forcing_rigid():
     # Sec. 2.2.2, Eq. (18) with eta = 1, U^D = 0; |dX/ds| = 1 for rigid bodies.
-    w = W.cylinder_c2(small=True)
+    w = W.cylinder_channel(small=True)
     p = O.make_problem(w.problem)
     rng = np.random.default_rng(2)
     U = 1e-3 * rng.standard_normal(w.X0.shape)
@@ -133,7 +133,7 @@ def _star_polygon(rng, n, cx, cy, rmin, rmax, grid=None):
 
 def _polys():
     rng = np.random.default_rng(7)
-    out = [W.membrane_c1().X0, _regular(17, 6.0, 20.0, 20.0)]
+    out = [W.membrane_ellipse64().X0, _regular(17, 6.0, 20.0, 20.0)]
     for t in range(6):
         out.append(_star_polygon(rng, 30 + 10 * t, 24.0, 22.0, 5.0, 14.0))
     for grid in (1.0, 0.5, 0.25):
@@ -223,8 +223,8 @@ def test_cutlinks_antisymmetric_and_match_inside_outside(k):
 
 
 def test_cutlinks_each_lattice_line_crosses_closed_curve_evenly():
-    X = W.membrane_c1().X0
-    p = O.make_problem(W.membrane_c1().problem)
+    X = W.membrane_ellipse64().X0
+    p = O.make_problem(W.membrane_ellipse64().problem)
     rec = O.cutlinks(p, X)
     # horizontal lines: links of direction 1 per row
     for y in range(64):
@@ -253,7 +253,7 @@ def test_p1p2_example_vertical_interface():
 
 
 def test_rigid_cutlinks_level_set():
-    w = W.cylinder_c2(small=True)
+    w = W.cylinder_channel(small=True)
     p = O.make_problem(w.problem)
     rec = O.cutlinks(p, w.X0, np.linspace(0, 1, 13))
     ex, ey, _ = O.d2q9()
@@ -331,7 +331,7 @@ def test_step_mass_conservation_and_momentum_budget(collision):
     # periodic sides the total mass is conserved to round-off.
     # P-10: the momentum change of one step is exactly the spread force plus
     # the jump contributions sigma w_i [[p]] e_i / c_s^2 of all cut links.
-    w = W.membrane_c1()
+    w = W.membrane_ellipse64()
     w.problem.collision = collision
     p = O.make_problem(w.problem)
     ex, ey, wt = O.d2q9()
@@ -355,7 +355,7 @@ def test_jump_records_independent_of_collision_operator():
     # Sec. 3.1: the jump conditions are the same for SRT and MRT.
     recs = []
     for coll in (W.SRT, W.MRT):
-        w = W.membrane_c1()
+        w = W.membrane_ellipse64()
         w.problem.collision = coll
         p = O.make_problem(w.problem)
         f = O.rest_state(p)
@@ -367,7 +367,7 @@ def test_jump_records_independent_of_collision_operator():
 def test_rigid_channel_step_mass_and_walls():
     # Direct-forcing cylinder in the NEE channel: wall nodes keep u = 0 and the
     # inlet row carries the parabola after every step.
-    w = W.cylinder_c2(small=True)
+    w = W.cylinder_channel(small=True)
     p = O.make_problem(w.problem)
     f = O.rest_state(p)
     X = w.X0.copy()
@@ -381,12 +381,12 @@ def test_rigid_channel_step_mass_and_walls():
     assert np.all(np.isfinite(fh))
 
 
-def test_membrane_c1_laplace_law_and_area():
+def test_membrane_ellipse64_laplace_law_and_area():
     # P-12: the 64x64 membrane relaxes towards a circle whose pressure jump
     # obeys Laplace's law dp = T / R (T = kappa l / dX, R from the enclosed
     # area); time-averaged over steps 1000..2000 within 1 %.  After the initial
     # compression transient the enclosed area stays within 0.5 %.
-    w = W.membrane_c1()
+    w = W.membrane_ellipse64()
     p = O.make_problem(w.problem)
     f = O.rest_state(p)
     X = w.X0.copy()

@@ -170,7 +170,7 @@ def test_signed_distance_square_and_regular_polygon():
 
 
 def test_inside_polygon_agrees_with_c_oracle_on_the_lattice():
-    w = W.membrane_c1()
+    w = W.membrane_ellipse64()
     p = O.make_problem(w.problem)
     yy, xx = np.mgrid[0:64, 0:64]
     ins = L.inside_polygon(w.X0, xx.astype(float), yy.astype(float))
@@ -191,7 +191,7 @@ def test_extract_patch_wraps_periodically():
 
 
 def test_apply_correction_skips_cut_links_and_non_band_nodes():
-    w = W.membrane_c1()
+    w = W.membrane_ellipse64()
     f = np.ones((9, 64, 64))
     yy, xx = np.mgrid[0:64, 0:64]
     sd = L.signed_distance(w.X0, xx.astype(float), yy.astype(float))

@@ -123,7 +123,7 @@ def test_spline_step_mass_and_momentum_budget():
     # As for the polygon: the jumps add +c and -c at the two ends of every
     # cut link (mass conserved), and the momentum change is the spread force
     # plus sigma w_i [[p]] e_i / c_s^2 summed over the crossings.
-    w = W.membrane_c1()
+    w = W.membrane_ellipse64()
     w.problem.geometry = W.GEOM_SPLINE
     p = O.make_problem(w.problem)
     ex, ey, wt = O.d2q9()
@@ -145,7 +145,7 @@ def test_spline_step_mass_and_momentum_budget():
 def test_spline_membrane_obeys_laplace_law():
     # The 64 x 64 membrane with the spline geometry relaxes to a circle whose
     # pressure jump is T / R within 1 % (time average over steps 1000..2000).
-    w = W.membrane_c1()
+    w = W.membrane_ellipse64()
     w.problem.geometry = W.GEOM_SPLINE
     p = O.make_problem(w.problem)
     f = O.rest_state(p)

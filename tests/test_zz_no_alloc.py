@@ -27,8 +27,8 @@ def B(require_gpu):
 
 
 def test_fields_noalloc_matches_fields_two_calls(B):
-    big = W.membrane_c3(L=512)                     # 13 FP64 planes: 27 MB
-    small = W.membrane_c1()                        # 64 x 64, FP32 planes
+    big = W.membrane_seeded(L=512)                     # 13 FP64 planes: 27 MB
+    small = W.membrane_ellipse64()                        # 64 x 64, FP32 planes
     _say("fields_noalloc: 512x512 all planes FP64, then 64x64 rho/u FP32")
     a = B.Sim([big.problem], [big.X0])
     b = B.Sim([small.problem], [small.X0])
