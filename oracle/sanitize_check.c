@@ -1,7 +1,7 @@
 /*
  * Sanitizer driver of the D2Q9 oracle (TEST INFRASTRUCTURE ONLY): compiled
  * together with iilbm_oracle.c into one executable under AddressSanitizer and
- * UndefinedBehaviorSanitizer by tests/test_oracle_sanitized.py, it walks every
+ * UndefinedBehaviorSanitizer by tests/test_sanitized.py, it walks every
  * path of the oracle once on small problems: the membrane under the four
  * force modes with SRT and MRT, the cubic-spline membrane, the cut-link
  * enumerations (chord-wise, brute force, spline, level set), the walled

@@ -1,7 +1,7 @@
 /*
  * Sanitizer driver of the D3Q19 oracle (TEST INFRASTRUCTURE ONLY): compiled
  * together with iilbm3_oracle.c into one executable under AddressSanitizer and
- * UndefinedBehaviorSanitizer by tests/test_oracle_sanitized.py.  It walks the
+ * UndefinedBehaviorSanitizer by tests/test_sanitized.py.  It walks the
  * level-set sphere (II-LBM and IB-LBM, SRT and MRT), the fixed triangulated
  * surface, the deformable membrane under II-LBM and IB-LBM, the rigid surface
  * and the free sphere once each, on a small periodic box with a geodesic

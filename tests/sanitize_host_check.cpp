@@ -1,5 +1,5 @@
 // Host-side sanitizer driver of the II-LBM library (test infrastructure):
-// tests/test_oracle_sanitized.py builds the library's host code with
+// tests/test_sanitized.py builds the library's host code with
 // AddressSanitizer and UndefinedBehaviorSanitizer and links this driver to it.
 // It exercises every path that runs without a GPU: problem validation and
 // workspace layout (ii_lbm_workspace_size, and ii_lbm_init on problems that
