@@ -557,6 +557,8 @@ struct Batch {
     int storage, math, iface;
     int guo;               // Guo's force term (uniform over the batch)
     int jumps;             // II-LBM force mode (uniform over the batch)
+    const int2* geo_table; // (instance, block of 256 markers): membrane geometry
+    int geo_units;
 };
 
 // What other translation units may see of a handle: descriptors (host and

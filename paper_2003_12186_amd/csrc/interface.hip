@@ -31,6 +31,113 @@ __device__ __forceinline__ int wrap_or_clamp(int v, int n, int periodic)
     return v < 0 ? 0 : (v >= n ? n - 1 : v);
 }
 
+// Spring force kappa (X_{k+1} - 2 X_k + X_{k-1}) / dX^2 (Sec. 2.2.2,
+// Eq. (19)) of membrane marker k, its outward normal and |dX/ds|: from the
+// spline tangent at the knot (geometry 1), else from the central chord with
+// the mean length of the two chords at the marker.
+__device__ __forceinline__ void membrane_geometry(const InstDev& I, const DevPtrs& P, int m, int kp,
+                                                  double2 Xm, double2 Xk, double2 Xp, double& gx,
+                                                  double& gy, double& nx_, double& ny_, double& jac)
+{
+    const double d2 = I.dX * I.dX;
+    gx = I.kappa * (Xp.x - 2.0 * Xk.x + Xm.x) / d2;
+    gy = I.kappa * (Xp.y - 2.0 * Xk.y + Xm.y) / d2;
+    if (I.geometry == 1) {
+        // spline tangent at the knot, T = S_k'(0), its normal and |T| / dX
+        const double2 Mk = P.M[m], Mp = P.M[I.mk_off + kp];
+        const double tx = Xp.x - Xk.x - (2.0 * Mk.x + Mp.x) / 6.0;
+        const double ty = Xp.y - Xk.y - (2.0 * Mk.y + Mp.y) / 6.0;
+        const double tl = sqrt(tx * tx + ty * ty);
+        nx_ = ty / tl;
+        ny_ = -tx / tl;
+        jac = tl / I.dX;
+    } else {
+        // outward normal of the counter-clockwise curve, from the central chord
+        const double tx = Xp.x - Xm.x, ty = Xp.y - Xm.y;
+        const double tl = sqrt(tx * tx + ty * ty);
+        nx_ = ty / tl;
+        ny_ = -tx / tl;
+        // |dX/ds|: mean length of the two chords at the marker over Delta X
+        const double lp = hypot(Xp.x - Xk.x, Xp.y - Xk.y);
+        const double lm = hypot(Xk.x - Xm.x, Xk.y - Xm.y);
+        jac = (lp + lm) / (2.0 * I.dX);
+    }
+}
+
+// [[p]] = G.n / |dX/ds| (Sec. 3.1, Eq. (40)) and G_par = G - (G.n) n (Eq. (46))
+// of marker m.
+__device__ __forceinline__ void store_marker_force(const DevPtrs& P, int m, double gx, double gy,
+                                                   double nx_, double ny_, double jac)
+{
+    const double gn = gx * nx_ + gy * ny_;
+    P.G[m] = make_double2(gx, gy);
+    P.jp[m] = gn / jac;
+    P.Gt[m] = make_double2(gx - gn * nx_, gy - gn * ny_);
+}
+
+// The tiles within 2.5 lu of chord (k, k+1), [tx0, tx1] x [ty0, ty1]: those
+// tiles hold the nodes whose links it can cut and the support of marker k's
+// delta.  False when the chord is not finite.
+__device__ __forceinline__ bool chord_tiles(const InstDev& I, const DevPtrs& P, int m, int kp,
+                                            double2 Xk, double2 Xp, int& tx0, int& tx1, int& ty0,
+                                            int& ty1)
+{
+    double xmin = fmin(Xk.x, Xp.x) - 2.5, xmax = fmax(Xk.x, Xp.x) + 2.5;
+    double ymin = fmin(Xk.y, Xp.y) - 2.5, ymax = fmax(Xk.y, Xp.y) + 2.5;
+    if (I.geometry == 1) {
+        // the spline segment lies in the hull of its Bezier control points
+        const double2 Mk = P.M[m], Mp = P.M[I.mk_off + kp];
+        const double bx = Xp.x - Xk.x - (2.0 * Mk.x + Mp.x) / 6.0;
+        const double by = Xp.y - Xk.y - (2.0 * Mk.y + Mp.y) / 6.0;
+        const double ex_ = Xp.x - Xk.x + (Mk.x + 2.0 * Mp.x) / 6.0;   // S'(1)
+        const double ey_ = Xp.y - Xk.y + (Mk.y + 2.0 * Mp.y) / 6.0;
+        const double c1x = Xk.x + bx / 3.0, c1y = Xk.y + by / 3.0;
+        const double c2x = Xp.x - ex_ / 3.0, c2y = Xp.y - ey_ / 3.0;
+        xmin = fmin(xmin, fmin(c1x, c2x) - 2.5);
+        xmax = fmax(xmax, fmax(c1x, c2x) + 2.5);
+        ymin = fmin(ymin, fmin(c1y, c2y) - 2.5);
+        ymax = fmax(ymax, fmax(c1y, c2y) + 2.5);
+    }
+    if (!(xmin == xmin) || !(ymin == ymin) || !(xmax == xmax) || !(ymax == ymax)) return false;
+    tx0 = max(0, (int)floor(fmax(xmin, 0.0) / kTile));
+    tx1 = min(I.tiles_x - 1, (int)floor(fmin(xmax, (double)I.nx) / kTile));
+    ty0 = max(0, (int)floor(fmax(ymin, 0.0) / kTile));
+    ty1 = min(I.tiles_y - 1, (int)floor(fmin(ymax, (double)I.ny) / kTile));
+    return true;
+}
+
+// Chord k at position `pos` of tile t's list (pos taken from the tile's
+// count); the tile's first chord also lists the tile as active.
+__device__ __forceinline__ void list_chord(const InstDev& I, const DevPtrs& P, int par, int k, int t,
+                                           int pos)
+{
+    if (pos < I.tile_cap)
+        P.tile_list[I.list_off + (long long)t * I.tile_cap + pos] = k;
+    else
+        atomicOr(&P.err[I.inst], (int)kErrCapacity);
+    if (pos == 0) {
+        const int a = atomicAdd(&P.act_count[2 * I.inst + par], 1);
+        if (a < I.act_cap)
+            P.act_list[par][I.act_off + a] = make_int2(I.inst, t);
+        else
+            atomicOr(&P.err[I.inst], (int)kErrCapacity);
+    }
+}
+
+// Bin chord (k, k+1) into its tiles; the calling lanes take the tiles first,
+// first + stride, ...
+__device__ __forceinline__ void bin_chord(const InstDev& I, const DevPtrs& P, int par, int k, int m,
+                                          int kp, double2 Xk, double2 Xp, int first, int stride)
+{
+    int tx0, tx1, ty0, ty1;
+    if (!chord_tiles(I, P, m, kp, Xk, Xp, tx0, tx1, ty0, ty1)) return;
+    const int tw = tx1 - tx0 + 1, ntile = tw * (ty1 - ty0 + 1);
+    for (int q = first; q < ntile; q += stride) {
+        const int t = (ty0 + q / tw) * I.tiles_x + tx0 + q % tw;
+        list_chord(I, P, par, k, t, atomicAdd(&P.tile_count[I.tile_off + t], 1));
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Markers: 16 lanes per marker, one per node of the 4 x 4 delta stencil.
 //
@@ -163,30 +270,7 @@ __device__ __forceinline__ void markers_body(const InstDev& I, const DevPtrs& P,
         const double2 Xm = X[km];
         double gx, gy, nx_, ny_, jac;
         if (I.iface == II_LBM_IF_MEMBRANE) {
-            // spring force kappa (X_{k+1} - 2 X_k + X_{k-1}) / dX^2 (Sec. 2.2.2, Eq. (19))
-            const double d2 = I.dX * I.dX;
-            gx = I.kappa * (Xp.x - 2.0 * Xk.x + Xm.x) / d2;
-            gy = I.kappa * (Xp.y - 2.0 * Xk.y + Xm.y) / d2;
-            if (I.geometry == 1) {
-                // spline tangent at the knot, T = S_k'(0), its normal and |T| / dX
-                const double2 Mk = P.M[m], Mp = P.M[I.mk_off + kp];
-                const double tx = Xp.x - Xk.x - (2.0 * Mk.x + Mp.x) / 6.0;
-                const double ty = Xp.y - Xk.y - (2.0 * Mk.y + Mp.y) / 6.0;
-                const double tl = sqrt(tx * tx + ty * ty);
-                nx_ = ty / tl;
-                ny_ = -tx / tl;
-                jac = tl / I.dX;
-            } else {
-                // outward normal of the counter-clockwise curve, from the central chord
-                const double tx = Xp.x - Xm.x, ty = Xp.y - Xm.y;
-                const double tl = sqrt(tx * tx + ty * ty);
-                nx_ = ty / tl;
-                ny_ = -tx / tl;
-                // |dX/ds|: mean length of the two chords at the marker over Delta X
-                const double lp = hypot(Xp.x - Xk.x, Xp.y - Xk.y);
-                const double lm = hypot(Xk.x - Xm.x, Xk.y - Xm.y);
-                jac = (lp + lm) / (2.0 * I.dX);
-            }
+            membrane_geometry(I, P, m, kp, Xm, Xk, Xp, gx, gy, nx_, ny_, jac);
         } else if (I.iface == II_LBM_IF_NORMAL) {
             // prescribed uniform normal force F n on the fixed circle (Sec. 4.1)
             nx_ = (Xk.x - I.cx) / I.radius;
@@ -211,54 +295,96 @@ __device__ __forceinline__ void markers_body(const InstDev& I, const DevPtrs& P,
             ny_ = ry / I.radius;
             jac = 1.0;
         }
-        // [[p]] = G.n / |dX/ds| (Sec. 3.1, Eq. (40)); G_par = G - (G.n) n (Eq. (46))
-        const double gn = gx * nx_ + gy * ny_;
-        P.G[m] = make_double2(gx, gy);
-        P.jp[m] = gn / jac;
-        P.Gt[m] = make_double2(gx - gn * nx_, gy - gn * ny_);
+        store_marker_force(P, m, gx, gy, nx_, ny_, jac);
     }
+    bin_chord(I, P, par, k, m, kp, Xk, Xp, s, 16);   // one tile per lane of the group
+}
 
-    // Bin chord (k, k+1) into every tile within 2.5 lu of it (those tiles hold
-    // the nodes whose links it can cut and the support of marker k's delta),
-    // one tile per lane of the group.
-    double xmin = fmin(Xk.x, Xp.x) - 2.5, xmax = fmax(Xk.x, Xp.x) + 2.5;
-    double ymin = fmin(Xk.y, Xp.y) - 2.5, ymax = fmax(Xk.y, Xp.y) + 2.5;
-    if (I.geometry == 1) {
-        // the spline segment lies in the hull of its Bezier control points
-        const double2 Mk = P.M[m], Mp = P.M[I.mk_off + kp];
-        const double bx = Xp.x - Xk.x - (2.0 * Mk.x + Mp.x) / 6.0;
-        const double by = Xp.y - Xk.y - (2.0 * Mk.y + Mp.y) / 6.0;
-        const double ex_ = Xp.x - Xk.x + (Mk.x + 2.0 * Mp.x) / 6.0;   // S'(1)
-        const double ey_ = Xp.y - Xk.y + (Mk.y + 2.0 * Mp.y) / 6.0;
-        const double c1x = Xk.x + bx / 3.0, c1y = Xk.y + by / 3.0;
-        const double c2x = Xp.x - ex_ / 3.0, c2y = Xp.y - ey_ / 3.0;
-        xmin = fmin(xmin, fmin(c1x, c2x) - 2.5);
-        xmax = fmax(xmax, fmax(c1x, c2x) + 2.5);
-        ymin = fmin(ymin, fmin(c1y, c2y) - 2.5);
-        ymax = fmax(ymax, fmax(c1y, c2y) + 2.5);
+// Membrane geometry (GEOM) with one thread per marker: the same values as
+// the 16-lane form, whose per-marker arithmetic would run on one lane of 16.
+// The block's 256 consecutive chords bin to a few tiles: they are counted per
+// tile in LDS first, so that each tile's global count takes one atomic per
+// block (a chord's fifth and later tiles, and tiles beyond the LDS table,
+// take theirs directly).  The lists' order is immaterial: the tile pass
+// orders every tile's chords by index.
+constexpr int kGeoHash = 128;   // distinct tiles of a block counted in LDS
+constexpr int kGeoTiles = 4;    // tiles of one chord counted in LDS
+
+__device__ __forceinline__ void geom_body(const InstDev& I, const DevPtrs& P, int par, int k)
+{
+    __shared__ int hkey[kGeoHash], hcnt[kGeoHash], hbase[kGeoHash];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < kGeoHash; i += blockDim.x) {
+        hkey[i] = -1;
+        hcnt[i] = 0;
     }
-    if (!(xmin == xmin) || !(ymin == ymin) || !(xmax == xmax) || !(ymax == ymax)) return;
-    const int tx0 = max(0, (int)floor(fmax(xmin, 0.0) / kTile));
-    const int tx1 = min(I.tiles_x - 1, (int)floor(fmin(xmax, (double)I.nx) / kTile));
-    const int ty0 = max(0, (int)floor(fmax(ymin, 0.0) / kTile));
-    const int ty1 = min(I.tiles_y - 1, (int)floor(fmin(ymax, (double)I.ny) / kTile));
-    const int tw = tx1 - tx0 + 1, ntile = tw * (ty1 - ty0 + 1);
-    for (int q = s; q < ntile; q += 16) {
-        const int t = (ty0 + q / tw) * I.tiles_x + tx0 + q % tw;
-        const int gt = I.tile_off + t;
-        const int pos = atomicAdd(&P.tile_count[gt], 1);
-        if (pos < I.tile_cap)
-            P.tile_list[I.list_off + (long long)t * I.tile_cap + pos] = k;
-        else
-            atomicOr(&P.err[I.inst], (int)kErrCapacity);
-        if (pos == 0) {
-            const int a = atomicAdd(&P.act_count[2 * I.inst + par], 1);
-            if (a < I.act_cap)
-                P.act_list[par][I.act_off + a] = make_int2(I.inst, t);
-            else
-                atomicOr(&P.err[I.inst], (int)kErrCapacity);
+    const int N = I.n_markers;
+    int nt = 0, tx0 = 0, ty0 = 0, tw = 1;   // this thread's chord's tiles
+    if (k < N) {
+        const double2* X = P.X[par] + I.mk_off;
+        const int m = I.mk_off + k;
+        const double2 Xk = X[k];
+        if (Xk.x >= 0.0 && Xk.x < (double)I.nx && Xk.y >= 0.0 && Xk.y < (double)I.ny) {
+            const int fx0 = (int)floor(Xk.x) - 1, fy0 = (int)floor(Xk.y) - 1;
+            // the per-axis delta weights, reused by the spread of this step
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                P.wx[4 * m + q] = peskin((double)(fx0 + q) - Xk.x);
+                P.wy[4 * m + q] = peskin((double)(fy0 + q) - Xk.y);
+            }
+            P.f0[m] = make_int2(fx0, fy0);
+            const int km = (k + N - 1) % N, kp = (k + 1) % N;
+            const double2 Xm = X[km], Xp = X[kp];
+            double gx, gy, nx_, ny_, jac;
+            membrane_geometry(I, P, m, kp, Xm, Xk, Xp, gx, gy, nx_, ny_, jac);
+            store_marker_force(P, m, gx, gy, nx_, ny_, jac);
+            int tx1, ty1;
+            if (chord_tiles(I, P, m, kp, Xk, Xp, tx0, tx1, ty0, ty1)) {
+                tw = tx1 - tx0 + 1;
+                nt = tw * (ty1 - ty0 + 1);
+            }
+        } else {
+            // non-finite or outside the lattice: keep the marker, flag the handle
+            atomicOr(&P.err[I.inst], isfinite(Xk.x) && isfinite(Xk.y) ? (int)kErrGeometry
+                                                                      : (int)kErrUnstable);
+            P.G[m] = make_double2(0.0, 0.0);
+            P.Gt[m] = make_double2(0.0, 0.0);
+            P.jp[m] = 0.0;
         }
     }
+    __syncthreads();
+    int hs[kGeoTiles], lp[kGeoTiles];
+#pragma unroll
+    for (int q = 0; q < kGeoTiles; q++) {
+        hs[q] = -1;
+        lp[q] = 0;
+        if (q >= nt) continue;
+        const int t = (ty0 + q / tw) * I.tiles_x + tx0 + q % tw;
+        unsigned h = ((unsigned)t * 2654435761u) >> 25;   // 7 bits: kGeoHash = 128
+        for (int probe = 0; probe < kGeoHash; probe++) {
+            const int prev = atomicCAS(&hkey[h], -1, t);
+            if (prev == -1 || prev == t) {
+                hs[q] = (int)h;
+                break;
+            }
+            h = (h + 1) & (kGeoHash - 1);
+        }
+        if (hs[q] >= 0)
+            lp[q] = atomicAdd(&hcnt[hs[q]], 1);
+        else
+            list_chord(I, P, par, k, t, atomicAdd(&P.tile_count[I.tile_off + t], 1));
+    }
+    for (int q = kGeoTiles; q < nt; q++) {
+        const int t = (ty0 + q / tw) * I.tiles_x + tx0 + q % tw;
+        list_chord(I, P, par, k, t, atomicAdd(&P.tile_count[I.tile_off + t], 1));
+    }
+    __syncthreads();
+    for (int i = tid; i < kGeoHash; i += blockDim.x)
+        if (hkey[i] >= 0) hbase[i] = atomicAdd(&P.tile_count[I.tile_off + hkey[i]], hcnt[i]);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kGeoTiles; q++)
+        if (hs[q] >= 0) list_chord(I, P, par, k, hkey[hs[q]], hbase[hs[q]] + lp[q]);
 }
 
 // Before the tiles of step m are binned: the tiles of step m-2 (same slot
@@ -300,6 +426,20 @@ __global__ __launch_bounds__(256) void k_markers_batch(const InstDev* __restrict
     markers_body<T, M, MODE>(I, P, A, par, u.y);
 }
 
+__global__ __launch_bounds__(256) void k_geom(InstDev I, DevPtrs P, int par)
+{
+    geom_body(I, P, par, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_geom_batch(const InstDev* __restrict__ insts,
+                                                    const int2* __restrict__ units, DevPtrs P,
+                                                    int par)
+{
+    const int2 u = units[blockIdx.x];
+    const InstDev I = insts[u.x];
+    geom_body(I, P, par, u.y * blockDim.x + threadIdx.x);
+}
+
 __global__ __launch_bounds__(256) void k_slot_reset(InstDev I, DevPtrs P, int par)
 {
     slot_reset_body(I, P, par);
@@ -339,6 +479,10 @@ hipError_t launch_markers(const InstDev& I, const DevPtrs& P, const void* A, int
 {
     if (I.n_markers == 0) return hipSuccess;
     if (mode == kModeInterp) return markers_m<kModeInterp>(I, P, A, par, s);
+    if (mode == kModeGeom && I.iface == II_LBM_IF_MEMBRANE) {
+        hipLaunchKernelGGL(k_geom, dim3((I.n_markers + 255) / 256), dim3(256), 0, s, I, P, par);
+        return hipGetLastError();
+    }
     if (mode == kModeGeom) return markers_m<kModeGeom>(I, P, A, par, s);
     return markers_m<kModeFull>(I, P, A, par, s);
 }
@@ -369,6 +513,11 @@ hipError_t launch_markers_batch(const Batch& b, const DevPtrs& P, const void* A,
 {
     if (b.mk_units == 0) return hipSuccess;
     if (mode == kModeInterp) return markers_batch_m<kModeInterp>(b, P, A, par, s);
+    if (mode == kModeGeom && b.iface == II_LBM_IF_MEMBRANE) {
+        hipLaunchKernelGGL(k_geom_batch, dim3(b.geo_units), dim3(256), 0, s, b.insts, b.geo_table,
+                           P, par);
+        return hipGetLastError();
+    }
     if (mode == kModeGeom) return markers_batch_m<kModeGeom>(b, P, A, par, s);
     return markers_batch_m<kModeFull>(b, P, A, par, s);
 }
@@ -1263,16 +1412,25 @@ __global__ __launch_bounds__(256) void k_tiles_ib_batch(const InstDev* __restric
     tiles_ib_body(I, P, parity, u.y, I.tile_blocks);
 }
 
+// Membrane tile blocks (without records) are held to 80 registers (six waves
+// per SIMD), so that beside the tile pass the sweep keeps wave slots and
+// registers on every CU: 4 tile blocks per CU at 96 registers left it three
+// waves per SIMD, at 80 four.
+constexpr int tile_waves(int iface, bool rec)
+{
+    return iface == II_LBM_IF_MEMBRANE && !rec ? 6 : 1;
+}
+
 template <int IFACE, bool REC>
-__global__ __launch_bounds__(256) void k_tiles(InstDev I, DevPtrs P, int parity)
+__global__ __launch_bounds__(256, tile_waves(IFACE, REC)) void k_tiles(InstDev I, DevPtrs P,
+                                                                       int parity)
 {
     tiles_body<IFACE, REC>(I, P, parity, blockIdx.x, gridDim.x);
 }
 
 template <int IFACE, bool REC>
-__global__ __launch_bounds__(256) void k_tiles_batch(const InstDev* __restrict__ insts,
-                                                     const int2* __restrict__ units, DevPtrs P,
-                                                     int parity)
+__global__ __launch_bounds__(256, tile_waves(IFACE, REC)) void k_tiles_batch(
+    const InstDev* __restrict__ insts, const int2* __restrict__ units, DevPtrs P, int parity)
 {
     const int2 u = units[blockIdx.x];
     const InstDev I = insts[u.x];

@@ -70,7 +70,8 @@ struct Layout {
     size_t off_M = 0, off_taps = 0;
     int taps_total = 0;
     size_t off_insts = 0, off_mk_table = 0, off_tile_table = 0, off_sweep_table = 0;
-    int mk_units = 0, tile_units = 0, sweep_units_max = 0;
+    size_t off_geo_table = 0;
+    int mk_units = 0, tile_units = 0, sweep_units_max = 0, geo_units = 0;
     size_t total = 0;
     int n_markers_total = 0, tiles_total = 0, act_total = 0, rec_total = 0;
 };
@@ -234,6 +235,7 @@ int build_layout(const ii_lbm_problem* p, int n_inst, Layout& L)
         I.mk_blocks = (16 * I.n_markers + 255) / 256;
         I.tile_blocks = std::max(1, std::min(I.act_cap, 2048));
         L.mk_units += I.n_markers > 0 ? I.mk_blocks : 0;
+        L.geo_units += (I.n_markers + 255) / 256;
         L.sweep_units_max += (int)(((long long)q.nx * q.ny + 127) / 128);
         if (j == n_inst - 1) L.sweep_units_max += kXcds;   // padding of the XCD interleave
         L.inst[j] = I;
@@ -285,6 +287,7 @@ int build_layout(const ii_lbm_problem* p, int n_inst, Layout& L)
     for (const InstDev& I : L.inst) tile_units += I.n_markers > 0 ? I.act_cap : 0;
     L.off_insts = take((size_t)n_inst * sizeof(InstDev));
     L.off_mk_table = take((size_t)std::max(L.mk_units, 1) * sizeof(int2));
+    L.off_geo_table = take((size_t)std::max(L.geo_units, 1) * sizeof(int2));
     L.off_tile_table = take((size_t)std::max(tile_units, 1) * sizeof(int2));
     L.off_sweep_table = take((size_t)std::max(L.sweep_units_max, 1) * sizeof(int2));
     L.total = o;
@@ -915,6 +918,7 @@ int ii_lbm_init(const ii_lbm_problem* p, int32_t n_inst, const double* const* X0
         Batch& b = h->batch;
         b.insts = (const InstDev*)(h->ws + L.off_insts);
         b.mk_table = (const int2*)(h->ws + L.off_mk_table);
+        b.geo_table = (const int2*)(h->ws + L.off_geo_table);
         b.tile_table = (const int2*)(h->ws + L.off_tile_table);
         b.sweep_table = (const int2*)(h->ws + L.off_sweep_table);
         b.storage = p[0].storage;
@@ -922,7 +926,7 @@ int ii_lbm_init(const ii_lbm_problem* p, int32_t n_inst, const double* const* X0
         b.iface = iface;
         b.guo = h->L.inst[0].guo;
         b.jumps = h->L.inst[0].jumps;
-        std::vector<int2> mk, tl;
+        std::vector<int2> mk, tl, geo;
         h->tile_est.assign(n_inst, 0);
         for (int j = 0; j < n_inst; j++) {
             InstDev& I = h->L.inst[j];
@@ -931,13 +935,17 @@ int ii_lbm_init(const ii_lbm_problem* p, int32_t n_inst, const double* const* X0
             h->tile_est[j] = est;
             I.tile_blocks = std::max(1, std::min(I.act_cap, est + est / 4 + 1));
             for (int q = 0; q < I.mk_blocks; q++) mk.push_back(make_int2(j, q));
+            for (int q = 0; q < (I.n_markers + 255) / 256; q++) geo.push_back(make_int2(j, q));
             for (int q = 0; q < I.tile_blocks; q++) tl.push_back(make_int2(j, q));
         }
         b.mk_units = (int)mk.size();
+        b.geo_units = (int)geo.size();
         b.tile_units = (int)tl.size();
         e = hipMemcpy((void*)b.insts, h->L.inst.data(), n_inst * sizeof(InstDev), hipMemcpyHostToDevice);
         if (e == hipSuccess && !mk.empty())
             e = hipMemcpy((void*)b.mk_table, mk.data(), mk.size() * sizeof(int2), hipMemcpyHostToDevice);
+        if (e == hipSuccess && !geo.empty())
+            e = hipMemcpy((void*)b.geo_table, geo.data(), geo.size() * sizeof(int2), hipMemcpyHostToDevice);
         if (e == hipSuccess && !tl.empty())
             e = hipMemcpy((void*)b.tile_table, tl.data(), tl.size() * sizeof(int2), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = upload_sweep_table(h, 256, 1);
