@@ -344,13 +344,15 @@ int ii_lbm_set_overlap(ii_lbm_handle* h, int32_t mode);
  *  1. the batched sweep (writing only the buffer the next step overwrites)
  *     for slices of 128, 256 and 512 nodes and two instance orders (as
  *     given, largest first), `trials` launches each;
- *  2. for membranes, whose interface pass runs beside the sweep, the
- *     footprint of the tile pass (ii_lbm_set_tile_blocks: 0, 16, 8, 4, 2 and
- *     1 blocks per CU), timed on `trials` whole steps each.  A step started
- *     again from the same state recomputes the same results, so the state is
- *     left as it was.
- * It keeps the fastest of each.  Outputs (may be NULL): the slice size, the
- * order and the sweep's time in us (ii_lbm_get_schedule reports the rest).
+ *  2. for membranes, whose interface pass runs beside the sweep, the slice
+ *     size again (in the order of stage 1) together with the footprint of the
+ *     tile pass (ii_lbm_set_tile_blocks: 0, 16, 8, 4, 2 and 1 blocks per CU),
+ *     timed on `trials` whole steps per pair.  A step started again from the
+ *     same state recomputes the same results, so the state is left as it was.
+ * It keeps the fastest order of stage 1 and the fastest pair of stage 2 (the
+ * fastest slice of stage 1 without it).  Outputs (may be NULL): the slice
+ * size, the order and that schedule's sweep time alone in us
+ * (ii_lbm_get_schedule reports the rest).
  * A single-instance handle reports 0 and keeps its row-segment sweep. */
 int ii_lbm_autotune(ii_lbm_handle* h, int32_t trials, int32_t* unit, int32_t* order, double* best_us);
 

@@ -1122,7 +1122,7 @@ int ii_lbm_autotune(ii_lbm_handle* h, int32_t trials, int32_t* unit, int32_t* or
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return hip_fail(h, hipErrorUnknown);
     const int units[3] = {128, 256, 512};
-    double best = 1e300;
+    double best = 1e300, alone[2][3] = {{0.0}};
     int bu = 256, bo = 1;
     hipError_t e = hipSuccess;
     for (int o = 0; o < 2 && e == hipSuccess; o++)
@@ -1140,6 +1140,7 @@ int ii_lbm_autotune(ii_lbm_handle* h, int32_t trials, int32_t* unit, int32_t* or
             float ms = 0.f;
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
             const double us = 1e3 * ms / trials;
+            alone[o][ui] = us;
             if (e == hipSuccess && us < best) {
                 best = us;
                 bu = units[ui];
@@ -1147,33 +1148,43 @@ int ii_lbm_autotune(ii_lbm_handle* h, int32_t trials, int32_t* unit, int32_t* or
             }
         }
     if (e == hipSuccess) e = upload_sweep_table(h, bu, bo);
-    // Membranes whose interface pass runs beside the sweep: the footprint of
-    // the tile pass, timed on whole steps.  A step that starts again from the
-    // same parity recomputes the same results (each phase reads one plane and
-    // writes the other), so repeating it leaves the state as it was.
+    // Membranes whose interface pass runs beside the sweep: the slice width
+    // (in the chosen order) and the footprint of the tile pass together,
+    // timed on whole steps, since the sweep's slices and the tile blocks share
+    // the CUs (widths within a microsecond of each other alone differ by a
+    // tenth of a step beside the interface pass).  A step that starts again
+    // from the same parity recomputes the same results (each phase reads one
+    // plane and writes the other), so repeating it leaves the state as it was.
     double best_step = 0.0;
     if (e == hipSuccess && h->lookahead && h->overlap != II_LBM_OVERLAP_SERIAL) {
         const int cands[6] = {0, 16, 8, 4, 2, 1};
-        int bc = 0;
+        int bc = 0, bw = bu;
         best_step = 1e300;
-        for (int ci = 0; ci < 6 && e == hipSuccess; ci++) {
-            e = upload_tile_table(h, cands[ci]);
-            if (e == hipSuccess) e = enqueue_step(h, h->parity, h->stream, false);
-            if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
-            for (int t = 0; t < trials && e == hipSuccess; t++)
-                e = enqueue_step(h, h->parity, h->stream, false);
-            if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0.f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            const double us = 1e3 * ms / trials;
-            if (e == hipSuccess && us < best_step) {
-                best_step = us;
-                bc = cands[ci];
+        for (int ui = 0; ui < 3 && e == hipSuccess; ui++) {
+            e = upload_sweep_table(h, units[ui], bo);
+            for (int ci = 0; ci < 6 && e == hipSuccess; ci++) {
+                e = upload_tile_table(h, cands[ci]);
+                if (e == hipSuccess) e = enqueue_step(h, h->parity, h->stream, false);
+                if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+                for (int t = 0; t < trials && e == hipSuccess; t++)
+                    e = enqueue_step(h, h->parity, h->stream, false);
+                if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                const double us = 1e3 * ms / trials;
+                if (e == hipSuccess && us < best_step) {
+                    best_step = us;
+                    bc = cands[ci];
+                    bw = units[ui];
+                }
             }
         }
         if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e == hipSuccess) e = upload_sweep_table(h, bw, bo);
         if (e == hipSuccess) e = upload_tile_table(h, bc);
+        bu = bw;
+        best = alone[bo][bw == 128 ? 0 : bw == 256 ? 1 : 2];
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
