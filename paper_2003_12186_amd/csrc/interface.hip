@@ -1,8 +1,11 @@
 // Interface kernels of one II-LBM step (compiled without FP contraction so
 // that the FP64 geometry is evaluated exactly as written):
-//   k_markers  one thread per marker: interpolated velocity U^n, force G^n,
-//              outward normal, |dX/ds|, [[p]] and the tangential part; the new
-//              position X^{n+1}; binning of chord (k, k+1) into 16x16 tiles.
+//   k_markers  16 lanes per marker (one per stencil node): interpolated
+//              velocity U^n, force G^n, outward normal, |dX/ds|, [[p]] and the
+//              tangential part; the new position X^{n+1}; binning of chord
+//              (k, k+1) into 16x16 tiles.
+//   k_geom_batch  the geometry and binning of batched membranes, one thread
+//              per marker, tile counts gathered per block in LDS.
 //   k_tiles    one block per tile that holds chords: spreads the tangential
 //              force (the whole force under IB-LBM) onto its nodes, finds
 //              (under II-LBM) every cut link leaving its nodes
@@ -300,13 +303,16 @@ __device__ __forceinline__ void markers_body(const InstDev& I, const DevPtrs& P,
     bin_chord(I, P, par, k, m, kp, Xk, Xp, s, 16);   // one tile per lane of the group
 }
 
-// Membrane geometry (GEOM) with one thread per marker: the same values as
-// the 16-lane form, whose per-marker arithmetic would run on one lane of 16.
-// The block's 256 consecutive chords bin to a few tiles: they are counted per
-// tile in LDS first, so that each tile's global count takes one atomic per
-// block (a chord's fifth and later tiles, and tiles beyond the LDS table,
-// take theirs directly).  The lists' order is immaterial: the tile pass
-// orders every tile's chords by index.
+// Membrane geometry (GEOM) of batched membranes, one thread per marker: the
+// same values as the 16-lane form, whose per-marker arithmetic would run on
+// one lane of 16.  The block's 256 consecutive chords bin to a few tiles:
+// they are counted per tile in LDS first, so that each tile's global count
+// takes one atomic per block (a chord's fifth and later tiles, and tiles
+// beyond the LDS table, take theirs directly).  With hundreds of thousands
+// of markers the per-chord atomics had made this pass 4.5 times longer.  The
+// lists' order is immaterial: the tile pass orders every tile's chords by
+// index.  (A single membrane of a few thousand markers keeps the 16-lane
+// form, whose pass is shorter there.)
 constexpr int kGeoHash = 128;   // distinct tiles of a block counted in LDS
 constexpr int kGeoTiles = 4;    // tiles of one chord counted in LDS
 
@@ -426,11 +432,6 @@ __global__ __launch_bounds__(256) void k_markers_batch(const InstDev* __restrict
     markers_body<T, M, MODE>(I, P, A, par, u.y);
 }
 
-__global__ __launch_bounds__(256) void k_geom(InstDev I, DevPtrs P, int par)
-{
-    geom_body(I, P, par, blockIdx.x * blockDim.x + threadIdx.x);
-}
-
 __global__ __launch_bounds__(256) void k_geom_batch(const InstDev* __restrict__ insts,
                                                     const int2* __restrict__ units, DevPtrs P,
                                                     int par)
@@ -479,10 +480,6 @@ hipError_t launch_markers(const InstDev& I, const DevPtrs& P, const void* A, int
 {
     if (I.n_markers == 0) return hipSuccess;
     if (mode == kModeInterp) return markers_m<kModeInterp>(I, P, A, par, s);
-    if (mode == kModeGeom && I.iface == II_LBM_IF_MEMBRANE) {
-        hipLaunchKernelGGL(k_geom, dim3((I.n_markers + 255) / 256), dim3(256), 0, s, I, P, par);
-        return hipGetLastError();
-    }
     if (mode == kModeGeom) return markers_m<kModeGeom>(I, P, A, par, s);
     return markers_m<kModeFull>(I, P, A, par, s);
 }
