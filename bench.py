@@ -1092,6 +1092,10 @@ def bench_batch(args, B, W) -> int:
     set_overlap(sim, B, args)
     sim.step(2)
     tune = sim.autotune(5)
+    if args.tile_blocks is not None:
+        sim.set_tile_blocks(args.tile_blocks)
+        tune["tile_blocks_per_cu"] = args.tile_blocks
+        tune["forced"] = True
     sim.set_graph(args.graph == "on")
     sim.step(args.warmup)
     sim.sync()
@@ -1183,6 +1187,8 @@ def main() -> int:
                     help="learned workload: strength of the correction (1 = as trained)")
     ap.add_argument("--instances", type=int, default=None,
                     help="instances of the batch512 (default 512) or learned (200) workload")
+    ap.add_argument("--tile-blocks", type=int, default=None, metavar="PER_CU",
+                    help="batch512: tile-pass blocks per CU after autotuning (0: one per tile)")
     ap.add_argument("--graph", choices=["on", "off"], default="on",
                     help="replay steps as HIP graphs (two steps per replay) or launch directly")
     ap.add_argument("--overlap", choices=["default", "serial", "full", "interp_first"],
