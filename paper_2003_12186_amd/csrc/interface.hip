@@ -634,10 +634,11 @@ struct TileShared {
     int key[kTileCap];           // chord ids in increasing order
     Chord ch[kTileCap];
     short box[kTileCap][4];      // candidate source nodes of the chord's links
+    int winv[kTileCap];          // ceil(2^16 / box width): q / w as (q * winv) >> 16
     double jpa[kTileCap], jpb[kTileCap];
     float wx[kTileCap][4], wy[kTileCap][4];
     int2 f0[kTileCap];
-    double gtx[kTileCap], gty[kTileCap];
+    double gtx[kTileCap], gty[kTileCap];   // G_par dX of each chord's marker
     int acc[8][kTileNodes];      // jump sums of the eight outgoing populations per node
     unsigned char strip[4][kTileCap];   // per wave: chords whose stencil meets its 4 rows
     int strip_n[4];
@@ -680,7 +681,8 @@ __device__ __forceinline__ void add_jump(TS& S, int node, int i, int sigma, doub
 }
 
 __device__ __forceinline__ double jump_sum(long long acc) { return (double)acc * (1.0 / kJumpFix); }
-__device__ __forceinline__ double jump_sum(int acc, double scale) { return (double)acc / scale; }
+// (inv_scale is the exact reciprocal of the tile's power-of-two scale)
+__device__ __forceinline__ double jump_sum(int acc, double inv_scale) { return (double)acc * inv_scale; }
 
 // The power of two that maps the tile's largest jump term to at most 2^27.
 __device__ __forceinline__ double jump_scale(unsigned jmax_bits)
@@ -757,7 +759,7 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
             atomicMax(&S.jmax, __float_as_uint((float)fmax(fabs(jpa), fabs(jpb))));
         }
         __syncthreads();   // raw is reused as start below
-        const double jscale = jump_scale(S.jmax);
+        const double jscale = jump_scale(S.jmax), jinv = 1.0 / jscale;
         if (tid < c) {
             S.key[r] = k;
             const long long ax = (long long)rint(a0.x * kSnap), ay = (long long)rint(a0.y * kSnap);
@@ -776,6 +778,8 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
             S.box[r][2] = (short)by0; S.box[r][3] = (short)by1;
             S.start[r] = (IFACE == II_LBM_IF_MEMBRANE && I.jumps && bx0 <= bx1 && by0 <= by1)
                              ? (bx1 - bx0 + 1) * (by1 - by0 + 1) : 0;
+            // exact for widths up to 16 and candidates q < 256 (the box lies in the tile)
+            S.winv[r] = bx0 <= bx1 ? (65536 + bx1 - bx0) / (bx1 - bx0 + 1) : 0;
             S.jpa[r] = jpa;
             S.jpb[r] = jpb;
             S.f0[r] = f0;
@@ -784,7 +788,7 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
                 S.wx[r][q] = (float)wxd[q];
                 S.wy[r][q] = (float)wyd[q];
             }
-            S.gtx[r] = g.x; S.gty[r] = g.y;
+            S.gtx[r] = g.x * I.dX; S.gty[r] = g.y * I.dX;   // G_par dX
         }
         __syncthreads();
 
@@ -835,7 +839,8 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
                 const int j = lo, q = g - S.start[j];
                 const int bx0 = S.box[j][0], by0 = S.box[j][2];
                 const int w = S.box[j][1] - bx0 + 1;
-                const int x = bx0 + q % w, y = by0 + q / w;
+                const int qy = (q * S.winv[j]) >> 16;
+                const int x = bx0 + q - qy * w, y = by0 + qy;
                 const Chord ch = S.ch[j];
                 const long long dx = ch.bx - ch.ax, dy = ch.by - ch.ay;
                 const long long oP = dx * (((long long)y << 16) - ch.ay) - dy * (((long long)x << 16) - ch.ax);
@@ -870,8 +875,8 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
                 const int ix = x - f.x, iy = y - f.y;
                 const bool in = (unsigned)ix <= 3u && (unsigned)iy <= 3u;
                 const double wgt = in ? (double)S.wx[j][ix & 3] * (double)S.wy[j][iy & 3] : 0.0;
-                gx += S.gtx[j] * wgt * I.dX;
-                gy += S.gty[j] * wgt * I.dX;
+                gx += S.gtx[j] * wgt;
+                gy += S.gty[j] * wgt;
             }
             if (IFACE == II_LBM_IF_RIGID && I.jumps) {
                 // Rigid circle: level set phi = |x - c|^2 - R^2, interior phi < 0.
@@ -916,7 +921,7 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
             for (int i = 1; i < 9; i++) {
                 const double delta =
                     valid ? fs * WD[i] * ((double)EX[i] * gx + (double)EY[i] * gy) +
-                                jump_sum(S.acc[i - 1][tid], jscale)
+                                jump_sum(S.acc[i - 1][tid], jinv)
                           : 0.0;
                 dl[i - 1] = (float)delta;
                 nz = nz || dl[i - 1] != 0.f;
