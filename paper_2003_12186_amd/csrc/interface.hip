@@ -423,10 +423,15 @@ __global__ __launch_bounds__(256) void k_markers(InstDev I, DevPtrs P, const T* 
 // Batched: every block looks its (instance, block) up in a work table.
 template <typename T, typename M, int MODE>
 __global__ __launch_bounds__(256) void k_markers_batch(const InstDev* __restrict__ insts,
-                                                       const int2* __restrict__ units, DevPtrs P,
-                                                       const T* __restrict__ A, int par)
+                                                       const int2* __restrict__ units, int n_units,
+                                                       DevPtrs P, const T* __restrict__ A, int par)
 {
-    const int2 u = units[blockIdx.x];
+    // workgroup b runs on XCD b mod 8: give each XCD one contiguous run of
+    // the table, so that neighbouring markers share that XCD's L2
+    const int per = gridDim.x / 8;
+    const int idx = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (idx >= n_units) return;   // padding of the grid (whole block)
+    const int2 u = units[idx];
     const InstDev I = insts[u.x];
     if (MODE == kModeInterp && u.y == 0) slot_reset_body(I, P, par ^ 1);   // as in k_markers
     markers_body<T, M, MODE>(I, P, A, par, u.y);
@@ -488,12 +493,13 @@ template <typename T, int MODE>
 static hipError_t markers_batch_t(const Batch& b, const DevPtrs& P, const void* A, int par,
                                   hipStream_t s)
 {
+    const dim3 grid(8 * ((b.mk_units + 7) / 8));
     if (b.math == II_LBM_MATH_FP64)
-        hipLaunchKernelGGL((k_markers_batch<T, double, MODE>), dim3(b.mk_units), dim3(256), 0, s,
-                           b.insts, b.mk_table, P, (const T*)A, par);
+        hipLaunchKernelGGL((k_markers_batch<T, double, MODE>), grid, dim3(256), 0, s, b.insts,
+                           b.mk_table, b.mk_units, P, (const T*)A, par);
     else
-        hipLaunchKernelGGL((k_markers_batch<T, float, MODE>), dim3(b.mk_units), dim3(256), 0, s,
-                           b.insts, b.mk_table, P, (const T*)A, par);
+        hipLaunchKernelGGL((k_markers_batch<T, float, MODE>), grid, dim3(256), 0, s, b.insts,
+                           b.mk_table, b.mk_units, P, (const T*)A, par);
     return hipGetLastError();
 }
 
