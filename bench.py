@@ -1245,12 +1245,8 @@ def main() -> int:
     p.geometry = W.GEOM_SPLINE if args.geometry == "spline" else W.GEOM_POLYGON
     sim = B.Sim([p], [w.X0], device="cuda:0")
     set_overlap(sim, B, args)
-    # the tile pass's blocks per CU beside the sweep, timed on whole steps
-    tune = sim.autotune(5)
     if args.tile_blocks is not None:
         sim.set_tile_blocks(args.tile_blocks)
-        tune["tile_blocks_per_cu"] = args.tile_blocks
-        tune["forced"] = True
     graph = args.graph == "on"
     sim.set_graph(graph)
     sim.step(args.warmup)
@@ -1299,8 +1295,7 @@ def main() -> int:
                                + ("_spline" if args.geometry == "spline" else ""),
                    "nx": p.nx, "ny": p.ny, "markers": p.n_markers, "tau": round(p.tau, 6),
                    "kappa": p.kappa, "storage": args.storage, "collision_math": args.math,
-                   "cut_links": d["n_cut_links"], "graph": graph,
-                   "tile_blocks_per_cu": tune["tile_blocks_per_cu"]},
+                   "cut_links": d["n_cut_links"], "graph": graph},
         "roofline": {"bound": "hbm", "kernel": "k_sweep", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "bytes_per_launch": bytes_per_launch,

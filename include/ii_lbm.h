@@ -353,10 +353,7 @@ int ii_lbm_set_overlap(ii_lbm_handle* h, int32_t mode);
  * fastest slice of stage 1 without it).  Outputs (may be NULL): the slice
  * size, the order and that schedule's sweep time alone in us
  * (ii_lbm_get_schedule reports the rest).
- * A single-instance handle keeps its row-segment sweep and reports 0 for all
- * three; a single membrane whose interface pass runs beside the sweep has
- * its tile pass's blocks per CU (1, 2, 4, 8) timed on `trials` whole steps
- * each in the same way, and keeps the fastest. */
+ * A single-instance handle reports 0 and keeps its row-segment sweep. */
 int ii_lbm_autotune(ii_lbm_handle* h, int32_t trials, int32_t* unit, int32_t* order, double* best_us);
 
 /* Footprint of a batched handle's tile pass: about per_cu blocks per compute
@@ -368,10 +365,10 @@ int ii_lbm_autotune(ii_lbm_handle* h, int32_t trials, int32_t* unit, int32_t* or
  * Synchronises a batched handle; EINVAL for per_cu outside 0 ... 64. */
 int ii_lbm_set_tile_blocks(ii_lbm_handle* h, int32_t per_cu);
 
-/* The schedule in use: sweep slice size, instance order, tile-pass blocks
- * per CU, and the whole-step time in us that the autotuner measured for it
- * (0 before ii_lbm_autotune or without its whole-step stage).  Outputs may be
- * NULL; a single-instance handle reports 0 for the slice size and order. */
+/* The batched schedule in use: sweep slice size, instance order, tile-pass
+ * blocks per CU, and the whole-step time in us that the autotuner measured
+ * for it (0 before ii_lbm_autotune or without its second stage).  Outputs may
+ * be NULL; a single-instance handle reports zeros. */
 int ii_lbm_get_schedule(ii_lbm_handle* h, int32_t* unit, int32_t* order, int32_t* tile_per_cu,
                         double* step_us);
 

@@ -24,7 +24,7 @@ COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(HERE, "..", "include")]
 UNITS = {
-    "sweep.hip": ["-ffp-contract=on"],
+    "sweep.hip": [],
     "interface.hip": ["-ffp-contract=off"],
     "runtime.hip": [],
     "learned.hip": [],

@@ -1114,43 +1114,6 @@ int ii_lbm_autotune(ii_lbm_handle* h, int32_t trials, int32_t* unit, int32_t* or
         if (unit) *unit = 0;
         if (order) *order = 0;
         if (best_us) *best_us = 0.0;
-        // a single membrane beside its sweep: the tile pass's blocks per CU,
-        // timed on whole steps (each started again from the same state)
-        if (!h->lookahead || h->overlap == II_LBM_OVERLAP_SERIAL) return II_LBM_OK;
-        hipEvent_t e0, e1;
-        if (hipEventCreate(&e0) != hipSuccess) return hip_fail(h, hipErrorUnknown);
-        if (hipEventCreate(&e1) != hipSuccess) {
-            (void)hipEventDestroy(e0);
-            return hip_fail(h, hipErrorUnknown);
-        }
-        const int cands[4] = {1, 2, 4, 8};
-        double best_step = 1e300;
-        int bc = 1;
-        hipError_t e = hipStreamSynchronize(h->stream);
-        for (int ci = 0; ci < 4 && e == hipSuccess; ci++) {
-            h->tile_per_cu = cands[ci];
-            size_tile_blocks(h);
-            e = enqueue_step(h, h->parity, h->stream, false);
-            if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
-            for (int t = 0; t < trials && e == hipSuccess; t++)
-                e = enqueue_step(h, h->parity, h->stream, false);
-            if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0.f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            const double us = 1e3 * ms / trials;
-            if (e == hipSuccess && us < best_step) {
-                best_step = us;
-                bc = cands[ci];
-            }
-        }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        if (e != hipSuccess) return hip_fail(h, e);
-        h->tile_per_cu = bc;
-        size_tile_blocks(h);
-        drop_graphs(h);
-        h->tuned_step_us = best_step;
         return II_LBM_OK;
     }
     // The sweep is a pure function of the current lattice: time each

@@ -17,14 +17,18 @@ namespace iilbm {
 // GUO: Guo's force term of the whole Eulerian force (the body force plus the
 // spread force the tile's slot holds in its last two planes); the slot's
 // population planes then hold the jumps alone.
-// Collision of the gathered populations d of node (x, y), in place.
-template <typename M, int COLL, bool GUO>
-__device__ __forceinline__ void finish_node(const InstDev& I, M d[9], int x, int y,
-                                            const int* __restrict__ tile_slot,
-                                            const float* __restrict__ corr,
-                                            const unsigned long long* __restrict__ cmask,
-                                            bool residue)
+template <typename T, typename M, int COLL, bool BOUNDED, bool GUO>
+__device__ __forceinline__ void sweep_node(const InstDev& I, const T* __restrict__ A,
+                                           T* __restrict__ B, int x, int y,
+                                           const int* __restrict__ tile_slot,
+                                           const float* __restrict__ corr,
+                                           const unsigned long long* __restrict__ cmask)
 {
+    M d[9];
+    if (BOUNDED && is_edge(I, x, y))
+        nee<T, M>(I, A, x, y, d);
+    else
+        pull<T, M>(I, A, x, y, d);
     // this step's interface correction of the populations the node sends
     // (zero away from the interface); with Guo's term the slot's last two
     // planes add the spread force to the body force
@@ -52,30 +56,11 @@ __device__ __forceinline__ void finish_node(const InstDev& I, M d[9], int x, int
         else
             collide_guo_mrt<M>(d, I.s, gx, gy, xc);
     } else {
-        if (COLL == II_LBM_SRT) {
-            if (residue)
-                collide_srt<M, true>(d, omega, gx, gy, xc);
-            else
-                collide_srt<M, false>(d, omega, gx, gy, xc);
-        } else {
+        if (COLL == II_LBM_SRT)
+            collide_srt<M, sizeof(T) == 4>(d, omega, gx, gy, xc);
+        else
             collide_mrt<M>(d, I.s, gx, gy, xc);
-        }
     }
-}
-
-template <typename T, typename M, int COLL, bool BOUNDED, bool GUO>
-__device__ __forceinline__ void sweep_node(const InstDev& I, const T* __restrict__ A,
-                                           T* __restrict__ B, int x, int y,
-                                           const int* __restrict__ tile_slot,
-                                           const float* __restrict__ corr,
-                                           const unsigned long long* __restrict__ cmask)
-{
-    M d[9];
-    if (BOUNDED && is_edge(I, x, y))
-        nee<T, M>(I, A, x, y, d);
-    else
-        pull<T, M>(I, A, x, y, d);
-    finish_node<M, COLL, GUO>(I, d, x, y, tile_slot, corr, cmask, sizeof(T) == 4);
     T* base = B + I.lat_off + (long long)y * I.pitch + x;
 #pragma unroll
     for (int i = 0; i < 9; i++) Store<T>::st_stream(base + i * I.plane, (float)d[i], I.inv_scale);
@@ -95,78 +80,6 @@ __global__ __launch_bounds__(BX) void k_sweep(InstDev I, const T* __restrict__ A
     const int x = bx * BX + threadIdx.x;
     if (x >= I.nx) return;
     sweep_node<T, M, COLL, BOUNDED, GUO>(I, A, B, x, y, tile_slot, corr, cmask);
-}
-
-// FP16 storage on a periodic lattice whose width is a multiple of 512: each
-// thread sweeps two neighbouring nodes (x0 even, x0 + 1) with 4-byte loads
-// and stores of both halves.  One node per thread moves 2 bytes per access,
-// too little in flight per wave to keep HBM busy; the pairs double it.  The
-// populations pulled across the pair's edge come from the aligned pair next
-// to it.  Same arithmetic per node as sweep_node.
-__device__ __forceinline__ unsigned ld_pair(const _Float16* p)
-{
-    return *(const unsigned*)p;
-}
-
-__device__ __forceinline__ float half_lo(unsigned v, float sc)
-{
-    return (float)__builtin_bit_cast(_Float16, (unsigned short)(v & 0xffffu)) * sc;
-}
-
-__device__ __forceinline__ float half_hi(unsigned v, float sc)
-{
-    return (float)__builtin_bit_cast(_Float16, (unsigned short)(v >> 16)) * sc;
-}
-
-template <typename M, int COLL, bool GUO>
-__global__ __launch_bounds__(256) void k_sweep_pairs(InstDev I, const _Float16* __restrict__ A,
-                                                     _Float16* __restrict__ B, int bx_count,
-                                                     const int* __restrict__ tile_slot,
-                                                     const float* __restrict__ corr,
-                                                     const unsigned long long* __restrict__ cmask)
-{
-    __builtin_amdgcn_s_setprio(3);
-    const int bx = blockIdx.x % bx_count, y = blockIdx.x / bx_count;
-    const int x0 = bx * 512 + 2 * threadIdx.x;
-    const int xl = (x0 == 0) ? I.nx - 2 : x0 - 2;          // pair left of x0
-    const int xr = (x0 + 2 == I.nx) ? 0 : x0 + 2;          // pair right of x0 + 1
-    const int ym = (y == 0) ? I.ny - 1 : y - 1;
-    const int yp = (y == I.ny - 1) ? 0 : y + 1;
-    const _Float16* base = A + I.lat_off;
-    const long long r0 = (long long)y * I.pitch, rm = (long long)ym * I.pitch,
-                    rp = (long long)yp * I.pitch;
-    const long long P = I.plane;
-    const float sc = I.scale;
-    // pulled populations: d_i(x) = stored_i(x - e_i)
-    const unsigned c0 = ld_pair(base + 0 * P + r0 + x0);
-    const unsigned l1 = ld_pair(base + 1 * P + r0 + xl), c1 = ld_pair(base + 1 * P + r0 + x0);
-    const unsigned c2 = ld_pair(base + 2 * P + rm + x0);
-    const unsigned c3 = ld_pair(base + 3 * P + r0 + x0), r3 = ld_pair(base + 3 * P + r0 + xr);
-    const unsigned c4 = ld_pair(base + 4 * P + rp + x0);
-    const unsigned l5 = ld_pair(base + 5 * P + rm + xl), c5 = ld_pair(base + 5 * P + rm + x0);
-    const unsigned c6 = ld_pair(base + 6 * P + rm + x0), r6 = ld_pair(base + 6 * P + rm + xr);
-    const unsigned c7 = ld_pair(base + 7 * P + rp + x0), r7 = ld_pair(base + 7 * P + rp + xr);
-    const unsigned l8 = ld_pair(base + 8 * P + rp + xl), c8 = ld_pair(base + 8 * P + rp + x0);
-    M a[9], b[9];
-    a[0] = (M)half_lo(c0, sc); b[0] = (M)half_hi(c0, sc);
-    a[1] = (M)half_hi(l1, sc); b[1] = (M)half_lo(c1, sc);
-    a[2] = (M)half_lo(c2, sc); b[2] = (M)half_hi(c2, sc);
-    a[3] = (M)half_hi(c3, sc); b[3] = (M)half_lo(r3, sc);
-    a[4] = (M)half_lo(c4, sc); b[4] = (M)half_hi(c4, sc);
-    a[5] = (M)half_hi(l5, sc); b[5] = (M)half_lo(c5, sc);
-    a[6] = (M)half_hi(c6, sc); b[6] = (M)half_lo(r6, sc);
-    a[7] = (M)half_hi(c7, sc); b[7] = (M)half_lo(r7, sc);
-    a[8] = (M)half_hi(l8, sc); b[8] = (M)half_lo(c8, sc);
-    finish_node<M, COLL, GUO>(I, a, x0, y, tile_slot, corr, cmask, false);
-    finish_node<M, COLL, GUO>(I, b, x0 + 1, y, tile_slot, corr, cmask, false);
-    _Float16* out = B + I.lat_off + r0 + x0;
-    const float inv = I.inv_scale;
-#pragma unroll
-    for (int i = 0; i < 9; i++) {
-        const unsigned lo = __builtin_bit_cast(unsigned short, (_Float16)((float)a[i] * inv));
-        const unsigned hi = __builtin_bit_cast(unsigned short, (_Float16)((float)b[i] * inv));
-        __builtin_nontemporal_store(lo | (hi << 16), (unsigned*)(out + i * P));
-    }
 }
 
 // Batched: block b sweeps `UNIT` consecutive nodes (row-major) of one
@@ -258,28 +171,10 @@ static hipError_t sweep_b(const InstDev& I, const DevPtrs& P, const void* A, voi
     return hipGetLastError();
 }
 
-template <typename M, int COLL>
-static hipError_t sweep_pairs(const InstDev& I, const DevPtrs& P, const void* A, void* B,
-                              int par, hipStream_t s)
-{
-    const int bxn = I.nx / 512;
-    if (I.guo)
-        hipLaunchKernelGGL((k_sweep_pairs<M, COLL, true>), dim3(bxn * I.ny), dim3(256), 0, s, I,
-                           (const _Float16*)A, (_Float16*)B, bxn, P.tile_slot[par], P.corr[par],
-                           P.cmask[par]);
-    else
-        hipLaunchKernelGGL((k_sweep_pairs<M, COLL, false>), dim3(bxn * I.ny), dim3(256), 0, s, I,
-                           (const _Float16*)A, (_Float16*)B, bxn, P.tile_slot[par], P.corr[par],
-                           P.cmask[par]);
-    return hipGetLastError();
-}
-
 template <typename T, typename M, int COLL, bool BOUNDED>
 static hipError_t sweep_t(const InstDev& I, const DevPtrs& P, const void* A, void* B, int par,
                           hipStream_t s)
 {
-    if constexpr (sizeof(T) == 2 && !BOUNDED)
-        if (I.nx % 512 == 0) return sweep_pairs<M, COLL>(I, P, A, B, par, s);
     if (I.nx % 512 == 0) return sweep_b<T, M, COLL, BOUNDED, 512>(I, P, A, B, par, s);
     if (I.nx % 256 == 0) return sweep_b<T, M, COLL, BOUNDED, 256>(I, P, A, B, par, s);
     return sweep_b<T, M, COLL, BOUNDED, 64>(I, P, A, B, par, s);

@@ -68,12 +68,10 @@ def test_batched_equals_single_and_oracle(B, math_):
 
 
 @pytest.mark.parametrize("math_", [W.MATH_FP32, W.MATH_FP64])
-def test_fp16_pair_sweep_equals_batched_sweep(B, math_):
-    # A single FP16 membrane on a periodic lattice 512 wide sweeps two nodes
-    # per thread (4-byte accesses of both halves); the batched sweep takes one
-    # node per thread.  The per-node arithmetic is the same, so the fields
-    # agree bit for bit.  The single handle's autotuner (its tile pass's
-    # blocks per CU, timed on restarted whole steps) leaves them unchanged.
+def test_fp16_batched_equals_single(B, math_):
+    # FP16 storage: the batched sweep (one launch over the slices of every
+    # instance) and the single-instance row-segment sweep of a 512-wide
+    # lattice run the same per-node arithmetic and agree bit for bit.
     ws = [W.membrane_seeded(L=512, seed=s, storage=W.STORE_FP16) for s in (0, 2)]
     for w in ws:
         w.problem.math = math_
@@ -82,11 +80,7 @@ def test_fp16_pair_sweep_equals_batched_sweep(B, math_):
     sim.step(200)
     for j, w in enumerate(ws):
         one = B.Sim([w.problem], [w.X0])
-        one.step(20)
-        tune = one.autotune(2)
-        _say(f"  instance {j}: single-handle autotune {tune}")
-        assert tune["tile_blocks_per_cu"] in (1, 2, 4, 8) and tune["step_us"] > 0.0
-        one.step(180)
+        one.step(200)
         assert np.array_equal(sim.fields(B.F_DISTRIB, inst=j, dtype=np.float32),
                               one.fields(B.F_DISTRIB, dtype=np.float32))
         assert np.array_equal(sim.markers(j)[0], one.markers()[0])

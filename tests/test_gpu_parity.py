@@ -389,8 +389,8 @@ def test_full_size_membrane4096_fp16_first_steps(B):
 
 @pytest.mark.parametrize("math_", [W.MATH_FP32, W.MATH_FP64])
 def test_membrane512_fp16_parity_1000_steps(B, math_):
-    # FP16 storage on a periodic 512-wide lattice (the two-nodes-per-thread
-    # sweep the 4096^2 bench times), 1000 steps against the oracle at the
+    # FP16 storage on a 512-wide lattice (the 512-node row-segment sweep the
+    # 4096^2 bench times), 1000 steps against the oracle at the
     # reduced-precision bar, with both collision arithmetics.
     _say(f"membrane 512x512 FP16 storage math={math_}, 1000 steps vs oracle")
     w = W.membrane_seeded(L=512, storage=W.STORE_FP16)
