@@ -89,6 +89,36 @@ def test_fp16_batched_equals_single(B, math_):
     sim.close()
 
 
+def test_batched_binning_of_longest_chords_equals_single(B):
+    # The longest chords an initial curve may have (4 lu) on a wavy membrane:
+    # each chord's box meets up to four tiles (all counted in the batched
+    # geometry pass's LDS table), and the one block of 256 chords meets about
+    # ninety tiles (the table holds 128).  The tile lists differ from the
+    # single-instance pass in order only, so the fields agree bit for bit.
+    L, n = 512, 256
+    th = 2.0 * np.pi * np.arange(n) / n
+    r = 130.0 + 12.0 * np.sin(8.0 * th)
+    X = np.stack([L / 2.0 + r * np.cos(th), L / 2.0 + r * np.sin(th)], axis=1)
+    chords = np.hypot(*(np.roll(X, -1, axis=0) - X).T)
+    assert 3.9 < chords.max() <= 4.0
+    probs = [W.Problem(nx=L, ny=L, tau=0.8, interface=W.IF_MEMBRANE, n_markers=n, kappa=kappa,
+                       dX=2.0) for kappa in (2e-3, 5e-3)]
+    _say(f"batched binning of {n} chords up to {chords.max():.2f} lu long on {L}^2, "
+         "50 steps vs single runs")
+    sim = B.Sim(probs, [X, X])
+    sim.step(50)
+    for j in range(2):
+        one = B.Sim([probs[j]], [X])
+        one.step(50)
+        assert np.array_equal(sim.fields(B.F_DISTRIB, inst=j, dtype=np.float32),
+                              one.fields(B.F_DISTRIB, dtype=np.float32))
+        assert np.array_equal(sim.markers(j)[0], one.markers()[0])
+        assert one.diag()["error_bits"] == 0
+        one.close()
+    assert all(sim.diag(j)["error_bits"] == 0 for j in range(2))
+    sim.close()
+
+
 @pytest.mark.parametrize("case", ["membrane", "membrane_batch", "rigid"])
 def test_graph_replay_equals_direct_launches(B, case):
     _say(f"graph replay vs direct launches, {case}")
