@@ -315,14 +315,16 @@ int ii_lbm_get_timing(ii_lbm_handle* h, double* sweep_ms, int64_t* launches);
  * move: nine loads and nine stores of the stored deviation per node. */
 int ii_lbm_sweep_bytes(ii_lbm_handle* h, int32_t inst, double* bytes);
 
-/* Replays the steps as HIP graphs when enable != 0: a long graph of S steps
- * (enable = 1: S = 16; an even enable from 2 to 256: S = enable) for as many
- * whole runs of S as a call holds, then two-step graphs, then a last direct
- * step when the count is odd.  Fewer graph launches shorten the gaps between
- * steps.  Enabling captures and instantiates every graph (per starting
- * lattice buffer) at once, without running them; a later change of schedule,
- * learned correction, tuning or S drops them and the next step rebuilds all,
- * so no replay ever captures.  Timing mode uses direct launches.  Results are
+/* Replays the steps as HIP graphs when enable != 0: graphs of S steps
+ * (enable = 1: S = 64; an even enable from 2 to 256: S = enable), then of
+ * each power of two below S down to 4, each for as many whole runs as the
+ * rest of a call holds, then two-step graphs, then a last direct step when
+ * the count is odd (20 steps with S = 64: one graph of 16 and one of 4).
+ * Fewer graph launches shorten the gaps between steps.  Enabling captures
+ * and instantiates every graph (per length and starting lattice buffer) at
+ * once, without running them; a later change of schedule, learned
+ * correction, tuning or S drops them and the next step rebuilds all, so no
+ * replay ever captures.  Timing mode uses direct launches.  Results are
  * identical either way.  EINVAL for an odd enable above 1 or one above 256;
  * ESTATE on a failed handle. */
 int ii_lbm_set_graph(ii_lbm_handle* h, int32_t enable);

@@ -286,8 +286,8 @@ class Sim:
         return ms.value, n.value
 
     def set_graph(self, enable: bool, steps: int = 0) -> None:
-        """HIP-graph replay on or off; steps: length of the long graph (even,
-        0 = the library's default)."""
+        """HIP-graph replay on or off; steps: length of the longest graph
+        (even, 0 = the library's default)."""
         check(load().ii_lbm_set_graph(self.h, (int(steps) if steps else 1) if enable else 0), "set_graph")
 
     def set_isolation(self, enable: bool) -> None:

@@ -325,12 +325,16 @@ struct ii_lbm_handle {
     std::vector<int> tile_est;     // estimated active tiles per instance (batched)
     int tile_per_cu = 0;           // tile-pass blocks per CU (0: one per estimated tile)
     double tuned_step_us = 0.0;    // the autotuner's fastest whole step
-    // hipGraph replay of two steps (one graph per starting parity)
+    // hipGraph replay: graphs of two steps and a ladder of longer ones (the
+    // longest of graph_steps steps, then the powers of two below it down to
+    // four), one per length and starting parity
     bool use_graph = false;
-    int graph_steps = 16;          // steps of the long graph (even; 2: the pair only)
+    int graph_steps = 64;          // steps of the longest graph (even; 2: the pair only)
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};       // two steps, per starting parity
-    hipGraphExec_t gexec_long[2] = {nullptr, nullptr};  // graph_steps steps
+    static constexpr int kLadder = 7;                   // 256, 128, ..., 4 at most
+    int ladder[kLadder] = {};                           // lengths, longest first (0: unused)
+    hipGraphExec_t gexec_long[kLadder][2] = {};
     // Membranes: the interface work of step m+1 runs on `aux` while the
     // sweep of step m runs on the main stream (fork/join through events).
     bool lookahead = false;
@@ -607,18 +611,34 @@ static int ensure_records(ii_lbm_handle* h)
 static void drop_graphs(ii_lbm_handle* h)
 {
     // replays run on the handle's stream: let any in flight finish first
-    if (h->gexec[0] || h->gexec[1] || h->gexec_long[0] || h->gexec_long[1])
-        (void)hipStreamSynchronize(h->stream);
+    bool any = h->gexec[0] || h->gexec[1];
+    for (auto& pair : h->gexec_long) any = any || pair[0] || pair[1];
+    if (any) (void)hipStreamSynchronize(h->stream);
     for (auto& g : h->gexec)
         if (g) {
             (void)hipGraphExecDestroy(g);
             g = nullptr;
         }
-    for (auto& g : h->gexec_long)
-        if (g) {
-            (void)hipGraphExecDestroy(g);
-            g = nullptr;
-        }
+    for (auto& pair : h->gexec_long)
+        for (auto& g : pair)
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
+}
+
+// Lengths of the long graphs for the longest L: L, then the powers of two
+// below it down to four (a call of n steps replays them greedily, so that
+// few launches cover it: 20 steps of the default ladder take 16 + 4).
+static void set_ladder(ii_lbm_handle* h, int L)
+{
+    for (int& v : h->ladder) v = 0;
+    if (L <= 2) return;
+    int q = 0;
+    h->ladder[q++] = L;
+    int p = 1;
+    while (p * 2 < L) p *= 2;
+    for (; p >= 4 && q < ii_lbm_handle::kLadder; p /= 2) h->ladder[q++] = p;
 }
 
 // Blocks of the batched tile pass.  per_cu = 0: one block per estimated
@@ -678,20 +698,23 @@ static hipError_t build_graph(ii_lbm_handle* h, int par, int n, hipGraphExec_t* 
     return e;
 }
 
-// Every graph (pair and long, one of each per starting parity) at once: an
-// odd number of direct steps between replays flips the parity, and no graph
-// may be captured and instantiated in the middle of a caller's timed loop.
+// Every graph (the pair and each long length, one of each per starting
+// parity) at once: an odd number of direct steps between replays flips the
+// parity, and no graph may be captured and instantiated in the middle of a
+// caller's timed loop.
 static hipError_t ensure_graphs(ii_lbm_handle* h)
 {
+    if (h->ladder[0] != (h->graph_steps > 2 ? h->graph_steps : 0)) set_ladder(h, h->graph_steps);
     for (int par = 0; par < 2; par++) {
         if (!h->gexec[par]) {
             const hipError_t e = build_graph(h, par, 2, &h->gexec[par]);
             if (e != hipSuccess) return e;
         }
-        if (h->graph_steps > 2 && !h->gexec_long[par]) {
-            const hipError_t e = build_graph(h, par, h->graph_steps, &h->gexec_long[par]);
-            if (e != hipSuccess) return e;
-        }
+        for (int q = 0; q < ii_lbm_handle::kLadder && h->ladder[q] > 0; q++)
+            if (!h->gexec_long[q][par]) {
+                const hipError_t e = build_graph(h, par, h->ladder[q], &h->gexec_long[q][par]);
+                if (e != hipSuccess) return e;
+            }
     }
     return hipSuccess;
 }
@@ -998,12 +1021,13 @@ int ii_lbm_step(ii_lbm_handle* h, int64_t n_steps)
             if (e != hipSuccess) return hip_fail(h, e);
         }
         // an even number of steps leaves the parity unchanged
-        while (h->graph_steps > 2 && left >= h->graph_steps) {
-            const hipError_t e = hipGraphLaunch(h->gexec_long[h->parity], h->stream);
-            if (e != hipSuccess) return hip_fail(h, e);
-            h->steps += h->graph_steps;
-            left -= h->graph_steps;
-        }
+        for (int q = 0; q < ii_lbm_handle::kLadder && h->ladder[q] > 0; q++)
+            while (left >= h->ladder[q]) {
+                const hipError_t e = hipGraphLaunch(h->gexec_long[q][h->parity], h->stream);
+                if (e != hipSuccess) return hip_fail(h, e);
+                h->steps += h->ladder[q];
+                left -= h->ladder[q];
+            }
         while (left >= 2) {
             const hipError_t e = hipGraphLaunch(h->gexec[h->parity], h->stream);
             if (e != hipSuccess) return hip_fail(h, e);
@@ -1094,7 +1118,7 @@ int ii_lbm_instance_errors(ii_lbm_handle* h, int32_t* bits, int32_t n)
 int ii_lbm_set_graph(ii_lbm_handle* h, int32_t enable)
 {
     if (!h || enable < 0 || enable > 256 || (enable > 1 && enable % 2 != 0)) return II_LBM_EINVAL;
-    const int steps = enable <= 1 ? 16 : enable;
+    const int steps = enable <= 1 ? 64 : enable;
     if (steps != h->graph_steps) drop_graphs(h);
     h->graph_steps = steps;
     h->use_graph = enable != 0;
