@@ -348,7 +348,7 @@ int ii_lbm_set_overlap(ii_lbm_handle* h, int32_t mode);
  *     given, largest first), `trials` launches each;
  *  2. for membranes, whose interface pass runs beside the sweep, the slice
  *     size again (in the order of stage 1) together with the footprint of the
- *     tile pass (ii_lbm_set_tile_blocks: 0, 16, 8, 4, 2 and 1 blocks per CU),
+ *     tile pass (ii_lbm_set_tile_blocks: 0, 24, 16, 12, 8, 4, 2 and 1 blocks per CU),
  *     timed on `trials` whole steps per pair.  A step started again from the
  *     same state recomputes the same results, so the state is left as it was.
  * It keeps the fastest order of stage 1 and the fastest pair of stage 2 (the

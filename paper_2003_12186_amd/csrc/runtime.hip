@@ -1181,12 +1181,12 @@ int ii_lbm_autotune(ii_lbm_handle* h, int32_t trials, int32_t* unit, int32_t* or
     // plane and writes the other), so repeating it leaves the state as it was.
     double best_step = 0.0;
     if (e == hipSuccess && h->lookahead && h->overlap != II_LBM_OVERLAP_SERIAL) {
-        const int cands[6] = {0, 16, 8, 4, 2, 1};
+        const int cands[8] = {0, 24, 16, 12, 8, 4, 2, 1};
         int bc = 0, bw = bu;
         best_step = 1e300;
         for (int ui = 0; ui < 3 && e == hipSuccess; ui++) {
             e = upload_sweep_table(h, units[ui], bo);
-            for (int ci = 0; ci < 6 && e == hipSuccess; ci++) {
+            for (int ci = 0; ci < 8 && e == hipSuccess; ci++) {
                 e = upload_tile_table(h, cands[ci]);
                 if (e == hipSuccess) e = enqueue_step(h, h->parity, h->stream, false);
                 if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
