@@ -119,6 +119,44 @@ def test_batched_binning_of_longest_chords_equals_single(B):
     sim.close()
 
 
+@pytest.mark.parametrize("math_", [W.MATH_FP32, W.MATH_FP64])
+def test_batched_ragged_lattices_equal_single_and_oracle(B, math_):
+    # Lattices whose sides are not multiples of the 16-node tile (partial
+    # tiles on two sides) nor of the sweep's slices (slices run across row
+    # ends): the batched passes clip as the single-instance ones do.
+    shapes = [(72, 56, 20.0, 14.0), (100, 84, 30.0, 24.0), (45, 61, 12.0, 17.0)]
+    probs, X0 = [], []
+    for j, (nx, ny, a, b) in enumerate(shapes):
+        n = int(round(W.ramanujan_perimeter(a, b) / 0.8))
+        probs.append(W.Problem(nx=nx, ny=ny, tau=0.7 + 0.1 * j, interface=W.IF_MEMBRANE,
+                               n_markers=n, kappa=0.02, dX=W.membrane_dX(a, b, n), math=math_))
+        X0.append(W.ellipse_markers(nx / 2.0, ny / 2.0, a, b, n))
+    _say(f"batched membranes on ragged lattices {[(p.nx, p.ny) for p in probs]}, math={math_}, "
+         "300 steps")
+    sim = B.Sim(probs, X0)
+    sim.autotune(2)
+    sim.step(300)
+    for j, p in enumerate(probs):
+        one = B.Sim([p], [X0[j]])
+        one.step(300)
+        assert np.array_equal(sim.fields(B.F_DISTRIB, inst=j, dtype=np.float32),
+                              one.fields(B.F_DISTRIB, dtype=np.float32))
+        assert np.array_equal(sim.markers(j)[0], one.markers()[0])
+        one.close()
+        q = O.make_problem(p)
+        f = O.rest_state(q)
+        X = X0[j].copy()
+        O.run(q, f, X, 300)
+        _, ux, uy = O.moments(q, f)
+        g = sim.fields(B.F_UX | B.F_UY, inst=j)
+        err = np.sqrt(((g[0] - ux) ** 2 + (g[1] - uy) ** 2).sum() / (ux ** 2 + uy ** 2).sum())
+        _say(f"  {p.nx}x{p.ny}: rel L2 u vs oracle {err:.2e}, max |dX| "
+             f"{np.abs(sim.markers(j)[0] - X).max():.1e}")
+        assert err <= 1e-6
+    assert all(sim.diag(j)["error_bits"] == 0 for j in range(len(probs)))
+    sim.close()
+
+
 @pytest.mark.parametrize("case", ["membrane", "membrane_batch", "rigid"])
 def test_graph_replay_equals_direct_launches(B, case):
     _say(f"graph replay vs direct launches, {case}")
