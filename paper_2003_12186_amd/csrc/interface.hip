@@ -413,10 +413,12 @@ template <typename T, typename M, int MODE>
 __global__ __launch_bounds__(256) void k_markers(InstDev I, DevPtrs P, const T* __restrict__ A,
                                                  int par)
 {
-    // The interpolation of step m also resets the slot plane of step m+1
-    // (last read by the sweep of step m-1, which has finished), saving the
-    // interface pass of step m+1 a launch of its own.
-    if (MODE == kModeInterp && blockIdx.x == 0) slot_reset_body(I, P, par ^ 1);
+    // The interpolation of step m (for membranes) or the marker pass of step m
+    // (FULL, direct forcing) also resets the slot plane of step m+1, last
+    // read by the sweep of step m-1, which has finished: the interface pass
+    // of step m+1 needs no launch of its own for it.
+    if ((MODE == kModeInterp || MODE == kModeFull) && blockIdx.x == 0)
+        slot_reset_body(I, P, par ^ 1);
     markers_body<T, M, MODE>(I, P, A, par, blockIdx.x);
 }
 
@@ -433,7 +435,8 @@ __global__ __launch_bounds__(256) void k_markers_batch(const InstDev* __restrict
     if (idx >= n_units) return;   // padding of the grid (whole block)
     const int2 u = units[idx];
     const InstDev I = insts[u.x];
-    if (MODE == kModeInterp && u.y == 0) slot_reset_body(I, P, par ^ 1);   // as in k_markers
+    if ((MODE == kModeInterp || MODE == kModeFull) && u.y == 0)
+        slot_reset_body(I, P, par ^ 1);   // as in k_markers
     markers_body<T, M, MODE>(I, P, A, par, u.y);
 }
 

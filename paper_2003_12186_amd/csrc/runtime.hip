@@ -518,7 +518,8 @@ static hipError_t enqueue_interp(ii_lbm_handle* h, int par, hipStream_t s)
 //     FULL:    fork -> aux: interp(m), reset/geom/tiles(m+1); s: sweep(m) -> join
 //     INTERP_FIRST: interp(m) on s, fork -> aux: reset/geom/tiles(m+1);
 //              s: sweep(m) -> join
-//   rigid bodies: reset/full markers/tiles(m) -> sweep(m), in order on s
+//   rigid bodies: full markers (resetting the slot plane of m+1)/tiles(m) ->
+//     sweep(m), in order on s
 // The learned correction's phases for the state of plane `par` on stream s.
 static hipError_t enqueue_learned(ii_lbm_handle* h, int par, hipStream_t s,
                                   hipError_t (*phase)(const HandleView&, const LearnedCfg&))
@@ -577,7 +578,9 @@ static hipError_t enqueue_step(ii_lbm_handle* h, int par, hipStream_t s, bool ti
         if (e == hipSuccess) e = hipStreamWaitEvent(s, h->ev_join, 0);
         return e;
     }
-    e = enqueue_interface(h, par, kModeFull, s, true);
+    // the plane of this step was reset by the previous step's marker pass
+    // (or is still as the set-up left it)
+    e = enqueue_interface(h, par, kModeFull, s, true, false);
     if (e == hipSuccess) e = enqueue_sweep(h, par, s, timed);
     for (size_t j = 0; j < h->L.inst.size() && e == hipSuccess; j++)
         if (h->L.inst[j].moving) e = launch_body(h->L.inst[j], h->P, par, s);
