@@ -531,7 +531,10 @@ static hipError_t enqueue_learned(ii_lbm_handle* h, int par, hipStream_t s,
     return phase(v, h->learned);
 }
 
-static hipError_t enqueue_step(ii_lbm_handle* h, int par, hipStream_t s, bool timed)
+// `records`: a rigid body's tile pass also writes the cut-link records.  Only
+// the newest step's are ever reported, so a graph builds them on its last step.
+static hipError_t enqueue_step(ii_lbm_handle* h, int par, hipStream_t s, bool timed,
+                               bool records = true)
 {
     hipError_t e = hipSuccess;
     const bool lrn = h->learned.on;
@@ -580,7 +583,7 @@ static hipError_t enqueue_step(ii_lbm_handle* h, int par, hipStream_t s, bool ti
     }
     // the plane of this step was reset by the previous step's marker pass
     // (or is still as the set-up left it)
-    e = enqueue_interface(h, par, kModeFull, s, true, false);
+    e = enqueue_interface(h, par, kModeFull, s, records, false);
     if (e == hipSuccess) e = enqueue_sweep(h, par, s, timed);
     for (size_t j = 0; j < h->L.inst.size() && e == hipSuccess; j++)
         if (h->L.inst[j].moving) e = launch_body(h->L.inst[j], h->P, par, s);
@@ -682,7 +685,7 @@ static hipError_t upload_tile_table(ii_lbm_handle* h, int per_cu)
 }
 
 // n (even) steps starting at parity `par`, captured on the handle's own
-// stream into *out.
+// stream into *out; the last step builds the cut-link records.
 static hipError_t build_graph(ii_lbm_handle* h, int par, int n, hipGraphExec_t* out)
 {
     if (!h->cap_stream) {
@@ -693,7 +696,8 @@ static hipError_t build_graph(ii_lbm_handle* h, int par, int n, hipGraphExec_t* 
     hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
     hipError_t e1 = hipSuccess;
-    for (int k = 0; k < n && e1 == hipSuccess; k++) e1 = enqueue_step(h, par ^ (k & 1), h->cap_stream, false);
+    for (int k = 0; k < n && e1 == hipSuccess; k++)
+        e1 = enqueue_step(h, par ^ (k & 1), h->cap_stream, false, k == n - 1);
     e = hipStreamEndCapture(h->cap_stream, &g);
     if (e1 != hipSuccess) e = e1;
     if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);

@@ -167,3 +167,31 @@ def test_moving_body_checkpoint_restart_and_fixed_body_has_no_state(B):
         fixed.body()
     assert e.value.code == B.EINVAL
     fixed.close()
+
+
+@pytest.mark.parametrize("kind", ["fixed", "prescribed"])
+def test_graph_steps_report_the_last_steps_links(B, kind):
+    # A graph builds the cut-link records on its last step only: after calls
+    # that end on a long graph (64), a direct step (3 = pair + 1) and a pair
+    # graph (66 = 64 + 2), the reported links, the field and the diagnostics
+    # equal those of direct steps, each of which records.
+    if kind == "fixed":
+        w = W.cylinder_channel(re=20.0, small=True)
+        prob, X0 = w.problem, w.X0
+    else:
+        prob, X0 = _box_body(W.FORCE_II_LBM, presc_amp=(4.0, 0.0), presc_umax=(0.02, 0.0))
+    _say(f"rigid {kind}: graph replays against direct steps, links after 64, 67 and 133 steps")
+    g = B.Sim([prob], [X0])
+    g.set_graph(True)
+    d = B.Sim([prob], [X0])
+    d.set_graph(False)
+    order = lambda r: r[np.lexsort((r["seg"], r["dir"], r["y"], r["x"]))]
+    for n in (64, 3, 66):
+        g.step(n)
+        d.step(n)
+        lg, ld = g.cutlinks(), d.cutlinks()
+        assert len(lg) > 10 and np.array_equal(order(lg), order(ld))
+        assert np.array_equal(g.fields(B.F_UX | B.F_UY), d.fields(B.F_UX | B.F_UY))
+        assert g.diag()["n_cut_links"] == d.diag()["n_cut_links"] == len(ld)
+    g.close()
+    d.close()
