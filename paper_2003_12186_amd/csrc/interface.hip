@@ -602,19 +602,26 @@ __device__ __forceinline__ bool link_crossing(int x, int y, int i, const Chord& 
 // angle between markers k and k+1.
 // (cx, cy, th0): the circle's centre and orientation this step (a moving
 // body's marker k sits at angle th0 + 2 pi k / N, th0 in [0, 2 pi)).
+// Velocity and weight of link direction i (1..8) when i differs across the
+// lanes of a wave: decoded from packed constants rather than read from a table.
+__device__ __forceinline__ int link_ex(int i) { return (int)((0x20919u >> (2 * i)) & 3u) - 1; }
+__device__ __forceinline__ int link_ey(int i) { return (int)((0x2865u >> (2 * i)) & 3u) - 1; }
+__device__ __forceinline__ double link_w(int i) { return i < 5 ? WD[1] : WD[5]; }
+
 __device__ __forceinline__ void rigid_cut(const InstDev& I, double cx, double cy, double th0,
                                           int x, int y, int i, bool inP, double& q, double& th,
                                           int& k)
 {
     const int N = I.n_markers;
+    const int ex = link_ex(i), ey = link_ey(i);
     const double R2 = I.radius * I.radius;
     const double dx = (double)x - cx, dy = (double)y - cy;
-    const double ee = (double)(EX[i] * EX[i] + EY[i] * EY[i]);
-    const double de = dx * EX[i] + dy * EY[i];
+    const double ee = (double)(ex * ex + ey * ey);
+    const double de = dx * ex + dy * ey;
     const double dd = dx * dx + dy * dy - R2;
     const double disc = sqrt(de * de - ee * dd);
     q = inP ? (-de + disc) / ee : (-de - disc) / ee;
-    const double cxp = (double)x + q * EX[i] - cx, cyp = (double)y + q * EY[i] - cy;
+    const double cxp = (double)x + q * ex - cx, cyp = (double)y + q * ey - cy;
     double ang = atan2(cyp, cxp) - th0;
     if (ang < 0.0) ang += 2.0 * M_PI;
     if (ang < 0.0) ang += 2.0 * M_PI;
@@ -675,7 +682,7 @@ template <class TS>
 __device__ __forceinline__ void add_jump(TS& S, int node, int i, int sigma, double jpc, int* err,
                                          double scale = kJumpFix)
 {
-    const double v = (double)sigma * WD[i] * jpc / kCs2;
+    const double v = (double)sigma * link_w(i) * jpc / kCs2;
     if (!isfinite(v)) {
         atomicOr(err, (int)kErrUnstable);
         return;
@@ -898,11 +905,20 @@ __device__ __forceinline__ void tiles_body(const InstDev& I, const DevPtrs& P, i
                 const double R2 = I.radius * I.radius;
                 const double dx = (double)x - ccx, dy = (double)y - ccy;
                 const double phP = dx * dx + dy * dy - R2;
+                const bool inP = phP < 0.0;
+                // the links whose far end lies on the other side; the wave then
+                // walks each lane's cut links together (as many passes as the
+                // most any lane has, not one per direction any lane cuts)
+                unsigned cut = 0u;
+#pragma unroll
                 for (int i = 1; i < 9; i++) {
                     const double qxd = (double)(x + EX[i]), qyd = (double)(y + EY[i]);
                     const double phQ = (qxd - ccx) * (qxd - ccx) + (qyd - ccy) * (qyd - ccy) - R2;
-                    const bool inP = phP < 0.0, inQ = phQ < 0.0;
-                    if (inP == inQ) continue;
+                    if ((phQ < 0.0) != inP) cut |= 1u << i;
+                }
+                while (cut != 0u) {
+                    const int i = __builtin_ctz(cut);
+                    cut &= cut - 1u;
                     double q, th;
                     int k;
                     rigid_cut(I, ccx, ccy, th0, x, y, i, inP, q, th, k);
